@@ -1,0 +1,107 @@
+"""Pins of the oracle's matrix-product circuit.
+
+* the permutations reproduce Jiang's identity A B = sum_k phi^k(sigma A) (.) psi^k(tau B)
+  in FP64 (Eq. 4) and the diagonal formulas Eq. 5 (Z) and Eq. 6 (T) cell by cell;
+* the homomorphic transforms decrypt to the FP64 permutations;
+* decrypt(he_matmul) matches the FP64 product within 2^-15.
+"""
+import numpy as np
+import pytest
+
+from paper_2305_17341_amd import inputs as I
+
+BOUND = 2.0**-15
+
+
+def apply_perm(p, v):
+    return v[p]
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 32])
+def test_jiang_identity_fp64(oracle_mod, n):
+    sig, tau = oracle_mod.perm("sigma", n), oracle_mod.perm("tau", n)
+    g = np.random.default_rng(n)
+    A, B = g.uniform(-1, 1, (n, n)), g.uniform(-1, 1, (n, n))
+    a, b = A.ravel(), B.ravel()
+    sa, tb = apply_perm(sig, a).reshape(n, n), apply_perm(tau, b).reshape(n, n)
+    acc = np.zeros((n, n))
+    for k in range(n):
+        acc += np.roll(sa, -k, axis=1) * np.roll(tb, -k, axis=0)
+    assert np.allclose(acc, A @ B, atol=1e-12)
+    tr = oracle_mod.perm("transpose", n)
+    assert np.array_equal(apply_perm(tr, a).reshape(n, n), A.T)
+
+
+def _diag(p, l, n2):
+    return np.array([1.0 if (p[t] - t - l) % n2 == 0 else 0.0 for t in range(n2)])
+
+
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_sigma_diagonals_are_eq5(oracle_mod, n):
+    p = oracle_mod.perm("sigma", n)
+    n2 = n * n
+    nonzero = set()
+    for k in range(-(n2 // 2) + 1, n2 // 2 + 1):
+        d = _diag(p, k, n2)
+        want = np.zeros(n2)
+        for ell in range(n2):
+            if k >= 0 and 0 <= ell - n * k < n - k:
+                want[ell] = 1
+            if k < 0 and -k <= ell - (n + k) * n < n:
+                want[ell] = 1
+        assert np.array_equal(d, want), k
+        if d.any():
+            nonzero.add(k)
+    assert nonzero == set(range(-n + 1, n))
+
+
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_tau_diagonals_are_eq6(oracle_mod, n):
+    p = oracle_mod.perm("tau", n)
+    n2 = n * n
+    for k in range(n):
+        d = _diag(p, k * n, n2)
+        want = np.array([1.0 if ell % n == k else 0.0 for ell in range(n2)])
+        assert np.array_equal(d, want)
+    others = [l for l in range(n2) if l % n and _diag(p, l, n2).any()]
+    assert others == []
+
+
+@pytest.fixture(scope="module")
+def small(oracle_mod):
+    c = I.SMALL
+    o = oracle_mod.Oracle(c.log_n, c.q_bits, c.p_bits, seed=11)
+    n = 16
+    steps = set(range(1, 4)) | {4 * i for i in range(-4, 4) if i} \
+        | {n * j for j in range(1, 4)} | {n * 4 * i for i in range(1, 4)} | {-n}
+    steps |= {(n - 1) * 4 * i for i in range(-4, 4) if i} | {(n - 1) * j for j in range(1, 4)}
+    o.keygen(rot_steps=sorted(steps), relin=True)
+    return o
+
+
+def test_lintrans_sigma_tau_transpose_decrypt(small):
+    n = 16
+    A = I.uniform_matrix(1, n)
+    ct = small.encrypt(A.ravel(), nonce=1)
+    import oracle.oracle as O
+    for name, f in (("sigma", lambda: small.lt_sigma(ct, n, 4)),
+                    ("tau", lambda: small.lt_tau(ct, n, 4)),
+                    ("transpose", lambda: small.lt_transpose(ct, n, 4))):
+        r = f()
+        assert r.level == ct.level - 1
+        want = A.ravel()[O.perm(name, n)]
+        got = small.decrypt(r)[: n * n]
+        assert np.max(np.abs(got - want)) < 2.0**-20, name
+
+
+def test_matmul_small_decrypts_to_fp64_product(small):
+    n = 16
+    A, B = I.uniform_matrix(1, n), I.uniform_matrix(2, n)
+    ca, cb = small.encrypt(A.ravel(), nonce=1), small.encrypt(B.ravel(), nonce=2)
+    r = small.matmul(ca, cb, n, 4, 4)
+    assert r.level == small.L - 3
+    got = small.decrypt(r)
+    S = small.slots
+    want = np.tile((A @ B).ravel(), S // (n * n))
+    err = np.max(np.abs(got - want))
+    assert err < BOUND, err
