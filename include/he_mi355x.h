@@ -1,0 +1,186 @@
+/*
+ * he_mi355x.h - C ABI of the MI355X (gfx950) RNS-CKKS homomorphic matrix
+ * product library.
+ *
+ * The operations follow "Improved Privacy-Preserving PCA Using Optimized
+ * Homomorphic Matrix Multiplication" (arXiv 2305.17341):
+ *   - full-RNS CKKS (Appendix A: Setparams, Encode/Decode, SecKeyGen,
+ *     PubKeyGen, SwitchKeyGen, Enc, Dec, Add, PMult, Mult, Rescale,
+ *     KeySwitch, Rot),
+ *   - hoisted and double-hoisted BSGS linear transforms (section 3.3.1,
+ *     Eq. 2 and Eq. 3'),
+ *   - Jiang's matrix product sum_k C^k Z a (.) R^k T b (Eq. 4) with the
+ *     hoisting of section 4.1 and the diagonal convergence decomposition of
+ *     section 4.2 (Algorithms DCDforZ, DCDforT, DMatrixMult),
+ *   - the covariance circuit of section 5 (Algorithm HCovMtrx).
+ *
+ * Conventions
+ *   - Every call returns he_status (HE_OK = 0); on failure the message of the
+ *     last error of the calling thread is available from he_last_error().
+ *     Calls never abort the process and no C++ exception crosses the ABI.
+ *   - Host pointers are plain CPU memory owned by the caller; the library
+ *     copies what it needs before returning.  Ciphertexts (he_ct) and all
+ *     keys live in device memory owned by the library.
+ *   - Work is issued on the context's HIP stream and is asynchronous; calls
+ *     that hand data to the host (he_decrypt, he_ct_export) synchronise.
+ *   - A ciphertext at level l is u64[2][l+1][N] (limb-major, evaluation
+ *     domain, residues in [0, q_i)); its scale is a double tracked exactly.
+ *   - Slot vectors hold N/2 reals; a shorter message is replicated with its
+ *     own period (a d x d matrix, row-major, uses period d*d).
+ *   - Limits: 10 <= log N <= 16, at most 48 Q primes, 1..4 special primes,
+ *     at most 16 decomposition digits, prime sizes 30..61 bits.
+ */
+#ifndef HE_MI355X_H
+#define HE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HE_OK = 0,
+  HE_EINVAL = -1,   /* bad argument or shape */
+  HE_ELEVEL = -2,   /* not enough levels left / level mismatch */
+  HE_ESCALE = -3,   /* scale mismatch for an addition */
+  HE_EKEY = -4,     /* a needed switching key was not generated */
+  HE_ENOMEM = -5,   /* device allocation failed */
+  HE_EDEVICE = -6,  /* HIP runtime error */
+  HE_EBUSY = -7,
+  HE_ENEEDREFRESH = -8
+} he_status;
+
+typedef struct he_ctx he_ctx; /* parameters, tables, keys, plaintext caches */
+typedef struct he_ct he_ct;   /* one device-resident ciphertext */
+
+/* Setparams (Appendix A): N = 2^log_n, q_bits[n_q] sizes of q_0..q_L,
+ * p_bits[n_p] sizes of the special primes p_0..p_{alpha-1}; every prime is
+ * 1 mod 2N (the largest such primes below 2^bits, Q first, then P).
+ * Default scale Delta = 2^log2_scale; sigma = error width (support |e| <= 19). */
+typedef struct {
+  uint32_t log_n;
+  const uint32_t* q_bits;
+  uint32_t n_q;
+  const uint32_t* p_bits;
+  uint32_t n_p;
+  double log2_scale;
+  double sigma;
+} he_params;
+
+/* Optional device-memory hooks (e.g. a framework's caching allocator) and the
+ * HIP stream to run on.  Any field may be NULL: hipMalloc / a stream owned by
+ * the context are used instead. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*release)(void* p, void* user);
+  void* user;
+  void* hip_stream;
+} he_device;
+
+/* Options of the matrix product.  Zero fields take the defaults:
+ * n1_z = n1_t = 2^ceil(log2(d)/2) (baby steps of the sigma/tau BSGS),
+ * nprime_z = nprime_t = d - 1 (no diagonal convergence decomposition). */
+typedef struct {
+  uint32_t n1_z, n1_t;
+  uint32_t nprime_z, nprime_t;
+  uint32_t flags; /* HE_MM_* below */
+} he_matmul_opts;
+#define HE_MM_BATCHED 1u /* fused multi-rotation kernels (same residues) */
+
+/* Create a context on the current HIP device.  `dev` may be NULL.  `seed`
+ * keys every random draw of the context (Philox4x64-10 streams).
+ * Returns HE_EINVAL for unsupported parameters, HE_EDEVICE without a device. */
+he_status he_ctx_create(const he_params* params, const he_device* dev, uint64_t seed, he_ctx** out);
+he_status he_ctx_destroy(he_ctx* ctx);
+/* number of primes (Q then P) and their values */
+he_status he_ctx_moduli(const he_ctx* ctx, uint64_t* out, size_t cap, size_t* n);
+
+/* SecKeyGen + PubKeyGen + relinearisation key + rotation keys for each left
+ * rotation step in rot_steps (Appendix A).  Calling it again only adds keys
+ * that are missing. */
+he_status he_keygen(he_ctx* ctx, const int32_t* rot_steps, size_t n_steps);
+/* rotation steps the d x d product needs with these options (for keygen);
+ * writes at most cap entries and the total count to *n */
+he_status he_matmul_rot_steps(const he_ctx* ctx, uint32_t d, const he_matmul_opts* opts, int32_t* steps,
+                              size_t cap, size_t* n);
+/* rotation steps of the transposition (G) with baby-step count n1 (0 = default) */
+he_status he_transpose_rot_steps(const he_ctx* ctx, uint32_t d, uint32_t n1, int32_t* steps, size_t cap, size_t* n);
+
+/* Encode (Appendix A): m_i = floor(v_i + 1/2 + 2^-30) with
+ * v_i = (2 Delta/N) sum_j z_j cos(pi 5^j i / N); z replicated to N/2 slots.
+ * `n` must divide N/2.  Output: N signed coefficients (host). */
+he_status he_encode(he_ctx* ctx, const double* z, size_t n, double delta, int64_t* out);
+
+/* Enc at `level` with the public key; randomness is a pure function of
+ * (context seed, nonce).  he_encrypt_matrix packs a d x d row-major matrix. */
+he_status he_encrypt_slots(he_ctx* ctx, const double* z, size_t n, uint32_t level, uint64_t nonce, he_ct** out);
+he_status he_encrypt_matrix(he_ctx* ctx, const double* a_rowmajor, uint32_t d, uint32_t level, uint64_t nonce,
+                            he_ct** out);
+/* Dec + Decode of the first n slots (client side, holds the secret key).
+ * Uses the residue mod q_0, exact while |message * scale| < q_0 / 2. */
+he_status he_decrypt(he_ctx* ctx, const he_ct* ct, double* out, size_t n);
+
+/* ciphertext metadata, transfer and lifetime */
+he_status he_ct_info(const he_ct* ct, uint32_t* level, double* scale);
+he_status he_ct_export(const he_ct* ct, uint64_t* host, size_t words, uint32_t* level, double* scale);
+he_status he_ct_import(he_ctx* ctx, const uint64_t* host, size_t words, uint32_t level, double scale, he_ct** out);
+he_status he_ct_free(he_ct* ct);
+
+/* Add / Sub (equal level and scale), Mult = tensor + relinearisation (no
+ * rescale), Rescale, Rot (left rotation by `step` slots), level drop. */
+he_status he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
+he_status he_sub(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
+he_status he_mult(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
+he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out);
+he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out);
+he_status he_drop_level(he_ctx* ctx, const he_ct* a, uint32_t level, he_ct** out);
+/* PMult by the encoding of z (n slots, replicated) at scale pt_scale */
+he_status he_pmult_slots(he_ctx* ctx, const he_ct* a, const double* z, size_t n, double pt_scale, he_ct** out);
+
+/* Linear transforms of section 4 on a d x d matrix ciphertext by
+ * double-hoisted BSGS, one level consumed: kind 0 = sigma (Z), 1 = tau (T),
+ * 2 = transposition (G); `weight` multiplies every diagonal (1.0 = plain). */
+he_status he_lintrans(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, double weight,
+                      he_ct** out);
+
+/* The homomorphic d x d product (Eq. 4, Algorithm DMatrixMult): a and b at
+ * the same level l >= 3 (more with decomposition); result at level l - 3. */
+he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, const he_matmul_opts* opts,
+                    he_ct** out);
+/* `count` independent products; out[count] receives new ciphertexts */
+he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const* b, const uint32_t* d,
+                          size_t count, const he_matmul_opts* opts, he_ct** out);
+
+/* Block covariance of a centred dataset (Algorithm HCovMtrx): x holds
+ * row_blocks * k ciphertexts, x[r*k + j] = block (row block r, feature block
+ * j) of size d x d.  cov[a*k + b] receives block (a, b) of X^T X / n_samples. */
+he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks, uint32_t k, uint32_t d,
+                        uint64_t n_samples, const he_matmul_opts* opts, he_ct** cov);
+
+/* wait for all work of the context */
+he_status he_sync(he_ctx* ctx);
+/* device bytes held by the context (live, cached, peak) */
+he_status he_mem_info(const he_ctx* ctx, size_t* live, size_t* cached, size_t* peak);
+
+/* Raw limb transforms for parity checks: host in/out u64[nlimbs][N]; limb k
+ * uses modulus mod_idx[k] (index into he_ctx_moduli order). */
+he_status he_ntt_limbs(he_ctx* ctx, const uint64_t* in, uint64_t* out, size_t nlimbs, const int32_t* mod_idx,
+                       int inverse);
+/* Raw automorphism X -> X^g on evaluation-domain limbs (host in/out). */
+he_status he_automorph_limbs(he_ctx* ctx, const uint64_t* in, uint64_t* out, size_t nlimbs, uint64_t galois);
+/* Hoisted rotation left in R_{Q_l P} (section 3.3.1), exported to host as
+ * u64[2][l+1+alpha][N]: the double-hoisting building block. */
+he_status he_hoisted_rotate_export(he_ctx* ctx, const he_ct* a, int32_t step, uint64_t* host, size_t words);
+
+/* time spent in the last he_matmul / he_matmul_batch call, milliseconds
+ * (HIP events around the call's stream work) */
+he_status he_last_op_ms(const he_ctx* ctx, double* ms);
+
+const char* he_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HE_MI355X_H */

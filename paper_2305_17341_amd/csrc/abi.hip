@@ -1,0 +1,386 @@
+// C ABI of the library (include/he_mi355x.h): argument checks, error
+// translation and ownership; all computation is in runtime.hip / kernels.hip.
+#include <cstdio>
+#include <set>
+
+#include "runtime.h"
+
+namespace {
+template <class F>
+he_status guard(F&& f) {
+  try {
+    f();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(HE_EDEVICE, std::string("HIP launch: ") + hipGetErrorString(e));
+    return HE_OK;
+  } catch (const HeError& e) {
+    g_last_error = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return HE_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HE_EINVAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return HE_EINVAL;
+  }
+}
+void need(bool ok, const char* what) {
+  if (!ok) fail(HE_EINVAL, what);
+}
+he_ct* wrap(he_ctx* c, HeCt&& x) {
+  he_ct* r = new he_ct;
+  r->ctx = c;
+  r->ct = std::move(x);
+  return r;
+}
+void check_ct(const he_ctx* c, const he_ct* a) {
+  need(a != nullptr, "null ciphertext");
+  need(a->ctx == c, "ciphertext belongs to another context");
+}
+void opts_of(const he_matmul_opts* o, int d, int& n1z, int& n1t) {
+  n1z = (o && o->n1_z) ? (int)o->n1_z : default_n1(d);
+  n1t = (o && o->n1_t) ? (int)o->n1_t : default_n1(d);
+  if (o && ((o->nprime_z && o->nprime_z != (u32)d - 1) || (o->nprime_t && o->nprime_t != (u32)d - 1)))
+    fail(HE_EINVAL, "diagonal convergence decomposition is not available in this build");
+}
+}  // namespace
+
+extern "C" {
+
+const char* he_last_error(void) { return g_last_error.c_str(); }
+
+he_status he_ctx_create(const he_params* params, const he_device* dev, uint64_t seed, he_ctx** out) {
+  return guard([&] {
+    need(out != nullptr && params != nullptr, "null argument");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+      (void)hipGetLastError();
+      fail(HE_EDEVICE, "no HIP device");
+    }
+    he_ctx* c = new he_ctx;
+    try {
+      c->impl.init(params, dev, seed);
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
+he_status he_ctx_destroy(he_ctx* ctx) {
+  return guard([&] { delete ctx; });
+}
+
+he_status he_ctx_moduli(const he_ctx* ctx, uint64_t* out, size_t cap, size_t* n) {
+  return guard([&] {
+    need(ctx != nullptr, "null context");
+    const HeCtxImpl& c = ctx->impl;
+    if (n) *n = (size_t)c.nmods;
+    for (int k = 0; k < c.nmods && (size_t)k < cap; k++) out[k] = c.mods[k];
+  });
+}
+
+he_status he_keygen(he_ctx* ctx, const int32_t* rot_steps, size_t n_steps) {
+  return guard([&] {
+    need(ctx != nullptr, "null context");
+    HeCtxImpl& c = ctx->impl;
+    c.keygen_secret();
+    c.keygen_relin();
+    for (size_t i = 0; i < n_steps; i++) c.keygen_rot(rot_steps[i]);
+    hip_check(hipStreamSynchronize(c.stream), "keygen");
+  });
+}
+
+he_status he_matmul_rot_steps(const he_ctx* ctx, uint32_t d, const he_matmul_opts* opts, int32_t* steps, size_t cap,
+                              size_t* n) {
+  return guard([&] {
+    need(ctx != nullptr && d >= 2, "bad arguments");
+    int n1z, n1t;
+    opts_of(opts, (int)d, n1z, n1t);
+    std::vector<long> s = matmul_steps((int)d, n1z, n1t);
+    if (n) *n = s.size();
+    for (size_t i = 0; i < s.size() && i < cap; i++) steps[i] = (int32_t)s[i];
+  });
+}
+
+he_status he_transpose_rot_steps(const he_ctx* ctx, uint32_t d, uint32_t n1, int32_t* steps, size_t cap, size_t* n) {
+  return guard([&] {
+    need(ctx != nullptr && d >= 2, "bad arguments");
+    std::vector<long> s = transpose_steps((int)d, n1 ? (int)n1 : default_n1((int)d));
+    if (n) *n = s.size();
+    for (size_t i = 0; i < s.size() && i < cap; i++) steps[i] = (int32_t)s[i];
+  });
+}
+
+he_status he_encode(he_ctx* ctx, const double* z, size_t n, double delta, int64_t* out) {
+  return guard([&] {
+    need(ctx && z && out && n > 0, "bad arguments");
+    HeCtxImpl& c = ctx->impl;
+    DevBuf m = c.encode_batch(z, (int)n, 1, delta);
+    hip_check(hipMemcpyAsync(out, m.p, c.N * 8, hipMemcpyDeviceToHost, c.stream), "download");
+    hip_check(hipStreamSynchronize(c.stream), "encode");
+  });
+}
+
+he_status he_encrypt_slots(he_ctx* ctx, const double* z, size_t n, uint32_t level, uint64_t nonce, he_ct** out) {
+  return guard([&] {
+    need(ctx && z && out && n > 0, "bad arguments");
+    *out = wrap(ctx, ctx->impl.encrypt(z, (int)n, (int)level, nonce));
+  });
+}
+
+he_status he_encrypt_matrix(he_ctx* ctx, const double* a, uint32_t d, uint32_t level, uint64_t nonce, he_ct** out) {
+  return guard([&] {
+    need(ctx && a && out && d > 0, "bad arguments");
+    need((u64)d * d <= ctx->impl.N / 2 && (ctx->impl.N / 2) % ((u64)d * d) == 0, "d*d must divide N/2");
+    *out = wrap(ctx, ctx->impl.encrypt(a, (int)(d * d), (int)level, nonce));
+  });
+}
+
+he_status he_decrypt(he_ctx* ctx, const he_ct* ct, double* out, size_t n) {
+  return guard([&] {
+    check_ct(ctx, ct);
+    need(out != nullptr && n <= ctx->impl.N / 2, "bad output size");
+    std::vector<double> z = ctx->impl.decrypt(ct->ct);
+    std::copy(z.begin(), z.begin() + n, out);
+  });
+}
+
+he_status he_ct_info(const he_ct* ct, uint32_t* level, double* scale) {
+  return guard([&] {
+    need(ct != nullptr, "null ciphertext");
+    if (level) *level = (uint32_t)ct->ct.level;
+    if (scale) *scale = ct->ct.scale;
+  });
+}
+
+he_status he_ct_export(const he_ct* ct, uint64_t* host, size_t words, uint32_t* level, double* scale) {
+  return guard([&] {
+    need(ct != nullptr && host != nullptr, "null argument");
+    need(words >= ct->ct.d.words, "host buffer too small");
+    HeCtxImpl& c = ct->ctx->impl;
+    hip_check(hipMemcpyAsync(host, ct->ct.d.p, ct->ct.d.words * 8, hipMemcpyDeviceToHost, c.stream), "export");
+    hip_check(hipStreamSynchronize(c.stream), "export");
+    if (level) *level = (uint32_t)ct->ct.level;
+    if (scale) *scale = ct->ct.scale;
+  });
+}
+
+he_status he_ct_import(he_ctx* ctx, const uint64_t* host, size_t words, uint32_t level, double scale, he_ct** out) {
+  return guard([&] {
+    need(ctx && host && out, "null argument");
+    HeCtxImpl& c = ctx->impl;
+    need((int)level <= c.L, "level out of range");
+    HeCt x = c.ct_new((int)level, false, scale);
+    need(words == x.d.words, "word count does not match 2*(level+1)*N");
+    hip_check(hipMemcpyAsync(x.d.p, host, words * 8, hipMemcpyHostToDevice, c.stream), "import");
+    hip_check(hipStreamSynchronize(c.stream), "import");
+    *out = wrap(ctx, std::move(x));
+  });
+}
+
+he_status he_ct_free(he_ct* ct) {
+  return guard([&] { delete ct; });
+}
+
+he_status he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    check_ct(ctx, b);
+    *out = wrap(ctx, ctx->impl.add(a->ct, b->ct, false));
+  });
+}
+he_status he_sub(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    check_ct(ctx, b);
+    *out = wrap(ctx, ctx->impl.add(a->ct, b->ct, true));
+  });
+}
+he_status he_mult(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    check_ct(ctx, b);
+    *out = wrap(ctx, ctx->impl.mult(a->ct, b->ct));
+  });
+}
+he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    *out = wrap(ctx, ctx->impl.rescale(a->ct));
+  });
+}
+he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    *out = wrap(ctx, ctx->impl.rotate(a->ct, step));
+  });
+}
+he_status he_drop_level(he_ctx* ctx, const he_ct* a, uint32_t level, he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    *out = wrap(ctx, ctx->impl.drop(a->ct, (int)level));
+  });
+}
+he_status he_pmult_slots(he_ctx* ctx, const he_ct* a, const double* z, size_t n, double pt_scale, he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    need(z && n > 0, "bad plaintext");
+    HeCtxImpl& c = ctx->impl;
+    DevBuf m = c.encode_batch(z, (int)n, 1, pt_scale);
+    *out = wrap(ctx, c.pmult_int(a->ct, (const i64*)m.p, pt_scale));
+  });
+}
+
+he_status he_lintrans(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, double weight,
+                      he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    need(kind <= 2 && d >= 2, "bad transform");
+    *out = wrap(ctx, ctx->impl.lintrans(a->ct, (int)kind, (int)d, n1 ? (int)n1 : default_n1((int)d), weight));
+  });
+}
+
+he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, const he_matmul_opts* opts,
+                    he_ct** out) {
+  return guard([&] {
+    check_ct(ctx, a);
+    check_ct(ctx, b);
+    need(out != nullptr && d >= 2, "bad arguments");
+    HeCtxImpl& c = ctx->impl;
+    int n1z, n1t;
+    opts_of(opts, (int)d, n1z, n1t);
+    hip_check(hipEventRecord(c.ev0, c.stream), "event");
+    HeCt r = c.matmul(a->ct, b->ct, (int)d, n1z, n1t);
+    hip_check(hipEventRecord(c.ev1, c.stream), "event");
+    *out = wrap(ctx, std::move(r));
+  });
+}
+
+he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const* b, const uint32_t* d,
+                          size_t count, const he_matmul_opts* opts, he_ct** out) {
+  return guard([&] {
+    need(a && b && d && out, "null argument");
+    HeCtxImpl& c = ctx->impl;
+    for (size_t i = 0; i < count; i++) {
+      check_ct(ctx, a[i]);
+      check_ct(ctx, b[i]);
+      out[i] = nullptr;
+    }
+    hip_check(hipEventRecord(c.ev0, c.stream), "event");
+    try {
+      for (size_t i = 0; i < count; i++) {
+        int n1z, n1t;
+        opts_of(opts, (int)d[i], n1z, n1t);
+        out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], n1z, n1t));
+      }
+    } catch (...) {
+      for (size_t i = 0; i < count; i++) {
+        delete out[i];
+        out[i] = nullptr;
+      }
+      throw;
+    }
+    hip_check(hipEventRecord(c.ev1, c.stream), "event");
+  });
+}
+
+he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks, uint32_t k, uint32_t d,
+                        uint64_t n_samples, const he_matmul_opts* opts, he_ct** cov) {
+  return guard([&] {
+    need(x && cov && row_blocks > 0 && k > 0 && d >= 2 && n_samples > 0, "bad arguments");
+    std::vector<const HeCt*> xs;
+    for (uint32_t i = 0; i < row_blocks * k; i++) {
+      check_ct(ctx, x[i]);
+      xs.push_back(&x[i]->ct);
+    }
+    int n1z, n1t;
+    opts_of(opts, (int)d, n1z, n1t);
+    HeCtxImpl& c = ctx->impl;
+    hip_check(hipEventRecord(c.ev0, c.stream), "event");
+    std::vector<HeCt> r = c.covariance(xs, (int)row_blocks, (int)k, (int)d, n_samples, n1z, n1t, default_n1((int)d));
+    hip_check(hipEventRecord(c.ev1, c.stream), "event");
+    for (uint32_t i = 0; i < k * k; i++) cov[i] = wrap(ctx, std::move(r[i]));
+  });
+}
+
+he_status he_sync(he_ctx* ctx) {
+  return guard([&] {
+    need(ctx != nullptr, "null context");
+    hip_check(hipStreamSynchronize(ctx->impl.stream), "sync");
+  });
+}
+
+he_status he_mem_info(const he_ctx* ctx, size_t* live, size_t* cached, size_t* peak) {
+  return guard([&] {
+    need(ctx != nullptr, "null context");
+    if (live) *live = ctx->impl.pool.bytes_live;
+    if (cached) *cached = ctx->impl.pool.bytes_cached;
+    if (peak) *peak = ctx->impl.pool.peak;
+  });
+}
+
+he_status he_ntt_limbs(he_ctx* ctx, const uint64_t* in, uint64_t* out, size_t nlimbs, const int32_t* mod_idx,
+                       int inverse) {
+  return guard([&] {
+    need(ctx && in && out && mod_idx && nlimbs > 0 && nlimbs <= 960, "bad arguments");
+    HeCtxImpl& c = ctx->impl;
+    LimbMap m;
+    m.n = (int)nlimbs;
+    for (size_t k = 0; k < nlimbs; k++) {
+      need(mod_idx[k] >= 0 && mod_idx[k] < c.nmods, "modulus index out of range");
+      m.idx[k] = (short)mod_idx[k];
+    }
+    for (size_t k = 0; k < nlimbs; k++)
+      for (u64 i = 0; i < c.N; i++) need(in[k * c.N + i] < c.mods[mod_idx[k]], "residue not reduced");
+    DevBuf d(&c.pool, nlimbs * c.N);
+    hip_check(hipMemcpyAsync(d.p, in, nlimbs * c.N * 8, hipMemcpyHostToDevice, c.stream), "upload");
+    launch_ntt(c.T, d.p, (int)nlimbs, m, inverse != 0, c.stream);
+    hip_check(hipMemcpyAsync(out, d.p, nlimbs * c.N * 8, hipMemcpyDeviceToHost, c.stream), "download");
+    hip_check(hipStreamSynchronize(c.stream), "ntt");
+  });
+}
+
+he_status he_automorph_limbs(he_ctx* ctx, const uint64_t* in, uint64_t* out, size_t nlimbs, uint64_t galois) {
+  return guard([&] {
+    need(ctx && in && out && nlimbs > 0, "bad arguments");
+    HeCtxImpl& c = ctx->impl;
+    need(galois % 2 == 1 && galois < 2 * c.N, "Galois element must be odd and below 2N");
+    DevBuf a(&c.pool, nlimbs * c.N), b(&c.pool, nlimbs * c.N);
+    hip_check(hipMemcpyAsync(a.p, in, nlimbs * c.N * 8, hipMemcpyHostToDevice, c.stream), "upload");
+    launch_automorph(c.T, b.p, a.p, (int)nlimbs, galois, c.stream);
+    hip_check(hipMemcpyAsync(out, b.p, nlimbs * c.N * 8, hipMemcpyDeviceToHost, c.stream), "download");
+    hip_check(hipStreamSynchronize(c.stream), "automorph");
+  });
+}
+
+he_status he_hoisted_rotate_export(he_ctx* ctx, const he_ct* a, int32_t step, uint64_t* host, size_t words) {
+  return guard([&] {
+    check_ct(ctx, a);
+    HeCtxImpl& c = ctx->impl;
+    u64 g = c.galois(step);
+    DevBuf dig;
+    if (g != 1) dig = c.decompose(a->ct.poly(1), a->ct.level);
+    HeCt h = c.hoisted(a->ct, dig.p, g);
+    need(words >= h.d.words, "host buffer too small");
+    hip_check(hipMemcpyAsync(host, h.d.p, h.d.words * 8, hipMemcpyDeviceToHost, c.stream), "download");
+    hip_check(hipStreamSynchronize(c.stream), "hoisted");
+  });
+}
+
+he_status he_last_op_ms(const he_ctx* ctx, double* ms) {
+  return guard([&] {
+    need(ctx && ms, "null argument");
+    float f = 0;
+    hip_check(hipEventSynchronize(ctx->impl.ev1), "event");
+    hip_check(hipEventElapsedTime(&f, ctx->impl.ev0, ctx->impl.ev1), "event");
+    *ms = f;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Internal declarations of the MI355X RNS-CKKS library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+typedef uint64_t u64;
+typedef int64_t i64;
+typedef uint32_t u32;
+
+#define HE_MAXMOD 64
+
+// ---------------------------------------------------------------------------
+// Per-modulus constants (device resident, one entry per Q or P prime)
+// ---------------------------------------------------------------------------
+struct ModConst {
+  u64 q;
+  u64 mu;      // Barrett: floor(2^(2b) / q)
+  u32 bits;    // b = bit length of q
+  u32 pad;
+  u64 ninv;    // N^{-1} mod q
+  u64 ninv_sh; // Shoup companion floor(ninv * 2^64 / q)
+  u64 r64;     // 2^64 mod q
+  u64 r64_sh;
+};
+
+// ---------------------------------------------------------------------------
+// Device modular arithmetic (64-bit residues, q < 2^61)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 mulhi64(u64 a, u64 b) { return __umul64hi(a, b); }
+
+// a*w mod q for a constant w with companion wp = floor(w 2^64 / q); any a < 2^64.
+__device__ __forceinline__ u64 shoup_mul(u64 a, u64 w, u64 wp, u64 q) {
+  u64 qh = mulhi64(a, wp);
+  u64 r = a * w - qh * q;
+  return r >= q ? r - q : r;
+}
+// lazy variant: result in [0, 2q)
+__device__ __forceinline__ u64 shoup_mul_lazy(u64 a, u64 w, u64 wp, u64 q) {
+  u64 qh = mulhi64(a, wp);
+  return a * w - qh * q;
+}
+
+// Barrett reduction of x = hi*2^64 + lo < 2^(2b) (b = bit length of q).
+__device__ __forceinline__ u64 barrett_reduce128(u64 hi, u64 lo, const ModConst& m) {
+  const u32 b = m.bits;
+  u64 t = (lo >> (b - 1)) | (hi << (65 - b));
+  u64 th = mulhi64(t, m.mu), tl = t * m.mu;
+  u64 qhat = (tl >> (b + 1)) | (th << (63 - b));
+  u64 r = lo - qhat * m.q;
+  if (r >= m.q) r -= m.q;
+  if (r >= m.q) r -= m.q;
+  return r;
+}
+// a*b mod q for a, b < q
+__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const ModConst& m) {
+  return barrett_reduce128(mulhi64(a, b), a * b, m);
+}
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
+  u64 s = a + b;
+  return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+// any 64-bit value mod q
+__device__ __forceinline__ u64 reduce64(u64 x, const ModConst& m) { return barrett_reduce128(0, x, m); }
+// signed 64-bit value mod q
+__device__ __forceinline__ u64 reduce_signed(i64 v, const ModConst& m) {
+  if (v >= 0) return reduce64((u64)v, m);
+  u64 r = reduce64((u64)(-v), m);
+  return r ? m.q - r : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side objects
+// ---------------------------------------------------------------------------
+// Stream-ordered caching pool over hipMalloc.  All work of a context runs on
+// its stream, so a block released here may be handed to a later launch on
+// the same stream immediately.
+struct DevPool {
+  std::multimap<size_t, void*> free_;
+  std::map<void*, size_t> live_;
+  size_t bytes_live = 0, bytes_cached = 0, peak = 0;
+  void* (*user_alloc)(size_t, void*) = nullptr;
+  void (*user_release)(void*, void*) = nullptr;
+  void* user = nullptr;
+  void* get(size_t bytes);
+  void put(void* p);
+  void trim();
+  ~DevPool();
+};
+
+struct DevBuf {
+  DevPool* pool = nullptr;
+  u64* p = nullptr;
+  size_t words = 0;
+  DevBuf() {}
+  DevBuf(DevPool* pl, size_t w) : pool(pl), words(w) { p = (u64*)pl->get(w * 8); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : pool(o.pool), p(o.p), words(o.words) { o.p = nullptr; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    release();
+    pool = o.pool; p = o.p; words = o.words; o.p = nullptr;
+    return *this;
+  }
+  void release() { if (p && pool) pool->put(p); p = nullptr; }
+  ~DevBuf() { release(); }
+};
+
+// A ciphertext (or an element of R_{Q_l P}^2 when qp = true): u64[2][nlimbs][N]
+struct HeCt {
+  u64 N = 0;
+  int level = 0;
+  bool qp = false;
+  int nlimbs = 0;
+  double scale = 1.0;
+  DevBuf d;
+  u64* poly(int p) const { return d.p + (size_t)p * nlimbs * N; }
+  u64* limb(int p, int k) const { return d.p + ((size_t)p * nlimbs + k) * N; }
+};

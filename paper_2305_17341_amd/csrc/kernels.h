@@ -1,0 +1,97 @@
+// Launch wrappers for the gfx950 kernels (internal).
+#pragma once
+#include "he_internal.h"
+
+// Limb batch -> modulus index map; -1 skips the limb.
+struct LimbMap {
+  int n;                 // period
+  short idx[960];
+};
+
+struct DeviceTables {
+  int logN = 0;
+  u64 N = 0;
+  int nmods = 0;
+  ModConst* mc = nullptr;      // [nmods]
+  u64* psi = nullptr;          // [nmods][N] psi^brv(k)
+  u64* psi_sh = nullptr;
+  u64* ipsi = nullptr;         // [nmods][N] psi^-brv(k)
+  u64* ipsi_sh = nullptr;
+  // double-double FFT tables for the canonical embedding
+  double* fft_tw = nullptr;    // [N/2][4] exp(-2 pi i k / N) as (re_hi, re_lo, im_hi, im_lo)
+  double* zeta = nullptr;      // [N][4] (cos(pi i/N), sin(pi i/N)) dd
+  u32* rotgroup = nullptr;     // [N/2] 5^j mod 2N
+  u64* cdt = nullptr;          // [38] Gaussian inversion table
+};
+
+// transforms
+void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s);
+
+// data movement / elementwise (data laid out [nlimbs][N], limb k uses map)
+void launch_automorph(const DeviceTables& T, u64* out, const u64* in, int nlimbs, u64 g, hipStream_t s);
+void launch_add(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nlimbs, const LimbMap& m, hipStream_t s);
+void launch_sub(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nlimbs, const LimbMap& m, hipStream_t s);
+void launch_mul(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nlimbs, const LimbMap& m, hipStream_t s);
+// out = a * b where b has period b_limbs (b limb = k % b_limbs)
+void launch_mul_bcast(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nlimbs, int b_limbs,
+                      const LimbMap& m, hipStream_t s);
+// acc += a * b (b broadcast with period b_limbs)
+void launch_mul_acc(const DeviceTables& T, u64* acc, const u64* a, const u64* b, int nlimbs, int b_limbs,
+                    const LimbMap& m, hipStream_t s);
+// out = a * c_k for a per-limb constant (host array, Shoup)
+void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const u64* consts /*[map.n]*/,
+                      const LimbMap& m, hipStream_t s);
+void launch_neg(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const LimbMap& m, hipStream_t s);
+void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, hipStream_t s);
+void launch_int_to_limbs(const DeviceTables& T, u64* out, const i64* in, int nlimbs, const LimbMap& m, hipStream_t s);
+
+// key switching pieces
+struct FbcTable {
+  // source set S (ns primes) -> any target modulus:
+  // y_a = x_a * hatinv_a mod q_a ; out_t = sum_a y_a * hat_{a,t} mod t
+  int ns = 0;
+  int src[8];
+  u64 hatinv[8], hatinv_sh[8];
+  u64* hat_t = nullptr;     // device [ns][nmods] (hat_a mod t)
+  u64* hat_t_sh = nullptr;  // device [ns][nmods]
+};
+// digits[j][pos] (pos over Q_l then P): own limbs copy ntt_in, others are the
+// coefficient-domain conversion of digit j (to be transformed by the caller)
+void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64* ntt_in, int level, int L,
+                  int alpha, int beta, const FbcTable* tabs /* host array [beta] */, hipStream_t s);
+void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, const FbcTable& tab, hipStream_t s);
+void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u64* y, int nq,
+                          const u64* pinv /*device [nmods] Shoup pairs*/, int npoly, int x_stride_limbs,
+                          hipStream_t s);
+// hoisted rotation: out[2][nqp][N] = sum_j pi_g(d_j) * key_j (+ P pi_g(c0) on Q limbs)
+void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,
+                    const u64* pmod /*device [nmods][2]*/, int level, int L, int alpha, int beta, u64 g,
+                    hipStream_t s);
+// P-lift: out[2][nqp][N] = (P c0, P c1) on Q limbs, 0 on P limbs
+void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha,
+                  hipStream_t s);
+// rescale pieces
+void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int npoly, hipStream_t s);
+void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u64* t, int l, int npoly,
+                          int x_stride_limbs, const u64* qlinv /*device [l][2]*/, hipStream_t s);
+
+// randomness (Philox4x64-10, counter = (coefficient, c1, c2, c3), key = (seed, tag))
+void launch_sample_uniform(const DeviceTables& T, u64* out, int nlimbs, const LimbMap& m, u64 seed, u64 tag,
+                           u64 c2, u64 c3, hipStream_t s);
+void launch_sample_ternary(const DeviceTables& T, i64* out, u64 seed, u64 tag, u64 c1, u64 c2, u64 c3,
+                           hipStream_t s);
+void launch_sample_gauss(const DeviceTables& T, i64* out, u64 seed, u64 tag, u64 c1, u64 c2, u64 c3,
+                         hipStream_t s);
+void launch_add_int(i64* out, const i64* a, const i64* b, u64 N, hipStream_t s);
+// switching key b part: b = e - a s (+ pmod s' on the digit's primes)
+void launch_swk_b(const DeviceTables& T, u64* b, const u64* a, const u64* e, const u64* s_ntt, const u64* sp_ntt,
+                  const u64* pmod, int nlimbs_total, int digit, int alpha, int L, hipStream_t s);
+
+// canonical embedding (double-double FFT)
+void launch_encode(const DeviceTables& T, i64* out, const double* z, int nz, int batch, double delta, void* scratch,
+                   hipStream_t s);
+size_t encode_scratch_bytes(const DeviceTables& T, int batch);
+void launch_decode(const DeviceTables& T, double* out, const i64* m, int batch, const double* inv_scale,
+                   void* scratch, hipStream_t s);
+// decryption helpers
+void launch_centre_to_int(const DeviceTables& T, i64* out, const u64* coef, int mod, hipStream_t s);

@@ -1,0 +1,767 @@
+// gfx950 kernels of the RNS-CKKS matrix-product path.
+//
+// Residues are 64-bit words in [0, q) with q < 2^61, limb-major
+// (u64[limbs][N]).  Products by constants use Shoup's method (precomputed
+// floor(w 2^64 / q)); products of two variables use Barrett reduction of the
+// 128-bit product.  Every kernel computes an exactly defined integer result,
+// so fusion and reordering never change a residue.
+#include "kernels.h"
+
+#include <cstdio>
+
+#define TPB 256
+#define NTT_LDS 4096  // u64 words of LDS per NTT work-group (32 KiB)
+
+static inline int cdiv(u64 a, u64 b) { return (int)((a + b - 1) / b); }
+
+__device__ __forceinline__ int limb_mod(const LimbMap& m, int k) { return m.idx[k % m.n]; }
+
+__device__ __forceinline__ u32 brv(u32 x, int bits) { return __brev(x) >> (32 - bits); }
+
+// ---------------------------------------------------------------------------
+// Negacyclic NTT.  Forward: natural-order coefficients -> evaluations with
+// index i holding a(psi^(2 brv(i)+1)) (Cooley-Tukey butterflies, twiddles
+// psi^brv).  Inverse: Gentleman-Sande with psi^-brv, then N^{-1}.
+//
+// The log N stages are split in two LDS passes.  With R = 2^s1 rows and
+// T1 = N / R columns: the first s1 stages pair elements of one column
+// (stride >= T1), the last s2 = log N - s1 stages pair elements inside one
+// contiguous block of T1 words.  Each pass loads a tile into LDS once, runs
+// its stages there and writes back once.
+// ---------------------------------------------------------------------------
+struct NttShape {
+  int logN, s1, R, T1, C, K;
+};
+static NttShape ntt_shape(int logN) {
+  NttShape sh;
+  sh.logN = logN;
+  sh.s1 = logN / 2;
+  sh.R = 1 << sh.s1;
+  sh.T1 = 1 << (logN - sh.s1);
+  sh.C = NTT_LDS / sh.R;
+  if (sh.C > sh.T1) sh.C = sh.T1;
+  sh.K = NTT_LDS / sh.T1;
+  if (sh.K > sh.R) sh.K = sh.R;
+  return sh;
+}
+
+// Column pass: forward stages [0, s1) / inverse stages [s2, logN).
+__global__ void __launch_bounds__(TPB) k_ntt_cols(u64* data, LimbMap map, int logN, int R, int T1, int C,
+                                                  int inverse, const u64* __restrict__ tw,
+                                                  const u64* __restrict__ twsh, const ModConst* __restrict__ mc) {
+  __shared__ u64 sh[NTT_LDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << logN;
+  u64* a = data + (size_t)limb * N;
+  const int c0 = blockIdx.x * C;
+  const int tot = R * C;
+  for (int e = threadIdx.x; e < tot; e += TPB) {
+    int r = e / C, c = e - r * C;
+    sh[e] = a[(size_t)r * T1 + c0 + c];
+  }
+  __syncthreads();
+  const ModConst mk = mc[m];
+  const u64 q = mk.q;
+  const u64* w = tw + (size_t)m * N;
+  const u64* wsh = twsh + (size_t)m * N;
+  const int nbf = tot >> 1;
+  if (!inverse) {
+    int s = 0;
+    for (int half = R >> 1; half >= 1; half >>= 1, s++) {
+      for (int b = threadIdx.x; b < nbf; b += TPB) {
+        int c = b % C, bb = b / C;
+        int i = bb / half, rr = bb - i * half;
+        int r = 2 * i * half + rr;
+        u64 W = w[(1 << s) + i], Wp = wsh[(1 << s) + i];
+        u64 U = sh[r * C + c];
+        u64 V = shoup_mul(sh[(r + half) * C + c], W, Wp, q);
+        sh[r * C + c] = add_mod(U, V, q);
+        sh[(r + half) * C + c] = sub_mod(U, V, q);
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < tot; e += TPB) {
+      int r = e / C, c = e - r * C;
+      a[(size_t)r * T1 + c0 + c] = sh[e];
+    }
+  } else {
+    // global GS stages with t = half*T1, h = R / (2 half)
+    for (int half = 1; half < R; half <<= 1) {
+      int h = R / (2 * half);
+      for (int b = threadIdx.x; b < nbf; b += TPB) {
+        int c = b % C, bb = b / C;
+        int i = bb / half, rr = bb - i * half;
+        int r = 2 * i * half + rr;
+        u64 W = w[h + i], Wp = wsh[h + i];
+        u64 U = sh[r * C + c], V = sh[(r + half) * C + c];
+        sh[r * C + c] = add_mod(U, V, q);
+        sh[(r + half) * C + c] = shoup_mul(sub_mod(U, V, q), W, Wp, q);
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < tot; e += TPB) {
+      int r = e / C, c = e - r * C;
+      a[(size_t)r * T1 + c0 + c] = shoup_mul(sh[e], mk.ninv, mk.ninv_sh, q);
+    }
+  }
+}
+
+// Block pass: forward stages [s1, logN) / inverse stages [0, s2), on K
+// contiguous blocks of T1 words per work-group.
+__global__ void __launch_bounds__(TPB) k_ntt_rows(u64* data, LimbMap map, int logN, int s1, int T1, int K,
+                                                  int inverse, const u64* __restrict__ tw,
+                                                  const u64* __restrict__ twsh, const ModConst* __restrict__ mc) {
+  __shared__ u64 sh[NTT_LDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << logN;
+  const int blk0 = blockIdx.x * K;
+  u64* a = data + (size_t)limb * N + (size_t)blk0 * T1;
+  const int tot = K * T1;
+  for (int e = threadIdx.x; e < tot; e += TPB) sh[e] = a[e];
+  __syncthreads();
+  const u64 q = mc[m].q;
+  const u64* w = tw + (size_t)m * N;
+  const u64* wsh = twsh + (size_t)m * N;
+  const int nbf = tot >> 1;
+  if (!inverse) {
+    int sp = 0;
+    for (int t = T1 >> 1; t >= 1; t >>= 1, sp++) {
+      for (int b = threadIdx.x; b < nbf; b += TPB) {
+        int blk = b / (T1 >> 1), lb = b - blk * (T1 >> 1);
+        int i = lb / t, rr = lb - i * t;
+        int lo = 2 * i * t + rr;
+        int hi = blk0 + blk;
+        int widx = (1 << (s1 + sp)) + (hi << sp) + i;
+        u64 W = w[widx], Wp = wsh[widx];
+        int x = blk * T1 + lo;
+        u64 U = sh[x];
+        u64 V = shoup_mul(sh[x + t], W, Wp, q);
+        sh[x] = add_mod(U, V, q);
+        sh[x + t] = sub_mod(U, V, q);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int t = 1; t < T1; t <<= 1) {
+      for (int b = threadIdx.x; b < nbf; b += TPB) {
+        int blk = b / (T1 >> 1), lb = b - blk * (T1 >> 1);
+        int i = lb / t, rr = lb - i * t;
+        int lo = 2 * i * t + rr;
+        int hi = blk0 + blk;
+        // global group index j/(2t) = hi*T1/(2t) + i ; h = N/(2t)
+        u64 h = N / (2 * (u64)t);
+        u64 widx = h + (u64)hi * (T1 / (2 * t)) + i;
+        u64 W = w[widx], Wp = wsh[widx];
+        int x = blk * T1 + lo;
+        u64 U = sh[x], V = sh[x + t];
+        sh[x] = add_mod(U, V, q);
+        sh[x + t] = shoup_mul(sub_mod(U, V, q), W, Wp, q);
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = threadIdx.x; e < tot; e += TPB) a[e] = sh[e];
+}
+
+void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s) {
+  if (nlimbs <= 0) return;
+  NttShape sh = ntt_shape(T.logN);
+  dim3 gc(sh.T1 / sh.C, nlimbs), gr(sh.R / sh.K, nlimbs);
+  if (!inverse) {
+    hipLaunchKernelGGL(k_ntt_cols, gc, dim3(TPB), 0, s, data, map, sh.logN, sh.R, sh.T1, sh.C, 0, T.psi,
+                       T.psi_sh, T.mc);
+    hipLaunchKernelGGL(k_ntt_rows, gr, dim3(TPB), 0, s, data, map, sh.logN, sh.s1, sh.T1, sh.K, 0, T.psi,
+                       T.psi_sh, T.mc);
+  } else {
+    hipLaunchKernelGGL(k_ntt_rows, gr, dim3(TPB), 0, s, data, map, sh.logN, sh.s1, sh.T1, sh.K, 1, T.ipsi,
+                       T.ipsi_sh, T.mc);
+    hipLaunchKernelGGL(k_ntt_cols, gc, dim3(TPB), 0, s, data, map, sh.logN, sh.R, sh.T1, sh.C, 1, T.ipsi,
+                       T.ipsi_sh, T.mc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Galois automorphism in the evaluation domain:
+//   out[i] = in[brv((g (2 brv(i) + 1) mod 2N - 1) / 2)]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u32 automorph_src(u32 i, u64 g, int logN) {
+  u64 twoN_mask = (2ull << logN) - 1;
+  u64 e = (g * (2ull * brv(i, logN) + 1)) & twoN_mask;
+  return brv((u32)((e - 1) >> 1), logN);
+}
+
+__global__ void k_automorph(u64* out, const u64* in, int nlimbs, u64 g, int logN) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  if (i >= N) return;
+  u32 src = automorph_src(i, g, logN);
+  for (int k = blockIdx.y; k < nlimbs; k += gridDim.y) out[(size_t)k * N + i] = in[(size_t)k * N + src];
+}
+
+void launch_automorph(const DeviceTables& T, u64* out, const u64* in, int nlimbs, u64 g, hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), nlimbs < 64 ? nlimbs : 64);
+  hipLaunchKernelGGL(k_automorph, grid, dim3(TPB), 0, s, out, in, nlimbs, g, T.logN);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise
+// ---------------------------------------------------------------------------
+enum { EW_ADD = 0, EW_SUB, EW_MUL, EW_MULACC, EW_NEG };
+
+__global__ void k_elementwise(int op, u64* out, const u64* a, const u64* b, int nlimbs, int b_limbs, LimbMap map,
+                              int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= N || k >= nlimbs) return;
+  int m = limb_mod(map, k);
+  if (m < 0) return;
+  const ModConst mk = mc[m];
+  size_t o = (size_t)k * N + i;
+  size_t ob = (size_t)(k % b_limbs) * N + i;
+  switch (op) {
+    case EW_ADD: out[o] = add_mod(a[o], b[ob], mk.q); break;
+    case EW_SUB: out[o] = sub_mod(a[o], b[ob], mk.q); break;
+    case EW_MUL: out[o] = mul_mod(a[o], b[ob], mk); break;
+    case EW_MULACC: out[o] = add_mod(out[o], mul_mod(a[o], b[ob], mk), mk.q); break;
+    case EW_NEG: out[o] = a[o] ? mk.q - a[o] : 0; break;
+  }
+}
+
+static void ew(const DeviceTables& T, int op, u64* out, const u64* a, const u64* b, int nlimbs, int b_limbs,
+               const LimbMap& m, hipStream_t s) {
+  if (nlimbs <= 0) return;
+  dim3 grid(cdiv(T.N, TPB), nlimbs);
+  hipLaunchKernelGGL(k_elementwise, grid, dim3(TPB), 0, s, op, out, a, b, nlimbs, b_limbs, m, T.logN, T.mc);
+}
+void launch_add(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nl, const LimbMap& m,
+                hipStream_t s) { ew(T, EW_ADD, out, a, b, nl, nl, m, s); }
+void launch_sub(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nl, const LimbMap& m,
+                hipStream_t s) { ew(T, EW_SUB, out, a, b, nl, nl, m, s); }
+void launch_mul(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nl, const LimbMap& m,
+                hipStream_t s) { ew(T, EW_MUL, out, a, b, nl, nl, m, s); }
+void launch_mul_bcast(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nl, int bl,
+                      const LimbMap& m, hipStream_t s) { ew(T, EW_MUL, out, a, b, nl, bl, m, s); }
+void launch_mul_acc(const DeviceTables& T, u64* acc, const u64* a, const u64* b, int nl, int bl, const LimbMap& m,
+                    hipStream_t s) { ew(T, EW_MULACC, acc, a, b, nl, bl, m, s); }
+void launch_neg(const DeviceTables& T, u64* out, const u64* a, int nl, const LimbMap& m, hipStream_t s) {
+  ew(T, EW_NEG, out, a, a, nl, nl, m, s);
+}
+
+struct ConstPairs {
+  u64 w[HE_MAXMOD * 2];
+};
+__global__ void k_mul_const(u64* out, const u64* a, int nlimbs, ConstPairs c, LimbMap map, int logN,
+                            const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= N || k >= nlimbs) return;
+  int m = limb_mod(map, k);
+  if (m < 0) return;
+  int ci = k % map.n;
+  size_t o = (size_t)k * N + i;
+  out[o] = shoup_mul(a[o], c.w[2 * ci], c.w[2 * ci + 1], mc[m].q);
+}
+void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const u64* consts,
+                      const LimbMap& m, hipStream_t s) {
+  ConstPairs c;
+  for (int k = 0; k < m.n && k < HE_MAXMOD; k++) {
+    c.w[2 * k] = consts[2 * k];
+    c.w[2 * k + 1] = consts[2 * k + 1];
+  }
+  dim3 grid(cdiv(T.N, TPB), nlimbs);
+  hipLaunchKernelGGL(k_mul_const, grid, dim3(TPB), 0, s, out, a, nlimbs, c, m, T.logN, T.mc);
+}
+
+// Tensor of two ciphertexts over Q_l: (a0 b0, a0 b1 + a1 b0, a1 b1)
+__global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= N) return;
+  const ModConst mk = mc[k];
+  size_t o0 = (size_t)k * N + i, o1 = (size_t)(nl + k) * N + i;
+  u64 a0 = a[o0], a1 = a[o1], b0 = b[o0], b1 = b[o1];
+  out[o0] = mul_mod(a0, b0, mk);
+  out[o1] = add_mod(mul_mod(a0, b1, mk), mul_mod(a1, b0, mk), mk.q);
+  out[(size_t)(2 * nl + k) * N + i] = mul_mod(a1, b1, mk);
+}
+void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), nl);
+  hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, s, out3, a, b, nl, T.logN, T.mc);
+}
+
+__global__ void k_int_to_limbs(u64* out, const i64* in, int nlimbs, LimbMap map, int logN,
+                               const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= N) return;
+  int m = limb_mod(map, k);
+  if (m < 0) return;
+  out[(size_t)k * N + i] = reduce_signed(in[i], mc[m]);
+}
+void launch_int_to_limbs(const DeviceTables& T, u64* out, const i64* in, int nlimbs, const LimbMap& m,
+                         hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), nlimbs);
+  hipLaunchKernelGGL(k_int_to_limbs, grid, dim3(TPB), 0, s, out, in, nlimbs, m, T.logN, T.mc);
+}
+
+// ---------------------------------------------------------------------------
+// Key switching: Decompose (ModUp), MultSum, ModDown
+// ---------------------------------------------------------------------------
+struct ModupArgs {
+  int nq, nqp, alpha, beta, L;
+  int ns[16];
+  u64 hatinv[16][4], hatinv_sh[16][4];
+  const u64* hat_t[16];
+  const u64* hat_t_sh[16];
+};
+
+// digits[j][pos][i]: coefficient-domain fast basis conversion of digit j to
+// every modulus of Q_l and P; the digit's own limbs receive the input itself.
+__global__ void k_modup(u64* digits, const u64* coef, const u64* ntt_in, ModupArgs A, int logN, int nmods,
+                        const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int j = blockIdx.y;
+  if (i >= N) return;
+  const int ns = A.ns[j];
+  u64 y[4];
+  for (int a = 0; a < ns; a++) {
+    int sm = j * A.alpha + a;
+    u64 x = coef[(size_t)sm * N + i];
+    y[a] = shoup_mul(x, A.hatinv[j][a], A.hatinv_sh[j][a], mc[sm].q);
+  }
+  for (int pos = 0; pos < A.nqp; pos++) {
+    u64* o = digits + ((size_t)j * A.nqp + pos) * N + i;
+    if (pos < A.nq && pos / A.alpha == j) {
+      *o = ntt_in[(size_t)pos * N + i];
+      continue;
+    }
+    int m = pos < A.nq ? pos : A.L + 1 + (pos - A.nq);
+    u64 q = mc[m].q, acc = 0;
+    for (int a = 0; a < ns; a++)
+      acc = add_mod(acc, shoup_mul(y[a], A.hat_t[j][(size_t)a * nmods + m], A.hat_t_sh[j][(size_t)a * nmods + m], q),
+                    q);
+    *o = acc;
+  }
+}
+
+void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64* ntt_in, int level, int L,
+                  int alpha, int beta, const FbcTable* tabs, hipStream_t s) {
+  ModupArgs A;
+  A.nq = level + 1;
+  A.nqp = level + 1 + alpha;
+  A.alpha = alpha;
+  A.beta = beta;
+  A.L = L;
+  for (int j = 0; j < beta; j++) {
+    A.ns[j] = tabs[j].ns;
+    for (int a = 0; a < tabs[j].ns; a++) {
+      A.hatinv[j][a] = tabs[j].hatinv[a];
+      A.hatinv_sh[j][a] = tabs[j].hatinv_sh[a];
+    }
+    A.hat_t[j] = tabs[j].hat_t;
+    A.hat_t_sh[j] = tabs[j].hat_t_sh;
+  }
+  dim3 grid(cdiv(T.N, TPB), beta);
+  hipLaunchKernelGGL(k_modup, grid, dim3(TPB), 0, s, digits, coef, ntt_in, A, T.logN, T.nmods, T.mc);
+}
+
+struct FbcArgs {
+  int ns;
+  int src[8];
+  u64 hatinv[8], hatinv_sh[8];
+  const u64* hat_t;
+  const u64* hat_t_sh;
+};
+// y[t][i] = sum_a [x_a hatinv_a]_{p_a} (hat_a mod q_t) mod q_t for t < nq; batch over polys (grid.z)
+__global__ void k_fbc_to_q(u64* y, const u64* xp, int nq, FbcArgs A, int logN, int nmods,
+                           const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  if (i >= N) return;
+  int poly = blockIdx.z;
+  const u64* x = xp + (size_t)poly * A.ns * N;
+  u64* yy = y + (size_t)poly * nq * N;
+  u64 v[8];
+  for (int a = 0; a < A.ns; a++) v[a] = shoup_mul(x[(size_t)a * N + i], A.hatinv[a], A.hatinv_sh[a], mc[A.src[a]].q);
+  for (int t = blockIdx.y; t < nq; t += gridDim.y) {
+    u64 q = mc[t].q, acc = 0;
+    for (int a = 0; a < A.ns; a++)
+      acc = add_mod(acc, shoup_mul(v[a], A.hat_t[(size_t)a * nmods + t], A.hat_t_sh[(size_t)a * nmods + t], q), q);
+    yy[(size_t)t * N + i] = acc;
+  }
+}
+void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, const FbcTable& tab, hipStream_t s) {
+  // (npoly encoded by the caller through repeated launches; here one poly per z)
+  FbcArgs A;
+  A.ns = tab.ns;
+  for (int a = 0; a < tab.ns; a++) {
+    A.src[a] = tab.src[a];
+    A.hatinv[a] = tab.hatinv[a];
+    A.hatinv_sh[a] = tab.hatinv_sh[a];
+  }
+  A.hat_t = tab.hat_t;
+  A.hat_t_sh = tab.hat_t_sh;
+  dim3 grid(cdiv(T.N, TPB), nq < 8 ? nq : 8, 2);
+  hipLaunchKernelGGL(k_fbc_to_q, grid, dim3(TPB), 0, s, y, xp_coef, nq, A, T.logN, T.nmods, T.mc);
+}
+
+// out[p][t] = (x[p][t] - y[p][t]) * P^{-1} mod q_t   (p < npoly, t < nq)
+__global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, const u64* pinv, int x_stride_limbs,
+                                int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int t = blockIdx.y, p = blockIdx.z;
+  if (i >= N) return;
+  u64 q = mc[t].q;
+  u64 d = sub_mod(x[((size_t)p * x_stride_limbs + t) * N + i], y[((size_t)p * nq + t) * N + i], q);
+  out[((size_t)p * nq + t) * N + i] = shoup_mul(d, pinv[2 * t], pinv[2 * t + 1], q);
+}
+void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u64* y, int nq, const u64* pinv,
+                          int npoly, int x_stride_limbs, hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), nq, npoly);
+  hipLaunchKernelGGL(k_moddown_final, grid, dim3(TPB), 0, s, out, x, y, nq, pinv, x_stride_limbs, T.logN, T.mc);
+}
+
+// Hoisted rotation in R_{Q_l P}: for each limb pos and both key halves,
+//   out = sum_j pi_g(d_j) * swk_j  (+ P * pi_g(c0) on the Q limbs of the b half)
+__global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict__ digits,
+                                                 const u64* __restrict__ key, const u64* __restrict__ c0,
+                                                 const u64* __restrict__ pmod, int nq, int nqp, int L, int beta,
+                                                 int nmods, u64 g, int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int pos = blockIdx.y;
+  if (i >= N) return;
+  int m = pos < nq ? pos : L + 1 + (pos - nq);
+  const ModConst mk = mc[m];
+  u32 src = g == 1 ? i : automorph_src(i, g, logN);
+  u64 acc0 = 0, acc1 = 0;
+  for (int j = 0; j < beta; j++) {
+    u64 d = digits[((size_t)j * nqp + pos) * N + src];
+    u64 kb = key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
+    u64 ka = key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
+    acc0 = add_mod(acc0, mul_mod(d, kb, mk), mk.q);
+    acc1 = add_mod(acc1, mul_mod(d, ka, mk), mk.q);
+  }
+  if (c0 && pos < nq) {
+    u64 v = c0[(size_t)pos * N + src];
+    acc0 = add_mod(acc0, shoup_mul(v, pmod[2 * m], pmod[2 * m + 1], mk.q), mk.q);
+  }
+  out[(size_t)pos * N + i] = acc0;
+  out[((size_t)nqp + pos) * N + i] = acc1;
+}
+void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,
+                    const u64* pmod, int level, int L, int alpha, int beta, u64 g, hipStream_t s) {
+  int nq = level + 1, nqp = nq + alpha;
+  dim3 grid(cdiv(T.N, TPB), nqp);
+  hipLaunchKernelGGL(k_multsum, grid, dim3(TPB), 0, s, out, digits, key, c0, pmod, nq, nqp, L, beta, T.nmods, g,
+                     T.logN, T.mc);
+}
+
+// P-lift: out[p][pos] = P * c[p][pos] (pos < nq), 0 on P limbs
+__global__ void k_plift(u64* out, const u64* c, const u64* pmod, int nq, int nqp, int logN,
+                        const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int pos = blockIdx.y, p = blockIdx.z;
+  if (i >= N) return;
+  u64 v = 0;
+  if (pos < nq) v = shoup_mul(c[((size_t)p * nq + pos) * N + i], pmod[2 * pos], pmod[2 * pos + 1], mc[pos].q);
+  out[((size_t)p * nqp + pos) * N + i] = v;
+}
+void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha,
+                  hipStream_t s) {
+  int nq = level + 1, nqp = nq + alpha;
+  dim3 grid(cdiv(T.N, TPB), nqp, 2);
+  hipLaunchKernelGGL(k_plift, grid, dim3(TPB), 0, s, out, c, pmod, nq, nqp, T.logN, T.mc);
+}
+
+// ---------------------------------------------------------------------------
+// Rescale: t_i = [x_l]_{q_l} mod q_i (centred top limb), out_i = (x_i - t_i) q_l^{-1}
+// ---------------------------------------------------------------------------
+__global__ void k_rescale_lift(u64* t, const u64* top, int l, int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y, p = blockIdx.z;
+  if (i >= N) return;
+  u64 ql = mc[l].q;
+  u64 x = top[(size_t)p * N + i];
+  const ModConst mk = mc[k];
+  u64 v;
+  if (x > (ql >> 1)) {
+    u64 r = reduce64(ql - x, mk);
+    v = r ? mk.q - r : 0;
+  } else {
+    v = reduce64(x, mk);
+  }
+  t[((size_t)p * l + k) * N + i] = v;
+}
+void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int npoly, hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), l, npoly);
+  hipLaunchKernelGGL(k_rescale_lift, grid, dim3(TPB), 0, s, t, top_coef, l, T.logN, T.mc);
+}
+__global__ void k_rescale_final(u64* out, const u64* x, const u64* t, int l, int x_stride_limbs, const u64* qlinv,
+                                int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y, p = blockIdx.z;
+  if (i >= N) return;
+  u64 q = mc[k].q;
+  u64 d = sub_mod(x[((size_t)p * x_stride_limbs + k) * N + i], t[((size_t)p * l + k) * N + i], q);
+  out[((size_t)p * l + k) * N + i] = shoup_mul(d, qlinv[2 * k], qlinv[2 * k + 1], q);
+}
+void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u64* t, int l, int npoly,
+                          int x_stride_limbs, const u64* qlinv, hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), l, npoly);
+  hipLaunchKernelGGL(k_rescale_final, grid, dim3(TPB), 0, s, out, x, t, l, x_stride_limbs, qlinv, T.logN, T.mc);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11) and the samplers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64(u64 c[4], u64 k0, u64 k1) {
+  const u64 M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const u64 W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    if (r) { k0 += W0; k1 += W1; }
+    u64 hi0 = mulhi64(M0, c[0]), lo0 = M0 * c[0];
+    u64 hi1 = mulhi64(M1, c[2]), lo1 = M1 * c[2];
+    u64 n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+// uniform residues drawn directly in the evaluation domain:
+// counter (i, modulus index, c2, c3); value (w0 2^64 + w1) mod q
+__global__ void k_sample_uniform(u64* out, int nlimbs, LimbMap map, u64 seed, u64 tag, u64 c2, u64 c3, int logN,
+                                 const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= N) return;
+  int m = limb_mod(map, k);
+  if (m < 0) return;
+  u64 c[4] = {i, (u64)m, c2, c3};
+  philox4x64(c, seed, tag);
+  const ModConst mk = mc[m];
+  u64 hi = reduce64(c[0], mk);
+  u64 v = add_mod(shoup_mul(hi, mk.r64, mk.r64_sh, mk.q), reduce64(c[1], mk), mk.q);
+  out[(size_t)k * N + i] = v;
+}
+void launch_sample_uniform(const DeviceTables& T, u64* out, int nlimbs, const LimbMap& m, u64 seed, u64 tag, u64 c2,
+                           u64 c3, hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), nlimbs);
+  hipLaunchKernelGGL(k_sample_uniform, grid, dim3(TPB), 0, s, out, nlimbs, m, seed, tag, c2, c3, T.logN, T.mc);
+}
+
+__global__ void k_sample_small(i64* out, int kind, u64 seed, u64 tag, u64 c1, u64 c2, u64 c3, int logN,
+                               const u64* __restrict__ cdt) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  if (i >= N) return;
+  u64 c[4] = {i, c1, c2, c3};
+  philox4x64(c, seed, tag);
+  i64 v;
+  if (kind == 0) {
+    v = (i64)(c[0] % 3) - 1;
+  } else {
+    v = -19;
+    for (int k = 0; k < 38; k++) v += c[0] >= cdt[k] ? 1 : 0;
+  }
+  out[i] = v;
+}
+void launch_sample_ternary(const DeviceTables& T, i64* out, u64 seed, u64 tag, u64 c1, u64 c2, u64 c3,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_small, dim3(cdiv(T.N, TPB)), dim3(TPB), 0, s, out, 0, seed, tag, c1, c2, c3, T.logN,
+                     T.cdt);
+}
+void launch_sample_gauss(const DeviceTables& T, i64* out, u64 seed, u64 tag, u64 c1, u64 c2, u64 c3,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_small, dim3(cdiv(T.N, TPB)), dim3(TPB), 0, s, out, 1, seed, tag, c1, c2, c3, T.logN,
+                     T.cdt);
+}
+__global__ void k_add_int(i64* out, const i64* a, const i64* b, u64 N) {
+  u64 i = (u64)blockIdx.x * TPB + threadIdx.x;
+  if (i < N) out[i] = a[i] + b[i];
+}
+void launch_add_int(i64* out, const i64* a, const i64* b, u64 N, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_int, dim3(cdiv(N, TPB)), dim3(TPB), 0, s, out, a, b, N);
+}
+
+// b = e - a s (+ (P mod q) s' on the primes of digit `digit`)
+__global__ void k_swk_b(u64* b, const u64* a, const u64* e, const u64* s_ntt, const u64* sp_ntt, const u64* pmod,
+                        int digit, int alpha, int L, int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int m = blockIdx.y;
+  if (i >= N) return;
+  const ModConst mk = mc[m];
+  size_t o = (size_t)m * N + i;
+  u64 v = sub_mod(e[o], mul_mod(a[o], s_ntt[o], mk), mk.q);
+  if (sp_ntt && m <= L && m / alpha == digit) v = add_mod(v, mul_mod(pmod[2 * m], sp_ntt[o], mk), mk.q);
+  b[o] = v;
+}
+void launch_swk_b(const DeviceTables& T, u64* b, const u64* a, const u64* e, const u64* s_ntt, const u64* sp_ntt,
+                  const u64* pmod, int nlimbs_total, int digit, int alpha, int L, hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), nlimbs_total);
+  hipLaunchKernelGGL(k_swk_b, grid, dim3(TPB), 0, s, b, a, e, s_ntt, sp_ntt, pmod, digit, alpha, L, T.logN, T.mc);
+}
+
+// centred integer of one coefficient-domain limb
+__global__ void k_centre(i64* out, const u64* coef, int m, int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  if (i >= N) return;
+  u64 q = mc[m].q, x = coef[i];
+  out[i] = x > (q >> 1) ? -(i64)(q - x) : (i64)x;
+}
+void launch_centre_to_int(const DeviceTables& T, i64* out, const u64* coef, int mod, hipStream_t s) {
+  hipLaunchKernelGGL(k_centre, dim3(cdiv(T.N, TPB)), dim3(TPB), 0, s, out, coef, mod, T.logN, T.mc);
+}
+
+// ---------------------------------------------------------------------------
+// Canonical embedding in double-double arithmetic (Dekker / Knuth error-free
+// transformations).  Encoding computes
+//   v_i = (Delta / N) Re( zeta^-i sum_t u[t] w^(-t i) ),   m_i = floor(v_i + 1/2 + 2^-30)
+// with u[t] = z_j at the odd exponents 2t+1 = +-5^j mod 2N.
+// ---------------------------------------------------------------------------
+struct dd { double hi, lo; };
+struct cdd { dd re, im; };
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd quick_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi), t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = quick_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+  double p = a.hi * b.hi;
+  double e = fma(a.hi, b.hi, -p);
+  e += a.hi * b.lo + a.lo * b.hi;
+  return quick_two_sum(p, e);
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double b) {
+  double p = a.hi * b;
+  double e = fma(a.hi, b, -p);
+  e += a.lo * b;
+  return quick_two_sum(p, e);
+}
+__device__ __forceinline__ cdd cdd_mul(cdd a, cdd b) {
+  return {dd_add(dd_mul(a.re, b.re), dd_neg(dd_mul(a.im, b.im))), dd_add(dd_mul(a.re, b.im), dd_mul(a.im, b.re))};
+}
+__device__ __forceinline__ cdd cdd_add(cdd a, cdd b) { return {dd_add(a.re, b.re), dd_add(a.im, b.im)}; }
+__device__ __forceinline__ cdd cdd_sub(cdd a, cdd b) { return {dd_add(a.re, dd_neg(b.re)), dd_add(a.im, dd_neg(b.im))}; }
+
+// scatter the message into bit-reversed FFT input order
+__global__ void k_enc_scatter(cdd* x, const double* z, int nz, int batch, int logN, const u32* rotgroup) {
+  const u64 N = 1ull << logN, S = N >> 1;
+  u64 j = (u64)blockIdx.x * TPB + threadIdx.x;
+  int b = blockIdx.y;
+  if (j >= S) return;
+  double v = z[(size_t)b * nz + (j % nz)];
+  u32 e = rotgroup[j];
+  u32 t1 = (e - 1) >> 1, t2 = (u32)((2 * N - e - 1) >> 1);
+  cdd val = {{v, 0.0}, {0.0, 0.0}};
+  x[(size_t)b * N + brv(t1, logN)] = val;
+  x[(size_t)b * N + brv(t2, logN)] = val;
+}
+
+// one radix-2 stage of an in-place DIT FFT (input in bit-reversed order);
+// sign = -1 uses exp(-2 pi i k/N), +1 its conjugate
+__global__ void k_fft_stage(cdd* x, int logN, int len, int sign, const double* tw) {
+  const u64 N = 1ull << logN;
+  u64 t = (u64)blockIdx.x * TPB + threadIdx.x;
+  int b = blockIdx.y;
+  if (t >= N / 2) return;
+  int half = len >> 1;
+  u64 blk = t / half, k = t % half;
+  u64 i0 = blk * len + k, i1 = i0 + half;
+  u64 ti = k * (N / len);
+  const double* w4 = tw + 4 * ti;
+  cdd w = {{w4[0], w4[1]}, {sign < 0 ? w4[2] : -w4[2], sign < 0 ? w4[3] : -w4[3]}};
+  cdd* xb = x + (size_t)b * N;
+  cdd a = xb[i0], c = cdd_mul(xb[i1], w);
+  xb[i0] = cdd_add(a, c);
+  xb[i1] = cdd_sub(a, c);
+}
+
+__global__ void k_enc_finish(i64* out, const cdd* x, double delta_over_n, int logN, const double* zeta) {
+  const u64 N = 1ull << logN;
+  u64 i = (u64)blockIdx.x * TPB + threadIdx.x;
+  int b = blockIdx.y;
+  if (i >= N) return;
+  cdd U = x[(size_t)b * N + i];
+  dd c = {zeta[4 * i], zeta[4 * i + 1]}, s = {zeta[4 * i + 2], zeta[4 * i + 3]};
+  // Re(zeta^-i U) = Re(U) cos + Im(U) sin
+  dd re = dd_add(dd_mul(U.re, c), dd_mul(U.im, s));
+  dd v = dd_mul_d(re, delta_over_n);
+  dd w = dd_add(v, dd{0.500000000931322574615478515625, 0.0});  // 1/2 + 2^-30, exact
+  double f = floor(w.hi);
+  i64 r = (i64)f;
+  if (f == w.hi && w.lo < 0.0) r -= 1;
+  out[(size_t)b * N + i] = r;
+}
+
+size_t encode_scratch_bytes(const DeviceTables& T, int batch) { return (size_t)batch * T.N * sizeof(cdd); }
+
+void launch_encode(const DeviceTables& T, i64* out, const double* z, int nz, int batch, double delta, void* scratch,
+                   hipStream_t s) {
+  cdd* x = (cdd*)scratch;  // every entry is written by the scatter (+-5^j cover all odd residues)
+  hipLaunchKernelGGL(k_enc_scatter, dim3(cdiv(T.N / 2, TPB), batch), dim3(TPB), 0, s, x, z, nz, batch, T.logN,
+                     T.rotgroup);
+  for (int len = 2; len <= (int)T.N; len <<= 1)
+    hipLaunchKernelGGL(k_fft_stage, dim3(cdiv(T.N / 2, TPB), batch), dim3(TPB), 0, s, x, T.logN, len, -1, T.fft_tw);
+  hipLaunchKernelGGL(k_enc_finish, dim3(cdiv(T.N, TPB), batch), dim3(TPB), 0, s, out, x, delta / (double)T.N,
+                     T.logN, T.zeta);
+}
+
+// decoding: y[t] = sum_i (m_i zeta^i) w^(t i); z_j = Re(y[(5^j - 1)/2]) / scale
+__global__ void k_dec_scatter(cdd* x, const i64* m, int logN, const double* zeta) {
+  const u64 N = 1ull << logN;
+  u64 i = (u64)blockIdx.x * TPB + threadIdx.x;
+  int b = blockIdx.y;
+  if (i >= N) return;
+  i64 v = m[(size_t)b * N + i];
+  double hi = (double)v;
+  double lo = (double)(v - (i64)hi);
+  dd mv = quick_two_sum(hi, lo);
+  dd c = {zeta[4 * i], zeta[4 * i + 1]}, s = {zeta[4 * i + 2], zeta[4 * i + 3]};
+  x[(size_t)b * N + brv((u32)i, logN)] = {dd_mul(mv, c), dd_mul(mv, s)};
+}
+__global__ void k_dec_gather(double* out, const cdd* x, int logN, const u32* rotgroup, const double* inv_scale) {
+  const u64 N = 1ull << logN, S = N >> 1;
+  u64 j = (u64)blockIdx.x * TPB + threadIdx.x;
+  int b = blockIdx.y;
+  if (j >= S) return;
+  cdd y = x[(size_t)b * N + ((rotgroup[j] - 1) >> 1)];
+  out[(size_t)b * S + j] = (y.re.hi + y.re.lo) * inv_scale[b];
+}
+void launch_decode(const DeviceTables& T, double* out, const i64* m, int batch, const double* inv_scale,
+                   void* scratch, hipStream_t s) {
+  cdd* x = (cdd*)scratch;
+  hipLaunchKernelGGL(k_dec_scatter, dim3(cdiv(T.N, TPB), batch), dim3(TPB), 0, s, x, m, T.logN, T.zeta);
+  for (int len = 2; len <= (int)T.N; len <<= 1)
+    hipLaunchKernelGGL(k_fft_stage, dim3(cdiv(T.N / 2, TPB), batch), dim3(TPB), 0, s, x, T.logN, len, +1, T.fft_tw);
+  hipLaunchKernelGGL(k_dec_gather, dim3(cdiv(T.N / 2, TPB), batch), dim3(TPB), 0, s, out, x, T.logN, T.rotgroup,
+                     inv_scale);
+}

@@ -1,0 +1,116 @@
+// Host runtime declarations (internal).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/he_mi355x.h"
+#include "kernels.h"
+
+struct HeError {
+  he_status st;
+  std::string msg;
+};
+[[noreturn]] inline void fail(he_status st, const std::string& m) { throw HeError{st, m}; }
+void hip_check(hipError_t e, const char* what);
+extern thread_local std::string g_last_error;
+u64 shoup_pre(u64 w, u64 q);
+
+// randomness stream tags (Philox key = (seed, tag))
+enum { TAG_SK = 1, TAG_PK_A = 2, TAG_PK_E = 3, TAG_SWK_A = 4, TAG_SWK_E = 5, TAG_ENC_V = 6, TAG_ENC_E0 = 7,
+       TAG_ENC_E1 = 8 };
+
+enum { LT_SIGMA = 0, LT_TAU = 1, LT_TRANSPOSE = 2 };
+
+struct LtGeom {
+  int a, n1, i_lo, i_hi;
+};
+LtGeom lt_geom(int kind, int n, int n1);
+std::vector<int> make_perm(int kind, int n);
+int default_n1(int n);
+std::vector<long> matmul_steps(int n, int n1z, int n1t);
+std::vector<long> transpose_steps(int n, int n1);
+
+struct HeCtxImpl {
+  int logN = 0;
+  u64 N = 0;
+  int L = 0, alpha = 0, beta = 0, nmods = 0;
+  u64 mods[HE_MAXMOD];
+  double delta = 0, sigma = 0;
+  u64 seed = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevPool pool;
+  DeviceTables T;
+  std::vector<ModConst> mc;
+  std::vector<DevBuf> tables;
+  std::vector<std::vector<FbcTable>> up;  // [level][digit]
+  FbcTable down;                          // P -> Q
+  DevBuf pmod, pinv, qlinv;
+  DevBuf s_ntt, pk;
+  bool have_sk = false;
+  std::map<u64, DevBuf> keys;             // Galois element -> key; 0 = relinearisation
+  std::map<std::string, DevBuf> ptcache;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0;
+  long n_decompose = 0, n_multsum = 0, n_moddown = 0;
+
+  ~HeCtxImpl();
+  void init(const he_params* p, const he_device* dev, u64 seed);
+
+  int nq_of(int level) const { return level + 1; }
+  int nqp_of(int level) const { return level + 1 + alpha; }
+  int beta_at(int level) const { return (level + alpha) / alpha; }
+  int qp_mod(int level, int pos) const { return pos <= level ? pos : L + 1 + (pos - level - 1); }
+  LimbMap qmap(int nq) const;
+  LimbMap qpmap(int level) const;
+  LimbMap one(int mod) const;
+  u64 galois(long step) const;
+  u64* table_upload(const void* host, size_t bytes);
+
+  HeCt ct_new(int level, bool qp, double scale);
+  HeCt ct_copy(const HeCt& x);
+  void copy_limbs(u64* dst, const u64* src, size_t nlimbs);
+
+  DevBuf encode_batch(const double* z_host, int nz, int batch, double delta);
+  void int_to_ntt(u64* out, const i64* m, const LimbMap& map);
+
+  void keygen_secret();
+  void swk_gen(const u64* sp, u64 kid, DevBuf& out);
+  void keygen_relin();
+  void keygen_rot(long step);
+  const DevBuf& key(u64 g);
+
+  HeCt encrypt_int(const i64* m_dev, int level, double scale, u64 nonce);
+  HeCt encrypt(const double* z, int nz, int level, u64 nonce);
+  std::vector<double> decrypt(const HeCt& c);
+
+  HeCt add(const HeCt& a, const HeCt& b, bool sub);
+  void add_into(HeCt& acc, const HeCt& b);
+  HeCt drop(const HeCt& a, int level);
+  HeCt rescale(const HeCt& a);
+  DevBuf decompose(const u64* d, int level);
+  HeCt hoisted(const HeCt& x, const u64* digits, u64 g);
+  HeCt moddown(const HeCt& x);
+  HeCt keyswitch(const u64* d, int level, u64 g_key);
+  HeCt mult(const HeCt& a, const HeCt& b);
+  HeCt rotate(const HeCt& x, long step);
+  HeCt pmult_int(const HeCt& a, const i64* m_dev, double pt_scale);
+
+  std::vector<const u64*> plaintexts(const std::vector<std::string>& keys, const std::vector<std::vector<double>>& vecs,
+                                     int n2, int level, bool qp, double scale);
+  HeCt lintrans(const HeCt& x, int kind, int n, int n1, double weight);
+  HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t);
+  std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, double weight);
+  std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t);
+  void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
+  std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,
+                               int n1t, int n1g);
+};
+
+struct he_ctx {
+  HeCtxImpl impl;
+};
+struct he_ct {
+  he_ctx* ctx;
+  HeCt ct;
+};

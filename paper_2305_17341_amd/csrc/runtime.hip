@@ -1,0 +1,994 @@
+// Host runtime of the MI355X RNS-CKKS library: parameters and tables, device
+// memory, key generation, the CKKS operations, the double-hoisted linear
+// transforms and Jiang's matrix product.  The C ABI wrappers live in abi.hip.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <set>
+
+extern "C" void he_host_dd_tables(int logN, double* fft_tw, double* zeta);
+
+typedef unsigned __int128 u128;
+
+thread_local std::string g_last_error;
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(HE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// device memory pool
+// ---------------------------------------------------------------------------
+void* DevPool::get(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  bytes = (bytes + 255) & ~(size_t)255;
+  auto it = free_.lower_bound(bytes);
+  if (it != free_.end() && it->first <= bytes + bytes / 4) {
+    void* p = it->second;
+    size_t sz = it->first;
+    free_.erase(it);
+    bytes_cached -= sz;
+    live_[p] = sz;
+    bytes_live += sz;
+    peak = std::max(peak, bytes_live);
+    return p;
+  }
+  void* p = nullptr;
+  for (int attempt = 0; attempt < 2; attempt++) {
+    if (user_alloc) {
+      p = user_alloc(bytes, user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (p) break;
+    trim();
+  }
+  if (!p) fail(HE_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  live_[p] = bytes;
+  bytes_live += bytes;
+  peak = std::max(peak, bytes_live);
+  return p;
+}
+void DevPool::put(void* p) {
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  size_t sz = it->second;
+  live_.erase(it);
+  bytes_live -= sz;
+  free_.insert({sz, p});
+  bytes_cached += sz;
+}
+void DevPool::trim() {
+  (void)hipDeviceSynchronize();
+  for (auto& kv : free_) {
+    if (user_release) user_release(kv.second, user);
+    else (void)hipFree(kv.second);
+  }
+  free_.clear();
+  bytes_cached = 0;
+}
+DevPool::~DevPool() {
+  trim();
+  for (auto& kv : live_) {
+    if (user_release) user_release(kv.first, user);
+    else (void)hipFree(kv.first);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host number theory
+// ---------------------------------------------------------------------------
+static u64 hmul(u64 a, u64 b, u64 q) { return (u64)((u128)a * b % q); }
+static u64 hpow(u64 b, u64 e, u64 q) {
+  u64 r = 1 % q;
+  b %= q;
+  for (; e; e >>= 1) {
+    if (e & 1) r = hmul(r, b, q);
+    b = hmul(b, b, q);
+  }
+  return r;
+}
+static u64 hinv(u64 a, u64 q) { return hpow(a % q, q - 2, q); }
+u64 shoup_pre(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+
+static bool miller_rabin(u64 n) {
+  if (n < 4) return n == 2 || n == 3;
+  if (!(n & 1)) return false;
+  u64 d = n - 1;
+  int r = 0;
+  while (!(d & 1)) { d >>= 1; r++; }
+  static const u64 bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (u64 a : bases) {
+    if (a % n == 0) continue;
+    u64 x = hpow(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool composite = true;
+    for (int k = 1; k < r && composite; k++) {
+      x = hmul(x, x, n);
+      if (x == n - 1) composite = false;
+    }
+    if (composite) return false;
+  }
+  return true;
+}
+
+static u32 brv_host(u32 x, int bits) {
+  u32 r = 0;
+  for (int i = 0; i < bits; i++) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// context construction
+// ---------------------------------------------------------------------------
+HeCtxImpl::~HeCtxImpl() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  ptcache.clear();
+  keys.clear();
+  s_ntt.release();
+  pk.release();
+  tables.clear();
+  for (auto& row : up)
+    for (auto& t : row) (void)t;
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+LimbMap HeCtxImpl::qmap(int nq) const {
+  LimbMap m;
+  m.n = nq;
+  for (int k = 0; k < nq; k++) m.idx[k] = (short)k;
+  return m;
+}
+LimbMap HeCtxImpl::qpmap(int level) const {
+  LimbMap m;
+  m.n = nqp_of(level);
+  for (int k = 0; k < m.n; k++) m.idx[k] = (short)qp_mod(level, k);
+  return m;
+}
+LimbMap HeCtxImpl::one(int mod) const {
+  LimbMap m;
+  m.n = 1;
+  m.idx[0] = (short)mod;
+  return m;
+}
+u64 HeCtxImpl::galois(long step) const {
+  long S = (long)(N / 2);
+  long r = ((step % S) + S) % S;
+  u64 g = 1;
+  for (long i = 0; i < r; i++) g = (g * 5) % (2 * N);
+  return g;
+}
+u64* HeCtxImpl::table_upload(const void* host, size_t bytes) {
+  tables.emplace_back(&pool, (bytes + 7) / 8);
+  hip_check(hipMemcpy(tables.back().p, host, bytes, hipMemcpyHostToDevice), "table upload");
+  return tables.back().p;
+}
+
+// Setparams (Appendix A): for each bit size the candidates 1 + t 2N below
+// 2^bits are scanned downward; Q takes them first, then P.
+static void choose_primes(int logN, const std::vector<int>& bits, u64* out) {
+  u64 twoN = 2ull << logN;
+  std::map<int, u64> cursor;
+  for (size_t k = 0; k < bits.size(); k++) {
+    int b = bits[k];
+    if (!cursor.count(b)) cursor[b] = ((1ull << b) - 2) / twoN;
+    for (;;) {
+      u64 t = cursor[b];
+      if (t == 0) fail(HE_EINVAL, "no NTT-friendly prime left");
+      cursor[b] = t - 1;
+      u64 q = t * twoN + 1;
+      if (q < (1ull << (b - 1))) fail(HE_EINVAL, "not enough NTT-friendly primes of this size");
+      if (miller_rabin(q)) {
+        out[k] = q;
+        break;
+      }
+    }
+  }
+}
+
+// smallest x >= 2 whose (q-1)/2N-th power has order exactly 2N
+static u64 root_2n(u64 q, int logN) {
+  u64 N = 1ull << logN;
+  for (u64 x = 2;; x++) {
+    u64 r = hpow(x, (q - 1) / (2 * N), q);
+    if (hpow(r, N, q) == q - 1) return r;
+  }
+}
+
+static FbcTable make_fbc(HeCtxImpl* c, const std::vector<int>& src) {
+  FbcTable t;
+  t.ns = (int)src.size();
+  std::vector<u64> hat((size_t)t.ns * c->nmods), hat_sh((size_t)t.ns * c->nmods);
+  for (int a = 0; a < t.ns; a++) {
+    t.src[a] = src[a];
+    u64 qa = c->mods[src[a]];
+    u64 h = 1;
+    for (int b = 0; b < t.ns; b++)
+      if (b != a) h = hmul(h, c->mods[src[b]] % qa, qa);
+    t.hatinv[a] = hinv(h, qa);
+    t.hatinv_sh[a] = shoup_pre(t.hatinv[a], qa);
+    for (int m = 0; m < c->nmods; m++) {
+      u64 qt = c->mods[m], ht = 1;
+      for (int b = 0; b < t.ns; b++)
+        if (b != a) ht = hmul(ht, c->mods[src[b]] % qt, qt);
+      hat[(size_t)a * c->nmods + m] = ht;
+      hat_sh[(size_t)a * c->nmods + m] = shoup_pre(ht, qt);
+    }
+  }
+  t.hat_t = c->table_upload(hat.data(), hat.size() * 8);
+  t.hat_t_sh = c->table_upload(hat_sh.data(), hat_sh.size() * 8);
+  return t;
+}
+
+void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
+  if (!p || p->log_n < 10 || p->log_n > 16) fail(HE_EINVAL, "log_n must be in [10, 16]");
+  if (p->n_q < 1 || p->n_q > 48 || p->n_p < 1 || p->n_p > 4) fail(HE_EINVAL, "1..48 Q primes and 1..4 P primes");
+  logN = (int)p->log_n;
+  N = 1ull << logN;
+  L = (int)p->n_q - 1;
+  alpha = (int)p->n_p;
+  beta = (L + alpha) / alpha;
+  if (beta > 16) fail(HE_EINVAL, "at most 16 decomposition digits");
+  nmods = L + 1 + alpha;
+  std::vector<int> bits;
+  for (u32 k = 0; k < p->n_q; k++) bits.push_back((int)p->q_bits[k]);
+  for (u32 k = 0; k < p->n_p; k++) bits.push_back((int)p->p_bits[k]);
+  for (int b : bits)
+    if (b < 30 || b > 61) fail(HE_EINVAL, "prime sizes must be 30..61 bits");
+  choose_primes(logN, bits, mods);
+  delta = std::pow(2.0, p->log2_scale);
+  sigma = p->sigma;
+  seed = seed_;
+
+  if (dev) {
+    pool.user_alloc = dev->alloc;
+    pool.user_release = dev->release;
+    pool.user = dev->user;
+    stream = (hipStream_t)dev->hip_stream;
+  }
+  if (!stream) {
+    hip_check(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "stream");
+    own_stream = true;
+  }
+  hip_check(hipEventCreate(&ev0), "event");
+  hip_check(hipEventCreate(&ev1), "event");
+
+  // per-modulus constants and NTT twiddles (Shoup pairs)
+  mc.resize(nmods);
+  std::vector<u64> psi((size_t)nmods * N), psi_sh((size_t)nmods * N), ipsi((size_t)nmods * N),
+      ipsi_sh((size_t)nmods * N);
+  for (int m = 0; m < nmods; m++) {
+    u64 q = mods[m];
+    ModConst& k = mc[m];
+    k.q = q;
+    k.bits = 64 - __builtin_clzll(q);
+    k.mu = (u64)(((u128)1 << (2 * k.bits)) / q);
+    k.ninv = hinv(N % q, q);
+    k.ninv_sh = shoup_pre(k.ninv, q);
+    k.r64 = (u64)(((u128)1 << 64) % q);
+    k.r64_sh = shoup_pre(k.r64, q);
+    u64 w = root_2n(q, logN), wi = hinv(w, q);
+    for (u64 i = 0; i < N; i++) {
+      u32 e = brv_host((u32)i, logN);
+      u64 a = hpow(w, e, q), b = hpow(wi, e, q);
+      psi[(size_t)m * N + i] = a;
+      psi_sh[(size_t)m * N + i] = shoup_pre(a, q);
+      ipsi[(size_t)m * N + i] = b;
+      ipsi_sh[(size_t)m * N + i] = shoup_pre(b, q);
+    }
+  }
+  T.logN = logN;
+  T.N = N;
+  T.nmods = nmods;
+  T.mc = (ModConst*)table_upload(mc.data(), sizeof(ModConst) * nmods);
+  T.psi = table_upload(psi.data(), psi.size() * 8);
+  T.psi_sh = table_upload(psi_sh.data(), psi_sh.size() * 8);
+  T.ipsi = table_upload(ipsi.data(), ipsi.size() * 8);
+  T.ipsi_sh = table_upload(ipsi_sh.data(), ipsi_sh.size() * 8);
+
+  // canonical embedding tables
+  std::vector<double> tw(N / 2 * 4), zt(N * 4);
+  he_host_dd_tables(logN, tw.data(), zt.data());
+  T.fft_tw = (double*)table_upload(tw.data(), tw.size() * 8);
+  T.zeta = (double*)table_upload(zt.data(), zt.size() * 8);
+  std::vector<u32> rg(N / 2);
+  u64 g = 1;
+  for (u64 j = 0; j < N / 2; j++) {
+    rg[j] = (u32)g;
+    g = (g * 5) % (2 * N);
+  }
+  T.rotgroup = (u32*)table_upload(rg.data(), rg.size() * 4);
+
+  // Gaussian inversion table for chi_e: cumulative discrete Gaussian, |e| <= 19
+  {
+    double rho[39], z = 0.0;
+    for (int x = -19; x <= 19; x++) rho[x + 19] = std::exp(-((double)x * (double)x) / (2.0 * sigma * sigma));
+    for (int k = 0; k < 39; k++) z += rho[k];
+    u64 cdt[38];
+    double cum = 0.0;
+    for (int k = 0; k < 38; k++) {
+      cum += rho[k];
+      cdt[k] = (u64)(cum / z * 18446744073709551616.0);
+    }
+    T.cdt = table_upload(cdt, sizeof cdt);
+  }
+
+  // ModUp tables per (level, digit); ModDown table P -> Q
+  up.resize(L + 1);
+  for (int l = 0; l <= L; l++) {
+    for (int j = 0; j < beta_at(l); j++) {
+      std::vector<int> src;
+      for (int k = j * alpha; k < (j + 1) * alpha && k <= l; k++) src.push_back(k);
+      up[l].push_back(make_fbc(this, src));
+    }
+  }
+  {
+    std::vector<int> src;
+    for (int k = 0; k < alpha; k++) src.push_back(L + 1 + k);
+    down = make_fbc(this, src);
+  }
+  // P mod q, P^{-1} mod q (Shoup pairs) and q_l^{-1} mod q_k
+  std::vector<u64> pm(2 * nmods), pi(2 * nmods), ql((size_t)nmods * nmods * 2);
+  for (int m = 0; m < nmods; m++) {
+    u64 q = mods[m], P = 1;
+    for (int k = 0; k < alpha; k++) P = hmul(P, mods[L + 1 + k] % q, q);
+    pm[2 * m] = P;
+    pm[2 * m + 1] = shoup_pre(P, q);
+    u64 Pi = m <= L ? hinv(P, q) : 0;
+    pi[2 * m] = Pi;
+    pi[2 * m + 1] = shoup_pre(Pi, q);
+  }
+  for (int l = 0; l < nmods; l++)
+    for (int k = 0; k < nmods; k++) {
+      u64 v = k == l ? 0 : hinv(mods[l] % mods[k], mods[k]);
+      ql[((size_t)l * nmods + k) * 2] = v;
+      ql[((size_t)l * nmods + k) * 2 + 1] = shoup_pre(v, mods[k]);
+    }
+  pmod = DevBuf(&pool, pm.size());
+  hip_check(hipMemcpy(pmod.p, pm.data(), pm.size() * 8, hipMemcpyHostToDevice), "pmod");
+  pinv = DevBuf(&pool, pi.size());
+  hip_check(hipMemcpy(pinv.p, pi.data(), pi.size() * 8, hipMemcpyHostToDevice), "pinv");
+  qlinv = DevBuf(&pool, ql.size());
+  hip_check(hipMemcpy(qlinv.p, ql.data(), ql.size() * 8, hipMemcpyHostToDevice), "qlinv");
+  hip_check(hipDeviceSynchronize(), "init");
+}
+
+// ---------------------------------------------------------------------------
+// basic containers
+// ---------------------------------------------------------------------------
+HeCt HeCtxImpl::ct_new(int level, bool qp, double scale) {
+  HeCt c;
+  c.N = N;
+  c.level = level;
+  c.qp = qp;
+  c.nlimbs = level + 1 + (qp ? alpha : 0);
+  c.scale = scale;
+  c.d = DevBuf(&pool, (size_t)2 * c.nlimbs * N);
+  return c;
+}
+HeCt HeCtxImpl::ct_copy(const HeCt& x) {
+  HeCt c = ct_new(x.level, x.qp, x.scale);
+  hip_check(hipMemcpyAsync(c.d.p, x.d.p, c.d.words * 8, hipMemcpyDeviceToDevice, stream), "copy");
+  return c;
+}
+void HeCtxImpl::copy_limbs(u64* dst, const u64* src, size_t nlimbs) {
+  hip_check(hipMemcpyAsync(dst, src, nlimbs * N * 8, hipMemcpyDeviceToDevice, stream), "copy");
+}
+
+// ---------------------------------------------------------------------------
+// encoding
+// ---------------------------------------------------------------------------
+DevBuf HeCtxImpl::encode_batch(const double* z_host, int nz, int batch, double dlt) {
+  if (nz <= 0 || (N / 2) % (u64)nz) fail(HE_EINVAL, "message length must divide N/2");
+  DevBuf zd;
+  zd = DevBuf(&pool, (size_t)nz * batch);
+  hip_check(hipMemcpyAsync(zd.p, z_host, (size_t)nz * batch * 8, hipMemcpyHostToDevice, stream), "z upload");
+  DevBuf out(&pool, (size_t)batch * N);
+  DevBuf scratch(&pool, encode_scratch_bytes(T, batch) / 8);
+  launch_encode(T, (i64*)out.p, (const double*)zd.p, nz, batch, dlt, scratch.p, stream);
+  // the host buffer may be reused by the caller once the copy is done
+  hip_check(hipStreamSynchronize(stream), "encode");
+  return out;
+}
+
+// integer coefficients -> evaluation-domain limbs for the map's moduli
+void HeCtxImpl::int_to_ntt(u64* out, const i64* m, const LimbMap& map) {
+  launch_int_to_limbs(T, out, m, map.n, map, stream);
+  launch_ntt(T, out, map.n, map, false, stream);
+}
+
+// ---------------------------------------------------------------------------
+// key generation (Appendix A)
+// ---------------------------------------------------------------------------
+void HeCtxImpl::keygen_secret() {
+  if (have_sk) return;
+  DevBuf si(&pool, N);
+  launch_sample_ternary(T, (i64*)si.p, seed, TAG_SK, 0, 0, 0, stream);
+  s_ntt = DevBuf(&pool, (size_t)nmods * N);
+  LimbMap all;
+  all.n = nmods;
+  for (int m = 0; m < nmods; m++) all.idx[m] = (short)m;
+  int_to_ntt(s_ntt.p, (const i64*)si.p, all);
+  // public key (-a s + e, a) over Q_L
+  pk = DevBuf(&pool, (size_t)2 * (L + 1) * N);
+  u64* a = pk.p + (size_t)(L + 1) * N;
+  LimbMap qm = qmap(L + 1);
+  launch_sample_uniform(T, a, L + 1, qm, seed, TAG_PK_A, 0, 0, stream);
+  DevBuf e(&pool, N), en(&pool, (size_t)(L + 1) * N);
+  launch_sample_gauss(T, (i64*)e.p, seed, TAG_PK_E, 0, 0, 0, stream);
+  int_to_ntt(en.p, (const i64*)e.p, qm);
+  launch_swk_b(T, pk.p, a, en.p, s_ntt.p, nullptr, pmod.p, L + 1, 0, alpha, L, stream);
+  have_sk = true;
+}
+
+// switching key from s' (evaluation domain over all moduli) to s
+void HeCtxImpl::swk_gen(const u64* sp, u64 kid, DevBuf& out) {
+  out = DevBuf(&pool, (size_t)beta * 2 * nmods * N);
+  LimbMap all;
+  all.n = nmods;
+  for (int m = 0; m < nmods; m++) all.idx[m] = (short)m;
+  DevBuf e(&pool, N), en(&pool, (size_t)nmods * N);
+  for (int j = 0; j < beta; j++) {
+    u64* bj = out.p + ((size_t)j * 2 + 0) * nmods * N;
+    u64* aj = out.p + ((size_t)j * 2 + 1) * nmods * N;
+    launch_sample_uniform(T, aj, nmods, all, seed, TAG_SWK_A, (u64)j, kid, stream);
+    launch_sample_gauss(T, (i64*)e.p, seed, TAG_SWK_E, 0, (u64)j, kid, stream);
+    int_to_ntt(en.p, (const i64*)e.p, all);
+    launch_swk_b(T, bj, aj, en.p, s_ntt.p, sp, pmod.p, nmods, j, alpha, L, stream);
+  }
+}
+
+void HeCtxImpl::keygen_relin() {
+  if (keys.count(0)) return;
+  LimbMap all;
+  all.n = nmods;
+  for (int m = 0; m < nmods; m++) all.idx[m] = (short)m;
+  DevBuf s2(&pool, (size_t)nmods * N);
+  launch_mul(T, s2.p, s_ntt.p, s_ntt.p, nmods, all, stream);
+  swk_gen(s2.p, 0, keys[0]);
+}
+
+void HeCtxImpl::keygen_rot(long step) {
+  u64 g = galois(step);
+  if (g == 1 || keys.count(g)) return;
+  DevBuf sg(&pool, (size_t)nmods * N);
+  launch_automorph(T, sg.p, s_ntt.p, nmods, g, stream);
+  swk_gen(sg.p, g, keys[g]);
+}
+
+const DevBuf& HeCtxImpl::key(u64 g) {
+  auto it = keys.find(g);
+  if (it == keys.end()) fail(HE_EKEY, "missing switching key for Galois element " + std::to_string(g));
+  return it->second;
+}
+
+// ---------------------------------------------------------------------------
+// encryption / decryption (Appendix A: Enc, Dec)
+// ---------------------------------------------------------------------------
+HeCt HeCtxImpl::encrypt_int(const i64* m_dev, int level, double scale, u64 nonce) {
+  if (!have_sk) fail(HE_EKEY, "keys not generated");
+  if (level < 0 || level > L) fail(HE_ELEVEL, "level out of range");
+  int nl = level + 1;
+  LimbMap qm = qmap(nl);
+  DevBuf v(&pool, N), e0(&pool, N), e1(&pool, N);
+  launch_sample_ternary(T, (i64*)v.p, seed, TAG_ENC_V, 0, nonce, 0, stream);
+  launch_sample_gauss(T, (i64*)e0.p, seed, TAG_ENC_E0, 0, nonce, 0, stream);
+  launch_sample_gauss(T, (i64*)e1.p, seed, TAG_ENC_E1, 0, nonce, 0, stream);
+  launch_add_int((i64*)e0.p, (const i64*)e0.p, m_dev, N, stream);
+  DevBuf vn(&pool, (size_t)nl * N);
+  int_to_ntt(vn.p, (const i64*)v.p, qm);
+  HeCt c = ct_new(level, false, scale);
+  int_to_ntt(c.poly(0), (const i64*)e0.p, qm);
+  int_to_ntt(c.poly(1), (const i64*)e1.p, qm);
+  // c0 += v pk0 ; c1 += v pk1  (pk rows restricted to the first nl limbs)
+  launch_mul_acc(T, c.poly(0), vn.p, pk.p, nl, nl, qm, stream);
+  launch_mul_acc(T, c.poly(1), vn.p, pk.p + (size_t)(L + 1) * N, nl, nl, qm, stream);
+  return c;
+}
+
+HeCt HeCtxImpl::encrypt(const double* z, int nz, int level, u64 nonce) {
+  DevBuf m = encode_batch(z, nz, 1, delta);
+  return encrypt_int((const i64*)m.p, level, delta, nonce);
+}
+
+std::vector<double> HeCtxImpl::decrypt(const HeCt& c) {
+  if (!have_sk) fail(HE_EKEY, "keys not generated");
+  if (c.qp) fail(HE_EINVAL, "cannot decrypt an R_QP element");
+  DevBuf t(&pool, N);
+  LimbMap m0 = one(0);
+  launch_mul(T, t.p, c.limb(1, 0), s_ntt.p, 1, m0, stream);
+  launch_add(T, t.p, t.p, c.limb(0, 0), 1, m0, stream);
+  launch_ntt(T, t.p, 1, m0, true, stream);
+  DevBuf mi(&pool, N);
+  launch_centre_to_int(T, (i64*)mi.p, t.p, 0, stream);
+  double inv = 1.0 / c.scale;
+  DevBuf invd(&pool, 1);
+  hip_check(hipMemcpyAsync(invd.p, &inv, 8, hipMemcpyHostToDevice, stream), "scale");
+  DevBuf out(&pool, N / 2);
+  DevBuf scratch(&pool, encode_scratch_bytes(T, 1) / 8);
+  launch_decode(T, (double*)out.p, (const i64*)mi.p, 1, (const double*)invd.p, scratch.p, stream);
+  std::vector<double> h(N / 2);
+  hip_check(hipMemcpyAsync(h.data(), out.p, (N / 2) * 8, hipMemcpyDeviceToHost, stream), "download");
+  hip_check(hipStreamSynchronize(stream), "decrypt");
+  return h;
+}
+
+// ---------------------------------------------------------------------------
+// Add / Sub / PMult / Mult / Rescale / level drop
+// ---------------------------------------------------------------------------
+static void need_same(const HeCt& a, const HeCt& b) {
+  if (a.level != b.level || a.qp != b.qp) fail(HE_ELEVEL, "operands at different levels");
+}
+HeCt HeCtxImpl::add(const HeCt& a, const HeCt& b, bool sub) {
+  need_same(a, b);
+  if (a.scale != b.scale) fail(HE_ESCALE, "operands with different scales");
+  HeCt c = ct_new(a.level, a.qp, a.scale);
+  LimbMap m = a.qp ? qpmap(a.level) : qmap(a.level + 1);
+  if (sub) launch_sub(T, c.d.p, a.d.p, b.d.p, 2 * a.nlimbs, m, stream);
+  else launch_add(T, c.d.p, a.d.p, b.d.p, 2 * a.nlimbs, m, stream);
+  return c;
+}
+void HeCtxImpl::add_into(HeCt& acc, const HeCt& b) {
+  need_same(acc, b);
+  LimbMap m = acc.qp ? qpmap(acc.level) : qmap(acc.level + 1);
+  launch_add(T, acc.d.p, acc.d.p, b.d.p, 2 * acc.nlimbs, m, stream);
+}
+
+HeCt HeCtxImpl::drop(const HeCt& a, int level) {
+  if (a.qp || level > a.level || level < 0) fail(HE_ELEVEL, "bad level drop");
+  HeCt c = ct_new(level, false, a.scale);
+  for (int p = 0; p < 2; p++) copy_limbs(c.poly(p), a.poly(p), level + 1);
+  return c;
+}
+
+HeCt HeCtxImpl::rescale(const HeCt& a) {
+  if (a.qp) fail(HE_EINVAL, "rescale of an R_QP element");
+  int l = a.level;
+  if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
+  DevBuf top(&pool, 2 * N);
+  copy_limbs(top.p, a.limb(0, l), 1);
+  copy_limbs(top.p + N, a.limb(1, l), 1);
+  launch_ntt(T, top.p, 2, one(l), true, stream);
+  DevBuf t(&pool, (size_t)2 * l * N);
+  launch_rescale_lift(T, t.p, top.p, l, 2, stream);
+  launch_ntt(T, t.p, 2 * l, qmap(l), false, stream);
+  HeCt c = ct_new(l - 1, false, a.scale / (double)mods[l]);
+  launch_rescale_final(T, c.d.p, a.d.p, t.p, l, 2, l + 1, qlinv.p + (size_t)l * nmods * 2, stream);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// key switching (section 3.3.1; Appendix A KeySwitch)
+// ---------------------------------------------------------------------------
+// Decompose: digits u64[beta_l][l+1+alpha][N], evaluation domain
+DevBuf HeCtxImpl::decompose(const u64* d, int level) {
+  int nq = nq_of(level), nqp = nqp_of(level), bl = beta_at(level);
+  DevBuf coef(&pool, (size_t)nq * N);
+  copy_limbs(coef.p, d, nq);
+  launch_ntt(T, coef.p, nq, qmap(nq), true, stream);
+  DevBuf dig(&pool, (size_t)bl * nqp * N);
+  launch_modup(T, dig.p, coef.p, d, level, L, alpha, bl, up[level].data(), stream);
+  LimbMap m;
+  m.n = bl * nqp;
+  if (m.n > 960) fail(HE_EINVAL, "too many digit limbs");
+  for (int j = 0; j < bl; j++)
+    for (int pos = 0; pos < nqp; pos++) {
+      bool own = pos < nq && pos / alpha == j;
+      m.idx[j * nqp + pos] = own ? (short)-1 : (short)qp_mod(level, pos);
+    }
+  launch_ntt(T, dig.p, m.n, m, false, stream);
+  n_decompose++;
+  return dig;
+}
+
+// hoisted rotation left in R_{Q_l P}; g = 1 gives the P-lift
+HeCt HeCtxImpl::hoisted(const HeCt& x, const u64* digits, u64 g) {
+  HeCt h = ct_new(x.level, true, x.scale);
+  if (g == 1) {
+    launch_plift(T, h.d.p, x.d.p, pmod.p, x.level, alpha, stream);
+    return h;
+  }
+  const DevBuf& k = key(g);
+  launch_multsum(T, h.d.p, digits, k.p, x.poly(0), pmod.p, x.level, L, alpha, beta_at(x.level), g, stream);
+  n_multsum++;
+  return h;
+}
+
+// ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - FBC_{P->Q}(x mod P)) P^{-1}
+HeCt HeCtxImpl::moddown(const HeCt& x) {
+  if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
+  int nq = nq_of(x.level), nqp = nqp_of(x.level);
+  DevBuf pc(&pool, (size_t)2 * alpha * N);
+  copy_limbs(pc.p, x.limb(0, nq), alpha);
+  copy_limbs(pc.p + (size_t)alpha * N, x.limb(1, nq), alpha);
+  LimbMap pm;
+  pm.n = alpha;
+  for (int k = 0; k < alpha; k++) pm.idx[k] = (short)(L + 1 + k);
+  launch_ntt(T, pc.p, 2 * alpha, pm, true, stream);
+  DevBuf y(&pool, (size_t)2 * nq * N);
+  launch_fbc_to_q(T, y.p, pc.p, nq, down, stream);
+  launch_ntt(T, y.p, 2 * nq, qmap(nq), false, stream);
+  HeCt c = ct_new(x.level, false, x.scale);
+  launch_moddown_final(T, c.d.p, x.d.p, y.p, nq, pinv.p, 2, nqp, stream);
+  n_moddown++;
+  return c;
+}
+
+HeCt HeCtxImpl::keyswitch(const u64* d, int level, u64 g_key) {
+  DevBuf dig = decompose(d, level);
+  HeCt h = ct_new(level, true, 1.0);
+  const DevBuf& k = key(g_key);
+  launch_multsum(T, h.d.p, dig.p, k.p, nullptr, pmod.p, level, L, alpha, beta_at(level), 1, stream);
+  n_multsum++;
+  return moddown(h);
+}
+
+HeCt HeCtxImpl::mult(const HeCt& a, const HeCt& b) {
+  need_same(a, b);
+  if (a.qp) fail(HE_EINVAL, "mult of R_QP elements");
+  int nl = a.nlimbs;
+  DevBuf t3(&pool, (size_t)3 * nl * N);
+  launch_tensor(T, t3.p, a.d.p, b.d.p, nl, stream);
+  HeCt ks = keyswitch(t3.p + (size_t)2 * nl * N, a.level, 0);
+  HeCt c = ct_new(a.level, false, a.scale * b.scale);
+  launch_add(T, c.d.p, t3.p, ks.d.p, 2 * nl, qmap(nl), stream);
+  return c;
+}
+
+HeCt HeCtxImpl::rotate(const HeCt& x, long step) {
+  u64 g = galois(step);
+  if (g == 1) return ct_copy(x);
+  DevBuf dig = decompose(x.poly(1), x.level);
+  HeCt h = hoisted(x, dig.p, g);
+  return moddown(h);
+}
+
+HeCt HeCtxImpl::pmult_int(const HeCt& a, const i64* m_dev, double pt_scale) {
+  LimbMap m = a.qp ? qpmap(a.level) : qmap(a.level + 1);
+  DevBuf pt(&pool, (size_t)a.nlimbs * N);
+  int_to_ntt(pt.p, m_dev, m);
+  HeCt c = ct_new(a.level, a.qp, a.scale * pt_scale);
+  launch_mul_bcast(T, c.d.p, a.d.p, pt.p, 2 * a.nlimbs, a.nlimbs, m, stream);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// plaintext diagonals (cached per transform, level and basis)
+// ---------------------------------------------------------------------------
+// ensure every vector in `vecs` (each of length n2) has an evaluation-domain
+// plaintext over Q_level (+P if qp) under cache key keys[i]; returns pointers
+std::vector<const u64*> HeCtxImpl::plaintexts(const std::vector<std::string>& keys_,
+                                              const std::vector<std::vector<double>>& vecs, int n2, int level,
+                                              bool qp, double scale) {
+  std::vector<const u64*> out(keys_.size(), nullptr);
+  std::vector<int> missing;
+  char suffix[96];
+  snprintf(suffix, sizeof suffix, "|L%d|%d|%.17g", level, qp ? 1 : 0, scale);
+  for (size_t i = 0; i < keys_.size(); i++) {
+    auto it = ptcache.find(keys_[i] + suffix);
+    if (it != ptcache.end()) out[i] = it->second.p;
+    else missing.push_back((int)i);
+  }
+  if (missing.empty()) return out;
+  LimbMap m = qp ? qpmap(level) : qmap(level + 1);
+  int nl = m.n;
+  const int chunk = std::max(1, (int)std::min<u64>(256, (1ull << 26) / N));
+  for (size_t s0 = 0; s0 < missing.size(); s0 += chunk) {
+    int b = (int)std::min(missing.size() - s0, (size_t)chunk);
+    std::vector<double> host((size_t)b * n2);
+    for (int t = 0; t < b; t++) std::copy(vecs[missing[s0 + t]].begin(), vecs[missing[s0 + t]].end(),
+                                          host.begin() + (size_t)t * n2);
+    DevBuf ints = encode_batch(host.data(), n2, b, scale);
+    for (int t = 0; t < b; t++) {
+      int i = missing[s0 + t];
+      DevBuf pt(&pool, (size_t)nl * N);
+      int_to_ntt(pt.p, (const i64*)ints.p + (size_t)t * N, m);
+      out[i] = pt.p;
+      ptcache[keys_[i] + suffix] = std::move(pt);
+    }
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Jiang's permutations (Eq. 4) on the row-major n^2 vector: output t takes
+// input perm[t].
+// ---------------------------------------------------------------------------
+std::vector<int> make_perm(int kind, int n) {
+  std::vector<int> p((size_t)n * n);
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) {
+      int t = i * n + j;
+      if (kind == LT_SIGMA) p[t] = i * n + (i + j) % n;
+      else if (kind == LT_TAU) p[t] = ((i + j) % n) * n + j;
+      else p[t] = j * n + i;
+    }
+  return p;
+}
+
+static long pmod_l(long a, long m) { return ((a % m) + m) % m; }
+
+// diagonal l of the (weighted) permutation, pre-rotated right by `shift`
+static bool diag_vec(const std::vector<int>& perm, long l, long shift, double w, std::vector<double>& out) {
+  long n2 = (long)perm.size();
+  out.assign(n2, 0.0);
+  bool nz = false;
+  long lm = pmod_l(l, n2);
+  for (long t = 0; t < n2; t++) {
+    long s = pmod_l(t - shift, n2);
+    if (pmod_l((long)perm[s] - s, n2) == lm) {
+      out[t] = w;
+      nz = true;
+    }
+  }
+  return nz;
+}
+
+static int ceil_div_i(int a, int b) { return (a + b - 1) / b; }
+
+LtGeom lt_geom(int kind, int n, int n1) {
+  LtGeom g;
+  g.n1 = n1;
+  int n2 = ceil_div_i(n, n1);
+  if (kind == LT_SIGMA) { g.a = 1; g.i_lo = -n2; g.i_hi = n2; }
+  else if (kind == LT_TAU) { g.a = n; g.i_lo = 0; g.i_hi = n2; }
+  else { g.a = n - 1; g.i_lo = -n2; g.i_hi = n2; }
+  return g;
+}
+
+// double-hoisted BSGS: U x = sum_i rot( sum_j rot(u_{a(n1 i+j)}, -a n1 i) (.) rot(x, a j), a n1 i )
+HeCt HeCtxImpl::lintrans(const HeCt& x, int kind, int n, int n1, double weight) {
+  if (x.qp) fail(HE_EINVAL, "linear transform of an R_QP element");
+  if (x.level < 1) fail(HE_ELEVEL, "linear transform needs one level");
+  if ((u64)n * n > N / 2 || n1 < 1) fail(HE_EINVAL, "matrix does not fit the slots");
+  LtGeom G = lt_geom(kind, n, n1);
+  std::vector<int> perm = make_perm(kind, n);
+  const int level = x.level;
+  const int nqp = nqp_of(level);
+  // diagonals actually present
+  std::vector<std::string> keys_;
+  std::vector<std::vector<double>> vecs;
+  std::vector<std::pair<int, int>> ij;
+  std::vector<double> v;
+  for (int i = G.i_lo; i < G.i_hi; i++)
+    for (int j = 0; j < n1; j++) {
+      long l = (long)G.a * ((long)n1 * i + j);
+      if (!diag_vec(perm, l, (long)G.a * n1 * i, weight, v)) continue;
+      char key[96];
+      snprintf(key, sizeof key, "lt%d|n%d|n1_%d|i%d|j%d|w%.17g", kind, n, n1, i, j, weight);
+      keys_.push_back(key);
+      vecs.push_back(v);
+      ij.push_back({i, j});
+    }
+  std::vector<const u64*> pts = plaintexts(keys_, vecs, n * n, level, true, delta);
+  std::vector<bool> used(n1, false);
+  for (auto& p : ij) used[p.second] = true;
+  // Decompose once, baby-step hoisted rotations kept in R_{Q_l P}
+  DevBuf dig = decompose(x.poly(1), level);
+  std::vector<HeCt> baby(n1);
+  for (int j = 0; j < n1; j++)
+    if (used[j]) baby[j] = hoisted(x, dig.p, galois((long)G.a * j));
+  dig.release();
+  LimbMap qpm = qpmap(level);
+  HeCt acc = ct_new(level, true, x.scale * delta);
+  bool acc_set = false;
+  size_t e = 0;
+  for (int i = G.i_lo; i < G.i_hi; i++) {
+    HeCt inner;
+    bool inner_set = false;
+    for (; e < ij.size() && ij[e].first == i; e++) {
+      int j = ij[e].second;
+      if (!inner_set) {
+        inner = ct_new(level, true, x.scale * delta);
+        launch_mul_bcast(T, inner.d.p, baby[j].d.p, pts[e], 2 * nqp, nqp, qpm, stream);
+        inner_set = true;
+      } else {
+        launch_mul_acc(T, inner.d.p, baby[j].d.p, pts[e], 2 * nqp, nqp, qpm, stream);
+      }
+    }
+    if (!inner_set) continue;
+    HeCt term;
+    if (i == 0) {
+      term = std::move(inner);
+    } else {
+      HeCt t = moddown(inner);
+      DevBuf d2 = decompose(t.poly(1), level);
+      term = hoisted(t, d2.p, galois((long)G.a * n1 * i));
+    }
+    if (!acc_set) {
+      acc = std::move(term);
+      acc_set = true;
+    } else {
+      add_into(acc, term);
+    }
+  }
+  HeCt md = moddown(acc);
+  return rescale(md);
+}
+
+// ---------------------------------------------------------------------------
+// The matrix product (Eq. 4; Algorithm DMatrixMult; hoisted C^k / R^k of
+// section 4.1.1)
+// ---------------------------------------------------------------------------
+int default_n1(int n) {
+  int lg = 0;
+  while ((1 << lg) < n) lg++;
+  return 1 << ((lg + 1) / 2);
+}
+
+std::vector<long> matmul_steps(int n, int n1z, int n1t) {
+  std::set<long> s;
+  int n2z = ceil_div_i(n, n1z), n2t = ceil_div_i(n, n1t);
+  for (int j = 1; j < n1z; j++) s.insert(j);
+  for (int i = -n2z; i < n2z; i++)
+    if (i) s.insert((long)n1z * i);
+  for (int j = 1; j < n1t; j++) s.insert((long)n * j);
+  for (int i = 1; i < n2t; i++) s.insert((long)n * n1t * i);
+  s.insert(n1z);
+  s.insert(-(long)n);
+  s.insert((long)n * n1t);
+  return std::vector<long>(s.begin(), s.end());
+}
+
+std::vector<long> transpose_steps(int n, int n1) {
+  std::set<long> s;
+  LtGeom G = lt_geom(LT_TRANSPOSE, n, n1);
+  for (int j = 1; j < n1; j++) s.insert((long)G.a * j);
+  for (int i = G.i_lo; i < G.i_hi; i++)
+    if (i) s.insert((long)G.a * n1 * i);
+  return std::vector<long>(s.begin(), s.end());
+}
+
+static void col_mask(int n, int k, bool second, std::vector<double>& out) {
+  out.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) {
+      bool first = j < n - k;
+      out[(size_t)i * n + j] = (second ? !first : first) ? 1.0 : 0.0;
+    }
+}
+
+// A side: A_k = Rescale(ModDown(m_k (.) HR(B_b, r) + m'_k (.) HR(B'_b, r))), k = b n1z + r,
+// with bases B_b = Rot(B_{b-1}, n1z), B'_0 = Rot(sigma A, -n), B'_b = Rot(B'_{b-1}, n1z)
+std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, double weight) {
+  HeCt A0 = lintrans(ca, LT_SIGMA, n, n1z, weight);
+  const int lvl = A0.level;
+  const int nqp = nqp_of(lvl);
+  LimbMap qpm = qpmap(lvl);
+  std::vector<std::string> keys_;
+  std::vector<std::vector<double>> vecs;
+  std::vector<double> v;
+  for (int k = 0; k < n; k++) {
+    for (int second = 0; second < 2; second++) {
+      if (second && k == 0) continue;
+      char key[64];
+      snprintf(key, sizeof key, "colmask|n%d|k%d|%d", n, k, second);
+      col_mask(n, k, second, v);
+      keys_.push_back(key);
+      vecs.push_back(v);
+    }
+  }
+  std::vector<const u64*> masks = plaintexts(keys_, vecs, n * n, lvl, true, delta);
+  auto mask_of = [&](int k, int second) { return masks[k == 0 ? 0 : 2 * k - 1 + second]; };
+  std::vector<HeCt> Ak(n);
+  HeCt Bb = ct_copy(A0), Bpb = rotate(A0, -(long)n);
+  A0 = HeCt();
+  for (int b = 0; b * n1z < n; b++) {
+    if (b > 0) {
+      Bb = rotate(Bb, n1z);
+      Bpb = rotate(Bpb, n1z);
+    }
+    DevBuf d1 = decompose(Bb.poly(1), lvl);
+    DevBuf d2 = decompose(Bpb.poly(1), lvl);
+    for (int r = 0; r < n1z && b * n1z + r < n; r++) {
+      int k = b * n1z + r;
+      u64 g = galois(r);
+      HeCt acc = ct_new(lvl, true, Bb.scale * delta);
+      {
+        HeCt h = hoisted(Bb, d1.p, g);
+        launch_mul_bcast(T, acc.d.p, h.d.p, mask_of(k, 0), 2 * nqp, nqp, qpm, stream);
+      }
+      if (k > 0) {
+        HeCt h = hoisted(Bpb, d2.p, g);
+        launch_mul_acc(T, acc.d.p, h.d.p, mask_of(k, 1), 2 * nqp, nqp, qpm, stream);
+      }
+      HeCt md = moddown(acc);
+      Ak[k] = rescale(md);
+    }
+  }
+  return Ak;
+}
+
+// B side: C_0 = tau B, C_b = Rot(C_{b-1}, n n1t), B_k = ModDown(HR(C_b, n r)),
+// dropped one level to meet the A side
+std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t) {
+  HeCt Cb = lintrans(cb, LT_TAU, n, n1t, 1.0);
+  const int lvl = Cb.level;
+  std::vector<HeCt> Bk(n);
+  for (int b = 0; b * n1t < n; b++) {
+    if (b > 0) Cb = rotate(Cb, (long)n * n1t);
+    DevBuf d1 = decompose(Cb.poly(1), lvl);
+    for (int r = 0; r < n1t && b * n1t + r < n; r++) {
+      int k = b * n1t + r;
+      if (r == 0) {
+        Bk[k] = drop(Cb, lvl - 1);
+      } else {
+        HeCt h = hoisted(Cb, d1.p, galois((long)n * r));
+        HeCt full = moddown(h);
+        Bk[k] = drop(full, lvl - 1);
+      }
+    }
+  }
+  return Bk;
+}
+
+// acc (+)= sum_k Relin(Tensor(A_k, B_k))
+void HeCtxImpl::matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk) {
+  for (size_t k = 0; k < Ak.size(); k++) {
+    HeCt p = mult(Ak[k], Bk[k]);
+    if (!acc_set) {
+      acc = std::move(p);
+      acc_set = true;
+    } else {
+      add_into(acc, p);
+    }
+  }
+}
+
+HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t) {
+  if (ca.qp || cb.qp || ca.level != cb.level) fail(HE_ELEVEL, "operands must be ciphertexts at one level");
+  if (ca.level < 3) fail(HE_ELEVEL, "the product needs three levels");
+  if ((u64)n * n > N / 2 || n % n1z || n % n1t) fail(HE_EINVAL, "bad matrix size / baby-step count");
+  std::vector<HeCt> Ak = matmul_side_a(ca, n, n1z, 1.0);
+  std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t);
+  HeCt acc;
+  bool set = false;
+  matmul_accumulate(acc, set, Ak, Bk);
+  return rescale(acc);
+}
+
+// Covariance (Algorithm HCovMtrx, centred data): block (a, b) of X^T X / s is
+//   Rescale( sum_r sum_k Relin(Tensor(A_k(G(X_a[r]) / s), B_k(X_b[r]))) )
+// for b <= a, and G(block (b, a)) for a < b; the A and B sides of each
+// row block are formed once and reused for every pair (one-to-many caching).
+std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples,
+                                        int n1z, int n1t, int n1g) {
+  if ((int)x.size() != rb * k) fail(HE_EINVAL, "block count mismatch");
+  int level = x[0]->level;
+  for (auto* c : x)
+    if (c->level != level || c->qp) fail(HE_ELEVEL, "dataset blocks must share one level");
+  if (level < 5) fail(HE_ELEVEL, "the covariance needs five levels");
+  std::vector<HeCt> acc(k * k);
+  std::vector<bool> set(k * k, false);
+  for (int r = 0; r < rb; r++) {
+    std::vector<std::vector<HeCt>> A(k), B(k);
+    for (int a = 0; a < k; a++) {
+      HeCt xt = lintrans(*x[r * k + a], LT_TRANSPOSE, n, n1g, 1.0 / (double)n_samples);
+      A[a] = matmul_side_a(xt, n, n1z, 1.0);
+    }
+    for (int b = 0; b < k; b++) {
+      HeCt xb = drop(*x[r * k + b], level - 1);
+      B[b] = matmul_side_b(xb, n, n1t);
+    }
+    for (int a = 0; a < k; a++)
+      for (int b = 0; b <= a; b++) {
+        bool s = set[a * k + b];
+        matmul_accumulate(acc[a * k + b], s, A[a], B[b]);
+        set[a * k + b] = s;
+      }
+  }
+  std::vector<HeCt> out(k * k);
+  for (int a = 0; a < k; a++)
+    for (int b = 0; b <= a; b++) out[a * k + b] = rescale(acc[a * k + b]);
+  int final_level = out[0].level - 1;
+  for (int a = 0; a < k; a++)
+    for (int b = a + 1; b < k; b++) out[a * k + b] = lintrans(out[b * k + a], LT_TRANSPOSE, n, n1g, 1.0);
+  for (int a = 0; a < k; a++)
+    for (int b = 0; b <= a; b++) out[a * k + b] = drop(out[a * k + b], final_level);
+  return out;
+}
