@@ -254,10 +254,14 @@ oc_ctx *oc_create(int logN, const int *qbits, int nq, const int *pbits, int np,
     u64 psinv = invmod(c->psi[m], q);
     c->psi_rev[m] = alloc_u64(c->N);
     c->psi_inv_rev[m] = alloc_u64(c->N);
+    /* successive powers psi^k, psi^-k, then placed at bit-reversed k */
+    u64 pw = 1, pwi = 1;
     for (u64 k = 0; k < c->N; k++) {
       u64 e = bitrev(k, logN);
-      c->psi_rev[m][k] = powmod(c->psi[m], e, q);
-      c->psi_inv_rev[m][k] = powmod(psinv, e, q);
+      c->psi_rev[m][e] = pw;
+      c->psi_inv_rev[m][e] = pwi;
+      pw = mulmod(pw, c->psi[m], q);
+      pwi = mulmod(pwi, psinv, q);
     }
     c->ninv[m] = invmod(c->N % q, q);
   }
@@ -884,26 +888,100 @@ u64 *oc_decompose(const oc_ctx *c, const u64 *d, int level) {
   return out;
 }
 
-/* ModDown: x in R_{Q_l P} (NTT domain, l+1+alpha limbs) ->
- *   (x_i - FBC_{P->q_i}(x mod P)) P^{-1} mod q_i. */
+/* Fixed-width unsigned big integers (little-endian 64-bit words), enough for
+ * products of up to four 61-bit primes. */
+#define BW 5
+typedef struct { u64 w[BW]; } big;
+static big big_u64(u64 v) { big r; memset(&r, 0, sizeof r); r.w[0] = v; return r; }
+static big big_mul_u64(big a, u64 b) {
+  big r;
+  u128 carry = 0;
+  for (int k = 0; k < BW; k++) {
+    u128 t = (u128)a.w[k] * b + carry;
+    r.w[k] = (u64)t;
+    carry = t >> 64;
+  }
+  return r;
+}
+static big big_add(big a, big b) {
+  big r;
+  u128 carry = 0;
+  for (int k = 0; k < BW; k++) {
+    u128 t = (u128)a.w[k] + b.w[k] + carry;
+    r.w[k] = (u64)t;
+    carry = t >> 64;
+  }
+  return r;
+}
+static big big_sub(big a, big b) { /* a >= b */
+  big r;
+  u64 borrow = 0;
+  for (int k = 0; k < BW; k++) {
+    u64 t = a.w[k] - b.w[k] - borrow;
+    borrow = (a.w[k] < b.w[k]) || (a.w[k] - b.w[k] < borrow);
+    r.w[k] = t;
+  }
+  return r;
+}
+static int big_cmp(big a, big b) {
+  for (int k = BW - 1; k >= 0; k--) {
+    if (a.w[k] != b.w[k]) return a.w[k] < b.w[k] ? -1 : 1;
+  }
+  return 0;
+}
+static u64 big_mod_u64(big a, u64 q) {
+  u128 r = 0;
+  for (int k = BW - 1; k >= 0; k--) r = ((r << 64) | a.w[k]) % q;
+  return (u64)r;
+}
+
+/* ModDown (Appendix A, KeySwitch): x in R_{Q_l P} (NTT domain, l+1+alpha
+ * limbs) -> round(x / P) in R_{Q_l}:
+ *   out_i = (x_i - [x]_P) P^{-1} mod q_i,
+ * with [x]_P the exact centred residue of x modulo P, reconstructed by CRT
+ * from the P limbs. */
 static void moddown_poly(const oc_ctx *c, const u64 *x, int level, u64 *out) {
   u64 N = c->N;
   int nq = level + 1, al = c->alpha;
   u64 *pc = alloc_u64((size_t)al * N);
-  int pidx[MAXMOD], src[MAXMOD];
-  for (int k = 0; k < al; k++) {
-    pidx[k] = c->L + 1 + k;
-    src[k] = c->L + 1 + k;
-  }
+  int pidx[MAXMOD];
+  for (int k = 0; k < al; k++) pidx[k] = c->L + 1 + k;
   memcpy(pc, x + (size_t)nq * N, sizeof(u64) * al * N);
   intt_limbs(c, pc, pidx, al);
-  const u64 *xs[MAXMOD];
-  for (int k = 0; k < al; k++) xs[k] = pc + (size_t)k * N;
+  /* CRT constants: P, P/p_k and (P/p_k)^{-1} mod p_k */
+  big P = big_u64(1), H[MAXMOD];
+  u64 Hinv[MAXMOD];
+  for (int k = 0; k < al; k++) P = big_mul_u64(P, c->mods[c->L + 1 + k]);
+  for (int k = 0; k < al; k++) {
+    u64 pk = c->mods[c->L + 1 + k];
+    H[k] = big_u64(1);
+    for (int m = 0; m < al; m++)
+      if (m != k) H[k] = big_mul_u64(H[k], c->mods[c->L + 1 + m]);
+    Hinv[k] = invmod(big_mod_u64(H[k], pk), pk);
+  }
+  /* centred residue, kept as (magnitude, sign) per coefficient */
+  big *mag = (big *)malloc(sizeof(big) * N);
+  char *neg = (char *)malloc(N);
+#pragma omp parallel for schedule(static)
+  for (u64 t = 0; t < N; t++) {
+    big S = big_u64(0);
+    for (int k = 0; k < al; k++) {
+      u64 pk = c->mods[c->L + 1 + k];
+      S = big_add(S, big_mul_u64(H[k], mulmod(pc[(size_t)k * N + t], Hinv[k], pk)));
+    }
+    while (big_cmp(S, P) >= 0) S = big_sub(S, P);
+    big twoS = big_add(S, S);
+    if (big_cmp(twoS, P) > 0) { mag[t] = big_sub(P, S); neg[t] = 1; }
+    else { mag[t] = S; neg[t] = 0; }
+  }
 #pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < nq; i++) {
     u64 q = c->mods[i];
     u64 *y = alloc_u64(N);
-    fbc(c, xs, src, al, i, y);
+    for (u64 t = 0; t < N; t++) {
+      u64 r = big_mod_u64(mag[t], q);
+      y[t] = neg[t] ? (r ? q - r : 0) : r;
+    }
     oc_ntt(c, i, y);
     u64 pinv = 1;
     for (int k = 0; k < al; k++) pinv = mulmod(pinv, c->mods[c->L + 1 + k] % q, q);
@@ -913,6 +991,8 @@ static void moddown_poly(const oc_ctx *c, const u64 *x, int level, u64 *out) {
     free(y);
   }
   free(pc);
+  free(mag);
+  free(neg);
 }
 
 oc_ct *oc_moddown(const oc_ctx *c, const oc_ct *a) {

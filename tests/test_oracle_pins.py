@@ -272,19 +272,20 @@ def test_decompose_is_exact_lift_up_to_multiple_of_digit_modulus(toy):
                 assert outs[pos][i] == y % q
 
 
-def test_moddown_is_division_by_P_within_alpha(toy):
-    z = np.random.default_rng(2).uniform(-1, 1, toy.slots)
-    ct = toy.encrypt(z, nonce=9)
-    h = toy.hoisted_rotate(ct, 1)
-    md = toy.moddown(h)
-    P = math.prod(toy.p)
+@pytest.mark.parametrize("p_bits", [(60,), (60, 60), (60, 60, 60), (61, 61, 61, 61)])
+def test_moddown_is_rounded_division_by_P(oracle_mod, p_bits):
+    # KeySwitch (Appendix A) rounds P^{-1} <a, swk> to the nearest integer
+    o = oracle_mod.Oracle(10, (60, 40, 40, 40), p_bits, seed=2)
+    o.keygen(rot_steps=[1], relin=False)
+    z = np.random.default_rng(2).uniform(-1, 1, o.slots)
+    ct = o.encrypt(z, nonce=9)
+    h = o.hoisted_rotate(ct, 1)
+    md = o.moddown(h)
+    P = math.prod(o.p)
     for p in (0, 1):
-        x, _ = _coef_ints(toy, h, p)
-        y, Q = _coef_ints(toy, md, p)
-        for i in range(0, toy.N, 11):
-            want = t0.round_div(x[i], P)
-            diff = t0.centred(y[i] - want, Q)
-            assert abs(diff) <= toy.alpha
+        x, _ = _coef_ints(o, h, p)
+        y, Q = _coef_ints(o, md, p)
+        assert y == [t0.centred(t0.round_div(v, P), Q) for v in x]
 
 
 def test_rotation_rotates_slots(toy):
