@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of the homomorphic d x d matrix product at N = 2^16 on one MI355X.
+
+One step = one batch of `--batch` independent 128 x 128 products (Eq. 4 of
+the paper: sigma/tau double-hoisted BSGS, hoisted column/row shifts, n
+relinearised products, rescale) on ciphertexts already resident in HBM.
+Prints one JSON line: matmuls/s (the headline), key-switched rotations/s,
+per-step latency percentiles, the roofline of the dominant kernel family
+(HIP events around its launches during the timed steps) and the CPU oracle
+timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HE d×d matmuls/s & key-switched rotations/s at N=2^16, batched vs plain; p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pct(xs, p):
+    return float(np.percentile(np.asarray(xs), p)) if xs else None
+
+
+def cpu_baseline(chain, counts, n_rescale, seconds_budget=30.0):
+    """Oracle on a bounded sample: one Decompose, one hoisted rotation, one
+    ModDown and one Rescale at the top level of the chain, scaled to one
+    product by the product's operation counts."""
+    from oracle import oracle as O
+    o = O.Oracle(chain.log_n, chain.q_bits, chain.p_bits, seed=5)
+    o.keygen(rot_steps=[1], relin=False)
+    z = np.random.default_rng(0).uniform(-1, 1, o.slots)
+    ct = o.encrypt(z, nonce=1)
+    lvl = ct.level
+    t0 = time.perf_counter()
+    o.decompose(ct.data()[1], lvl)
+    t_dp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    h = o.hoisted_rotate(ct, 1)
+    t_hr = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    md = o.moddown(h)
+    t_md = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.rescale(md)
+    t_rs = time.perf_counter() - t0
+    t_ms = max(t_hr - t_dp, 0.0)
+    t_rot = t_hr + t_md
+    t_mm = counts["decompose"] * t_dp + counts["multsum"] * t_ms + counts["moddown"] * t_md + n_rescale * t_rs
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": 1.0 / t_mm,
+        "unit": "matmuls/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle at N=2^{chain.log_n}, level {lvl}: one Decompose ({t_dp:.2f} s), one hoisted "
+                   f"rotation ({t_hr:.2f} s), one ModDown ({t_md:.2f} s), one Rescale ({t_rs:.2f} s); one "
+                   f"product extrapolated from its operation counts {counts} and {n_rescale} rescales "
+                   f"(top-level costs, an upper bound)"),
+        "rotations_per_s": 1.0 / t_rot,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--d", type=int, default=128)
+    ap.add_argument("--rotations", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2305_17341_amd import he, inputs as I
+    chain = I.LARGE
+    d, B = args.d, args.batch
+    log(f"[bench] context N=2^{chain.log_n}, {len(chain.q_bits)} Q primes, {len(chain.p_bits)} P primes")
+    ctx = he.chain_context(chain, seed=1)
+    steps = ctx.matmul_rot_steps(d)
+    t0 = time.perf_counter()
+    ctx.keygen(steps)
+    log(f"[bench] keygen: {len(steps)} rotation keys + relin in {time.perf_counter() - t0:.1f} s")
+    As = [I.uniform_matrix(100 + i, d) for i in range(B)]
+    Bs = [I.uniform_matrix(200 + i, d) for i in range(B)]
+    cA = [ctx.encrypt_matrix(a, nonce=1 + i) for i, a in enumerate(As)]
+    cB = [ctx.encrypt_matrix(b, nonce=1001 + i) for i, b in enumerate(Bs)]
+    ctx.sync()
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        outs = ctx.matmul_batch(cA, cB, [d] * B)
+        ctx.sync()
+        log(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f} s")
+    # accuracy of the last warm-up output against FP64
+    err = float(np.max(np.abs(ctx.decrypt(outs[0], d * d) - (As[0] @ Bs[0]).ravel())))
+    del outs
+    c0 = ctx.op_counts()
+
+    ctx.profile_enable(True)
+    lat = []
+    ctx.sync()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        outs = ctx.matmul_batch(cA, cB, [d] * B)
+        lat.append(ctx.last_op_ms())
+        del outs
+    ctx.sync()
+    t_total = time.perf_counter() - t_start
+    fams = ["ntt", "multsum", "modup", "moddown", "rescale", "elementwise", "tensor", "plift"]
+    prof = {f: ctx.profile_read(f) for f in fams}
+    ctx.profile_enable(False)
+    c1 = ctx.op_counts()
+    n_mm = args.steps * B
+    per_mm = {k: (c1[k] - c0[k]) / n_mm for k in c0}
+
+    # key-switched rotations at the top level
+    ct = cA[0]
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.rotations):
+        r = ctx.rotate(ct, 1)
+        del r
+    ctx.sync()
+    rot_s = args.rotations / (time.perf_counter() - t0)
+
+    value = n_mm / t_total
+    fam_ms = {f: prof[f][0] / args.steps for f in fams}
+    dom = max(fams, key=lambda f: prof[f][0])
+    ms, launches, nbytes = prof[dom]
+    avg_ms = ms / max(launches, 1)
+    bytes_per_launch = nbytes / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 5), "launches": launches,
+                "algorithmic_bytes_per_launch": round(bytes_per_launch)}
+    n_rescale = 2 + 1 + d  # sigma, tau, the d column shifts, the final product
+    result = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "matmuls/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_total / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"he_matmul d={d} at N=2^16 (q0 60b + 30x40b, P 3x60b, levels 30->27), "
+                               f"uniform[-1,1] FP64 inputs", "d": d, "log_n": chain.log_n, "batch": B,
+                   "path": "plain"},
+        "rotations_per_s": round(rot_s, 2),
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "max_abs_err": err,
+        "op_counts_per_matmul": per_mm,
+        "kernel_ms_per_step": {f: round(v, 3) for f, v in fam_ms.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle sample ...")
+        result["cpu_baseline"] = cpu_baseline(chain, per_mm, n_rescale)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -178,6 +178,16 @@ he_status he_hoisted_rotate_export(he_ctx* ctx, const he_ct* a, int32_t step, ui
  * (HIP events around the call's stream work) */
 he_status he_last_op_ms(const he_ctx* ctx, double* ms);
 
+/* Device-time profile by kernel family ("ntt", "multsum", "modup", "moddown",
+ * "rescale", "elementwise", "tensor", "plift"): while enabled, HIP events are
+ * recorded on the launching stream around every launch of the family.
+ * Enabling clears the totals.  `bytes` (may be NULL) receives the family's
+ * algorithmic HBM bytes: every input read once, every output written once. */
+he_status he_profile_enable(he_ctx* ctx, int on);
+he_status he_profile_read(he_ctx* ctx, const char* family, double* total_ms, uint64_t* launches, double* bytes);
+/* counts of Decompose / MultSum / ModDown operations issued by the context */
+he_status he_op_counts(const he_ctx* ctx, uint64_t* decompose, uint64_t* multsum, uint64_t* moddown);
+
 const char* he_last_error(void);
 
 #ifdef __cplusplus

@@ -795,12 +795,14 @@ oc_ct *oc_rescale(const oc_ctx *c, const oc_ct *a) {
   int l = a->level;
   u64 ql = c->mods[l];
   oc_ct *r = ct_new(c, l - 1, 0, a->scale / (double)ql);
-  u64 *top = alloc_u64(N), *t = alloc_u64(N);
+  u64 *top = alloc_u64(N);
   for (int p = 0; p < 2; p++) {
     memcpy(top, poly(c, a, p, l), sizeof(u64) * N);
     oc_intt(c, l, top);
+#pragma omp parallel for schedule(dynamic)
     for (int k = 0; k < l; k++) {
       u64 q = c->mods[k];
+      u64 *t = alloc_u64(N);
       for (u64 i = 0; i < N; i++) {
         i64 centred = top[i] > ql / 2 ? (i64)top[i] - (i64)ql : (i64)top[i];
         t[i] = smod(centred, q);
@@ -808,9 +810,10 @@ oc_ct *oc_rescale(const oc_ctx *c, const oc_ct *a) {
       oc_ntt(c, k, t);
       u64 inv = invmod(ql % q, q);
       for (u64 i = 0; i < N; i++) poly(c, r, p, k)[i] = mulmod(submod(poly(c, a, p, k)[i], t[i], q), inv, q);
+      free(t);
     }
   }
-  free(top); free(t);
+  free(top);
   return r;
 }
 

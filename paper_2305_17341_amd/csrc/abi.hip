@@ -383,4 +383,33 @@ he_status he_last_op_ms(const he_ctx* ctx, double* ms) {
   });
 }
 
+he_status he_profile_enable(he_ctx* ctx, int on) {
+  return guard([&] {
+    need(ctx != nullptr, "null context");
+    hip_check(hipStreamSynchronize(ctx->impl.stream), "sync");
+    prof_enable(on != 0);
+  });
+}
+
+he_status he_profile_read(he_ctx* ctx, const char* family, double* total_ms, uint64_t* launches, double* bytes) {
+  return guard([&] {
+    need(ctx && family && total_ms && launches, "null argument");
+    hip_check(hipStreamSynchronize(ctx->impl.stream), "sync");
+    u64 n = 0;
+    double b = 0;
+    prof_read(family, total_ms, &n, &b);
+    *launches = n;
+    if (bytes) *bytes = b;
+  });
+}
+
+he_status he_op_counts(const he_ctx* ctx, uint64_t* decompose, uint64_t* multsum, uint64_t* moddown) {
+  return guard([&] {
+    need(ctx != nullptr, "null context");
+    if (decompose) *decompose = (uint64_t)ctx->impl.n_decompose;
+    if (multsum) *multsum = (uint64_t)ctx->impl.n_multsum;
+    if (moddown) *moddown = (uint64_t)ctx->impl.n_moddown;
+  });
+}
+
 }  // extern "C"

@@ -54,6 +54,12 @@ struct FbcTable {
   u64 hatinv[8], hatinv_sh[8];
   u64* hat_t = nullptr;     // device [ns][nmods] (hat_a mod t)
   u64* hat_t_sh = nullptr;  // device [ns][nmods]
+  // exact centred lift (ModDown): D = prod of the sources as 4 words, its
+  // cofactors D / q_a, the sources as doubles, and D mod t (Shoup pairs)
+  u64 Dw[4] = {0, 0, 0, 0};
+  u64 Hw[8][4];
+  double qd[8];
+  u64* D_mod_t = nullptr;   // device [nmods][2]
 };
 // digits[j][pos] (pos over Q_l then P): own limbs copy ntt_in, others are the
 // coefficient-domain conversion of digit j (to be transformed by the caller)
@@ -95,3 +101,8 @@ void launch_decode(const DeviceTables& T, double* out, const i64* m, int batch, 
                    void* scratch, hipStream_t s);
 // decryption helpers
 void launch_centre_to_int(const DeviceTables& T, i64* out, const u64* coef, int mod, hipStream_t s);
+
+// per-family device timing (HIP events around launches)
+void prof_enable(bool on);
+bool prof_read(const char* family, double* ms, u64* launches, double* bytes);
+std::vector<std::string> prof_families();

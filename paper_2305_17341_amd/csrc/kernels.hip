@@ -14,6 +14,99 @@
 
 static inline int cdiv(u64 a, u64 b) { return (int)((a + b - 1) / b); }
 
+// ---------------------------------------------------------------------------
+// Optional per-family device timing: HIP events recorded on the launching
+// stream around each launch while enabled.
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfPair {
+  hipEvent_t a, b;
+};
+bool g_prof_on = false;
+std::map<std::string, std::vector<ProfPair>> g_prof;
+struct ProfTotal {
+  double ms = 0, bytes = 0;
+  u64 launches = 0;
+};
+std::map<std::string, ProfTotal> g_prof_done;
+std::map<std::string, double> g_prof_bytes;
+std::vector<hipEvent_t> g_ev_free;
+hipEvent_t ev_get() {
+  if (!g_ev_free.empty()) {
+    hipEvent_t e = g_ev_free.back();
+    g_ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  (void)hipEventCreate(&e);
+  return e;
+}
+// `bytes` = algorithmic HBM bytes of the launch (every input read once,
+// every output written once)
+struct ProfScope {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(const char* n, hipStream_t st, double bytes = 0) : name(n), s(st) {
+    if (g_prof_on) {
+      a = ev_get();
+      (void)hipEventRecord(a, s);
+      g_prof_bytes[name] += bytes;
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = ev_get();
+      (void)hipEventRecord(b, s);
+      g_prof[name].push_back({a, b});
+    }
+  }
+};
+void prof_collect() {
+  for (auto& kv : g_prof) {
+    auto& acc = g_prof_done[kv.first];
+    for (auto& p : kv.second) {
+      float ms = 0;
+      (void)hipEventSynchronize(p.b);
+      (void)hipEventElapsedTime(&ms, p.a, p.b);
+      acc.ms += ms;
+      acc.launches += 1;
+      g_ev_free.push_back(p.a);
+      g_ev_free.push_back(p.b);
+    }
+    kv.second.clear();
+  }
+  for (auto& kv : g_prof_bytes) g_prof_done[kv.first].bytes += kv.second;
+  g_prof_bytes.clear();
+}
+}  // namespace
+
+void prof_enable(bool on) {
+  prof_collect();
+  if (on) g_prof_done.clear();
+  g_prof_on = on;
+}
+bool prof_read(const char* family, double* ms, u64* launches, double* bytes) {
+  prof_collect();
+  auto it = g_prof_done.find(family);
+  if (it == g_prof_done.end()) {
+    *ms = 0;
+    *launches = 0;
+    *bytes = 0;
+    return false;
+  }
+  *ms = it->second.ms;
+  *launches = it->second.launches;
+  *bytes = it->second.bytes;
+  return true;
+}
+std::vector<std::string> prof_families() {
+  prof_collect();
+  std::vector<std::string> r;
+  for (auto& kv : g_prof_done) r.push_back(kv.first);
+  return r;
+}
+
 __device__ __forceinline__ int limb_mod(const LimbMap& m, int k) { return m.idx[k % m.n]; }
 
 __device__ __forceinline__ u32 brv(u32 x, int bits) { return __brev(x) >> (32 - bits); }
@@ -169,6 +262,9 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows(u64* data, LimbMap map, int lo
 
 void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s) {
   if (nlimbs <= 0) return;
+  int active = 0;
+  for (int k = 0; k < nlimbs; k++) active += map.idx[k % map.n] >= 0;
+  ProfScope ps("ntt", s, 16.0 * active * T.N);
   NttShape sh = ntt_shape(T.logN);
   dim3 gc(sh.T1 / sh.C, nlimbs), gr(sh.R / sh.K, nlimbs);
   if (!inverse) {
@@ -235,6 +331,9 @@ __global__ void k_elementwise(int op, u64* out, const u64* a, const u64* b, int 
 static void ew(const DeviceTables& T, int op, u64* out, const u64* a, const u64* b, int nlimbs, int b_limbs,
                const LimbMap& m, hipStream_t s) {
   if (nlimbs <= 0) return;
+  // reads a (and b once per distinct limb), writes out; the accumulate also reads out
+  double words = (double)nlimbs * (op == EW_MULACC ? 3 : (op == EW_NEG ? 2 : 2)) + (op == EW_NEG ? 0 : b_limbs);
+  ProfScope ps("elementwise", s, 8.0 * T.N * words);
   dim3 grid(cdiv(T.N, TPB), nlimbs);
   hipLaunchKernelGGL(k_elementwise, grid, dim3(TPB), 0, s, op, out, a, b, nlimbs, b_limbs, m, T.logN, T.mc);
 }
@@ -292,6 +391,7 @@ __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int logN,
   out[(size_t)(2 * nl + k) * N + i] = mul_mod(a1, b1, mk);
 }
 void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, hipStream_t s) {
+  ProfScope ps("tensor", s, 8.0 * T.N * 7 * nl);
   dim3 grid(cdiv(T.N, TPB), nl);
   hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, s, out3, a, b, nl, T.logN, T.mc);
 }
@@ -370,18 +470,67 @@ void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64
     A.hat_t[j] = tabs[j].hat_t;
     A.hat_t_sh[j] = tabs[j].hat_t_sh;
   }
+  ProfScope ps("modup", s, 8.0 * T.N * ((level + 1) + (double)beta * (level + 1 + alpha)));
   dim3 grid(cdiv(T.N, TPB), beta);
   hipLaunchKernelGGL(k_modup, grid, dim3(TPB), 0, s, digits, coef, ntt_in, A, T.logN, T.nmods, T.mc);
 }
 
 struct FbcArgs {
   int ns;
-  int src[8];
-  u64 hatinv[8], hatinv_sh[8];
+  int src[4];
+  u64 hatinv[4], hatinv_sh[4];
   const u64* hat_t;
   const u64* hat_t_sh;
+  u64 Dw[4];
+  u64 Hw[4][4];
+  double qd[4];
+  const u64* D_mod_t;
 };
-// y[t][i] = sum_a [x_a hatinv_a]_{p_a} (hat_a mod q_t) mod q_t for t < nq; batch over polys (grid.z)
+
+// acc (4 words) += H (4 words) * y, carries beyond the top word dropped
+__device__ __forceinline__ void w4_muladd(u64 acc[4], const u64 H[4], u64 y) {
+  u64 carry = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    u64 lo = H[k] * y, hi = mulhi64(H[k], y);
+    u64 s = acc[k] + lo;
+    u64 c1 = s < lo;
+    u64 s2 = s + carry;
+    u64 c2 = s2 < carry;
+    acc[k] = s2;
+    carry = hi + c1 + c2;
+  }
+}
+__device__ __forceinline__ int w4_cmp(const u64 a[4], const u64 b[4]) {
+  for (int k = 3; k >= 0; k--)
+    if (a[k] != b[k]) return a[k] < b[k] ? -1 : 1;
+  return 0;
+}
+
+// round(S / D) for S = sum_a y_a (D / q_a), 0 <= y_a < q_a: a double estimate
+// of sum_a y_a / q_a, replaced by an exact multiword comparison when the
+// estimate lies within 2^-40 of a rounding boundary (its error is < 2^-47).
+__device__ __forceinline__ u64 round_quotient(const u64* y, const FbcArgs& A) {
+  double f = 0.0;
+  for (int a = 0; a < A.ns; a++) f += (double)y[a] / A.qd[a];
+  double t = f + 0.5;
+  double fl = floor(t);
+  double fr = t - fl;
+  if (fr > 9.094947017729282e-13 && fr < 1.0 - 9.094947017729282e-13) return (u64)fl;
+  // exact: v = #{ w >= 1 : 2 S > (2w - 1) D }
+  u64 S2[4] = {0, 0, 0, 0};
+  for (int a = 0; a < A.ns; a++) w4_muladd(S2, A.Hw[a], 2 * y[a]);
+  u64 v = 0;
+  for (u64 w = 1; w <= (u64)A.ns; w++) {
+    u64 T[4] = {0, 0, 0, 0};
+    w4_muladd(T, A.Dw, 2 * w - 1);
+    if (w4_cmp(S2, T) > 0) v = w;
+  }
+  return v;
+}
+
+// y[t][i] = ([x]_D mod q_t) for t < nq, with [x]_D the exact centred residue
+// of the source limbs x (coefficient domain); batch over polys (grid.z)
 __global__ void k_fbc_to_q(u64* y, const u64* xp, int nq, FbcArgs A, int logN, int nmods,
                            const ModConst* __restrict__ mc) {
   const u64 N = 1ull << logN;
@@ -390,12 +539,14 @@ __global__ void k_fbc_to_q(u64* y, const u64* xp, int nq, FbcArgs A, int logN, i
   int poly = blockIdx.z;
   const u64* x = xp + (size_t)poly * A.ns * N;
   u64* yy = y + (size_t)poly * nq * N;
-  u64 v[8];
+  u64 v[4];
   for (int a = 0; a < A.ns; a++) v[a] = shoup_mul(x[(size_t)a * N + i], A.hatinv[a], A.hatinv_sh[a], mc[A.src[a]].q);
+  const u64 r = round_quotient(v, A);
   for (int t = blockIdx.y; t < nq; t += gridDim.y) {
     u64 q = mc[t].q, acc = 0;
     for (int a = 0; a < A.ns; a++)
       acc = add_mod(acc, shoup_mul(v[a], A.hat_t[(size_t)a * nmods + t], A.hat_t_sh[(size_t)a * nmods + t], q), q);
+    acc = sub_mod(acc, shoup_mul(r, A.D_mod_t[2 * t], A.D_mod_t[2 * t + 1], q), q);
     yy[(size_t)t * N + i] = acc;
   }
 }
@@ -407,9 +558,14 @@ void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, 
     A.src[a] = tab.src[a];
     A.hatinv[a] = tab.hatinv[a];
     A.hatinv_sh[a] = tab.hatinv_sh[a];
+    A.qd[a] = tab.qd[a];
+    for (int w = 0; w < 4; w++) A.Hw[a][w] = tab.Hw[a][w];
   }
+  for (int w = 0; w < 4; w++) A.Dw[w] = tab.Dw[w];
   A.hat_t = tab.hat_t;
   A.hat_t_sh = tab.hat_t_sh;
+  A.D_mod_t = tab.D_mod_t;
+  ProfScope ps("moddown", s, 8.0 * T.N * (2.0 * tab.ns + 2.0 * nq));
   dim3 grid(cdiv(T.N, TPB), nq < 8 ? nq : 8, 2);
   hipLaunchKernelGGL(k_fbc_to_q, grid, dim3(TPB), 0, s, y, xp_coef, nq, A, T.logN, T.nmods, T.mc);
 }
@@ -427,6 +583,7 @@ __global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, co
 }
 void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u64* y, int nq, const u64* pinv,
                           int npoly, int x_stride_limbs, hipStream_t s) {
+  ProfScope ps("moddown", s, 8.0 * T.N * 3.0 * npoly * nq);
   dim3 grid(cdiv(T.N, TPB), nq, npoly);
   hipLaunchKernelGGL(k_moddown_final, grid, dim3(TPB), 0, s, out, x, y, nq, pinv, x_stride_limbs, T.logN, T.mc);
 }
@@ -462,6 +619,8 @@ __global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict
 void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,
                     const u64* pmod, int level, int L, int alpha, int beta, u64 g, hipStream_t s) {
   int nq = level + 1, nqp = nq + alpha;
+  // digits + both key halves + c0 read once, both output polys written once
+  ProfScope ps("multsum", s, 8.0 * T.N * (3.0 * beta * nqp + (c0 ? nq : 0) + 2.0 * nqp));
   dim3 grid(cdiv(T.N, TPB), nqp);
   hipLaunchKernelGGL(k_multsum, grid, dim3(TPB), 0, s, out, digits, key, c0, pmod, nq, nqp, L, beta, T.nmods, g,
                      T.logN, T.mc);
@@ -481,6 +640,7 @@ __global__ void k_plift(u64* out, const u64* c, const u64* pmod, int nq, int nqp
 void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha,
                   hipStream_t s) {
   int nq = level + 1, nqp = nq + alpha;
+  ProfScope ps("plift", s, 8.0 * T.N * (2.0 * nq + 2.0 * nqp));
   dim3 grid(cdiv(T.N, TPB), nqp, 2);
   hipLaunchKernelGGL(k_plift, grid, dim3(TPB), 0, s, out, c, pmod, nq, nqp, T.logN, T.mc);
 }
@@ -506,6 +666,7 @@ __global__ void k_rescale_lift(u64* t, const u64* top, int l, int logN, const Mo
   t[((size_t)p * l + k) * N + i] = v;
 }
 void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int npoly, hipStream_t s) {
+  ProfScope ps("rescale", s, 8.0 * T.N * npoly * (1.0 + l));
   dim3 grid(cdiv(T.N, TPB), l, npoly);
   hipLaunchKernelGGL(k_rescale_lift, grid, dim3(TPB), 0, s, t, top_coef, l, T.logN, T.mc);
 }
@@ -521,6 +682,7 @@ __global__ void k_rescale_final(u64* out, const u64* x, const u64* t, int l, int
 }
 void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u64* t, int l, int npoly,
                           int x_stride_limbs, const u64* qlinv, hipStream_t s) {
+  ProfScope ps("rescale", s, 8.0 * T.N * npoly * 3.0 * l);
   dim3 grid(cdiv(T.N, TPB), l, npoly);
   hipLaunchKernelGGL(k_rescale_final, grid, dim3(TPB), 0, s, out, x, t, l, x_stride_limbs, qlinv, T.logN, T.mc);
 }

@@ -222,6 +222,33 @@ static FbcTable make_fbc(HeCtxImpl* c, const std::vector<int>& src) {
   }
   t.hat_t = c->table_upload(hat.data(), hat.size() * 8);
   t.hat_t_sh = c->table_upload(hat_sh.data(), hat_sh.size() * 8);
+  // D and its cofactors as 4-word integers (for the exact centred lift)
+  auto mul_words = [](u64* w, u64 v) {
+    u128 carry = 0;
+    for (int k = 0; k < 4; k++) {
+      u128 p = (u128)w[k] * v + carry;
+      w[k] = (u64)p;
+      carry = p >> 64;
+    }
+  };
+  for (int k = 0; k < 4; k++) t.Dw[k] = 0;
+  t.Dw[0] = 1;
+  for (int a = 0; a < t.ns; a++) mul_words(t.Dw, c->mods[src[a]]);
+  for (int a = 0; a < t.ns; a++) {
+    for (int k = 0; k < 4; k++) t.Hw[a][k] = 0;
+    t.Hw[a][0] = 1;
+    for (int b = 0; b < t.ns; b++)
+      if (b != a) mul_words(t.Hw[a], c->mods[src[b]]);
+    t.qd[a] = (double)c->mods[src[a]];
+  }
+  std::vector<u64> dm((size_t)c->nmods * 2);
+  for (int m = 0; m < c->nmods; m++) {
+    u64 qt = c->mods[m], d = 1;
+    for (int a = 0; a < t.ns; a++) d = hmul(d, c->mods[src[a]] % qt, qt);
+    dm[2 * m] = d;
+    dm[2 * m + 1] = shoup_pre(d, qt);
+  }
+  t.D_mod_t = c->table_upload(dm.data(), dm.size() * 8);
   return t;
 }
 

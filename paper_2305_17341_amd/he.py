@@ -25,7 +25,7 @@ EXPORTS = [
     "he_ct_export", "he_ct_import", "he_ct_free", "he_add", "he_sub", "he_mult", "he_rescale", "he_rotate",
     "he_drop_level", "he_pmult_slots", "he_lintrans", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
     "he_mem_info", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
-    "he_last_error",
+    "he_profile_enable", "he_profile_read", "he_op_counts", "he_last_error",
 ]
 
 u64p = C.POINTER(C.c_uint64)
@@ -98,6 +98,9 @@ def load():
         "he_automorph_limbs": [vp, u64p, u64p, C.c_size_t, C.c_uint64],
         "he_hoisted_rotate_export": [vp, vp, C.c_int32, u64p, C.c_size_t],
         "he_last_op_ms": [vp, dblp],
+        "he_profile_enable": [vp, C.c_int],
+        "he_profile_read": [vp, C.c_char_p, dblp, u64p, dblp],
+        "he_op_counts": [vp, u64p, u64p, u64p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -294,6 +297,20 @@ class Context:
         ms = C.c_double()
         _check(load().he_last_op_ms(self.ptr, C.byref(ms)))
         return ms.value
+
+    def profile_enable(self, on=True):
+        _check(load().he_profile_enable(self.ptr, 1 if on else 0))
+
+    def profile_read(self, family):
+        """(device ms, launches, algorithmic bytes) of a kernel family since enabling."""
+        ms, n, b = C.c_double(), C.c_uint64(), C.c_double()
+        _check(load().he_profile_read(self.ptr, family.encode(), C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, n.value, b.value
+
+    def op_counts(self):
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(load().he_op_counts(self.ptr, C.byref(a), C.byref(b), C.byref(c)))
+        return {"decompose": a.value, "multsum": b.value, "moddown": c.value}
 
     # raw pieces for parity checks
     def ntt_limbs(self, limbs, mod_idx, inverse=False):
