@@ -1142,14 +1142,15 @@ typedef struct {
 
 static i64 pmod_i(i64 a, i64 m) { return ((a % m) + m) % m; }
 
-/* diagonal u_l, pre-rotated by -shift: out[t] = u_l[t - shift] */
+/* diagonal u_l, pre-rotated by -shift: out[t] = u_l[t - shift]
+ * (perm[s] < 0 marks an all-zero row) */
 static int diag_vec(const lt_perm *U, i64 l, i64 shift, double *out) {
   int nz = 0;
   i64 n2 = U->n2;
   for (i64 t = 0; t < n2; t++) {
     i64 s = pmod_i(t - shift, n2);
     double v = 0.0;
-    if (pmod_i((i64)U->perm[s] - s, n2) == pmod_i(l, n2)) v = U->w ? U->w[s] : 1.0;
+    if (U->perm[s] >= 0 && pmod_i((i64)U->perm[s] - s, n2) == pmod_i(l, n2)) v = U->w ? U->w[s] : 1.0;
     out[t] = v;
     if (v != 0.0) nz = 1;
   }
@@ -1325,8 +1326,148 @@ oc_ct *oc_lt_transpose(const oc_ctx *c, const oc_ct *x, int n, int n1, double we
 }
 
 /* ------------------------------------------------------------------------ */
-/* The homomorphic matrix product (Eq. 4; Algorithm DMatrixMult without a    */
-/* decomposition; hoisted column/row shifts of section 4.1.1).               */
+/* Diagonal convergence decomposition (section 4.2: Definition 4, Theorem 2, */
+/* Algorithms DCDforZ and DCDforT).                                          */
+/*                                                                           */
+/* A permutation transform (output t takes input perm[t]) is written as a   */
+/* product L R_m ... R_1 (R_1 applied first).  Following one 1-entry of the */
+/* matrix with remaining diagonal k, each right factor moves it by r(k) and */
+/* keeps the column (Definition 4); the left factor takes the rest:          */
+/*   Z: |k| >= n'  -> r = sign(k) n',  else 0   (Z split into k >= 0, k < 0) */
+/*   T: k = i n, i > n' -> r = n' n,    else 0                                */
+/* with ceil((n-1)/n') - 1 right factors.                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int n2;
+  int *perm; /* -1: zero row */
+  i64 a;     /* BSGS stride */
+  int n1, i_lo, i_hi;
+} oc_factor;
+
+static i64 floor_div_i(i64 a, i64 b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+enum { DCD_Z1 = 0, DCD_Z2 = 1, DCD_T = 2 };
+
+/* factors in application order; returns their count, -1 if a factor would
+ * not be a partial permutation */
+static int dcd_chain(int n, const int *perm, int which, int nprime, int n1, oc_factor *out) {
+  int n2 = n * n;
+  int iters = ceil_div(n - 1, nprime) - 1;
+  i64 *pos = (i64 *)malloc(sizeof(i64) * n2), *k = (i64 *)malloc(sizeof(i64) * n2);
+  char *sel = (char *)calloc(n2, 1);
+  for (int t = 0; t < n2; t++) {
+    i64 kk = which == DCD_T ? pmod_i((i64)perm[t] - t, n2) : (i64)perm[t] - t;
+    if (which == DCD_Z1 && kk < 0) continue;
+    if (which == DCD_Z2 && kk >= 0) continue;
+    sel[t] = 1;
+    pos[t] = perm[t];
+    k[t] = kk;
+  }
+  i64 dnz = which == DCD_Z1 ? nprime : which == DCD_Z2 ? -nprime : (i64)nprime * n;
+  for (int j = 0; j < iters; j++) {
+    oc_factor *f = &out[j];
+    f->n2 = n2;
+    f->perm = (int *)malloc(sizeof(int) * n2);
+    for (int t = 0; t < n2; t++) f->perm[t] = -1;
+    for (int t = 0; t < n2; t++) {
+      if (!sel[t]) continue;
+      i64 d;
+      if (which == DCD_T) d = (k[t] / n > nprime) ? dnz : 0;
+      else d = (k[t] >= nprime || k[t] <= -nprime) ? dnz : 0;
+      i64 np = pmod_i(pos[t] - d, n2);
+      if (f->perm[np] != -1) { free(pos); free(k); free(sel); return -1; }
+      f->perm[np] = (int)pos[t];
+      pos[t] = np;
+      k[t] -= d;
+    }
+    f->a = dnz;
+    f->n1 = 2;
+    f->i_lo = 0;
+    f->i_hi = 1;
+  }
+  oc_factor *lf = &out[iters];
+  lf->n2 = n2;
+  lf->perm = (int *)malloc(sizeof(int) * n2);
+  i64 a = which == DCD_T ? n : 1, kmin = 0, kmax = 0;
+  int first = 1;
+  for (int t = 0; t < n2; t++) {
+    lf->perm[t] = sel[t] ? (int)pos[t] : -1;
+    if (!sel[t]) continue;
+    i64 kk = k[t] / a;
+    if (first || kk < kmin) kmin = kk;
+    if (first || kk > kmax) kmax = kk;
+    first = 0;
+  }
+  lf->a = a;
+  lf->n1 = n1;
+  lf->i_lo = (int)floor_div_i(kmin, n1);
+  lf->i_hi = (int)floor_div_i(kmax, n1) + 1;
+  free(pos); free(k); free(sel);
+  return iters + 1;
+}
+
+/* exported for the planner pins: factor count and each factor's perm */
+int oc_dcd_factors(int n, int which, int nprime, int n1, int *perms /* [maxf][n*n] */, long long *geom /* [maxf][4] */,
+                   int maxf) {
+  int *p = which == DCD_T ? perm_tau(n) : perm_sigma(n);
+  oc_factor f[64];
+  int nf = dcd_chain(n, p, which, nprime, n1, f);
+  free(p);
+  if (nf < 0) return -1;
+  for (int j = 0; j < nf; j++) {
+    if (j < maxf) {
+      memcpy(perms + (size_t)j * n * n, f[j].perm, sizeof(int) * n * n);
+      geom[4 * j] = f[j].a; geom[4 * j + 1] = f[j].n1; geom[4 * j + 2] = f[j].i_lo; geom[4 * j + 3] = f[j].i_hi;
+    }
+    free(f[j].perm);
+  }
+  return nf;
+}
+
+static oc_ct *apply_chain(const oc_ctx *c, const oc_ct *x, const oc_factor *f, int nf, int *err) {
+  oc_ct *cur = oc_ct_copy(c, x);
+  for (int j = 0; j < nf && cur; j++) {
+    lt_perm U = {f[j].n2, f[j].perm, NULL};
+    oc_ct *nx = lintrans(c, cur, &U, f[j].a, f[j].n1, f[j].i_lo, f[j].i_hi, c->delta, err);
+    oc_ct_free(cur);
+    cur = nx;
+  }
+  return cur;
+}
+
+/* sigma (Z) of Algorithm DMatrixMult: Z1 chain + Z2 chain when n' < n-1 */
+static oc_ct *sigma_dcd(const oc_ctx *c, const oc_ct *x, int n, int n1, int nprime, int *err) {
+  if (nprime >= n - 1) return oc_lt_sigma(c, x, n, n1, err);
+  int *p = perm_sigma(n);
+  oc_factor f1[64], f2[64];
+  int c1 = dcd_chain(n, p, DCD_Z1, nprime, n1, f1), c2 = dcd_chain(n, p, DCD_Z2, nprime, n1, f2);
+  free(p);
+  if (c1 < 0 || c2 < 0) { *err = -1; return NULL; }
+  oc_ct *a1 = apply_chain(c, x, f1, c1, err);
+  oc_ct *a2 = apply_chain(c, x, f2, c2, err);
+  oc_ct *r = (a1 && a2) ? oc_add(c, a1, a2) : NULL;
+  oc_ct_free(a1); oc_ct_free(a2);
+  for (int j = 0; j < c1; j++) free(f1[j].perm);
+  for (int j = 0; j < c2; j++) free(f2[j].perm);
+  return r;
+}
+
+/* tau (T): one chain when n' < n-1 */
+static oc_ct *tau_dcd(const oc_ctx *c, const oc_ct *x, int n, int n1, int nprime, int *err) {
+  if (nprime >= n - 1) return oc_lt_tau(c, x, n, n1, err);
+  int *p = perm_tau(n);
+  oc_factor f[64];
+  int nf = dcd_chain(n, p, DCD_T, nprime, n1, f);
+  free(p);
+  if (nf < 0) { *err = -1; return NULL; }
+  oc_ct *r = apply_chain(c, x, f, nf, err);
+  for (int j = 0; j < nf; j++) free(f[j].perm);
+  return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The homomorphic matrix product (Eq. 4; Algorithm DMatrixMult; hoisted     */
+/* column / row shifts of section 4.1.1).                                    */
 /* ------------------------------------------------------------------------ */
 static void col_mask(int n, int k, int second, double *out) {
   for (int i = 0; i < n; i++)
@@ -1336,34 +1477,28 @@ static void col_mask(int n, int k, int second, double *out) {
     }
 }
 
-oc_ct *oc_matmul(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int *err) {
+/* A side: A_k = C^k Z a for k < n.  Bases B_b = Rot(B_{b-1}, n1z) from
+ * B_0 = Z a and B'_0 = Rot(Z a, -n); for k = b n1z + r:
+ *   A_k = Rescale(ModDown(m_k (.) HR(B_b, r) + m'_k (.) HR(B'_b, r))). */
+static oc_ct **side_a(const oc_ctx *c, const oc_ct *ca, int n, int n1z, int npz, int *err) {
   u64 N = c->N;
-  *err = 0;
-  if (ca->qp || cb->qp || ca->level != cb->level || ca->level < 3) { *err = -2; return NULL; }
-  if ((u64)n * n > N / 2 || n % n1z || n % n1t) { *err = -1; return NULL; }
   int n2sq = n * n;
-  /* sigma(A), tau(B): level l -> l-1 */
-  oc_ct *A0 = oc_lt_sigma(c, ca, n, n1z, err);
+  oc_ct *A0 = sigma_dcd(c, ca, n, n1z, npz, err);
   if (!A0) return NULL;
-  oc_ct *B0 = oc_lt_tau(c, cb, n, n1t, err);
-  if (!B0) { oc_ct_free(A0); return NULL; }
+  if (A0->level < 1) { *err = -2; oc_ct_free(A0); return NULL; }
   int lvl = A0->level;
   double *vec = (double *)malloc(sizeof(double) * n2sq);
   i64 *m = (i64 *)malloc(sizeof(i64) * N);
   oc_ct **Ak = (oc_ct **)calloc(n, sizeof(oc_ct *));
-  oc_ct **Bk = (oc_ct **)calloc(n, sizeof(oc_ct *));
-  /* phi^k: bases B_b = Rot(B_{b-1}, n1z), B'_0 = Rot(A0, -n), B'_b = Rot(B'_{b-1}, n1z) */
   oc_ct *Bb = oc_ct_copy(c, A0), *Bpb = oc_rotate(c, A0, -(i64)n);
-  g_counts.decompose++; g_counts.multsum++; g_counts.moddown++;
-  for (int b = 0; b * n1z < n; b++) {
+  for (int b = 0; b * n1z < n && Bb && Bpb; b++) {
     if (b > 0) {
       oc_ct *t = oc_rotate(c, Bb, n1z); oc_ct_free(Bb); Bb = t;
       t = oc_rotate(c, Bpb, n1z); oc_ct_free(Bpb); Bpb = t;
-      g_counts.decompose += 2; g_counts.multsum += 2; g_counts.moddown += 2;
+      if (!Bb || !Bpb) break;
     }
     u64 *d1 = oc_decompose(c, poly(c, Bb, 1, 0), lvl);
     u64 *d2 = oc_decompose(c, poly(c, Bpb, 1, 0), lvl);
-    g_counts.decompose += 2;
     for (int r = 0; r < n1z && b * n1z + r < n; r++) {
       int k = b * n1z + r;
       u64 g = oc_galois_of_step(c, r);
@@ -1373,63 +1508,158 @@ oc_ct *oc_matmul(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n
       pt_int(c, vec, n2sq, c->delta, m);
       qp_pmult_acc(c, acc, h, m);
       oc_ct_free(h);
-      if (r) g_counts.multsum++;
       if (k > 0) {
         h = hoisted_rot(c, Bpb, d2, g, err);
         col_mask(n, k, 1, vec);
         pt_int(c, vec, n2sq, c->delta, m);
         qp_pmult_acc(c, acc, h, m);
         oc_ct_free(h);
-        if (r) g_counts.multsum++;
       }
       oc_ct *md = oc_moddown(c, acc);
-      g_counts.moddown++;
       Ak[k] = oc_rescale(c, md);
-      g_counts.rescale++;
       oc_ct_free(md);
       oc_ct_free(acc);
     }
     free(d1); free(d2);
   }
-  oc_ct_free(Bb); oc_ct_free(Bpb);
-  /* psi^k: C_0 = B0, C_b = Rot(C_{b-1}, n n1t); B_k = ModDown(HR(C_b, n r)) */
-  oc_ct *Cb = oc_ct_copy(c, B0);
-  for (int b = 0; b * n1t < n; b++) {
+  oc_ct_free(Bb); oc_ct_free(Bpb); oc_ct_free(A0);
+  free(vec); free(m);
+  for (int k = 0; k < n; k++)
+    if (!Ak[k]) { if (!*err) *err = -4; for (int j = 0; j < n; j++) oc_ct_free(Ak[j]); free(Ak); return NULL; }
+  return Ak;
+}
+
+/* B side: B_k = R^k T b.  C_0 = T b, C_b = Rot(C_{b-1}, n n1t),
+ * B_k = ModDown(HR(C_b, n r)) for k = b n1t + r (C_b itself for r = 0). */
+static oc_ct **side_b(const oc_ctx *c, const oc_ct *cb, int n, int n1t, int npt, int *err) {
+  oc_ct *Cb = tau_dcd(c, cb, n, n1t, npt, err);
+  if (!Cb) return NULL;
+  int lvl = Cb->level;
+  oc_ct **Bk = (oc_ct **)calloc(n, sizeof(oc_ct *));
+  for (int b = 0; b * n1t < n && Cb; b++) {
     if (b > 0) {
       oc_ct *t = oc_rotate(c, Cb, (i64)n * n1t); oc_ct_free(Cb); Cb = t;
-      g_counts.decompose++; g_counts.multsum++; g_counts.moddown++;
+      if (!Cb) break;
     }
     u64 *d1 = oc_decompose(c, poly(c, Cb, 1, 0), lvl);
-    g_counts.decompose++;
     for (int r = 0; r < n1t && b * n1t + r < n; r++) {
       int k = b * n1t + r;
-      oc_ct *full;
-      if (r == 0) full = oc_ct_copy(c, Cb);
+      if (r == 0) Bk[k] = oc_ct_copy(c, Cb);
       else {
         oc_ct *h = hoisted_rot(c, Cb, d1, oc_galois_of_step(c, (i64)n * r), err);
-        full = oc_moddown(c, h);
+        if (h) Bk[k] = oc_moddown(c, h);
         oc_ct_free(h);
-        g_counts.multsum++; g_counts.moddown++;
       }
-      Bk[k] = oc_drop(c, full, lvl - 1);
-      oc_ct_free(full);
     }
     free(d1);
   }
   oc_ct_free(Cb);
-  /* products: sum_k Relin(Tensor(A_k, B_k)), then one Rescale */
-  oc_ct *acc = NULL;
+  for (int k = 0; k < n; k++)
+    if (!Bk[k]) { if (!*err) *err = -4; for (int j = 0; j < n; j++) oc_ct_free(Bk[j]); free(Bk); return NULL; }
+  return Bk;
+}
+
+/* both sides dropped to their common (lowest) level */
+static void align_sides(const oc_ctx *c, oc_ct **Ak, oc_ct **Bk, int n) {
+  int lv = Ak[0]->level < Bk[0]->level ? Ak[0]->level : Bk[0]->level;
+  for (int k = 0; k < n; k++) {
+    if (Ak[k]->level > lv) { oc_ct *t = oc_drop(c, Ak[k], lv); oc_ct_free(Ak[k]); Ak[k] = t; }
+    if (Bk[k]->level > lv) { oc_ct *t = oc_drop(c, Bk[k], lv); oc_ct_free(Bk[k]); Bk[k] = t; }
+  }
+}
+
+/* acc += sum_k Relin(Tensor(A_k, B_k)) */
+static oc_ct *accumulate(const oc_ctx *c, oc_ct *acc, oc_ct **Ak, oc_ct **Bk, int n) {
   for (int k = 0; k < n; k++) {
     oc_ct *p = oc_mult(c, Ak[k], Bk[k]);
-    g_counts.decompose++; g_counts.multsum++; g_counts.moddown++;
     if (!acc) acc = p;
     else { add_into(c, acc, p); oc_ct_free(p); }
   }
+  return acc;
+}
+
+static void free_list(oc_ct **l, int n) {
+  if (!l) return;
+  for (int k = 0; k < n; k++) oc_ct_free(l[k]);
+  free(l);
+}
+
+oc_ct *oc_matmul_ex(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int npz, int npt,
+                    int *err) {
+  *err = 0;
+  if (ca->qp || cb->qp || ca->level != cb->level) { *err = -2; return NULL; }
+  if ((u64)n * n > c->N / 2 || n % n1z || n % n1t || npz < 1 || npt < 1) { *err = -1; return NULL; }
+  oc_ct **Ak = side_a(c, ca, n, n1z, npz, err);
+  if (!Ak) return NULL;
+  oc_ct **Bk = side_b(c, cb, n, n1t, npt, err);
+  if (!Bk) { free_list(Ak, n); return NULL; }
+  align_sides(c, Ak, Bk, n);
+  if (Ak[0]->level < 1) { *err = -2; free_list(Ak, n); free_list(Bk, n); return NULL; }
+  oc_ct *acc = accumulate(c, NULL, Ak, Bk, n);
   oc_ct *out = oc_rescale(c, acc);
-  g_counts.rescale++;
   oc_ct_free(acc);
-  for (int k = 0; k < n; k++) { oc_ct_free(Ak[k]); oc_ct_free(Bk[k]); }
-  free(Ak); free(Bk); free(vec); free(m);
-  oc_ct_free(A0); oc_ct_free(B0);
+  free_list(Ak, n); free_list(Bk, n);
   return out;
+}
+
+oc_ct *oc_matmul(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int *err) {
+  return oc_matmul_ex(c, ca, cb, n, n1z, n1t, n - 1, n - 1, err);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Covariance of a centred dataset (Algorithm HCovMtrx, section 5.2).        */
+/* x[r k + j] = block (row block r, feature block j).  Block (a, b) of        */
+/* X^T X / s for b <= a is Rescale(sum_r sum_k Relin(Tensor(A_k, B_k))) with */
+/* A from G(x[r k + a]) scaled by 1/s and B from x[r k + b]; blocks a < b    */
+/* are G of block (b, a); every block ends at one level.                     */
+/* ------------------------------------------------------------------------ */
+int oc_covariance(const oc_ctx *c, oc_ct *const *x, int rb, int k, int n, u64 n_samples, int n1z, int n1t, int npz,
+                  int npt, int n1g, oc_ct **out) {
+  int err = 0;
+  int level = x[0]->level;
+  oc_ct **acc = (oc_ct **)calloc(k * k, sizeof(oc_ct *));
+  for (int r = 0; r < rb; r++) {
+    oc_ct ***A = (oc_ct ***)calloc(k, sizeof(oc_ct **)), ***B = (oc_ct ***)calloc(k, sizeof(oc_ct **));
+    for (int a = 0; a < k; a++) {
+      oc_ct *xt = oc_lt_transpose(c, x[r * k + a], n, n1g, 1.0 / (double)n_samples, &err);
+      if (!xt) return err ? err : -1;
+      A[a] = side_a(c, xt, n, n1z, npz, &err);
+      oc_ct_free(xt);
+      if (!A[a]) return err ? err : -1;
+    }
+    for (int b = 0; b < k; b++) {
+      oc_ct *xb = oc_drop(c, x[r * k + b], level - 1);
+      B[b] = side_b(c, xb, n, n1t, npt, &err);
+      oc_ct_free(xb);
+      if (!B[b]) return err ? err : -1;
+    }
+    for (int a = 0; a < k; a++) align_sides(c, A[a], B[0], n);
+    for (int b = 0; b < k; b++) align_sides(c, A[0], B[b], n);
+    for (int a = 0; a < k; a++)
+      for (int b = 0; b <= a; b++) acc[a * k + b] = accumulate(c, acc[a * k + b], A[a], B[b], n);
+    for (int a = 0; a < k; a++) free_list(A[a], n);
+    for (int b = 0; b < k; b++) free_list(B[b], n);
+    free(A); free(B);
+  }
+  for (int a = 0; a < k; a++)
+    for (int b = 0; b <= a; b++) {
+      out[a * k + b] = oc_rescale(c, acc[a * k + b]);
+      oc_ct_free(acc[a * k + b]);
+    }
+  free(acc);
+  for (int a = 0; a < k; a++)
+    for (int b = a + 1; b < k; b++) {
+      out[a * k + b] = oc_lt_transpose(c, out[b * k + a], n, n1g, 1.0, &err);
+      if (!out[a * k + b]) return err ? err : -1;
+    }
+  if (k > 1) {
+    int fl = out[1]->level;
+    for (int a = 0; a < k; a++)
+      for (int b = 0; b <= a; b++) {
+        oc_ct *t = oc_drop(c, out[a * k + b], fl);
+        oc_ct_free(out[a * k + b]);
+        out[a * k + b] = t;
+      }
+  }
+  return 0;
 }

@@ -117,6 +117,12 @@ def lib():
         L.oc_lt_transpose.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double, intp]
         L.oc_matmul.restype = C.c_void_p
         L.oc_matmul.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, intp]
+        L.oc_matmul_ex.restype = C.c_void_p
+        L.oc_matmul_ex.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, intp]
+        L.oc_dcd_factors.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, intp, C.POINTER(C.c_longlong), C.c_int]
+        L.oc_covariance.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_uint64,
+                                    C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
         L.oc_perm.argtypes = [C.c_int, C.c_int, intp]
         L.oc_counts_reset.argtypes = []
         L.oc_counts_get.argtypes = [intp]
@@ -364,8 +370,37 @@ class Oracle:
     def lt_transpose(self, a, n, n1, weight=1.0):
         return self._lt(lib().oc_lt_transpose, a.ptr, n, n1, weight)
 
-    def matmul(self, a, b, n, n1z, n1t):
-        return self._lt(lib().oc_matmul, a.ptr, b.ptr, n, n1z, n1t)
+    def matmul(self, a, b, n, n1z, n1t, npz=None, npt=None):
+        npz = n - 1 if npz is None else npz
+        npt = n - 1 if npt is None else npt
+        return self._lt(lib().oc_matmul_ex, a.ptr, b.ptr, n, n1z, n1t, npz, npt)
+
+    def covariance(self, blocks, rb, k, n, n_samples, n1z, n1t, n1g, npz=None, npt=None):
+        npz = n - 1 if npz is None else npz
+        npt = n - 1 if npt is None else npt
+        px = (C.c_void_p * len(blocks))(*[b.ptr for b in blocks])
+        out = (C.c_void_p * (k * k))()
+        rc = lib().oc_covariance(self.ptr, px, rb, k, n, n_samples, n1z, n1t, npz, npt, n1g, out)
+        if rc:
+            raise RuntimeError(f"covariance failed ({rc})")
+        return [Ct(self, out[i]) for i in range(k * k)]
+
+
+DCD_KIND = {"Z1": 0, "Z2": 1, "T": 2}
+
+
+def dcd_factors(n, which, nprime, n1):
+    """Factors of the diagonal convergence decomposition in application order:
+    list of (perm, (a, n1, i_lo, i_hi)); perm[t] = input of output t or -1."""
+    maxf = 64
+    perms = np.zeros(maxf * n * n, dtype=np.int32)
+    geom = np.zeros(maxf * 4, dtype=np.int64)
+    nf = lib().oc_dcd_factors(n, DCD_KIND[which], nprime, n1, perms.ctypes.data_as(intp),
+                              geom.ctypes.data_as(C.POINTER(C.c_longlong)), maxf)
+    if nf < 0:
+        raise ValueError("decomposition is not a product of partial permutations")
+    return [(perms[j * n * n:(j + 1) * n * n].copy(), tuple(int(v) for v in geom[4 * j:4 * j + 4]))
+            for j in range(nf)]
 
 
 def perm(which: str, n: int) -> np.ndarray:

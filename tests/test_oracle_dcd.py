@@ -1,0 +1,152 @@
+"""Pins of the diagonal convergence decomposition (section 4.2) and of the
+covariance circuit (section 5.2) in the oracle.
+
+* composing the factors reproduces Z (= Z1-chain + Z2-chain) and T exactly;
+* ceil((n-1)/n') factors; right factors only on diagonals {0, +-n'} (Z) or
+  {0, n' n} (T); leftmost within [-n'+1, n'-1] (Z) or {0..n'} n (T);
+* the rotation keys the factors need reproduce every row of Table 3;
+* decrypt(DCD product) and decrypt(covariance) match FP64.
+"""
+import csv
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2305_17341_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def compose(factors, n2):
+    """apply the factors (first one first) to the index vector: entry t ends up
+    holding the input index it reads, or -1"""
+    v = np.arange(n2)
+    for p, _ in factors:
+        p = np.asarray(p)
+        v = np.where(p >= 0, v[np.maximum(p, 0)], -1)
+        v = np.where(p >= 0, v, -1)
+    return v
+
+
+def diagonals(p):
+    n2 = len(p)
+    return {(s - t) % n2 for t, s in enumerate(p) if s >= 0}
+
+
+def signed(d, n2):
+    return d - n2 if d > n2 // 2 else d
+
+
+CASES = [(16, 4, 4), (16, 8, 4), (32, 8, 4), (64, 16, 8), (128, 32, 16), (128, 64, 16)]
+
+
+@pytest.mark.parametrize("n,nprime,n1", CASES)
+def test_dcd_z_composes_to_sigma(oracle_mod, n, nprime, n1):
+    n2 = n * n
+    total = np.full(n2, -1)
+    for which in ("Z1", "Z2"):
+        fs = oracle_mod.dcd_factors(n, which, nprime, n1)
+        assert len(fs) == math.ceil((n - 1) / nprime)
+        for p, _ in fs[:-1]:
+            assert {signed(d, n2) for d in diagonals(p)} <= {0, nprime if which == "Z1" else -nprime}
+        left = {signed(d, n2) for d in diagonals(fs[-1][0])}
+        assert all(-nprime < d < nprime for d in left)
+        v = compose(fs, n2)
+        assert np.all((total < 0) | (v < 0))          # Z1 and Z2 fill disjoint rows
+        total = np.where(v >= 0, v, total)
+    assert np.array_equal(total, oracle_mod.perm("sigma", n))
+
+
+@pytest.mark.parametrize("n,nprime,n1", CASES)
+def test_dcd_t_composes_to_tau(oracle_mod, n, nprime, n1):
+    fs = oracle_mod.dcd_factors(n, "T", nprime, n1)
+    assert len(fs) == math.ceil((n - 1) / nprime)
+    for p, _ in fs[:-1]:
+        assert diagonals(p) <= {0, nprime * n}
+    assert diagonals(fs[-1][0]) <= {i * n for i in range(nprime + 1)}
+    assert np.array_equal(compose(fs, n * n), oracle_mod.perm("tau", n))
+
+
+def factor_keys(p, geom):
+    """rotation steps a double-hoisted BSGS over this factor performs"""
+    a, n1, i_lo, i_hi = geom
+    n2 = len(p)
+    present = diagonals(p)
+    keys = set()
+    for i in range(i_lo, i_hi):
+        js = [j for j in range(n1) if (a * (n1 * i + j)) % n2 in present]
+        if not js:
+            continue
+        keys |= {a * j for j in js if j}
+        if i:
+            keys.add(a * n1 * i)
+    return keys
+
+
+def transform_keys(oracle_mod, matrix, n, n1, maxdiag):
+    if maxdiag >= n - 1:
+        kind = "sigma" if matrix == "Z" else "tau"
+        p = oracle_mod.perm(kind, n)
+        n2 = -(-n // n1)
+        geom = (1, n1, -n2, n2) if matrix == "Z" else (n, n1, 0, n2)
+        return factor_keys(p, geom)
+    keys = set()
+    for which in (("Z1", "Z2") if matrix == "Z" else ("T",)):
+        for p, g in oracle_mod.dcd_factors(n, which, maxdiag, n1):
+            keys |= factor_keys(p, g)
+    return keys
+
+
+def test_key_counts_reproduce_table3(oracle_mod):
+    rows = list(csv.DictReader(l for l in open(os.path.join(HERE, "golden", "table3_ZT_keys.csv"))
+                               if not l.startswith("#")))
+    assert len(rows) == 12
+    for r in rows:
+        keys = transform_keys(oracle_mod, r["matrix"], 128, int(r["n1"]), int(r["maxdiag"]))
+        assert 45 * (len(keys) + 1) == int(r["rtk_mb"]), r
+        depth = 1 if int(r["maxdiag"]) == 127 else math.ceil(127 / int(r["maxdiag"]))
+        assert depth == int(r["depth"])
+
+
+# decryption checks on a chain deep enough for the decomposed product / covariance
+DEEP = I.Chain("n11_deep", 11, (60,) + (40,) * 6, (60, 60))
+
+
+@pytest.fixture(scope="module")
+def deep(oracle_mod):
+    o = oracle_mod.Oracle(DEEP.log_n, DEEP.q_bits, DEEP.p_bits, seed=17)
+    steps = set(range(-32, 33)) | {16 * j for j in range(-16, 17)} | {15 * j for j in range(-16, 17)}
+    steps |= {8 * j for j in range(-8, 9)} | {7 * j for j in range(-8, 9)}
+    o.keygen(rot_steps=sorted(s for s in steps if s), relin=True)
+    return o
+
+
+@pytest.mark.parametrize("npz,npt", [(8, 8), (4, 4), (4, 15), (15, 4)])
+def test_dcd_matmul_decrypts_to_fp64(deep, npz, npt):
+    n = 16
+    A, B = I.uniform_matrix(7, n), I.uniform_matrix(8, n)
+    r = deep.matmul(deep.encrypt(A.ravel(), nonce=1), deep.encrypt(B.ravel(), nonce=2), n, 4, 4, npz, npt)
+    dz, dt = math.ceil(15 / npz) if npz < 15 else 1, math.ceil(15 / npt) if npt < 15 else 1
+    assert r.level == DEEP.top_level - (max(dz + 1, dt) + 1)
+    got = deep.decrypt(r)[: n * n]
+    assert np.max(np.abs(got - (A @ B).ravel())) < 2.0**-15
+
+
+def test_covariance_decrypts_to_fp64(deep):
+    n, k, rb = 8, 2, 2
+    X = I.centre(I.dataset(3, rb * n - 3, k * n - 5))   # ragged: padded rows and features
+    s = X.shape[0]
+    blocks = I.blocks(X, n)
+    cts = [deep.encrypt(blocks[r, j].ravel(), nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
+    cov = deep.covariance(cts, rb, k, n, s, 2, 2, 2)
+    P = np.zeros((rb * n, k * n))
+    P[: X.shape[0], : X.shape[1]] = X
+    want = P.T @ P / s
+    for a in range(k):
+        for b in range(k):
+            ct = cov[a * k + b]
+            assert ct.level == DEEP.top_level - 5
+            got = deep.decrypt(ct)[: n * n].reshape(n, n)
+            assert np.max(np.abs(got - want[a * n:(a + 1) * n, b * n:(b + 1) * n])) < 2.0**-15
