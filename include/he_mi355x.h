@@ -105,6 +105,12 @@ he_status he_keygen(he_ctx* ctx, const int32_t* rot_steps, size_t n_steps);
  * writes at most cap entries and the total count to *n */
 he_status he_matmul_rot_steps(const he_ctx* ctx, uint32_t d, const he_matmul_opts* opts, int32_t* steps,
                               size_t cap, size_t* n);
+/* Planner, no context or device needed: rotation steps of one transform of a
+ * d x d product (kind 0 = Z, 1 = T, 2 = transposition G) by double-hoisted
+ * BSGS with n1 baby steps, decomposed (section 4.2) when 0 < nprime < d - 1
+ * (MinRotKeys of Tables 1 and 2). */
+he_status he_lintrans_rot_steps(uint32_t kind, uint32_t d, uint32_t n1, uint32_t nprime, int32_t* steps, size_t cap,
+                                size_t* n);
 /* rotation steps of the transposition (G) with baby-step count n1 (0 = default) */
 he_status he_transpose_rot_steps(const he_ctx* ctx, uint32_t d, uint32_t n1, int32_t* steps, size_t cap, size_t* n);
 

@@ -27,6 +27,23 @@ he_status guard(F&& f) {
     return HE_EINVAL;
   }
 }
+// host-only calls: no HIP runtime query (they work without a device)
+template <class F>
+he_status guard_host(F&& f) {
+  try {
+    f();
+    return HE_OK;
+  } catch (const HeError& e) {
+    g_last_error = e.msg;
+    return e.st;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HE_EINVAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return HE_EINVAL;
+  }
+}
 void need(bool ok, const char* what) {
   if (!ok) fail(HE_EINVAL, what);
 }
@@ -40,11 +57,19 @@ void check_ct(const he_ctx* c, const he_ct* a) {
   need(a != nullptr, "null ciphertext");
   need(a->ctx == c, "ciphertext belongs to another context");
 }
-void opts_of(const he_matmul_opts* o, int d, int& n1z, int& n1t) {
-  n1z = (o && o->n1_z) ? (int)o->n1_z : default_n1(d);
-  n1t = (o && o->n1_t) ? (int)o->n1_t : default_n1(d);
-  if (o && ((o->nprime_z && o->nprime_z != (u32)d - 1) || (o->nprime_t && o->nprime_t != (u32)d - 1)))
-    fail(HE_EINVAL, "diagonal convergence decomposition is not available in this build");
+struct MmOpts {
+  int n1z, n1t, npz, npt;
+};
+MmOpts opts_of(const he_matmul_opts* o, int d) {
+  MmOpts m;
+  m.n1z = (o && o->n1_z) ? (int)o->n1_z : default_n1(d);
+  m.n1t = (o && o->n1_t) ? (int)o->n1_t : default_n1(d);
+  m.npz = (o && o->nprime_z) ? (int)o->nprime_z : d - 1;
+  m.npt = (o && o->nprime_t) ? (int)o->nprime_t : d - 1;
+  if (m.npz > d - 1) m.npz = d - 1;
+  if (m.npt > d - 1) m.npt = d - 1;
+  if (m.n1z < 1 || m.n1t < 1 || d % m.n1z || d % m.n1t) fail(HE_EINVAL, "baby-step counts must divide d");
+  return m;
 }
 }  // namespace
 
@@ -100,11 +125,25 @@ he_status he_matmul_rot_steps(const he_ctx* ctx, uint32_t d, const he_matmul_opt
                               size_t* n) {
   return guard([&] {
     need(ctx != nullptr && d >= 2, "bad arguments");
-    int n1z, n1t;
-    opts_of(opts, (int)d, n1z, n1t);
-    std::vector<long> s = matmul_steps((int)d, n1z, n1t);
+    MmOpts m = opts_of(opts, (int)d);
+    std::vector<long> s = matmul_steps((int)d, m.n1z, m.n1t, m.npz, m.npt);
     if (n) *n = s.size();
     for (size_t i = 0; i < s.size() && i < cap; i++) steps[i] = (int32_t)s[i];
+  });
+}
+
+he_status he_lintrans_rot_steps(uint32_t kind, uint32_t d, uint32_t n1, uint32_t nprime, int32_t* steps, size_t cap,
+                                size_t* n) {
+  return guard_host([&] {
+    need(kind <= 2 && d >= 2 && n1 >= 1 && d % n1 == 0, "bad arguments");
+    std::set<long> s;
+    lintrans_steps((int)kind, (int)d, (int)n1, nprime ? (int)nprime : (int)d - 1, s);
+    if (n) *n = s.size();
+    size_t i = 0;
+    for (long v : s) {
+      if (i < cap) steps[i] = (int32_t)v;
+      i++;
+    }
   });
 }
 
@@ -253,10 +292,9 @@ he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, con
     check_ct(ctx, b);
     need(out != nullptr && d >= 2, "bad arguments");
     HeCtxImpl& c = ctx->impl;
-    int n1z, n1t;
-    opts_of(opts, (int)d, n1z, n1t);
+    MmOpts m = opts_of(opts, (int)d);
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
-    HeCt r = c.matmul(a->ct, b->ct, (int)d, n1z, n1t);
+    HeCt r = c.matmul(a->ct, b->ct, (int)d, m.n1z, m.n1t, m.npz, m.npt);
     hip_check(hipEventRecord(c.ev1, c.stream), "event");
     *out = wrap(ctx, std::move(r));
   });
@@ -275,9 +313,8 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
     try {
       for (size_t i = 0; i < count; i++) {
-        int n1z, n1t;
-        opts_of(opts, (int)d[i], n1z, n1t);
-        out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], n1z, n1t));
+        MmOpts m = opts_of(opts, (int)d[i]);
+        out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], m.n1z, m.n1t, m.npz, m.npt));
       }
     } catch (...) {
       for (size_t i = 0; i < count; i++) {
@@ -299,11 +336,11 @@ he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks,
       check_ct(ctx, x[i]);
       xs.push_back(&x[i]->ct);
     }
-    int n1z, n1t;
-    opts_of(opts, (int)d, n1z, n1t);
+    MmOpts m = opts_of(opts, (int)d);
     HeCtxImpl& c = ctx->impl;
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
-    std::vector<HeCt> r = c.covariance(xs, (int)row_blocks, (int)k, (int)d, n_samples, n1z, n1t, default_n1((int)d));
+    std::vector<HeCt> r =
+        c.covariance(xs, (int)row_blocks, (int)k, (int)d, n_samples, m.n1z, m.n1t, default_n1((int)d), m.npz, m.npt);
     hip_check(hipEventRecord(c.ev1, c.stream), "event");
     for (uint32_t i = 0; i < k * k; i++) cov[i] = wrap(ctx, std::move(r[i]));
   });

@@ -1,5 +1,6 @@
 // Host runtime declarations (internal).
 #pragma once
+#include <set>
 #include <string>
 #include <vector>
 
@@ -21,13 +22,24 @@ enum { TAG_SK = 1, TAG_PK_A = 2, TAG_PK_E = 3, TAG_SWK_A = 4, TAG_SWK_E = 5, TAG
 
 enum { LT_SIGMA = 0, LT_TAU = 1, LT_TRANSPOSE = 2 };
 
+// BSGS geometry: indices a (n1 i + j), j in [0, n1), i in [i_lo, i_hi)
 struct LtGeom {
   int a, n1, i_lo, i_hi;
 };
 LtGeom lt_geom(int kind, int n, int n1);
 std::vector<int> make_perm(int kind, int n);
 int default_n1(int n);
-std::vector<long> matmul_steps(int n, int n1z, int n1t);
+
+// diagonal convergence decomposition
+enum { DCD_Z1 = 0, DCD_Z2 = 1, DCD_T = 2 };
+struct DcdFactor {
+  std::vector<int> perm;  // output t takes input perm[t]; -1 = zero row
+  LtGeom G;
+};
+std::vector<DcdFactor> dcd_chain(int n, const std::vector<int>& perm, int which, int nprime, int n1);
+void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& out);
+void lintrans_steps(int kind, int n, int n1, int nprime, std::set<long>& s);
+std::vector<long> matmul_steps(int n, int n1z, int n1t, int npz, int npt);
 std::vector<long> transpose_steps(int n, int n1);
 
 struct HeCtxImpl {
@@ -99,12 +111,18 @@ struct HeCtxImpl {
   std::vector<const u64*> plaintexts(const std::vector<std::string>& keys, const std::vector<std::vector<double>>& vecs,
                                      int n2, int level, bool qp, double scale);
   HeCt lintrans(const HeCt& x, int kind, int n, int n1, double weight);
-  HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t);
-  std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, double weight);
-  std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t);
+  HeCt lintrans_perm(const HeCt& x, const std::vector<int>& perm, const LtGeom& G, double weight,
+                     const std::string& tag);
+  HeCt apply_chain(const HeCt& x, const std::vector<DcdFactor>& fs, const std::string& tag);
+  HeCt sigma_dcd(const HeCt& x, int n, int n1, int nprime);
+  HeCt tau_dcd(const HeCt& x, int n, int n1, int nprime);
+  HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t, int npz, int npt);
+  std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz);
+  std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t, int npt);
+  void align_sides(std::vector<HeCt>& Ak, std::vector<HeCt>& Bk);
   void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,
-                               int n1t, int n1g);
+                               int n1t, int n1g, int npz, int npt);
 };
 
 struct he_ctx {

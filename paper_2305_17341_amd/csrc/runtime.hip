@@ -748,7 +748,7 @@ static bool diag_vec(const std::vector<int>& perm, long l, long shift, double w,
   long lm = pmod_l(l, n2);
   for (long t = 0; t < n2; t++) {
     long s = pmod_l(t - shift, n2);
-    if (pmod_l((long)perm[s] - s, n2) == lm) {
+    if (perm[s] >= 0 && pmod_l((long)perm[s] - s, n2) == lm) {
       out[t] = w;
       nz = true;
     }
@@ -770,11 +770,33 @@ LtGeom lt_geom(int kind, int n, int n1) {
 
 // double-hoisted BSGS: U x = sum_i rot( sum_j rot(u_{a(n1 i+j)}, -a n1 i) (.) rot(x, a j), a n1 i )
 HeCt HeCtxImpl::lintrans(const HeCt& x, int kind, int n, int n1, double weight) {
+  if ((u64)n * n > N / 2 || n1 < 1) fail(HE_EINVAL, "matrix does not fit the slots");
+  char tag[64];
+  snprintf(tag, sizeof tag, "lt%d|n%d", kind, n);
+  return lintrans_perm(x, make_perm(kind, n), lt_geom(kind, n, n1), weight, tag);
+}
+
+// rotation steps a double-hoisted BSGS over `perm` with geometry G performs
+void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& out) {
+  std::vector<double> v;
+  for (int i = G.i_lo; i < G.i_hi; i++) {
+    bool any = false;
+    for (int j = 0; j < G.n1; j++) {
+      long l = (long)G.a * ((long)G.n1 * i + j);
+      if (!diag_vec(perm, l, 0, 1.0, v)) continue;
+      any = true;
+      if (j) out.insert((long)G.a * j);
+    }
+    if (any && i) out.insert((long)G.a * G.n1 * i);
+  }
+}
+
+HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const LtGeom& G, double weight,
+                              const std::string& tag) {
   if (x.qp) fail(HE_EINVAL, "linear transform of an R_QP element");
   if (x.level < 1) fail(HE_ELEVEL, "linear transform needs one level");
-  if ((u64)n * n > N / 2 || n1 < 1) fail(HE_EINVAL, "matrix does not fit the slots");
-  LtGeom G = lt_geom(kind, n, n1);
-  std::vector<int> perm = make_perm(kind, n);
+  const int n1 = G.n1;
+  const int n2sq = (int)perm.size();
   const int level = x.level;
   const int nqp = nqp_of(level);
   // diagonals actually present
@@ -786,13 +808,14 @@ HeCt HeCtxImpl::lintrans(const HeCt& x, int kind, int n, int n1, double weight) 
     for (int j = 0; j < n1; j++) {
       long l = (long)G.a * ((long)n1 * i + j);
       if (!diag_vec(perm, l, (long)G.a * n1 * i, weight, v)) continue;
-      char key[96];
-      snprintf(key, sizeof key, "lt%d|n%d|n1_%d|i%d|j%d|w%.17g", kind, n, n1, i, j, weight);
+      char key[160];
+      snprintf(key, sizeof key, "%s|a%ld|n1_%d|i%d|j%d|w%.17g", tag.c_str(), (long)G.a, n1, i, j, weight);
       keys_.push_back(key);
       vecs.push_back(v);
       ij.push_back({i, j});
     }
-  std::vector<const u64*> pts = plaintexts(keys_, vecs, n * n, level, true, delta);
+  if (ij.empty()) fail(HE_EINVAL, "transform has no nonzero diagonal");
+  std::vector<const u64*> pts = plaintexts(keys_, vecs, n2sq, level, true, delta);
   std::vector<bool> used(n1, false);
   for (auto& p : ij) used[p.second] = true;
   // Decompose once, baby-step hoisted rotations kept in R_{Q_l P}
@@ -848,27 +871,115 @@ int default_n1(int n) {
   return 1 << ((lg + 1) / 2);
 }
 
-std::vector<long> matmul_steps(int n, int n1z, int n1t) {
+// ---------------------------------------------------------------------------
+// Diagonal convergence decomposition (section 4.2: Definition 4, Theorem 2,
+// Algorithms DCDforZ / DCDforT).  Each 1-entry of the permutation with
+// remaining diagonal k is moved by the right factors one step r(k) at a time
+// (same column, Definition 4); the left factor takes what remains.
+//   Z (split into k >= 0 and k < 0): r = sign(k) n' while |k| >= n'
+//   T (k = i n):                      r = n' n     while i > n'
+// ---------------------------------------------------------------------------
+static long floor_div_l(long a, long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+std::vector<DcdFactor> dcd_chain(int n, const std::vector<int>& perm, int which, int nprime, int n1) {
+  const int n2 = n * n;
+  const int iters = ceil_div_i(n - 1, nprime) - 1;
+  std::vector<long> pos(n2, -1), rem(n2, 0);
+  std::vector<char> sel(n2, 0);
+  for (int t = 0; t < n2; t++) {
+    long k = which == DCD_T ? pmod_l((long)perm[t] - t, n2) : (long)perm[t] - t;
+    if ((which == DCD_Z1 && k < 0) || (which == DCD_Z2 && k >= 0)) continue;
+    sel[t] = 1;
+    pos[t] = perm[t];
+    rem[t] = k;
+  }
+  const long step = which == DCD_Z1 ? nprime : which == DCD_Z2 ? -(long)nprime : (long)nprime * n;
+  std::vector<DcdFactor> out;
+  for (int it = 0; it < iters; it++) {
+    DcdFactor f;
+    f.perm.assign(n2, -1);
+    for (int t = 0; t < n2; t++) {
+      if (!sel[t]) continue;
+      long r = which == DCD_T ? (rem[t] / n > nprime ? step : 0) : (std::labs(rem[t]) >= nprime ? step : 0);
+      long np = pmod_l(pos[t] - r, n2);
+      if (f.perm[np] != -1) fail(HE_EINVAL, "decomposition factor is not a partial permutation");
+      f.perm[np] = (int)pos[t];
+      pos[t] = np;
+      rem[t] -= r;
+    }
+    f.G = LtGeom{(int)step, 2, 0, 1};
+    out.push_back(std::move(f));
+  }
+  DcdFactor lf;
+  lf.perm.assign(n2, -1);
+  const long a = which == DCD_T ? n : 1;
+  long kmin = 0, kmax = 0;
+  bool first = true;
+  for (int t = 0; t < n2; t++) {
+    if (!sel[t]) continue;
+    lf.perm[t] = (int)pos[t];
+    long kk = rem[t] / a;
+    if (first || kk < kmin) kmin = kk;
+    if (first || kk > kmax) kmax = kk;
+    first = false;
+  }
+  lf.G = LtGeom{(int)a, n1, (int)floor_div_l(kmin, n1), (int)floor_div_l(kmax, n1) + 1};
+  out.push_back(std::move(lf));
+  return out;
+}
+
+void lintrans_steps(int kind, int n, int n1, int nprime, std::set<long>& s) {
+  if (kind == LT_TRANSPOSE || nprime >= n - 1) {
+    bsgs_steps(make_perm(kind, n), lt_geom(kind, n, n1), s);
+    return;
+  }
+  std::vector<int> perm = make_perm(kind, n);
+  std::vector<int> chains = kind == LT_SIGMA ? std::vector<int>{DCD_Z1, DCD_Z2} : std::vector<int>{DCD_T};
+  for (int ch : chains)
+    for (auto& f : dcd_chain(n, perm, ch, nprime, n1)) bsgs_steps(f.perm, f.G, s);
+}
+
+std::vector<long> matmul_steps(int n, int n1z, int n1t, int npz, int npt) {
   std::set<long> s;
-  int n2z = ceil_div_i(n, n1z), n2t = ceil_div_i(n, n1t);
+  lintrans_steps(LT_SIGMA, n, n1z, npz, s);
+  lintrans_steps(LT_TAU, n, n1t, npt, s);
+  // column shifts (r < n1z, chain n1z, second chain from -n), row shifts (n r, chain n n1t)
   for (int j = 1; j < n1z; j++) s.insert(j);
-  for (int i = -n2z; i < n2z; i++)
-    if (i) s.insert((long)n1z * i);
-  for (int j = 1; j < n1t; j++) s.insert((long)n * j);
-  for (int i = 1; i < n2t; i++) s.insert((long)n * n1t * i);
   s.insert(n1z);
   s.insert(-(long)n);
+  for (int j = 1; j < n1t; j++) s.insert((long)n * j);
   s.insert((long)n * n1t);
   return std::vector<long>(s.begin(), s.end());
 }
 
 std::vector<long> transpose_steps(int n, int n1) {
   std::set<long> s;
-  LtGeom G = lt_geom(LT_TRANSPOSE, n, n1);
-  for (int j = 1; j < n1; j++) s.insert((long)G.a * j);
-  for (int i = G.i_lo; i < G.i_hi; i++)
-    if (i) s.insert((long)G.a * n1 * i);
+  lintrans_steps(LT_TRANSPOSE, n, n1, n - 1, s);
   return std::vector<long>(s.begin(), s.end());
+}
+
+HeCt HeCtxImpl::apply_chain(const HeCt& x, const std::vector<DcdFactor>& fs, const std::string& tag) {
+  HeCt cur = ct_copy(x);
+  for (size_t j = 0; j < fs.size(); j++) cur = lintrans_perm(cur, fs[j].perm, fs[j].G, 1.0, tag + "|f" + std::to_string(j));
+  return cur;
+}
+
+// Z a: one double-hoisted BSGS, or the Z1 and Z2 chains of the decomposition
+HeCt HeCtxImpl::sigma_dcd(const HeCt& x, int n, int n1, int nprime) {
+  if (nprime >= n - 1) return lintrans(x, LT_SIGMA, n, n1, 1.0);
+  std::vector<int> perm = make_perm(LT_SIGMA, n);
+  char tag[64];
+  snprintf(tag, sizeof tag, "dcdZ|n%d|np%d", n, nprime);
+  HeCt a1 = apply_chain(x, dcd_chain(n, perm, DCD_Z1, nprime, n1), std::string(tag) + "|1");
+  HeCt a2 = apply_chain(x, dcd_chain(n, perm, DCD_Z2, nprime, n1), std::string(tag) + "|2");
+  return add(a1, a2, false);
+}
+
+HeCt HeCtxImpl::tau_dcd(const HeCt& x, int n, int n1, int nprime) {
+  if (nprime >= n - 1) return lintrans(x, LT_TAU, n, n1, 1.0);
+  char tag[64];
+  snprintf(tag, sizeof tag, "dcdT|n%d|np%d", n, nprime);
+  return apply_chain(x, dcd_chain(n, make_perm(LT_TAU, n), DCD_T, nprime, n1), tag);
 }
 
 static void col_mask(int n, int k, bool second, std::vector<double>& out) {
@@ -880,11 +991,12 @@ static void col_mask(int n, int k, bool second, std::vector<double>& out) {
     }
 }
 
-// A side: A_k = Rescale(ModDown(m_k (.) HR(B_b, r) + m'_k (.) HR(B'_b, r))), k = b n1z + r,
-// with bases B_b = Rot(B_{b-1}, n1z), B'_0 = Rot(sigma A, -n), B'_b = Rot(B'_{b-1}, n1z)
-std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, double weight) {
-  HeCt A0 = lintrans(ca, LT_SIGMA, n, n1z, weight);
+// A side: A_k = C^k Z a.  A_k = Rescale(ModDown(m_k (.) HR(B_b, r) + m'_k (.) HR(B'_b, r))),
+// k = b n1z + r, with bases B_b = Rot(B_{b-1}, n1z), B'_0 = Rot(Z a, -n), B'_b = Rot(B'_{b-1}, n1z)
+std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int npz) {
+  HeCt A0 = sigma_dcd(ca, n, n1z, npz);
   const int lvl = A0.level;
+  if (lvl < 1) fail(HE_ELEVEL, "no level left for the column shifts");
   const int nqp = nqp_of(lvl);
   LimbMap qpm = qpmap(lvl);
   std::vector<std::string> keys_;
@@ -931,10 +1043,9 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, doubl
   return Ak;
 }
 
-// B side: C_0 = tau B, C_b = Rot(C_{b-1}, n n1t), B_k = ModDown(HR(C_b, n r)),
-// dropped one level to meet the A side
-std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t) {
-  HeCt Cb = lintrans(cb, LT_TAU, n, n1t, 1.0);
+// B side: B_k = R^k T b.  C_0 = T b, C_b = Rot(C_{b-1}, n n1t), B_k = ModDown(HR(C_b, n r))
+std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int npt) {
+  HeCt Cb = tau_dcd(cb, n, n1t, npt);
   const int lvl = Cb.level;
   std::vector<HeCt> Bk(n);
   for (int b = 0; b * n1t < n; b++) {
@@ -943,15 +1054,23 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t) {
     for (int r = 0; r < n1t && b * n1t + r < n; r++) {
       int k = b * n1t + r;
       if (r == 0) {
-        Bk[k] = drop(Cb, lvl - 1);
+        Bk[k] = ct_copy(Cb);
       } else {
         HeCt h = hoisted(Cb, d1.p, galois((long)n * r));
-        HeCt full = moddown(h);
-        Bk[k] = drop(full, lvl - 1);
+        Bk[k] = moddown(h);
       }
     }
   }
   return Bk;
+}
+
+// drop both sides to their common (lowest) level
+void HeCtxImpl::align_sides(std::vector<HeCt>& Ak, std::vector<HeCt>& Bk) {
+  int lv = std::min(Ak[0].level, Bk[0].level);
+  for (auto& a : Ak)
+    if (a.level > lv) a = drop(a, lv);
+  for (auto& b : Bk)
+    if (b.level > lv) b = drop(b, lv);
 }
 
 // acc (+)= sum_k Relin(Tensor(A_k, B_k))
@@ -967,12 +1086,15 @@ void HeCtxImpl::matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<He
   }
 }
 
-HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t) {
+HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, int npz, int npt) {
   if (ca.qp || cb.qp || ca.level != cb.level) fail(HE_ELEVEL, "operands must be ciphertexts at one level");
-  if (ca.level < 3) fail(HE_ELEVEL, "the product needs three levels");
-  if ((u64)n * n > N / 2 || n % n1z || n % n1t) fail(HE_EINVAL, "bad matrix size / baby-step count");
-  std::vector<HeCt> Ak = matmul_side_a(ca, n, n1z, 1.0);
-  std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t);
+  if ((u64)n * n > N / 2 || n % n1z || n % n1t || npz < 1 || npt < 1)
+    fail(HE_EINVAL, "bad matrix size / baby-step count / decomposition");
+  int dz = npz >= n - 1 ? 1 : ceil_div_i(n - 1, npz), dt = npt >= n - 1 ? 1 : ceil_div_i(n - 1, npt);
+  if (ca.level < std::max(dz + 1, dt) + 1) fail(HE_ELEVEL, "not enough levels for the product");
+  std::vector<HeCt> Ak = matmul_side_a(ca, n, n1z, npz);
+  std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t, npt);
+  align_sides(Ak, Bk);
   HeCt acc;
   bool set = false;
   matmul_accumulate(acc, set, Ak, Bk);
@@ -984,24 +1106,27 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t) 
 // for b <= a, and G(block (b, a)) for a < b; the A and B sides of each
 // row block are formed once and reused for every pair (one-to-many caching).
 std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples,
-                                        int n1z, int n1t, int n1g) {
+                                        int n1z, int n1t, int n1g, int npz, int npt) {
   if ((int)x.size() != rb * k) fail(HE_EINVAL, "block count mismatch");
   int level = x[0]->level;
   for (auto* c : x)
     if (c->level != level || c->qp) fail(HE_ELEVEL, "dataset blocks must share one level");
-  if (level < 5) fail(HE_ELEVEL, "the covariance needs five levels");
+  int dz = npz >= n - 1 ? 1 : ceil_div_i(n - 1, npz), dt = npt >= n - 1 ? 1 : ceil_div_i(n - 1, npt);
+  if (level < std::max(dz + 1, dt) + 3) fail(HE_ELEVEL, "not enough levels for the covariance");
   std::vector<HeCt> acc(k * k);
   std::vector<bool> set(k * k, false);
   for (int r = 0; r < rb; r++) {
     std::vector<std::vector<HeCt>> A(k), B(k);
     for (int a = 0; a < k; a++) {
       HeCt xt = lintrans(*x[r * k + a], LT_TRANSPOSE, n, n1g, 1.0 / (double)n_samples);
-      A[a] = matmul_side_a(xt, n, n1z, 1.0);
+      A[a] = matmul_side_a(xt, n, n1z, npz);
     }
     for (int b = 0; b < k; b++) {
       HeCt xb = drop(*x[r * k + b], level - 1);
-      B[b] = matmul_side_b(xb, n, n1t);
+      B[b] = matmul_side_b(xb, n, n1t, npt);
     }
+    for (int a = 0; a < k; a++) align_sides(A[a], B[0]);
+    for (int b = 0; b < k; b++) align_sides(A[0], B[b]);
     for (int a = 0; a < k; a++)
       for (int b = 0; b <= a; b++) {
         bool s = set[a * k + b];
@@ -1012,10 +1137,12 @@ std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int r
   std::vector<HeCt> out(k * k);
   for (int a = 0; a < k; a++)
     for (int b = 0; b <= a; b++) out[a * k + b] = rescale(acc[a * k + b]);
-  int final_level = out[0].level - 1;
   for (int a = 0; a < k; a++)
     for (int b = a + 1; b < k; b++) out[a * k + b] = lintrans(out[b * k + a], LT_TRANSPOSE, n, n1g, 1.0);
-  for (int a = 0; a < k; a++)
-    for (int b = 0; b <= a; b++) out[a * k + b] = drop(out[a * k + b], final_level);
+  if (k > 1) {
+    int fl = out[1].level;
+    for (int a = 0; a < k; a++)
+      for (int b = 0; b <= a; b++) out[a * k + b] = drop(out[a * k + b], fl);
+  }
   return out;
 }

@@ -25,7 +25,7 @@ EXPORTS = [
     "he_ct_export", "he_ct_import", "he_ct_free", "he_add", "he_sub", "he_mult", "he_rescale", "he_rotate",
     "he_drop_level", "he_pmult_slots", "he_lintrans", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
     "he_mem_info", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
-    "he_profile_enable", "he_profile_read", "he_op_counts", "he_last_error",
+    "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_last_error",
 ]
 
 u64p = C.POINTER(C.c_uint64)
@@ -101,6 +101,8 @@ def load():
         "he_profile_enable": [vp, C.c_int],
         "he_profile_read": [vp, C.c_char_p, dblp, u64p, dblp],
         "he_op_counts": [vp, u64p, u64p, u64p],
+        "he_lintrans_rot_steps": [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32), C.c_size_t,
+                                  C.POINTER(C.c_size_t)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -333,6 +335,15 @@ class Context:
         out = np.zeros(2 * (lv + 1 + self.alpha) * self.N, dtype=np.uint64)
         _check(load().he_hoisted_rotate_export(self.ptr, a.ptr, int(step), out.ctypes.data_as(u64p), out.size))
         return out.reshape(2, lv + 1 + self.alpha, self.N)
+
+
+def lintrans_rot_steps(kind, d, n1, nprime=0):
+    """Planner (host only): rotation steps of one transform ("Z", "T", "G")."""
+    k = {"Z": 0, "T": 1, "G": 2}[kind]
+    n = C.c_size_t()
+    buf = (C.c_int32 * 8192)()
+    _check(load().he_lintrans_rot_steps(k, d, n1, nprime, buf, 8192, C.byref(n)))
+    return [int(buf[i]) for i in range(n.value)]
 
 
 def chain_context(chain, seed=1) -> Context:

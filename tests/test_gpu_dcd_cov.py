@@ -1,0 +1,85 @@
+"""GPU parity of the decomposed product (section 4.2) and of the covariance
+circuit (section 5.2): bit-exact against the oracle on a chain deep enough
+for them, and the full-size covariance against FP64."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2305_17341_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DEEP = I.Chain("n11_deep", 11, (60,) + (40,) * 6, (60, 60))
+BOUND = 2.0**-15
+OPTS = [(8, 8), (4, 4), (4, 15), (15, 4)]
+
+
+@pytest.fixture(scope="module")
+def pair(oracle_mod):
+    from paper_2305_17341_amd import he
+    n = 16
+    ctx = he.chain_context(DEEP, seed=17)
+    steps = set(ctx.transpose_rot_steps(8)) | set(ctx.matmul_rot_steps(8, {"n1_z": 2, "n1_t": 2}))
+    for npz, npt in OPTS:
+        steps |= set(ctx.matmul_rot_steps(n, {"n1_z": 4, "n1_t": 4, "nprime_z": npz, "nprime_t": npt}))
+    steps = sorted(steps)
+    ctx.keygen(steps)
+    o = oracle_mod.Oracle(DEEP.log_n, DEEP.q_bits, DEEP.p_bits, seed=17)
+    o.keygen(rot_steps=steps)
+    return ctx, o
+
+
+@pytest.mark.parametrize("npz,npt", OPTS)
+def test_dcd_matmul_bit_exact(pair, npz, npt):
+    ctx, o = pair
+    n = 16
+    A, B = I.uniform_matrix(7, n), I.uniform_matrix(8, n)
+    opts = {"n1_z": 4, "n1_t": 4, "nprime_z": npz, "nprime_t": npt}
+    r = ctx.matmul(ctx.encrypt_matrix(A, nonce=1), ctx.encrypt_matrix(B, nonce=2), n, opts)
+    want = o.matmul(o.encrypt(A.ravel(), nonce=1), o.encrypt(B.ravel(), nonce=2), n, 4, 4, npz, npt)
+    assert r.level == want.level
+    assert np.array_equal(r.export(), want.data())
+    assert np.max(np.abs(ctx.decrypt(r, n * n) - (A @ B).ravel())) < BOUND
+
+
+def test_covariance_bit_exact(pair):
+    ctx, o = pair
+    n, k, rb = 8, 2, 2
+    X = I.centre(I.dataset(3, rb * n - 3, k * n - 5))
+    s = X.shape[0]
+    blocks = I.blocks(X, n)
+    g = [ctx.encrypt_matrix(blocks[r, j], nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
+    oc = [o.encrypt(blocks[r, j].ravel(), nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
+    cov = ctx.covariance(g, rb, k, n, s, {"n1_z": 2, "n1_t": 2})
+    want = o.covariance(oc, rb, k, n, s, 2, 2, 2)
+    P = np.zeros((rb * n, k * n))
+    P[: X.shape[0], : X.shape[1]] = X
+    ref = P.T @ P / s
+    for i in range(k * k):
+        assert np.array_equal(cov[i].export(), want[i].data()), i
+        a, b = divmod(i, k)
+        got = ctx.decrypt(cov[i], n * n).reshape(n, n)
+        assert np.max(np.abs(got - ref[a * n:(a + 1) * n, b * n:(b + 1) * n])) < BOUND
+
+
+def test_covariance_full_size_dcd(oracle_mod):
+    """256 x 256 uniform[0,1] dataset, centred, at N=2^16 with 128 x 128
+    blocks, n' = 32 and n1 = 16 for Z and T."""
+    from paper_2305_17341_amd import he
+    c = I.LARGE
+    n, k, rb = 128, 2, 2
+    ctx = he.chain_context(c, seed=41)
+    opts = {"n1_z": 16, "n1_t": 16, "nprime_z": 32, "nprime_t": 32}
+    ctx.keygen(sorted(set(ctx.matmul_rot_steps(n, opts)) | set(ctx.transpose_rot_steps(n))))
+    X = I.centre(I.dataset(5, rb * n, k * n))
+    blocks = I.blocks(X, n)
+    g = [ctx.encrypt_matrix(blocks[r, j], nonce=10 + r * k + j) for r in range(rb) for j in range(k)]
+    cov = ctx.covariance(g, rb, k, n, X.shape[0], opts)
+    ref = X.T @ X / X.shape[0]
+    depth = 1 + (math.ceil(127 / 32) + 1) + 1 + 1
+    for i in range(k * k):
+        a, b = divmod(i, k)
+        assert cov[i].level == c.top_level - depth
+        got = ctx.decrypt(cov[i], n * n).reshape(n, n)
+        assert np.max(np.abs(got - ref[a * n:(a + 1) * n, b * n:(b + 1) * n])) < BOUND
