@@ -260,11 +260,241 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows(u64* data, LimbMap map, int lo
   for (int e = threadIdx.x; e < tot; e += TPB) a[e] = sh[e];
 }
 
+// ---------------------------------------------------------------------------
+// Register-blocked NTT (log N = 12..16).  Each pass streams a 4096-word tile
+// through LDS once; inside the pass every thread holds 2^G residues in
+// registers and runs G consecutive butterfly stages on them (G <= 4), twice,
+// with one LDS exchange in between.
+//
+// Forward stage s (Cooley-Tukey) pairs bit logN-1-s of the index with twiddle
+// psi^brv at 2^s + (x >> (logN - s)).  A thread's values v[r] sit at
+// x = base + (r << (logN - s0 - G)); with hi = base >> (logN - s0) the
+// twiddle of stage s0 + j is at 2^(s0+j) + (hi << j) + (r >> (G - j)).
+// Inverse stage on bit b (Gentleman-Sande) uses psi^-brv at
+// 2^(logN-1-b) + (x >> (b+1)); values at x = base + (r << b0), hi = base >> (b0 + G).
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ void fwd_group(u64 (&v)[16], int s0, u32 hi, const u64* __restrict__ w,
+                                          const u64* __restrict__ wsh, u64 q) {
+#pragma unroll
+  for (int j = 0; j < G; j++) {
+    const int half = 1 << (G - 1 - j);
+#pragma unroll
+    for (int r = 0; r < (1 << G); r++) {
+      if (r & half) continue;
+      const u32 widx = (1u << (s0 + j)) + (hi << j) + (u32)(r >> (G - j));
+      const u64 W = w[widx], Wp = wsh[widx];
+      const u64 U = v[r];
+      const u64 V = shoup_mul(v[r + half], W, Wp, q);
+      v[r] = add_mod(U, V, q);
+      v[r + half] = sub_mod(U, V, q);
+    }
+  }
+}
+
+template <int G>
+__device__ __forceinline__ void inv_group(u64 (&v)[16], int b0, int logN, u32 hi, const u64* __restrict__ w,
+                                          const u64* __restrict__ wsh, u64 q) {
+#pragma unroll
+  for (int j = 0; j < G; j++) {
+    const int half = 1 << j;
+#pragma unroll
+    for (int r = 0; r < (1 << G); r++) {
+      if (r & half) continue;
+      const u32 widx = (1u << (logN - 1 - b0 - j)) + (hi << (G - j - 1)) + (u32)(r >> (j + 1));
+      const u64 W = w[widx], Wp = wsh[widx];
+      const u64 U = v[r], V = v[r + half];
+      v[r] = add_mod(U, V, q);
+      v[r + half] = shoup_mul(sub_mod(U, V, q), W, Wp, q);
+    }
+  }
+}
+
+#define TILE 4096
+// LDS index of (row r, column c) in the column pass, C columns per tile
+__device__ __forceinline__ int lds_rc(int r, int c, int C) { return r * (C + 1) + c; }
+// LDS index of (block b, element e) in the block pass, T1 words per block
+__device__ __forceinline__ int lds_be(int b, int e, int T1) { return b * (T1 + (T1 >> 4) + 1) + e + (e >> 4); }
+#define LDS_WORDS (TILE + TILE / 16 + 64)
+
+// Column pass: rows R = 2^(GA+GB), C = TILE / R columns per work-group.
+template <int LOGN, int GA, int GB, bool INV>
+__global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const u64* __restrict__ tw,
+                                                   const u64* __restrict__ twsh, const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << LOGN;
+  u64* a = data + (size_t)limb * N;
+  const int c0 = blockIdx.x * C;
+  const ModConst mk = mc[m];
+  const u64 q = mk.q;
+  const u64* w = tw + (size_t)m * N;
+  const u64* wsh = twsh + (size_t)m * N;
+  const int tid = threadIdx.x;
+  u64 v[16];
+  if (!INV) {
+    // group A: r bits [GB, S1) -> stages 0..GA-1
+    constexpr int ITA = 16 >> GA;
+#pragma unroll
+    for (int k = 0; k < ITA; k++) {
+      const int it = tid + TPB * k, c = it % C, rl = it / C;
+#pragma unroll
+      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = a[(size_t)(rl + (mm << GB)) * T1 + c0 + c];
+      fwd_group<GA>(v, 0, 0u, w, wsh, q);
+#pragma unroll
+      for (int mm = 0; mm < (1 << GA); mm++) sh[lds_rc(rl + (mm << GB), c, C)] = v[mm];
+    }
+    __syncthreads();
+    // group B: r bits [0, GB) -> stages GA..S1-1
+    constexpr int ITB = 16 >> GB;
+#pragma unroll
+    for (int k = 0; k < ITB; k++) {
+      const int it = tid + TPB * k, c = it % C, rh = it / C;
+#pragma unroll
+      for (int mm = 0; mm < (1 << GB); mm++) v[mm] = sh[lds_rc((rh << GB) + mm, c, C)];
+      fwd_group<GB>(v, GA, (u32)rh, w, wsh, q);
+#pragma unroll
+      for (int mm = 0; mm < (1 << GB); mm++) a[(size_t)((rh << GB) + mm) * T1 + c0 + c] = v[mm];
+    }
+  } else {
+    constexpr int S2 = LOGN - S1;
+    // inverse bits [S2, S2+GB) = r bits [0, GB)
+    constexpr int ITB = 16 >> GB;
+#pragma unroll
+    for (int k = 0; k < ITB; k++) {
+      const int it = tid + TPB * k, c = it % C, rh = it / C;
+#pragma unroll
+      for (int mm = 0; mm < (1 << GB); mm++) v[mm] = a[(size_t)((rh << GB) + mm) * T1 + c0 + c];
+      inv_group<GB>(v, S2, LOGN, (u32)rh, w, wsh, q);
+#pragma unroll
+      for (int mm = 0; mm < (1 << GB); mm++) sh[lds_rc((rh << GB) + mm, c, C)] = v[mm];
+    }
+    __syncthreads();
+    // inverse bits [S2+GB, LOGN) = r bits [GB, S1), then N^{-1}
+    constexpr int ITA = 16 >> GA;
+#pragma unroll
+    for (int k = 0; k < ITA; k++) {
+      const int it = tid + TPB * k, c = it % C, rl = it / C;
+#pragma unroll
+      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = sh[lds_rc(rl + (mm << GB), c, C)];
+      inv_group<GA>(v, S2 + GB, LOGN, 0u, w, wsh, q);
+#pragma unroll
+      for (int mm = 0; mm < (1 << GA); mm++)
+        a[(size_t)(rl + (mm << GB)) * T1 + c0 + c] = shoup_mul(v[mm], mk.ninv, mk.ninv_sh, q);
+    }
+  }
+}
+
+// Block pass: blocks of T1 = 2^(GC+GD) words, K = TILE / T1 blocks per work-group.
+template <int LOGN, int GC, int GD, bool INV>
+__global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const u64* __restrict__ tw,
+                                                   const u64* __restrict__ twsh, const ModConst* __restrict__ mc) {
+  constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1, S1 = LOGN - S2;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << LOGN;
+  const int blk0 = blockIdx.x * K;
+  u64* a = data + (size_t)limb * N + (size_t)blk0 * T1;
+  const u64 q = mc[m].q;
+  const u64* w = tw + (size_t)m * N;
+  const u64* wsh = twsh + (size_t)m * N;
+  const int tid = threadIdx.x;
+  constexpr int LOWC = 1 << (S2 - GC);  // e bits below group C
+  u64 v[16];
+  if (!INV) {
+    // group C: e bits [GD, S2) -> stages S1..S1+GC-1
+    constexpr int ITC = 16 >> GC;
+#pragma unroll
+    for (int k = 0; k < ITC; k++) {
+      const int it = tid + TPB * k, el = it % LOWC, b = it / LOWC;
+#pragma unroll
+      for (int mm = 0; mm < (1 << GC); mm++) v[mm] = a[(size_t)b * T1 + el + (mm << GD)];
+      fwd_group<GC>(v, S1, (u32)(blk0 + b), w, wsh, q);
+#pragma unroll
+      for (int mm = 0; mm < (1 << GC); mm++) sh[lds_be(b, el + (mm << GD), T1)] = v[mm];
+    }
+    __syncthreads();
+    // group D: e bits [0, GD) -> stages S1+GC..LOGN-1
+    constexpr int ITD = 16 >> GD;
+    constexpr int HIGHD = 1 << (S2 - GD);
+#pragma unroll
+    for (int k = 0; k < ITD; k++) {
+      const int it = tid + TPB * k, eh = it % HIGHD, b = it / HIGHD;
+#pragma unroll
+      for (int mm = 0; mm < (1 << GD); mm++) v[mm] = sh[lds_be(b, (eh << GD) + mm, T1)];
+      fwd_group<GD>(v, S1 + GC, (u32)(((blk0 + b) << GC) + eh), w, wsh, q);
+#pragma unroll
+      for (int mm = 0; mm < (1 << GD); mm++) sh[lds_be(b, (eh << GD) + mm, T1)] = v[mm];
+    }
+    __syncthreads();
+    for (int e = tid; e < TILE; e += TPB) a[e] = sh[lds_be(e / T1, e % T1, T1)];
+  } else {
+    // inverse bits [0, GD) of e
+    constexpr int ITD = 16 >> GD;
+    constexpr int HIGHD = 1 << (S2 - GD);
+    for (int e = tid; e < TILE; e += TPB) sh[lds_be(e / T1, e % T1, T1)] = a[e];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITD; k++) {
+      const int it = tid + TPB * k, eh = it % HIGHD, b = it / HIGHD;
+#pragma unroll
+      for (int mm = 0; mm < (1 << GD); mm++) v[mm] = sh[lds_be(b, (eh << GD) + mm, T1)];
+      inv_group<GD>(v, 0, LOGN, (u32)(((blk0 + b) << GC) + eh), w, wsh, q);
+#pragma unroll
+      for (int mm = 0; mm < (1 << GD); mm++) sh[lds_be(b, (eh << GD) + mm, T1)] = v[mm];
+    }
+    __syncthreads();
+    // inverse bits [GD, S2) of e
+    constexpr int ITC = 16 >> GC;
+#pragma unroll
+    for (int k = 0; k < ITC; k++) {
+      const int it = tid + TPB * k, el = it % LOWC, b = it / LOWC;
+#pragma unroll
+      for (int mm = 0; mm < (1 << GC); mm++) v[mm] = sh[lds_be(b, el + (mm << GD), T1)];
+      inv_group<GC>(v, GD, LOGN, (u32)(blk0 + b), w, wsh, q);
+#pragma unroll
+      for (int mm = 0; mm < (1 << GC); mm++) a[(size_t)b * T1 + el + (mm << GD)] = v[mm];
+    }
+  }
+}
+
+template <int LOGN, int GA, int GB, int GC, int GD>
+static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s) {
+  constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
+  static_assert(GA + GB + GC + GD == LOGN, "stage split");
+  dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
+  if (!inverse) {
+    hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh, T.mc);
+    hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false>), gr, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh, T.mc);
+  } else {
+    hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, true>), gr, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh, T.mc);
+    hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, true>), gc, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh, T.mc);
+  }
+}
+
+static bool ntt_register_blocked(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse,
+                                 hipStream_t s) {
+  switch (T.logN) {
+    case 16: ntt2<16, 4, 4, 4, 4>(T, data, nlimbs, map, inverse, s); return true;
+    case 15: ntt2<15, 4, 3, 4, 4>(T, data, nlimbs, map, inverse, s); return true;
+    case 14: ntt2<14, 4, 3, 4, 3>(T, data, nlimbs, map, inverse, s); return true;
+    case 13: ntt2<13, 3, 3, 4, 3>(T, data, nlimbs, map, inverse, s); return true;
+    case 12: ntt2<12, 3, 3, 3, 3>(T, data, nlimbs, map, inverse, s); return true;
+    default: return false;
+  }
+}
+
 void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s) {
   if (nlimbs <= 0) return;
   int active = 0;
   for (int k = 0; k < nlimbs; k++) active += map.idx[k % map.n] >= 0;
   ProfScope ps("ntt", s, 16.0 * active * T.N);
+  if (ntt_register_blocked(T, data, nlimbs, map, inverse, s)) return;
   NttShape sh = ntt_shape(T.logN);
   dim3 gc(sh.T1 / sh.C, nlimbs), gr(sh.R / sh.K, nlimbs);
   if (!inverse) {

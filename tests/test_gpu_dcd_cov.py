@@ -52,7 +52,7 @@ def test_covariance_bit_exact(pair):
     g = [ctx.encrypt_matrix(blocks[r, j], nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
     oc = [o.encrypt(blocks[r, j].ravel(), nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
     cov = ctx.covariance(g, rb, k, n, s, {"n1_z": 2, "n1_t": 2})
-    want = o.covariance(oc, rb, k, n, s, 2, 2, 2)
+    want = o.covariance(oc, rb, k, n, s, 2, 2, 4)   # transposition: default 4 baby steps at n = 8
     P = np.zeros((rb * n, k * n))
     P[: X.shape[0], : X.shape[1]] = X
     ref = P.T @ P / s
