@@ -4,10 +4,14 @@
 One step = one batch of `--batch` independent 128 x 128 products (Eq. 4 of
 the paper: sigma/tau double-hoisted BSGS, hoisted column/row shifts, n
 relinearised products, rescale) on ciphertexts already resident in HBM.
-Prints one JSON line: matmuls/s (the headline), key-switched rotations/s,
-per-step latency percentiles, the roofline of the dominant kernel family
-(HIP events around its launches during the timed steps) and the CPU oracle
-timed on a bounded sample on this host.
+The same steps are timed twice: plain (one product after another) and
+batched (the products stacked, every launch serving all of them); the
+headline value is the batched rate, the plain rate and the speedup sit
+beside it, together with a residue-for-residue comparison of the two.
+Prints one JSON line: matmuls/s, key-switched rotations/s, per-step latency
+percentiles, the roofline of the dominant kernel family (HIP events around
+its launches during the timed batched steps) and the CPU oracle timed on a
+bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -78,7 +82,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--rotations", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -103,32 +108,47 @@ def main():
     cB = [ctx.encrypt_matrix(b, nonce=1001 + i) for i, b in enumerate(Bs)]
     ctx.sync()
 
-    for w in range(args.warmup):
-        t0 = time.perf_counter()
-        outs = ctx.matmul_batch(cA, cB, [d] * B)
-        ctx.sync()
-        log(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f} s")
-    # accuracy of the last warm-up output against FP64
-    err = float(np.max(np.abs(ctx.decrypt(outs[0], d * d) - (As[0] @ Bs[0]).ravel())))
-    del outs
-    c0 = ctx.op_counts()
+    batched = {"flags": 1}
 
-    ctx.profile_enable(True)
-    lat = []
-    ctx.sync()
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        outs = ctx.matmul_batch(cA, cB, [d] * B)
-        lat.append(ctx.last_op_ms())
-        del outs
-    ctx.sync()
-    t_total = time.perf_counter() - t_start
+    def timed(opts, profile):
+        """warm-up then `--steps` timed steps of B products; returns (seconds, per-step ms, outputs of warm-up)"""
+        outs = None
+        for w in range(args.warmup):
+            t0 = time.perf_counter()
+            outs = ctx.matmul_batch(cA, cB, [d] * B, opts=opts)
+            ctx.sync()
+            log(f"[bench] warmup {w} ({'batched' if opts else 'plain'}): {time.perf_counter() - t0:.2f} s")
+        if profile:
+            ctx.profile_enable(True)
+        lat = []
+        ctx.sync()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            o = ctx.matmul_batch(cA, cB, [d] * B, opts=opts)
+            lat.append(ctx.last_op_ms())
+            del o
+        ctx.sync()
+        t_total = time.perf_counter() - t_start
+        log(f"[bench] {args.steps} timed steps ({'batched' if opts else 'plain'}): {t_total:.2f} s")
+        return t_total, lat, outs
+
+    plain_outs = None
+    if not args.no_plain:
+        t_plain, lat_plain, plain_outs = timed(None, False)
+    c0 = ctx.op_counts()
+    t_total, lat, outs = timed(batched, True)
     fams = ["ntt", "multsum", "modup", "moddown", "rescale", "elementwise", "tensor", "plift"]
     prof = {f: ctx.profile_read(f) for f in fams}
     ctx.profile_enable(False)
     c1 = ctx.op_counts()
-    n_mm = args.steps * B
+    n_mm = (args.steps + args.warmup) * B
     per_mm = {k: (c1[k] - c0[k]) / n_mm for k in c0}
+    # accuracy of a warm-up output against FP64, and batched == plain residue for residue
+    err = float(np.max(np.abs(ctx.decrypt(outs[0], d * d) - (As[0] @ Bs[0]).ravel())))
+    same = None
+    if plain_outs is not None:
+        same = all(np.array_equal(p.export(), q.export()) for p, q in zip(plain_outs, outs))
+    del outs, plain_outs
 
     # key-switched rotations at the top level
     ct = cA[0]
@@ -140,7 +160,7 @@ def main():
     ctx.sync()
     rot_s = args.rotations / (time.perf_counter() - t0)
 
-    value = n_mm / t_total
+    value = args.steps * B / t_total
     fam_ms = {f: prof[f][0] / args.steps for f in fams}
     dom = max(fams, key=lambda f: prof[f][0])
     ms, launches, nbytes = prof[dom]
@@ -167,7 +187,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"he_matmul d={d} at N=2^16 (q0 60b + 30x40b, P 3x60b, levels 30->27), "
                                f"uniform[-1,1] FP64 inputs", "d": d, "log_n": chain.log_n, "batch": B,
-                   "path": "plain"},
+                   "path": "batched"},
+        "plain": None if args.no_plain else {
+            "value": round(args.steps * B / t_plain, 4), "unit": "matmuls/s",
+            "latency_ms": {"p50": pct(lat_plain, 50), "p99": pct(lat_plain, 99)},
+            "speedup_batched": round(t_plain / t_total, 3), "residues_identical": same},
         "rotations_per_s": round(rot_s, 2),
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "max_abs_err": err,

@@ -87,7 +87,12 @@ typedef struct {
   uint32_t nprime_z, nprime_t;
   uint32_t flags; /* HE_MM_* below */
 } he_matmul_opts;
-#define HE_MM_BATCHED 1u /* fused multi-rotation kernels (same residues) */
+/* he_matmul_batch only: consecutive products of equal d (and equal operand
+ * level and scales) run as one stacked batch of up to 8 members, so every
+ * kernel launch of the plan serves all of them and each switching-key word is
+ * read once per batch.  Results are residue-for-residue identical to the
+ * unbatched path.  Costs 8x the temporaries of one product in HBM. */
+#define HE_MM_BATCHED 1u
 
 /* Create a context on the current HIP device.  `dev` may be NULL.  `seed`
  * keys every random draw of the context (Philox4x64-10 streams).

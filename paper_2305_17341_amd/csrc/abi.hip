@@ -312,9 +312,32 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
     }
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
     try {
-      for (size_t i = 0; i < count; i++) {
-        MmOpts m = opts_of(opts, (int)d[i]);
-        out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], m.n1z, m.n1t, m.npz, m.npt));
+      if (opts && (opts->flags & HE_MM_BATCHED)) {
+        // runs of equal d stacked into batches of up to 8: every launch of the
+        // plan then serves the whole batch (keys read once per batch)
+        size_t i = 0;
+        while (i < count) {
+          size_t j = i + 1;
+          while (j < count && j - i < 8 && d[j] == d[i] && a[j]->ct.level == a[i]->ct.level &&
+                 a[j]->ct.scale == a[i]->ct.scale && b[j]->ct.scale == b[i]->ct.scale)
+            j++;
+          std::vector<const HeCt*> xa, xb;
+          for (size_t k = i; k < j; k++) {
+            xa.push_back(&a[k]->ct);
+            xb.push_back(&b[k]->ct);
+          }
+          MmOpts m = opts_of(opts, (int)d[i]);
+          HeCt sa = c.stack(xa), sb = c.stack(xb);
+          HeCt r = c.matmul(sa, sb, (int)d[i], m.n1z, m.n1t, m.npz, m.npt);
+          std::vector<HeCt> parts = c.unstack(r);
+          for (size_t k = i; k < j; k++) out[k] = wrap(ctx, std::move(parts[k - i]));
+          i = j;
+        }
+      } else {
+        for (size_t i = 0; i < count; i++) {
+          MmOpts m = opts_of(opts, (int)d[i]);
+          out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], m.n1z, m.n1t, m.npz, m.npt));
+        }
       }
     } catch (...) {
       for (size_t i = 0; i < count; i++) {

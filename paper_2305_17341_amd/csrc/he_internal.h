@@ -112,14 +112,20 @@ struct DevBuf {
   ~DevBuf() { release(); }
 };
 
-// A ciphertext (or an element of R_{Q_l P}^2 when qp = true): u64[2][nlimbs][N]
+// B ciphertexts at one level and scale (or elements of R_{Q_l P}^2 when qp =
+// true), stacked as u64[2][B][nlimbs][N]: poly(p) holds component p of every
+// member contiguously, so a batch is just more limbs for every kernel.
 struct HeCt {
   u64 N = 0;
   int level = 0;
   bool qp = false;
   int nlimbs = 0;
+  int B = 1;
   double scale = 1.0;
   DevBuf d;
-  u64* poly(int p) const { return d.p + (size_t)p * nlimbs * N; }
-  u64* limb(int p, int k) const { return d.p + ((size_t)p * nlimbs + k) * N; }
+  u64* poly(int p) const { return d.p + (size_t)p * B * nlimbs * N; }
+  u64* limb(int p, int k) const { return d.p + ((size_t)p * B * nlimbs + k) * N; }
+  // member b, component p
+  u64* member(int p, int b) const { return d.p + ((size_t)p * B + b) * nlimbs * N; }
+  size_t polys() const { return (size_t)2 * B; }
 };

@@ -42,7 +42,8 @@ void launch_mul_acc(const DeviceTables& T, u64* acc, const u64* a, const u64* b,
 void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const u64* consts /*[map.n]*/,
                       const LimbMap& m, hipStream_t s);
 void launch_neg(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const LimbMap& m, hipStream_t s);
-void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, hipStream_t s);
+// batch pairs of ciphertexts [2][batch][nl] -> [3][batch][nl]
+void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, hipStream_t s);
 void launch_int_to_limbs(const DeviceTables& T, u64* out, const i64* in, int nlimbs, const LimbMap& m, hipStream_t s);
 
 // key switching pieces
@@ -64,17 +65,19 @@ struct FbcTable {
 // digits[j][pos] (pos over Q_l then P): own limbs copy ntt_in, others are the
 // coefficient-domain conversion of digit j (to be transformed by the caller)
 void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64* ntt_in, int level, int L,
-                  int alpha, int beta, const FbcTable* tabs /* host array [beta] */, hipStream_t s);
-void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, const FbcTable& tab, hipStream_t s);
+                  int alpha, int beta, const FbcTable* tabs /* host array [beta] */, int batch, hipStream_t s);
+// y[npoly][nq] = exact centred lift of the source limbs xp[npoly][ns] to each q_t
+void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
+                     hipStream_t s);
 void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u64* y, int nq,
                           const u64* pinv /*device [nmods] Shoup pairs*/, int npoly, int x_stride_limbs,
                           hipStream_t s);
 // hoisted rotation: out[2][nqp][N] = sum_j pi_g(d_j) * key_j (+ P pi_g(c0) on Q limbs)
 void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,
                     const u64* pmod /*device [nmods][2]*/, int level, int L, int alpha, int beta, u64 g,
-                    hipStream_t s);
+                    int batch, hipStream_t s);
 // P-lift: out[2][nqp][N] = (P c0, P c1) on Q limbs, 0 on P limbs
-void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha,
+void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha, int npoly,
                   hipStream_t s);
 // rescale pieces
 void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int npoly, hipStream_t s);

@@ -607,23 +607,26 @@ void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs,
   hipLaunchKernelGGL(k_mul_const, grid, dim3(TPB), 0, s, out, a, nlimbs, c, m, T.logN, T.mc);
 }
 
-// Tensor of two ciphertexts over Q_l: (a0 b0, a0 b1 + a1 b0, a1 b1)
-__global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int logN, const ModConst* __restrict__ mc) {
+// Tensor of B pairs of ciphertexts over Q_l ([2][B][nl] each):
+// (a0 b0, a0 b1 + a1 b0, a1 b1) into [3][B][nl]
+__global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, int logN,
+                         const ModConst* __restrict__ mc) {
   const u64 N = 1ull << logN;
   u32 i = blockIdx.x * TPB + threadIdx.x;
   int k = blockIdx.y;
   if (i >= N) return;
-  const ModConst mk = mc[k];
-  size_t o0 = (size_t)k * N + i, o1 = (size_t)(nl + k) * N + i;
+  const ModConst mk = mc[k % nl];
+  size_t o0 = (size_t)k * N + i, o1 = (size_t)(nt + k) * N + i;
   u64 a0 = a[o0], a1 = a[o1], b0 = b[o0], b1 = b[o1];
   out[o0] = mul_mod(a0, b0, mk);
   out[o1] = add_mod(mul_mod(a0, b1, mk), mul_mod(a1, b0, mk), mk.q);
-  out[(size_t)(2 * nl + k) * N + i] = mul_mod(a1, b1, mk);
+  out[(size_t)(2 * nt + k) * N + i] = mul_mod(a1, b1, mk);
 }
-void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, hipStream_t s) {
-  ProfScope ps("tensor", s, 8.0 * T.N * 7 * nl);
-  dim3 grid(cdiv(T.N, TPB), nl);
-  hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, s, out3, a, b, nl, T.logN, T.mc);
+void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, hipStream_t s) {
+  const int nt = nl * batch;
+  ProfScope ps("tensor", s, 8.0 * T.N * 7 * nt);
+  dim3 grid(cdiv(T.N, TPB), nt);
+  hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, s, out3, a, b, nl, nt, T.logN, T.mc);
 }
 
 __global__ void k_int_to_limbs(u64* out, const i64* in, int nlimbs, LimbMap map, int logN,
@@ -661,6 +664,10 @@ __global__ void k_modup(u64* digits, const u64* coef, const u64* ntt_in, ModupAr
   u32 i = blockIdx.x * TPB + threadIdx.x;
   int j = blockIdx.y;
   if (i >= N) return;
+  // batch member blockIdx.z: inputs [B][nq][N], digits [B][beta][nqp][N]
+  digits += (size_t)blockIdx.z * A.beta * A.nqp * N;
+  coef += (size_t)blockIdx.z * A.nq * N;
+  ntt_in += (size_t)blockIdx.z * A.nq * N;
   const int ns = A.ns[j];
   u64 y[4];
   for (int a = 0; a < ns; a++) {
@@ -684,7 +691,7 @@ __global__ void k_modup(u64* digits, const u64* coef, const u64* ntt_in, ModupAr
 }
 
 void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64* ntt_in, int level, int L,
-                  int alpha, int beta, const FbcTable* tabs, hipStream_t s) {
+                  int alpha, int beta, const FbcTable* tabs, int batch, hipStream_t s) {
   ModupArgs A;
   A.nq = level + 1;
   A.nqp = level + 1 + alpha;
@@ -700,8 +707,8 @@ void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64
     A.hat_t[j] = tabs[j].hat_t;
     A.hat_t_sh[j] = tabs[j].hat_t_sh;
   }
-  ProfScope ps("modup", s, 8.0 * T.N * ((level + 1) + (double)beta * (level + 1 + alpha)));
-  dim3 grid(cdiv(T.N, TPB), beta);
+  ProfScope ps("modup", s, 8.0 * T.N * batch * ((level + 1) + (double)beta * (level + 1 + alpha)));
+  dim3 grid(cdiv(T.N, TPB), beta, batch);
   hipLaunchKernelGGL(k_modup, grid, dim3(TPB), 0, s, digits, coef, ntt_in, A, T.logN, T.nmods, T.mc);
 }
 
@@ -780,8 +787,8 @@ __global__ void k_fbc_to_q(u64* y, const u64* xp, int nq, FbcArgs A, int logN, i
     yy[(size_t)t * N + i] = acc;
   }
 }
-void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, const FbcTable& tab, hipStream_t s) {
-  // (npoly encoded by the caller through repeated launches; here one poly per z)
+void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
+                     hipStream_t s) {
   FbcArgs A;
   A.ns = tab.ns;
   for (int a = 0; a < tab.ns; a++) {
@@ -795,8 +802,8 @@ void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, 
   A.hat_t = tab.hat_t;
   A.hat_t_sh = tab.hat_t_sh;
   A.D_mod_t = tab.D_mod_t;
-  ProfScope ps("moddown", s, 8.0 * T.N * (2.0 * tab.ns + 2.0 * nq));
-  dim3 grid(cdiv(T.N, TPB), nq < 8 ? nq : 8, 2);
+  ProfScope ps("moddown", s, 8.0 * T.N * npoly * ((double)tab.ns + nq));
+  dim3 grid(cdiv(T.N, TPB), nq < 8 ? nq : 8, npoly);
   hipLaunchKernelGGL(k_fbc_to_q, grid, dim3(TPB), 0, s, y, xp_coef, nq, A, T.logN, T.nmods, T.mc);
 }
 
@@ -818,12 +825,18 @@ void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u
   hipLaunchKernelGGL(k_moddown_final, grid, dim3(TPB), 0, s, out, x, y, nq, pinv, x_stride_limbs, T.logN, T.mc);
 }
 
-// Hoisted rotation in R_{Q_l P}: for each limb pos and both key halves,
-//   out = sum_j pi_g(d_j) * swk_j  (+ P * pi_g(c0) on the Q limbs of the b half)
+// Hoisted rotation in R_{Q_l P} of MB batch members sharing one key: for each
+// limb pos and both key halves,
+//   out_b = sum_j pi_g(d_{b,j}) * swk_j  (+ P * pi_g(c0_b) on the Q limbs of the b half)
+// Each key word is read once and applied to every member.
+// digits [B][beta][nqp][N], c0 [B][nq][N], out [2][B][nqp][N]
+#define MS_MAXB 8
+template <int MB>
 __global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict__ digits,
                                                  const u64* __restrict__ key, const u64* __restrict__ c0,
                                                  const u64* __restrict__ pmod, int nq, int nqp, int L, int beta,
-                                                 int nmods, u64 g, int logN, const ModConst* __restrict__ mc) {
+                                                 int nmods, int B, int b0, u64 g, int logN,
+                                                 const ModConst* __restrict__ mc) {
   const u64 N = 1ull << logN;
   u32 i = blockIdx.x * TPB + threadIdx.x;
   int pos = blockIdx.y;
@@ -831,32 +844,51 @@ __global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict
   int m = pos < nq ? pos : L + 1 + (pos - nq);
   const ModConst mk = mc[m];
   u32 src = g == 1 ? i : automorph_src(i, g, logN);
-  u64 acc0 = 0, acc1 = 0;
+  u64 acc0[MB], acc1[MB];
+#pragma unroll
+  for (int b = 0; b < MB; b++) acc0[b] = acc1[b] = 0;
+  const size_t dstride = (size_t)beta * nqp * N;
   for (int j = 0; j < beta; j++) {
-    u64 d = digits[((size_t)j * nqp + pos) * N + src];
     u64 kb = key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
     u64 ka = key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
-    acc0 = add_mod(acc0, mul_mod(d, kb, mk), mk.q);
-    acc1 = add_mod(acc1, mul_mod(d, ka, mk), mk.q);
+#pragma unroll
+    for (int b = 0; b < MB; b++) {
+      u64 d = digits[(size_t)(b0 + b) * dstride + ((size_t)j * nqp + pos) * N + src];
+      acc0[b] = add_mod(acc0[b], mul_mod(d, kb, mk), mk.q);
+      acc1[b] = add_mod(acc1[b], mul_mod(d, ka, mk), mk.q);
+    }
   }
-  if (c0 && pos < nq) {
-    u64 v = c0[(size_t)pos * N + src];
-    acc0 = add_mod(acc0, shoup_mul(v, pmod[2 * m], pmod[2 * m + 1], mk.q), mk.q);
+#pragma unroll
+  for (int b = 0; b < MB; b++) {
+    if (c0 && pos < nq) {
+      u64 v = c0[((size_t)(b0 + b) * nq + pos) * N + src];
+      acc0[b] = add_mod(acc0[b], shoup_mul(v, pmod[2 * m], pmod[2 * m + 1], mk.q), mk.q);
+    }
+    out[((size_t)(b0 + b) * nqp + pos) * N + i] = acc0[b];
+    out[((size_t)(B + b0 + b) * nqp + pos) * N + i] = acc1[b];
   }
-  out[(size_t)pos * N + i] = acc0;
-  out[((size_t)nqp + pos) * N + i] = acc1;
 }
 void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,
-                    const u64* pmod, int level, int L, int alpha, int beta, u64 g, hipStream_t s) {
+                    const u64* pmod, int level, int L, int alpha, int beta, u64 g, int batch, hipStream_t s) {
   int nq = level + 1, nqp = nq + alpha;
-  // digits + both key halves + c0 read once, both output polys written once
-  ProfScope ps("multsum", s, 8.0 * T.N * (3.0 * beta * nqp + (c0 ? nq : 0) + 2.0 * nqp));
   dim3 grid(cdiv(T.N, TPB), nqp);
-  hipLaunchKernelGGL(k_multsum, grid, dim3(TPB), 0, s, out, digits, key, c0, pmod, nq, nqp, L, beta, T.nmods, g,
-                     T.logN, T.mc);
+  for (int b0 = 0; b0 < batch; b0 += MS_MAXB) {
+    const int mb = batch - b0 < MS_MAXB ? batch - b0 : MS_MAXB;
+    // key read once; digits and c0 of the mb members read once; outputs written once
+    ProfScope ps("multsum", s, 8.0 * T.N * (2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + 2.0 * nqp)));
+#define MS_CASE(K)                                                                                              \
+  case K:                                                                                                       \
+    hipLaunchKernelGGL(k_multsum<K>, grid, dim3(TPB), 0, s, out, digits, key, c0, pmod, nq, nqp, L, beta, T.nmods, \
+                       batch, b0, g, T.logN, T.mc);                                                             \
+    break;
+    switch (mb) {
+      MS_CASE(1) MS_CASE(2) MS_CASE(3) MS_CASE(4) MS_CASE(5) MS_CASE(6) MS_CASE(7) MS_CASE(8)
+    }
+#undef MS_CASE
+  }
 }
 
-// P-lift: out[p][pos] = P * c[p][pos] (pos < nq), 0 on P limbs
+// P-lift of npoly polys [npoly][nq] -> [npoly][nqp]: P * c on Q limbs, 0 on P limbs
 __global__ void k_plift(u64* out, const u64* c, const u64* pmod, int nq, int nqp, int logN,
                         const ModConst* __restrict__ mc) {
   const u64 N = 1ull << logN;
@@ -867,11 +899,11 @@ __global__ void k_plift(u64* out, const u64* c, const u64* pmod, int nq, int nqp
   if (pos < nq) v = shoup_mul(c[((size_t)p * nq + pos) * N + i], pmod[2 * pos], pmod[2 * pos + 1], mc[pos].q);
   out[((size_t)p * nqp + pos) * N + i] = v;
 }
-void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha,
+void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha, int npoly,
                   hipStream_t s) {
   int nq = level + 1, nqp = nq + alpha;
-  ProfScope ps("plift", s, 8.0 * T.N * (2.0 * nq + 2.0 * nqp));
-  dim3 grid(cdiv(T.N, TPB), nqp, 2);
+  ProfScope ps("plift", s, 8.0 * T.N * npoly * ((double)nq + nqp));
+  dim3 grid(cdiv(T.N, TPB), nqp, npoly);
   hipLaunchKernelGGL(k_plift, grid, dim3(TPB), 0, s, out, c, pmod, nq, nqp, T.logN, T.mc);
 }
 

@@ -79,7 +79,7 @@ struct HeCtxImpl {
   u64 galois(long step) const;
   u64* table_upload(const void* host, size_t bytes);
 
-  HeCt ct_new(int level, bool qp, double scale);
+  HeCt ct_new(int level, bool qp, double scale, int B = 1);
   HeCt ct_copy(const HeCt& x);
   void copy_limbs(u64* dst, const u64* src, size_t nlimbs);
 
@@ -100,13 +100,16 @@ struct HeCtxImpl {
   void add_into(HeCt& acc, const HeCt& b);
   HeCt drop(const HeCt& a, int level);
   HeCt rescale(const HeCt& a);
-  DevBuf decompose(const u64* d, int level);
+  DevBuf decompose(const u64* d, int level, int B = 1);
   HeCt hoisted(const HeCt& x, const u64* digits, u64 g);
   HeCt moddown(const HeCt& x);
-  HeCt keyswitch(const u64* d, int level, u64 g_key);
+  HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);
   HeCt rotate(const HeCt& x, long step);
   HeCt pmult_int(const HeCt& a, const i64* m_dev, double pt_scale);
+  void gather_limbs(u64* dst, const HeCt& x, int first, int count);
+  HeCt stack(const std::vector<const HeCt*>& xs);
+  std::vector<HeCt> unstack(const HeCt& x);
 
   std::vector<const u64*> plaintexts(const std::vector<std::string>& keys, const std::vector<std::vector<double>>& vecs,
                                      int n2, int level, bool qp, double scale);

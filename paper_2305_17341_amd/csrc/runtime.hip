@@ -388,18 +388,19 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
 // ---------------------------------------------------------------------------
 // basic containers
 // ---------------------------------------------------------------------------
-HeCt HeCtxImpl::ct_new(int level, bool qp, double scale) {
+HeCt HeCtxImpl::ct_new(int level, bool qp, double scale, int B) {
   HeCt c;
   c.N = N;
   c.level = level;
   c.qp = qp;
   c.nlimbs = level + 1 + (qp ? alpha : 0);
+  c.B = B;
   c.scale = scale;
-  c.d = DevBuf(&pool, (size_t)2 * c.nlimbs * N);
+  c.d = DevBuf(&pool, (size_t)2 * B * c.nlimbs * N);
   return c;
 }
 HeCt HeCtxImpl::ct_copy(const HeCt& x) {
-  HeCt c = ct_new(x.level, x.qp, x.scale);
+  HeCt c = ct_new(x.level, x.qp, x.scale, x.B);
   hip_check(hipMemcpyAsync(c.d.p, x.d.p, c.d.words * 8, hipMemcpyDeviceToDevice, stream), "copy");
   return c;
 }
@@ -526,6 +527,7 @@ HeCt HeCtxImpl::encrypt(const double* z, int nz, int level, u64 nonce) {
 std::vector<double> HeCtxImpl::decrypt(const HeCt& c) {
   if (!have_sk) fail(HE_EKEY, "keys not generated");
   if (c.qp) fail(HE_EINVAL, "cannot decrypt an R_QP element");
+  if (c.B != 1) fail(HE_EINVAL, "decrypt takes a single ciphertext, not a batch");
   DevBuf t(&pool, N);
   LimbMap m0 = one(0);
   launch_mul(T, t.p, c.limb(1, 0), s_ntt.p, 1, m0, stream);
@@ -546,30 +548,39 @@ std::vector<double> HeCtxImpl::decrypt(const HeCt& c) {
 }
 
 // ---------------------------------------------------------------------------
-// Add / Sub / PMult / Mult / Rescale / level drop
+// Add / Sub / PMult / Mult / Rescale / level drop (B members at once)
 // ---------------------------------------------------------------------------
 static void need_same(const HeCt& a, const HeCt& b) {
   if (a.level != b.level || a.qp != b.qp) fail(HE_ELEVEL, "operands at different levels");
+  if (a.B != b.B) fail(HE_EINVAL, "operands with different batch sizes");
 }
 HeCt HeCtxImpl::add(const HeCt& a, const HeCt& b, bool sub) {
   need_same(a, b);
   if (a.scale != b.scale) fail(HE_ESCALE, "operands with different scales");
-  HeCt c = ct_new(a.level, a.qp, a.scale);
+  HeCt c = ct_new(a.level, a.qp, a.scale, a.B);
   LimbMap m = a.qp ? qpmap(a.level) : qmap(a.level + 1);
-  if (sub) launch_sub(T, c.d.p, a.d.p, b.d.p, 2 * a.nlimbs, m, stream);
-  else launch_add(T, c.d.p, a.d.p, b.d.p, 2 * a.nlimbs, m, stream);
+  const int nl = (int)a.polys() * a.nlimbs;
+  if (sub) launch_sub(T, c.d.p, a.d.p, b.d.p, nl, m, stream);
+  else launch_add(T, c.d.p, a.d.p, b.d.p, nl, m, stream);
   return c;
 }
 void HeCtxImpl::add_into(HeCt& acc, const HeCt& b) {
   need_same(acc, b);
   LimbMap m = acc.qp ? qpmap(acc.level) : qmap(acc.level + 1);
-  launch_add(T, acc.d.p, acc.d.p, b.d.p, 2 * acc.nlimbs, m, stream);
+  launch_add(T, acc.d.p, acc.d.p, b.d.p, (int)acc.polys() * acc.nlimbs, m, stream);
+}
+
+// the first `count` limbs of every poly of x into dst [polys][count][N]
+void HeCtxImpl::gather_limbs(u64* dst, const HeCt& x, int first, int count) {
+  hip_check(hipMemcpy2DAsync(dst, (size_t)count * N * 8, x.d.p + (size_t)first * N, (size_t)x.nlimbs * N * 8,
+                             (size_t)count * N * 8, x.polys(), hipMemcpyDeviceToDevice, stream),
+            "gather");
 }
 
 HeCt HeCtxImpl::drop(const HeCt& a, int level) {
   if (a.qp || level > a.level || level < 0) fail(HE_ELEVEL, "bad level drop");
-  HeCt c = ct_new(level, false, a.scale);
-  for (int p = 0; p < 2; p++) copy_limbs(c.poly(p), a.poly(p), level + 1);
+  HeCt c = ct_new(level, false, a.scale, a.B);
+  gather_limbs(c.d.p, a, 0, level + 1);
   return c;
 }
 
@@ -577,29 +588,29 @@ HeCt HeCtxImpl::rescale(const HeCt& a) {
   if (a.qp) fail(HE_EINVAL, "rescale of an R_QP element");
   int l = a.level;
   if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
-  DevBuf top(&pool, 2 * N);
-  copy_limbs(top.p, a.limb(0, l), 1);
-  copy_limbs(top.p + N, a.limb(1, l), 1);
-  launch_ntt(T, top.p, 2, one(l), true, stream);
-  DevBuf t(&pool, (size_t)2 * l * N);
-  launch_rescale_lift(T, t.p, top.p, l, 2, stream);
-  launch_ntt(T, t.p, 2 * l, qmap(l), false, stream);
-  HeCt c = ct_new(l - 1, false, a.scale / (double)mods[l]);
-  launch_rescale_final(T, c.d.p, a.d.p, t.p, l, 2, l + 1, qlinv.p + (size_t)l * nmods * 2, stream);
+  const int np = (int)a.polys();
+  DevBuf top(&pool, (size_t)np * N);
+  gather_limbs(top.p, a, l, 1);
+  launch_ntt(T, top.p, np, one(l), true, stream);
+  DevBuf t(&pool, (size_t)np * l * N);
+  launch_rescale_lift(T, t.p, top.p, l, np, stream);
+  launch_ntt(T, t.p, np * l, qmap(l), false, stream);
+  HeCt c = ct_new(l - 1, false, a.scale / (double)mods[l], a.B);
+  launch_rescale_final(T, c.d.p, a.d.p, t.p, l, np, l + 1, qlinv.p + (size_t)l * nmods * 2, stream);
   return c;
 }
 
 // ---------------------------------------------------------------------------
 // key switching (section 3.3.1; Appendix A KeySwitch)
 // ---------------------------------------------------------------------------
-// Decompose: digits u64[beta_l][l+1+alpha][N], evaluation domain
-DevBuf HeCtxImpl::decompose(const u64* d, int level) {
+// Decompose B polynomials d [B][l+1][N]: digits u64[B][beta_l][l+1+alpha][N], evaluation domain
+DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
   int nq = nq_of(level), nqp = nqp_of(level), bl = beta_at(level);
-  DevBuf coef(&pool, (size_t)nq * N);
-  copy_limbs(coef.p, d, nq);
-  launch_ntt(T, coef.p, nq, qmap(nq), true, stream);
-  DevBuf dig(&pool, (size_t)bl * nqp * N);
-  launch_modup(T, dig.p, coef.p, d, level, L, alpha, bl, up[level].data(), stream);
+  DevBuf coef(&pool, (size_t)B * nq * N);
+  copy_limbs(coef.p, d, (size_t)B * nq);
+  launch_ntt(T, coef.p, B * nq, qmap(nq), true, stream);
+  DevBuf dig(&pool, (size_t)B * bl * nqp * N);
+  launch_modup(T, dig.p, coef.p, d, level, L, alpha, bl, up[level].data(), B, stream);
   LimbMap m;
   m.n = bl * nqp;
   if (m.n > 960) fail(HE_EINVAL, "too many digit limbs");
@@ -608,69 +619,69 @@ DevBuf HeCtxImpl::decompose(const u64* d, int level) {
       bool own = pos < nq && pos / alpha == j;
       m.idx[j * nqp + pos] = own ? (short)-1 : (short)qp_mod(level, pos);
     }
-  launch_ntt(T, dig.p, m.n, m, false, stream);
-  n_decompose++;
+  launch_ntt(T, dig.p, B * m.n, m, false, stream);
+  n_decompose += B;
   return dig;
 }
 
 // hoisted rotation left in R_{Q_l P}; g = 1 gives the P-lift
 HeCt HeCtxImpl::hoisted(const HeCt& x, const u64* digits, u64 g) {
-  HeCt h = ct_new(x.level, true, x.scale);
+  HeCt h = ct_new(x.level, true, x.scale, x.B);
   if (g == 1) {
-    launch_plift(T, h.d.p, x.d.p, pmod.p, x.level, alpha, stream);
+    launch_plift(T, h.d.p, x.d.p, pmod.p, x.level, alpha, (int)x.polys(), stream);
     return h;
   }
   const DevBuf& k = key(g);
-  launch_multsum(T, h.d.p, digits, k.p, x.poly(0), pmod.p, x.level, L, alpha, beta_at(x.level), g, stream);
-  n_multsum++;
+  launch_multsum(T, h.d.p, digits, k.p, x.poly(0), pmod.p, x.level, L, alpha, beta_at(x.level), g, x.B, stream);
+  n_multsum += x.B;
   return h;
 }
 
-// ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - FBC_{P->Q}(x mod P)) P^{-1}
+// ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact centred residue
 HeCt HeCtxImpl::moddown(const HeCt& x) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   int nq = nq_of(x.level), nqp = nqp_of(x.level);
-  DevBuf pc(&pool, (size_t)2 * alpha * N);
-  copy_limbs(pc.p, x.limb(0, nq), alpha);
-  copy_limbs(pc.p + (size_t)alpha * N, x.limb(1, nq), alpha);
+  const int np = (int)x.polys();
+  DevBuf pc(&pool, (size_t)np * alpha * N);
+  gather_limbs(pc.p, x, nq, alpha);
   LimbMap pm;
   pm.n = alpha;
   for (int k = 0; k < alpha; k++) pm.idx[k] = (short)(L + 1 + k);
-  launch_ntt(T, pc.p, 2 * alpha, pm, true, stream);
-  DevBuf y(&pool, (size_t)2 * nq * N);
-  launch_fbc_to_q(T, y.p, pc.p, nq, down, stream);
-  launch_ntt(T, y.p, 2 * nq, qmap(nq), false, stream);
-  HeCt c = ct_new(x.level, false, x.scale);
-  launch_moddown_final(T, c.d.p, x.d.p, y.p, nq, pinv.p, 2, nqp, stream);
-  n_moddown++;
+  launch_ntt(T, pc.p, np * alpha, pm, true, stream);
+  DevBuf y(&pool, (size_t)np * nq * N);
+  launch_fbc_to_q(T, y.p, pc.p, nq, np, down, stream);
+  launch_ntt(T, y.p, np * nq, qmap(nq), false, stream);
+  HeCt c = ct_new(x.level, false, x.scale, x.B);
+  launch_moddown_final(T, c.d.p, x.d.p, y.p, nq, pinv.p, np, nqp, stream);
+  n_moddown += x.B;
   return c;
 }
 
-HeCt HeCtxImpl::keyswitch(const u64* d, int level, u64 g_key) {
-  DevBuf dig = decompose(d, level);
-  HeCt h = ct_new(level, true, 1.0);
+HeCt HeCtxImpl::keyswitch(const u64* d, int level, u64 g_key, int B) {
+  DevBuf dig = decompose(d, level, B);
+  HeCt h = ct_new(level, true, 1.0, B);
   const DevBuf& k = key(g_key);
-  launch_multsum(T, h.d.p, dig.p, k.p, nullptr, pmod.p, level, L, alpha, beta_at(level), 1, stream);
-  n_multsum++;
+  launch_multsum(T, h.d.p, dig.p, k.p, nullptr, pmod.p, level, L, alpha, beta_at(level), 1, B, stream);
+  n_multsum += B;
   return moddown(h);
 }
 
 HeCt HeCtxImpl::mult(const HeCt& a, const HeCt& b) {
   need_same(a, b);
   if (a.qp) fail(HE_EINVAL, "mult of R_QP elements");
-  int nl = a.nlimbs;
-  DevBuf t3(&pool, (size_t)3 * nl * N);
-  launch_tensor(T, t3.p, a.d.p, b.d.p, nl, stream);
-  HeCt ks = keyswitch(t3.p + (size_t)2 * nl * N, a.level, 0);
-  HeCt c = ct_new(a.level, false, a.scale * b.scale);
-  launch_add(T, c.d.p, t3.p, ks.d.p, 2 * nl, qmap(nl), stream);
+  int nl = a.nlimbs, nt = a.B * nl;
+  DevBuf t3(&pool, (size_t)3 * nt * N);
+  launch_tensor(T, t3.p, a.d.p, b.d.p, nl, a.B, stream);
+  HeCt ks = keyswitch(t3.p + (size_t)2 * nt * N, a.level, 0, a.B);
+  HeCt c = ct_new(a.level, false, a.scale * b.scale, a.B);
+  launch_add(T, c.d.p, t3.p, ks.d.p, 2 * nt, qmap(nl), stream);
   return c;
 }
 
 HeCt HeCtxImpl::rotate(const HeCt& x, long step) {
   u64 g = galois(step);
   if (g == 1) return ct_copy(x);
-  DevBuf dig = decompose(x.poly(1), x.level);
+  DevBuf dig = decompose(x.poly(1), x.level, x.B);
   HeCt h = hoisted(x, dig.p, g);
   return moddown(h);
 }
@@ -679,9 +690,30 @@ HeCt HeCtxImpl::pmult_int(const HeCt& a, const i64* m_dev, double pt_scale) {
   LimbMap m = a.qp ? qpmap(a.level) : qmap(a.level + 1);
   DevBuf pt(&pool, (size_t)a.nlimbs * N);
   int_to_ntt(pt.p, m_dev, m);
-  HeCt c = ct_new(a.level, a.qp, a.scale * pt_scale);
-  launch_mul_bcast(T, c.d.p, a.d.p, pt.p, 2 * a.nlimbs, a.nlimbs, m, stream);
+  HeCt c = ct_new(a.level, a.qp, a.scale * pt_scale, a.B);
+  launch_mul_bcast(T, c.d.p, a.d.p, pt.p, (int)a.polys() * a.nlimbs, a.nlimbs, m, stream);
   return c;
+}
+
+// B single ciphertexts of one level and scale -> one batch, and back
+HeCt HeCtxImpl::stack(const std::vector<const HeCt*>& xs) {
+  const HeCt& x0 = *xs[0];
+  for (auto* x : xs)
+    if (x->level != x0.level || x->qp || x->B != 1 || x->scale != x0.scale)
+      fail(HE_EINVAL, "batched members must share level and scale");
+  HeCt c = ct_new(x0.level, false, x0.scale, (int)xs.size());
+  for (size_t b = 0; b < xs.size(); b++)
+    for (int p = 0; p < 2; p++) copy_limbs(c.member(p, (int)b), xs[b]->poly(p), x0.nlimbs);
+  return c;
+}
+std::vector<HeCt> HeCtxImpl::unstack(const HeCt& x) {
+  std::vector<HeCt> out;
+  for (int b = 0; b < x.B; b++) {
+    HeCt c = ct_new(x.level, x.qp, x.scale, 1);
+    for (int p = 0; p < 2; p++) copy_limbs(c.poly(p), x.member(p, b), x.nlimbs);
+    out.push_back(std::move(c));
+  }
+  return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -819,13 +851,13 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
   std::vector<bool> used(n1, false);
   for (auto& p : ij) used[p.second] = true;
   // Decompose once, baby-step hoisted rotations kept in R_{Q_l P}
-  DevBuf dig = decompose(x.poly(1), level);
+  DevBuf dig = decompose(x.poly(1), level, x.B);
   std::vector<HeCt> baby(n1);
   for (int j = 0; j < n1; j++)
     if (used[j]) baby[j] = hoisted(x, dig.p, galois((long)G.a * j));
   dig.release();
   LimbMap qpm = qpmap(level);
-  HeCt acc = ct_new(level, true, x.scale * delta);
+  HeCt acc = ct_new(level, true, x.scale * delta, x.B);
   bool acc_set = false;
   size_t e = 0;
   for (int i = G.i_lo; i < G.i_hi; i++) {
@@ -834,11 +866,11 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
     for (; e < ij.size() && ij[e].first == i; e++) {
       int j = ij[e].second;
       if (!inner_set) {
-        inner = ct_new(level, true, x.scale * delta);
-        launch_mul_bcast(T, inner.d.p, baby[j].d.p, pts[e], 2 * nqp, nqp, qpm, stream);
+        inner = ct_new(level, true, x.scale * delta, x.B);
+        launch_mul_bcast(T, inner.d.p, baby[j].d.p, pts[e], 2 * x.B * nqp, nqp, qpm, stream);
         inner_set = true;
       } else {
-        launch_mul_acc(T, inner.d.p, baby[j].d.p, pts[e], 2 * nqp, nqp, qpm, stream);
+        launch_mul_acc(T, inner.d.p, baby[j].d.p, pts[e], 2 * x.B * nqp, nqp, qpm, stream);
       }
     }
     if (!inner_set) continue;
@@ -847,7 +879,7 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
       term = std::move(inner);
     } else {
       HeCt t = moddown(inner);
-      DevBuf d2 = decompose(t.poly(1), level);
+      DevBuf d2 = decompose(t.poly(1), level, t.B);
       term = hoisted(t, d2.p, galois((long)G.a * n1 * i));
     }
     if (!acc_set) {
@@ -1022,19 +1054,19 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       Bb = rotate(Bb, n1z);
       Bpb = rotate(Bpb, n1z);
     }
-    DevBuf d1 = decompose(Bb.poly(1), lvl);
-    DevBuf d2 = decompose(Bpb.poly(1), lvl);
+    DevBuf d1 = decompose(Bb.poly(1), lvl, Bb.B);
+    DevBuf d2 = decompose(Bpb.poly(1), lvl, Bpb.B);
     for (int r = 0; r < n1z && b * n1z + r < n; r++) {
       int k = b * n1z + r;
       u64 g = galois(r);
-      HeCt acc = ct_new(lvl, true, Bb.scale * delta);
+      HeCt acc = ct_new(lvl, true, Bb.scale * delta, Bb.B);
       {
         HeCt h = hoisted(Bb, d1.p, g);
-        launch_mul_bcast(T, acc.d.p, h.d.p, mask_of(k, 0), 2 * nqp, nqp, qpm, stream);
+        launch_mul_bcast(T, acc.d.p, h.d.p, mask_of(k, 0), 2 * Bb.B * nqp, nqp, qpm, stream);
       }
       if (k > 0) {
         HeCt h = hoisted(Bpb, d2.p, g);
-        launch_mul_acc(T, acc.d.p, h.d.p, mask_of(k, 1), 2 * nqp, nqp, qpm, stream);
+        launch_mul_acc(T, acc.d.p, h.d.p, mask_of(k, 1), 2 * Bb.B * nqp, nqp, qpm, stream);
       }
       HeCt md = moddown(acc);
       Ak[k] = rescale(md);
@@ -1050,7 +1082,7 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int n
   std::vector<HeCt> Bk(n);
   for (int b = 0; b * n1t < n; b++) {
     if (b > 0) Cb = rotate(Cb, (long)n * n1t);
-    DevBuf d1 = decompose(Cb.poly(1), lvl);
+    DevBuf d1 = decompose(Cb.poly(1), lvl, Cb.B);
     for (int r = 0; r < n1t && b * n1t + r < n; r++) {
       int k = b * n1t + r;
       if (r == 0) {
