@@ -28,6 +28,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "HE d×d matmuls/s & key-switched rotations/s at N=2^16, batched vs plain; p99"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2305_17341_amd/csrc/kernels.hip", "paper_2305_17341_amd/csrc/he_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernels_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE counters,
+    scaled by a plain copy's reading) recorded with the kernel sources they
+    were taken on; None when absent or the sources have changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None or rec.get("kernels_sha256") != kernels_sha256():
+        return None
+    return k["bytes_per_launch"]
 
 
 def log(msg):
@@ -87,6 +112,9 @@ def main():
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--rotations", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving run (0: skip it)")
+    ap.add_argument("--calib-copies", type=int, default=0,
+                    help="device copies of one top-level ciphertext at the end (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -137,7 +165,8 @@ def main():
         t_plain, lat_plain, plain_outs = timed(None, False)
     c0 = ctx.op_counts()
     t_total, lat, outs = timed(batched, True)
-    fams = ["ntt", "multsum", "modup", "moddown", "rescale", "elementwise", "tensor", "plift"]
+    fams = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "multsum", "modup", "fbc_to_q",
+            "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor", "plift"]
     prof = {f: ctx.profile_read(f) for f in fams}
     ctx.profile_enable(False)
     c1 = ctx.op_counts()
@@ -159,6 +188,10 @@ def main():
         del r
     ctx.sync()
     rot_s = args.rotations / (time.perf_counter() - t0)
+    for _ in range(args.calib_copies):
+        r = ctx.rotate(ct, 0)   # step 0: a plain device copy of 2 x 31 limbs
+        del r
+    ctx.sync()
 
     value = args.steps * B / t_total
     fam_ms = {f: prof[f][0] / args.steps for f in fams}
@@ -167,8 +200,10 @@ def main():
     avg_ms = ms / max(launches, 1)
     bytes_per_launch = nbytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
                 "avg_launch_ms": round(avg_ms, 5), "launches": launches,
                 "algorithmic_bytes_per_launch": round(bytes_per_launch)}
     n_rescale = 2 + 1 + d  # sigma, tau, the d column shifts, the final product
@@ -199,6 +234,10 @@ def main():
         "kernel_ms_per_step": {f: round(v, 3) for f, v in fam_ms.items()},
         "roofline": roofline,
     }
+    if args.serve_jobs > 0:
+        from paper_2305_17341_amd import serve
+        log("[bench] serving run ...")
+        result["serving"] = serve.serve_bench(["--jobs", str(args.serve_jobs)])
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
         result["cpu_baseline"] = cpu_baseline(chain, per_mm, n_rescale)

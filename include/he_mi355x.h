@@ -23,6 +23,10 @@
  *     keys live in device memory owned by the library.
  *   - Work is issued on the context's HIP stream and is asynchronous; calls
  *     that hand data to the host (he_decrypt, he_ct_export) synchronise.
+ *   - Calls that touch one context (or its ciphertexts) are serialised by a
+ *     lock held inside the library; different contexts may be driven from
+ *     different threads at once, and their work overlaps on the device.
+ *     he_ctx_destroy must not race with any other call on that context.
  *   - A ciphertext at level l is u64[2][l+1][N] (limb-major, evaluation
  *     domain, residues in [0, q_i)); its scale is a double tracked exactly.
  *   - Slot vectors hold N/2 reals; a shorter message is replicated with its
@@ -174,6 +178,11 @@ he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks,
 he_status he_sync(he_ctx* ctx);
 /* device bytes held by the context (live, cached, peak) */
 he_status he_mem_info(const he_ctx* ctx, size_t* live, size_t* cached, size_t* peak);
+/* free and total bytes of the current HIP device */
+he_status he_device_memory(size_t* free_bytes, size_t* total_bytes);
+/* wait for the context's work, return its cached (free) device blocks to the
+ * allocator and restart the peak mark at the live bytes */
+he_status he_trim(he_ctx* ctx);
 
 /* Raw limb transforms for parity checks: host in/out u64[nlimbs][N]; limb k
  * uses modulus mod_idx[k] (index into he_ctx_moduli order). */
@@ -189,11 +198,16 @@ he_status he_hoisted_rotate_export(he_ctx* ctx, const he_ct* a, int32_t step, ui
  * (HIP events around the call's stream work) */
 he_status he_last_op_ms(const he_ctx* ctx, double* ms);
 
-/* Device-time profile by kernel family ("ntt", "multsum", "modup", "moddown",
- * "rescale", "elementwise", "tensor", "plift"): while enabled, HIP events are
- * recorded on the launching stream around every launch of the family.
- * Enabling clears the totals.  `bytes` (may be NULL) receives the family's
- * algorithmic HBM bytes: every input read once, every output written once. */
+/* Device-time profile by kernel: "ntt_fwd_cols", "ntt_fwd_rows",
+ * "ntt_inv_rows", "ntt_inv_cols" (the two passes of each transform),
+ * "multsum", "modup", "fbc_to_q", "moddown_final", "rescale_lift",
+ * "rescale_final", "elementwise", "tensor", "plift".  While enabled, HIP
+ * events are recorded on the launching stream around every launch of the
+ * kernel.  Enabling clears the totals.  `bytes` (may be NULL) receives the
+ * kernel's algorithmic HBM bytes: every input read once, every output written
+ * once (for an NTT pass: every active limb read and written once).  The
+ * profile is process-wide: enable it only while a single thread drives the
+ * library. */
 he_status he_profile_enable(he_ctx* ctx, int on);
 he_status he_profile_read(he_ctx* ctx, const char* family, double* total_ms, uint64_t* launches, double* bytes);
 /* counts of Decompose / MultSum / ModDown operations issued by the context */

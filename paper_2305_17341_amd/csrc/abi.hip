@@ -47,6 +47,15 @@ he_status guard_host(F&& f) {
 void need(bool ok, const char* what) {
   if (!ok) fail(HE_EINVAL, what);
 }
+// one caller at a time per context (its stream, pool and caches are shared)
+std::unique_lock<std::recursive_mutex> hold(const he_ctx* c) {
+  need(c != nullptr, "null context");
+  return std::unique_lock<std::recursive_mutex>(c->mu);
+}
+std::unique_lock<std::recursive_mutex> hold_ct(const he_ct* x) {
+  need(x != nullptr, "null ciphertext");
+  return hold(x->ctx);
+}
 he_ct* wrap(he_ctx* c, HeCt&& x) {
   he_ct* r = new he_ct;
   r->ctx = c;
@@ -103,6 +112,7 @@ he_status he_ctx_destroy(he_ctx* ctx) {
 
 he_status he_ctx_moduli(const he_ctx* ctx, uint64_t* out, size_t cap, size_t* n) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx != nullptr, "null context");
     const HeCtxImpl& c = ctx->impl;
     if (n) *n = (size_t)c.nmods;
@@ -112,6 +122,7 @@ he_status he_ctx_moduli(const he_ctx* ctx, uint64_t* out, size_t cap, size_t* n)
 
 he_status he_keygen(he_ctx* ctx, const int32_t* rot_steps, size_t n_steps) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx != nullptr, "null context");
     HeCtxImpl& c = ctx->impl;
     c.keygen_secret();
@@ -124,6 +135,7 @@ he_status he_keygen(he_ctx* ctx, const int32_t* rot_steps, size_t n_steps) {
 he_status he_matmul_rot_steps(const he_ctx* ctx, uint32_t d, const he_matmul_opts* opts, int32_t* steps, size_t cap,
                               size_t* n) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx != nullptr && d >= 2, "bad arguments");
     MmOpts m = opts_of(opts, (int)d);
     std::vector<long> s = matmul_steps((int)d, m.n1z, m.n1t, m.npz, m.npt);
@@ -149,6 +161,7 @@ he_status he_lintrans_rot_steps(uint32_t kind, uint32_t d, uint32_t n1, uint32_t
 
 he_status he_transpose_rot_steps(const he_ctx* ctx, uint32_t d, uint32_t n1, int32_t* steps, size_t cap, size_t* n) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx != nullptr && d >= 2, "bad arguments");
     std::vector<long> s = transpose_steps((int)d, n1 ? (int)n1 : default_n1((int)d));
     if (n) *n = s.size();
@@ -158,6 +171,7 @@ he_status he_transpose_rot_steps(const he_ctx* ctx, uint32_t d, uint32_t n1, int
 
 he_status he_encode(he_ctx* ctx, const double* z, size_t n, double delta, int64_t* out) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx && z && out && n > 0, "bad arguments");
     HeCtxImpl& c = ctx->impl;
     DevBuf m = c.encode_batch(z, (int)n, 1, delta);
@@ -168,6 +182,7 @@ he_status he_encode(he_ctx* ctx, const double* z, size_t n, double delta, int64_
 
 he_status he_encrypt_slots(he_ctx* ctx, const double* z, size_t n, uint32_t level, uint64_t nonce, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx && z && out && n > 0, "bad arguments");
     *out = wrap(ctx, ctx->impl.encrypt(z, (int)n, (int)level, nonce));
   });
@@ -175,6 +190,7 @@ he_status he_encrypt_slots(he_ctx* ctx, const double* z, size_t n, uint32_t leve
 
 he_status he_encrypt_matrix(he_ctx* ctx, const double* a, uint32_t d, uint32_t level, uint64_t nonce, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx && a && out && d > 0, "bad arguments");
     need((u64)d * d <= ctx->impl.N / 2 && (ctx->impl.N / 2) % ((u64)d * d) == 0, "d*d must divide N/2");
     *out = wrap(ctx, ctx->impl.encrypt(a, (int)(d * d), (int)level, nonce));
@@ -183,6 +199,7 @@ he_status he_encrypt_matrix(he_ctx* ctx, const double* a, uint32_t d, uint32_t l
 
 he_status he_decrypt(he_ctx* ctx, const he_ct* ct, double* out, size_t n) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, ct);
     need(out != nullptr && n <= ctx->impl.N / 2, "bad output size");
     std::vector<double> z = ctx->impl.decrypt(ct->ct);
@@ -192,6 +209,7 @@ he_status he_decrypt(he_ctx* ctx, const he_ct* ct, double* out, size_t n) {
 
 he_status he_ct_info(const he_ct* ct, uint32_t* level, double* scale) {
   return guard([&] {
+    auto lk = hold_ct(ct);
     need(ct != nullptr, "null ciphertext");
     if (level) *level = (uint32_t)ct->ct.level;
     if (scale) *scale = ct->ct.scale;
@@ -200,6 +218,7 @@ he_status he_ct_info(const he_ct* ct, uint32_t* level, double* scale) {
 
 he_status he_ct_export(const he_ct* ct, uint64_t* host, size_t words, uint32_t* level, double* scale) {
   return guard([&] {
+    auto lk = hold_ct(ct);
     need(ct != nullptr && host != nullptr, "null argument");
     need(words >= ct->ct.d.words, "host buffer too small");
     HeCtxImpl& c = ct->ctx->impl;
@@ -212,6 +231,7 @@ he_status he_ct_export(const he_ct* ct, uint64_t* host, size_t words, uint32_t* 
 
 he_status he_ct_import(he_ctx* ctx, const uint64_t* host, size_t words, uint32_t level, double scale, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx && host && out, "null argument");
     HeCtxImpl& c = ctx->impl;
     need((int)level <= c.L, "level out of range");
@@ -224,11 +244,16 @@ he_status he_ct_import(he_ctx* ctx, const uint64_t* host, size_t words, uint32_t
 }
 
 he_status he_ct_free(he_ct* ct) {
-  return guard([&] { delete ct; });
+  return guard([&] {
+    if (!ct) return;
+    auto lk = hold(ct->ctx);
+    delete ct;
+  });
 }
 
 he_status he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     check_ct(ctx, b);
     *out = wrap(ctx, ctx->impl.add(a->ct, b->ct, false));
@@ -236,6 +261,7 @@ he_status he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
 }
 he_status he_sub(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     check_ct(ctx, b);
     *out = wrap(ctx, ctx->impl.add(a->ct, b->ct, true));
@@ -243,6 +269,7 @@ he_status he_sub(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
 }
 he_status he_mult(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     check_ct(ctx, b);
     *out = wrap(ctx, ctx->impl.mult(a->ct, b->ct));
@@ -250,24 +277,28 @@ he_status he_mult(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
 }
 he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     *out = wrap(ctx, ctx->impl.rescale(a->ct));
   });
 }
 he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     *out = wrap(ctx, ctx->impl.rotate(a->ct, step));
   });
 }
 he_status he_drop_level(he_ctx* ctx, const he_ct* a, uint32_t level, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     *out = wrap(ctx, ctx->impl.drop(a->ct, (int)level));
   });
 }
 he_status he_pmult_slots(he_ctx* ctx, const he_ct* a, const double* z, size_t n, double pt_scale, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     need(z && n > 0, "bad plaintext");
     HeCtxImpl& c = ctx->impl;
@@ -279,6 +310,7 @@ he_status he_pmult_slots(he_ctx* ctx, const he_ct* a, const double* z, size_t n,
 he_status he_lintrans(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, double weight,
                       he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     need(kind <= 2 && d >= 2, "bad transform");
     *out = wrap(ctx, ctx->impl.lintrans(a->ct, (int)kind, (int)d, n1 ? (int)n1 : default_n1((int)d), weight));
@@ -288,6 +320,7 @@ he_status he_lintrans(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, ui
 he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, const he_matmul_opts* opts,
                     he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     check_ct(ctx, b);
     need(out != nullptr && d >= 2, "bad arguments");
@@ -303,6 +336,7 @@ he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, con
 he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const* b, const uint32_t* d,
                           size_t count, const he_matmul_opts* opts, he_ct** out) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(a && b && d && out, "null argument");
     HeCtxImpl& c = ctx->impl;
     for (size_t i = 0; i < count; i++) {
@@ -353,6 +387,7 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
 he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks, uint32_t k, uint32_t d,
                         uint64_t n_samples, const he_matmul_opts* opts, he_ct** cov) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(x && cov && row_blocks > 0 && k > 0 && d >= 2 && n_samples > 0, "bad arguments");
     std::vector<const HeCt*> xs;
     for (uint32_t i = 0; i < row_blocks * k; i++) {
@@ -371,6 +406,7 @@ he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks,
 
 he_status he_sync(he_ctx* ctx) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx != nullptr, "null context");
     hip_check(hipStreamSynchronize(ctx->impl.stream), "sync");
   });
@@ -378,6 +414,7 @@ he_status he_sync(he_ctx* ctx) {
 
 he_status he_mem_info(const he_ctx* ctx, size_t* live, size_t* cached, size_t* peak) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx != nullptr, "null context");
     if (live) *live = ctx->impl.pool.bytes_live;
     if (cached) *cached = ctx->impl.pool.bytes_cached;
@@ -385,9 +422,27 @@ he_status he_mem_info(const he_ctx* ctx, size_t* live, size_t* cached, size_t* p
   });
 }
 
+he_status he_device_memory(size_t* free_bytes, size_t* total_bytes) {
+  return guard([&] {
+    need(free_bytes && total_bytes, "null argument");
+    hip_check(hipMemGetInfo(free_bytes, total_bytes), "memory info");
+  });
+}
+
+he_status he_trim(he_ctx* ctx) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    need(ctx != nullptr, "null context");
+    hip_check(hipStreamSynchronize(ctx->impl.stream), "sync");
+    ctx->impl.pool.trim();
+    ctx->impl.pool.peak = ctx->impl.pool.bytes_live;
+  });
+}
+
 he_status he_ntt_limbs(he_ctx* ctx, const uint64_t* in, uint64_t* out, size_t nlimbs, const int32_t* mod_idx,
                        int inverse) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx && in && out && mod_idx && nlimbs > 0 && nlimbs <= 960, "bad arguments");
     HeCtxImpl& c = ctx->impl;
     LimbMap m;
@@ -408,6 +463,7 @@ he_status he_ntt_limbs(he_ctx* ctx, const uint64_t* in, uint64_t* out, size_t nl
 
 he_status he_automorph_limbs(he_ctx* ctx, const uint64_t* in, uint64_t* out, size_t nlimbs, uint64_t galois) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx && in && out && nlimbs > 0, "bad arguments");
     HeCtxImpl& c = ctx->impl;
     need(galois % 2 == 1 && galois < 2 * c.N, "Galois element must be odd and below 2N");
@@ -421,6 +477,7 @@ he_status he_automorph_limbs(he_ctx* ctx, const uint64_t* in, uint64_t* out, siz
 
 he_status he_hoisted_rotate_export(he_ctx* ctx, const he_ct* a, int32_t step, uint64_t* host, size_t words) {
   return guard([&] {
+    auto lk = hold(ctx);
     check_ct(ctx, a);
     HeCtxImpl& c = ctx->impl;
     u64 g = c.galois(step);
@@ -435,6 +492,7 @@ he_status he_hoisted_rotate_export(he_ctx* ctx, const he_ct* a, int32_t step, ui
 
 he_status he_last_op_ms(const he_ctx* ctx, double* ms) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx && ms, "null argument");
     float f = 0;
     hip_check(hipEventSynchronize(ctx->impl.ev1), "event");
@@ -445,6 +503,7 @@ he_status he_last_op_ms(const he_ctx* ctx, double* ms) {
 
 he_status he_profile_enable(he_ctx* ctx, int on) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx != nullptr, "null context");
     hip_check(hipStreamSynchronize(ctx->impl.stream), "sync");
     prof_enable(on != 0);
@@ -453,6 +512,7 @@ he_status he_profile_enable(he_ctx* ctx, int on) {
 
 he_status he_profile_read(he_ctx* ctx, const char* family, double* total_ms, uint64_t* launches, double* bytes) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx && family && total_ms && launches, "null argument");
     hip_check(hipStreamSynchronize(ctx->impl.stream), "sync");
     u64 n = 0;
@@ -465,6 +525,7 @@ he_status he_profile_read(he_ctx* ctx, const char* family, double* total_ms, uin
 
 he_status he_op_counts(const he_ctx* ctx, uint64_t* decompose, uint64_t* multsum, uint64_t* moddown) {
   return guard([&] {
+    auto lk = hold(ctx);
     need(ctx != nullptr, "null context");
     if (decompose) *decompose = (uint64_t)ctx->impl.n_decompose;
     if (multsum) *multsum = (uint64_t)ctx->impl.n_multsum;

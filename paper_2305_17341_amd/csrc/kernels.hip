@@ -464,47 +464,65 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
 }
 
 template <int LOGN, int GA, int GB, int GC, int GD>
-static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s) {
+static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, double pass_bytes,
+                 hipStream_t s) {
   constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
   static_assert(GA + GB + GC + GD == LOGN, "stage split");
   dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
   if (!inverse) {
-    hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh, T.mc);
+    {
+      ProfScope ps("ntt_fwd_cols", s, pass_bytes);
+      hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh, T.mc);
+    }
+    ProfScope ps("ntt_fwd_rows", s, pass_bytes);
     hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false>), gr, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh, T.mc);
   } else {
-    hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, true>), gr, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh, T.mc);
+    {
+      ProfScope ps("ntt_inv_rows", s, pass_bytes);
+      hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, true>), gr, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh, T.mc);
+    }
+    ProfScope ps("ntt_inv_cols", s, pass_bytes);
     hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, true>), gc, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh, T.mc);
   }
 }
 
 static bool ntt_register_blocked(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse,
-                                 hipStream_t s) {
+                                 double pass_bytes, hipStream_t s) {
   switch (T.logN) {
-    case 16: ntt2<16, 4, 4, 4, 4>(T, data, nlimbs, map, inverse, s); return true;
-    case 15: ntt2<15, 4, 3, 4, 4>(T, data, nlimbs, map, inverse, s); return true;
-    case 14: ntt2<14, 4, 3, 4, 3>(T, data, nlimbs, map, inverse, s); return true;
-    case 13: ntt2<13, 3, 3, 4, 3>(T, data, nlimbs, map, inverse, s); return true;
-    case 12: ntt2<12, 3, 3, 3, 3>(T, data, nlimbs, map, inverse, s); return true;
+    case 16: ntt2<16, 4, 4, 4, 4>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
+    case 15: ntt2<15, 4, 3, 4, 4>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
+    case 14: ntt2<14, 4, 3, 4, 3>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
+    case 13: ntt2<13, 3, 3, 4, 3>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
+    case 12: ntt2<12, 3, 3, 3, 3>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
     default: return false;
   }
 }
 
+// Each pass streams every active limb in and out once: 16 bytes per coefficient.
 void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s) {
   if (nlimbs <= 0) return;
   int active = 0;
   for (int k = 0; k < nlimbs; k++) active += map.idx[k % map.n] >= 0;
-  ProfScope ps("ntt", s, 16.0 * active * T.N);
-  if (ntt_register_blocked(T, data, nlimbs, map, inverse, s)) return;
+  const double pass_bytes = 16.0 * active * T.N;
+  if (ntt_register_blocked(T, data, nlimbs, map, inverse, pass_bytes, s)) return;
   NttShape sh = ntt_shape(T.logN);
   dim3 gc(sh.T1 / sh.C, nlimbs), gr(sh.R / sh.K, nlimbs);
   if (!inverse) {
-    hipLaunchKernelGGL(k_ntt_cols, gc, dim3(TPB), 0, s, data, map, sh.logN, sh.R, sh.T1, sh.C, 0, T.psi,
-                       T.psi_sh, T.mc);
+    {
+      ProfScope ps("ntt_fwd_cols", s, pass_bytes);
+      hipLaunchKernelGGL(k_ntt_cols, gc, dim3(TPB), 0, s, data, map, sh.logN, sh.R, sh.T1, sh.C, 0, T.psi,
+                         T.psi_sh, T.mc);
+    }
+    ProfScope ps("ntt_fwd_rows", s, pass_bytes);
     hipLaunchKernelGGL(k_ntt_rows, gr, dim3(TPB), 0, s, data, map, sh.logN, sh.s1, sh.T1, sh.K, 0, T.psi,
                        T.psi_sh, T.mc);
   } else {
-    hipLaunchKernelGGL(k_ntt_rows, gr, dim3(TPB), 0, s, data, map, sh.logN, sh.s1, sh.T1, sh.K, 1, T.ipsi,
-                       T.ipsi_sh, T.mc);
+    {
+      ProfScope ps("ntt_inv_rows", s, pass_bytes);
+      hipLaunchKernelGGL(k_ntt_rows, gr, dim3(TPB), 0, s, data, map, sh.logN, sh.s1, sh.T1, sh.K, 1, T.ipsi,
+                         T.ipsi_sh, T.mc);
+    }
+    ProfScope ps("ntt_inv_cols", s, pass_bytes);
     hipLaunchKernelGGL(k_ntt_cols, gc, dim3(TPB), 0, s, data, map, sh.logN, sh.R, sh.T1, sh.C, 1, T.ipsi,
                        T.ipsi_sh, T.mc);
   }
@@ -802,7 +820,7 @@ void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, 
   A.hat_t = tab.hat_t;
   A.hat_t_sh = tab.hat_t_sh;
   A.D_mod_t = tab.D_mod_t;
-  ProfScope ps("moddown", s, 8.0 * T.N * npoly * ((double)tab.ns + nq));
+  ProfScope ps("fbc_to_q", s, 8.0 * T.N * npoly * ((double)tab.ns + nq));
   dim3 grid(cdiv(T.N, TPB), nq < 8 ? nq : 8, npoly);
   hipLaunchKernelGGL(k_fbc_to_q, grid, dim3(TPB), 0, s, y, xp_coef, nq, A, T.logN, T.nmods, T.mc);
 }
@@ -820,7 +838,7 @@ __global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, co
 }
 void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u64* y, int nq, const u64* pinv,
                           int npoly, int x_stride_limbs, hipStream_t s) {
-  ProfScope ps("moddown", s, 8.0 * T.N * 3.0 * npoly * nq);
+  ProfScope ps("moddown_final", s, 8.0 * T.N * 3.0 * npoly * nq);
   dim3 grid(cdiv(T.N, TPB), nq, npoly);
   hipLaunchKernelGGL(k_moddown_final, grid, dim3(TPB), 0, s, out, x, y, nq, pinv, x_stride_limbs, T.logN, T.mc);
 }
@@ -928,7 +946,7 @@ __global__ void k_rescale_lift(u64* t, const u64* top, int l, int logN, const Mo
   t[((size_t)p * l + k) * N + i] = v;
 }
 void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int npoly, hipStream_t s) {
-  ProfScope ps("rescale", s, 8.0 * T.N * npoly * (1.0 + l));
+  ProfScope ps("rescale_lift", s, 8.0 * T.N * npoly * (1.0 + l));
   dim3 grid(cdiv(T.N, TPB), l, npoly);
   hipLaunchKernelGGL(k_rescale_lift, grid, dim3(TPB), 0, s, t, top_coef, l, T.logN, T.mc);
 }
@@ -944,7 +962,7 @@ __global__ void k_rescale_final(u64* out, const u64* x, const u64* t, int l, int
 }
 void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u64* t, int l, int npoly,
                           int x_stride_limbs, const u64* qlinv, hipStream_t s) {
-  ProfScope ps("rescale", s, 8.0 * T.N * npoly * 3.0 * l);
+  ProfScope ps("rescale_final", s, 8.0 * T.N * npoly * 3.0 * l);
   dim3 grid(cdiv(T.N, TPB), l, npoly);
   hipLaunchKernelGGL(k_rescale_final, grid, dim3(TPB), 0, s, out, x, t, l, x_stride_limbs, qlinv, T.logN, T.mc);
 }

@@ -1,5 +1,6 @@
 // Host runtime declarations (internal).
 #pragma once
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -129,6 +130,7 @@ struct HeCtxImpl {
 };
 
 struct he_ctx {
+  mutable std::recursive_mutex mu;
   HeCtxImpl impl;
 };
 struct he_ct {

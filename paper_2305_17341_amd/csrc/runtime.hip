@@ -158,9 +158,10 @@ LimbMap HeCtxImpl::one(int mod) const {
 }
 u64 HeCtxImpl::galois(long step) const {
   long S = (long)(N / 2);
-  long r = ((step % S) + S) % S;
-  u64 g = 1;
-  for (long i = 0; i < r; i++) g = (g * 5) % (2 * N);
+  u64 r = (u64)(((step % S) + S) % S);
+  u64 g = 1, b = 5;
+  for (; r; r >>= 1, b = (b * b) % (2 * N))   // 5^r mod 2N, 2N <= 2^17
+    if (r & 1) g = (g * b) % (2 * N);
   return g;
 }
 u64* HeCtxImpl::table_upload(const void* host, size_t bytes) {

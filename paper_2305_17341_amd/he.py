@@ -24,7 +24,7 @@ EXPORTS = [
     "he_transpose_rot_steps", "he_encode", "he_encrypt_slots", "he_encrypt_matrix", "he_decrypt", "he_ct_info",
     "he_ct_export", "he_ct_import", "he_ct_free", "he_add", "he_sub", "he_mult", "he_rescale", "he_rotate",
     "he_drop_level", "he_pmult_slots", "he_lintrans", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
-    "he_mem_info", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
+    "he_mem_info", "he_trim", "he_device_memory", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
     "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_last_error",
 ]
 
@@ -94,6 +94,8 @@ def load():
                           C.POINTER(he_matmul_opts), C.POINTER(vp)],
         "he_sync": [vp],
         "he_mem_info": [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
+        "he_trim": [vp],
+        "he_device_memory": [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
         "he_ntt_limbs": [vp, u64p, u64p, C.c_size_t, C.POINTER(C.c_int32), C.c_int],
         "he_automorph_limbs": [vp, u64p, u64p, C.c_size_t, C.c_uint64],
         "he_hoisted_rotate_export": [vp, vp, C.c_int32, u64p, C.c_size_t],
@@ -295,6 +297,9 @@ class Context:
         _check(load().he_mem_info(self.ptr, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
+    def trim(self):
+        _check(load().he_trim(self.ptr))
+
     def last_op_ms(self):
         ms = C.c_double()
         _check(load().he_last_op_ms(self.ptr, C.byref(ms)))
@@ -344,6 +349,13 @@ def lintrans_rot_steps(kind, d, n1, nprime=0):
     buf = (C.c_int32 * 8192)()
     _check(load().he_lintrans_rot_steps(k, d, n1, nprime, buf, 8192, C.byref(n)))
     return [int(buf[i]) for i in range(n.value)]
+
+
+def device_memory():
+    """(free, total) bytes of the current device"""
+    a, b = C.c_size_t(), C.c_size_t()
+    _check(load().he_device_memory(C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def chain_context(chain, seed=1) -> Context:

@@ -1,0 +1,432 @@
+"""Serving layer: continuous batching of homomorphic matrix products and
+covariance jobs over device-resident keys and ciphertexts.
+
+Model (the client/cloud split of the paper's experimental section): clients
+encrypt their matrices and hand the ciphertexts to the server; the server
+keeps one context per ring dimension N (keys, plaintext diagonals and the
+submitted ciphertexts stay in HBM) and returns result ciphertexts.
+
+Scheduling
+  * Admission by HBM footprint: every request carries the working-set bytes
+    its computation will allocate (`product_footprint`,
+    `covariance_footprint`).  Requests are admitted strictly in arrival
+    order while the admitted footprints fit the budget; a request larger
+    than the whole budget is rejected at submission.
+  * Continuous batching: one worker per context.  Whenever a worker is free
+    it takes the oldest admitted request of its N together with every other
+    admitted product of the same d (up to `max_batch`) and runs them as one
+    stacked batch, so requests that arrived while earlier work was on the
+    device join the next launch sequence.  Workers of different N run
+    concurrently, each on its context's stream, so their kernels overlap on
+    the GPU.  Memory freed by a finished batch admits waiting requests.
+  * The batched path gives the same residues as running a product alone, so
+    a result does not depend on what it was batched with.
+
+Latency is measured per request from submission to the host seeing its
+batch complete; `Server.stats()` reports p50/p99 latency and jobs/s.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+
+BATCHED = 1  # HE_MM_BATCHED
+POOL_SLACK = 1.25  # a cached device block is reused for requests down to 1/1.25 of its size
+
+
+class AdmissionError(RuntimeError):
+    pass
+
+
+def default_n1(d: int) -> int:
+    return 1 << ((max(d - 1, 1).bit_length() + 1) // 2)
+
+
+def _qp(level: int, alpha: int) -> int:
+    return level + 1 + alpha
+
+
+def _beta(level: int, alpha: int) -> int:
+    return -(-(level + 1) // alpha)
+
+
+def product_footprint(log_n: int, top_level: int, alpha: int, d: int, batch: int = 1) -> int:
+    """Upper bound on the device bytes one d x d product (inputs at
+    `top_level`, no decomposition) allocates beyond what is resident, times
+    `batch` stacked members: the n column-shifted A_k (level l-2) and the n
+    row-shifted B_k (level l-1) held together before the products, plus the
+    largest transient of a linear transform (n1 baby-step rotations in
+    R_{Q_l P}, the digits of one decomposition and a few accumulators), plus
+    stacked copies of the inputs and the output."""
+    l = top_level
+    n1 = default_n1(d)
+    sides = d * 2 * (l - 1) + d * 2 * l
+    trans = 2 * (n1 + 4) * _qp(l, alpha) + _beta(l, alpha) * _qp(l, alpha) + 6 * (l + 1)
+    io = 4 * (l + 1) + 2 * (l - 2)
+    words = batch * (sides + trans + io) << log_n
+    return int(math.ceil(words * 8 * POOL_SLACK))
+
+
+def covariance_footprint(log_n: int, top_level: int, alpha: int, d: int, k: int) -> int:
+    """Upper bound for the block covariance of k feature blocks: per row
+    block the A and B sides of all k blocks are held (one-to-many reuse),
+    plus the k^2 accumulators and one product's transient."""
+    l = top_level
+    n1 = default_n1(d)
+    sides = 2 * k * d * 2 * l
+    acc = k * k * 2 * l
+    trans = 2 * (n1 + 4) * _qp(l, alpha) + _beta(l, alpha) * _qp(l, alpha) + 8 * (l + 1)
+    words = (sides + acc + trans) << log_n
+    return int(math.ceil(words * 8 * POOL_SLACK))
+
+
+@dataclass
+class Request:
+    kind: str                       # "matmul" | "covariance"
+    log_n: int
+    d: int
+    args: tuple                     # (a, b) or (blocks, row_blocks, k, n_samples)
+    id: int = 0
+    footprint: int = 0
+    t_submit: float = 0.0
+    t_admit: float = 0.0
+    t_start: float = 0.0
+    t_done: float = 0.0
+    batch: int = 0
+    future: Future = field(default_factory=Future)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_submit
+
+
+class HeBackend:
+    """One context per ring dimension, keys for every served product size."""
+
+    def __init__(self, chains, ds_by_log_n, seed=1, covariance_d=()):
+        from . import he
+        self.contexts = {}
+        self.chains = {}
+        for chain in chains:
+            ctx = he.chain_context(chain, seed=seed)
+            steps = set()
+            for d in ds_by_log_n.get(chain.log_n, ()):
+                steps |= set(ctx.matmul_rot_steps(d))
+            if chain.log_n in dict(covariance_d):
+                steps |= set(ctx.transpose_rot_steps(dict(covariance_d)[chain.log_n]))
+            ctx.keygen(sorted(steps))
+            self.contexts[chain.log_n] = ctx
+            self.chains[chain.log_n] = chain
+
+    def log_ns(self):
+        return sorted(self.contexts)
+
+    def footprint(self, r: Request) -> int:
+        ch = self.chains[r.log_n]
+        if r.kind == "matmul":
+            return product_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d)
+        _, rb, k, _ = r.args
+        return covariance_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d, k)
+
+    def run(self, log_n: int, reqs):
+        ctx = self.contexts[log_n]
+        if reqs[0].kind == "covariance":
+            blocks, rb, k, n_samples = reqs[0].args
+            out = [ctx.covariance(blocks, rb, k, reqs[0].d, n_samples)]
+        else:
+            out = ctx.matmul_batch([r.args[0] for r in reqs], [r.args[1] for r in reqs], [r.d for r in reqs],
+                                   opts={"flags": BATCHED})
+        ctx.sync()
+        return out
+
+    def release(self, log_n: int, keep_bytes: int):
+        """once the context is idle, give its cached device blocks back if
+        they exceed `keep_bytes` (other contexts may need the memory)"""
+        ctx = self.contexts[log_n]
+        _, cached, _ = ctx.mem_info()
+        if cached > keep_bytes:
+            ctx.trim()
+
+
+class Server:
+    def __init__(self, backend, hbm_budget: int, max_batch: int = 8, trim_when_idle: bool = True):
+        self.backend = backend
+        self.budget = int(hbm_budget)
+        self.max_batch = max_batch
+        self.trim_when_idle = trim_when_idle
+        self._cv = threading.Condition()
+        self._pending = collections.deque()
+        self._ready = {n: [] for n in backend.log_ns()}
+        self._in_use = 0
+        self._peak = 0
+        self._stop = False
+        self._next_id = 0
+        self._done = []
+        self._rejected = 0
+        self._batches = []
+        self._workers = [threading.Thread(target=self._work, args=(n,), daemon=True) for n in backend.log_ns()]
+        for w in self._workers:
+            w.start()
+
+    # -- client side --------------------------------------------------------
+    def submit(self, kind: str, log_n: int, d: int, args: tuple) -> Future:
+        if log_n not in self._ready:
+            raise ValueError(f"no context for N = 2^{log_n}")
+        r = Request(kind, log_n, d, args)
+        r.footprint = self.backend.footprint(r)
+        r.t_submit = time.perf_counter()
+        with self._cv:
+            r.id = self._next_id
+            self._next_id += 1
+            if r.footprint > self.budget:
+                self._rejected += 1
+                r.future.set_exception(AdmissionError(
+                    f"request {r.id} needs {r.footprint} B of device memory; the budget is {self.budget} B"))
+                return r.future
+            if self._stop:
+                raise RuntimeError("server is stopping")
+            self._pending.append(r)
+            self._admit()
+            self._cv.notify_all()
+        return r.future
+
+    def close(self):
+        with self._cv:
+            self._stop = True
+            self._cv.notify_all()
+        for w in self._workers:
+            w.join()
+
+    def stats(self) -> dict:
+        with self._cv:
+            done = list(self._done)
+            batches = list(self._batches)
+            peak, rejected = self._peak, self._rejected
+        if not done:
+            return {"jobs": 0, "rejected": rejected}
+        lat = sorted(r.latency for r in done)
+
+        def q(p):
+            k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
+            return lat[k]
+        span = max(r.t_done for r in done) - min(r.t_submit for r in done)
+        return {
+            "jobs": len(done),
+            "rejected": rejected,
+            "jobs_per_s": len(done) / span if span > 0 else None,
+            "latency_s": {"p50": q(50), "p99": q(99), "max": lat[-1]},
+            "mean_batch": sum(batches) / len(batches),
+            "batches": len(batches),
+            "peak_admitted_bytes": peak,
+            "budget_bytes": self.budget,
+        }
+
+    # -- scheduler ------------------------------------------------------------
+    def _admit(self):
+        # strict arrival order: the head waits until it fits, nothing overtakes it
+        while self._pending and self._pending[0].footprint <= self.budget - self._in_use:
+            r = self._pending.popleft()
+            self._in_use += r.footprint
+            self._peak = max(self._peak, self._in_use)
+            r.t_admit = time.perf_counter()
+            self._ready[r.log_n].append(r)
+
+    def _take(self, log_n):
+        ready = self._ready[log_n]
+        head = ready[0]
+        if head.kind != "matmul":
+            group = [head]
+        else:
+            group = [r for r in ready if r.kind == "matmul" and r.d == head.d][: self.max_batch]
+        ids = {id(r) for r in group}
+        self._ready[log_n] = [r for r in ready if id(r) not in ids]
+        return group
+
+    def _work(self, log_n):
+        while True:
+            with self._cv:
+                while not self._ready[log_n]:
+                    if self._stop and not any(p.log_n == log_n for p in self._pending):
+                        return
+                    self._cv.wait()
+                group = self._take(log_n)
+            t0 = time.perf_counter()
+            err, out = None, None
+            try:
+                out = self.backend.run(log_n, group)
+            except Exception as e:  # delivered to every request of the batch
+                err = e
+            t1 = time.perf_counter()
+            with self._cv:
+                for r in group:
+                    self._in_use -= r.footprint
+                    r.t_start, r.t_done, r.batch = t0, t1, len(group)
+                    if err is None:
+                        self._done.append(r)
+                self._batches.append(len(group))
+                self._admit()
+                idle = not self._ready[log_n]
+                self._cv.notify_all()
+            for i, r in enumerate(group):
+                if err is None:
+                    r.future.set_result(out[i])
+                else:
+                    r.future.set_exception(err)
+            if idle and self.trim_when_idle:
+                self.backend.release(log_n, self.budget // len(self._ready))
+
+
+def valid_pairs(chains, ds=(16, 32, 64, 128)):
+    """(d, log_n) with d^2 <= N/2 (one matrix per ciphertext) and depth 3 available"""
+    out = []
+    for ch in chains:
+        for d in ds:
+            if d * d <= ch.N // 2 and ch.top_level >= 3:
+                out.append((d, ch.log_n))
+    return out
+
+
+def run_trace(server, jobs, payloads, extra=()):
+    """Submit `jobs` at their arrival times (seconds from now); `payloads[i]`
+    is (kind, log_n, d, args) of job i; `extra` lists (arrival, payload)
+    submitted alongside.  Returns the futures in submission order."""
+    events = sorted([(j.arrival, p) for j, p in zip(jobs, payloads)] + list(extra), key=lambda e: e[0])
+    t0 = time.perf_counter()
+    futs = []
+    for at, (kind, log_n, d, args) in events:
+        delay = at - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        futs.append(((kind, log_n, d, args), server.submit(kind, log_n, d, args)))
+    return futs
+
+
+def main(argv=None):
+    import json
+    print(json.dumps(serve_bench(argv)), flush=True)
+
+
+def serve_bench(argv=None):
+    """Poisson mix of products over every (d, N) pair with d in {16, 32, 64,
+    128}, N in {2^13 .. 2^16} and d^2 <= N/2, plus one block-covariance job
+    at N = 2^16; prints one JSON line with jobs/s and p50/p99 latency."""
+    import argparse
+    import sys
+
+    import numpy as np
+
+    from . import inputs as I
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=120)
+    ap.add_argument("--load", type=float, default=0.8, help="offered rate as a fraction of the one-at-a-time rate")
+    ap.add_argument("--budget-gib", type=float, default=0.0, help="0: half of the free device memory")
+    ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--no-covariance", action="store_true")
+    args = ap.parse_args(argv)
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
+    chains = [I.SMALL, I.MID, I.SERVE15, I.LARGE]
+    pairs = valid_pairs(chains)
+    ds_by = {}
+    for d, ln in pairs:
+        ds_by.setdefault(ln, []).append(d)
+    cov_n = 128
+    t0 = time.perf_counter()
+    backend = HeBackend(chains, ds_by, seed=args.seed, covariance_d=() if args.no_covariance else ((16, cov_n),))
+    log(f"[serve] contexts and keys for {len(pairs)} (d, N) pairs in {time.perf_counter() - t0:.1f} s")
+
+    # warm-up: every pair once alone (fills the plaintext caches), then its solo latency
+    solo = {}
+    for d, ln in pairs:
+        ctx = backend.contexts[ln]
+        A = I.uniform_matrix(1, d)
+        ca, cb = ctx.encrypt_matrix(A, nonce=1), ctx.encrypt_matrix(A, nonce=2)
+        for rep in range(2):
+            t = time.perf_counter()
+            r = ctx.matmul(ca, cb, d)
+            ctx.sync()
+            solo[(d, ln)] = time.perf_counter() - t
+            del r
+    one_at_a_time = len(pairs) / sum(solo.values())
+    rate = args.load * one_at_a_time
+    log(f"[serve] solo latency per pair (ms): " + ", ".join(f"d={d}/2^{ln}: {1e3 * s:.1f}"
+                                                          for (d, ln), s in sorted(solo.items())))
+
+    jobs = I.poisson_jobs(args.seed, args.jobs, rate, pairs)
+    payloads, plain = [], []
+    for j in jobs:
+        ctx = backend.contexts[j.log_n]
+        A, B = I.uniform_matrix(j.seed, j.d), I.uniform_matrix(j.seed + 1, j.d)
+        payloads.append(("matmul", j.log_n, j.d,
+                         (ctx.encrypt_matrix(A, nonce=2 * j.seed), ctx.encrypt_matrix(B, nonce=2 * j.seed + 1))))
+        plain.append(A @ B)
+    extra = []
+    if not args.no_covariance:
+        # 256 x 256 uniform[0,1] dataset, centred on the client, as 2 x 2 blocks of 128 x 128
+        X = I.centre(I.dataset(args.seed, 2 * cov_n, 2 * cov_n))
+        blk = I.blocks(X, cov_n)
+        ctx = backend.contexts[16]
+        cts = [ctx.encrypt_matrix(blk[r, c], nonce=10**6 + 2 * r + c) for r in range(2) for c in range(2)]
+        extra.append((jobs[len(jobs) // 2].arrival, ("covariance", 16, cov_n, (cts, 2, 2, X.shape[0]))))
+    ctx16 = backend.contexts[16]
+    for c in backend.contexts.values():
+        c.sync()
+
+    if args.budget_gib > 0:
+        budget = int(args.budget_gib * 2**30)
+    else:
+        from . import he
+        free, _ = he.device_memory()
+        budget = int(0.5 * free)
+    srv = Server(backend, hbm_budget=budget)
+    log(f"[serve] {len(jobs)} jobs at {rate:.2f} jobs/s offered (load {args.load} of {one_at_a_time:.2f}/s), "
+        f"budget {budget / 2**30:.1f} GiB")
+    futs = run_trace(srv, jobs, payloads, extra)
+    results = [f.result() for _, f in futs]
+    srv.close()
+    st = srv.stats()
+    log(f"[serve] done: {st['jobs']} jobs, {st['batches']} batches")
+
+    # client side: every 8th product and the covariance decrypted against FP64
+    errs = []
+    for (kind, ln, d, a), res in zip([p for p, _ in futs], results):
+        if kind == "matmul":
+            idx = next(i for i, p in enumerate(payloads) if p[3] is a)
+            if idx % 8 == 0:
+                got = backend.contexts[ln].decrypt(res, d * d)
+                errs.append(float(np.max(np.abs(got - plain[idx].ravel()))))
+        else:
+            X = I.centre(I.dataset(args.seed, 2 * cov_n, 2 * cov_n))
+            ref = X.T @ X / X.shape[0]
+            for i, c in enumerate(res):
+                a_, b_ = divmod(i, 2)
+                got = ctx16.decrypt(c, cov_n * cov_n).reshape(cov_n, cov_n)
+                errs.append(float(np.max(np.abs(got - ref[a_ * cov_n:(a_ + 1) * cov_n, b_ * cov_n:(b_ + 1) * cov_n]))))
+    out = {
+        "metric": "served HE jobs/s and latency percentiles (Poisson mix of d x d products over 14 (d, N) pairs"
+                  + ("" if args.no_covariance else " + one 256x256 block covariance") + ")",
+        "jobs_per_s": st["jobs_per_s"],
+        "latency_ms": {k2: 1e3 * v for k2, v in st["latency_s"].items()},
+        "offered_rate": rate,
+        "one_at_a_time_rate": one_at_a_time,
+        "mean_batch": st["mean_batch"],
+        "batches": st["batches"],
+        "jobs": st["jobs"],
+        "rejected": st["rejected"],
+        "peak_admitted_gib": st["peak_admitted_bytes"] / 2**30,
+        "budget_gib": budget / 2**30,
+        "max_abs_err_sampled": max(errs) if errs else None,
+        "solo_ms": {f"d{d}_n{ln}": round(1e3 * s, 2) for (d, ln), s in sorted(solo.items())},
+    }
+    return out
+
+
+if __name__ == "__main__":
+    main()
