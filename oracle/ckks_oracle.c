@@ -757,6 +757,22 @@ oc_ct *oc_pmult(const oc_ctx *c, const oc_ct *a, const i64 *m, double pt_scale) 
   return r;
 }
 
+/* PAdd: (c0 + m, c1) for a plaintext m given as integer coefficients at the
+ * ciphertext's scale (Appendix A, addition module). */
+oc_ct *oc_padd(const oc_ctx *c, const oc_ct *a, const i64 *m) {
+  int nl = a->nlimbs, idx[MAXMOD];
+  for (int k = 0; k < nl; k++) idx[k] = limb_mod(c, a, k);
+  u64 *mn = alloc_u64((size_t)nl * c->N);
+  poly_from_int(c, m, idx, nl, mn);
+  oc_ct *r = oc_ct_copy(c, a);
+  for (int k = 0; k < nl; k++) {
+    u64 q = c->mods[idx[k]];
+    for (u64 i = 0; i < c->N; i++) poly(c, r, 0, k)[i] = addmod(poly(c, a, 0, k)[i], mn[(size_t)k * c->N + i], q);
+  }
+  free(mn);
+  return r;
+}
+
 /* multiplication by a small integer constant (no level consumed) */
 oc_ct *oc_mul_int(const oc_ctx *c, const oc_ct *a, i64 k) {
   oc_ct *r = ct_new(c, a->level, a->qp, a->scale);

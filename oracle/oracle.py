@@ -91,6 +91,8 @@ def lib():
             f.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.oc_pmult.restype = C.c_void_p
         L.oc_pmult.argtypes = [C.c_void_p, C.c_void_p, i64p, C.c_double]
+        L.oc_padd.restype = C.c_void_p
+        L.oc_padd.argtypes = [C.c_void_p, C.c_void_p, i64p]
         L.oc_mul_int.restype = C.c_void_p
         L.oc_mul_int.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.oc_tensor.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, u64p]
@@ -314,6 +316,10 @@ class Oracle:
     def pmult(self, a, m, pt_scale):
         m = np.ascontiguousarray(m, dtype=np.int64)
         return Ct(self, lib().oc_pmult(self.ptr, a.ptr, m.ctypes.data_as(i64p), pt_scale))
+
+    def padd(self, a, m):
+        m = np.ascontiguousarray(m, dtype=np.int64)
+        return Ct(self, lib().oc_padd(self.ptr, a.ptr, m.ctypes.data_as(i64p)))
 
     def mul_int(self, a, k):
         return Ct(self, lib().oc_mul_int(self.ptr, a.ptr, int(k)))
