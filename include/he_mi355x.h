@@ -174,6 +174,58 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
 he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks, uint32_t k, uint32_t d,
                         uint64_t n_samples, const he_matmul_opts* opts, he_ct** cov);
 
+/* ------------------------------------------------------------------------
+ * PowerMethod (section 6.1; Algorithms Aggregate, TaylorInit,
+ * IterativeInvSRTbyNewton, AxisFlipping, HPowerMethod, HEigenShift).
+ *
+ * A replicated vector of t = k d components is k ciphertexts of d x d
+ * blocks: axis 0 = every row of block i holds segment i (a row vector),
+ * axis 1 = every column does (a column vector).  cov[r*k + c] is block
+ * (row block r, column block c) of the symmetric t x t covariance (the
+ * layout he_covariance returns).  d is a power of two; the rotation keys of
+ * he_power_rot_steps(d) must exist.
+ * ------------------------------------------------------------------------ */
+
+/* Interactive refresh (client side, needs the secret key): ct is replaced in
+ * place by a fresh encryption at the top level, with the nominal scale Delta,
+ * of its message: the centred residue m mod q_0 of the decryption (exact
+ * while |m| < q_0/2), re-scaled exactly to m' = round(m Delta / scale)
+ * (halves away from zero).  Randomness from (context seed, nonce). */
+he_status he_refresh(he_ctx* ctx, he_ct* ct, uint64_t nonce);
+
+/* Called by the library when an operand sits at level 0; must replace *ct in
+ * place by a ciphertext with levels left (he_refresh does) and return HE_OK. */
+typedef he_status (*he_refresh_fn)(he_ct* ct, void* user);
+
+/* Rotation steps of Aggregate for d x d blocks: +-2^j and d 2^j, 2^j < d. */
+he_status he_power_rot_steps(uint32_t d, int32_t* steps, size_t cap, size_t* n);
+
+/* One round of HPowerMethod on the replicated vector v[k] in `axis` form:
+ *   y = Cov v (block products, Aggregate along the other axis), x = <y, y>;
+ *   last == 0: v_out = y * Newton_{newton_iters}(T(x), x) in the flipped
+ *              form, with T the order-1 Taylor expansion of x^-1/2 at
+ *              taylor_x0 (taylor_order must be 1) and the Newton step
+ *              y <- y (3 - x y^2) / 2 (Lazy Normalization: the caller picks
+ *              newton_iters per round);
+ *   last != 0: lambda_out = <y, v> (eigenvalue, every slot) and vt_out[k] =
+ *              v flipped to the other axis (AxisFlipping); v stays the result.
+ * *axis_out receives the form of v_out (last: of v).  Operands at level 0
+ * are handed to `refresh` (NULL: HE_ENEEDREFRESH), which may thus replace
+ * entries of cov and v in place.  Outputs are new ciphertexts owned by the
+ * caller. */
+he_status he_power_step(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, he_ct* const* v, uint32_t axis,
+                        uint32_t newton_iters, double taylor_x0, uint32_t taylor_order, int last,
+                        he_refresh_fn refresh, void* user, he_ct** v_out, uint32_t* axis_out, he_ct** lambda_out,
+                        he_ct** vt_out);
+
+/* HEigenShift: cov_out[r*k + c] = cov[r*k + c] - lambda (v v^T)_(r,c), with v
+ * in `axis` form and vt its flip (as the last power step returns them).
+ * Each covariance block is first taken to the level and scale of the
+ * subtracted term (drop, multiplication by the constant 1 encoded at the
+ * scale ratio, rescale).  Same refresh rule as he_power_step. */
+he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, he_ct* lambda, he_ct* const* v,
+                         he_ct* const* vt, uint32_t axis, he_refresh_fn refresh, void* user, he_ct** cov_out);
+
 /* wait for all work of the context */
 he_status he_sync(he_ctx* ctx);
 /* device bytes held by the context (live, cached, peak) */

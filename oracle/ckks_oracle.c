@@ -1207,10 +1207,13 @@ void oc_counts_get(int *out5) {
 /* U m via double-hoisted BSGS with indices a (n1 i + j), j in [0, n1),
  * i in [i_lo, i_hi); diagonals encoded at scale pt_scale; one Rescale. */
 static oc_ct *lintrans(const oc_ctx *c, const oc_ct *x, const lt_perm *U, i64 a, int n1, int i_lo,
-                       int i_hi, double pt_scale, int *err) {
+                       int i_hi, int *err) {
   u64 N = c->N;
   int level = x->level;
   if (level < 1) { *err = -2; return NULL; }
+  /* diagonals encoded at scale q_l: the closing rescale by q_l gives back
+   * exactly the input scale */
+  double pt_scale = (double)c->mods[level];
   /* Decompose once; baby-step hoisted rotations HR(x, a j), j in [0, n1) */
   u64 *dig = oc_decompose(c, poly(c, x, 1, 0), level);
   g_counts.decompose++;
@@ -1263,6 +1266,7 @@ static oc_ct *lintrans(const oc_ctx *c, const oc_ct *x, const lt_perm *U, i64 a,
   oc_ct *r = oc_rescale(c, md);
   g_counts.rescale++;
   oc_ct_free(md);
+  if (r) r->scale = x->scale;
   for (int j = 0; j < n1; j++) oc_ct_free(baby[j]);
   free(baby); free(vec); free(m); free(dig); free(used);
   return r;
@@ -1313,7 +1317,7 @@ oc_ct *oc_lt_sigma(const oc_ctx *c, const oc_ct *x, int n, int n1, int *err) {
   int *p = perm_sigma(n);
   lt_perm U = {n * n, p, NULL};
   int n2 = ceil_div(n, n1);
-  oc_ct *r = lintrans(c, x, &U, 1, n1, -n2, n2, c->delta, err);
+  oc_ct *r = lintrans(c, x, &U, 1, n1, -n2, n2, err);
   free(p);
   return r;
 }
@@ -1322,7 +1326,7 @@ oc_ct *oc_lt_tau(const oc_ctx *c, const oc_ct *x, int n, int n1, int *err) {
   int *p = perm_tau(n);
   lt_perm U = {n * n, p, NULL};
   int n2 = ceil_div(n, n1);
-  oc_ct *r = lintrans(c, x, &U, n, n1, 0, n2, c->delta, err);
+  oc_ct *r = lintrans(c, x, &U, n, n1, 0, n2, err);
   free(p);
   return r;
 }
@@ -1336,7 +1340,7 @@ oc_ct *oc_lt_transpose(const oc_ctx *c, const oc_ct *x, int n, int n1, double we
   }
   lt_perm U = {n * n, p, w};
   int n2 = ceil_div(n, n1);
-  oc_ct *r = lintrans(c, x, &U, n - 1, n1, -n2, n2, c->delta, err);
+  oc_ct *r = lintrans(c, x, &U, n - 1, n1, -n2, n2, err);
   free(p); free(w);
   return r;
 }
@@ -1444,7 +1448,7 @@ static oc_ct *apply_chain(const oc_ctx *c, const oc_ct *x, const oc_factor *f, i
   oc_ct *cur = oc_ct_copy(c, x);
   for (int j = 0; j < nf && cur; j++) {
     lt_perm U = {f[j].n2, f[j].perm, NULL};
-    oc_ct *nx = lintrans(c, cur, &U, f[j].a, f[j].n1, f[j].i_lo, f[j].i_hi, c->delta, err);
+    oc_ct *nx = lintrans(c, cur, &U, f[j].a, f[j].n1, f[j].i_lo, f[j].i_hi, err);
     oc_ct_free(cur);
     cur = nx;
   }
@@ -1518,21 +1522,24 @@ static oc_ct **side_a(const oc_ctx *c, const oc_ct *ca, int n, int n1z, int npz,
     for (int r = 0; r < n1z && b * n1z + r < n; r++) {
       int k = b * n1z + r;
       u64 g = oc_galois_of_step(c, r);
-      oc_ct *acc = ct_new(c, lvl, 1, Bb->scale * c->delta);
+      /* masks encoded at scale q_lvl: the rescale restores Bb's scale */
+      double ql = (double)c->mods[lvl];
+      oc_ct *acc = ct_new(c, lvl, 1, Bb->scale * ql);
       oc_ct *h = hoisted_rot(c, Bb, d1, g, err);
       col_mask(n, k, 0, vec);
-      pt_int(c, vec, n2sq, c->delta, m);
+      pt_int(c, vec, n2sq, ql, m);
       qp_pmult_acc(c, acc, h, m);
       oc_ct_free(h);
       if (k > 0) {
         h = hoisted_rot(c, Bpb, d2, g, err);
         col_mask(n, k, 1, vec);
-        pt_int(c, vec, n2sq, c->delta, m);
+        pt_int(c, vec, n2sq, ql, m);
         qp_pmult_acc(c, acc, h, m);
         oc_ct_free(h);
       }
       oc_ct *md = oc_moddown(c, acc);
       Ak[k] = oc_rescale(c, md);
+      if (Ak[k]) Ak[k]->scale = Bb->scale;
       oc_ct_free(md);
       oc_ct_free(acc);
     }

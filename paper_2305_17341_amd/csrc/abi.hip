@@ -404,6 +404,107 @@ he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks,
   });
 }
 
+// ---------------------------------------------------------------------------
+// PowerMethod (section 6.1) and the interactive refresh
+// ---------------------------------------------------------------------------
+he_status he_refresh(he_ctx* ctx, he_ct* ct, uint64_t nonce) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    check_ct(ctx, ct);
+    ct->ct = ctx->impl.refresh(ct->ct, nonce);
+  });
+}
+
+he_status he_power_rot_steps(uint32_t d, int32_t* steps, size_t cap, size_t* n) {
+  return guard_host([&] {
+    need(d >= 2 && (d & (d - 1)) == 0 && n != nullptr, "d must be a power of two");
+    std::set<long> s;
+    for (long i = 1; i < (long)d; i <<= 1) {
+      s.insert(i);
+      s.insert(-i);
+      s.insert(i * (long)d);
+    }
+    *n = s.size();
+    size_t i = 0;
+    for (long v : s) {
+      if (i < cap) steps[i] = (int32_t)v;
+      i++;
+    }
+  });
+}
+
+namespace {
+RefreshFn make_refresh(he_ctx* ctx, he_refresh_fn fn, void* user) {
+  return [ctx, fn, user](HeCt& x) {
+    if (!fn) fail(HE_ENEEDREFRESH, "a ciphertext ran out of levels and no refresh callback was given");
+    he_ct tmp;
+    tmp.ctx = ctx;
+    tmp.ct = std::move(x);
+    he_status st = fn(&tmp, user);
+    x = std::move(tmp.ct);
+    if (st != HE_OK) fail(st, "refresh callback failed");
+    if (x.level < 1) fail(HE_ENEEDREFRESH, "refresh callback left the ciphertext without levels");
+  };
+}
+}  // namespace
+
+he_status he_power_step(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, he_ct* const* v, uint32_t axis,
+                        uint32_t newton_iters, double taylor_x0, uint32_t taylor_order, int last,
+                        he_refresh_fn refresh, void* user, he_ct** v_out, uint32_t* axis_out, he_ct** lambda_out,
+                        he_ct** vt_out) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    need(cov && v && axis_out && k > 0, "null argument");
+    need(taylor_order == 1, "only the order-1 TaylorInit is implemented");
+    need(taylor_x0 > 0, "Taylor point must be positive");
+    need(last ? (lambda_out && vt_out) : (v_out != nullptr), "null output");
+    std::vector<HeCt*> C, V;
+    for (uint32_t i = 0; i < k * k; i++) {
+      check_ct(ctx, cov[i]);
+      C.push_back(&cov[i]->ct);
+    }
+    for (uint32_t i = 0; i < k; i++) {
+      check_ct(ctx, v[i]);
+      V.push_back(&v[i]->ct);
+    }
+    std::vector<HeCt> vo, vto;
+    HeCt lam;
+    int ax = 0;
+    ctx->impl.power_step(C, (int)k, (int)d, V, (int)axis, (int)newton_iters, taylor_x0, last != 0,
+                         make_refresh(ctx, refresh, user), vo, ax, lam, vto);
+    *axis_out = (uint32_t)ax;
+    if (last) {
+      *lambda_out = wrap(ctx, std::move(lam));
+      for (uint32_t i = 0; i < k; i++) vt_out[i] = wrap(ctx, std::move(vto[i]));
+    } else {
+      for (uint32_t i = 0; i < k; i++) v_out[i] = wrap(ctx, std::move(vo[i]));
+    }
+  });
+}
+
+he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, he_ct* lambda, he_ct* const* v,
+                         he_ct* const* vt, uint32_t axis, he_refresh_fn refresh, void* user, he_ct** cov_out) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    need(cov && v && vt && lambda && cov_out && k > 0 && axis <= 1, "bad arguments");
+    check_ct(ctx, lambda);
+    std::vector<HeCt*> C, V, VT;
+    for (uint32_t i = 0; i < k * k; i++) {
+      check_ct(ctx, cov[i]);
+      C.push_back(&cov[i]->ct);
+    }
+    for (uint32_t i = 0; i < k; i++) {
+      check_ct(ctx, v[i]);
+      check_ct(ctx, vt[i]);
+      V.push_back(&v[i]->ct);
+      VT.push_back(&vt[i]->ct);
+    }
+    std::vector<HeCt> out;
+    ctx->impl.eigen_shift(C, (int)k, (int)d, lambda->ct, V, VT, (int)axis, make_refresh(ctx, refresh, user), out);
+    for (uint32_t i = 0; i < k * k; i++) cov_out[i] = wrap(ctx, std::move(out[i]));
+  });
+}
+
 he_status he_sync(he_ctx* ctx) {
   return guard([&] {
     auto lk = hold(ctx);

@@ -92,6 +92,8 @@ void launch_sample_ternary(const DeviceTables& T, i64* out, u64 seed, u64 tag, u
 void launch_sample_gauss(const DeviceTables& T, i64* out, u64 seed, u64 tag, u64 c1, u64 c2, u64 c3,
                          hipStream_t s);
 void launch_add_int(i64* out, const i64* a, const i64* b, u64 N, hipStream_t s);
+// m <- round(m * mant / 2^shift) (halves away from zero), 1 <= shift < 128, |m| mant < 2^127
+void launch_scale_int(i64* m, u64 mant, int shift, u64 N, hipStream_t s);
 // switching key b part: b = e - a s (+ pmod s' on the digit's primes)
 void launch_swk_b(const DeviceTables& T, u64* b, const u64* a, const u64* e, const u64* s_ntt, const u64* sp_ntt,
                   const u64* pmod, int nlimbs_total, int digit, int alpha, int L, hipStream_t s);

@@ -1040,6 +1040,29 @@ void launch_add_int(i64* out, const i64* a, const i64* b, u64 N, hipStream_t s) 
   hipLaunchKernelGGL(k_add_int, dim3(cdiv(N, TPB)), dim3(TPB), 0, s, out, a, b, N);
 }
 
+// m <- round(m * mant / 2^shift), halves away from zero, exact (128-bit product)
+__global__ void k_scale_int(i64* m, u64 mant, int shift, u64 N) {
+  u64 i = (u64)blockIdx.x * TPB + threadIdx.x;
+  if (i >= N) return;
+  i64 v = m[i];
+  u64 a = v < 0 ? (u64)0 - (u64)v : (u64)v;
+  u64 lo = a * mant, hi = mulhi64(a, mant);
+  // + 2^(shift-1)
+  if (shift - 1 < 64) {
+    u64 add = 1ull << (shift - 1);
+    u64 l2 = lo + add;
+    hi += l2 < lo;
+    lo = l2;
+  } else {
+    hi += 1ull << (shift - 1 - 64);
+  }
+  u64 r = shift < 64 ? (lo >> shift) | (hi << (64 - shift)) : hi >> (shift - 64);
+  m[i] = v < 0 ? -(i64)r : (i64)r;
+}
+void launch_scale_int(i64* m, u64 mant, int shift, u64 N, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_int, dim3(cdiv(N, TPB)), dim3(TPB), 0, s, m, mant, shift, N);
+}
+
 // b = e - a s (+ (P mod q) s' on the primes of digit `digit`)
 __global__ void k_swk_b(u64* b, const u64* a, const u64* e, const u64* s_ntt, const u64* sp_ntt, const u64* pmod,
                         int digit, int alpha, int L, int logN, const ModConst* __restrict__ mc) {

@@ -1,0 +1,235 @@
+// The homomorphic PowerMethod round and the eigen-shift (section 6.1:
+// covariance transformation on replicated vectors, Aggregate, Lazy
+// Normalization with TaylorInit and Newton InvSRT, AxisFlipping and the
+// eigenvalue; Algorithms Aggregate, TaylorInit, IterativeInvSRTbyNewton,
+// AxisFlipping, HEigenShift, HPowerMethod) and the interactive refresh.
+//
+// Conventions (readings of the paper):
+//   * cov[r*k + c] is block (row block r, column block c); the paper's
+//     Cov_i[j] is block (j, i).  Axis 0: every row of a block holds the
+//     vector segment (row vector); axis 1: every column does.
+//   * Aggregate(A; 0) adds Rot(A; i), i = n, 2n, .. < n^2 (column sums);
+//     Aggregate(A; 1) adds Rot(A; i), i = 1, 2, .. < n, keeps column 0 with
+//     a 0/1 mask (one level), then adds Rot(A; i), i = -1, -2, .. > -n.
+//   * The transformation's j-loop multiplies V[j]; axis 0 takes block (i, j),
+//     axis 1 block (j, i).
+//   * Newton: y <- y (1.5 + (-x/2) y^2), -x/2 formed once per normalisation;
+//     three products and three levels per step.  TaylorInit of order 1:
+//     T(x) = 1.5 x0^-1/2 - 0.5 x0^-3/2 x.
+//   * Constants and masks multiplied in at level l are encoded at scale q_l
+//     and rescaled; constants added are encoded at the ciphertext's scale.
+//     Product operands meet at the lower level by dropping limbs.
+//   * An operand of a product or of a plaintext multiplication that sits at
+//     level 0 is refreshed (through the caller's callback) right before it.
+//     A refresh re-encrypts at the top level at the nominal scale Delta
+//     (integer polynomial re-scaled exactly): every Newton step would
+//     otherwise triple the relative drift of the scale.
+#include <cmath>
+
+#include "runtime.h"
+
+// ---------------------------------------------------------------------------
+// refresh (client side): decrypt to the centred integer polynomial (residue
+// mod q_0, exact while |m| < q_0 / 2), m' = round(m Delta / scale) exactly,
+// encrypt m' at the top level with scale Delta
+// ---------------------------------------------------------------------------
+DevBuf HeCtxImpl::decrypt_int(const HeCt& c) {
+  if (!have_sk) fail(HE_EKEY, "keys not generated");
+  if (c.qp || c.B != 1) fail(HE_EINVAL, "decrypt takes one ciphertext over Q");
+  DevBuf t(&pool, N);
+  LimbMap m0 = one(0);
+  launch_mul(T, t.p, c.limb(1, 0), s_ntt.p, 1, m0, stream);
+  launch_add(T, t.p, t.p, c.limb(0, 0), 1, m0, stream);
+  launch_ntt(T, t.p, 1, m0, true, stream);
+  DevBuf mi(&pool, N);
+  launch_centre_to_int(T, (i64*)mi.p, t.p, 0, stream);
+  return mi;
+}
+
+HeCt HeCtxImpl::refresh(const HeCt& c, u64 nonce) {
+  DevBuf m = decrypt_int(c);
+  const double r = delta / c.scale;
+  int e = 0;
+  const double f = std::frexp(r, &e);            // r = f 2^e, f in [1/2, 1)
+  const u64 mant = (u64)std::ldexp(f, 53);       // exact: r = mant 2^(e - 53)
+  const int shift = 53 - e;
+  if (shift < 1 || shift > 120) fail(HE_ESCALE, "scale too far from the nominal one to refresh");
+  launch_scale_int((i64*)m.p, mant, shift, N, stream);
+  return encrypt_int((const i64*)m.p, L, delta, nonce);
+}
+
+HeCt HeCtxImpl::padd_int(const HeCt& a, const i64* m_dev) {
+  if (a.qp || a.B != 1) fail(HE_EINVAL, "plaintext addition takes one ciphertext over Q");
+  LimbMap m = qmap(a.level + 1);
+  DevBuf pt(&pool, (size_t)a.nlimbs * N);
+  int_to_ntt(pt.p, m_dev, m);
+  HeCt c = ct_copy(a);
+  launch_add(T, c.poly(0), a.poly(0), pt.p, a.nlimbs, m, stream);
+  return c;
+}
+
+namespace {
+struct Circuit {
+  HeCtxImpl& c;
+  int n;
+  const RefreshFn& refresh;
+
+  DevBuf const_pt(double v, double scale) {
+    std::vector<double> z((size_t)n * n, v);
+    return c.encode_batch(z.data(), n * n, 1, scale);
+  }
+  DevBuf mask_pt(bool col0, double scale) {
+    std::vector<double> z((size_t)n * n, 0.0);
+    for (int i = 0; i < n; i++) z[(size_t)i * n + (col0 ? 0 : i)] = 1.0;
+    return c.encode_batch(z.data(), n * n, 1, scale);
+  }
+  void ready(HeCt& x) {
+    if (x.level < 1) refresh(x);
+  }
+  // Mult with relinearisation, then Rescale
+  HeCt mul(HeCt& A, HeCt& B) {
+    ready(A);
+    if (&A != &B) ready(B);
+    const int lv = std::min(A.level, B.level);
+    HeCt a2, b2;
+    const HeCt* pa = &A;
+    const HeCt* pb = &B;
+    if (A.level != lv) { a2 = c.drop(A, lv); pa = &a2; }
+    if (B.level != lv) { b2 = c.drop(B, lv); pb = &b2; }
+    HeCt t = c.mult(*pa, *pb);
+    return c.rescale(t);
+  }
+  HeCt pmul_pt(HeCt& A, bool is_mask, bool col0, double v) {
+    ready(A);
+    const double ql = (double)c.mods[A.level];
+    DevBuf pt = is_mask ? mask_pt(col0, ql) : const_pt(v, ql);
+    HeCt t = c.pmult_int(A, (const i64*)pt.p, ql);
+    return c.rescale(t);
+  }
+  HeCt pmul_const(HeCt& A, double v) { return pmul_pt(A, false, false, v); }
+  HeCt pmul_mask(HeCt& A, bool col0) { return pmul_pt(A, true, col0, 0.0); }
+  HeCt padd_const(const HeCt& a, double v) {
+    DevBuf pt = const_pt(v, a.scale);
+    return c.padd_int(a, (const i64*)pt.p);
+  }
+  HeCt add(const HeCt& a, const HeCt& b) {
+    const int lv = std::min(a.level, b.level);
+    HeCt a2, b2;
+    const HeCt* pa = &a;
+    const HeCt* pb = &b;
+    if (a.level != lv) { a2 = c.drop(a, lv); pa = &a2; }
+    if (b.level != lv) { b2 = c.drop(b, lv); pb = &b2; }
+    return c.add(*pa, *pb, false);
+  }
+  HeCt aggregate(HeCt A, int axis) {
+    if (axis == 0) {
+      for (long i = n; i < (long)n * n; i <<= 1) A = c.add(A, c.rotate(A, i), false);
+      return A;
+    }
+    for (long i = 1; i < n; i <<= 1) A = c.add(A, c.rotate(A, i), false);
+    A = pmul_mask(A, true);
+    for (long i = -1; i > -n; i *= 2) A = c.add(A, c.rotate(A, i), false);
+    return A;
+  }
+  HeCt axis_flip(HeCt& V, int axis) { return aggregate(pmul_mask(V, false), 1 - axis); }
+  HeCt taylor(HeCt& X, double x0) {
+    const double c1 = -0.5 * std::pow(x0, -1.5), c0 = 1.5 * std::pow(x0, -0.5);
+    return padd_const(pmul_const(X, c1), c0);
+  }
+  HeCt newton(HeCt& X, HeCt Y, int tau) {
+    if (tau == 0) return Y;
+    HeCt Xh = pmul_const(X, -0.5);
+    for (int it = 0; it < tau; it++) {
+      HeCt Y2 = mul(Y, Y);
+      HeCt P = mul(Y2, Xh);
+      HeCt W = padd_const(P, 1.5);
+      Y = mul(Y, W);
+    }
+    return Y;
+  }
+  // x at a higher level brought to (level, scale)
+  HeCt match(const HeCt& x, int level, double scale) {
+    if (x.level <= level) fail(HE_ELEVEL, "scale matching needs a higher level");
+    HeCt d;
+    const HeCt* px = &x;
+    if (x.level > level + 1) { d = c.drop(x, level + 1); px = &d; }
+    const double q = (double)c.mods[level + 1];
+    const double p = scale * q / px->scale;
+    DevBuf one = const_pt(1.0, p);
+    HeCt t = c.pmult_int(*px, (const i64*)one.p, p);
+    HeCt r = c.rescale(t);
+    r.scale = scale;
+    return r;
+  }
+  HeCt sub_matched(HeCt& A, const HeCt& b) {
+    if (A.scale == b.scale) {
+      const int lv = std::min(A.level, b.level);
+      HeCt a2, b2;
+      const HeCt* pa = &A;
+      const HeCt* pb = &b;
+      if (A.level != lv) { a2 = c.drop(A, lv); pa = &a2; }
+      if (b.level != lv) { b2 = c.drop(b, lv); pb = &b2; }
+      return c.add(*pa, *pb, true);
+    }
+    if (A.level <= b.level) refresh(A);
+    return c.add(match(A, b.level, b.scale), b, true);
+  }
+};
+}  // namespace
+
+void HeCtxImpl::power_step(std::vector<HeCt*>& cov, int k, int n, std::vector<HeCt*>& V, int axis, int tau,
+                           double x0, bool last, const RefreshFn& refresh_fn, std::vector<HeCt>& v_out,
+                           int& axis_out, HeCt& lambda_out, std::vector<HeCt>& vt_out) {
+  if ((int)cov.size() != k * k || (int)V.size() != k || k < 1) fail(HE_EINVAL, "block counts");
+  if ((u64)n * n > N / 2 || n < 2 || (n & (n - 1))) fail(HE_EINVAL, "block size must be a power of two, n^2 <= N/2");
+  if (axis != 0 && axis != 1) fail(HE_EINVAL, "axis must be 0 or 1");
+  Circuit C{*this, n, refresh_fn};
+  std::vector<HeCt> nv(k);
+  for (int i = 0; i < k; i++) {
+    HeCt S;
+    for (int j = 0; j < k; j++) {
+      HeCt& blk = axis == 0 ? *cov[i * k + j] : *cov[j * k + i];
+      HeCt P = C.mul(blk, *V[j]);
+      S = j == 0 ? std::move(P) : C.add(S, P);
+    }
+    nv[i] = C.aggregate(std::move(S), 1 - axis);
+  }
+  const int ax2 = 1 - axis;
+  HeCt S;
+  for (int i = 0; i < k; i++) {
+    HeCt P = C.mul(nv[i], nv[i]);
+    S = i == 0 ? std::move(P) : C.add(S, P);
+  }
+  HeCt X = C.aggregate(std::move(S), 1 - ax2);
+  if (!last) {
+    HeCt Y0 = C.taylor(X, x0);
+    HeCt Y = C.newton(X, std::move(Y0), tau);
+    v_out.clear();
+    for (int i = 0; i < k; i++) v_out.push_back(C.mul(nv[i], Y));
+    axis_out = ax2;
+    return;
+  }
+  vt_out.clear();
+  for (int i = 0; i < k; i++) vt_out.push_back(C.axis_flip(*V[i], axis));
+  HeCt S2;
+  for (int i = 0; i < k; i++) {
+    HeCt P = C.mul(nv[i], vt_out[i]);
+    S2 = i == 0 ? std::move(P) : C.add(S2, P);
+  }
+  lambda_out = C.aggregate(std::move(S2), 1 - ax2);
+  axis_out = axis;
+}
+
+void HeCtxImpl::eigen_shift(std::vector<HeCt*>& cov, int k, int n, HeCt& lambda, std::vector<HeCt*>& V,
+                            std::vector<HeCt*>& VT, int axis, const RefreshFn& refresh_fn,
+                            std::vector<HeCt>& out) {
+  if ((int)cov.size() != k * k || (int)V.size() != k || (int)VT.size() != k) fail(HE_EINVAL, "block counts");
+  Circuit C{*this, n, refresh_fn};
+  out.clear();
+  for (int r = 0; r < k; r++)
+    for (int cc = 0; cc < k; cc++) {
+      HeCt O = axis == 0 ? C.mul(*VT[r], *V[cc]) : C.mul(*V[r], *VT[cc]);
+      HeCt Tm = C.mul(lambda, O);
+      out.push_back(C.sub_matched(*cov[r * k + cc], Tm));
+    }
+}

@@ -1,5 +1,6 @@
 // Host runtime declarations (internal).
 #pragma once
+#include <functional>
 #include <mutex>
 #include <set>
 #include <string>
@@ -42,6 +43,9 @@ void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& o
 void lintrans_steps(int kind, int n, int n1, int nprime, std::set<long>& s);
 std::vector<long> matmul_steps(int n, int n1z, int n1t, int npz, int npt);
 std::vector<long> transpose_steps(int n, int n1);
+
+// replaces a ciphertext that ran out of levels by a fresh one (client side)
+using RefreshFn = std::function<void(HeCt&)>;
 
 struct HeCtxImpl {
   int logN = 0;
@@ -127,6 +131,16 @@ struct HeCtxImpl {
   void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,
                                int n1t, int n1g, int npz, int npt);
+
+  // PowerMethod (section 6.1) and the interactive refresh
+  DevBuf decrypt_int(const HeCt& c);
+  HeCt refresh(const HeCt& c, u64 nonce);
+  HeCt padd_int(const HeCt& a, const i64* m_dev);
+  void power_step(std::vector<HeCt*>& cov, int k, int n, std::vector<HeCt*>& V, int axis, int tau, double x0,
+                  bool last, const RefreshFn& refresh_fn, std::vector<HeCt>& v_out, int& axis_out,
+                  HeCt& lambda_out, std::vector<HeCt>& vt_out);
+  void eigen_shift(std::vector<HeCt*>& cov, int k, int n, HeCt& lambda, std::vector<HeCt*>& V,
+                   std::vector<HeCt*>& VT, int axis, const RefreshFn& refresh_fn, std::vector<HeCt>& out);
 };
 
 struct he_ctx {

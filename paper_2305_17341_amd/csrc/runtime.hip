@@ -848,7 +848,10 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
       ij.push_back({i, j});
     }
   if (ij.empty()) fail(HE_EINVAL, "transform has no nonzero diagonal");
-  std::vector<const u64*> pts = plaintexts(keys_, vecs, n2sq, level, true, delta);
+  // diagonals encoded at scale q_l: the closing rescale by q_l gives back
+  // exactly the input scale
+  const double ql = (double)mods[level];
+  std::vector<const u64*> pts = plaintexts(keys_, vecs, n2sq, level, true, ql);
   std::vector<bool> used(n1, false);
   for (auto& p : ij) used[p.second] = true;
   // Decompose once, baby-step hoisted rotations kept in R_{Q_l P}
@@ -858,7 +861,7 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
     if (used[j]) baby[j] = hoisted(x, dig.p, galois((long)G.a * j));
   dig.release();
   LimbMap qpm = qpmap(level);
-  HeCt acc = ct_new(level, true, x.scale * delta, x.B);
+  HeCt acc = ct_new(level, true, x.scale * ql, x.B);
   bool acc_set = false;
   size_t e = 0;
   for (int i = G.i_lo; i < G.i_hi; i++) {
@@ -867,7 +870,7 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
     for (; e < ij.size() && ij[e].first == i; e++) {
       int j = ij[e].second;
       if (!inner_set) {
-        inner = ct_new(level, true, x.scale * delta, x.B);
+        inner = ct_new(level, true, x.scale * ql, x.B);
         launch_mul_bcast(T, inner.d.p, baby[j].d.p, pts[e], 2 * x.B * nqp, nqp, qpm, stream);
         inner_set = true;
       } else {
@@ -891,7 +894,9 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
     }
   }
   HeCt md = moddown(acc);
-  return rescale(md);
+  HeCt r = rescale(md);
+  r.scale = x.scale;
+  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -1045,7 +1050,9 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       vecs.push_back(v);
     }
   }
-  std::vector<const u64*> masks = plaintexts(keys_, vecs, n * n, lvl, true, delta);
+  // masks encoded at scale q_lvl: each rescale restores the base's scale
+  const double ql = (double)mods[lvl];
+  std::vector<const u64*> masks = plaintexts(keys_, vecs, n * n, lvl, true, ql);
   auto mask_of = [&](int k, int second) { return masks[k == 0 ? 0 : 2 * k - 1 + second]; };
   std::vector<HeCt> Ak(n);
   HeCt Bb = ct_copy(A0), Bpb = rotate(A0, -(long)n);
@@ -1060,7 +1067,7 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
     for (int r = 0; r < n1z && b * n1z + r < n; r++) {
       int k = b * n1z + r;
       u64 g = galois(r);
-      HeCt acc = ct_new(lvl, true, Bb.scale * delta, Bb.B);
+      HeCt acc = ct_new(lvl, true, Bb.scale * ql, Bb.B);
       {
         HeCt h = hoisted(Bb, d1.p, g);
         launch_mul_bcast(T, acc.d.p, h.d.p, mask_of(k, 0), 2 * Bb.B * nqp, nqp, qpm, stream);
@@ -1071,6 +1078,7 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       }
       HeCt md = moddown(acc);
       Ak[k] = rescale(md);
+      Ak[k].scale = Bb.scale;
     }
   }
   return Ak;

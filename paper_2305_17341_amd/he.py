@@ -25,8 +25,12 @@ EXPORTS = [
     "he_ct_export", "he_ct_import", "he_ct_free", "he_add", "he_sub", "he_mult", "he_rescale", "he_rotate",
     "he_drop_level", "he_pmult_slots", "he_lintrans", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
     "he_mem_info", "he_trim", "he_device_memory", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
-    "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_last_error",
+    "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_refresh",
+    "he_power_rot_steps", "he_power_step", "he_eigen_shift", "he_last_error",
 ]
+
+# he_refresh_fn: status (he_ct*, void* user)
+REFRESH_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p)
 
 u64p = C.POINTER(C.c_uint64)
 i64p = C.POINTER(C.c_int64)
@@ -105,6 +109,13 @@ def load():
         "he_op_counts": [vp, u64p, u64p, u64p],
         "he_lintrans_rot_steps": [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32), C.c_size_t,
                                   C.POINTER(C.c_size_t)],
+        "he_refresh": [vp, vp, C.c_uint64],
+        "he_power_rot_steps": [C.c_uint32, C.POINTER(C.c_int32), C.c_size_t, C.POINTER(C.c_size_t)],
+        "he_power_step": [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.POINTER(vp), C.c_uint32, C.c_uint32,
+                          C.c_double, C.c_uint32, C.c_int, REFRESH_FN, vp, C.POINTER(vp), C.POINTER(C.c_uint32),
+                          C.POINTER(vp), C.POINTER(vp)],
+        "he_eigen_shift": [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, vp, C.POINTER(vp), C.POINTER(vp), C.c_uint32,
+                           REFRESH_FN, vp, C.POINTER(vp)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -289,6 +300,35 @@ class Context:
         _check(load().he_covariance(self.ptr, px, row_blocks, k, d, n_samples, _opts(opts), out))
         return [Ciphertext(self, vp(out[i])) for i in range(k * k)]
 
+    def refresh(self, ct, nonce):
+        """in place: ct becomes a top-level encryption of its message"""
+        _check(load().he_refresh(self.ptr, ct.ptr, nonce))
+
+    def power_step(self, cov, k, d, V, axis, tau, x0, last, refresher=None):
+        """One HPowerMethod round.  Returns (V', axis') or, for the last
+        round, (V, axis, lambda, V^T)."""
+        pc = (vp * (k * k))(*[c.ptr for c in cov])
+        pv = (vp * k)(*[x.ptr for x in V])
+        vo = (vp * k)()
+        vto = (vp * k)()
+        lam = vp()
+        ax = C.c_uint32()
+        fn = refresher.fn if refresher is not None else REFRESH_FN()
+        _check(load().he_power_step(self.ptr, pc, k, d, pv, axis, tau, x0, 1, 1 if last else 0, fn, None, vo,
+                                    C.byref(ax), C.byref(lam), vto))
+        if last:
+            return V, ax.value, Ciphertext(self, lam), [Ciphertext(self, vp(vto[i])) for i in range(k)]
+        return [Ciphertext(self, vp(vo[i])) for i in range(k)], ax.value
+
+    def eigen_shift(self, cov, k, d, lam, V, VT, axis, refresher=None):
+        pc = (vp * (k * k))(*[c.ptr for c in cov])
+        pv = (vp * k)(*[x.ptr for x in V])
+        pvt = (vp * k)(*[x.ptr for x in VT])
+        out = (vp * (k * k))()
+        fn = refresher.fn if refresher is not None else REFRESH_FN()
+        _check(load().he_eigen_shift(self.ptr, pc, k, d, lam.ptr, pv, pvt, axis, fn, None, out))
+        return [Ciphertext(self, vp(out[i])) for i in range(k * k)]
+
     def sync(self):
         _check(load().he_sync(self.ptr))
 
@@ -348,6 +388,31 @@ def lintrans_rot_steps(kind, d, n1, nprime=0):
     n = C.c_size_t()
     buf = (C.c_int32 * 8192)()
     _check(load().he_lintrans_rot_steps(k, d, n1, nprime, buf, 8192, C.byref(n)))
+    return [int(buf[i]) for i in range(n.value)]
+
+
+class Refresher:
+    """Client-side refresh for he_power_step / he_eigen_shift: re-encrypts
+    the ciphertext it is handed at the top level with the next nonce."""
+
+    def __init__(self, ctx: "Context", nonce0: int = 1 << 40):
+        self.ctx = ctx
+        self.nonce = nonce0
+        self.count = 0
+
+        def cb(ct_ptr, user):
+            st = load().he_refresh(self.ctx.ptr, ct_ptr, self.nonce)
+            self.nonce += 1
+            self.count += 1
+            return st
+
+        self.fn = REFRESH_FN(cb)
+
+
+def power_rot_steps(d):
+    n = C.c_size_t()
+    buf = (C.c_int32 * 256)()
+    _check(load().he_power_rot_steps(d, buf, 256, C.byref(n)))
     return [int(buf[i]) for i in range(n.value)]
 
 

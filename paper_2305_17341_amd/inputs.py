@@ -77,6 +77,17 @@ def planted_dataset(seed: int, s: int, t: int, decay: float = 0.7, noise: float 
     return np.clip(X, 0.0, 1.0)
 
 
+def pca_dataset(seed: int, s: int, t: int, top: float = 8.0, decay: float = 0.7) -> np.ndarray:
+    """s x t dataset in [0, 1] (pixel-like) whose covariance has a planted
+    spectrum close to top * decay^i: the leading eigenvalues stay above the
+    contraction coefficient 0.5 the Lazy Normalization schedule assumes."""
+    g = rng(seed)
+    lam = top * decay ** np.arange(t)
+    Q, _ = np.linalg.qr(g.standard_normal((t, t)))
+    Z = (g.standard_normal((s, t)) * np.sqrt(lam)) @ Q.T
+    return np.clip(0.5 + Z, 0.0, 1.0)
+
+
 def centre(X: np.ndarray) -> np.ndarray:
     return X - X.mean(axis=0, keepdims=True)
 
