@@ -1601,14 +1601,35 @@ static oc_ct *accumulate(const oc_ctx *c, oc_ct *acc, oc_ct **Ak, oc_ct **Bk, in
   return acc;
 }
 
+/* Lazy relinearisation (a variant, not the paper's order): the tensors of
+ * all products are summed in three components and relinearised once.
+ * acc3 = u64[3][l+1][N] running sum (NULL: start a new one). */
+static u64 *accumulate_tensors(const oc_ctx *c, u64 *acc3, oc_ct **Ak, oc_ct **Bk, int n) {
+  int nq = Ak[0]->nlimbs;
+  size_t words = (size_t)3 * nq * c->N;
+  u64 *t3 = alloc_u64(words);
+  if (!acc3) acc3 = alloc_u64(words);  /* zeroed */
+  for (int k = 0; k < n; k++) {
+    oc_tensor(c, Ak[k], Bk[k], t3);
+    for (int p = 0; p < 3; p++)
+      for (int l = 0; l < nq; l++) {
+        u64 q = c->mods[l];
+        u64 *a = acc3 + ((size_t)p * nq + l) * c->N, *t = t3 + ((size_t)p * nq + l) * c->N;
+        for (u64 i = 0; i < c->N; i++) a[i] = addmod(a[i], t[i], q);
+      }
+  }
+  free(t3);
+  return acc3;
+}
+
 static void free_list(oc_ct **l, int n) {
   if (!l) return;
   for (int k = 0; k < n; k++) oc_ct_free(l[k]);
   free(l);
 }
 
-oc_ct *oc_matmul_ex(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int npz, int npt,
-                    int *err) {
+oc_ct *oc_matmul_lazy(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int npz,
+                      int npt, int lazy, int *err) {
   *err = 0;
   if (ca->qp || cb->qp || ca->level != cb->level) { *err = -2; return NULL; }
   if ((u64)n * n > c->N / 2 || n % n1z || n % n1t || npz < 1 || npt < 1) { *err = -1; return NULL; }
@@ -1618,11 +1639,23 @@ oc_ct *oc_matmul_ex(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, in
   if (!Bk) { free_list(Ak, n); return NULL; }
   align_sides(c, Ak, Bk, n);
   if (Ak[0]->level < 1) { *err = -2; free_list(Ak, n); free_list(Bk, n); return NULL; }
-  oc_ct *acc = accumulate(c, NULL, Ak, Bk, n);
+  oc_ct *acc;
+  if (lazy) {
+    u64 *acc3 = accumulate_tensors(c, NULL, Ak, Bk, n);
+    acc = oc_relin(c, acc3, Ak[0]->level, Ak[0]->scale * Bk[0]->scale);
+    free(acc3);
+  } else {
+    acc = accumulate(c, NULL, Ak, Bk, n);
+  }
   oc_ct *out = oc_rescale(c, acc);
   oc_ct_free(acc);
   free_list(Ak, n); free_list(Bk, n);
   return out;
+}
+
+oc_ct *oc_matmul_ex(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int npz, int npt,
+                    int *err) {
+  return oc_matmul_lazy(c, ca, cb, n, n1z, n1t, npz, npt, 0, err);
 }
 
 oc_ct *oc_matmul(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int *err) {
@@ -1636,11 +1669,14 @@ oc_ct *oc_matmul(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n
 /* A from G(x[r k + a]) scaled by 1/s and B from x[r k + b]; blocks a < b    */
 /* are G of block (b, a); every block ends at one level.                     */
 /* ------------------------------------------------------------------------ */
-int oc_covariance(const oc_ctx *c, oc_ct *const *x, int rb, int k, int n, u64 n_samples, int n1z, int n1t, int npz,
-                  int npt, int n1g, oc_ct **out) {
+int oc_covariance_lazy(const oc_ctx *c, oc_ct *const *x, int rb, int k, int n, u64 n_samples, int n1z, int n1t,
+                       int npz, int npt, int n1g, int lazy, oc_ct **out) {
   int err = 0;
   int level = x[0]->level;
   oc_ct **acc = (oc_ct **)calloc(k * k, sizeof(oc_ct *));
+  u64 **acc3 = (u64 **)calloc(k * k, sizeof(u64 *));
+  int acc_level = 0;
+  double acc_scale = 0;
   for (int r = 0; r < rb; r++) {
     oc_ct ***A = (oc_ct ***)calloc(k, sizeof(oc_ct **)), ***B = (oc_ct ***)calloc(k, sizeof(oc_ct **));
     for (int a = 0; a < k; a++) {
@@ -1658,18 +1694,28 @@ int oc_covariance(const oc_ctx *c, oc_ct *const *x, int rb, int k, int n, u64 n_
     }
     for (int a = 0; a < k; a++) align_sides(c, A[a], B[0], n);
     for (int b = 0; b < k; b++) align_sides(c, A[0], B[b], n);
+    acc_level = A[0][0]->level;
+    acc_scale = A[0][0]->scale * B[0][0]->scale;
     for (int a = 0; a < k; a++)
-      for (int b = 0; b <= a; b++) acc[a * k + b] = accumulate(c, acc[a * k + b], A[a], B[b], n);
+      for (int b = 0; b <= a; b++) {
+        if (lazy) acc3[a * k + b] = accumulate_tensors(c, acc3[a * k + b], A[a], B[b], n);
+        else acc[a * k + b] = accumulate(c, acc[a * k + b], A[a], B[b], n);
+      }
     for (int a = 0; a < k; a++) free_list(A[a], n);
     for (int b = 0; b < k; b++) free_list(B[b], n);
     free(A); free(B);
   }
   for (int a = 0; a < k; a++)
     for (int b = 0; b <= a; b++) {
+      if (lazy) {
+        acc[a * k + b] = oc_relin(c, acc3[a * k + b], acc_level, acc_scale);
+        free(acc3[a * k + b]);
+      }
       out[a * k + b] = oc_rescale(c, acc[a * k + b]);
       oc_ct_free(acc[a * k + b]);
     }
   free(acc);
+  free(acc3);
   for (int a = 0; a < k; a++)
     for (int b = a + 1; b < k; b++) {
       out[a * k + b] = oc_lt_transpose(c, out[b * k + a], n, n1g, 1.0, &err);
@@ -1685,4 +1731,9 @@ int oc_covariance(const oc_ctx *c, oc_ct *const *x, int rb, int k, int n, u64 n_
       }
   }
   return 0;
+}
+
+int oc_covariance(const oc_ctx *c, oc_ct *const *x, int rb, int k, int n, u64 n_samples, int n1z, int n1t, int npz,
+                  int npt, int n1g, oc_ct **out) {
+  return oc_covariance_lazy(c, x, rb, k, n, n_samples, n1z, n1t, npz, npt, n1g, 0, out);
 }

@@ -122,6 +122,12 @@ def lib():
         L.oc_matmul_ex.restype = C.c_void_p
         L.oc_matmul_ex.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.c_int, intp]
+        L.oc_matmul_lazy.restype = C.c_void_p
+        L.oc_matmul_lazy.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.c_int, C.c_int, intp]
+        L.oc_covariance_lazy.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_uint64,
+                                         C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(C.c_void_p)]
         L.oc_dcd_factors.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, intp, C.POINTER(C.c_longlong), C.c_int]
         L.oc_covariance.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_uint64,
                                     C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
@@ -376,17 +382,20 @@ class Oracle:
     def lt_transpose(self, a, n, n1, weight=1.0):
         return self._lt(lib().oc_lt_transpose, a.ptr, n, n1, weight)
 
-    def matmul(self, a, b, n, n1z, n1t, npz=None, npt=None):
+    def matmul(self, a, b, n, n1z, n1t, npz=None, npt=None, lazy=False):
+        """lazy: relinearise once after summing the n tensors (a variant;
+        the paper's order relinearises every product)"""
         npz = n - 1 if npz is None else npz
         npt = n - 1 if npt is None else npt
-        return self._lt(lib().oc_matmul_ex, a.ptr, b.ptr, n, n1z, n1t, npz, npt)
+        return self._lt(lib().oc_matmul_lazy, a.ptr, b.ptr, n, n1z, n1t, npz, npt, 1 if lazy else 0)
 
-    def covariance(self, blocks, rb, k, n, n_samples, n1z, n1t, n1g, npz=None, npt=None):
+    def covariance(self, blocks, rb, k, n, n_samples, n1z, n1t, n1g, npz=None, npt=None, lazy=False):
         npz = n - 1 if npz is None else npz
         npt = n - 1 if npt is None else npt
         px = (C.c_void_p * len(blocks))(*[b.ptr for b in blocks])
         out = (C.c_void_p * (k * k))()
-        rc = lib().oc_covariance(self.ptr, px, rb, k, n, n_samples, n1z, n1t, npz, npt, n1g, out)
+        rc = lib().oc_covariance_lazy(self.ptr, px, rb, k, n, n_samples, n1z, n1t, npz, npt, n1g, 1 if lazy else 0,
+                                      out)
         if rc:
             raise RuntimeError(f"covariance failed ({rc})")
         return [Ct(self, out[i]) for i in range(k * k)]

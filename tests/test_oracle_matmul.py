@@ -105,3 +105,40 @@ def test_matmul_small_decrypts_to_fp64_product(small):
     want = np.tile((A @ B).ravel(), S // (n * n))
     err = np.max(np.abs(got - want))
     assert err < BOUND, err
+
+
+def test_lazy_relinearisation_variant_decrypts_to_fp64_product(small):
+    """Variant: the n tensors summed in three components and relinearised
+    once.  Different residues from the paper's per-product relinearisation,
+    same product within the bound, and no more noise."""
+    n = 16
+    A, B = I.uniform_matrix(3, n), I.uniform_matrix(4, n)
+    ca, cb = small.encrypt(A.ravel(), nonce=3), small.encrypt(B.ravel(), nonce=4)
+    eager = small.matmul(ca, cb, n, 4, 4)
+    lazy = small.matmul(ca, cb, n, 4, 4, lazy=True)
+    assert lazy.level == eager.level and lazy.scale == eager.scale
+    assert not np.array_equal(lazy.data(), eager.data())
+    want = np.tile((A @ B).ravel(), small.slots // (n * n))
+    e_eager = np.max(np.abs(small.decrypt(eager) - want))
+    e_lazy = np.max(np.abs(small.decrypt(lazy) - want))
+    assert e_lazy < BOUND, e_lazy
+    assert e_lazy < 2 * e_eager
+
+
+def test_lazy_covariance_decrypts(oracle_mod):
+    c = I.SMALL
+    o = oracle_mod.Oracle(c.log_n, c.q_bits + (40, 40), c.p_bits, seed=12)
+    n, k, rb = 8, 2, 2
+    # every rotation a small product and transposition can ask for
+    steps = {s for s in range(-n * n + 1, n * n) if s}
+    o.keygen(rot_steps=sorted(steps), relin=True)
+    X = I.centre(I.dataset(5, rb * n - 3, k * n - 5))
+    blk = I.blocks(X, n)
+    cts = [o.encrypt(blk[r, j].ravel(), nonce=10 + r * k + j) for r in range(rb) for j in range(k)]
+    cov = o.covariance(cts, rb, k, n, X.shape[0], 4, 4, 4, lazy=True)
+    ref = np.zeros((k * n, k * n))
+    ref[: X.shape[1], : X.shape[1]] = X.T @ X / X.shape[0]
+    for i in range(k * k):
+        a, b = divmod(i, k)
+        got = o.decrypt(cov[i])[: n * n].reshape(n, n)
+        assert np.max(np.abs(got - ref[a * n:(a + 1) * n, b * n:(b + 1) * n])) < BOUND
