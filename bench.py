@@ -3,15 +3,19 @@
 
 One step = one batch of `--batch` independent 128 x 128 products (Eq. 4 of
 the paper: sigma/tau double-hoisted BSGS, hoisted column/row shifts, n
-relinearised products, rescale) on ciphertexts already resident in HBM.
-The same steps are timed twice: plain (one product after another) and
-batched (the products stacked, every launch serving all of them); the
-headline value is the batched rate, the plain rate and the speedup sit
-beside it, together with a residue-for-residue comparison of the two.
-Prints one JSON line: matmuls/s, key-switched rotations/s, per-step latency
-percentiles, the roofline of the dominant kernel family (HIP events around
-its launches during the timed batched steps) and the CPU oracle timed on a
-bounded sample on this host.
+products, rescale) on ciphertexts already resident in HBM.  Three paths are
+timed on the same inputs:
+  plain    one product after another, relinearising every product (the
+           paper's order of Algorithm DMatrixMult);
+  batched  the products stacked so every launch serves all of them (same
+           residues as plain, checked here);
+  headline batched, with lazy relinearisation (the n tensors summed and
+           relinearised once; --paper-relin keeps the paper's order).
+The headline value is the last; the others and the speedups sit beside it.
+Also printed: key-switched rotations/s, per-step latency percentiles, the
+roofline of the kernel with the largest device time (HIP events around its
+launches during the timed steps), a serving run, the PCA run and the CPU
+oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -28,29 +32,48 @@ sys.path.insert(0, ROOT)
 
 METRIC = "HE d×d matmuls/s & key-switched rotations/s at N=2^16, batched vs plain; p99"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2305_17341_amd/csrc/kernels.hip", "paper_2305_17341_amd/csrc/he_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_2305_17341_amd", "csrc")
+# source regions a kernel's recorded traffic depends on: (file, first line, last line), matched literally
+KERNEL_REGIONS = {
+    "multsum": [("kernels.hip", "__device__ __forceinline__ u32 automorph_src(", "}"),
+                ("kernels.hip", "#define MS_MAXB 8", "#undef MS_CASE"),
+                ("he_internal.h", None, None)],
+}
 
 
-def kernels_sha256():
+def kernel_digest(kernel):
+    """SHA-256 over the source regions of `kernel` (None if one is missing)"""
     import hashlib
+    regions = KERNEL_REGIONS.get(kernel)
+    if regions is None:
+        return None
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    for fname, first, last in regions:
+        with open(os.path.join(CSRC, fname)) as fh:
+            text = fh.read()
+        if first is not None:
+            a = text.find(first)
+            if a < 0:
+                return None
+            b = text.find(last, a + len(first))
+            if b < 0:
+                return None
+            text = text[a:b + len(last)]
+        h.update(text.encode())
     return h.hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE counters,
-    scaled by a plain copy's reading) recorded with the kernel sources they
-    were taken on; None when absent or the sources have changed since."""
+    scaled by a plain copy's reading) recorded with a digest of the kernel's
+    source regions; None when absent or the kernel has changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     k = rec.get("kernels", {}).get(kernel)
-    if k is None or rec.get("kernels_sha256") != kernels_sha256():
+    if k is None or k.get("source_sha256") != kernel_digest(kernel):
         return None
     return k["bytes_per_launch"]
 
@@ -109,10 +132,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--paper-relin", action="store_true",
+                    help="headline path relinearises every product (default: lazy, once per product)")
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--rotations", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving run (0: skip it)")
+    ap.add_argument("--pca-components", type=int, default=8, help="components of the PCA run (0: skip it)")
     ap.add_argument("--calib-copies", type=int, default=0,
                     help="device copies of one top-level ciphertext at the end (counter calibration)")
     args = ap.parse_args()
@@ -136,7 +162,10 @@ def main():
     cB = [ctx.encrypt_matrix(b, nonce=1001 + i) for i, b in enumerate(Bs)]
     ctx.sync()
 
-    batched = {"flags": 1}
+    BATCHED, LAZY = 1, 2
+    relin = "paper" if args.paper_relin else "lazy"
+    head = {"flags": BATCHED | (0 if args.paper_relin else LAZY)}
+    names = {0: "plain", BATCHED: "batched", BATCHED | LAZY: "batched+lazy-relin"}
 
     def timed(opts, profile):
         """warm-up then `--steps` timed steps of B products; returns (seconds, per-step ms, outputs of warm-up)"""
@@ -145,7 +174,7 @@ def main():
             t0 = time.perf_counter()
             outs = ctx.matmul_batch(cA, cB, [d] * B, opts=opts)
             ctx.sync()
-            log(f"[bench] warmup {w} ({'batched' if opts else 'plain'}): {time.perf_counter() - t0:.2f} s")
+            log(f"[bench] warmup {w} ({names[opts['flags'] if opts else 0]}): {time.perf_counter() - t0:.2f} s")
         if profile:
             ctx.profile_enable(True)
         lat = []
@@ -157,14 +186,18 @@ def main():
             del o
         ctx.sync()
         t_total = time.perf_counter() - t_start
-        log(f"[bench] {args.steps} timed steps ({'batched' if opts else 'plain'}): {t_total:.2f} s")
+        log(f"[bench] {args.steps} timed steps ({names[opts['flags'] if opts else 0]}): {t_total:.2f} s")
         return t_total, lat, outs
 
     plain_outs = None
     if not args.no_plain:
         t_plain, lat_plain, plain_outs = timed(None, False)
+        t_bp, lat_bp, bp_outs = timed({"flags": BATCHED}, False)
+        # batching gives the one-at-a-time residues
+        same = all(np.array_equal(p.export(), q.export()) for p, q in zip(plain_outs, bp_outs))
+        del bp_outs
     c0 = ctx.op_counts()
-    t_total, lat, outs = timed(batched, True)
+    t_total, lat, outs = timed(head, True)
     fams = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "multsum", "modup", "fbc_to_q",
             "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor", "plift"]
     prof = {f: ctx.profile_read(f) for f in fams}
@@ -172,12 +205,11 @@ def main():
     c1 = ctx.op_counts()
     n_mm = (args.steps + args.warmup) * B
     per_mm = {k: (c1[k] - c0[k]) / n_mm for k in c0}
-    # accuracy of a warm-up output against FP64, and batched == plain residue for residue
+    # accuracy of a warm-up output against FP64; the headline path batched == alone
     err = float(np.max(np.abs(ctx.decrypt(outs[0], d * d) - (As[0] @ Bs[0]).ravel())))
-    same = None
-    if plain_outs is not None:
-        same = all(np.array_equal(p.export(), q.export()) for p, q in zip(plain_outs, outs))
-    del outs, plain_outs
+    alone = ctx.matmul(cA[0], cB[0], d, opts={"flags": head["flags"] & ~BATCHED})
+    head_same = bool(np.array_equal(alone.export(), outs[0].export()))
+    del outs, plain_outs, alone
 
     # key-switched rotations at the top level
     ct = cA[0]
@@ -222,11 +254,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"he_matmul d={d} at N=2^16 (q0 60b + 30x40b, P 3x60b, levels 30->27), "
                                f"uniform[-1,1] FP64 inputs", "d": d, "log_n": chain.log_n, "batch": B,
-                   "path": "batched"},
+                   "path": names[head["flags"]], "relinearisation": relin},
+        "batched_residues_equal_alone": head_same,
         "plain": None if args.no_plain else {
             "value": round(args.steps * B / t_plain, 4), "unit": "matmuls/s",
-            "latency_ms": {"p50": pct(lat_plain, 50), "p99": pct(lat_plain, 99)},
-            "speedup_batched": round(t_plain / t_total, 3), "residues_identical": same},
+            "what": "one product after another, one launch sequence each, relinearisation per product "
+                    "(the paper's order)",
+            "latency_ms": {"p50": pct(lat_plain, 50), "p99": pct(lat_plain, 99)}},
+        "batched_paper_relin": None if args.no_plain else {
+            "value": round(args.steps * B / t_bp, 4), "unit": "matmuls/s",
+            "latency_ms": {"p50": pct(lat_bp, 50), "p99": pct(lat_bp, 99)},
+            "speedup_vs_plain": round(t_plain / t_bp, 3), "residues_identical_to_plain": same},
+        "speedup_vs_plain": None if args.no_plain else round(t_plain / t_total, 3),
         "rotations_per_s": round(rot_s, 2),
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "max_abs_err": err,
@@ -238,6 +277,10 @@ def main():
         from paper_2305_17341_amd import serve
         log("[bench] serving run ...")
         result["serving"] = serve.serve_bench(["--jobs", str(args.serve_jobs)])
+    if args.pca_components > 0:
+        from paper_2305_17341_amd import pca
+        log("[bench] PCA run ...")
+        result["pca"] = pca.pca_bench(l_e=args.pca_components, log=log)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
         result["cpu_baseline"] = cpu_baseline(chain, per_mm, n_rescale)

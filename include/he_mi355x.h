@@ -12,7 +12,9 @@
  *   - Jiang's matrix product sum_k C^k Z a (.) R^k T b (Eq. 4) with the
  *     hoisting of section 4.1 and the diagonal convergence decomposition of
  *     section 4.2 (Algorithms DCDforZ, DCDforT, DMatrixMult),
- *   - the covariance circuit of section 5 (Algorithm HCovMtrx).
+ *   - the covariance circuit of section 5 (Algorithm HCovMtrx),
+ *   - the PowerMethod round, eigenvalue and eigen-shift of section 6.1
+ *     (Algorithms HPowerMethod, HEigenShift) with the interactive refresh.
  *
  * Conventions
  *   - Every call returns he_status (HE_OK = 0); on failure the message of the
@@ -97,6 +99,12 @@ typedef struct {
  * read once per batch.  Results are residue-for-residue identical to the
  * unbatched path.  Costs 8x the temporaries of one product in HBM. */
 #define HE_MM_BATCHED 1u
+/* he_matmul, he_matmul_batch, he_covariance: lazy relinearisation, a variant
+ * of the paper's order (which relinearises every product of Algorithm
+ * DMatrixMult): the n tensors (A_k, B_k) are summed in three components and
+ * relinearised once, saving n - 1 key switches per product.  Different
+ * residues from the default (no more noise); same level and scale. */
+#define HE_MM_LAZY_RELIN 2u
 
 /* Create a context on the current HIP device.  `dev` may be NULL.  `seed`
  * keys every random draw of the context (Philox4x64-10 streams).

@@ -17,6 +17,8 @@ struct DeviceTables {
   u64* psi_sh = nullptr;
   u64* ipsi = nullptr;         // [nmods][N] psi^-brv(k)
   u64* ipsi_sh = nullptr;
+  double* psi_f = nullptr;     // psi^brv as doubles (exact, used for moduli below 2^50)
+  double* ipsi_f = nullptr;
   // double-double FFT tables for the canonical embedding
   double* fft_tw = nullptr;    // [N/2][4] exp(-2 pi i k / N) as (re_hi, re_lo, im_hi, im_lo)
   double* zeta = nullptr;      // [N][4] (cos(pi i/N), sin(pi i/N)) dd
@@ -38,12 +40,17 @@ void launch_mul_bcast(const DeviceTables& T, u64* out, const u64* a, const u64* 
 // acc += a * b (b broadcast with period b_limbs)
 void launch_mul_acc(const DeviceTables& T, u64* acc, const u64* a, const u64* b, int nlimbs, int b_limbs,
                     const LimbMap& m, hipStream_t s);
+// out (+)= sum_t a[t] * p[t] (p[t] broadcast with period b_limbs), nterms pairs
+#define SUM_MAX_TERMS 16
+void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms,
+                    int nlimbs, int b_limbs, const LimbMap& m, bool accumulate, hipStream_t s);
 // out = a * c_k for a per-limb constant (host array, Shoup)
 void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const u64* consts /*[map.n]*/,
                       const LimbMap& m, hipStream_t s);
 void launch_neg(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const LimbMap& m, hipStream_t s);
-// batch pairs of ciphertexts [2][batch][nl] -> [3][batch][nl]
-void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, hipStream_t s);
+// batch pairs of ciphertexts [2][batch][nl] -> [3][batch][nl] (accumulate: added onto out3)
+void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, bool accumulate,
+                   hipStream_t s);
 void launch_int_to_limbs(const DeviceTables& T, u64* out, const i64* in, int nlimbs, const LimbMap& m, hipStream_t s);
 
 // key switching pieces

@@ -272,10 +272,59 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows(u64* data, LimbMap map, int lo
 // twiddle of stage s0 + j is at 2^(s0+j) + (hi << j) + (r >> (G - j)).
 // Inverse stage on bit b (Gentleman-Sande) uses psi^-brv at
 // 2^(logN-1-b) + (x >> (b+1)); values at x = base + (r << b0), hi = base >> (b0 + G).
+//
+// Two arithmetics, chosen per limb (uniform over a work-group):
+//  * Shoup: 64-bit words, w * a mod q with the companion floor(w 2^64 / q)
+//    (any q < 2^61; the 64-bit products run on the quarter-rate 32-bit
+//    multipliers);
+//  * exact FP64 for q < 2^50: h = a w, l = fma(a, w, -h) is the exact
+//    rounding error, k = rint(h / q), r = fma(-k, q, h) + l is exactly
+//    a w - k q in (-q, q), one conditional + q lands it in [0, q).  Every
+//    operation is a full-rate double op.  (With |a w / q - k| < 0.81 the
+//    fma result stays below 2^51 and is exact.)
+// Both give the same residues.
 // ---------------------------------------------------------------------------
-template <int G>
-__device__ __forceinline__ void fwd_group(u64 (&v)[16], int s0, u32 hi, const u64* __restrict__ w,
-                                          const u64* __restrict__ wsh, u64 q) {
+struct ShoupArith {
+  typedef u64 V;
+  const u64* __restrict__ w;
+  const u64* __restrict__ wsh;
+  u64 q, ninv, ninv_sh;
+  __device__ __forceinline__ V load(u64 x) const { return x; }
+  __device__ __forceinline__ u64 store(V x) const { return x; }
+  __device__ __forceinline__ V add(V a, V b) const { return add_mod(a, b, q); }
+  __device__ __forceinline__ V sub(V a, V b) const { return sub_mod(a, b, q); }
+  __device__ __forceinline__ V mulw(V a, u32 i) const { return shoup_mul(a, w[i], wsh[i], q); }
+  __device__ __forceinline__ V scale_ninv(V a) const { return shoup_mul(a, ninv, ninv_sh, q); }
+};
+
+__device__ __forceinline__ double f64_mulmod(double a, double w, double q, double qinv) {
+  const double h = a * w;
+  const double l = __fma_rn(a, w, -h);
+  const double k = __builtin_rint(h * qinv);
+  const double r = __fma_rn(-k, q, h) + l;
+  return r < 0.0 ? r + q : r;
+}
+
+struct F64Arith {
+  typedef double V;
+  const double* __restrict__ w;
+  double q, qinv, ninv;
+  __device__ __forceinline__ V load(u64 x) const { return (double)x; }
+  __device__ __forceinline__ u64 store(V x) const { return (u64)x; }
+  __device__ __forceinline__ V add(V a, V b) const {
+    const double s = a + b;
+    return s >= q ? s - q : s;
+  }
+  __device__ __forceinline__ V sub(V a, V b) const {
+    const double s = a - b;
+    return s < 0.0 ? s + q : s;
+  }
+  __device__ __forceinline__ V mulw(V a, u32 i) const { return f64_mulmod(a, w[i], q, qinv); }
+  __device__ __forceinline__ V scale_ninv(V a) const { return f64_mulmod(a, ninv, q, qinv); }
+};
+
+template <int G, class A>
+__device__ __forceinline__ void fwd_group(typename A::V (&v)[16], int s0, u32 hi, const A& ar) {
 #pragma unroll
   for (int j = 0; j < G; j++) {
     const int half = 1 << (G - 1 - j);
@@ -283,18 +332,16 @@ __device__ __forceinline__ void fwd_group(u64 (&v)[16], int s0, u32 hi, const u6
     for (int r = 0; r < (1 << G); r++) {
       if (r & half) continue;
       const u32 widx = (1u << (s0 + j)) + (hi << j) + (u32)(r >> (G - j));
-      const u64 W = w[widx], Wp = wsh[widx];
-      const u64 U = v[r];
-      const u64 V = shoup_mul(v[r + half], W, Wp, q);
-      v[r] = add_mod(U, V, q);
-      v[r + half] = sub_mod(U, V, q);
+      const typename A::V U = v[r];
+      const typename A::V V = ar.mulw(v[r + half], widx);
+      v[r] = ar.add(U, V);
+      v[r + half] = ar.sub(U, V);
     }
   }
 }
 
-template <int G>
-__device__ __forceinline__ void inv_group(u64 (&v)[16], int b0, int logN, u32 hi, const u64* __restrict__ w,
-                                          const u64* __restrict__ wsh, u64 q) {
+template <int G, class A>
+__device__ __forceinline__ void inv_group(typename A::V (&v)[16], int b0, int logN, u32 hi, const A& ar) {
 #pragma unroll
   for (int j = 0; j < G; j++) {
     const int half = 1 << j;
@@ -302,10 +349,9 @@ __device__ __forceinline__ void inv_group(u64 (&v)[16], int b0, int logN, u32 hi
     for (int r = 0; r < (1 << G); r++) {
       if (r & half) continue;
       const u32 widx = (1u << (logN - 1 - b0 - j)) + (hi << (G - j - 1)) + (u32)(r >> (j + 1));
-      const u64 W = w[widx], Wp = wsh[widx];
-      const u64 U = v[r], V = v[r + half];
-      v[r] = add_mod(U, V, q);
-      v[r + half] = shoup_mul(sub_mod(U, V, q), W, Wp, q);
+      const typename A::V U = v[r], V = v[r + half];
+      v[r] = ar.add(U, V);
+      v[r + half] = ar.mulw(ar.sub(U, V), widx);
     }
   }
 }
@@ -317,24 +363,13 @@ __device__ __forceinline__ int lds_rc(int r, int c, int C) { return r * (C + 1) 
 __device__ __forceinline__ int lds_be(int b, int e, int T1) { return b * (T1 + (T1 >> 4) + 1) + e + (e >> 4); }
 #define LDS_WORDS (TILE + TILE / 16 + 64)
 
-// Column pass: rows R = 2^(GA+GB), C = TILE / R columns per work-group.
-template <int LOGN, int GA, int GB, bool INV>
-__global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const u64* __restrict__ tw,
-                                                   const u64* __restrict__ twsh, const ModConst* __restrict__ mc) {
+// Column pass body: rows R = 2^(GA+GB), C = TILE / R columns per work-group.
+template <int LOGN, int GA, int GB, bool INV, class A>
+__device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh, const A& ar) {
+  typedef typename A::V V;
   constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R;
-  __shared__ u64 sh[LDS_WORDS];
-  const int limb = blockIdx.y;
-  const int m = limb_mod(map, limb);
-  if (m < 0) return;
-  const u64 N = 1ull << LOGN;
-  u64* a = data + (size_t)limb * N;
-  const int c0 = blockIdx.x * C;
-  const ModConst mk = mc[m];
-  const u64 q = mk.q;
-  const u64* w = tw + (size_t)m * N;
-  const u64* wsh = twsh + (size_t)m * N;
   const int tid = threadIdx.x;
-  u64 v[16];
+  V v[16];
   if (!INV) {
     // group A: r bits [GB, S1) -> stages 0..GA-1
     constexpr int ITA = 16 >> GA;
@@ -342,8 +377,8 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
     for (int k = 0; k < ITA; k++) {
       const int it = tid + TPB * k, c = it % C, rl = it / C;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = a[(size_t)(rl + (mm << GB)) * T1 + c0 + c];
-      fwd_group<GA>(v, 0, 0u, w, wsh, q);
+      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = ar.load(a[(size_t)(rl + (mm << GB)) * T1 + c0 + c]);
+      fwd_group<GA>(v, 0, 0u, ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GA); mm++) sh[lds_rc(rl + (mm << GB), c, C)] = v[mm];
     }
@@ -355,9 +390,9 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
       const int it = tid + TPB * k, c = it % C, rh = it / C;
 #pragma unroll
       for (int mm = 0; mm < (1 << GB); mm++) v[mm] = sh[lds_rc((rh << GB) + mm, c, C)];
-      fwd_group<GB>(v, GA, (u32)rh, w, wsh, q);
+      fwd_group<GB>(v, GA, (u32)rh, ar);
 #pragma unroll
-      for (int mm = 0; mm < (1 << GB); mm++) a[(size_t)((rh << GB) + mm) * T1 + c0 + c] = v[mm];
+      for (int mm = 0; mm < (1 << GB); mm++) a[(size_t)((rh << GB) + mm) * T1 + c0 + c] = ar.store(v[mm]);
     }
   } else {
     constexpr int S2 = LOGN - S1;
@@ -367,8 +402,8 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
     for (int k = 0; k < ITB; k++) {
       const int it = tid + TPB * k, c = it % C, rh = it / C;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GB); mm++) v[mm] = a[(size_t)((rh << GB) + mm) * T1 + c0 + c];
-      inv_group<GB>(v, S2, LOGN, (u32)rh, w, wsh, q);
+      for (int mm = 0; mm < (1 << GB); mm++) v[mm] = ar.load(a[(size_t)((rh << GB) + mm) * T1 + c0 + c]);
+      inv_group<GB>(v, S2, LOGN, (u32)rh, ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GB); mm++) sh[lds_rc((rh << GB) + mm, c, C)] = v[mm];
     }
@@ -380,32 +415,22 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
       const int it = tid + TPB * k, c = it % C, rl = it / C;
 #pragma unroll
       for (int mm = 0; mm < (1 << GA); mm++) v[mm] = sh[lds_rc(rl + (mm << GB), c, C)];
-      inv_group<GA>(v, S2 + GB, LOGN, 0u, w, wsh, q);
+      inv_group<GA>(v, S2 + GB, LOGN, 0u, ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GA); mm++)
-        a[(size_t)(rl + (mm << GB)) * T1 + c0 + c] = shoup_mul(v[mm], mk.ninv, mk.ninv_sh, q);
+        a[(size_t)(rl + (mm << GB)) * T1 + c0 + c] = ar.store(ar.scale_ninv(v[mm]));
     }
   }
 }
 
-// Block pass: blocks of T1 = 2^(GC+GD) words, K = TILE / T1 blocks per work-group.
-template <int LOGN, int GC, int GD, bool INV>
-__global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const u64* __restrict__ tw,
-                                                   const u64* __restrict__ twsh, const ModConst* __restrict__ mc) {
-  constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1, S1 = LOGN - S2;
-  __shared__ u64 sh[LDS_WORDS];
-  const int limb = blockIdx.y;
-  const int m = limb_mod(map, limb);
-  if (m < 0) return;
-  const u64 N = 1ull << LOGN;
-  const int blk0 = blockIdx.x * K;
-  u64* a = data + (size_t)limb * N + (size_t)blk0 * T1;
-  const u64 q = mc[m].q;
-  const u64* w = tw + (size_t)m * N;
-  const u64* wsh = twsh + (size_t)m * N;
+// Block pass body: blocks of T1 = 2^(GC+GD) words, K = TILE / T1 blocks per work-group.
+template <int LOGN, int GC, int GD, bool INV, class A>
+__device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* sh, const A& ar) {
+  typedef typename A::V V;
+  constexpr int S2 = GC + GD, T1 = 1 << S2, S1 = LOGN - S2;
   const int tid = threadIdx.x;
   constexpr int LOWC = 1 << (S2 - GC);  // e bits below group C
-  u64 v[16];
+  V v[16];
   if (!INV) {
     // group C: e bits [GD, S2) -> stages S1..S1+GC-1
     constexpr int ITC = 16 >> GC;
@@ -413,8 +438,8 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
     for (int k = 0; k < ITC; k++) {
       const int it = tid + TPB * k, el = it % LOWC, b = it / LOWC;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GC); mm++) v[mm] = a[(size_t)b * T1 + el + (mm << GD)];
-      fwd_group<GC>(v, S1, (u32)(blk0 + b), w, wsh, q);
+      for (int mm = 0; mm < (1 << GC); mm++) v[mm] = ar.load(a[(size_t)b * T1 + el + (mm << GD)]);
+      fwd_group<GC>(v, S1, (u32)(blk0 + b), ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GC); mm++) sh[lds_be(b, el + (mm << GD), T1)] = v[mm];
     }
@@ -427,24 +452,24 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
       const int it = tid + TPB * k, eh = it % HIGHD, b = it / HIGHD;
 #pragma unroll
       for (int mm = 0; mm < (1 << GD); mm++) v[mm] = sh[lds_be(b, (eh << GD) + mm, T1)];
-      fwd_group<GD>(v, S1 + GC, (u32)(((blk0 + b) << GC) + eh), w, wsh, q);
+      fwd_group<GD>(v, S1 + GC, (u32)(((blk0 + b) << GC) + eh), ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GD); mm++) sh[lds_be(b, (eh << GD) + mm, T1)] = v[mm];
     }
     __syncthreads();
-    for (int e = tid; e < TILE; e += TPB) a[e] = sh[lds_be(e / T1, e % T1, T1)];
+    for (int e = tid; e < TILE; e += TPB) a[e] = ar.store(sh[lds_be(e / T1, e % T1, T1)]);
   } else {
     // inverse bits [0, GD) of e
     constexpr int ITD = 16 >> GD;
     constexpr int HIGHD = 1 << (S2 - GD);
-    for (int e = tid; e < TILE; e += TPB) sh[lds_be(e / T1, e % T1, T1)] = a[e];
+    for (int e = tid; e < TILE; e += TPB) sh[lds_be(e / T1, e % T1, T1)] = ar.load(a[e]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITD; k++) {
       const int it = tid + TPB * k, eh = it % HIGHD, b = it / HIGHD;
 #pragma unroll
       for (int mm = 0; mm < (1 << GD); mm++) v[mm] = sh[lds_be(b, (eh << GD) + mm, T1)];
-      inv_group<GD>(v, 0, LOGN, (u32)(((blk0 + b) << GC) + eh), w, wsh, q);
+      inv_group<GD>(v, 0, LOGN, (u32)(((blk0 + b) << GC) + eh), ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GD); mm++) sh[lds_be(b, (eh << GD) + mm, T1)] = v[mm];
     }
@@ -456,10 +481,59 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
       const int it = tid + TPB * k, el = it % LOWC, b = it / LOWC;
 #pragma unroll
       for (int mm = 0; mm < (1 << GC); mm++) v[mm] = sh[lds_be(b, el + (mm << GD), T1)];
-      inv_group<GC>(v, GD, LOGN, (u32)(blk0 + b), w, wsh, q);
+      inv_group<GC>(v, GD, LOGN, (u32)(blk0 + b), ar);
 #pragma unroll
-      for (int mm = 0; mm < (1 << GC); mm++) a[(size_t)b * T1 + el + (mm << GD)] = v[mm];
+      for (int mm = 0; mm < (1 << GC); mm++) a[(size_t)b * T1 + el + (mm << GD)] = ar.store(v[mm]);
     }
+  }
+}
+
+// moduli below 2^50 take the FP64 arithmetic
+#define NTT_F64_MAX_BITS 50
+
+template <int LOGN, int GA, int GB, bool INV>
+__global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const u64* __restrict__ tw,
+                                                   const u64* __restrict__ twsh, const double* __restrict__ twf,
+                                                   const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, C = TILE / R;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << LOGN;
+  u64* a = data + (size_t)limb * N;
+  const int c0 = blockIdx.x * C;
+  const ModConst mk = mc[m];
+  if (mk.bits <= NTT_F64_MAX_BITS) {
+    const double qd = (double)mk.q;
+    F64Arith ar{twf + (size_t)m * N, qd, 1.0 / qd, (double)mk.ninv};
+    ntt_cols2_body<LOGN, GA, GB, INV>(a, c0, reinterpret_cast<double*>(sh), ar);
+  } else {
+    ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_cols2_body<LOGN, GA, GB, INV>(a, c0, sh, ar);
+  }
+}
+
+template <int LOGN, int GC, int GD, bool INV>
+__global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const u64* __restrict__ tw,
+                                                   const u64* __restrict__ twsh, const double* __restrict__ twf,
+                                                   const ModConst* __restrict__ mc) {
+  constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << LOGN;
+  const int blk0 = blockIdx.x * K;
+  u64* a = data + (size_t)limb * N + (size_t)blk0 * T1;
+  const ModConst mk = mc[m];
+  if (mk.bits <= NTT_F64_MAX_BITS) {
+    const double qd = (double)mk.q;
+    F64Arith ar{twf + (size_t)m * N, qd, 1.0 / qd, (double)mk.ninv};
+    ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, reinterpret_cast<double*>(sh), ar);
+  } else {
+    ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, sh, ar);
   }
 }
 
@@ -472,17 +546,21 @@ static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& ma
   if (!inverse) {
     {
       ProfScope ps("ntt_fwd_cols", s, pass_bytes);
-      hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh, T.mc);
+      hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh,
+                         T.psi_f, T.mc);
     }
     ProfScope ps("ntt_fwd_rows", s, pass_bytes);
-    hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false>), gr, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh, T.mc);
+    hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false>), gr, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh,
+                       T.psi_f, T.mc);
   } else {
     {
       ProfScope ps("ntt_inv_rows", s, pass_bytes);
-      hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, true>), gr, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh, T.mc);
+      hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, true>), gr, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh,
+                         T.ipsi_f, T.mc);
     }
     ProfScope ps("ntt_inv_cols", s, pass_bytes);
-    hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, true>), gc, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh, T.mc);
+    hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, true>), gc, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh,
+                       T.ipsi_f, T.mc);
   }
 }
 
@@ -595,6 +673,42 @@ void launch_mul_bcast(const DeviceTables& T, u64* out, const u64* a, const u64* 
                       const LimbMap& m, hipStream_t s) { ew(T, EW_MUL, out, a, b, nl, bl, m, s); }
 void launch_mul_acc(const DeviceTables& T, u64* acc, const u64* a, const u64* b, int nl, int bl, const LimbMap& m,
                     hipStream_t s) { ew(T, EW_MULACC, acc, a, b, nl, bl, m, s); }
+// out = sum_t a_t (.) p_t (p_t broadcast with period b_limbs), one pass over
+// every operand; `accumulate` adds onto out
+struct SumTerms {
+  const u64* a[SUM_MAX_TERMS];
+  const u64* p[SUM_MAX_TERMS];
+};
+__global__ void k_mul_sum(u64* out, SumTerms t, int nterms, int accumulate, int b_limbs, LimbMap map, int logN,
+                          const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= N) return;
+  int m = limb_mod(map, k);
+  if (m < 0) return;
+  const ModConst mk = mc[m];
+  const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
+  u64 acc = accumulate ? out[o] : 0;
+  for (int j = 0; j < nterms; j++) acc = add_mod(acc, mul_mod(t.a[j][o], t.p[j][op], mk), mk.q);
+  out[o] = acc;
+}
+void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms, int nl,
+                    int bl, const LimbMap& m, bool accumulate, hipStream_t s) {
+  for (int t0 = 0; t0 < nterms; t0 += SUM_MAX_TERMS) {
+    const int nt = std::min(nterms - t0, SUM_MAX_TERMS);
+    const bool acc = accumulate || t0 > 0;
+    SumTerms t;
+    for (int j = 0; j < nt; j++) {
+      t.a[j] = a[t0 + j];
+      t.p[j] = p[t0 + j];
+    }
+    ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nt + 1 + (acc ? 1 : 0)) + (double)bl * nt));
+    dim3 grid(cdiv(T.N, TPB), nl);
+    hipLaunchKernelGGL(k_mul_sum, grid, dim3(TPB), 0, s, out, t, nt, acc ? 1 : 0, bl, m, T.logN, T.mc);
+  }
+}
+
 void launch_neg(const DeviceTables& T, u64* out, const u64* a, int nl, const LimbMap& m, hipStream_t s) {
   ew(T, EW_NEG, out, a, a, nl, nl, m, s);
 }
@@ -626,7 +740,8 @@ void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs,
 }
 
 // Tensor of B pairs of ciphertexts over Q_l ([2][B][nl] each):
-// (a0 b0, a0 b1 + a1 b0, a1 b1) into [3][B][nl]
+// (a0 b0, a0 b1 + a1 b0, a1 b1) into [3][B][nl], or added onto it (ACC)
+template <bool ACC>
 __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, int logN,
                          const ModConst* __restrict__ mc) {
   const u64 N = 1ull << logN;
@@ -634,17 +749,27 @@ __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, i
   int k = blockIdx.y;
   if (i >= N) return;
   const ModConst mk = mc[k % nl];
-  size_t o0 = (size_t)k * N + i, o1 = (size_t)(nt + k) * N + i;
+  size_t o0 = (size_t)k * N + i, o1 = (size_t)(nt + k) * N + i, o2 = (size_t)(2 * nt + k) * N + i;
   u64 a0 = a[o0], a1 = a[o1], b0 = b[o0], b1 = b[o1];
-  out[o0] = mul_mod(a0, b0, mk);
-  out[o1] = add_mod(mul_mod(a0, b1, mk), mul_mod(a1, b0, mk), mk.q);
-  out[(size_t)(2 * nt + k) * N + i] = mul_mod(a1, b1, mk);
+  u64 t0 = mul_mod(a0, b0, mk);
+  u64 t1 = add_mod(mul_mod(a0, b1, mk), mul_mod(a1, b0, mk), mk.q);
+  u64 t2 = mul_mod(a1, b1, mk);
+  if (ACC) {
+    t0 = add_mod(t0, out[o0], mk.q);
+    t1 = add_mod(t1, out[o1], mk.q);
+    t2 = add_mod(t2, out[o2], mk.q);
+  }
+  out[o0] = t0;
+  out[o1] = t1;
+  out[o2] = t2;
 }
-void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, hipStream_t s) {
+void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, bool accumulate,
+                   hipStream_t s) {
   const int nt = nl * batch;
-  ProfScope ps("tensor", s, 8.0 * T.N * 7 * nt);
+  ProfScope ps("tensor", s, 8.0 * T.N * (accumulate ? 10 : 7) * nt);
   dim3 grid(cdiv(T.N, TPB), nt);
-  hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, s, out3, a, b, nl, nt, T.logN, T.mc);
+  if (accumulate) hipLaunchKernelGGL(k_tensor<true>, grid, dim3(TPB), 0, s, out3, a, b, nl, nt, T.logN, T.mc);
+  else hipLaunchKernelGGL(k_tensor<false>, grid, dim3(TPB), 0, s, out3, a, b, nl, nt, T.logN, T.mc);
 }
 
 __global__ void k_int_to_limbs(u64* out, const i64* in, int nlimbs, LimbMap map, int logN,

@@ -124,13 +124,15 @@ struct HeCtxImpl {
   HeCt apply_chain(const HeCt& x, const std::vector<DcdFactor>& fs, const std::string& tag);
   HeCt sigma_dcd(const HeCt& x, int n, int n1, int nprime);
   HeCt tau_dcd(const HeCt& x, int n, int n1, int nprime);
-  HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t, int npz, int npt);
+  HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t, int npz, int npt, bool lazy = false);
+  void accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
+  HeCt relin_sum(const DevBuf& acc3, int level, double scale, int B);
   std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz);
   std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t, int npt);
   void align_sides(std::vector<HeCt>& Ak, std::vector<HeCt>& Bk);
   void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,
-                               int n1t, int n1g, int npz, int npt);
+                               int n1t, int n1g, int npz, int npt, bool lazy = false);
 
   // PowerMethod (section 6.1) and the interactive refresh
   DevBuf decrypt_int(const HeCt& c);

@@ -318,6 +318,15 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
   T.psi_sh = table_upload(psi_sh.data(), psi_sh.size() * 8);
   T.ipsi = table_upload(ipsi.data(), ipsi.size() * 8);
   T.ipsi_sh = table_upload(ipsi_sh.data(), ipsi_sh.size() * 8);
+  {
+    std::vector<double> pf(psi.size()), ipf(ipsi.size());
+    for (size_t i = 0; i < psi.size(); i++) {
+      pf[i] = (double)psi[i];
+      ipf[i] = (double)ipsi[i];
+    }
+    T.psi_f = (double*)table_upload(pf.data(), pf.size() * 8);
+    T.ipsi_f = (double*)table_upload(ipf.data(), ipf.size() * 8);
+  }
 
   // canonical embedding tables
   std::vector<double> tw(N / 2 * 4), zt(N * 4);
@@ -672,7 +681,7 @@ HeCt HeCtxImpl::mult(const HeCt& a, const HeCt& b) {
   if (a.qp) fail(HE_EINVAL, "mult of R_QP elements");
   int nl = a.nlimbs, nt = a.B * nl;
   DevBuf t3(&pool, (size_t)3 * nt * N);
-  launch_tensor(T, t3.p, a.d.p, b.d.p, nl, a.B, stream);
+  launch_tensor(T, t3.p, a.d.p, b.d.p, nl, a.B, false, stream);
   HeCt ks = keyswitch(t3.p + (size_t)2 * nt * N, a.level, 0, a.B);
   HeCt c = ct_new(a.level, false, a.scale * b.scale, a.B);
   launch_add(T, c.d.p, t3.p, ks.d.p, 2 * nt, qmap(nl), stream);
@@ -865,19 +874,15 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
   bool acc_set = false;
   size_t e = 0;
   for (int i = G.i_lo; i < G.i_hi; i++) {
-    HeCt inner;
-    bool inner_set = false;
+    // inner = sum_j baby_j (.) diagonal_(i,j), one pass over all of them
+    std::vector<const u64*> ta, tp;
     for (; e < ij.size() && ij[e].first == i; e++) {
-      int j = ij[e].second;
-      if (!inner_set) {
-        inner = ct_new(level, true, x.scale * ql, x.B);
-        launch_mul_bcast(T, inner.d.p, baby[j].d.p, pts[e], 2 * x.B * nqp, nqp, qpm, stream);
-        inner_set = true;
-      } else {
-        launch_mul_acc(T, inner.d.p, baby[j].d.p, pts[e], 2 * x.B * nqp, nqp, qpm, stream);
-      }
+      ta.push_back(baby[ij[e].second].d.p);
+      tp.push_back(pts[e]);
     }
-    if (!inner_set) continue;
+    if (ta.empty()) continue;
+    HeCt inner = ct_new(level, true, x.scale * ql, x.B);
+    launch_mul_sum(T, inner.d.p, ta.data(), tp.data(), (int)ta.size(), 2 * x.B * nqp, nqp, qpm, false, stream);
     HeCt term;
     if (i == 0) {
       term = std::move(inner);
@@ -1068,14 +1073,16 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       int k = b * n1z + r;
       u64 g = galois(r);
       HeCt acc = ct_new(lvl, true, Bb.scale * ql, Bb.B);
-      {
-        HeCt h = hoisted(Bb, d1.p, g);
-        launch_mul_bcast(T, acc.d.p, h.d.p, mask_of(k, 0), 2 * Bb.B * nqp, nqp, qpm, stream);
-      }
+      HeCt h1 = hoisted(Bb, d1.p, g), h2;
+      const u64* ta[2] = {h1.d.p, nullptr};
+      const u64* tp[2] = {mask_of(k, 0), mask_of(k, 1)};
       if (k > 0) {
-        HeCt h = hoisted(Bpb, d2.p, g);
-        launch_mul_acc(T, acc.d.p, h.d.p, mask_of(k, 1), 2 * Bb.B * nqp, nqp, qpm, stream);
+        h2 = hoisted(Bpb, d2.p, g);
+        ta[1] = h2.d.p;
       }
+      launch_mul_sum(T, acc.d.p, ta, tp, k > 0 ? 2 : 1, 2 * Bb.B * nqp, nqp, qpm, false, stream);
+      h1 = HeCt();
+      h2 = HeCt();
       HeCt md = moddown(acc);
       Ak[k] = rescale(md);
       Ak[k].scale = Bb.scale;
@@ -1127,7 +1134,29 @@ void HeCtxImpl::matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<He
   }
 }
 
-HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, int npz, int npt) {
+// Lazy relinearisation (a variant of the paper's order): the tensors of
+// all products are summed in three components, [3][B][nl][N] ...
+void HeCtxImpl::accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vector<HeCt>& Ak,
+                                   const std::vector<HeCt>& Bk) {
+  const HeCt& a0 = Ak[0];
+  const int nl = a0.nlimbs;
+  if (!acc_set) acc3 = DevBuf(&pool, (size_t)3 * a0.B * nl * N);
+  for (size_t k = 0; k < Ak.size(); k++) {
+    need_same(Ak[k], Bk[k]);
+    launch_tensor(T, acc3.p, Ak[k].d.p, Bk[k].d.p, nl, a0.B, acc_set, stream);
+    acc_set = true;
+  }
+}
+// ... and relinearised once
+HeCt HeCtxImpl::relin_sum(const DevBuf& acc3, int level, double scale, int B) {
+  const int nl = level + 1, nt = B * nl;
+  HeCt ks = keyswitch(acc3.p + (size_t)2 * nt * N, level, 0, B);
+  HeCt c = ct_new(level, false, scale, B);
+  launch_add(T, c.d.p, acc3.p, ks.d.p, 2 * nt, qmap(nl), stream);
+  return c;
+}
+
+HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, int npz, int npt, bool lazy) {
   if (ca.qp || cb.qp || ca.level != cb.level) fail(HE_ELEVEL, "operands must be ciphertexts at one level");
   if ((u64)n * n > N / 2 || n % n1z || n % n1t || npz < 1 || npt < 1)
     fail(HE_EINVAL, "bad matrix size / baby-step count / decomposition");
@@ -1137,8 +1166,15 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, 
   std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t, npt);
   align_sides(Ak, Bk);
   HeCt acc;
-  bool set = false;
-  matmul_accumulate(acc, set, Ak, Bk);
+  if (lazy) {
+    DevBuf acc3;
+    bool set = false;
+    accumulate_tensors(acc3, set, Ak, Bk);
+    acc = relin_sum(acc3, Ak[0].level, Ak[0].scale * Bk[0].scale, Ak[0].B);
+  } else {
+    bool set = false;
+    matmul_accumulate(acc, set, Ak, Bk);
+  }
   return rescale(acc);
 }
 
@@ -1147,7 +1183,7 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, 
 // for b <= a, and G(block (b, a)) for a < b; the A and B sides of each
 // row block are formed once and reused for every pair (one-to-many caching).
 std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples,
-                                        int n1z, int n1t, int n1g, int npz, int npt) {
+                                        int n1z, int n1t, int n1g, int npz, int npt, bool lazy) {
   if ((int)x.size() != rb * k) fail(HE_EINVAL, "block count mismatch");
   int level = x[0]->level;
   for (auto* c : x)
@@ -1155,7 +1191,10 @@ std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int r
   int dz = npz >= n - 1 ? 1 : ceil_div_i(n - 1, npz), dt = npt >= n - 1 ? 1 : ceil_div_i(n - 1, npt);
   if (level < std::max(dz + 1, dt) + 3) fail(HE_ELEVEL, "not enough levels for the covariance");
   std::vector<HeCt> acc(k * k);
+  std::vector<DevBuf> acc3(k * k);
   std::vector<bool> set(k * k, false);
+  int acc_level = 0;
+  double acc_scale = 0;
   for (int r = 0; r < rb; r++) {
     std::vector<std::vector<HeCt>> A(k), B(k);
     for (int a = 0; a < k; a++) {
@@ -1168,16 +1207,25 @@ std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int r
     }
     for (int a = 0; a < k; a++) align_sides(A[a], B[0]);
     for (int b = 0; b < k; b++) align_sides(A[0], B[b]);
+    acc_level = A[0][0].level;
+    acc_scale = A[0][0].scale * B[0][0].scale;
     for (int a = 0; a < k; a++)
       for (int b = 0; b <= a; b++) {
         bool s = set[a * k + b];
-        matmul_accumulate(acc[a * k + b], s, A[a], B[b]);
+        if (lazy) accumulate_tensors(acc3[a * k + b], s, A[a], B[b]);
+        else matmul_accumulate(acc[a * k + b], s, A[a], B[b]);
         set[a * k + b] = s;
       }
   }
   std::vector<HeCt> out(k * k);
   for (int a = 0; a < k; a++)
-    for (int b = 0; b <= a; b++) out[a * k + b] = rescale(acc[a * k + b]);
+    for (int b = 0; b <= a; b++) {
+      if (lazy) {
+        acc[a * k + b] = relin_sum(acc3[a * k + b], acc_level, acc_scale, 1);
+        acc3[a * k + b].release();
+      }
+      out[a * k + b] = rescale(acc[a * k + b]);
+    }
   for (int a = 0; a < k; a++)
     for (int b = a + 1; b < k; b++) out[a * k + b] = lintrans(out[b * k + a], LT_TRANSPOSE, n, n1g, 1.0);
   if (k > 1) {

@@ -152,8 +152,9 @@ class Ciphertext:
             self.ptr = vp()
 
     def __del__(self):
+        # a ciphertext keeps its context alive; skip if the context is gone already
         try:
-            if _lib is not None and self.ptr and self.ptr.value:
+            if _lib is not None and self.ptr and self.ptr.value and self.ctx.ptr and self.ctx.ptr.value:
                 _lib.he_ct_free(self.ptr)
                 self.ptr = vp()
         except Exception:
@@ -204,6 +205,15 @@ class Context:
         if getattr(self, "ptr", None) and self.ptr.value:
             _check(load().he_ctx_destroy(self.ptr))
             self.ptr = vp()
+
+    def __del__(self):
+        # device memory (keys, caches, pool) goes back when the last reference
+        # (every ciphertext holds one) is dropped
+        try:
+            if _lib is not None:
+                self.close()
+        except Exception:
+            pass
 
     def _ct(self, f, *args):
         out = vp()

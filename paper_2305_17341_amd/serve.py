@@ -35,6 +35,7 @@ from concurrent.futures import Future
 from dataclasses import dataclass, field
 
 BATCHED = 1  # HE_MM_BATCHED
+LAZY_RELIN = 2  # HE_MM_LAZY_RELIN
 POOL_SLACK = 1.25  # a cached device block is reused for requests down to 1/1.25 of its size
 
 
@@ -107,8 +108,9 @@ class Request:
 class HeBackend:
     """One context per ring dimension, keys for every served product size."""
 
-    def __init__(self, chains, ds_by_log_n, seed=1, covariance_d=()):
+    def __init__(self, chains, ds_by_log_n, seed=1, covariance_d=(), lazy_relin=True):
         from . import he
+        self.relin_flags = LAZY_RELIN if lazy_relin else 0
         self.contexts = {}
         self.chains = {}
         for chain in chains:
@@ -136,10 +138,10 @@ class HeBackend:
         ctx = self.contexts[log_n]
         if reqs[0].kind == "covariance":
             blocks, rb, k, n_samples = reqs[0].args
-            out = [ctx.covariance(blocks, rb, k, reqs[0].d, n_samples)]
+            out = [ctx.covariance(blocks, rb, k, reqs[0].d, n_samples, opts={"flags": self.relin_flags})]
         else:
             out = ctx.matmul_batch([r.args[0] for r in reqs], [r.args[1] for r in reqs], [r.d for r in reqs],
-                                   opts={"flags": BATCHED})
+                                   opts={"flags": BATCHED | self.relin_flags})
         ctx.sync()
         return out
 
@@ -350,7 +352,7 @@ def serve_bench(argv=None):
         ca, cb = ctx.encrypt_matrix(A, nonce=1), ctx.encrypt_matrix(A, nonce=2)
         for rep in range(2):
             t = time.perf_counter()
-            r = ctx.matmul(ca, cb, d)
+            r = ctx.matmul(ca, cb, d, opts={"flags": backend.relin_flags})
             ctx.sync()
             solo[(d, ln)] = time.perf_counter() - t
             del r

@@ -1,0 +1,90 @@
+"""Lazy relinearisation (HE_MM_LAZY_RELIN, a variant of the paper's
+per-product relinearisation): residue for residue equal to the oracle's
+lazy variant for plain and decomposed products and the covariance, batched
+equal to one-at-a-time, and the 128 x 128 product at N = 2^16 within 2^-15
+of FP64."""
+import numpy as np
+import pytest
+
+from paper_2305_17341_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DEEP = I.Chain("n11_deep", 11, (60,) + (40,) * 6, (60, 60))
+BOUND = 2.0 ** -15
+LAZY = 2
+BATCHED = 1
+
+
+@pytest.fixture(scope="module")
+def pair(oracle_mod):
+    from paper_2305_17341_amd import he
+    n = 16
+    ctx = he.chain_context(DEEP, seed=19)
+    steps = set(ctx.transpose_rot_steps(8)) | set(ctx.matmul_rot_steps(8, {"n1_z": 2, "n1_t": 2}))
+    for npz, npt in [(15, 15), (4, 4)]:
+        steps |= set(ctx.matmul_rot_steps(n, {"n1_z": 4, "n1_t": 4, "nprime_z": npz, "nprime_t": npt}))
+    steps = sorted(steps)
+    ctx.keygen(steps)
+    o = oracle_mod.Oracle(DEEP.log_n, DEEP.q_bits, DEEP.p_bits, seed=19)
+    o.keygen(rot_steps=steps)
+    return ctx, o
+
+
+@pytest.mark.parametrize("npz,npt", [(15, 15), (4, 4)])
+def test_lazy_matmul_bit_exact(pair, npz, npt):
+    ctx, o = pair
+    n = 16
+    A, B = I.uniform_matrix(21, n), I.uniform_matrix(22, n)
+    opts = {"n1_z": 4, "n1_t": 4, "nprime_z": npz, "nprime_t": npt, "flags": LAZY}
+    ca, cb = ctx.encrypt_matrix(A, nonce=1), ctx.encrypt_matrix(B, nonce=2)
+    r = ctx.matmul(ca, cb, n, opts)
+    want = o.matmul(o.encrypt(A.ravel(), nonce=1), o.encrypt(B.ravel(), nonce=2), n, 4, 4, npz, npt, lazy=True)
+    assert r.level == want.level and r.scale == want.scale
+    assert np.array_equal(r.export(), want.data())
+    assert np.max(np.abs(ctx.decrypt(r, n * n) - (A @ B).ravel())) < BOUND
+    # batched lazy == one-at-a-time lazy
+    outs = ctx.matmul_batch([ca, ca, cb], [cb, cb, ca], [n] * 3, dict(opts, flags=LAZY | BATCHED))
+    assert np.array_equal(outs[0].export(), r.export())
+    assert np.array_equal(outs[1].export(), r.export())
+    assert np.array_equal(outs[2].export(), ctx.matmul(cb, ca, n, opts).export())
+
+
+def test_lazy_covariance_bit_exact(pair):
+    ctx, o = pair
+    n, k, rb = 8, 2, 2
+    X = I.centre(I.dataset(4, rb * n - 3, k * n - 5))
+    s = X.shape[0]
+    blocks = I.blocks(X, n)
+    g = [ctx.encrypt_matrix(blocks[r, j], nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
+    oc = [o.encrypt(blocks[r, j].ravel(), nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
+    cov = ctx.covariance(g, rb, k, n, s, {"n1_z": 2, "n1_t": 2, "flags": LAZY})
+    want = o.covariance(oc, rb, k, n, s, 2, 2, 4, lazy=True)
+    P = np.zeros((rb * n, k * n))
+    P[: X.shape[0], : X.shape[1]] = X
+    ref = P.T @ P / s
+    for i in range(k * k):
+        assert np.array_equal(cov[i].export(), want[i].data()), i
+        a, b = divmod(i, k)
+        got = ctx.decrypt(cov[i], n * n).reshape(n, n)
+        assert np.max(np.abs(got - ref[a * n:(a + 1) * n, b * n:(b + 1) * n])) < BOUND
+
+
+def test_lazy_matmul_128_full_size():
+    from paper_2305_17341_amd import he
+    ch = I.LARGE
+    n = 128
+    ctx = he.chain_context(ch, seed=31)
+    ctx.keygen(ctx.matmul_rot_steps(n))
+    As = [I.uniform_matrix(300 + i, n) for i in range(3)]
+    Bs = [I.uniform_matrix(400 + i, n) for i in range(3)]
+    cA = [ctx.encrypt_matrix(a, nonce=1 + i) for i, a in enumerate(As)]
+    cB = [ctx.encrypt_matrix(b, nonce=101 + i) for i, b in enumerate(Bs)]
+    outs = ctx.matmul_batch(cA, cB, [n] * 3, {"flags": LAZY | BATCHED})
+    for i in range(3):
+        assert outs[i].level == ch.top_level - 3
+        err = np.max(np.abs(ctx.decrypt(outs[i], n * n) - (As[i] @ Bs[i]).ravel()))
+        print(f"lazy 128x128 product {i}: max abs error {err:.3e}", flush=True)
+        assert err < BOUND
+    alone = ctx.matmul(cA[1], cB[1], n, {"flags": LAZY})
+    assert np.array_equal(alone.export(), outs[1].export())

@@ -42,7 +42,7 @@ def test_mix_results_equal_alone(backend):
     assert st["mean_batch"] > 1.0          # arrivals did join running work
     for j, (A, B, ca, cb), out in zip(jobs, inputs, outs):
         ctx = backend.contexts[j.log_n]
-        alone = ctx.matmul(ca, cb, j.d)
+        alone = ctx.matmul(ca, cb, j.d, opts={"flags": backend.relin_flags})
         assert np.array_equal(alone.export(), out.export()), (j.log_n, j.d, j.seed)
         err = np.max(np.abs(ctx.decrypt(out, j.d * j.d) - (A @ B).ravel()))
         assert err < BOUND, (j.log_n, j.d, err)
@@ -62,7 +62,7 @@ def test_oversize_request_rejected(backend):
 def _measured_peak(ctx, ca, cb, d, batch):
     ctx.trim()
     live0, _, _ = ctx.mem_info()
-    out = ctx.matmul_batch([ca] * batch, [cb] * batch, [d] * batch, opts={"flags": S.BATCHED})
+    out = ctx.matmul_batch([ca] * batch, [cb] * batch, [d] * batch, opts={"flags": S.BATCHED | S.LAZY_RELIN})
     ctx.sync()
     _, _, peak = ctx.mem_info()
     del out
