@@ -27,6 +27,8 @@ struct ModConst {
   u64 ninv_sh; // Shoup companion floor(ninv * 2^64 / q)
   u64 r64;     // 2^64 mod q
   u64 r64_sh;
+  double qf;   // q and 1/q as doubles (FP64 path, q < 2^50)
+  double qinvf;
 };
 
 // ---------------------------------------------------------------------------
@@ -40,6 +42,8 @@ __device__ __forceinline__ u64 shoup_mul(u64 a, u64 w, u64 wp, u64 q) {
   u64 r = a * w - qh * q;
   return r >= q ? r - q : r;
 }
+// a*w mod q for a constant w < q (Shoup companion wp), arithmetic by the size of q
+__device__ __forceinline__ u64 mul_const_any(u64 a, u64 w, u64 wp, const ModConst& m);
 // lazy variant: result in [0, 2q)
 __device__ __forceinline__ u64 shoup_mul_lazy(u64 a, u64 w, u64 wp, u64 q) {
   u64 qh = mulhi64(a, wp);
@@ -60,6 +64,29 @@ __device__ __forceinline__ u64 barrett_reduce128(u64 hi, u64 lo, const ModConst&
 // a*b mod q for a, b < q
 __device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const ModConst& m) {
   return barrett_reduce128(mulhi64(a, b), a * b, m);
+}
+
+// Exact a*w mod q in FP64 for q < 2^50 and a, w < q: h = a w rounded,
+// l = fma(a, w, -h) its exact error, k = rint(h / q); then
+// r = fma(-k, q, h) + l = a w - k q exactly (|a w / q - k| < 0.81 keeps the
+// fma result below 2^51) and one conditional + q lands it in [0, q).
+// Full-rate double operations instead of the quarter-rate 32-bit multipliers.
+#define F64_MAX_BITS 50
+__device__ __forceinline__ double f64_mulmod(double a, double w, double q, double qinv) {
+  const double h = a * w;
+  const double l = __fma_rn(a, w, -h);
+  const double k = __builtin_rint(h * qinv);
+  const double r = __fma_rn(-k, q, h) + l;
+  return r < 0.0 ? r + q : r;
+}
+__device__ __forceinline__ u64 mul_const_any(u64 a, u64 w, u64 wp, const ModConst& m) {
+  if (m.bits <= F64_MAX_BITS) return (u64)f64_mulmod((double)a, (double)w, m.qf, m.qinvf);
+  return shoup_mul(a, w, wp, m.q);
+}
+// a*b mod q, choosing the arithmetic by the size of q (same residue either way)
+__device__ __forceinline__ u64 mul_mod_any(u64 a, u64 b, const ModConst& m) {
+  if (m.bits <= F64_MAX_BITS) return (u64)f64_mulmod((double)a, (double)b, m.qf, m.qinvf);
+  return mul_mod(a, b, m);
 }
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
   u64 s = a + b;

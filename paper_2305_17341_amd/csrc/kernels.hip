@@ -8,6 +8,7 @@
 #include "kernels.h"
 
 #include <cstdio>
+#include <type_traits>
 
 #define TPB 256
 #define NTT_LDS 4096  // u64 words of LDS per NTT work-group (32 KiB)
@@ -297,13 +298,6 @@ struct ShoupArith {
   __device__ __forceinline__ V scale_ninv(V a) const { return shoup_mul(a, ninv, ninv_sh, q); }
 };
 
-__device__ __forceinline__ double f64_mulmod(double a, double w, double q, double qinv) {
-  const double h = a * w;
-  const double l = __fma_rn(a, w, -h);
-  const double k = __builtin_rint(h * qinv);
-  const double r = __fma_rn(-k, q, h) + l;
-  return r < 0.0 ? r + q : r;
-}
 
 struct F64Arith {
   typedef double V;
@@ -489,7 +483,7 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
 }
 
 // moduli below 2^50 take the FP64 arithmetic
-#define NTT_F64_MAX_BITS 50
+#define NTT_F64_MAX_BITS F64_MAX_BITS
 
 template <int LOGN, int GA, int GB, bool INV>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const u64* __restrict__ tw,
@@ -648,8 +642,8 @@ __global__ void k_elementwise(int op, u64* out, const u64* a, const u64* b, int 
   switch (op) {
     case EW_ADD: out[o] = add_mod(a[o], b[ob], mk.q); break;
     case EW_SUB: out[o] = sub_mod(a[o], b[ob], mk.q); break;
-    case EW_MUL: out[o] = mul_mod(a[o], b[ob], mk); break;
-    case EW_MULACC: out[o] = add_mod(out[o], mul_mod(a[o], b[ob], mk), mk.q); break;
+    case EW_MUL: out[o] = mul_mod_any(a[o], b[ob], mk); break;
+    case EW_MULACC: out[o] = add_mod(out[o], mul_mod_any(a[o], b[ob], mk), mk.q); break;
     case EW_NEG: out[o] = a[o] ? mk.q - a[o] : 0; break;
   }
 }
@@ -690,7 +684,7 @@ __global__ void k_mul_sum(u64* out, SumTerms t, int nterms, int accumulate, int 
   const ModConst mk = mc[m];
   const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
   u64 acc = accumulate ? out[o] : 0;
-  for (int j = 0; j < nterms; j++) acc = add_mod(acc, mul_mod(t.a[j][o], t.p[j][op], mk), mk.q);
+  for (int j = 0; j < nterms; j++) acc = add_mod(acc, mul_mod_any(t.a[j][o], t.p[j][op], mk), mk.q);
   out[o] = acc;
 }
 void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms, int nl,
@@ -726,7 +720,7 @@ __global__ void k_mul_const(u64* out, const u64* a, int nlimbs, ConstPairs c, Li
   if (m < 0) return;
   int ci = k % map.n;
   size_t o = (size_t)k * N + i;
-  out[o] = shoup_mul(a[o], c.w[2 * ci], c.w[2 * ci + 1], mc[m].q);
+  out[o] = mul_const_any(a[o], c.w[2 * ci], c.w[2 * ci + 1], mc[m]);
 }
 void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const u64* consts,
                       const LimbMap& m, hipStream_t s) {
@@ -751,9 +745,9 @@ __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, i
   const ModConst mk = mc[k % nl];
   size_t o0 = (size_t)k * N + i, o1 = (size_t)(nt + k) * N + i, o2 = (size_t)(2 * nt + k) * N + i;
   u64 a0 = a[o0], a1 = a[o1], b0 = b[o0], b1 = b[o1];
-  u64 t0 = mul_mod(a0, b0, mk);
-  u64 t1 = add_mod(mul_mod(a0, b1, mk), mul_mod(a1, b0, mk), mk.q);
-  u64 t2 = mul_mod(a1, b1, mk);
+  u64 t0 = mul_mod_any(a0, b0, mk);
+  u64 t1 = add_mod(mul_mod_any(a0, b1, mk), mul_mod_any(a1, b0, mk), mk.q);
+  u64 t2 = mul_mod_any(a1, b1, mk);
   if (ACC) {
     t0 = add_mod(t0, out[o0], mk.q);
     t1 = add_mod(t1, out[o1], mk.q);
@@ -813,10 +807,12 @@ __global__ void k_modup(u64* digits, const u64* coef, const u64* ntt_in, ModupAr
   ntt_in += (size_t)blockIdx.z * A.nq * N;
   const int ns = A.ns[j];
   u64 y[4];
+  u32 src_bits = 0;
   for (int a = 0; a < ns; a++) {
     int sm = j * A.alpha + a;
     u64 x = coef[(size_t)sm * N + i];
-    y[a] = shoup_mul(x, A.hatinv[j][a], A.hatinv_sh[j][a], mc[sm].q);
+    y[a] = mul_const_any(x, A.hatinv[j][a], A.hatinv_sh[j][a], mc[sm]);
+    src_bits = max(src_bits, mc[sm].bits);
   }
   for (int pos = 0; pos < A.nqp; pos++) {
     u64* o = digits + ((size_t)j * A.nqp + pos) * N + i;
@@ -825,11 +821,23 @@ __global__ void k_modup(u64* digits, const u64* coef, const u64* ntt_in, ModupAr
       continue;
     }
     int m = pos < A.nq ? pos : A.L + 1 + (pos - A.nq);
-    u64 q = mc[m].q, acc = 0;
-    for (int a = 0; a < ns; a++)
-      acc = add_mod(acc, shoup_mul(y[a], A.hat_t[j][(size_t)a * nmods + m], A.hat_t_sh[j][(size_t)a * nmods + m], q),
-                    q);
-    *o = acc;
+    const ModConst& mt = mc[m];
+    const u64* hat = A.hat_t[j] + m;
+    const u64* hat_sh = A.hat_t_sh[j] + m;
+    if (mt.bits <= F64_MAX_BITS && src_bits <= mt.bits + 1) {
+      // inputs below 2 q_t: the FP64 product stays exact
+      double acc = 0.0;
+      for (int a = 0; a < ns; a++) {
+        acc += f64_mulmod((double)y[a], (double)hat[(size_t)a * nmods], mt.qf, mt.qinvf);
+        acc = acc >= mt.qf ? acc - mt.qf : acc;
+      }
+      *o = (u64)acc;
+    } else {
+      u64 acc = 0;
+      for (int a = 0; a < ns; a++)
+        acc = add_mod(acc, shoup_mul(y[a], hat[(size_t)a * nmods], hat_sh[(size_t)a * nmods], mt.q), mt.q);
+      *o = acc;
+    }
   }
 }
 
@@ -959,7 +967,7 @@ __global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, co
   if (i >= N) return;
   u64 q = mc[t].q;
   u64 d = sub_mod(x[((size_t)p * x_stride_limbs + t) * N + i], y[((size_t)p * nq + t) * N + i], q);
-  out[((size_t)p * nq + t) * N + i] = shoup_mul(d, pinv[2 * t], pinv[2 * t + 1], q);
+  out[((size_t)p * nq + t) * N + i] = mul_const_any(d, pinv[2 * t], pinv[2 * t + 1], mc[t]);
 }
 void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u64* y, int nq, const u64* pinv,
                           int npoly, int x_stride_limbs, hipStream_t s) {
@@ -974,6 +982,48 @@ void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u
 // Each key word is read once and applied to every member.
 // digits [B][beta][nqp][N], c0 [B][nq][N], out [2][B][nqp][N]
 #define MS_MAXB 8
+// key inner product of MB members, in the arithmetic A (the FP64 or the
+// integer one; identical residues)
+template <int MB, bool F64>
+__device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ digits, const u64* __restrict__ key,
+                                             const u64* __restrict__ c0, const u64* __restrict__ pmod, int nq,
+                                             int nqp, int beta, int nmods, int B, int b0, int m, int pos, u32 i,
+                                             u32 src, u64 N, const ModConst& mk) {
+  typedef typename std::conditional<F64, double, u64>::type V;
+  V acc0[MB], acc1[MB];
+#pragma unroll
+  for (int b = 0; b < MB; b++) acc0[b] = acc1[b] = 0;
+  const size_t dstride = (size_t)beta * nqp * N;
+  for (int j = 0; j < beta; j++) {
+    const u64 kb = key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
+    const u64 ka = key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
+#pragma unroll
+    for (int b = 0; b < MB; b++) {
+      const u64 d = digits[(size_t)(b0 + b) * dstride + ((size_t)j * nqp + pos) * N + src];
+      if (F64) {
+        const double q = mk.qf, qi = mk.qinvf, dd = (double)d;
+        double t0 = (double)acc0[b] + f64_mulmod(dd, (double)kb, q, qi);
+        double t1 = (double)acc1[b] + f64_mulmod(dd, (double)ka, q, qi);
+        acc0[b] = (V)(t0 >= q ? t0 - q : t0);
+        acc1[b] = (V)(t1 >= q ? t1 - q : t1);
+      } else {
+        acc0[b] = (V)add_mod((u64)acc0[b], mul_mod(d, kb, mk), mk.q);
+        acc1[b] = (V)add_mod((u64)acc1[b], mul_mod(d, ka, mk), mk.q);
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < MB; b++) {
+    u64 r0 = (u64)acc0[b];
+    if (c0 && pos < nq) {
+      const u64 v = c0[((size_t)(b0 + b) * nq + pos) * N + src];
+      r0 = add_mod(r0, mul_const_any(v, pmod[2 * m], pmod[2 * m + 1], mk), mk.q);
+    }
+    out[((size_t)(b0 + b) * nqp + pos) * N + i] = r0;
+    out[((size_t)(B + b0 + b) * nqp + pos) * N + i] = (u64)acc1[b];
+  }
+}
+
 template <int MB>
 __global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict__ digits,
                                                  const u64* __restrict__ key, const u64* __restrict__ c0,
@@ -987,29 +1037,10 @@ __global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict
   int m = pos < nq ? pos : L + 1 + (pos - nq);
   const ModConst mk = mc[m];
   u32 src = g == 1 ? i : automorph_src(i, g, logN);
-  u64 acc0[MB], acc1[MB];
-#pragma unroll
-  for (int b = 0; b < MB; b++) acc0[b] = acc1[b] = 0;
-  const size_t dstride = (size_t)beta * nqp * N;
-  for (int j = 0; j < beta; j++) {
-    u64 kb = key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
-    u64 ka = key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
-#pragma unroll
-    for (int b = 0; b < MB; b++) {
-      u64 d = digits[(size_t)(b0 + b) * dstride + ((size_t)j * nqp + pos) * N + src];
-      acc0[b] = add_mod(acc0[b], mul_mod(d, kb, mk), mk.q);
-      acc1[b] = add_mod(acc1[b], mul_mod(d, ka, mk), mk.q);
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < MB; b++) {
-    if (c0 && pos < nq) {
-      u64 v = c0[((size_t)(b0 + b) * nq + pos) * N + src];
-      acc0[b] = add_mod(acc0[b], shoup_mul(v, pmod[2 * m], pmod[2 * m + 1], mk.q), mk.q);
-    }
-    out[((size_t)(b0 + b) * nqp + pos) * N + i] = acc0[b];
-    out[((size_t)(B + b0 + b) * nqp + pos) * N + i] = acc1[b];
-  }
+  if (mk.bits <= F64_MAX_BITS)
+    multsum_body<MB, true>(out, digits, key, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk);
+  else
+    multsum_body<MB, false>(out, digits, key, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk);
 }
 void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,
                     const u64* pmod, int level, int L, int alpha, int beta, u64 g, int batch, hipStream_t s) {
@@ -1039,7 +1070,7 @@ __global__ void k_plift(u64* out, const u64* c, const u64* pmod, int nq, int nqp
   int pos = blockIdx.y, p = blockIdx.z;
   if (i >= N) return;
   u64 v = 0;
-  if (pos < nq) v = shoup_mul(c[((size_t)p * nq + pos) * N + i], pmod[2 * pos], pmod[2 * pos + 1], mc[pos].q);
+  if (pos < nq) v = mul_const_any(c[((size_t)p * nq + pos) * N + i], pmod[2 * pos], pmod[2 * pos + 1], mc[pos]);
   out[((size_t)p * nqp + pos) * N + i] = v;
 }
 void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha, int npoly,
@@ -1083,7 +1114,7 @@ __global__ void k_rescale_final(u64* out, const u64* x, const u64* t, int l, int
   if (i >= N) return;
   u64 q = mc[k].q;
   u64 d = sub_mod(x[((size_t)p * x_stride_limbs + k) * N + i], t[((size_t)p * l + k) * N + i], q);
-  out[((size_t)p * l + k) * N + i] = shoup_mul(d, qlinv[2 * k], qlinv[2 * k + 1], q);
+  out[((size_t)p * l + k) * N + i] = mul_const_any(d, qlinv[2 * k], qlinv[2 * k + 1], mc[k]);
 }
 void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u64* t, int l, int npoly,
                           int x_stride_limbs, const u64* qlinv, hipStream_t s) {
