@@ -1042,6 +1042,81 @@ __global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict
   else
     multsum_body<MB, false>(out, digits, key, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk);
 }
+// Several hoisted rotations of one decomposition in one launch.  A
+// work-group takes a 256-coefficient block S of the digits and one rotation
+// r: the automorphism maps the aligned block S onto an aligned block (it
+// permutes inside it), so thread t reads digit s = 256 S + t contiguously and
+// produces output i = pi_{g_r}^{-1}(s) with the key read at i.  Work-groups of
+// one source block for all rotations are spaced eight apart in dispatch
+// order, so they land on the same XCD back to back and the digits come from
+// its L2 after the first rotation: HBM reads them once per launch.
+struct MultiRot {
+  u64* out[MR_MAX];
+  const u64* key[MR_MAX];
+  u64 ginv[MR_MAX];
+};
+template <int MB>
+__global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, int nrot, const u64* __restrict__ digits,
+                                                     const u64* __restrict__ c0, const u64* __restrict__ pmod,
+                                                     int nq, int nqp, int L, int beta, int nmods, int B, int b0,
+                                                     int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  const u32 x = blockIdx.x, rest = x >> 3;
+  const u32 r = rest % (u32)nrot;
+  const u32 S = (rest / (u32)nrot) * 8 + (x & 7);
+  if ((u64)S * TPB >= N) return;
+  const u32 src = S * TPB + threadIdx.x;
+  const int pos = blockIdx.y;
+  const int m = pos < nq ? pos : L + 1 + (pos - nq);
+  const ModConst mk = mc[m];
+  const u32 i = automorph_src(src, R.ginv[r], logN);
+  if (mk.bits <= F64_MAX_BITS)
+    multsum_body<MB, true>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk);
+  else
+    multsum_body<MB, false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N,
+                            mk);
+}
+
+static u64 inv_mod_2n(u64 g, u64 twoN) {
+  // g odd: Newton iteration for the inverse modulo a power of two
+  u64 x = g;  // correct to 3 bits
+  for (int k = 0; k < 6; k++) x *= 2 - g * x;
+  return x & (twoN - 1);
+}
+
+void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
+                        const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
+                        int batch, hipStream_t s) {
+  const int nq = level + 1, nqp = nq + alpha;
+  const u64 twoN = 2 * T.N;
+  const int nblk = cdiv(T.N, TPB);
+  for (int r0 = 0; r0 < nrot; r0 += MR_MAX) {
+    const int nr = std::min(nrot - r0, MR_MAX);
+    MultiRot R;
+    for (int r = 0; r < nr; r++) {
+      R.out[r] = outs[r0 + r];
+      R.key[r] = keys[r0 + r];
+      R.ginv[r] = inv_mod_2n(gs[r0 + r], twoN);
+    }
+    dim3 grid(cdiv(nblk, 8) * 8 * nr, nqp);
+    for (int b0 = 0; b0 < batch; b0 += MS_MAXB) {
+      const int mb = batch - b0 < MS_MAXB ? batch - b0 : MS_MAXB;
+      // digits and c0 of the members once, each rotation's key once, outputs once
+      ProfScope ps("multsum", s,
+                   8.0 * T.N * (nr * 2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + nr * 2.0 * nqp)));
+#define MR_CASE(K)                                                                                                 \
+  case K:                                                                                                          \
+    hipLaunchKernelGGL(k_multsum_rot<K>, grid, dim3(TPB), 0, s, R, nr, digits, c0, pmod, nq, nqp, L, beta, T.nmods, \
+                       batch, b0, T.logN, T.mc);                                                                   \
+    break;
+      switch (mb) {
+        MR_CASE(1) MR_CASE(2) MR_CASE(3) MR_CASE(4) MR_CASE(5) MR_CASE(6) MR_CASE(7) MR_CASE(8)
+      }
+#undef MR_CASE
+    }
+  }
+}
+
 void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,
                     const u64* pmod, int level, int L, int alpha, int beta, u64 g, int batch, hipStream_t s) {
   int nq = level + 1, nqp = nq + alpha;

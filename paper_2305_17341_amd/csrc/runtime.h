@@ -107,6 +107,7 @@ struct HeCtxImpl {
   HeCt rescale(const HeCt& a);
   DevBuf decompose(const u64* d, int level, int B = 1);
   HeCt hoisted(const HeCt& x, const u64* digits, u64 g);
+  std::vector<HeCt> hoisted_multi(const HeCt& x, const u64* digits, const std::vector<u64>& gs);
   HeCt moddown(const HeCt& x);
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);

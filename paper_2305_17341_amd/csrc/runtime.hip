@@ -649,6 +649,29 @@ HeCt HeCtxImpl::hoisted(const HeCt& x, const u64* digits, u64 g) {
   return h;
 }
 
+// several hoisted rotations of one decomposition (one launch for all of them)
+std::vector<HeCt> HeCtxImpl::hoisted_multi(const HeCt& x, const u64* digits, const std::vector<u64>& gs) {
+  std::vector<HeCt> out(gs.size());
+  std::vector<u64*> outs;
+  std::vector<const u64*> ks;
+  std::vector<u64> g2;
+  for (size_t r = 0; r < gs.size(); r++) {
+    out[r] = ct_new(x.level, true, x.scale, x.B);
+    if (gs[r] == 1) {
+      launch_plift(T, out[r].d.p, x.d.p, pmod.p, x.level, alpha, (int)x.polys(), stream);
+      continue;
+    }
+    outs.push_back(out[r].d.p);
+    ks.push_back(key(gs[r]).p);
+    g2.push_back(gs[r]);
+  }
+  if (!outs.empty())
+    launch_multsum_rot(T, outs.data(), ks.data(), g2.data(), (int)outs.size(), digits, x.poly(0), pmod.p, x.level,
+                       L, alpha, beta_at(x.level), x.B, stream);
+  n_multsum += (long)x.B * (long)outs.size();
+  return out;
+}
+
 // ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact centred residue
 HeCt HeCtxImpl::moddown(const HeCt& x) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
@@ -868,8 +891,17 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
   // Decompose once, baby-step hoisted rotations kept in R_{Q_l P}
   DevBuf dig = decompose(x.poly(1), level, x.B);
   std::vector<HeCt> baby(n1);
-  for (int j = 0; j < n1; j++)
-    if (used[j]) baby[j] = hoisted(x, dig.p, galois((long)G.a * j));
+  {
+    std::vector<u64> gs;
+    std::vector<int> js;
+    for (int j = 0; j < n1; j++)
+      if (used[j]) {
+        gs.push_back(galois((long)G.a * j));
+        js.push_back(j);
+      }
+    std::vector<HeCt> hs = hoisted_multi(x, dig.p, gs);
+    for (size_t t = 0; t < js.size(); t++) baby[js[t]] = std::move(hs[t]);
+  }
   dig.release();
   LimbMap qpm = qpmap(level);
   HeCt acc = ct_new(level, true, x.scale * ql, x.B);
@@ -1069,22 +1101,31 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       Bb = rotate(Bb, n1z);
       Bpb = rotate(Bpb, n1z);
     }
-    DevBuf d1 = decompose(Bb.poly(1), lvl, Bb.B);
-    DevBuf d2 = decompose(Bpb.poly(1), lvl, Bpb.B);
-    for (int r = 0; r < n1z && b * n1z + r < n; r++) {
+    // all n1z hoisted rotations of each base in one launch per base
+    const int nr = std::min(n1z, n - b * n1z);
+    std::vector<u64> gs(nr);
+    for (int r = 0; r < nr; r++) gs[r] = galois(r);
+    std::vector<HeCt> h1, h2;
+    {
+      DevBuf d1 = decompose(Bb.poly(1), lvl, Bb.B);
+      h1 = hoisted_multi(Bb, d1.p, gs);
+    }
+    {
+      DevBuf d2 = decompose(Bpb.poly(1), lvl, Bpb.B);
+      // k = 0 has no second term
+      std::vector<u64> gs2(gs.begin() + (b == 0 ? 1 : 0), gs.end());
+      std::vector<HeCt> t = hoisted_multi(Bpb, d2.p, gs2);
+      h2.resize(nr);
+      for (size_t u = 0; u < t.size(); u++) h2[u + (b == 0 ? 1 : 0)] = std::move(t[u]);
+    }
+    for (int r = 0; r < nr; r++) {
       int k = b * n1z + r;
-      u64 g = galois(r);
       HeCt acc = ct_new(lvl, true, Bb.scale * ql, Bb.B);
-      HeCt h1 = hoisted(Bb, d1.p, g), h2;
-      const u64* ta[2] = {h1.d.p, nullptr};
+      const u64* ta[2] = {h1[r].d.p, k > 0 ? h2[r].d.p : nullptr};
       const u64* tp[2] = {mask_of(k, 0), mask_of(k, 1)};
-      if (k > 0) {
-        h2 = hoisted(Bpb, d2.p, g);
-        ta[1] = h2.d.p;
-      }
       launch_mul_sum(T, acc.d.p, ta, tp, k > 0 ? 2 : 1, 2 * Bb.B * nqp, nqp, qpm, false, stream);
-      h1 = HeCt();
-      h2 = HeCt();
+      h1[r] = HeCt();
+      if (k > 0) h2[r] = HeCt();
       HeCt md = moddown(acc);
       Ak[k] = rescale(md);
       Ak[k].scale = Bb.scale;
@@ -1100,15 +1141,18 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int n
   std::vector<HeCt> Bk(n);
   for (int b = 0; b * n1t < n; b++) {
     if (b > 0) Cb = rotate(Cb, (long)n * n1t);
-    DevBuf d1 = decompose(Cb.poly(1), lvl, Cb.B);
-    for (int r = 0; r < n1t && b * n1t + r < n; r++) {
-      int k = b * n1t + r;
-      if (r == 0) {
-        Bk[k] = ct_copy(Cb);
-      } else {
-        HeCt h = hoisted(Cb, d1.p, galois((long)n * r));
-        Bk[k] = moddown(h);
-      }
+    const int nr = std::min(n1t, n - b * n1t);
+    std::vector<HeCt> hs;
+    {
+      DevBuf d1 = decompose(Cb.poly(1), lvl, Cb.B);
+      std::vector<u64> gs;
+      for (int r = 1; r < nr; r++) gs.push_back(galois((long)n * r));
+      hs = hoisted_multi(Cb, d1.p, gs);
+    }
+    Bk[b * n1t] = ct_copy(Cb);
+    for (int r = 1; r < nr; r++) {
+      Bk[b * n1t + r] = moddown(hs[r - 1]);
+      hs[r - 1] = HeCt();
     }
   }
   return Bk;

@@ -61,12 +61,13 @@ def product_footprint(log_n: int, top_level: int, alpha: int, d: int, batch: int
     `batch` stacked members: the n column-shifted A_k (level l-2) and the n
     row-shifted B_k (level l-1) held together before the products, plus the
     largest transient of a linear transform (n1 baby-step rotations in
-    R_{Q_l P}, the digits of one decomposition and a few accumulators), plus
-    stacked copies of the inputs and the output."""
+    R_{Q_l P}, or the 2 n1 of the column shifts, the digits of one
+    decomposition and a few accumulators), plus stacked copies of the
+    inputs and the output."""
     l = top_level
     n1 = default_n1(d)
     sides = d * 2 * (l - 1) + d * 2 * l
-    trans = 2 * (n1 + 4) * _qp(l, alpha) + _beta(l, alpha) * _qp(l, alpha) + 6 * (l + 1)
+    trans = 2 * (2 * n1 + 4) * _qp(l, alpha) + _beta(l, alpha) * _qp(l, alpha) + 6 * (l + 1)
     io = 4 * (l + 1) + 2 * (l - 2)
     words = batch * (sides + trans + io) << log_n
     return int(math.ceil(words * 8 * POOL_SLACK))
@@ -80,7 +81,7 @@ def covariance_footprint(log_n: int, top_level: int, alpha: int, d: int, k: int)
     n1 = default_n1(d)
     sides = 2 * k * d * 2 * l
     acc = k * k * 2 * l
-    trans = 2 * (n1 + 4) * _qp(l, alpha) + _beta(l, alpha) * _qp(l, alpha) + 8 * (l + 1)
+    trans = 2 * (2 * n1 + 4) * _qp(l, alpha) + _beta(l, alpha) * _qp(l, alpha) + 8 * (l + 1)
     words = (sides + acc + trans) << log_n
     return int(math.ceil(words * 8 * POOL_SLACK))
 
