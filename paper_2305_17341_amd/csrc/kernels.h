@@ -44,6 +44,12 @@ void launch_mul_acc(const DeviceTables& T, u64* acc, const u64* a, const u64* b,
 #define SUM_MAX_TERMS 16
 void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms,
                     int nlimbs, int b_limbs, const LimbMap& m, bool accumulate, hipStream_t s);
+// outs[g] = sum_t a[t] * p[g * nterms + t] for g < nouts (null p: term absent);
+// false (nothing launched) beyond SUM_MAX_OUTS outputs or SUM_MAX_TERMS terms
+#define SUM_MAX_OUTS 4
+bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, const u64* const* a,
+                          const u64* const* p, int nterms, int nlimbs, int b_limbs, const LimbMap& m,
+                          hipStream_t s);
 // out = a * c_k for a per-limb constant (host array, Shoup)
 void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const u64* consts /*[map.n]*/,
                       const LimbMap& m, hipStream_t s);
@@ -68,6 +74,7 @@ struct FbcTable {
   u64 Hw[8][4];
   double qd[8];
   u64* D_mod_t = nullptr;   // device [nmods][2]
+  double* hat_f = nullptr;  // device [ns][nmods][3]: hat mod t, 2^32 hat mod t, D mod t (FP64 path)
 };
 // digits[j][pos] (pos over Q_l then P): own limbs copy ntt_in, others are the
 // coefficient-domain conversion of digit j (to be transformed by the caller)

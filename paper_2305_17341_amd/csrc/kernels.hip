@@ -703,6 +703,61 @@ void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const 
   }
 }
 
+// G sums at once over shared terms: out_g = sum_t a_t (.) p_(g,t) (p_(g,t) may be
+// absent); each a_t is read once for all G outputs
+struct SumMulti {
+  const u64* a[SUM_MAX_TERMS];
+  const u64* p[SUM_MAX_OUTS][SUM_MAX_TERMS];
+  u64* out[SUM_MAX_OUTS];
+};
+template <int G>
+__global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map, int logN,
+                                const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= N) return;
+  int m = limb_mod(map, k);
+  if (m < 0) return;
+  const ModConst mk = mc[m];
+  const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
+  u64 acc[G];
+#pragma unroll
+  for (int g = 0; g < G; g++) acc[g] = 0;
+  for (int j = 0; j < nterms; j++) {
+    const u64 x = t.a[j][o];
+#pragma unroll
+    for (int g = 0; g < G; g++)
+      if (t.p[g][j]) acc[g] = add_mod(acc[g], mul_mod_any(x, t.p[g][j][op], mk), mk.q);
+  }
+#pragma unroll
+  for (int g = 0; g < G; g++) t.out[g][o] = acc[g];
+}
+bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, const u64* const* a,
+                          const u64* const* p /* [nouts][nterms], null = absent */, int nterms, int nl, int bl,
+                          const LimbMap& m, hipStream_t s) {
+  if (nterms > SUM_MAX_TERMS || nouts > SUM_MAX_OUTS || nouts < 1 || nterms < 1) return false;
+  SumMulti t;
+  int present = 0;
+  for (int j = 0; j < nterms; j++) t.a[j] = a[j];
+  for (int g = 0; g < SUM_MAX_OUTS; g++) {
+    t.out[g] = g < nouts ? outs[g] : nullptr;
+    for (int j = 0; j < SUM_MAX_TERMS; j++) {
+      t.p[g][j] = (g < nouts && j < nterms) ? p[(size_t)g * nterms + j] : nullptr;
+      present += t.p[g][j] != nullptr;
+    }
+  }
+  ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nterms + nouts) + (double)bl * present));
+  dim3 grid(cdiv(T.N, TPB), nl);
+  switch (nouts) {
+    case 1: hipLaunchKernelGGL(k_mul_sum_multi<1>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc); break;
+    case 2: hipLaunchKernelGGL(k_mul_sum_multi<2>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc); break;
+    case 3: hipLaunchKernelGGL(k_mul_sum_multi<3>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc); break;
+    default: hipLaunchKernelGGL(k_mul_sum_multi<4>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc); break;
+  }
+  return true;
+}
+
 void launch_neg(const DeviceTables& T, u64* out, const u64* a, int nl, const LimbMap& m, hipStream_t s) {
   ew(T, EW_NEG, out, a, a, nl, nl, m, s);
 }
@@ -800,12 +855,19 @@ __global__ void k_modup(u64* digits, const u64* coef, const u64* ntt_in, ModupAr
   const u64 N = 1ull << logN;
   u32 i = blockIdx.x * TPB + threadIdx.x;
   int j = blockIdx.y;
-  if (i >= N) return;
   // batch member blockIdx.z: inputs [B][nq][N], digits [B][beta][nqp][N]
   digits += (size_t)blockIdx.z * A.beta * A.nqp * N;
   coef += (size_t)blockIdx.z * A.nq * N;
   ntt_in += (size_t)blockIdx.z * A.nq * N;
   const int ns = A.ns[j];
+  // the digit's conversion constants (ns x nmods, with Shoup companions) staged in LDS
+  __shared__ u64 hat_l[4 * HE_MAXMOD], hat_sh_l[4 * HE_MAXMOD];
+  for (int e = threadIdx.x; e < ns * nmods; e += TPB) {
+    hat_l[e] = A.hat_t[j][e];
+    hat_sh_l[e] = A.hat_t_sh[j][e];
+  }
+  __syncthreads();
+  if (i >= N) return;
   u64 y[4];
   u32 src_bits = 0;
   for (int a = 0; a < ns; a++) {
@@ -822,8 +884,8 @@ __global__ void k_modup(u64* digits, const u64* coef, const u64* ntt_in, ModupAr
     }
     int m = pos < A.nq ? pos : A.L + 1 + (pos - A.nq);
     const ModConst& mt = mc[m];
-    const u64* hat = A.hat_t[j] + m;
-    const u64* hat_sh = A.hat_t_sh[j] + m;
+    const u64* hat = hat_l + m;
+    const u64* hat_sh = hat_sh_l + m;
     if (mt.bits <= F64_MAX_BITS && src_bits <= mt.bits + 1) {
       // inputs below 2 q_t: the FP64 product stays exact
       double acc = 0.0;
@@ -871,8 +933,9 @@ struct FbcArgs {
   const u64* hat_t_sh;
   u64 Dw[4];
   u64 Hw[4][4];
-  double qd[4];
+  double qrecip[4];   // 1 / q_a of the sources
   const u64* D_mod_t;
+  const double* hat_f;
 };
 
 // acc (4 words) += H (4 words) * y, carries beyond the top word dropped
@@ -896,11 +959,12 @@ __device__ __forceinline__ int w4_cmp(const u64 a[4], const u64 b[4]) {
 }
 
 // round(S / D) for S = sum_a y_a (D / q_a), 0 <= y_a < q_a: a double estimate
-// of sum_a y_a / q_a, replaced by an exact multiword comparison when the
-// estimate lies within 2^-40 of a rounding boundary (its error is < 2^-47).
+// of sum_a y_a / q_a (products with the rounded reciprocals: error below
+// ns 2^-52), replaced by an exact multiword comparison when the estimate lies
+// within 2^-40 of a rounding boundary.
 __device__ __forceinline__ u64 round_quotient(const u64* y, const FbcArgs& A) {
   double f = 0.0;
-  for (int a = 0; a < A.ns; a++) f += (double)y[a] / A.qd[a];
+  for (int a = 0; a < A.ns; a++) f += (double)y[a] * A.qrecip[a];
   double t = f + 0.5;
   double fl = floor(t);
   double fr = t - fl;
@@ -931,11 +995,28 @@ __global__ void k_fbc_to_q(u64* y, const u64* xp, int nq, FbcArgs A, int logN, i
   for (int a = 0; a < A.ns; a++) v[a] = shoup_mul(x[(size_t)a * N + i], A.hatinv[a], A.hatinv_sh[a], mc[A.src[a]].q);
   const u64 r = round_quotient(v, A);
   for (int t = blockIdx.y; t < nq; t += gridDim.y) {
-    u64 q = mc[t].q, acc = 0;
-    for (int a = 0; a < A.ns; a++)
-      acc = add_mod(acc, shoup_mul(v[a], A.hat_t[(size_t)a * nmods + t], A.hat_t_sh[(size_t)a * nmods + t], q), q);
-    acc = sub_mod(acc, shoup_mul(r, A.D_mod_t[2 * t], A.D_mod_t[2 * t + 1], q), q);
-    yy[(size_t)t * N + i] = acc;
+    const ModConst& mt = mc[t];
+    if (mt.bits <= F64_MAX_BITS) {
+      // v = v_hi 2^32 + v_lo with both halves below q_t: two exact FP64 products
+      const double q = mt.qf, qi = mt.qinvf;
+      double acc = 0.0;
+      for (int a = 0; a < A.ns; a++) {
+        const double* e = A.hat_f + ((size_t)a * nmods + t) * 3;
+        acc += f64_mulmod((double)(v[a] & 0xffffffffull), e[0], q, qi);
+        acc = acc >= q ? acc - q : acc;
+        acc += f64_mulmod((double)(v[a] >> 32), e[1], q, qi);
+        acc = acc >= q ? acc - q : acc;
+      }
+      acc -= f64_mulmod((double)r, A.hat_f[(size_t)t * 3 + 2], q, qi);
+      acc = acc < 0.0 ? acc + q : acc;
+      yy[(size_t)t * N + i] = (u64)acc;
+    } else {
+      u64 q = mt.q, acc = 0;
+      for (int a = 0; a < A.ns; a++)
+        acc = add_mod(acc, shoup_mul(v[a], A.hat_t[(size_t)a * nmods + t], A.hat_t_sh[(size_t)a * nmods + t], q), q);
+      acc = sub_mod(acc, shoup_mul(r, A.D_mod_t[2 * t], A.D_mod_t[2 * t + 1], q), q);
+      yy[(size_t)t * N + i] = acc;
+    }
   }
 }
 void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
@@ -946,15 +1027,16 @@ void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, 
     A.src[a] = tab.src[a];
     A.hatinv[a] = tab.hatinv[a];
     A.hatinv_sh[a] = tab.hatinv_sh[a];
-    A.qd[a] = tab.qd[a];
+    A.qrecip[a] = 1.0 / tab.qd[a];
     for (int w = 0; w < 4; w++) A.Hw[a][w] = tab.Hw[a][w];
   }
   for (int w = 0; w < 4; w++) A.Dw[w] = tab.Dw[w];
   A.hat_t = tab.hat_t;
   A.hat_t_sh = tab.hat_t_sh;
   A.D_mod_t = tab.D_mod_t;
+  A.hat_f = tab.hat_f;
   ProfScope ps("fbc_to_q", s, 8.0 * T.N * npoly * ((double)tab.ns + nq));
-  dim3 grid(cdiv(T.N, TPB), nq < 8 ? nq : 8, npoly);
+  dim3 grid(cdiv(T.N, TPB), nq < 4 ? nq : 4, npoly);
   hipLaunchKernelGGL(k_fbc_to_q, grid, dim3(TPB), 0, s, y, xp_coef, nq, A, T.logN, T.nmods, T.mc);
 }
 

@@ -250,6 +250,19 @@ static FbcTable make_fbc(HeCtxImpl* c, const std::vector<int>& src) {
     dm[2 * m + 1] = shoup_pre(d, qt);
   }
   t.D_mod_t = c->table_upload(dm.data(), dm.size() * 8);
+  // FP64 form for targets below 2^50: a source value v (any size below 2^64)
+  // is split v = v_hi 2^32 + v_lo, and v hat = v_lo hat + v_hi (2^32 hat) mod
+  // q_t, both factors below q_t: [a][t] = (hat mod q_t, 2^32 hat mod q_t, D mod q_t)
+  std::vector<double> hf((size_t)t.ns * c->nmods * 3);
+  for (int a = 0; a < t.ns; a++)
+    for (int m = 0; m < c->nmods; m++) {
+      u64 qt = c->mods[m], h = hat[(size_t)a * c->nmods + m];
+      double* e = &hf[((size_t)a * c->nmods + m) * 3];
+      e[0] = (double)h;
+      e[1] = (double)hmul(h, (u64)(((u128)1 << 32) % qt), qt);
+      e[2] = (double)dm[2 * m];
+    }
+  t.hat_f = (double*)c->table_upload(hf.data(), hf.size() * 8);
   return t;
 }
 
@@ -906,30 +919,60 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
   LimbMap qpm = qpmap(level);
   HeCt acc = ct_new(level, true, x.scale * ql, x.B);
   bool acc_set = false;
-  size_t e = 0;
-  for (int i = G.i_lo; i < G.i_hi; i++) {
-    // inner = sum_j baby_j (.) diagonal_(i,j), one pass over all of them
-    std::vector<const u64*> ta, tp;
-    for (; e < ij.size() && ij[e].first == i; e++) {
-      ta.push_back(baby[ij[e].second].d.p);
-      tp.push_back(pts[e]);
+  // giant steps with at least one diagonal: (j, index into pts) per step
+  std::map<int, std::vector<std::pair<int, size_t>>> by_i;
+  for (size_t e = 0; e < ij.size(); e++) by_i[ij[e].first].push_back({ij[e].second, e});
+  std::vector<int> gi;
+  for (auto& kv : by_i) gi.push_back(kv.first);
+  const int nl = 2 * x.B * nqp;
+  for (size_t c0 = 0; c0 < gi.size(); c0 += SUM_MAX_OUTS) {
+    const int ng = (int)std::min<size_t>(SUM_MAX_OUTS, gi.size() - c0);
+    // inner_i = sum_j baby_j (.) diagonal_(i,j) for ng giant steps in one pass over the babies
+    std::vector<int> col(n1, -1), jl;
+    for (int g = 0; g < ng; g++)
+      for (auto& je : by_i[gi[c0 + g]])
+        if (col[je.first] < 0) {
+          col[je.first] = (int)jl.size();
+          jl.push_back(je.first);
+        }
+    const int nt = (int)jl.size();
+    std::vector<const u64*> ta(nt), tp((size_t)ng * nt, nullptr);
+    for (int t = 0; t < nt; t++) ta[t] = baby[jl[t]].d.p;
+    std::vector<HeCt> inner(ng);
+    std::vector<u64*> outs(ng);
+    for (int g = 0; g < ng; g++) {
+      for (auto& je : by_i[gi[c0 + g]]) tp[(size_t)g * nt + col[je.first]] = pts[je.second];
+      inner[g] = ct_new(level, true, x.scale * ql, x.B);
+      outs[g] = inner[g].d.p;
     }
-    if (ta.empty()) continue;
-    HeCt inner = ct_new(level, true, x.scale * ql, x.B);
-    launch_mul_sum(T, inner.d.p, ta.data(), tp.data(), (int)ta.size(), 2 * x.B * nqp, nqp, qpm, false, stream);
-    HeCt term;
-    if (i == 0) {
-      term = std::move(inner);
-    } else {
-      HeCt t = moddown(inner);
-      DevBuf d2 = decompose(t.poly(1), level, t.B);
-      term = hoisted(t, d2.p, galois((long)G.a * n1 * i));
+    if (!launch_mul_sum_multi(T, outs.data(), ng, ta.data(), tp.data(), nt, nl, nqp, qpm, stream)) {
+      for (int g = 0; g < ng; g++) {
+        std::vector<const u64*> a1, p1;
+        for (int t = 0; t < nt; t++)
+          if (tp[(size_t)g * nt + t]) {
+            a1.push_back(ta[t]);
+            p1.push_back(tp[(size_t)g * nt + t]);
+          }
+        launch_mul_sum(T, outs[g], a1.data(), p1.data(), (int)a1.size(), nl, nqp, qpm, false, stream);
+      }
     }
-    if (!acc_set) {
-      acc = std::move(term);
-      acc_set = true;
-    } else {
-      add_into(acc, term);
+    for (int g = 0; g < ng; g++) {
+      const int i = gi[c0 + g];
+      HeCt term;
+      if (i == 0) {
+        term = std::move(inner[g]);
+      } else {
+        HeCt t = moddown(inner[g]);
+        inner[g] = HeCt();
+        DevBuf d2 = decompose(t.poly(1), level, t.B);
+        term = hoisted(t, d2.p, galois((long)G.a * n1 * i));
+      }
+      if (!acc_set) {
+        acc = std::move(term);
+        acc_set = true;
+      } else {
+        add_into(acc, term);
+      }
     }
   }
   HeCt md = moddown(acc);
