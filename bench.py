@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--paper-relin", action="store_true",
                     help="headline path relinearises every product (default: lazy, once per product)")
     ap.add_argument("--d", type=int, default=128)
@@ -189,6 +190,15 @@ def main():
         log(f"[bench] {args.steps} timed steps ({names[opts['flags'] if opts else 0]}): {t_total:.2f} s")
         return t_total, lat, outs
 
+    tuned = None
+    if not args.no_autotune:
+        from paper_2305_17341_amd import autotune
+        warm = ctx.matmul_batch(cA, cB, [d] * B, opts=head)   # plaintext caches
+        ctx.sync()
+        del warm
+        best, tt = autotune.autotune(ctx, cA, cB, d, opts=head, log=log)
+        tuned = {"knobs": best, "step_ms": tt}
+
     plain_outs = None
     if not args.no_plain:
         t_plain, lat_plain, plain_outs = timed(None, False)
@@ -198,7 +208,8 @@ def main():
         del bp_outs
     c0 = ctx.op_counts()
     t_total, lat, outs = timed(head, True)
-    fams = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "multsum", "modup", "fbc_to_q",
+    fams = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "multsum", "multsum_rot", "modup",
+            "fbc_to_q",
             "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor", "plift"]
     prof = {f: ctx.profile_read(f) for f in fams}
     ctx.profile_enable(False)
@@ -256,6 +267,7 @@ def main():
                                f"uniform[-1,1] FP64 inputs", "d": d, "log_n": chain.log_n, "batch": B,
                    "path": names[head["flags"]], "relinearisation": relin},
         "batched_residues_equal_alone": head_same,
+        "autotune": tuned,
         "plain": None if args.no_plain else {
             "value": round(args.steps * B / t_plain, 4), "unit": "matmuls/s",
             "what": "one product after another, one launch sequence each, relinearisation per product "

@@ -234,6 +234,15 @@ he_status he_power_step(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, 
 he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, he_ct* lambda, he_ct* const* v,
                          he_ct* const* vt, uint32_t axis, he_refresh_fn refresh, void* user, he_ct** cov_out);
 
+/* Launch-shape knobs (process-wide; they regroup work into launches and never
+ * change a residue): "ms_members" (1..8, batch members per key inner product
+ * launch), "mr_members" (1..8) and "mr_rotations" (1..16) (members and
+ * rotations per multi-rotation launch).  Set them between calls, not while
+ * another thread drives the library.  The autotuner in the Python package
+ * picks them by timing. */
+he_status he_knob_set(const char* name, int32_t value);
+he_status he_knob_get(const char* name, int32_t* value);
+
 /* wait for all work of the context */
 he_status he_sync(he_ctx* ctx);
 /* device bytes held by the context (live, cached, peak) */
@@ -260,7 +269,7 @@ he_status he_last_op_ms(const he_ctx* ctx, double* ms);
 
 /* Device-time profile by kernel: "ntt_fwd_cols", "ntt_fwd_rows",
  * "ntt_inv_rows", "ntt_inv_cols" (the two passes of each transform),
- * "multsum", "modup", "fbc_to_q", "moddown_final", "rescale_lift",
+ * "multsum", "multsum_rot" (several rotations of one decomposition), "modup", "fbc_to_q", "moddown_final", "rescale_lift",
  * "rescale_final", "elementwise", "tensor", "plift".  While enabled, HIP
  * events are recorded on the launching stream around every launch of the
  * kernel.  Enabling clears the totals.  `bytes` (may be NULL) receives the

@@ -1,0 +1,39 @@
+"""Launch-shape autotuner: times the batched product under each value of the
+library's knobs (members and rotations per launch) and keeps the fastest.
+The knobs only regroup work into launches, so every choice gives the same
+residues; the timing decides."""
+from __future__ import annotations
+
+import time
+
+from . import he
+
+CANDIDATES = {
+    "mr_members": (2, 4, 8),
+    "mr_rotations": (4, 8, 16),
+    "ms_members": (4, 8),
+}
+
+
+def autotune(ctx, cA, cB, d, opts=None, candidates=CANDIDATES, log=None):
+    """Coordinate descent over the knobs, one batched step per candidate
+    value (the plaintext caches must be warm).  Leaves the best values set
+    and returns (best, timings in ms)."""
+    best = {k: he.knob_get(k) for k in candidates}
+    timings = {}
+    for name, values in candidates.items():
+        res = {}
+        for v in values:
+            he.knob_set(name, v)
+            ctx.sync()
+            t0 = time.perf_counter()
+            outs = ctx.matmul_batch(cA, cB, [d] * len(cA), opts=opts)
+            ctx.sync()
+            res[v] = 1e3 * (time.perf_counter() - t0)
+            del outs
+        best[name] = min(res, key=res.get)
+        he.knob_set(name, best[name])
+        timings[name] = {str(k): round(v, 2) for k, v in res.items()}
+        if log:
+            log(f"[autotune] {name}: " + ", ".join(f"{k}={v:.1f} ms" for k, v in res.items()) + f" -> {best[name]}")
+    return best, timings

@@ -508,6 +508,21 @@ he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d,
   });
 }
 
+he_status he_knob_set(const char* name, int32_t value) {
+  return guard_host([&] {
+    need(name != nullptr, "null name");
+    if (!knob_set(name, value)) fail(HE_EINVAL, std::string("unknown knob or value out of range: ") + name);
+  });
+}
+he_status he_knob_get(const char* name, int32_t* value) {
+  return guard_host([&] {
+    need(name != nullptr && value != nullptr, "null argument");
+    int v = 0;
+    if (!knob_get(name, &v)) fail(HE_EINVAL, std::string("unknown knob: ") + name);
+    *value = v;
+  });
+}
+
 he_status he_sync(he_ctx* ctx) {
   return guard([&] {
     auto lk = hold(ctx);

@@ -15,6 +15,32 @@
 
 static inline int cdiv(u64 a, u64 b) { return (int)((a + b - 1) / b); }
 
+// Launch-shape knobs (process-wide).  They change how work is grouped into
+// launches, never a residue; the autotuner picks them by timing.
+namespace {
+struct Knobs {
+  int ms_members = 8;   // batch members per key-inner-product launch (1..8)
+  int mr_members = 8;   // batch members per multi-rotation launch (1..8)
+  int mr_rotations = 16;  // rotations per multi-rotation launch (1..16)
+} g_knobs;
+}
+bool knob_set(const char* name, int v) {
+  std::string n(name);
+  if (n == "ms_members" && v >= 1 && v <= 8) g_knobs.ms_members = v;
+  else if (n == "mr_members" && v >= 1 && v <= 8) g_knobs.mr_members = v;
+  else if (n == "mr_rotations" && v >= 1 && v <= 16) g_knobs.mr_rotations = v;
+  else return false;
+  return true;
+}
+bool knob_get(const char* name, int* v) {
+  std::string n(name);
+  if (n == "ms_members") *v = g_knobs.ms_members;
+  else if (n == "mr_members") *v = g_knobs.mr_members;
+  else if (n == "mr_rotations") *v = g_knobs.mr_rotations;
+  else return false;
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // Optional per-family device timing: HIP events recorded on the launching
 // stream around each launch while enabled.
@@ -1064,45 +1090,93 @@ void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u
 // Each key word is read once and applied to every member.
 // digits [B][beta][nqp][N], c0 [B][nq][N], out [2][B][nqp][N]
 #define MS_MAXB 8
-// key inner product of MB members, in the arithmetic A (the FP64 or the
-// integer one; identical residues)
+// Key inner product of MB members, reduced once per output:
+//  * FP64 (q < 2^50): each product a w - k q (k = rint(a w / q)) is exact and
+//    lies in (-0.51 q, 0.51 q); beta <= 16 of them sum exactly in a double
+//    (below 2^45) and one final rint/fma/correction reduces the sum;
+//  * integer: the 128-bit products are summed (beta terms of < 2^122 fit in
+//    128 bits) and the sum is reduced once: hi 2^64 + lo = hi (2^64 mod q) + lo.
+// Both equal sum_j d_j key_j mod q exactly.
+__device__ __forceinline__ double f64_mulmod_signed(double a, double w, double q, double qinv) {
+  const double h = a * w;
+  const double l = __fma_rn(a, w, -h);
+  const double k = __builtin_rint(h * qinv);
+  return __fma_rn(-k, q, h) + l;
+}
+__device__ __forceinline__ u64 f64_reduce_signed(double s, double q, double qinv) {
+  const double k = __builtin_rint(s * qinv);
+  const double r = __fma_rn(-k, q, s);
+  return (u64)(r < 0.0 ? r + q : r);
+}
+struct U128 {
+  u64 lo, hi;
+};
+__device__ __forceinline__ void u128_mac(U128& acc, u64 a, u64 b) {
+  const u64 lo = a * b, hi = mulhi64(a, b);
+  const u64 s = acc.lo + lo;
+  acc.hi += hi + (s < lo);
+  acc.lo = s;
+}
+__device__ __forceinline__ u64 u128_reduce(const U128& x, const ModConst& m) {
+  const u64 h = reduce64(x.hi, m);
+  return add_mod(mul_mod(h, m.r64, m), reduce64(x.lo, m), m.q);
+}
+
 template <int MB, bool F64>
 __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ digits, const u64* __restrict__ key,
                                              const u64* __restrict__ c0, const u64* __restrict__ pmod, int nq,
                                              int nqp, int beta, int nmods, int B, int b0, int m, int pos, u32 i,
                                              u32 src, u64 N, const ModConst& mk) {
-  typedef typename std::conditional<F64, double, u64>::type V;
-  V acc0[MB], acc1[MB];
-#pragma unroll
-  for (int b = 0; b < MB; b++) acc0[b] = acc1[b] = 0;
   const size_t dstride = (size_t)beta * nqp * N;
-  for (int j = 0; j < beta; j++) {
-    const u64 kb = key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
-    const u64 ka = key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
+  u64 r0[MB], r1[MB];
+  if (F64) {
+    const double q = mk.qf, qi = mk.qinvf;
+    double s0[MB], s1[MB];
+#pragma unroll
+    for (int b = 0; b < MB; b++) s0[b] = s1[b] = 0.0;
+    for (int j = 0; j < beta; j++) {
+      const double kb = (double)key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
+      const double ka = (double)key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
+#pragma unroll
+      for (int b = 0; b < MB; b++) {
+        const double d = (double)digits[(size_t)(b0 + b) * dstride + ((size_t)j * nqp + pos) * N + src];
+        s0[b] += f64_mulmod_signed(d, kb, q, qi);
+        s1[b] += f64_mulmod_signed(d, ka, q, qi);
+      }
+    }
 #pragma unroll
     for (int b = 0; b < MB; b++) {
-      const u64 d = digits[(size_t)(b0 + b) * dstride + ((size_t)j * nqp + pos) * N + src];
-      if (F64) {
-        const double q = mk.qf, qi = mk.qinvf, dd = (double)d;
-        double t0 = (double)acc0[b] + f64_mulmod(dd, (double)kb, q, qi);
-        double t1 = (double)acc1[b] + f64_mulmod(dd, (double)ka, q, qi);
-        acc0[b] = (V)(t0 >= q ? t0 - q : t0);
-        acc1[b] = (V)(t1 >= q ? t1 - q : t1);
-      } else {
-        acc0[b] = (V)add_mod((u64)acc0[b], mul_mod(d, kb, mk), mk.q);
-        acc1[b] = (V)add_mod((u64)acc1[b], mul_mod(d, ka, mk), mk.q);
+      r0[b] = f64_reduce_signed(s0[b], q, qi);
+      r1[b] = f64_reduce_signed(s1[b], q, qi);
+    }
+  } else {
+    U128 s0[MB], s1[MB];
+#pragma unroll
+    for (int b = 0; b < MB; b++) s0[b] = s1[b] = U128{0, 0};
+    for (int j = 0; j < beta; j++) {
+      const u64 kb = key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
+      const u64 ka = key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
+#pragma unroll
+      for (int b = 0; b < MB; b++) {
+        const u64 d = digits[(size_t)(b0 + b) * dstride + ((size_t)j * nqp + pos) * N + src];
+        u128_mac(s0[b], d, kb);
+        u128_mac(s1[b], d, ka);
       }
+    }
+#pragma unroll
+    for (int b = 0; b < MB; b++) {
+      r0[b] = u128_reduce(s0[b], mk);
+      r1[b] = u128_reduce(s1[b], mk);
     }
   }
 #pragma unroll
   for (int b = 0; b < MB; b++) {
-    u64 r0 = (u64)acc0[b];
     if (c0 && pos < nq) {
       const u64 v = c0[((size_t)(b0 + b) * nq + pos) * N + src];
-      r0 = add_mod(r0, mul_const_any(v, pmod[2 * m], pmod[2 * m + 1], mk), mk.q);
+      r0[b] = add_mod(r0[b], mul_const_any(v, pmod[2 * m], pmod[2 * m + 1], mk), mk.q);
     }
-    out[((size_t)(b0 + b) * nqp + pos) * N + i] = r0;
-    out[((size_t)(B + b0 + b) * nqp + pos) * N + i] = (u64)acc1[b];
+    out[((size_t)(b0 + b) * nqp + pos) * N + i] = r0[b];
+    out[((size_t)(B + b0 + b) * nqp + pos) * N + i] = r1[b];
   }
 }
 
@@ -1172,8 +1246,10 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
   const int nq = level + 1, nqp = nq + alpha;
   const u64 twoN = 2 * T.N;
   const int nblk = cdiv(T.N, TPB);
-  for (int r0 = 0; r0 < nrot; r0 += MR_MAX) {
-    const int nr = std::min(nrot - r0, MR_MAX);
+  const int rstep = std::min(MR_MAX, g_knobs.mr_rotations);
+  const int mstep = std::min(MS_MAXB, g_knobs.mr_members);
+  for (int r0 = 0; r0 < nrot; r0 += rstep) {
+    const int nr = std::min(nrot - r0, rstep);
     MultiRot R;
     for (int r = 0; r < nr; r++) {
       R.out[r] = outs[r0 + r];
@@ -1181,10 +1257,10 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
       R.ginv[r] = inv_mod_2n(gs[r0 + r], twoN);
     }
     dim3 grid(cdiv(nblk, 8) * 8 * nr, nqp);
-    for (int b0 = 0; b0 < batch; b0 += MS_MAXB) {
-      const int mb = batch - b0 < MS_MAXB ? batch - b0 : MS_MAXB;
+    for (int b0 = 0; b0 < batch; b0 += mstep) {
+      const int mb = batch - b0 < mstep ? batch - b0 : mstep;
       // digits and c0 of the members once, each rotation's key once, outputs once
-      ProfScope ps("multsum", s,
+      ProfScope ps("multsum_rot", s,
                    8.0 * T.N * (nr * 2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + nr * 2.0 * nqp)));
 #define MR_CASE(K)                                                                                                 \
   case K:                                                                                                          \
@@ -1203,8 +1279,9 @@ void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u6
                     const u64* pmod, int level, int L, int alpha, int beta, u64 g, int batch, hipStream_t s) {
   int nq = level + 1, nqp = nq + alpha;
   dim3 grid(cdiv(T.N, TPB), nqp);
-  for (int b0 = 0; b0 < batch; b0 += MS_MAXB) {
-    const int mb = batch - b0 < MS_MAXB ? batch - b0 : MS_MAXB;
+  const int mstep = std::min(MS_MAXB, g_knobs.ms_members);
+  for (int b0 = 0; b0 < batch; b0 += mstep) {
+    const int mb = batch - b0 < mstep ? batch - b0 : mstep;
     // key read once; digits and c0 of the mb members read once; outputs written once
     ProfScope ps("multsum", s, 8.0 * T.N * (2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + 2.0 * nqp)));
 #define MS_CASE(K)                                                                                              \

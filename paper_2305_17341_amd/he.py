@@ -26,7 +26,7 @@ EXPORTS = [
     "he_drop_level", "he_pmult_slots", "he_lintrans", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
     "he_mem_info", "he_trim", "he_device_memory", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
     "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_refresh",
-    "he_power_rot_steps", "he_power_step", "he_eigen_shift", "he_last_error",
+    "he_power_rot_steps", "he_power_step", "he_eigen_shift", "he_knob_set", "he_knob_get", "he_last_error",
 ]
 
 # he_refresh_fn: status (he_ct*, void* user)
@@ -110,6 +110,8 @@ def load():
         "he_lintrans_rot_steps": [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32), C.c_size_t,
                                   C.POINTER(C.c_size_t)],
         "he_refresh": [vp, vp, C.c_uint64],
+        "he_knob_set": [C.c_char_p, C.c_int32],
+        "he_knob_get": [C.c_char_p, C.POINTER(C.c_int32)],
         "he_power_rot_steps": [C.c_uint32, C.POINTER(C.c_int32), C.c_size_t, C.POINTER(C.c_size_t)],
         "he_power_step": [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.POINTER(vp), C.c_uint32, C.c_uint32,
                           C.c_double, C.c_uint32, C.c_int, REFRESH_FN, vp, C.POINTER(vp), C.POINTER(C.c_uint32),
@@ -424,6 +426,16 @@ def power_rot_steps(d):
     buf = (C.c_int32 * 256)()
     _check(load().he_power_rot_steps(d, buf, 256, C.byref(n)))
     return [int(buf[i]) for i in range(n.value)]
+
+
+def knob_set(name, value):
+    _check(load().he_knob_set(name.encode(), int(value)))
+
+
+def knob_get(name):
+    v = C.c_int32()
+    _check(load().he_knob_get(name.encode(), C.byref(v)))
+    return v.value
 
 
 def device_memory():
