@@ -35,11 +35,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 CSRC = os.path.join(ROOT, "paper_2305_17341_amd", "csrc")
 # source regions a kernel's recorded traffic depends on: (file, first line, last line), matched literally
-KERNEL_REGIONS = {
-    "multsum": [("kernels.hip", "__device__ __forceinline__ u32 automorph_src(", "}"),
-                ("kernels.hip", "#define MS_MAXB 8", "#undef MS_CASE"),
-                ("he_internal.h", None, None)],
-}
+_MULTSUM_REGIONS = [("kernels.hip", "__device__ __forceinline__ u32 automorph_src(", "}"),
+                    ("kernels.hip", "#define MS_MAXB 8", "#undef MS_CASE"),
+                    ("he_internal.h", None, None)]
+KERNEL_REGIONS = {"multsum": _MULTSUM_REGIONS, "multsum_rot": _MULTSUM_REGIONS}
 
 
 def kernel_digest(kernel):
@@ -133,6 +132,8 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--knobs", default="",
+                    help="launch knobs set before the run, e.g. mr_members=4,ms_members=4 (with --no-autotune)")
     ap.add_argument("--paper-relin", action="store_true",
                     help="headline path relinearises every product (default: lazy, once per product)")
     ap.add_argument("--d", type=int, default=128)
@@ -191,6 +192,10 @@ def main():
         return t_total, lat, outs
 
     tuned = None
+    for kv in filter(None, args.knobs.split(",")):
+        name, v = kv.split("=")
+        he.knob_set(name.strip(), int(v))
+    tuned = {"knobs": {k: he.knob_get(k) for k in ("ms_members", "mr_members", "mr_rotations")}, "step_ms": None}
     if not args.no_autotune:
         from paper_2305_17341_amd import autotune
         warm = ctx.matmul_batch(cA, cB, [d] * B, opts=head)   # plaintext caches

@@ -710,7 +710,15 @@ __global__ void k_mul_sum(u64* out, SumTerms t, int nterms, int accumulate, int 
   const ModConst mk = mc[m];
   const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
   u64 acc = accumulate ? out[o] : 0;
-  for (int j = 0; j < nterms; j++) acc = add_mod(acc, mul_mod_any(t.a[j][o], t.p[j][op], mk), mk.q);
+  u64 an = t.a[0][o], pn = t.p[0][op];
+  for (int j = 0; j < nterms; j++) {
+    const u64 a = an, p = pn;
+    if (j + 1 < nterms) {
+      an = t.a[j + 1][o];
+      pn = t.p[j + 1][op];
+    }
+    acc = add_mod(acc, mul_mod_any(a, p, mk), mk.q);
+  }
   out[o] = acc;
 }
 void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms, int nl,
@@ -750,11 +758,23 @@ __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map
   u64 acc[G];
 #pragma unroll
   for (int g = 0; g < G; g++) acc[g] = 0;
+  // software-pipelined over the terms
+  u64 xn = t.a[0][o], pn[G];
+#pragma unroll
+  for (int g = 0; g < G; g++) pn[g] = t.p[g][0] ? t.p[g][0][op] : 0;
   for (int j = 0; j < nterms; j++) {
-    const u64 x = t.a[j][o];
+    const u64 x = xn;
+    u64 pv[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) pv[g] = pn[g];
+    if (j + 1 < nterms) {
+      xn = t.a[j + 1][o];
+#pragma unroll
+      for (int g = 0; g < G; g++) pn[g] = t.p[g][j + 1] ? t.p[g][j + 1][op] : 0;
+    }
 #pragma unroll
     for (int g = 0; g < G; g++)
-      if (t.p[g][j]) acc[g] = add_mod(acc[g], mul_mod_any(x, t.p[g][j][op], mk), mk.q);
+      if (t.p[g][j]) acc[g] = add_mod(acc[g], mul_mod_any(x, pv[g], mk), mk.q);
   }
 #pragma unroll
   for (int g = 0; g < G; g++) t.out[g][o] = acc[g];
@@ -1134,14 +1154,26 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
     double s0[MB], s1[MB];
 #pragma unroll
     for (int b = 0; b < MB; b++) s0[b] = s1[b] = 0.0;
+    // software-pipelined: the loads of digit j + 1 are in flight while j is multiplied
+    u64 kbn = key[((size_t)0 * nmods + m) * N + i], kan = key[((size_t)1 * nmods + m) * N + i], dn[MB];
+#pragma unroll
+    for (int b = 0; b < MB; b++) dn[b] = digits[(size_t)(b0 + b) * dstride + (size_t)pos * N + src];
     for (int j = 0; j < beta; j++) {
-      const double kb = (double)key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
-      const double ka = (double)key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
+      const double kb = (double)kbn, ka = (double)kan;
+      double d[MB];
+#pragma unroll
+      for (int b = 0; b < MB; b++) d[b] = (double)dn[b];
+      if (j + 1 < beta) {
+        kbn = key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i];
+        kan = key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i];
+#pragma unroll
+        for (int b = 0; b < MB; b++)
+          dn[b] = digits[(size_t)(b0 + b) * dstride + ((size_t)(j + 1) * nqp + pos) * N + src];
+      }
 #pragma unroll
       for (int b = 0; b < MB; b++) {
-        const double d = (double)digits[(size_t)(b0 + b) * dstride + ((size_t)j * nqp + pos) * N + src];
-        s0[b] += f64_mulmod_signed(d, kb, q, qi);
-        s1[b] += f64_mulmod_signed(d, ka, q, qi);
+        s0[b] += f64_mulmod_signed(d[b], kb, q, qi);
+        s1[b] += f64_mulmod_signed(d[b], ka, q, qi);
       }
     }
 #pragma unroll
@@ -1153,14 +1185,25 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
     U128 s0[MB], s1[MB];
 #pragma unroll
     for (int b = 0; b < MB; b++) s0[b] = s1[b] = U128{0, 0};
+    u64 kbn = key[((size_t)0 * nmods + m) * N + i], kan = key[((size_t)1 * nmods + m) * N + i], dn[MB];
+#pragma unroll
+    for (int b = 0; b < MB; b++) dn[b] = digits[(size_t)(b0 + b) * dstride + (size_t)pos * N + src];
     for (int j = 0; j < beta; j++) {
-      const u64 kb = key[(((size_t)j * 2 + 0) * nmods + m) * N + i];
-      const u64 ka = key[(((size_t)j * 2 + 1) * nmods + m) * N + i];
+      const u64 kb = kbn, ka = kan;
+      u64 d[MB];
+#pragma unroll
+      for (int b = 0; b < MB; b++) d[b] = dn[b];
+      if (j + 1 < beta) {
+        kbn = key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i];
+        kan = key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i];
+#pragma unroll
+        for (int b = 0; b < MB; b++)
+          dn[b] = digits[(size_t)(b0 + b) * dstride + ((size_t)(j + 1) * nqp + pos) * N + src];
+      }
 #pragma unroll
       for (int b = 0; b < MB; b++) {
-        const u64 d = digits[(size_t)(b0 + b) * dstride + ((size_t)j * nqp + pos) * N + src];
-        u128_mac(s0[b], d, kb);
-        u128_mac(s1[b], d, ka);
+        u128_mac(s0[b], d[b], kb);
+        u128_mac(s1[b], d[b], ka);
       }
     }
 #pragma unroll
