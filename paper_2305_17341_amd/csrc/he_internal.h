@@ -79,13 +79,50 @@ __device__ __forceinline__ double f64_mulmod(double a, double w, double q, doubl
   const double r = __fma_rn(-k, q, h) + l;
   return r < 0.0 ? r + q : r;
 }
+
+// Exact conversions between u64 and double for integers in [0, 2^52): the
+// value is ORed into the mantissa of 2^52 and 2^52 subtracted (and the
+// reverse).  One 32-bit logic op and one double add each way, where the
+// general conversions take four to six instructions.
+__device__ __forceinline__ double u2d(u64 x) {
+  return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 0x1p52;
+}
+__device__ __forceinline__ u64 d2u(double x) {
+  return (u64)__double_as_longlong(x + 0x1p52) & 0x000FFFFFFFFFFFFFull;
+}
+
+// Lazy FP64 arithmetic for q < 2^46: signed representatives are carried
+// through sums and butterflies and brought to [0, q) once.
+//  * f64_mulmod_signed(a, w), |a| <= 16 q and 0 <= w < q, returns a w - k q
+//    exactly with |result| < q: the product's rounding error l satisfies
+//    |l| / q < 16 q 2^-53 <= 2^-3, the quotient h * qinv misses h / q by at
+//    most 16 q 2^-52 <= 2^-2, so |a w / q - k| < 7/8; h - k q and the final
+//    sum are integers below 2^53, hence exact.
+//  * sums of up to 64 such terms stay below 2^52 and are exact;
+//  * f64_canon(s) for |s| < 2^52 returns s mod q in [0, q); f64_centre(s)
+//    a representative of absolute value at most q / 2 + 1.
+#define F64_LAZY_BITS 46
+__device__ __forceinline__ double f64_mulmod_signed(double a, double w, double q, double qinv) {
+  const double h = a * w;
+  const double l = __fma_rn(a, w, -h);
+  const double k = __builtin_rint(h * qinv);
+  return __fma_rn(-k, q, h) + l;
+}
+__device__ __forceinline__ double f64_centre(double s, double q, double qinv) {
+  return __fma_rn(-__builtin_rint(s * qinv), q, s);
+}
+__device__ __forceinline__ double f64_canon(double s, double q, double qinv) {
+  const double r = f64_centre(s, q, qinv);
+  return r < 0.0 ? r + q : r;
+}
+
 __device__ __forceinline__ u64 mul_const_any(u64 a, u64 w, u64 wp, const ModConst& m) {
-  if (m.bits <= F64_MAX_BITS) return (u64)f64_mulmod((double)a, (double)w, m.qf, m.qinvf);
+  if (m.bits <= F64_MAX_BITS) return d2u(f64_mulmod(u2d(a), u2d(w), m.qf, m.qinvf));
   return shoup_mul(a, w, wp, m.q);
 }
 // a*b mod q, choosing the arithmetic by the size of q (same residue either way)
 __device__ __forceinline__ u64 mul_mod_any(u64 a, u64 b, const ModConst& m) {
-  if (m.bits <= F64_MAX_BITS) return (u64)f64_mulmod((double)a, (double)b, m.qf, m.qinvf);
+  if (m.bits <= F64_MAX_BITS) return d2u(f64_mulmod(u2d(a), u2d(b), m.qf, m.qinvf));
   return mul_mod(a, b, m);
 }
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {

@@ -304,11 +304,14 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows(u64* data, LimbMap map, int lo
 //  * Shoup: 64-bit words, w * a mod q with the companion floor(w 2^64 / q)
 //    (any q < 2^61; the 64-bit products run on the quarter-rate 32-bit
 //    multipliers);
-//  * exact FP64 for q < 2^50: h = a w, l = fma(a, w, -h) is the exact
-//    rounding error, k = rint(h / q), r = fma(-k, q, h) + l is exactly
-//    a w - k q in (-q, q), one conditional + q lands it in [0, q).  Every
-//    operation is a full-rate double op.  (With |a w / q - k| < 0.81 the
-//    fma result stays below 2^51 and is exact.)
+//  * lazy FP64 for q < 2^46: values are signed doubles; a butterfly is one
+//    exact signed product a w - k q (|.| < q for |a| <= 16 q, see
+//    f64_mulmod_signed), one add and one subtract, with no conditional
+//    corrections.  Forward (Cooley-Tukey) stages add at most q to the bound,
+//    so the eight stages of a pass stay below 9 q; inverse (Gentleman-Sande)
+//    stages double it, so each group of four stages starts from a centred
+//    value (reduce) and ends below 16 q.  Stores to memory bring values to
+//    [0, q).  Every operation is a full-rate double op.
 // Both give the same residues.
 // ---------------------------------------------------------------------------
 struct ShoupArith {
@@ -318,29 +321,24 @@ struct ShoupArith {
   u64 q, ninv, ninv_sh;
   __device__ __forceinline__ V load(u64 x) const { return x; }
   __device__ __forceinline__ u64 store(V x) const { return x; }
+  __device__ __forceinline__ V reduce(V x) const { return x; }
   __device__ __forceinline__ V add(V a, V b) const { return add_mod(a, b, q); }
   __device__ __forceinline__ V sub(V a, V b) const { return sub_mod(a, b, q); }
   __device__ __forceinline__ V mulw(V a, u32 i) const { return shoup_mul(a, w[i], wsh[i], q); }
   __device__ __forceinline__ V scale_ninv(V a) const { return shoup_mul(a, ninv, ninv_sh, q); }
 };
 
-
-struct F64Arith {
+struct F64LazyArith {
   typedef double V;
   const double* __restrict__ w;
   double q, qinv, ninv;
-  __device__ __forceinline__ V load(u64 x) const { return (double)x; }
-  __device__ __forceinline__ u64 store(V x) const { return (u64)x; }
-  __device__ __forceinline__ V add(V a, V b) const {
-    const double s = a + b;
-    return s >= q ? s - q : s;
-  }
-  __device__ __forceinline__ V sub(V a, V b) const {
-    const double s = a - b;
-    return s < 0.0 ? s + q : s;
-  }
-  __device__ __forceinline__ V mulw(V a, u32 i) const { return f64_mulmod(a, w[i], q, qinv); }
-  __device__ __forceinline__ V scale_ninv(V a) const { return f64_mulmod(a, ninv, q, qinv); }
+  __device__ __forceinline__ V load(u64 x) const { return u2d(x); }
+  __device__ __forceinline__ u64 store(V x) const { return d2u(f64_canon(x, q, qinv)); }
+  __device__ __forceinline__ V reduce(V x) const { return f64_centre(x, q, qinv); }
+  __device__ __forceinline__ V add(V a, V b) const { return a + b; }
+  __device__ __forceinline__ V sub(V a, V b) const { return a - b; }
+  __device__ __forceinline__ V mulw(V a, u32 i) const { return f64_mulmod_signed(a, w[i], q, qinv); }
+  __device__ __forceinline__ V scale_ninv(V a) const { return f64_mulmod_signed(a, ninv, q, qinv); }
 };
 
 template <int G, class A>
@@ -434,7 +432,7 @@ __device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh
     for (int k = 0; k < ITA; k++) {
       const int it = tid + TPB * k, c = it % C, rl = it / C;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = sh[lds_rc(rl + (mm << GB), c, C)];
+      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = ar.reduce(sh[lds_rc(rl + (mm << GB), c, C)]);
       inv_group<GA>(v, S2 + GB, LOGN, 0u, ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GA); mm++)
@@ -500,7 +498,7 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
     for (int k = 0; k < ITC; k++) {
       const int it = tid + TPB * k, el = it % LOWC, b = it / LOWC;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GC); mm++) v[mm] = sh[lds_be(b, el + (mm << GD), T1)];
+      for (int mm = 0; mm < (1 << GC); mm++) v[mm] = ar.reduce(sh[lds_be(b, el + (mm << GD), T1)]);
       inv_group<GC>(v, GD, LOGN, (u32)(blk0 + b), ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GC); mm++) a[(size_t)b * T1 + el + (mm << GD)] = ar.store(v[mm]);
@@ -508,8 +506,7 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
   }
 }
 
-// moduli below 2^50 take the FP64 arithmetic
-#define NTT_F64_MAX_BITS F64_MAX_BITS
+// moduli below 2^46 take the lazy FP64 arithmetic
 
 template <int LOGN, int GA, int GB, bool INV>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const u64* __restrict__ tw,
@@ -524,9 +521,8 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
   u64* a = data + (size_t)limb * N;
   const int c0 = blockIdx.x * C;
   const ModConst mk = mc[m];
-  if (mk.bits <= NTT_F64_MAX_BITS) {
-    const double qd = (double)mk.q;
-    F64Arith ar{twf + (size_t)m * N, qd, 1.0 / qd, (double)mk.ninv};
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
     ntt_cols2_body<LOGN, GA, GB, INV>(a, c0, reinterpret_cast<double*>(sh), ar);
   } else {
     ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
@@ -547,9 +543,8 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
   const int blk0 = blockIdx.x * K;
   u64* a = data + (size_t)limb * N + (size_t)blk0 * T1;
   const ModConst mk = mc[m];
-  if (mk.bits <= NTT_F64_MAX_BITS) {
-    const double qd = (double)mk.q;
-    F64Arith ar{twf + (size_t)m * N, qd, 1.0 / qd, (double)mk.ninv};
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
     ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, reinterpret_cast<double*>(sh), ar);
   } else {
     ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
@@ -709,8 +704,23 @@ __global__ void k_mul_sum(u64* out, SumTerms t, int nterms, int accumulate, int 
   if (m < 0) return;
   const ModConst mk = mc[m];
   const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
-  u64 acc = accumulate ? out[o] : 0;
   u64 an = t.a[0][o], pn = t.p[0][op];
+  if (mk.bits <= F64_LAZY_BITS) {
+    // up to 16 signed exact products and the old value, reduced once
+    const double q = mk.qf, qi = mk.qinvf;
+    double acc = accumulate ? u2d(out[o]) : 0.0;
+    for (int j = 0; j < nterms; j++) {
+      const u64 a = an, p = pn;
+      if (j + 1 < nterms) {
+        an = t.a[j + 1][o];
+        pn = t.p[j + 1][op];
+      }
+      acc += f64_mulmod_signed(u2d(a), u2d(p), q, qi);
+    }
+    out[o] = d2u(f64_canon(acc, q, qi));
+    return;
+  }
+  u64 acc = accumulate ? out[o] : 0;
   for (int j = 0; j < nterms; j++) {
     const u64 a = an, p = pn;
     if (j + 1 < nterms) {
@@ -755,13 +765,37 @@ __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map
   if (m < 0) return;
   const ModConst mk = mc[m];
   const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
-  u64 acc[G];
-#pragma unroll
-  for (int g = 0; g < G; g++) acc[g] = 0;
   // software-pipelined over the terms
   u64 xn = t.a[0][o], pn[G];
 #pragma unroll
   for (int g = 0; g < G; g++) pn[g] = t.p[g][0] ? t.p[g][0][op] : 0;
+  if (mk.bits <= F64_LAZY_BITS) {
+    // signed exact products summed per output (at most 16), reduced once
+    const double q = mk.qf, qi = mk.qinvf;
+    double acc[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) acc[g] = 0.0;
+    for (int j = 0; j < nterms; j++) {
+      const double x = u2d(xn);
+      u64 pv[G];
+#pragma unroll
+      for (int g = 0; g < G; g++) pv[g] = pn[g];
+      if (j + 1 < nterms) {
+        xn = t.a[j + 1][o];
+#pragma unroll
+        for (int g = 0; g < G; g++) pn[g] = t.p[g][j + 1] ? t.p[g][j + 1][op] : 0;
+      }
+#pragma unroll
+      for (int g = 0; g < G; g++)
+        if (t.p[g][j]) acc[g] += f64_mulmod_signed(x, u2d(pv[g]), q, qi);
+    }
+#pragma unroll
+    for (int g = 0; g < G; g++) t.out[g][o] = d2u(f64_canon(acc[g], q, qi));
+    return;
+  }
+  u64 acc[G];
+#pragma unroll
+  for (int g = 0; g < G; g++) acc[g] = 0;
   for (int j = 0; j < nterms; j++) {
     const u64 x = xn;
     u64 pv[G];
@@ -846,6 +880,23 @@ __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, i
   const ModConst mk = mc[k % nl];
   size_t o0 = (size_t)k * N + i, o1 = (size_t)(nt + k) * N + i, o2 = (size_t)(2 * nt + k) * N + i;
   u64 a0 = a[o0], a1 = a[o1], b0 = b[o0], b1 = b[o1];
+  if (mk.bits <= F64_LAZY_BITS) {
+    // signed exact products, each output reduced once
+    const double q = mk.qf, qi = mk.qinvf;
+    const double x0 = u2d(a0), x1 = u2d(a1), y0 = u2d(b0), y1 = u2d(b1);
+    double s0 = f64_mulmod_signed(x0, y0, q, qi);
+    double s1 = f64_mulmod_signed(x0, y1, q, qi) + f64_mulmod_signed(x1, y0, q, qi);
+    double s2 = f64_mulmod_signed(x1, y1, q, qi);
+    if (ACC) {
+      s0 += u2d(out[o0]);
+      s1 += u2d(out[o1]);
+      s2 += u2d(out[o2]);
+    }
+    out[o0] = d2u(f64_canon(s0, q, qi));
+    out[o1] = d2u(f64_canon(s1, q, qi));
+    out[o2] = d2u(f64_canon(s2, q, qi));
+    return;
+  }
   u64 t0 = mul_mod_any(a0, b0, mk);
   u64 t1 = add_mod(mul_mod_any(a0, b1, mk), mul_mod_any(a1, b0, mk), mk.q);
   u64 t2 = mul_mod_any(a1, b1, mk);
@@ -932,14 +983,11 @@ __global__ void k_modup(u64* digits, const u64* coef, const u64* ntt_in, ModupAr
     const ModConst& mt = mc[m];
     const u64* hat = hat_l + m;
     const u64* hat_sh = hat_sh_l + m;
-    if (mt.bits <= F64_MAX_BITS && src_bits <= mt.bits + 1) {
-      // inputs below 2 q_t: the FP64 product stays exact
+    if (mt.bits <= F64_LAZY_BITS && src_bits <= mt.bits + 1) {
+      // inputs below 4 q_t: signed exact products, summed, reduced once
       double acc = 0.0;
-      for (int a = 0; a < ns; a++) {
-        acc += f64_mulmod((double)y[a], (double)hat[(size_t)a * nmods], mt.qf, mt.qinvf);
-        acc = acc >= mt.qf ? acc - mt.qf : acc;
-      }
-      *o = (u64)acc;
+      for (int a = 0; a < ns; a++) acc += f64_mulmod_signed(u2d(y[a]), u2d(hat[(size_t)a * nmods]), mt.qf, mt.qinvf);
+      *o = d2u(f64_canon(acc, mt.qf, mt.qinvf));
     } else {
       u64 acc = 0;
       for (int a = 0; a < ns; a++)
@@ -1042,20 +1090,18 @@ __global__ void k_fbc_to_q(u64* y, const u64* xp, int nq, FbcArgs A, int logN, i
   const u64 r = round_quotient(v, A);
   for (int t = blockIdx.y; t < nq; t += gridDim.y) {
     const ModConst& mt = mc[t];
-    if (mt.bits <= F64_MAX_BITS) {
-      // v = v_hi 2^32 + v_lo with both halves below q_t: two exact FP64 products
+    if (mt.bits <= F64_LAZY_BITS && mt.bits > 32) {
+      // v = v_hi 2^32 + v_lo with both halves below q_t: exact signed FP64
+      // products, summed, reduced once
       const double q = mt.qf, qi = mt.qinvf;
       double acc = 0.0;
       for (int a = 0; a < A.ns; a++) {
         const double* e = A.hat_f + ((size_t)a * nmods + t) * 3;
-        acc += f64_mulmod((double)(v[a] & 0xffffffffull), e[0], q, qi);
-        acc = acc >= q ? acc - q : acc;
-        acc += f64_mulmod((double)(v[a] >> 32), e[1], q, qi);
-        acc = acc >= q ? acc - q : acc;
+        acc += f64_mulmod_signed(u2d(v[a] & 0xffffffffull), e[0], q, qi);
+        acc += f64_mulmod_signed(u2d(v[a] >> 32), e[1], q, qi);
       }
-      acc -= f64_mulmod((double)r, A.hat_f[(size_t)t * 3 + 2], q, qi);
-      acc = acc < 0.0 ? acc + q : acc;
-      yy[(size_t)t * N + i] = (u64)acc;
+      acc -= f64_mulmod_signed(u2d(r), A.hat_f[(size_t)t * 3 + 2], q, qi);
+      yy[(size_t)t * N + i] = d2u(f64_canon(acc, q, qi));
     } else {
       u64 q = mt.q, acc = 0;
       for (int a = 0; a < A.ns; a++)
@@ -1111,23 +1157,12 @@ void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u
 // digits [B][beta][nqp][N], c0 [B][nq][N], out [2][B][nqp][N]
 #define MS_MAXB 8
 // Key inner product of MB members, reduced once per output:
-//  * FP64 (q < 2^50): each product a w - k q (k = rint(a w / q)) is exact and
-//    lies in (-0.51 q, 0.51 q); beta <= 16 of them sum exactly in a double
-//    (below 2^45) and one final rint/fma/correction reduces the sum;
+//  * FP64 (q < 2^46): the beta <= 16 signed products a w - k q (each below q
+//    in absolute value) sum exactly in a double and one f64_canon reduces
+//    the sum;
 //  * integer: the 128-bit products are summed (beta terms of < 2^122 fit in
 //    128 bits) and the sum is reduced once: hi 2^64 + lo = hi (2^64 mod q) + lo.
 // Both equal sum_j d_j key_j mod q exactly.
-__device__ __forceinline__ double f64_mulmod_signed(double a, double w, double q, double qinv) {
-  const double h = a * w;
-  const double l = __fma_rn(a, w, -h);
-  const double k = __builtin_rint(h * qinv);
-  return __fma_rn(-k, q, h) + l;
-}
-__device__ __forceinline__ u64 f64_reduce_signed(double s, double q, double qinv) {
-  const double k = __builtin_rint(s * qinv);
-  const double r = __fma_rn(-k, q, s);
-  return (u64)(r < 0.0 ? r + q : r);
-}
 struct U128 {
   u64 lo, hi;
 };
@@ -1159,10 +1194,10 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
 #pragma unroll
     for (int b = 0; b < MB; b++) dn[b] = digits[(size_t)(b0 + b) * dstride + (size_t)pos * N + src];
     for (int j = 0; j < beta; j++) {
-      const double kb = (double)kbn, ka = (double)kan;
+      const double kb = u2d(kbn), ka = u2d(kan);
       double d[MB];
 #pragma unroll
-      for (int b = 0; b < MB; b++) d[b] = (double)dn[b];
+      for (int b = 0; b < MB; b++) d[b] = u2d(dn[b]);
       if (j + 1 < beta) {
         kbn = key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i];
         kan = key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i];
@@ -1178,8 +1213,8 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
     }
 #pragma unroll
     for (int b = 0; b < MB; b++) {
-      r0[b] = f64_reduce_signed(s0[b], q, qi);
-      r1[b] = f64_reduce_signed(s1[b], q, qi);
+      r0[b] = d2u(f64_canon(s0[b], q, qi));
+      r1[b] = d2u(f64_canon(s1[b], q, qi));
     }
   } else {
     U128 s0[MB], s1[MB];
@@ -1236,7 +1271,7 @@ __global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict
   int m = pos < nq ? pos : L + 1 + (pos - nq);
   const ModConst mk = mc[m];
   u32 src = g == 1 ? i : automorph_src(i, g, logN);
-  if (mk.bits <= F64_MAX_BITS)
+  if (mk.bits <= F64_LAZY_BITS)
     multsum_body<MB, true>(out, digits, key, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk);
   else
     multsum_body<MB, false>(out, digits, key, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk);
@@ -1269,7 +1304,7 @@ __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, int nrot, const
   const int m = pos < nq ? pos : L + 1 + (pos - nq);
   const ModConst mk = mc[m];
   const u32 i = automorph_src(src, R.ginv[r], logN);
-  if (mk.bits <= F64_MAX_BITS)
+  if (mk.bits <= F64_LAZY_BITS)
     multsum_body<MB, true>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk);
   else
     multsum_body<MB, false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N,

@@ -250,7 +250,7 @@ static FbcTable make_fbc(HeCtxImpl* c, const std::vector<int>& src) {
     dm[2 * m + 1] = shoup_pre(d, qt);
   }
   t.D_mod_t = c->table_upload(dm.data(), dm.size() * 8);
-  // FP64 form for targets below 2^50: a source value v (any size below 2^64)
+  // FP64 form for targets of 33 to 46 bits: a source value v (any size below 2^64)
   // is split v = v_hi 2^32 + v_lo, and v hat = v_lo hat + v_hi (2^32 hat) mod
   // q_t, both factors below q_t: [a][t] = (hat mod q_t, 2^32 hat mod q_t, D mod q_t)
   std::vector<double> hf((size_t)t.ns * c->nmods * 3);
