@@ -269,7 +269,9 @@ he_status he_last_op_ms(const he_ctx* ctx, double* ms);
 
 /* Device-time profile by kernel: "ntt_fwd_cols", "ntt_fwd_rows",
  * "ntt_inv_rows", "ntt_inv_cols" (the two passes of each transform),
- * "multsum", "multsum_rot" (several rotations of one decomposition), "modup", "fbc_to_q", "moddown_final", "rescale_lift",
+ * "ntt_fwd_rows_sub" (the forward block pass that ends ModDown and Rescale:
+ * (x - y) c), "multsum", "multsum_rot" (several rotations of one
+ * decomposition), "modup", "fbc_to_q", "moddown_final", "rescale_lift",
  * "rescale_final", "elementwise", "tensor", "plift".  While enabled, HIP
  * events are recorded on the launching stream around every launch of the
  * kernel.  Enabling clears the totals.  `bytes` (may be NULL) receives the

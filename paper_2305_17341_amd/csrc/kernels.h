@@ -28,6 +28,10 @@ struct DeviceTables {
 
 // transforms
 void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s);
+// forward NTT of npoly x nq limbs y, then out = (x - y) c mod q_t with x
+// [npoly][x_stride][N] and c pairs (value, Shoup companion) per t < nq
+void launch_ntt_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,
+                        int x_stride, const u64* cpairs, u64* out, hipStream_t s);
 
 // data movement / elementwise (data laid out [nlimbs][N], limb k uses map)
 void launch_automorph(const DeviceTables& T, u64* out, const u64* in, int nlimbs, u64 g, hipStream_t s);

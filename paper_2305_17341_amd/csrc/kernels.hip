@@ -441,9 +441,34 @@ __device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh
   }
 }
 
+// Stores of the forward block pass: the transform itself, or (SubScale)
+// out = (x - y) c mod q, the tail of ModDown (c = P^-1) and of Rescale
+// (c = q_l^-1), so that y never returns to memory.
+template <class A>
+struct StorePlain {
+  u64* a;
+  const A& ar;
+  __device__ __forceinline__ void operator()(int e, typename A::V v) const { a[e] = ar.store(v); }
+};
+struct SubScaleShoup {
+  u64* out;
+  const u64* __restrict__ x;
+  u64 c, c_sh, q;
+  __device__ __forceinline__ void operator()(int e, u64 v) const { out[e] = shoup_mul(sub_mod(x[e], v, q), c, c_sh, q); }
+};
+struct SubScaleF64 {
+  u64* out;
+  const u64* __restrict__ x;
+  double c, q, qinv;
+  // v below 9 q in absolute value (eight forward stages): |x - v| < 10 q
+  __device__ __forceinline__ void operator()(int e, double v) const {
+    out[e] = d2u(f64_canon(f64_mulmod_signed(u2d(x[e]) - v, c, q, qinv), q, qinv));
+  }
+};
+
 // Block pass body: blocks of T1 = 2^(GC+GD) words, K = TILE / T1 blocks per work-group.
-template <int LOGN, int GC, int GD, bool INV, class A>
-__device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* sh, const A& ar) {
+template <int LOGN, int GC, int GD, bool INV, class A, class ST>
+__device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* sh, const A& ar, const ST& st) {
   typedef typename A::V V;
   constexpr int S2 = GC + GD, T1 = 1 << S2, S1 = LOGN - S2;
   const int tid = threadIdx.x;
@@ -475,7 +500,7 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
       for (int mm = 0; mm < (1 << GD); mm++) sh[lds_be(b, (eh << GD) + mm, T1)] = v[mm];
     }
     __syncthreads();
-    for (int e = tid; e < TILE; e += TPB) a[e] = ar.store(sh[lds_be(e / T1, e % T1, T1)]);
+    for (int e = tid; e < TILE; e += TPB) st(e, sh[lds_be(e / T1, e % T1, T1)]);
   } else {
     // inverse bits [0, GD) of e
     constexpr int ITD = 16 >> GD;
@@ -545,11 +570,59 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
   const ModConst mk = mc[m];
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
-    ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, reinterpret_cast<double*>(sh), ar);
+    ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, reinterpret_cast<double*>(sh), ar, StorePlain<F64LazyArith>{a, ar});
   } else {
     ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
-    ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, sh, ar);
+    ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, sh, ar, StorePlain<ShoupArith>{a, ar});
   }
+}
+
+// Forward block pass whose stores are the SubScale tail: data holds npoly x
+// nq limbs y (column pass done), x [npoly][x_stride][N], c pairs (value,
+// Shoup companion) per limb t < nq, out [npoly][nq][N].
+template <int LOGN, int GC, int GD>
+__global__ void __launch_bounds__(TPB) k_ntt_rows2_sub(u64* data, LimbMap map, const u64* __restrict__ tw,
+                                                       const u64* __restrict__ twsh, const double* __restrict__ twf,
+                                                       const ModConst* __restrict__ mc, int nq,
+                                                       const u64* __restrict__ x, int x_stride,
+                                                       const u64* __restrict__ cpairs, u64* out) {
+  constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const int p = limb / nq, t = limb - p * nq;
+  const u64 N = 1ull << LOGN;
+  const int blk0 = blockIdx.x * K;
+  const size_t off = (size_t)blk0 * T1;
+  u64* a = data + (size_t)limb * N + off;
+  const u64* xa = x + ((size_t)p * x_stride + t) * N + off;
+  u64* oa = out + ((size_t)p * nq + t) * N + off;
+  const ModConst mk = mc[m];
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
+    ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, reinterpret_cast<double*>(sh), ar,
+                                        SubScaleF64{oa, xa, u2d(cpairs[2 * t]), mk.qf, mk.qinvf});
+  } else {
+    ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, sh, ar, SubScaleShoup{oa, xa, cpairs[2 * t], cpairs[2 * t + 1], mk.q});
+  }
+}
+
+template <int LOGN, int GA, int GB, int GC, int GD>
+static void ntt2_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,
+                         int x_stride, const u64* cpairs, u64* out, hipStream_t s) {
+  constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
+  const int nlimbs = nq * npoly;
+  dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
+  {
+    ProfScope ps("ntt_fwd_cols", s, 16.0 * nlimbs * T.N);
+    hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, y, map, T.psi, T.psi_sh, T.psi_f,
+                       T.mc);
+  }
+  ProfScope ps("ntt_fwd_rows_sub", s, 24.0 * nlimbs * T.N);
+  hipLaunchKernelGGL((k_ntt_rows2_sub<LOGN, GC, GD>), gr, dim3(TPB), 0, s, y, map, T.psi, T.psi_sh, T.psi_f, T.mc,
+                     nq, x, x_stride, cpairs, out);
 }
 
 template <int LOGN, int GA, int GB, int GC, int GD>
@@ -619,6 +692,27 @@ void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map
     hipLaunchKernelGGL(k_ntt_cols, gc, dim3(TPB), 0, s, data, map, sh.logN, sh.R, sh.T1, sh.C, 1, T.ipsi,
                        T.ipsi_sh, T.mc);
   }
+}
+
+__global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, const u64* pinv, int x_stride_limbs,
+                                int logN, const ModConst* __restrict__ mc);
+// Forward NTT of npoly x nq limbs y (moduli q_0..q_{nq-1}) followed by
+// out = (x - y) c mod q_t; y is left in an unspecified state.
+void launch_ntt_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,
+                        int x_stride, const u64* cpairs, u64* out, hipStream_t s) {
+  if (nq <= 0 || npoly <= 0) return;
+  switch (T.logN) {
+    case 16: ntt2_fwd_sub<16, 4, 4, 4, 4>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
+    case 15: ntt2_fwd_sub<15, 4, 3, 4, 4>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
+    case 14: ntt2_fwd_sub<14, 4, 3, 4, 3>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
+    case 13: ntt2_fwd_sub<13, 3, 3, 4, 3>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
+    case 12: ntt2_fwd_sub<12, 3, 3, 3, 3>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
+    default: break;
+  }
+  launch_ntt(T, y, nq * npoly, map, false, s);
+  dim3 grid(cdiv(T.N, TPB), nq, npoly);
+  ProfScope ps("moddown_final", s, 8.0 * T.N * 3.0 * npoly * nq);
+  hipLaunchKernelGGL(k_moddown_final, grid, dim3(TPB), 0, s, out, x, y, nq, cpairs, x_stride, T.logN, T.mc);
 }
 
 // ---------------------------------------------------------------------------

@@ -619,9 +619,8 @@ HeCt HeCtxImpl::rescale(const HeCt& a) {
   launch_ntt(T, top.p, np, one(l), true, stream);
   DevBuf t(&pool, (size_t)np * l * N);
   launch_rescale_lift(T, t.p, top.p, l, np, stream);
-  launch_ntt(T, t.p, np * l, qmap(l), false, stream);
   HeCt c = ct_new(l - 1, false, a.scale / (double)mods[l], a.B);
-  launch_rescale_final(T, c.d.p, a.d.p, t.p, l, np, l + 1, qlinv.p + (size_t)l * nmods * 2, stream);
+  launch_ntt_fwd_sub(T, t.p, l, np, qmap(l), a.d.p, l + 1, qlinv.p + (size_t)l * nmods * 2, c.d.p, stream);
   return c;
 }
 
@@ -698,9 +697,8 @@ HeCt HeCtxImpl::moddown(const HeCt& x) {
   launch_ntt(T, pc.p, np * alpha, pm, true, stream);
   DevBuf y(&pool, (size_t)np * nq * N);
   launch_fbc_to_q(T, y.p, pc.p, nq, np, down, stream);
-  launch_ntt(T, y.p, np * nq, qmap(nq), false, stream);
   HeCt c = ct_new(x.level, false, x.scale, x.B);
-  launch_moddown_final(T, c.d.p, x.d.p, y.p, nq, pinv.p, np, nqp, stream);
+  launch_ntt_fwd_sub(T, y.p, nq, np, qmap(nq), x.d.p, nqp, pinv.p, c.d.p, stream);
   n_moddown += x.B;
   return c;
 }
