@@ -41,6 +41,11 @@ _MULTSUM_REGIONS = [("kernels.hip", "__device__ __forceinline__ u32 automorph_sr
 KERNEL_REGIONS = {"multsum": _MULTSUM_REGIONS, "multsum_rot": _MULTSUM_REGIONS}
 
 
+def autotune_knobs():
+    from paper_2305_17341_amd import autotune
+    return tuple(autotune.CANDIDATES)
+
+
 def kernel_digest(kernel):
     """SHA-256 over the source regions of `kernel` (None if one is missing)"""
     import hashlib
@@ -195,7 +200,7 @@ def main():
     for kv in filter(None, args.knobs.split(",")):
         name, v = kv.split("=")
         he.knob_set(name.strip(), int(v))
-    tuned = {"knobs": {k: he.knob_get(k) for k in ("ms_members", "mr_members", "mr_rotations")}, "step_ms": None}
+    tuned = {"knobs": {k: he.knob_get(k) for k in autotune_knobs()}, "step_ms": None}
     if not args.no_autotune:
         from paper_2305_17341_amd import autotune
         warm = ctx.matmul_batch(cA, cB, [d] * B, opts=head)   # plaintext caches
@@ -289,6 +294,8 @@ def main():
         "max_abs_err": err,
         "op_counts_per_matmul": per_mm,
         "kernel_ms_per_step": {f: round(v, 3) for f, v in fam_ms.items()},
+        "kernel_algorithmic_gbs": {f: round(prof[f][2] / (prof[f][0] * 1e-3) / 1e9, 1)
+                                   for f in fams if prof[f][0] > 0},
         "roofline": roofline,
     }
     if args.serve_jobs > 0:

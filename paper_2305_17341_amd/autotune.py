@@ -1,6 +1,7 @@
 """Launch-shape autotuner: times the batched product under each value of the
-library's knobs (members and rotations per launch) and keeps the fastest.
-The knobs only regroup work into launches, so every choice gives the same
+library's knobs (members and rotations per launch, the order in which the
+block passes and the plaintext sums visit limbs) and keeps the fastest.
+The knobs only regroup or reorder work, so every choice gives the same
 residues; the timing decides."""
 from __future__ import annotations
 
@@ -12,6 +13,8 @@ CANDIDATES = {
     "mr_members": (2, 4, 8),
     "mr_rotations": (4, 8, 16),
     "ms_members": (4, 8),
+    "ntt_interleave": (0, 1),
+    "ew_interleave": (0, 1),
 }
 
 

@@ -22,6 +22,8 @@ struct Knobs {
   int ms_members = 8;   // batch members per key-inner-product launch (1..8)
   int mr_members = 8;   // batch members per multi-rotation launch (1..8)
   int mr_rotations = 16;  // rotations per multi-rotation launch (1..16)
+  int ntt_interleave = 1;  // block passes visit limbs of one modulus back to back (0/1)
+  int ew_interleave = 1;   // plaintext-broadcast sums visit the limbs sharing a plaintext back to back (0/1)
 } g_knobs;
 }
 bool knob_set(const char* name, int v) {
@@ -29,6 +31,8 @@ bool knob_set(const char* name, int v) {
   if (n == "ms_members" && v >= 1 && v <= 8) g_knobs.ms_members = v;
   else if (n == "mr_members" && v >= 1 && v <= 8) g_knobs.mr_members = v;
   else if (n == "mr_rotations" && v >= 1 && v <= 16) g_knobs.mr_rotations = v;
+  else if (n == "ntt_interleave" && (v == 0 || v == 1)) g_knobs.ntt_interleave = v;
+  else if (n == "ew_interleave" && (v == 0 || v == 1)) g_knobs.ew_interleave = v;
   else return false;
   return true;
 }
@@ -37,6 +41,8 @@ bool knob_get(const char* name, int* v) {
   if (n == "ms_members") *v = g_knobs.ms_members;
   else if (n == "mr_members") *v = g_knobs.mr_members;
   else if (n == "mr_rotations") *v = g_knobs.mr_rotations;
+  else if (n == "ntt_interleave") *v = g_knobs.ntt_interleave;
+  else if (n == "ew_interleave") *v = g_knobs.ew_interleave;
   else return false;
   return true;
 }
@@ -135,6 +141,33 @@ std::vector<std::string> prof_families() {
 }
 
 __device__ __forceinline__ int limb_mod(const LimbMap& m, int k) { return m.idx[k % m.n]; }
+// Limb of grid row y when `outer` groups of gridDim.y / outer limbs are
+// visited interleaved (limb j of every group, then limb j + 1, ...): limbs
+// that share a modulus or a broadcast operand then run back to back, and
+// when a row's work-groups always land on the same XCDs (row length a
+// multiple of 8), the shared data is served from L2.  outer <= 1: y itself.
+__device__ __forceinline__ int grid_limb(int y, int outer) {
+  if (outer <= 1) return y;
+  const int inner = gridDim.y / outer;
+  return (y % outer) * inner + y / outer;
+}
+// host side: the interleave factor for nlimbs limbs in groups of `period`
+static inline int interleave_of(int nlimbs, int period, int knob) {
+  return (knob && period > 0 && nlimbs > period && nlimbs % period == 0) ? nlimbs / period : 1;
+}
+// the shortest period of a limb map's moduli (skipped limbs match anything)
+static inline int modulus_period(const LimbMap& m) {
+  for (int p = 1; p < m.n; p++) {
+    if (m.n % p) continue;
+    bool ok = true;
+    for (int k = p; k < m.n && ok; k++) {
+      const int a = m.idx[k], b = m.idx[k % p];
+      ok = a < 0 || b < 0 || a == b;
+    }
+    if (ok) return p;
+  }
+  return m.n;
+}
 
 __device__ __forceinline__ u32 brv(u32 x, int bits) { return __brev(x) >> (32 - bits); }
 
@@ -558,10 +591,10 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
 template <int LOGN, int GC, int GD, bool INV>
 __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const u64* __restrict__ tw,
                                                    const u64* __restrict__ twsh, const double* __restrict__ twf,
-                                                   const ModConst* __restrict__ mc) {
+                                                   const ModConst* __restrict__ mc, int il) {
   constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1;
   __shared__ u64 sh[LDS_WORDS];
-  const int limb = blockIdx.y;
+  const int limb = grid_limb(blockIdx.y, il);
   const int m = limb_mod(map, limb);
   if (m < 0) return;
   const u64 N = 1ull << LOGN;
@@ -585,10 +618,10 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2_sub(u64* data, LimbMap map, c
                                                        const u64* __restrict__ twsh, const double* __restrict__ twf,
                                                        const ModConst* __restrict__ mc, int nq,
                                                        const u64* __restrict__ x, int x_stride,
-                                                       const u64* __restrict__ cpairs, u64* out) {
+                                                       const u64* __restrict__ cpairs, u64* out, int il) {
   constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1;
   __shared__ u64 sh[LDS_WORDS];
-  const int limb = blockIdx.y;
+  const int limb = grid_limb(blockIdx.y, il);
   const int m = limb_mod(map, limb);
   if (m < 0) return;
   const int p = limb / nq, t = limb - p * nq;
@@ -622,7 +655,7 @@ static void ntt2_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const
   }
   ProfScope ps("ntt_fwd_rows_sub", s, 24.0 * nlimbs * T.N);
   hipLaunchKernelGGL((k_ntt_rows2_sub<LOGN, GC, GD>), gr, dim3(TPB), 0, s, y, map, T.psi, T.psi_sh, T.psi_f, T.mc,
-                     nq, x, x_stride, cpairs, out);
+                     nq, x, x_stride, cpairs, out, interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave));
 }
 
 template <int LOGN, int GA, int GB, int GC, int GD>
@@ -631,6 +664,7 @@ static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& ma
   constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
   static_assert(GA + GB + GC + GD == LOGN, "stage split");
   dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
+  const int il = interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave);
   if (!inverse) {
     {
       ProfScope ps("ntt_fwd_cols", s, pass_bytes);
@@ -639,12 +673,12 @@ static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& ma
     }
     ProfScope ps("ntt_fwd_rows", s, pass_bytes);
     hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false>), gr, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh,
-                       T.psi_f, T.mc);
+                       T.psi_f, T.mc, il);
   } else {
     {
       ProfScope ps("ntt_inv_rows", s, pass_bytes);
       hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, true>), gr, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh,
-                         T.ipsi_f, T.mc);
+                         T.ipsi_f, T.mc, il);
     }
     ProfScope ps("ntt_inv_cols", s, pass_bytes);
     hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, true>), gc, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh,
@@ -744,10 +778,10 @@ void launch_automorph(const DeviceTables& T, u64* out, const u64* in, int nlimbs
 enum { EW_ADD = 0, EW_SUB, EW_MUL, EW_MULACC, EW_NEG };
 
 __global__ void k_elementwise(int op, u64* out, const u64* a, const u64* b, int nlimbs, int b_limbs, LimbMap map,
-                              int logN, const ModConst* __restrict__ mc) {
+                              int logN, const ModConst* __restrict__ mc, int il) {
   const u64 N = 1ull << logN;
   u32 i = blockIdx.x * TPB + threadIdx.x;
-  int k = blockIdx.y;
+  int k = grid_limb(blockIdx.y, il);
   if (i >= N || k >= nlimbs) return;
   int m = limb_mod(map, k);
   if (m < 0) return;
@@ -770,7 +804,8 @@ static void ew(const DeviceTables& T, int op, u64* out, const u64* a, const u64*
   double words = (double)nlimbs * (op == EW_MULACC ? 3 : (op == EW_NEG ? 2 : 2)) + (op == EW_NEG ? 0 : b_limbs);
   ProfScope ps("elementwise", s, 8.0 * T.N * words);
   dim3 grid(cdiv(T.N, TPB), nlimbs);
-  hipLaunchKernelGGL(k_elementwise, grid, dim3(TPB), 0, s, op, out, a, b, nlimbs, b_limbs, m, T.logN, T.mc);
+  hipLaunchKernelGGL(k_elementwise, grid, dim3(TPB), 0, s, op, out, a, b, nlimbs, b_limbs, m, T.logN, T.mc,
+                     interleave_of(nlimbs, b_limbs, g_knobs.ew_interleave));
 }
 void launch_add(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nl, const LimbMap& m,
                 hipStream_t s) { ew(T, EW_ADD, out, a, b, nl, nl, m, s); }
@@ -789,10 +824,10 @@ struct SumTerms {
   const u64* p[SUM_MAX_TERMS];
 };
 __global__ void k_mul_sum(u64* out, SumTerms t, int nterms, int accumulate, int b_limbs, LimbMap map, int logN,
-                          const ModConst* __restrict__ mc) {
+                          const ModConst* __restrict__ mc, int il) {
   const u64 N = 1ull << logN;
   u32 i = blockIdx.x * TPB + threadIdx.x;
-  int k = blockIdx.y;
+  int k = grid_limb(blockIdx.y, il);
   if (i >= N) return;
   int m = limb_mod(map, k);
   if (m < 0) return;
@@ -837,7 +872,8 @@ void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const 
     }
     ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nt + 1 + (acc ? 1 : 0)) + (double)bl * nt));
     dim3 grid(cdiv(T.N, TPB), nl);
-    hipLaunchKernelGGL(k_mul_sum, grid, dim3(TPB), 0, s, out, t, nt, acc ? 1 : 0, bl, m, T.logN, T.mc);
+    hipLaunchKernelGGL(k_mul_sum, grid, dim3(TPB), 0, s, out, t, nt, acc ? 1 : 0, bl, m, T.logN, T.mc,
+                       interleave_of(nl, bl, g_knobs.ew_interleave));
   }
 }
 
@@ -850,10 +886,10 @@ struct SumMulti {
 };
 template <int G>
 __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map, int logN,
-                                const ModConst* __restrict__ mc) {
+                                const ModConst* __restrict__ mc, int il) {
   const u64 N = 1ull << logN;
   u32 i = blockIdx.x * TPB + threadIdx.x;
-  int k = blockIdx.y;
+  int k = grid_limb(blockIdx.y, il);
   if (i >= N) return;
   int m = limb_mod(map, k);
   if (m < 0) return;
@@ -923,11 +959,12 @@ bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, co
   }
   ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nterms + nouts) + (double)bl * present));
   dim3 grid(cdiv(T.N, TPB), nl);
+  const int il = interleave_of(nl, bl, g_knobs.ew_interleave);
   switch (nouts) {
-    case 1: hipLaunchKernelGGL(k_mul_sum_multi<1>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc); break;
-    case 2: hipLaunchKernelGGL(k_mul_sum_multi<2>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc); break;
-    case 3: hipLaunchKernelGGL(k_mul_sum_multi<3>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc); break;
-    default: hipLaunchKernelGGL(k_mul_sum_multi<4>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc); break;
+    case 1: hipLaunchKernelGGL(k_mul_sum_multi<1>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
+    case 2: hipLaunchKernelGGL(k_mul_sum_multi<2>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
+    case 3: hipLaunchKernelGGL(k_mul_sum_multi<3>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
+    default: hipLaunchKernelGGL(k_mul_sum_multi<4>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
   }
   return true;
 }

@@ -50,3 +50,24 @@ def test_context_without_device_reports_error():
     with pytest.raises(he.HeError) as e:
         he.chain_context(I.SMALL)
     assert e.value.status == -6
+
+
+def test_knobs_host_side():
+    """Launch-shape knobs are host state: names and ranges are checked, and
+    every knob the autotuner sweeps exists with its candidate values."""
+    from paper_2305_17341_amd import autotune, he
+    if not os.path.exists(he.LIB_PATH):
+        pytest.skip("library not built")
+    for name, values in autotune.CANDIDATES.items():
+        old = he.knob_get(name)
+        try:
+            for v in values:
+                he.knob_set(name, v)
+                assert he.knob_get(name) == v
+        finally:
+            he.knob_set(name, old)
+    for name, bad in [("ms_members", 0), ("ms_members", 9), ("mr_rotations", 17), ("ntt_interleave", 2),
+                      ("ew_interleave", -1), ("no_such_knob", 1)]:
+        with pytest.raises(he.HeError) as e:
+            he.knob_set(name, bad)
+        assert e.value.status == -1

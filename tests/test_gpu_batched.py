@@ -75,3 +75,28 @@ def test_batched_equals_plain_large_d128(large_ctx):
         assert np.array_equal(p.export(), fused[i].export()), f"member {i}"
         err = np.max(np.abs(large_ctx.decrypt(fused[i], 128 * 128) - (As[i] @ Bs[i]).ravel()))
         assert err < 2.0**-15, err
+
+
+def test_knobs_never_change_residues(small_ctx):
+    """Every launch-shape knob value (members and rotations per launch, the
+    limb visiting order of the NTT block passes and of the multiply-sums)
+    gives the residues of the default shape."""
+    from paper_2305_17341_amd import he
+    ds = [16] * 5
+    _, _, cA, cB = _encrypt_pairs(small_ctx, ds, 80)
+    opts = {"flags": 1 | 2}
+    ref = [c.export() for c in small_ctx.matmul_batch(cA, cB, ds, opts=opts)]
+    names = ("ms_members", "mr_members", "mr_rotations", "ntt_interleave", "ew_interleave")
+    saved = {n: he.knob_get(n) for n in names}
+    try:
+        for name, value in [("ms_members", 3), ("mr_members", 2), ("mr_rotations", 5),
+                            ("ntt_interleave", 0), ("ew_interleave", 0)]:
+            he.knob_set(name, value)
+            got = small_ctx.matmul_batch(cA, cB, ds, opts=opts)
+            for i, g in enumerate(got):
+                assert np.array_equal(g.export(), ref[i]), (name, value, i)
+        with pytest.raises(he.HeError):
+            he.knob_set("ntt_interleave", 2)
+    finally:
+        for n, v in saved.items():
+            he.knob_set(n, v)
