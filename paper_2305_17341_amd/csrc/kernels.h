@@ -104,7 +104,8 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
 void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha, int npoly,
                   hipStream_t s);
 // rescale pieces
-void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int npoly, hipStream_t s);
+void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int nout, int npoly,
+                         hipStream_t s);
 void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u64* t, int l, int npoly,
                           int x_stride_limbs, const u64* qlinv /*device [l][2]*/, hipStream_t s);
 

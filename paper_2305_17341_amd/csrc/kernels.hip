@@ -1527,7 +1527,8 @@ void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod
 // ---------------------------------------------------------------------------
 // Rescale: t_i = [x_l]_{q_l} mod q_i (centred top limb), out_i = (x_i - t_i) q_l^{-1}
 // ---------------------------------------------------------------------------
-__global__ void k_rescale_lift(u64* t, const u64* top, int l, int logN, const ModConst* __restrict__ mc) {
+// t [npoly][nout][N] for the moduli q_0..q_{nout-1}, nout <= l
+__global__ void k_rescale_lift(u64* t, const u64* top, int l, int nout, int logN, const ModConst* __restrict__ mc) {
   const u64 N = 1ull << logN;
   u32 i = blockIdx.x * TPB + threadIdx.x;
   int k = blockIdx.y, p = blockIdx.z;
@@ -1542,12 +1543,13 @@ __global__ void k_rescale_lift(u64* t, const u64* top, int l, int logN, const Mo
   } else {
     v = reduce64(x, mk);
   }
-  t[((size_t)p * l + k) * N + i] = v;
+  t[((size_t)p * nout + k) * N + i] = v;
 }
-void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int npoly, hipStream_t s) {
-  ProfScope ps("rescale_lift", s, 8.0 * T.N * npoly * (1.0 + l));
-  dim3 grid(cdiv(T.N, TPB), l, npoly);
-  hipLaunchKernelGGL(k_rescale_lift, grid, dim3(TPB), 0, s, t, top_coef, l, T.logN, T.mc);
+void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int nout, int npoly,
+                         hipStream_t s) {
+  ProfScope ps("rescale_lift", s, 8.0 * T.N * npoly * (1.0 + nout));
+  dim3 grid(cdiv(T.N, TPB), nout, npoly);
+  hipLaunchKernelGGL(k_rescale_lift, grid, dim3(TPB), 0, s, t, top_coef, l, nout, T.logN, T.mc);
 }
 __global__ void k_rescale_final(u64* out, const u64* x, const u64* t, int l, int x_stride_limbs, const u64* qlinv,
                                 int logN, const ModConst* __restrict__ mc) {

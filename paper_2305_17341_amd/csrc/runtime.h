@@ -104,11 +104,11 @@ struct HeCtxImpl {
   HeCt add(const HeCt& a, const HeCt& b, bool sub);
   void add_into(HeCt& acc, const HeCt& b);
   HeCt drop(const HeCt& a, int level);
-  HeCt rescale(const HeCt& a);
+  HeCt rescale(const HeCt& a, int out_level = -1);
   DevBuf decompose(const u64* d, int level, int B = 1);
   HeCt hoisted(const HeCt& x, const u64* digits, u64 g);
   std::vector<HeCt> hoisted_multi(const HeCt& x, const u64* digits, const std::vector<u64>& gs);
-  HeCt moddown(const HeCt& x);
+  HeCt moddown(const HeCt& x, int out_level = -1);
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);
   HeCt rotate(const HeCt& x, long step);
@@ -128,8 +128,8 @@ struct HeCtxImpl {
   HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t, int npz, int npt, bool lazy = false);
   void accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   HeCt relin_sum(const DevBuf& acc3, int level, double scale, int B);
-  std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz);
-  std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t, int npt);
+  std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level = -1);
+  std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t, int npt, int out_level = -1);
   void align_sides(std::vector<HeCt>& Ak, std::vector<HeCt>& Bk);
   void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,

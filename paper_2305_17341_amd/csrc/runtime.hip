@@ -609,18 +609,22 @@ HeCt HeCtxImpl::drop(const HeCt& a, int level) {
   return c;
 }
 
-HeCt HeCtxImpl::rescale(const HeCt& a) {
+// Rescale by q_l; out_level < l - 1 also drops the limbs above it (only the
+// kept limbs are computed: the same residues as Rescale followed by a drop)
+HeCt HeCtxImpl::rescale(const HeCt& a, int out_level) {
   if (a.qp) fail(HE_EINVAL, "rescale of an R_QP element");
   int l = a.level;
   if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
-  const int np = (int)a.polys();
+  if (out_level < 0) out_level = l - 1;
+  if (out_level > l - 1) fail(HE_ELEVEL, "rescale cannot raise the level");
+  const int np = (int)a.polys(), nout = out_level + 1;
   DevBuf top(&pool, (size_t)np * N);
   gather_limbs(top.p, a, l, 1);
   launch_ntt(T, top.p, np, one(l), true, stream);
-  DevBuf t(&pool, (size_t)np * l * N);
-  launch_rescale_lift(T, t.p, top.p, l, np, stream);
-  HeCt c = ct_new(l - 1, false, a.scale / (double)mods[l], a.B);
-  launch_ntt_fwd_sub(T, t.p, l, np, qmap(l), a.d.p, l + 1, qlinv.p + (size_t)l * nmods * 2, c.d.p, stream);
+  DevBuf t(&pool, (size_t)np * nout * N);
+  launch_rescale_lift(T, t.p, top.p, l, nout, np, stream);
+  HeCt c = ct_new(out_level, false, a.scale / (double)mods[l], a.B);
+  launch_ntt_fwd_sub(T, t.p, nout, np, qmap(nout), a.d.p, l + 1, qlinv.p + (size_t)l * nmods * 2, c.d.p, stream);
   return c;
 }
 
@@ -684,20 +688,23 @@ std::vector<HeCt> HeCtxImpl::hoisted_multi(const HeCt& x, const u64* digits, con
   return out;
 }
 
-// ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact centred residue
-HeCt HeCtxImpl::moddown(const HeCt& x) {
+// ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact
+// centred residue; out_level < l keeps (and computes) only the limbs up to it
+HeCt HeCtxImpl::moddown(const HeCt& x, int out_level) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
-  int nq = nq_of(x.level), nqp = nqp_of(x.level);
+  if (out_level < 0) out_level = x.level;
+  if (out_level > x.level) fail(HE_ELEVEL, "moddown cannot raise the level");
+  int nq = nq_of(out_level), nqp = nqp_of(x.level);
   const int np = (int)x.polys();
   DevBuf pc(&pool, (size_t)np * alpha * N);
-  gather_limbs(pc.p, x, nq, alpha);
+  gather_limbs(pc.p, x, nq_of(x.level), alpha);
   LimbMap pm;
   pm.n = alpha;
   for (int k = 0; k < alpha; k++) pm.idx[k] = (short)(L + 1 + k);
   launch_ntt(T, pc.p, np * alpha, pm, true, stream);
   DevBuf y(&pool, (size_t)np * nq * N);
   launch_fbc_to_q(T, y.p, pc.p, nq, np, down, stream);
-  HeCt c = ct_new(x.level, false, x.scale, x.B);
+  HeCt c = ct_new(out_level, false, x.scale, x.B);
   launch_ntt_fwd_sub(T, y.p, nq, np, qmap(nq), x.d.p, nqp, pinv.p, c.d.p, stream);
   n_moddown += x.B;
   return c;
@@ -1111,7 +1118,9 @@ static void col_mask(int n, int k, bool second, std::vector<double>& out) {
 
 // A side: A_k = C^k Z a.  A_k = Rescale(ModDown(m_k (.) HR(B_b, r) + m'_k (.) HR(B'_b, r))),
 // k = b n1z + r, with bases B_b = Rot(B_{b-1}, n1z), B'_0 = Rot(Z a, -n), B'_b = Rot(B'_{b-1}, n1z)
-std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int npz) {
+// out_level (if >= 0) caps the level of the A_k: limbs above it are never
+// computed (the same residues as computing them and dropping them).
+std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level) {
   HeCt A0 = sigma_dcd(ca, n, n1z, npz);
   const int lvl = A0.level;
   if (lvl < 1) fail(HE_ELEVEL, "no level left for the column shifts");
@@ -1168,7 +1177,7 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       h1[r] = HeCt();
       if (k > 0) h2[r] = HeCt();
       HeCt md = moddown(acc);
-      Ak[k] = rescale(md);
+      Ak[k] = rescale(md, out_level >= 0 ? std::min(out_level, lvl - 1) : -1);
       Ak[k].scale = Bb.scale;
     }
   }
@@ -1176,9 +1185,11 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
 }
 
 // B side: B_k = R^k T b.  C_0 = T b, C_b = Rot(C_{b-1}, n n1t), B_k = ModDown(HR(C_b, n r))
-std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int npt) {
+// out_level (if >= 0) caps the level of the B_k, as for the A side
+std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int npt, int out_level) {
   HeCt Cb = tau_dcd(cb, n, n1t, npt);
   const int lvl = Cb.level;
+  const int ol = out_level >= 0 ? std::min(out_level, lvl) : lvl;
   std::vector<HeCt> Bk(n);
   for (int b = 0; b * n1t < n; b++) {
     if (b > 0) Cb = rotate(Cb, (long)n * n1t);
@@ -1190,9 +1201,9 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int n
       for (int r = 1; r < nr; r++) gs.push_back(galois((long)n * r));
       hs = hoisted_multi(Cb, d1.p, gs);
     }
-    Bk[b * n1t] = ct_copy(Cb);
+    Bk[b * n1t] = ol < lvl ? drop(Cb, ol) : ct_copy(Cb);
     for (int r = 1; r < nr; r++) {
-      Bk[b * n1t + r] = moddown(hs[r - 1]);
+      Bk[b * n1t + r] = moddown(hs[r - 1], ol);
       hs[r - 1] = HeCt();
     }
   }
@@ -1249,8 +1260,11 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, 
     fail(HE_EINVAL, "bad matrix size / baby-step count / decomposition");
   int dz = npz >= n - 1 ? 1 : ceil_div_i(n - 1, npz), dt = npt >= n - 1 ? 1 : ceil_div_i(n - 1, npt);
   if (ca.level < std::max(dz + 1, dt) + 1) fail(HE_ELEVEL, "not enough levels for the product");
-  std::vector<HeCt> Ak = matmul_side_a(ca, n, n1z, npz);
-  std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t, npt);
+  // both sides produced at their common level (A: sigma, then the masks;
+  // B: tau); align_sides only guards the prediction
+  const int common = std::min(ca.level - dz - 1, cb.level - dt);
+  std::vector<HeCt> Ak = matmul_side_a(ca, n, n1z, npz, common);
+  std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t, npt, common);
   align_sides(Ak, Bk);
   HeCt acc;
   if (lazy) {
@@ -1282,15 +1296,18 @@ std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int r
   std::vector<bool> set(k * k, false);
   int acc_level = 0;
   double acc_scale = 0;
+  // the sides' common level: A after the transposition, sigma and the masks,
+  // B after tau
+  const int common = std::min(level - 1 - dz - 1, level - 1 - dt);
   for (int r = 0; r < rb; r++) {
     std::vector<std::vector<HeCt>> A(k), B(k);
     for (int a = 0; a < k; a++) {
       HeCt xt = lintrans(*x[r * k + a], LT_TRANSPOSE, n, n1g, 1.0 / (double)n_samples);
-      A[a] = matmul_side_a(xt, n, n1z, npz);
+      A[a] = matmul_side_a(xt, n, n1z, npz, common);
     }
     for (int b = 0; b < k; b++) {
       HeCt xb = drop(*x[r * k + b], level - 1);
-      B[b] = matmul_side_b(xb, n, n1t, npt);
+      B[b] = matmul_side_b(xb, n, n1t, npt, common);
     }
     for (int a = 0; a < k; a++) align_sides(A[a], B[0]);
     for (int b = 0; b < k; b++) align_sides(A[0], B[b]);
