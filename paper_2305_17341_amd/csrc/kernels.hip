@@ -1308,6 +1308,12 @@ __device__ __forceinline__ u64 u128_reduce(const U128& x, const ModConst& m) {
   return add_mod(mul_mod(h, m.r64, m), reduce64(x.lo, m), m.q);
 }
 
+// streaming accesses: each key word and each output word is touched once, so
+// they are loaded and stored non-temporally and leave L2 to the digits,
+// which every rotation of a launch reads again
+__device__ __forceinline__ u64 ldnt(const u64* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void stnt(u64* p, u64 v) { __builtin_nontemporal_store(v, p); }
+
 template <int MB, bool F64>
 __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ digits, const u64* __restrict__ key,
                                              const u64* __restrict__ c0, const u64* __restrict__ pmod, int nq,
@@ -1321,7 +1327,7 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
 #pragma unroll
     for (int b = 0; b < MB; b++) s0[b] = s1[b] = 0.0;
     // software-pipelined: the loads of digit j + 1 are in flight while j is multiplied
-    u64 kbn = key[((size_t)0 * nmods + m) * N + i], kan = key[((size_t)1 * nmods + m) * N + i], dn[MB];
+    u64 kbn = ldnt(&key[((size_t)0 * nmods + m) * N + i]), kan = ldnt(&key[((size_t)1 * nmods + m) * N + i]), dn[MB];
 #pragma unroll
     for (int b = 0; b < MB; b++) dn[b] = digits[(size_t)(b0 + b) * dstride + (size_t)pos * N + src];
     for (int j = 0; j < beta; j++) {
@@ -1330,8 +1336,8 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
 #pragma unroll
       for (int b = 0; b < MB; b++) d[b] = u2d(dn[b]);
       if (j + 1 < beta) {
-        kbn = key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i];
-        kan = key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i];
+        kbn = ldnt(&key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i]);
+        kan = ldnt(&key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i]);
 #pragma unroll
         for (int b = 0; b < MB; b++)
           dn[b] = digits[(size_t)(b0 + b) * dstride + ((size_t)(j + 1) * nqp + pos) * N + src];
@@ -1351,7 +1357,7 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
     U128 s0[MB], s1[MB];
 #pragma unroll
     for (int b = 0; b < MB; b++) s0[b] = s1[b] = U128{0, 0};
-    u64 kbn = key[((size_t)0 * nmods + m) * N + i], kan = key[((size_t)1 * nmods + m) * N + i], dn[MB];
+    u64 kbn = ldnt(&key[((size_t)0 * nmods + m) * N + i]), kan = ldnt(&key[((size_t)1 * nmods + m) * N + i]), dn[MB];
 #pragma unroll
     for (int b = 0; b < MB; b++) dn[b] = digits[(size_t)(b0 + b) * dstride + (size_t)pos * N + src];
     for (int j = 0; j < beta; j++) {
@@ -1360,8 +1366,8 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
 #pragma unroll
       for (int b = 0; b < MB; b++) d[b] = dn[b];
       if (j + 1 < beta) {
-        kbn = key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i];
-        kan = key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i];
+        kbn = ldnt(&key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i]);
+        kan = ldnt(&key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i]);
 #pragma unroll
         for (int b = 0; b < MB; b++)
           dn[b] = digits[(size_t)(b0 + b) * dstride + ((size_t)(j + 1) * nqp + pos) * N + src];
@@ -1384,8 +1390,8 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
       const u64 v = c0[((size_t)(b0 + b) * nq + pos) * N + src];
       r0[b] = add_mod(r0[b], mul_const_any(v, pmod[2 * m], pmod[2 * m + 1], mk), mk.q);
     }
-    out[((size_t)(b0 + b) * nqp + pos) * N + i] = r0[b];
-    out[((size_t)(B + b0 + b) * nqp + pos) * N + i] = r1[b];
+    stnt(&out[((size_t)(b0 + b) * nqp + pos) * N + i], r0[b]);
+    stnt(&out[((size_t)(B + b0 + b) * nqp + pos) * N + i], r1[b]);
   }
 }
 
