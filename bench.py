@@ -218,7 +218,8 @@ def main():
         del bp_outs
     c0 = ctx.op_counts()
     t_total, lat, outs = timed(head, True)
-    fams = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_fwd_rows_sub", "ntt_inv_rows", "ntt_inv_cols", "multsum",
+    fams = ["ntt_fwd_cols", "ntt_fwd_cols_modup", "ntt_fwd_rows", "ntt_fwd_rows_sub", "ntt_inv_rows", "ntt_inv_cols",
+            "multsum",
             "multsum_rot", "modup",
             "fbc_to_q",
             "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor", "plift"]

@@ -13,6 +13,7 @@ struct DeviceTables {
   u64 N = 0;
   int nmods = 0;
   ModConst* mc = nullptr;      // [nmods]
+  int bits[HE_MAXMOD] = {};    // host copy: bit length of each modulus
   u64* psi = nullptr;          // [nmods][N] psi^brv(k)
   u64* psi_sh = nullptr;
   u64* ipsi = nullptr;         // [nmods][N] psi^-brv(k)
@@ -32,6 +33,12 @@ void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map
 // [npoly][x_stride][N] and c pairs (value, Shoup companion) per t < nq
 void launch_ntt_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,
                         int x_stride, const u64* cpairs, u64* out, hipStream_t s);
+
+// Decompose's conversion fused into the forward NTT of the digits (false:
+// not available for this ring size; nothing was launched)
+struct FbcTable;
+bool launch_modup_ntt(const DeviceTables& T, u64* digits, const u64* y, const u64* ntt_in, int level, int L,
+                      int alpha, int beta, const FbcTable* tabs, int batch, const LimbMap& rows_map, hipStream_t s);
 
 // data movement / elementwise (data laid out [nlimbs][N], limb k uses map)
 void launch_automorph(const DeviceTables& T, u64* out, const u64* in, int nlimbs, u64 g, hipStream_t s);

@@ -414,9 +414,16 @@ __device__ __forceinline__ int lds_rc(int r, int c, int C) { return r * (C + 1) 
 __device__ __forceinline__ int lds_be(int b, int e, int T1) { return b * (T1 + (T1 >> 4) + 1) + e + (e >> 4); }
 #define LDS_WORDS (TILE + TILE / 16 + 64)
 
+// Loads of the forward column pass: the limb itself, or a value computed
+// from other limbs at the same coefficient (ModupLoad).
+struct LoadPlain {
+  const u64* a;
+  __device__ __forceinline__ u64 operator()(size_t idx) const { return a[idx]; }
+};
+
 // Column pass body: rows R = 2^(GA+GB), C = TILE / R columns per work-group.
-template <int LOGN, int GA, int GB, bool INV, class A>
-__device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh, const A& ar) {
+template <int LOGN, int GA, int GB, bool INV, class A, class LD>
+__device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh, const A& ar, const LD& ld) {
   typedef typename A::V V;
   constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R;
   const int tid = threadIdx.x;
@@ -428,7 +435,7 @@ __device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh
     for (int k = 0; k < ITA; k++) {
       const int it = tid + TPB * k, c = it % C, rl = it / C;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = ar.load(a[(size_t)(rl + (mm << GB)) * T1 + c0 + c]);
+      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = ar.load(ld((size_t)(rl + (mm << GB)) * T1 + c0 + c));
       fwd_group<GA>(v, 0, 0u, ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GA); mm++) sh[lds_rc(rl + (mm << GB), c, C)] = v[mm];
@@ -581,10 +588,10 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
   const ModConst mk = mc[m];
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
-    ntt_cols2_body<LOGN, GA, GB, INV>(a, c0, reinterpret_cast<double*>(sh), ar);
+    ntt_cols2_body<LOGN, GA, GB, INV>(a, c0, reinterpret_cast<double*>(sh), ar, LoadPlain{a});
   } else {
     ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
-    ntt_cols2_body<LOGN, GA, GB, INV>(a, c0, sh, ar);
+    ntt_cols2_body<LOGN, GA, GB, INV>(a, c0, sh, ar, LoadPlain{a});
   }
 }
 
@@ -640,6 +647,123 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2_sub(u64* data, LimbMap map, c
     ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
     ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, sh, ar, SubScaleShoup{oa, xa, cpairs[2 * t], cpairs[2 * t + 1], mk.q});
   }
+}
+
+// Decompose with the basis conversion fused into the forward column pass:
+// the value of digit j at modulus m and coefficient i is
+//   sum_a y_a[i] hat_(a,m) mod q_m,  y_a = coefficient-domain source limb a of
+// digit j already multiplied by its hat inverse,
+// computed while loading the pass's tile (no converted limb goes to memory).
+// The digit's own limbs copy the evaluation-domain input instead.
+struct ModupSrc {
+  const u64* y;       // [B][nq][N]
+  const u64* ntt_in;  // [B][nq][N]
+  int nq, nqp, alpha, beta, L;
+  int ns[16], srcbits[16];
+  const u64* hat_t[16];     // [ns][nmods]
+  const u64* hat_t_sh[16];
+};
+// F64: every source below 4 q (signed exact products, one reduction);
+// otherwise Shoup products.  The source count loop is fixed at 4 with
+// uniform guards, so the loads of a tile's values can all be issued first.
+template <bool F64>
+struct ModupLoad {
+  const u64* y0;
+  u64 N;
+  int ns;
+  u64 q, h[4], hs[4];
+  double qf, qinvf, hf[4];
+  __device__ __forceinline__ u64 operator()(size_t idx) const {
+    u64 x[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) x[a] = a < ns ? y0[(size_t)a * N + idx] : 0;
+    if (F64) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+        if (a < ns) acc += f64_mulmod_signed(u2d(x[a]), hf[a], qf, qinvf);
+      return d2u(f64_canon(acc, qf, qinvf));
+    }
+    u64 acc = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+      if (a < ns) acc = add_mod(acc, shoup_mul(x[a], h[a], hs[a], q), q);
+    return acc;
+  }
+};
+template <int LOGN, int GA, int GB>
+__global__ void __launch_bounds__(TPB) k_ntt_cols2_modup(u64* digits, ModupSrc S, const u64* __restrict__ tw,
+                                                         const u64* __restrict__ twsh,
+                                                         const double* __restrict__ twf, int nmods,
+                                                         const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int per = S.beta * S.nqp;
+  const int b = limb / per, rem = limb - b * per, j = rem / S.nqp, pos = rem - j * S.nqp;
+  const u64 N = 1ull << LOGN;
+  u64* a = digits + (size_t)limb * N;
+  const int c0 = blockIdx.x * C;
+  if (pos < S.nq && pos / S.alpha == j) {
+    const u64* src = S.ntt_in + ((size_t)b * S.nq + pos) * N;
+    for (int e = threadIdx.x; e < TILE; e += TPB) {
+      const size_t idx = (size_t)(e / C) * T1 + c0 + e % C;
+      a[idx] = src[idx];
+    }
+    return;
+  }
+  const int m = pos < S.nq ? pos : S.L + 1 + (pos - S.nq);
+  const ModConst mk = mc[m];
+  ModupLoad<true> lf;
+  lf.y0 = S.y + ((size_t)b * S.nq + (size_t)j * S.alpha) * N;
+  lf.N = N;
+  lf.ns = S.ns[j];
+  lf.q = mk.q;
+  lf.qf = mk.qf;
+  lf.qinvf = mk.qinvf;
+  for (int x = 0; x < 4; x++) {
+    const bool in = x < lf.ns;
+    lf.h[x] = in ? S.hat_t[j][(size_t)x * nmods + m] : 0;
+    lf.hs[x] = in ? S.hat_t_sh[j][(size_t)x * nmods + m] : 0;
+    lf.hf[x] = u2d(lf.h[x]);
+  }
+  ModupLoad<false> li;
+  li.y0 = lf.y0;
+  li.N = N;
+  li.ns = lf.ns;
+  li.q = mk.q;
+  for (int x = 0; x < 4; x++) {
+    li.h[x] = lf.h[x];
+    li.hs[x] = lf.hs[x];
+  }
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
+    if (S.srcbits[j] <= (int)mk.bits + 1)
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, lf);
+    else
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, li);
+  } else {
+    ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, li);
+  }
+}
+
+template <int LOGN, int GA, int GB, int GC, int GD>
+static void ntt2_modup(const DeviceTables& T, u64* digits, const ModupSrc& S, int batch, const LimbMap& rows_map,
+                       hipStream_t s) {
+  constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
+  const int nlimbs = batch * S.beta * S.nqp;
+  dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
+  {
+    ProfScope ps("ntt_fwd_cols_modup", s, 8.0 * T.N * batch * (2.0 * S.nq + (double)S.beta * S.nqp));
+    hipLaunchKernelGGL((k_ntt_cols2_modup<LOGN, GA, GB>), gc, dim3(TPB), 0, s, digits, S, T.psi, T.psi_sh, T.psi_f,
+                       T.nmods, T.mc);
+  }
+  int active = 0;
+  for (int k = 0; k < rows_map.n; k++) active += rows_map.idx[k] >= 0;
+  ProfScope ps("ntt_fwd_rows", s, 16.0 * T.N * batch * active);
+  hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false>), gr, dim3(TPB), 0, s, digits, rows_map, T.psi, T.psi_sh,
+                     T.psi_f, T.mc, interleave_of(nlimbs, modulus_period(rows_map), g_knobs.ntt_interleave));
 }
 
 template <int LOGN, int GA, int GB, int GC, int GD>
@@ -747,6 +871,37 @@ void launch_ntt_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const 
   dim3 grid(cdiv(T.N, TPB), nq, npoly);
   ProfScope ps("moddown_final", s, 8.0 * T.N * 3.0 * npoly * nq);
   hipLaunchKernelGGL(k_moddown_final, grid, dim3(TPB), 0, s, out, x, y, nq, cpairs, x_stride, T.logN, T.mc);
+}
+
+// Fused ModUp + forward NTT of every digit (see k_ntt_cols2_modup); false
+// when the ring size has no register-blocked NTT (the caller then converts
+// and transforms separately).  y holds the sources times their hat inverses.
+bool launch_modup_ntt(const DeviceTables& T, u64* digits, const u64* y, const u64* ntt_in, int level, int L,
+                      int alpha, int beta, const FbcTable* tabs, int batch, const LimbMap& rows_map, hipStream_t s) {
+  if (T.logN < 12 || T.logN > 16 || alpha > 4 || beta > 16) return false;
+  ModupSrc S;
+  S.y = y;
+  S.ntt_in = ntt_in;
+  S.nq = level + 1;
+  S.nqp = level + 1 + alpha;
+  S.alpha = alpha;
+  S.beta = beta;
+  S.L = L;
+  for (int j = 0; j < beta; j++) {
+    S.ns[j] = tabs[j].ns;
+    S.srcbits[j] = 0;
+    for (int a = 0; a < tabs[j].ns; a++) S.srcbits[j] = std::max(S.srcbits[j], (int)T.bits[tabs[j].src[a]]);
+    S.hat_t[j] = tabs[j].hat_t;
+    S.hat_t_sh[j] = tabs[j].hat_t_sh;
+  }
+  switch (T.logN) {
+    case 16: ntt2_modup<16, 4, 4, 4, 4>(T, digits, S, batch, rows_map, s); break;
+    case 15: ntt2_modup<15, 4, 3, 4, 4>(T, digits, S, batch, rows_map, s); break;
+    case 14: ntt2_modup<14, 4, 3, 4, 3>(T, digits, S, batch, rows_map, s); break;
+    case 13: ntt2_modup<13, 3, 3, 4, 3>(T, digits, S, batch, rows_map, s); break;
+    default: ntt2_modup<12, 3, 3, 3, 3>(T, digits, S, batch, rows_map, s); break;
+  }
+  return true;
 }
 
 // ---------------------------------------------------------------------------

@@ -51,6 +51,7 @@ struct HeCtxImpl {
   int logN = 0;
   u64 N = 0;
   int L = 0, alpha = 0, beta = 0, nmods = 0;
+  bool fused_modup = false;  // Decompose's conversion fused into the digits' NTT (log N 12..16)
   u64 mods[HE_MAXMOD];
   double delta = 0, sigma = 0;
   u64 seed = 0;

@@ -274,6 +274,7 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
   L = (int)p->n_q - 1;
   alpha = (int)p->n_p;
   beta = (L + alpha) / alpha;
+  fused_modup = logN >= 12 && logN <= 16;
   if (beta > 16) fail(HE_EINVAL, "at most 16 decomposition digits");
   nmods = L + 1 + alpha;
   std::vector<int> bits;
@@ -329,6 +330,7 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
   T.N = N;
   T.nmods = nmods;
   T.mc = (ModConst*)table_upload(mc.data(), sizeof(ModConst) * nmods);
+  for (int m = 0; m < nmods; m++) T.bits[m] = (int)mc[m].bits;
   T.psi = table_upload(psi.data(), psi.size() * 8);
   T.psi_sh = table_upload(psi_sh.data(), psi_sh.size() * 8);
   T.ipsi = table_upload(ipsi.data(), ipsi.size() * 8);
@@ -638,7 +640,6 @@ DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
   copy_limbs(coef.p, d, (size_t)B * nq);
   launch_ntt(T, coef.p, B * nq, qmap(nq), true, stream);
   DevBuf dig(&pool, (size_t)B * bl * nqp * N);
-  launch_modup(T, dig.p, coef.p, d, level, L, alpha, bl, up[level].data(), B, stream);
   LimbMap m;
   m.n = bl * nqp;
   if (m.n > 960) fail(HE_EINVAL, "too many digit limbs");
@@ -647,6 +648,22 @@ DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
       bool own = pos < nq && pos / alpha == j;
       m.idx[j * nqp + pos] = own ? (short)-1 : (short)qp_mod(level, pos);
     }
+  if (fused_modup) {
+    // sources times their hat inverses, then conversion + NTT in one pass pair
+    const std::vector<FbcTable>& tabs = up[level];
+    std::vector<u64> hinv((size_t)2 * nq);
+    for (int t = 0; t < nq; t++) {
+      hinv[2 * t] = tabs[t / alpha].hatinv[t % alpha];
+      hinv[2 * t + 1] = tabs[t / alpha].hatinv_sh[t % alpha];
+    }
+    launch_mul_const(T, coef.p, coef.p, B * nq, hinv.data(), qmap(nq), stream);
+    if (launch_modup_ntt(T, dig.p, coef.p, d, level, L, alpha, bl, tabs.data(), B, m, stream)) {
+      n_decompose += B;
+      return dig;
+    }
+    fail(HE_EINVAL, "fused decomposition unavailable for this ring size");
+  }
+  launch_modup(T, dig.p, coef.p, d, level, L, alpha, bl, up[level].data(), B, stream);
   launch_ntt(T, dig.p, B * m.n, m, false, stream);
   n_decompose += B;
   return dig;
