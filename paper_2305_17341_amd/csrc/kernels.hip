@@ -22,7 +22,7 @@ struct Knobs {
   int ms_members = 8;   // batch members per key-inner-product launch (1..8)
   int mr_members = 8;   // batch members per multi-rotation launch (1..8)
   int mr_rotations = 16;  // rotations per multi-rotation launch (1..16)
-  int ntt_interleave = 1;  // block passes visit limbs of one modulus back to back (0/1)
+  int ntt_interleave = 0;  // block passes visit limbs of one modulus back to back (0/1)
   int ew_interleave = 1;   // plaintext-broadcast sums visit the limbs sharing a plaintext back to back (0/1)
 } g_knobs;
 }
