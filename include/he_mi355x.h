@@ -274,7 +274,9 @@ he_status he_last_op_ms(const he_ctx* ctx, double* ms);
  * "ntt_inv_rows", "ntt_inv_cols" (the two passes of each transform),
  * "ntt_fwd_rows_sub" (the forward block pass that ends ModDown and Rescale:
  * (x - y) c), "ntt_fwd_cols_modup" (the forward column pass of Decompose's
- * digits, basis conversion included), "multsum", "multsum_rot" (several rotations of one
+ * digits, basis conversion included), "ntt_fwd_cols_fbc" (the forward
+ * column pass of ModDown, P-to-Q conversion included), "fbc_prep" (its
+ * per-coefficient quotient), "multsum", "multsum_rot" (several rotations of one
  * decomposition), "modup", "fbc_to_q", "moddown_final", "rescale_lift",
  * "rescale_final", "elementwise", "tensor", "plift".  While enabled, HIP
  * events are recorded on the launching stream around every launch of the

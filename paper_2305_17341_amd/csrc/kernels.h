@@ -91,6 +91,11 @@ struct FbcTable {
 // coefficient-domain conversion of digit j (to be transformed by the caller)
 void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64* ntt_in, int level, int L,
                   int alpha, int beta, const FbcTable* tabs /* host array [beta] */, int batch, hipStream_t s);
+// ModDown's conversion fused into the forward NTT of the Q limbs (the tail
+// (x - y) P^-1 in its block pass): scratch y [npoly][nq][N] and V
+// [npoly][ns + 1][N]; false when the ring size has no register-blocked NTT
+bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
+                          const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s);
 // y[npoly][nq] = exact centred lift of the source limbs xp[npoly][ns] to each q_t
 void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                      hipStream_t s);

@@ -151,6 +151,32 @@ __device__ __forceinline__ int grid_limb(int y, int outer) {
   const int inner = gridDim.y / outer;
   return (y % outer) * inner + y / outer;
 }
+// Work-group -> (coefficient block, limb) for the multiply-sums whose limbs
+// come in `outer` groups of `inner` limbs, limb g * inner + t using broadcast
+// operand t: with a 1-D grid, the `outer` limbs that share operand t at one
+// coefficient block get consecutive ids of one residue mod 8, so they run back
+// to back on one XCD and the shared block comes from its L2.  outer <= 1:
+// the 2-D grid (x = block, y = limb).
+__device__ __forceinline__ void block_limb(int outer, int inner, int nblk, int& blk, int& k) {
+  if (outer <= 1) {
+    blk = blockIdx.x;
+    k = blockIdx.y;
+    return;
+  }
+  const int id = blockIdx.x;
+  const int xcd = id & 7;
+  int r = id >> 3;
+  const int g = r % outer;
+  r /= outer;
+  const int nhi = nblk >> 3;
+  blk = (r % nhi) * 8 + xcd;
+  k = g * inner + r / nhi;
+}
+// launch shape for block_limb: nl limbs in groups sharing a period of bl
+static inline dim3 sum_grid(int nblk, int nl, int bl, int knob, int& outer) {
+  outer = (knob && bl > 0 && nl > bl && nl % bl == 0 && nblk % 8 == 0) ? nl / bl : 1;
+  return outer > 1 ? dim3((unsigned)(nblk * nl)) : dim3(nblk, nl);
+}
 // host side: the interleave factor for nlimbs limbs in groups of `period`
 static inline int interleave_of(int nlimbs, int period, int knob) {
   return (knob && period > 0 && nlimbs > period && nlimbs % period == 0) ? nlimbs / period : 1;
@@ -768,11 +794,11 @@ static void ntt2_modup(const DeviceTables& T, u64* digits, const ModupSrc& S, in
 
 template <int LOGN, int GA, int GB, int GC, int GD>
 static void ntt2_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,
-                         int x_stride, const u64* cpairs, u64* out, hipStream_t s) {
+                         int x_stride, const u64* cpairs, u64* out, hipStream_t s, bool do_cols = true) {
   constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
   const int nlimbs = nq * npoly;
   dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
-  {
+  if (do_cols) {
     ProfScope ps("ntt_fwd_cols", s, 16.0 * nlimbs * T.N);
     hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, y, map, T.psi, T.psi_sh, T.psi_f,
                        T.mc);
@@ -935,8 +961,9 @@ enum { EW_ADD = 0, EW_SUB, EW_MUL, EW_MULACC, EW_NEG };
 __global__ void k_elementwise(int op, u64* out, const u64* a, const u64* b, int nlimbs, int b_limbs, LimbMap map,
                               int logN, const ModConst* __restrict__ mc, int il) {
   const u64 N = 1ull << logN;
-  u32 i = blockIdx.x * TPB + threadIdx.x;
-  int k = grid_limb(blockIdx.y, il);
+  int blk, k;
+  block_limb(il, b_limbs, (int)(N / TPB), blk, k);
+  u32 i = blk * TPB + threadIdx.x;
   if (i >= N || k >= nlimbs) return;
   int m = limb_mod(map, k);
   if (m < 0) return;
@@ -958,9 +985,9 @@ static void ew(const DeviceTables& T, int op, u64* out, const u64* a, const u64*
   // reads a (and b once per distinct limb), writes out; the accumulate also reads out
   double words = (double)nlimbs * (op == EW_MULACC ? 3 : (op == EW_NEG ? 2 : 2)) + (op == EW_NEG ? 0 : b_limbs);
   ProfScope ps("elementwise", s, 8.0 * T.N * words);
-  dim3 grid(cdiv(T.N, TPB), nlimbs);
-  hipLaunchKernelGGL(k_elementwise, grid, dim3(TPB), 0, s, op, out, a, b, nlimbs, b_limbs, m, T.logN, T.mc,
-                     interleave_of(nlimbs, b_limbs, g_knobs.ew_interleave));
+  int il;
+  dim3 grid = sum_grid((int)cdiv(T.N, TPB), nlimbs, b_limbs, g_knobs.ew_interleave, il);
+  hipLaunchKernelGGL(k_elementwise, grid, dim3(TPB), 0, s, op, out, a, b, nlimbs, b_limbs, m, T.logN, T.mc, il);
 }
 void launch_add(const DeviceTables& T, u64* out, const u64* a, const u64* b, int nl, const LimbMap& m,
                 hipStream_t s) { ew(T, EW_ADD, out, a, b, nl, nl, m, s); }
@@ -981,8 +1008,9 @@ struct SumTerms {
 __global__ void k_mul_sum(u64* out, SumTerms t, int nterms, int accumulate, int b_limbs, LimbMap map, int logN,
                           const ModConst* __restrict__ mc, int il) {
   const u64 N = 1ull << logN;
-  u32 i = blockIdx.x * TPB + threadIdx.x;
-  int k = grid_limb(blockIdx.y, il);
+  int blk, k;
+  block_limb(il, b_limbs, (int)(N / TPB), blk, k);
+  u32 i = blk * TPB + threadIdx.x;
   if (i >= N) return;
   int m = limb_mod(map, k);
   if (m < 0) return;
@@ -1026,9 +1054,9 @@ void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const 
       t.p[j] = p[t0 + j];
     }
     ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nt + 1 + (acc ? 1 : 0)) + (double)bl * nt));
-    dim3 grid(cdiv(T.N, TPB), nl);
-    hipLaunchKernelGGL(k_mul_sum, grid, dim3(TPB), 0, s, out, t, nt, acc ? 1 : 0, bl, m, T.logN, T.mc,
-                       interleave_of(nl, bl, g_knobs.ew_interleave));
+    int il;
+    dim3 grid = sum_grid((int)cdiv(T.N, TPB), nl, bl, g_knobs.ew_interleave, il);
+    hipLaunchKernelGGL(k_mul_sum, grid, dim3(TPB), 0, s, out, t, nt, acc ? 1 : 0, bl, m, T.logN, T.mc, il);
   }
 }
 
@@ -1043,8 +1071,9 @@ template <int G>
 __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map, int logN,
                                 const ModConst* __restrict__ mc, int il) {
   const u64 N = 1ull << logN;
-  u32 i = blockIdx.x * TPB + threadIdx.x;
-  int k = grid_limb(blockIdx.y, il);
+  int blk, k;
+  block_limb(il, b_limbs, (int)(N / TPB), blk, k);
+  u32 i = blk * TPB + threadIdx.x;
   if (i >= N) return;
   int m = limb_mod(map, k);
   if (m < 0) return;
@@ -1113,8 +1142,8 @@ bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, co
     }
   }
   ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nterms + nouts) + (double)bl * present));
-  dim3 grid(cdiv(T.N, TPB), nl);
-  const int il = interleave_of(nl, bl, g_knobs.ew_interleave);
+  int il;
+  dim3 grid = sum_grid((int)cdiv(T.N, TPB), nl, bl, g_knobs.ew_interleave, il);
   switch (nouts) {
     case 1: hipLaunchKernelGGL(k_mul_sum_multi<1>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
     case 2: hipLaunchKernelGGL(k_mul_sum_multi<2>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
@@ -1416,6 +1445,159 @@ void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, 
   ProfScope ps("fbc_to_q", s, 8.0 * T.N * npoly * ((double)tab.ns + nq));
   dim3 grid(cdiv(T.N, TPB), nq < 4 ? nq : 4, npoly);
   hipLaunchKernelGGL(k_fbc_to_q, grid, dim3(TPB), 0, s, y, xp_coef, nq, A, T.logN, T.nmods, T.mc);
+}
+
+// ModDown with the basis conversion fused into the forward column pass.
+// k_fbc_prep stores, per coefficient, v_a = x_a hatinv_a mod p_a and the
+// rounded quotient r of the exact centred lift ([npoly][ns + 1][N]); the
+// column pass of target limb t then loads
+//   sum_a v_a hat_(a,t) - r D mod q_t
+// (the value k_fbc_to_q writes) while filling its tile, and the block pass
+// ends with (x - y) P^-1: no converted limb goes to memory.
+__global__ void k_fbc_prep(u64* V, const u64* xp, FbcArgs A, int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  if (i >= N) return;
+  const int poly = blockIdx.y;
+  const u64* x = xp + (size_t)poly * A.ns * N;
+  u64* o = V + (size_t)poly * (A.ns + 1) * N;
+  u64 v[4];
+  for (int a = 0; a < A.ns; a++) v[a] = shoup_mul(x[(size_t)a * N + i], A.hatinv[a], A.hatinv_sh[a], mc[A.src[a]].q);
+  const u64 r = round_quotient(v, A);
+  for (int a = 0; a < A.ns; a++) o[(size_t)a * N + i] = v[a];
+  o[(size_t)A.ns * N + i] = r;
+}
+// F64 (target of 33 to 46 bits): v = v_hi 2^32 + v_lo, both halves below
+// q_t, signed exact products, one reduction; otherwise Shoup products.
+template <bool F64>
+struct FbcLoad {
+  const u64* v0;
+  u64 N;
+  int ns;
+  u64 q, h[4], hs[4], D, Ds;
+  double qf, qinvf, e0[4], e1[4], e2;
+  __device__ __forceinline__ u64 operator()(size_t idx) const {
+    u64 x[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) x[a] = a < ns ? v0[(size_t)a * N + idx] : 0;
+    const u64 r = v0[(size_t)ns * N + idx];
+    if (F64) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+        if (a < ns) {
+          acc += f64_mulmod_signed(u2d(x[a] & 0xffffffffull), e0[a], qf, qinvf);
+          acc += f64_mulmod_signed(u2d(x[a] >> 32), e1[a], qf, qinvf);
+        }
+      acc -= f64_mulmod_signed(u2d(r), e2, qf, qinvf);
+      return d2u(f64_canon(acc, qf, qinvf));
+    }
+    u64 acc = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+      if (a < ns) acc = add_mod(acc, shoup_mul(x[a], h[a], hs[a], q), q);
+    return sub_mod(acc, shoup_mul(r, D, Ds, q), q);
+  }
+};
+template <int LOGN, int GA, int GB>
+__global__ void __launch_bounds__(TPB) k_ntt_cols2_fbc(u64* y, const u64* __restrict__ V, int nq, FbcArgs A,
+                                                       const u64* __restrict__ tw, const u64* __restrict__ twsh,
+                                                       const double* __restrict__ twf, int nmods,
+                                                       const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, C = TILE / R;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int p = limb / nq, t = limb - p * nq;
+  const u64 N = 1ull << LOGN;
+  u64* a = y + (size_t)limb * N;
+  const int c0 = blockIdx.x * C;
+  const ModConst mk = mc[t];
+  FbcLoad<true> lf;
+  lf.v0 = V + (size_t)p * (A.ns + 1) * N;
+  lf.N = N;
+  lf.ns = A.ns;
+  lf.q = mk.q;
+  lf.qf = mk.qf;
+  lf.qinvf = mk.qinvf;
+  lf.D = A.D_mod_t[2 * t];
+  lf.Ds = A.D_mod_t[2 * t + 1];
+  lf.e2 = A.hat_f[(size_t)t * 3 + 2];
+  for (int x = 0; x < 4; x++) {
+    const bool in = x < A.ns;
+    lf.h[x] = in ? A.hat_t[(size_t)x * nmods + t] : 0;
+    lf.hs[x] = in ? A.hat_t_sh[(size_t)x * nmods + t] : 0;
+    lf.e0[x] = in ? A.hat_f[((size_t)x * nmods + t) * 3] : 0.0;
+    lf.e1[x] = in ? A.hat_f[((size_t)x * nmods + t) * 3 + 1] : 0.0;
+  }
+  FbcLoad<false> li;
+  li.v0 = lf.v0;
+  li.N = N;
+  li.ns = lf.ns;
+  li.q = mk.q;
+  li.D = lf.D;
+  li.Ds = lf.Ds;
+  for (int x = 0; x < 4; x++) {
+    li.h[x] = lf.h[x];
+    li.hs[x] = lf.hs[x];
+  }
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)t * N, mk.qf, mk.qinvf, (double)mk.ninv};
+    if (mk.bits > 32)
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, lf);
+    else
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, li);
+  } else {
+    ShoupArith ar{tw + (size_t)t * N, twsh + (size_t)t * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, li);
+  }
+}
+template <int LOGN, int GA, int GB, int GC, int GD>
+static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const FbcArgs& A, int nq, int npoly,
+                          const LimbMap& map, const u64* x, int x_stride, const u64* pinv, u64* out, hipStream_t s) {
+  constexpr int R = 1 << (GA + GB), C = TILE / R;
+  dim3 gc((1 << LOGN) / R / C, nq * npoly);
+  {
+    ProfScope ps("ntt_fwd_cols_fbc", s, 8.0 * T.N * npoly * ((double)A.ns + 1 + nq));
+    hipLaunchKernelGGL((k_ntt_cols2_fbc<LOGN, GA, GB>), gc, dim3(TPB), 0, s, y, V, nq, A, T.psi, T.psi_sh, T.psi_f,
+                       T.nmods, T.mc);
+  }
+  ntt2_fwd_sub<LOGN, GA, GB, GC, GD>(T, y, nq, npoly, map, x, x_stride, pinv, out, s, false);
+}
+// ModDown of npoly polynomials: xp_coef their P limbs in the coefficient
+// domain [npoly][ns][N], x the R_{Q_l P} data ([npoly][x_stride][N]), out
+// [npoly][nq][N]; false when the ring size has no register-blocked NTT
+bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
+                          const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s) {
+  if (T.logN < 12 || T.logN > 16 || tab.ns > 4) return false;
+  FbcArgs A;
+  A.ns = tab.ns;
+  for (int a = 0; a < tab.ns; a++) {
+    A.src[a] = tab.src[a];
+    A.hatinv[a] = tab.hatinv[a];
+    A.hatinv_sh[a] = tab.hatinv_sh[a];
+    A.qrecip[a] = 1.0 / tab.qd[a];
+    for (int w = 0; w < 4; w++) A.Hw[a][w] = tab.Hw[a][w];
+  }
+  for (int w = 0; w < 4; w++) A.Dw[w] = tab.Dw[w];
+  A.hat_t = tab.hat_t;
+  A.hat_t_sh = tab.hat_t_sh;
+  A.D_mod_t = tab.D_mod_t;
+  A.hat_f = tab.hat_f;
+  {
+    ProfScope ps("fbc_prep", s, 8.0 * T.N * npoly * (2.0 * tab.ns + 1));
+    hipLaunchKernelGGL(k_fbc_prep, dim3(cdiv(T.N, TPB), npoly), dim3(TPB), 0, s, V, xp_coef, A, T.logN, T.mc);
+  }
+  LimbMap map;
+  map.n = nq;
+  for (int k = 0; k < nq; k++) map.idx[k] = (short)k;
+  switch (T.logN) {
+    case 16: moddown_fused<16, 4, 4, 4, 4>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
+    case 15: moddown_fused<15, 4, 3, 4, 4>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
+    case 14: moddown_fused<14, 4, 3, 4, 3>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
+    case 13: moddown_fused<13, 3, 3, 4, 3>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
+    default: moddown_fused<12, 3, 3, 3, 3>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
+  }
+  return true;
 }
 
 // out[p][t] = (x[p][t] - y[p][t]) * P^{-1} mod q_t   (p < npoly, t < nq)

@@ -720,9 +720,15 @@ HeCt HeCtxImpl::moddown(const HeCt& x, int out_level) {
   for (int k = 0; k < alpha; k++) pm.idx[k] = (short)(L + 1 + k);
   launch_ntt(T, pc.p, np * alpha, pm, true, stream);
   DevBuf y(&pool, (size_t)np * nq * N);
-  launch_fbc_to_q(T, y.p, pc.p, nq, np, down, stream);
   HeCt c = ct_new(out_level, false, x.scale, x.B);
-  launch_ntt_fwd_sub(T, y.p, nq, np, qmap(nq), x.d.p, nqp, pinv.p, c.d.p, stream);
+  if (fused_modup) {
+    DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
+    if (!launch_moddown_fused(T, pc.p, nq, np, down, x.d.p, nqp, pinv.p, c.d.p, y.p, V.p, stream))
+      fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
+  } else {
+    launch_fbc_to_q(T, y.p, pc.p, nq, np, down, stream);
+    launch_ntt_fwd_sub(T, y.p, nq, np, qmap(nq), x.d.p, nqp, pinv.p, c.d.p, stream);
+  }
   n_moddown += x.B;
   return c;
 }
