@@ -118,6 +118,12 @@ void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod
 // rescale pieces
 void launch_rescale_lift(const DeviceTables& T, u64* t, const u64* top_coef, int l, int nout, int npoly,
                          hipStream_t s);
+// Rescale's lift fused into the forward NTT of the kept limbs and its tail
+// (x - t) q_l^-1 into the block pass: t scratch [npoly][nout][N], top_coef
+// the top limbs in the coefficient domain; false when the ring size has no
+// register-blocked NTT
+bool launch_rescale_fused(const DeviceTables& T, u64* t, const u64* top_coef, int l, int nout, int npoly,
+                          const u64* x, int x_stride, const u64* cpairs, u64* out, hipStream_t s);
 void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u64* t, int l, int npoly,
                           int x_stride_limbs, const u64* qlinv /*device [l][2]*/, hipStream_t s);
 

@@ -1911,6 +1911,71 @@ void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u
   hipLaunchKernelGGL(k_rescale_final, grid, dim3(TPB), 0, s, out, x, t, l, x_stride_limbs, qlinv, T.logN, T.mc);
 }
 
+// Rescale with the lift fused into the forward column pass: the value of
+// limb k at a coefficient is the centred top-limb residue reduced mod q_k,
+// computed while filling the tile; the block pass ends with (x - t) q_l^-1.
+struct LiftLoad {
+  const u64* top;
+  u64 ql;
+  ModConst mk;
+  __device__ __forceinline__ u64 operator()(size_t idx) const {
+    const u64 x = top[idx];
+    if (x > (ql >> 1)) {
+      const u64 r = reduce64(ql - x, mk);
+      return r ? mk.q - r : 0;
+    }
+    return reduce64(x, mk);
+  }
+};
+template <int LOGN, int GA, int GB>
+__global__ void __launch_bounds__(TPB) k_ntt_cols2_lift(u64* t, const u64* __restrict__ top, int l, int nout,
+                                                        const u64* __restrict__ tw, const u64* __restrict__ twsh,
+                                                        const double* __restrict__ twf,
+                                                        const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, C = TILE / R;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int p = limb / nout, k = limb - p * nout;
+  const u64 N = 1ull << LOGN;
+  u64* a = t + (size_t)limb * N;
+  const int c0 = blockIdx.x * C;
+  const ModConst mk = mc[k];
+  LiftLoad ld{top + (size_t)p * N, mc[l].q, mk};
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)k * N, mk.qf, mk.qinvf, (double)mk.ninv};
+    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, ld);
+  } else {
+    ShoupArith ar{tw + (size_t)k * N, twsh + (size_t)k * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, ld);
+  }
+}
+template <int LOGN, int GA, int GB, int GC, int GD>
+static void rescale_fused(const DeviceTables& T, u64* t, const u64* top, int l, int nout, int npoly, const u64* x,
+                          int x_stride, const u64* cpairs, u64* out, hipStream_t s) {
+  constexpr int R = 1 << (GA + GB), C = TILE / R;
+  dim3 gc((1 << LOGN) / R / C, nout * npoly);
+  {
+    ProfScope ps("ntt_fwd_cols_lift", s, 8.0 * T.N * npoly * (1.0 + nout));
+    hipLaunchKernelGGL((k_ntt_cols2_lift<LOGN, GA, GB>), gc, dim3(TPB), 0, s, t, top, l, nout, T.psi, T.psi_sh,
+                       T.psi_f, T.mc);
+  }
+  LimbMap map;
+  map.n = nout;
+  for (int k = 0; k < nout; k++) map.idx[k] = (short)k;
+  ntt2_fwd_sub<LOGN, GA, GB, GC, GD>(T, t, nout, npoly, map, x, x_stride, cpairs, out, s, false);
+}
+bool launch_rescale_fused(const DeviceTables& T, u64* t, const u64* top_coef, int l, int nout, int npoly,
+                          const u64* x, int x_stride, const u64* cpairs, u64* out, hipStream_t s) {
+  switch (T.logN) {
+    case 16: rescale_fused<16, 4, 4, 4, 4>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
+    case 15: rescale_fused<15, 4, 3, 4, 4>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
+    case 14: rescale_fused<14, 4, 3, 4, 3>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
+    case 13: rescale_fused<13, 3, 3, 4, 3>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
+    case 12: rescale_fused<12, 3, 3, 3, 3>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
+    default: return false;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11) and the samplers
 // ---------------------------------------------------------------------------

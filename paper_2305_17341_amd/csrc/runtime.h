@@ -51,7 +51,9 @@ struct HeCtxImpl {
   int logN = 0;
   u64 N = 0;
   int L = 0, alpha = 0, beta = 0, nmods = 0;
-  bool fused_modup = false;  // Decompose's conversion fused into the digits' NTT (log N 12..16)
+  // log N 12..16: the conversions of Decompose, ModDown and Rescale are fused
+  // into the forward NTT passes (register-blocked NTT available)
+  bool fused_conv = false;
   u64 mods[HE_MAXMOD];
   double delta = 0, sigma = 0;
   u64 seed = 0;

@@ -274,7 +274,7 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
   L = (int)p->n_q - 1;
   alpha = (int)p->n_p;
   beta = (L + alpha) / alpha;
-  fused_modup = logN >= 12 && logN <= 16;
+  fused_conv = logN >= 12 && logN <= 16;
   if (beta > 16) fail(HE_EINVAL, "at most 16 decomposition digits");
   nmods = L + 1 + alpha;
   std::vector<int> bits;
@@ -624,9 +624,15 @@ HeCt HeCtxImpl::rescale(const HeCt& a, int out_level) {
   gather_limbs(top.p, a, l, 1);
   launch_ntt(T, top.p, np, one(l), true, stream);
   DevBuf t(&pool, (size_t)np * nout * N);
-  launch_rescale_lift(T, t.p, top.p, l, nout, np, stream);
   HeCt c = ct_new(out_level, false, a.scale / (double)mods[l], a.B);
-  launch_ntt_fwd_sub(T, t.p, nout, np, qmap(nout), a.d.p, l + 1, qlinv.p + (size_t)l * nmods * 2, c.d.p, stream);
+  const u64* ql_inv = qlinv.p + (size_t)l * nmods * 2;
+  if (fused_conv) {
+    if (!launch_rescale_fused(T, t.p, top.p, l, nout, np, a.d.p, l + 1, ql_inv, c.d.p, stream))
+      fail(HE_EINVAL, "fused Rescale unavailable for this ring size");
+    return c;
+  }
+  launch_rescale_lift(T, t.p, top.p, l, nout, np, stream);
+  launch_ntt_fwd_sub(T, t.p, nout, np, qmap(nout), a.d.p, l + 1, ql_inv, c.d.p, stream);
   return c;
 }
 
@@ -648,7 +654,7 @@ DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
       bool own = pos < nq && pos / alpha == j;
       m.idx[j * nqp + pos] = own ? (short)-1 : (short)qp_mod(level, pos);
     }
-  if (fused_modup) {
+  if (fused_conv) {
     // sources times their hat inverses, then conversion + NTT in one pass pair
     const std::vector<FbcTable>& tabs = up[level];
     std::vector<u64> hinv((size_t)2 * nq);
@@ -721,7 +727,7 @@ HeCt HeCtxImpl::moddown(const HeCt& x, int out_level) {
   launch_ntt(T, pc.p, np * alpha, pm, true, stream);
   DevBuf y(&pool, (size_t)np * nq * N);
   HeCt c = ct_new(out_level, false, x.scale, x.B);
-  if (fused_modup) {
+  if (fused_conv) {
     DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
     if (!launch_moddown_fused(T, pc.p, nq, np, down, x.d.p, nqp, pinv.p, c.d.p, y.p, V.p, stream))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
