@@ -107,11 +107,13 @@ void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u6
                     const u64* pmod /*device [nmods][2]*/, int level, int L, int alpha, int beta, u64 g,
                     int batch, hipStream_t s);
 // nrot hoisted rotations of the same digits (Galois elements gs[], keys[]) into
-// outs[r] (each [2][batch][nqp][N]); digits read from HBM once per launch
+// outs[r] (each [2][batch][nqp][N]); digits read from HBM once per launch.
+// With masks (plaintexts [nqp][N] in R_{Q_l P}, one per rotation) the outputs
+// are mask (.) rotation, added onto outs[r] when `accumulate`.
 #define MR_MAX 16
 void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
                         const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
-                        int batch, hipStream_t s);
+                        int batch, hipStream_t s, const u64* const* masks = nullptr, bool accumulate = false);
 // P-lift: out[2][nqp][N] = (P c0, P c1) on Q limbs, 0 on P limbs
 void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha, int npoly,
                   hipStream_t s);

@@ -1655,7 +1655,8 @@ template <int MB, bool F64>
 __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ digits, const u64* __restrict__ key,
                                              const u64* __restrict__ c0, const u64* __restrict__ pmod, int nq,
                                              int nqp, int beta, int nmods, int B, int b0, int m, int pos, u32 i,
-                                             u32 src, u64 N, const ModConst& mk) {
+                                             u32 src, u64 N, const ModConst& mk,
+                                             const u64* __restrict__ mask = nullptr, bool accumulate = false) {
   const size_t dstride = (size_t)beta * nqp * N;
   u64 r0[MB], r1[MB];
   if (F64) {
@@ -1721,14 +1722,27 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
       r1[b] = u128_reduce(s1[b], mk);
     }
   }
+  // optional epilogue: out (+)= mask (.) rotation, the mask a plaintext in
+  // R_{Q_l P} broadcast over members and both halves
+  const u64 mv = mask ? mask[(size_t)pos * N + i] : 0;
 #pragma unroll
   for (int b = 0; b < MB; b++) {
     if (c0 && pos < nq) {
       const u64 v = c0[((size_t)(b0 + b) * nq + pos) * N + src];
       r0[b] = add_mod(r0[b], mul_const_any(v, pmod[2 * m], pmod[2 * m + 1], mk), mk.q);
     }
-    stnt(&out[((size_t)(b0 + b) * nqp + pos) * N + i], r0[b]);
-    stnt(&out[((size_t)(B + b0 + b) * nqp + pos) * N + i], r1[b]);
+    u64* o0 = &out[((size_t)(b0 + b) * nqp + pos) * N + i];
+    u64* o1 = &out[((size_t)(B + b0 + b) * nqp + pos) * N + i];
+    if (mask) {
+      r0[b] = mul_mod_any(r0[b], mv, mk);
+      r1[b] = mul_mod_any(r1[b], mv, mk);
+      if (accumulate) {
+        r0[b] = add_mod(r0[b], *o0, mk.q);
+        r1[b] = add_mod(r1[b], *o1, mk.q);
+      }
+    }
+    stnt(o0, r0[b]);
+    stnt(o1, r1[b]);
   }
 }
 
@@ -1761,7 +1775,9 @@ __global__ void __launch_bounds__(TPB) k_multsum(u64* out, const u64* __restrict
 struct MultiRot {
   u64* out[MR_MAX];
   const u64* key[MR_MAX];
+  const u64* mask[MR_MAX];  // null: plain outputs
   u64 ginv[MR_MAX];
+  int accumulate;           // with masks: add onto the outputs
 };
 template <int MB>
 __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, int nrot, const u64* __restrict__ digits,
@@ -1779,10 +1795,11 @@ __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, int nrot, const
   const ModConst mk = mc[m];
   const u32 i = automorph_src(src, R.ginv[r], logN);
   if (mk.bits <= F64_LAZY_BITS)
-    multsum_body<MB, true>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk);
+    multsum_body<MB, true>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk,
+                           R.mask[r], R.accumulate != 0);
   else
     multsum_body<MB, false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N,
-                            mk);
+                            mk, R.mask[r], R.accumulate != 0);
 }
 
 static u64 inv_mod_2n(u64 g, u64 twoN) {
@@ -1794,7 +1811,7 @@ static u64 inv_mod_2n(u64 g, u64 twoN) {
 
 void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
                         const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
-                        int batch, hipStream_t s) {
+                        int batch, hipStream_t s, const u64* const* masks, bool accumulate) {
   const int nq = level + 1, nqp = nq + alpha;
   const u64 twoN = 2 * T.N;
   const int nblk = cdiv(T.N, TPB);
@@ -1803,17 +1820,21 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
   for (int r0 = 0; r0 < nrot; r0 += rstep) {
     const int nr = std::min(nrot - r0, rstep);
     MultiRot R;
+    R.accumulate = masks && accumulate ? 1 : 0;
     for (int r = 0; r < nr; r++) {
       R.out[r] = outs[r0 + r];
       R.key[r] = keys[r0 + r];
+      R.mask[r] = masks ? masks[r0 + r] : nullptr;
       R.ginv[r] = inv_mod_2n(gs[r0 + r], twoN);
     }
     dim3 grid(cdiv(nblk, 8) * 8 * nr, nqp);
     for (int b0 = 0; b0 < batch; b0 += mstep) {
       const int mb = batch - b0 < mstep ? batch - b0 : mstep;
       // digits and c0 of the members once, each rotation's key once, outputs once
+      // (+ the masks, and the outputs read back when accumulating)
       ProfScope ps("multsum_rot", s,
-                   8.0 * T.N * (nr * 2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + nr * 2.0 * nqp)));
+                   8.0 * T.N * (nr * 2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + nr * 2.0 * nqp) +
+                                (masks ? nr * (double)nqp : 0.0) + (R.accumulate ? mb * nr * 2.0 * nqp : 0.0)));
 #define MR_CASE(K)                                                                                                 \
   case K:                                                                                                          \
     hipLaunchKernelGGL(k_multsum_rot<K>, grid, dim3(TPB), 0, s, R, nr, digits, c0, pmod, nq, nqp, L, beta, T.nmods, \

@@ -111,6 +111,8 @@ struct HeCtxImpl {
   DevBuf decompose(const u64* d, int level, int B = 1);
   HeCt hoisted(const HeCt& x, const u64* digits, u64 g);
   std::vector<HeCt> hoisted_multi(const HeCt& x, const u64* digits, const std::vector<u64>& gs);
+  void hoisted_masked(const HeCt& x, const u64* digits, const std::vector<u64>& gs, const std::vector<u64*>& outs,
+                      const std::vector<const u64*>& masks, bool accumulate);
   HeCt moddown(const HeCt& x, int out_level = -1);
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);

@@ -711,6 +711,21 @@ std::vector<HeCt> HeCtxImpl::hoisted_multi(const HeCt& x, const u64* digits, con
   return out;
 }
 
+// hoisted rotations of one decomposition, each multiplied by its mask (a
+// plaintext in R_{Q_l P}) and written to (or, accumulate, added onto) outs[r]
+void HeCtxImpl::hoisted_masked(const HeCt& x, const u64* digits, const std::vector<u64>& gs,
+                               const std::vector<u64*>& outs, const std::vector<const u64*>& masks, bool accumulate) {
+  if (gs.empty()) return;
+  std::vector<const u64*> ks;
+  for (u64 g : gs) {
+    if (g == 1) fail(HE_EINVAL, "masked hoisted rotation by the identity");
+    ks.push_back(key(g).p);
+  }
+  launch_multsum_rot(T, outs.data(), ks.data(), gs.data(), (int)gs.size(), digits, x.poly(0), pmod.p, x.level, L,
+                     alpha, beta_at(x.level), x.B, stream, masks.data(), accumulate);
+  n_multsum += (long)x.B * (long)gs.size();
+}
+
 // ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact
 // centred residue; out_level < l keeps (and computes) only the limbs up to it
 HeCt HeCtxImpl::moddown(const HeCt& x, int out_level) {
@@ -1180,32 +1195,46 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       Bb = rotate(Bb, n1z);
       Bpb = rotate(Bpb, n1z);
     }
-    // all n1z hoisted rotations of each base in one launch per base
+    // all n1z hoisted rotations of each base in one launch per base; the
+    // masks are applied in the launch's epilogue, the second base's masked
+    // rotations added onto the first's, so that the hoisted rotations
+    // themselves never reach memory.  r = 0 (Galois element 1) is the P-lift.
     const int nr = std::min(n1z, n - b * n1z);
-    std::vector<u64> gs(nr);
-    for (int r = 0; r < nr; r++) gs[r] = galois(r);
-    std::vector<HeCt> h1, h2;
+    std::vector<HeCt> acc(nr);
+    for (int r = 0; r < nr; r++) acc[r] = ct_new(lvl, true, Bb.scale * ql, Bb.B);
+    std::vector<u64> gs;
+    std::vector<u64*> outs;
+    std::vector<const u64*> m1, m2;
+    for (int r = 1; r < nr; r++) {
+      const int k = b * n1z + r;
+      gs.push_back(galois(r));
+      outs.push_back(acc[r].d.p);
+      m1.push_back(mask_of(k, 0));
+      m2.push_back(mask_of(k, 1));
+    }
+    HeCt lift1, lift2;
     {
       DevBuf d1 = decompose(Bb.poly(1), lvl, Bb.B);
-      h1 = hoisted_multi(Bb, d1.p, gs);
+      hoisted_masked(Bb, d1.p, gs, outs, m1, false);
+      lift1 = hoisted(Bb, d1.p, 1);
     }
     {
       DevBuf d2 = decompose(Bpb.poly(1), lvl, Bpb.B);
-      // k = 0 has no second term
-      std::vector<u64> gs2(gs.begin() + (b == 0 ? 1 : 0), gs.end());
-      std::vector<HeCt> t = hoisted_multi(Bpb, d2.p, gs2);
-      h2.resize(nr);
-      for (size_t u = 0; u < t.size(); u++) h2[u + (b == 0 ? 1 : 0)] = std::move(t[u]);
+      hoisted_masked(Bpb, d2.p, gs, outs, m2, true);
+      if (b > 0) lift2 = hoisted(Bpb, d2.p, 1);  // k = 0 has no second term
     }
     for (int r = 0; r < nr; r++) {
       int k = b * n1z + r;
-      HeCt acc = ct_new(lvl, true, Bb.scale * ql, Bb.B);
-      const u64* ta[2] = {h1[r].d.p, k > 0 ? h2[r].d.p : nullptr};
-      const u64* tp[2] = {mask_of(k, 0), mask_of(k, 1)};
-      launch_mul_sum(T, acc.d.p, ta, tp, k > 0 ? 2 : 1, 2 * Bb.B * nqp, nqp, qpm, false, stream);
-      h1[r] = HeCt();
-      if (k > 0) h2[r] = HeCt();
-      HeCt md = moddown(acc);
+      HeCt& acc_k = acc[r];
+      if (r == 0) {
+        const u64* ta[2] = {lift1.d.p, k > 0 ? lift2.d.p : nullptr};
+        const u64* tp[2] = {mask_of(k, 0), mask_of(k, 1)};
+        launch_mul_sum(T, acc_k.d.p, ta, tp, k > 0 ? 2 : 1, 2 * Bb.B * nqp, nqp, qpm, false, stream);
+        lift1 = HeCt();
+        lift2 = HeCt();
+      }
+      HeCt sum = std::move(acc_k);
+      HeCt md = moddown(sum);
       Ak[k] = rescale(md, out_level >= 0 ? std::min(out_level, lvl - 1) : -1);
       Ak[k].scale = Bb.scale;
     }
