@@ -446,6 +446,13 @@ struct LoadPlain {
   const u64* a;
   __device__ __forceinline__ u64 operator()(size_t idx) const { return a[idx]; }
 };
+// A loader gives a residue in [0, q) (operator()); loaders with F64 = true
+// also give a centred double (dval, |value| <= q / 2 + 1), which the lazy
+// FP64 arithmetic takes as it is.
+template <class A, class LD>
+__device__ __forceinline__ typename A::V fetch(const A& ar, const LD& ld, size_t idx) {
+  return ar.load(ld(idx));
+}
 
 // Column pass body: rows R = 2^(GA+GB), C = TILE / R columns per work-group.
 template <int LOGN, int GA, int GB, bool INV, class A, class LD>
@@ -461,7 +468,7 @@ __device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh
     for (int k = 0; k < ITA; k++) {
       const int it = tid + TPB * k, c = it % C, rl = it / C;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = ar.load(ld((size_t)(rl + (mm << GB)) * T1 + c0 + c));
+      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = fetch(ar, ld, (size_t)(rl + (mm << GB)) * T1 + c0 + c);
       fwd_group<GA>(v, 0, 0u, ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GA); mm++) sh[lds_rc(rl + (mm << GB), c, C)] = v[mm];
@@ -716,7 +723,17 @@ struct ModupLoad {
       if (a < ns) acc = add_mod(acc, shoup_mul(x[a], h[a], hs[a], q), q);
     return acc;
   }
+  __device__ __forceinline__ double dval(size_t idx) const {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+      if (a < ns) acc += f64_mulmod_signed(u2d(y0[(size_t)a * N + idx]), hf[a], qf, qinvf);
+    return f64_centre(acc, qf, qinvf);
+  }
 };
+__device__ __forceinline__ double fetch(const F64LazyArith&, const ModupLoad<true>& ld, size_t idx) {
+  return ld.dval(idx);
+}
 template <int LOGN, int GA, int GB>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2_modup(u64* digits, ModupSrc S, const u64* __restrict__ tw,
                                                          const u64* __restrict__ twsh,
@@ -1498,7 +1515,24 @@ struct FbcLoad {
       if (a < ns) acc = add_mod(acc, shoup_mul(x[a], h[a], hs[a], q), q);
     return sub_mod(acc, shoup_mul(r, D, Ds, q), q);
   }
+  __device__ __forceinline__ double dval(size_t idx) const {
+    u64 x[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) x[a] = a < ns ? v0[(size_t)a * N + idx] : 0;
+    const u64 r = v0[(size_t)ns * N + idx];
+    double acc = -f64_mulmod_signed(u2d(r), e2, qf, qinvf);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+      if (a < ns) {
+        acc += f64_mulmod_signed(u2d(x[a] & 0xffffffffull), e0[a], qf, qinvf);
+        acc += f64_mulmod_signed(u2d(x[a] >> 32), e1[a], qf, qinvf);
+      }
+    return f64_centre(acc, qf, qinvf);
+  }
 };
+__device__ __forceinline__ double fetch(const F64LazyArith&, const FbcLoad<true>& ld, size_t idx) {
+  return ld.dval(idx);
+}
 template <int LOGN, int GA, int GB>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2_fbc(u64* y, const u64* __restrict__ V, int nq, FbcArgs A,
                                                        const u64* __restrict__ tw, const u64* __restrict__ twsh,
@@ -1948,6 +1982,19 @@ struct LiftLoad {
     return reduce64(x, mk);
   }
 };
+// top limb and target both below 2^46: centred top residue reduced in FP64
+struct LiftLoadF64 {
+  const u64* top;
+  double ql, q, qinv;
+  __device__ __forceinline__ u64 operator()(size_t idx) const { return d2u(f64_canon(dval_(idx), q, qinv)); }
+  __device__ __forceinline__ double dval_(size_t idx) const {
+    const double x = u2d(top[idx]);
+    return f64_centre(x > 0.5 * ql ? x - ql : x, q, qinv);
+  }
+};
+__device__ __forceinline__ double fetch(const F64LazyArith&, const LiftLoadF64& ld, size_t idx) {
+  return ld.dval_(idx);
+}
 template <int LOGN, int GA, int GB>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2_lift(u64* t, const u64* __restrict__ top, int l, int nout,
                                                         const u64* __restrict__ tw, const u64* __restrict__ twsh,
@@ -1964,7 +2011,11 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2_lift(u64* t, const u64* __res
   LiftLoad ld{top + (size_t)p * N, mc[l].q, mk};
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)k * N, mk.qf, mk.qinvf, (double)mk.ninv};
-    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, ld);
+    if (mc[l].bits <= F64_LAZY_BITS)
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar,
+                                          LiftLoadF64{top + (size_t)p * N, mc[l].qf, mk.qf, mk.qinvf});
+    else
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, ld);
   } else {
     ShoupArith ar{tw + (size_t)k * N, twsh + (size_t)k * N, mk.q, mk.ninv, mk.ninv_sh};
     ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, ld);
