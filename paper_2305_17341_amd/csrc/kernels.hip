@@ -443,15 +443,26 @@ __device__ __forceinline__ int lds_be(int b, int e, int T1) { return b * (T1 + (
 // Loads of the forward column pass: the limb itself, or a value computed
 // from other limbs at the same coefficient (ModupLoad).
 struct LoadPlain {
+  typedef u64 Raw;
   const u64* a;
-  __device__ __forceinline__ u64 operator()(size_t idx) const { return a[idx]; }
+  __device__ __forceinline__ void raw(size_t idx, Raw& r) const { r = a[idx]; }
+  __device__ __forceinline__ u64 fin_u(const Raw& r) const { return r; }
 };
-// A loader gives a residue in [0, q) (operator()); loaders with F64 = true
-// also give a centred double (dval, |value| <= q / 2 + 1), which the lazy
-// FP64 arithmetic takes as it is.
+// Loaders work in two phases so that the loads of a batch of values are all
+// in flight before any is used: raw() issues the loads, fin_u() gives the
+// residue in [0, q); loaders for the lazy FP64 arithmetic also give a centred
+// double (fin_d, |value| <= q / 2 + 1), which it takes as it is.
 template <class A, class LD>
-__device__ __forceinline__ typename A::V fetch(const A& ar, const LD& ld, size_t idx) {
-  return ar.load(ld(idx));
+__device__ __forceinline__ typename A::V fin(const A& ar, const LD& ld, const typename LD::Raw& r) {
+  return ar.load(ld.fin_u(r));
+}
+template <int NB, class A, class LD>
+__device__ __forceinline__ void fetch_batch(const A& ar, const LD& ld, const size_t (&idx)[NB], typename A::V* out) {
+  typename LD::Raw raw[NB];
+#pragma unroll
+  for (int e = 0; e < NB; e++) ld.raw(idx[e], raw[e]);
+#pragma unroll
+  for (int e = 0; e < NB; e++) out[e] = fin(ar, ld, raw[e]);
 }
 
 // Column pass body: rows R = 2^(GA+GB), C = TILE / R columns per work-group.
@@ -467,8 +478,14 @@ __device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh
 #pragma unroll
     for (int k = 0; k < ITA; k++) {
       const int it = tid + TPB * k, c = it % C, rl = it / C;
+      constexpr int NB = (1 << GA) < 8 ? (1 << GA) : 8;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GA); mm++) v[mm] = fetch(ar, ld, (size_t)(rl + (mm << GB)) * T1 + c0 + c);
+      for (int h = 0; h < (1 << GA) / NB; h++) {
+        size_t idx[NB];
+#pragma unroll
+        for (int e = 0; e < NB; e++) idx[e] = (size_t)(rl + ((h * NB + e) << GB)) * T1 + c0 + c;
+        fetch_batch<NB>(ar, ld, idx, v + h * NB);
+      }
       fwd_group<GA>(v, 0, 0u, ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GA); mm++) sh[lds_rc(rl + (mm << GB), c, C)] = v[mm];
@@ -697,42 +714,40 @@ struct ModupSrc {
   const u64* hat_t_sh[16];
 };
 // F64: every source below 4 q (signed exact products, one reduction);
-// otherwise Shoup products.  The source count loop is fixed at 4 with
-// uniform guards, so the loads of a tile's values can all be issued first.
+// otherwise Shoup products.  The source loop is fixed at 4 without branches
+// (sources past ns repeat the last one, against zero constants), so the loads
+// of a tile's values can all be in flight together.
 template <bool F64>
 struct ModupLoad {
+  struct Raw {
+    u64 x[4];
+  };
   const u64* y0;
   u64 N;
   int ns;
   u64 q, h[4], hs[4];
   double qf, qinvf, hf[4];
-  __device__ __forceinline__ u64 operator()(size_t idx) const {
-    u64 x[4];
+  __device__ __forceinline__ void raw(size_t idx, Raw& r) const {
 #pragma unroll
-    for (int a = 0; a < 4; a++) x[a] = a < ns ? y0[(size_t)a * N + idx] : 0;
-    if (F64) {
-      double acc = 0.0;
-#pragma unroll
-      for (int a = 0; a < 4; a++)
-        if (a < ns) acc += f64_mulmod_signed(u2d(x[a]), hf[a], qf, qinvf);
-      return d2u(f64_canon(acc, qf, qinvf));
-    }
-    u64 acc = 0;
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-      if (a < ns) acc = add_mod(acc, shoup_mul(x[a], h[a], hs[a], q), q);
-    return acc;
+    for (int a = 0; a < 4; a++) r.x[a] = y0[(size_t)(a < ns ? a : ns - 1) * N + idx];
   }
-  __device__ __forceinline__ double dval(size_t idx) const {
+  __device__ __forceinline__ double sum_f64(const Raw& r) const {
     double acc = 0.0;
 #pragma unroll
-    for (int a = 0; a < 4; a++)
-      if (a < ns) acc += f64_mulmod_signed(u2d(y0[(size_t)a * N + idx]), hf[a], qf, qinvf);
-    return f64_centre(acc, qf, qinvf);
+    for (int a = 0; a < 4; a++) acc += f64_mulmod_signed(u2d(r.x[a]), hf[a], qf, qinvf);
+    return acc;
   }
+  __device__ __forceinline__ u64 fin_u(const Raw& r) const {
+    if (F64) return d2u(f64_canon(sum_f64(r), qf, qinvf));
+    u64 acc = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++) acc = add_mod(acc, shoup_mul(r.x[a], h[a], hs[a], q), q);
+    return acc;
+  }
+  __device__ __forceinline__ double fin_d(const Raw& r) const { return f64_centre(sum_f64(r), qf, qinvf); }
 };
-__device__ __forceinline__ double fetch(const F64LazyArith&, const ModupLoad<true>& ld, size_t idx) {
-  return ld.dval(idx);
+__device__ __forceinline__ double fin(const F64LazyArith&, const ModupLoad<true>& ld, const ModupLoad<true>::Raw& r) {
+  return ld.fin_d(r);
 }
 template <int LOGN, int GA, int GB>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2_modup(u64* digits, ModupSrc S, const u64* __restrict__ tw,
@@ -1485,53 +1500,44 @@ __global__ void k_fbc_prep(u64* V, const u64* xp, FbcArgs A, int logN, const Mod
   o[(size_t)A.ns * N + i] = r;
 }
 // F64 (target of 33 to 46 bits): v = v_hi 2^32 + v_lo, both halves below
-// q_t, signed exact products, one reduction; otherwise Shoup products.
+// q_t, signed exact products, one reduction; otherwise Shoup products.  No
+// branches on the source count (sources past ns repeat the last one against
+// zero constants).
 template <bool F64>
 struct FbcLoad {
+  struct Raw {
+    u64 x[4], r;
+  };
   const u64* v0;
   u64 N;
   int ns;
   u64 q, h[4], hs[4], D, Ds;
   double qf, qinvf, e0[4], e1[4], e2;
-  __device__ __forceinline__ u64 operator()(size_t idx) const {
-    u64 x[4];
+  __device__ __forceinline__ void raw(size_t idx, Raw& w) const {
 #pragma unroll
-    for (int a = 0; a < 4; a++) x[a] = a < ns ? v0[(size_t)a * N + idx] : 0;
-    const u64 r = v0[(size_t)ns * N + idx];
-    if (F64) {
-      double acc = 0.0;
+    for (int a = 0; a < 4; a++) w.x[a] = v0[(size_t)(a < ns ? a : ns - 1) * N + idx];
+    w.r = v0[(size_t)ns * N + idx];
+  }
+  __device__ __forceinline__ double sum_f64(const Raw& w) const {
+    double acc = -f64_mulmod_signed(u2d(w.r), e2, qf, qinvf);
 #pragma unroll
-      for (int a = 0; a < 4; a++)
-        if (a < ns) {
-          acc += f64_mulmod_signed(u2d(x[a] & 0xffffffffull), e0[a], qf, qinvf);
-          acc += f64_mulmod_signed(u2d(x[a] >> 32), e1[a], qf, qinvf);
-        }
-      acc -= f64_mulmod_signed(u2d(r), e2, qf, qinvf);
-      return d2u(f64_canon(acc, qf, qinvf));
+    for (int a = 0; a < 4; a++) {
+      acc += f64_mulmod_signed(u2d(w.x[a] & 0xffffffffull), e0[a], qf, qinvf);
+      acc += f64_mulmod_signed(u2d(w.x[a] >> 32), e1[a], qf, qinvf);
     }
+    return acc;
+  }
+  __device__ __forceinline__ u64 fin_u(const Raw& w) const {
+    if (F64) return d2u(f64_canon(sum_f64(w), qf, qinvf));
     u64 acc = 0;
 #pragma unroll
-    for (int a = 0; a < 4; a++)
-      if (a < ns) acc = add_mod(acc, shoup_mul(x[a], h[a], hs[a], q), q);
-    return sub_mod(acc, shoup_mul(r, D, Ds, q), q);
+    for (int a = 0; a < 4; a++) acc = add_mod(acc, shoup_mul(w.x[a], h[a], hs[a], q), q);
+    return sub_mod(acc, shoup_mul(w.r, D, Ds, q), q);
   }
-  __device__ __forceinline__ double dval(size_t idx) const {
-    u64 x[4];
-#pragma unroll
-    for (int a = 0; a < 4; a++) x[a] = a < ns ? v0[(size_t)a * N + idx] : 0;
-    const u64 r = v0[(size_t)ns * N + idx];
-    double acc = -f64_mulmod_signed(u2d(r), e2, qf, qinvf);
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-      if (a < ns) {
-        acc += f64_mulmod_signed(u2d(x[a] & 0xffffffffull), e0[a], qf, qinvf);
-        acc += f64_mulmod_signed(u2d(x[a] >> 32), e1[a], qf, qinvf);
-      }
-    return f64_centre(acc, qf, qinvf);
-  }
+  __device__ __forceinline__ double fin_d(const Raw& w) const { return f64_centre(sum_f64(w), qf, qinvf); }
 };
-__device__ __forceinline__ double fetch(const F64LazyArith&, const FbcLoad<true>& ld, size_t idx) {
-  return ld.dval(idx);
+__device__ __forceinline__ double fin(const F64LazyArith&, const FbcLoad<true>& ld, const FbcLoad<true>::Raw& w) {
+  return ld.fin_d(w);
 }
 template <int LOGN, int GA, int GB>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2_fbc(u64* y, const u64* __restrict__ V, int nq, FbcArgs A,
@@ -1970,11 +1976,12 @@ void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u
 // limb k at a coefficient is the centred top-limb residue reduced mod q_k,
 // computed while filling the tile; the block pass ends with (x - t) q_l^-1.
 struct LiftLoad {
+  typedef u64 Raw;
   const u64* top;
   u64 ql;
   ModConst mk;
-  __device__ __forceinline__ u64 operator()(size_t idx) const {
-    const u64 x = top[idx];
+  __device__ __forceinline__ void raw(size_t idx, Raw& r) const { r = top[idx]; }
+  __device__ __forceinline__ u64 fin_u(const Raw& x) const {
     if (x > (ql >> 1)) {
       const u64 r = reduce64(ql - x, mk);
       return r ? mk.q - r : 0;
@@ -1984,17 +1991,17 @@ struct LiftLoad {
 };
 // top limb and target both below 2^46: centred top residue reduced in FP64
 struct LiftLoadF64 {
+  typedef u64 Raw;
   const u64* top;
   double ql, q, qinv;
-  __device__ __forceinline__ u64 operator()(size_t idx) const { return d2u(f64_canon(dval_(idx), q, qinv)); }
-  __device__ __forceinline__ double dval_(size_t idx) const {
-    const double x = u2d(top[idx]);
+  __device__ __forceinline__ void raw(size_t idx, Raw& r) const { r = top[idx]; }
+  __device__ __forceinline__ double fin_d(const Raw& r) const {
+    const double x = u2d(r);
     return f64_centre(x > 0.5 * ql ? x - ql : x, q, qinv);
   }
+  __device__ __forceinline__ u64 fin_u(const Raw& r) const { return d2u(f64_canon(fin_d(r), q, qinv)); }
 };
-__device__ __forceinline__ double fetch(const F64LazyArith&, const LiftLoadF64& ld, size_t idx) {
-  return ld.dval_(idx);
-}
+__device__ __forceinline__ double fin(const F64LazyArith&, const LiftLoadF64& ld, const u64& r) { return ld.fin_d(r); }
 template <int LOGN, int GA, int GB>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2_lift(u64* t, const u64* __restrict__ top, int l, int nout,
                                                         const u64* __restrict__ tw, const u64* __restrict__ twsh,
