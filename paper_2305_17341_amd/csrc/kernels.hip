@@ -1819,8 +1819,14 @@ struct MultiRot {
   u64 ginv[MR_MAX];
   int accumulate;           // with masks: add onto the outputs
 };
-template <int MB>
-__global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, int nrot, const u64* __restrict__ digits,
+// Positions (limbs of R_{Q_l P}) of one arithmetic: the FP64 and the integer
+// limbs go to separate launches, so that each kernel holds only its own
+// registers (the FP64 one runs more waves per SIMD).
+struct PosList {
+  short pos[HE_MAXMOD];
+};
+template <int MB, bool F64>
+__global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, PosList P, int nrot, const u64* __restrict__ digits,
                                                      const u64* __restrict__ c0, const u64* __restrict__ pmod,
                                                      int nq, int nqp, int L, int beta, int nmods, int B, int b0,
                                                      int logN, const ModConst* __restrict__ mc) {
@@ -1830,16 +1836,12 @@ __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, int nrot, const
   const u32 S = (rest / (u32)nrot) * 8 + (x & 7);
   if ((u64)S * TPB >= N) return;
   const u32 src = S * TPB + threadIdx.x;
-  const int pos = blockIdx.y;
+  const int pos = P.pos[blockIdx.y];
   const int m = pos < nq ? pos : L + 1 + (pos - nq);
   const ModConst mk = mc[m];
   const u32 i = automorph_src(src, R.ginv[r], logN);
-  if (mk.bits <= F64_LAZY_BITS)
-    multsum_body<MB, true>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk,
-                           R.mask[r], R.accumulate != 0);
-  else
-    multsum_body<MB, false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N,
-                            mk, R.mask[r], R.accumulate != 0);
+  multsum_body<MB, F64>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk,
+                        R.mask[r], R.accumulate != 0);
 }
 
 static u64 inv_mod_2n(u64 g, u64 twoN) {
@@ -1867,24 +1869,46 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
       R.mask[r] = masks ? masks[r0 + r] : nullptr;
       R.ginv[r] = inv_mod_2n(gs[r0 + r], twoN);
     }
-    dim3 grid(cdiv(nblk, 8) * 8 * nr, nqp);
+    PosList pf, pi;
+    int nf = 0, ni = 0;
+    for (int pos = 0; pos < nqp; pos++) {
+      const int m = pos < nq ? pos : L + 1 + (pos - nq);
+      if (T.bits[m] <= F64_LAZY_BITS) pf.pos[nf++] = (short)pos;
+      else pi.pos[ni++] = (short)pos;
+    }
     for (int b0 = 0; b0 < batch; b0 += mstep) {
       const int mb = batch - b0 < mstep ? batch - b0 : mstep;
-      // digits and c0 of the members once, each rotation's key once, outputs once
-      // (+ the masks, and the outputs read back when accumulating)
-      ProfScope ps("multsum_rot", s,
-                   8.0 * T.N * (nr * 2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + nr * 2.0 * nqp) +
-                                (masks ? nr * (double)nqp : 0.0) + (R.accumulate ? mb * nr * 2.0 * nqp : 0.0)));
-#define MR_CASE(K)                                                                                                 \
+      // per position: each rotation's key once, the members' digits (and c0 on
+      // the Q limbs) once, outputs once, the masks, the outputs read back when
+      // accumulating
+      auto bytes = [&](const PosList& P, int np) {
+        double w = 0;
+        for (int k = 0; k < np; k++)
+          w += nr * 2.0 * beta + mb * (beta + (c0 && P.pos[k] < nq ? 1.0 : 0.0) + nr * 2.0) + (masks ? nr : 0.0) +
+               (R.accumulate ? mb * nr * 2.0 : 0.0);
+        return 8.0 * T.N * w;
+      };
+#define MR_CASE(K, F, P, NP)                                                                                       \
   case K:                                                                                                          \
-    hipLaunchKernelGGL(k_multsum_rot<K>, grid, dim3(TPB), 0, s, R, nr, digits, c0, pmod, nq, nqp, L, beta, T.nmods, \
-                       batch, b0, T.logN, T.mc);                                                                   \
+    hipLaunchKernelGGL((k_multsum_rot<K, F>), dim3(cdiv(nblk, 8) * 8 * nr, NP), dim3(TPB), 0, s, R, P, nr, digits, \
+                       c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);                              \
     break;
-      switch (mb) {
-        MR_CASE(1) MR_CASE(2) MR_CASE(3) MR_CASE(4) MR_CASE(5) MR_CASE(6) MR_CASE(7) MR_CASE(8)
+      if (nf) {
+        ProfScope ps("multsum_rot", s, bytes(pf, nf));
+        switch (mb) {
+          MR_CASE(1, true, pf, nf) MR_CASE(2, true, pf, nf) MR_CASE(3, true, pf, nf) MR_CASE(4, true, pf, nf)
+          MR_CASE(5, true, pf, nf) MR_CASE(6, true, pf, nf) MR_CASE(7, true, pf, nf) MR_CASE(8, true, pf, nf)
+        }
       }
-#undef MR_CASE
+      if (ni) {
+        ProfScope ps("multsum_rot_int", s, bytes(pi, ni));
+        switch (mb) {
+          MR_CASE(1, false, pi, ni) MR_CASE(2, false, pi, ni) MR_CASE(3, false, pi, ni) MR_CASE(4, false, pi, ni)
+          MR_CASE(5, false, pi, ni) MR_CASE(6, false, pi, ni) MR_CASE(7, false, pi, ni) MR_CASE(8, false, pi, ni)
+        }
+      }
     }
+#undef MR_CASE
   }
 }
 
