@@ -417,6 +417,43 @@ __device__ __forceinline__ void fwd_group(typename A::V (&v)[16], int s0, u32 hi
   }
 }
 
+// The forward block pass's last G stages (s0 = log N - G, hi < 2^s0): any
+// arithmetic takes the twiddles from the table ...
+template <int G, class A>
+__device__ __forceinline__ void fwd_group_last(typename A::V (&v)[16], int s0, u32 hi, const A& ar) {
+  fwd_group<G>(v, s0, hi, ar);
+}
+// ... but the lazy FP64 one computes them: with W[k] = psi^brv(k),
+//   W[2^(s0+j) + (hi << j) + low] = W[2^(s0+j) + low] * Y^(2^(G-1-j)),
+//   Y = W[hi << (G-1)]
+// (bit reversal splits over the disjoint bit fields, and brv(hi) has its low
+// G bits clear).  One table load and G - 1 squarings per thread, then one
+// product per twiddle, against 2^G - 1 distinct table loads per thread: the
+// table W[2^(s0+j) + low] has 2^G - 1 entries shared by the whole grid.
+template <int G>
+__device__ __forceinline__ void fwd_group_last(double (&v)[16], int s0, u32 hi, const F64LazyArith& ar) {
+  double P[G];
+  P[G - 1] = ar.w[hi << (G - 1)];
+#pragma unroll
+  for (int j = G - 2; j >= 0; j--) P[j] = f64_mulmod_signed(P[j + 1], P[j + 1], ar.q, ar.qinv);
+#pragma unroll
+  for (int j = 0; j < G; j++) {
+    const int half = 1 << (G - 1 - j);
+    double w[1 << (G - 1)];
+#pragma unroll
+    for (int low = 0; low < (1 << j); low++)
+      w[low] = f64_mulmod_signed(ar.w[(1u << (s0 + j)) + low], P[j], ar.q, ar.qinv);
+#pragma unroll
+    for (int r = 0; r < (1 << G); r++) {
+      if (r & half) continue;
+      const double U = v[r];
+      const double V = f64_mulmod_signed(v[r + half], w[r >> (G - j)], ar.q, ar.qinv);
+      v[r] = U + V;
+      v[r + half] = U - V;
+    }
+  }
+}
+
 template <int G, class A>
 __device__ __forceinline__ void inv_group(typename A::V (&v)[16], int b0, int logN, u32 hi, const A& ar) {
 #pragma unroll
@@ -538,33 +575,49 @@ template <class A>
 struct StorePlain {
   u64* a;
   const A& ar;
-  __device__ __forceinline__ void operator()(int e, typename A::V v) const { a[e] = ar.store(v); }
+  __device__ __forceinline__ void pre() {}
+  __device__ __forceinline__ void operator()(int e, int k, typename A::V v) const { a[e] = ar.store(v); }
 };
+// x is read into registers when the pass starts (pre), so its loads are in
+// flight during the butterflies; element e = threadIdx.x + k TPB
 struct SubScaleShoup {
   u64* out;
   const u64* __restrict__ x;
   u64 c, c_sh, q;
-  __device__ __forceinline__ void operator()(int e, u64 v) const { out[e] = shoup_mul(sub_mod(x[e], v, q), c, c_sh, q); }
+  u64 xv[TILE / TPB];
+  __device__ __forceinline__ void pre() {
+#pragma unroll
+    for (int k = 0; k < TILE / TPB; k++) xv[k] = x[threadIdx.x + k * TPB];
+  }
+  __device__ __forceinline__ void operator()(int e, int k, u64 v) const {
+    out[e] = shoup_mul(sub_mod(xv[k], v, q), c, c_sh, q);
+  }
 };
 struct SubScaleF64 {
   u64* out;
   const u64* __restrict__ x;
   double c, q, qinv;
+  u64 xv[TILE / TPB];
+  __device__ __forceinline__ void pre() {
+#pragma unroll
+    for (int k = 0; k < TILE / TPB; k++) xv[k] = x[threadIdx.x + k * TPB];
+  }
   // v below 9 q in absolute value (eight forward stages): |x - v| < 10 q
-  __device__ __forceinline__ void operator()(int e, double v) const {
-    out[e] = d2u(f64_canon(f64_mulmod_signed(u2d(x[e]) - v, c, q, qinv), q, qinv));
+  __device__ __forceinline__ void operator()(int e, int k, double v) const {
+    out[e] = d2u(f64_canon(f64_mulmod_signed(u2d(xv[k]) - v, c, q, qinv), q, qinv));
   }
 };
 
 // Block pass body: blocks of T1 = 2^(GC+GD) words, K = TILE / T1 blocks per work-group.
 template <int LOGN, int GC, int GD, bool INV, class A, class ST>
-__device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* sh, const A& ar, const ST& st) {
+__device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* sh, const A& ar, ST st) {
   typedef typename A::V V;
   constexpr int S2 = GC + GD, T1 = 1 << S2, S1 = LOGN - S2;
   const int tid = threadIdx.x;
   constexpr int LOWC = 1 << (S2 - GC);  // e bits below group C
   V v[16];
   if (!INV) {
+    st.pre();
     // group C: e bits [GD, S2) -> stages S1..S1+GC-1
     constexpr int ITC = 16 >> GC;
 #pragma unroll
@@ -585,12 +638,16 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
       const int it = tid + TPB * k, eh = it % HIGHD, b = it / HIGHD;
 #pragma unroll
       for (int mm = 0; mm < (1 << GD); mm++) v[mm] = sh[lds_be(b, (eh << GD) + mm, T1)];
-      fwd_group<GD>(v, S1 + GC, (u32)(((blk0 + b) << GC) + eh), ar);
+      fwd_group_last<GD>(v, S1 + GC, (u32)(((blk0 + b) << GC) + eh), ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GD); mm++) sh[lds_be(b, (eh << GD) + mm, T1)] = v[mm];
     }
     __syncthreads();
-    for (int e = tid; e < TILE; e += TPB) st(e, sh[lds_be(e / T1, e % T1, T1)]);
+#pragma unroll
+    for (int k = 0; k < TILE / TPB; k++) {
+      const int e = tid + k * TPB;
+      st(e, k, sh[lds_be(e / T1, e % T1, T1)]);
+    }
   } else {
     // inverse bits [0, GD) of e
     constexpr int ITD = 16 >> GD;
