@@ -278,8 +278,7 @@ he_status he_last_op_ms(const he_ctx* ctx, double* ms);
  * column pass of ModDown, P-to-Q conversion included), "fbc_prep" (its
  * per-coefficient quotient), "ntt_fwd_cols_lift" (the forward column pass of
  * Rescale, lift of the top limb included), "multsum", "multsum_rot"
- * (several rotations of one decomposition, limbs below 2^46),
- * "multsum_rot_int" (the same, other limbs), "modup", "fbc_to_q",
+ * (several rotations of one decomposition), "modup", "fbc_to_q",
  * "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor",
  * "plift".  While enabled, HIP
  * events are recorded on the launching stream around every launch of the

@@ -1876,9 +1876,9 @@ struct MultiRot {
   u64 ginv[MR_MAX];
   int accumulate;           // with masks: add onto the outputs
 };
-// Positions (limbs of R_{Q_l P}) of one arithmetic: the FP64 and the integer
-// limbs go to separate launches, so that each kernel holds only its own
-// registers (the FP64 one runs more waves per SIMD).
+// Limbs of R_{Q_l P} in launch order: the integer limbs (moduli of 47 bits
+// or more, four members at a time to bound their registers) are spread
+// among the FP64 ones so that their VALU-heavy blocks overlap the others.
 struct PosList {
   short pos[HE_MAXMOD];
 };
@@ -1897,8 +1897,19 @@ __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, PosList P, int 
   const int m = pos < nq ? pos : L + 1 + (pos - nq);
   const ModConst mk = mc[m];
   const u32 i = automorph_src(src, R.ginv[r], logN);
-  multsum_body<MB, F64>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk,
-                        R.mask[r], R.accumulate != 0);
+  if (F64 || mk.bits <= F64_LAZY_BITS) {
+    multsum_body<MB, true>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk,
+                           R.mask[r], R.accumulate != 0);
+    return;
+  }
+  // integer limbs: at most four members at a time (128-bit sums hold the
+  // registers of two FP64 ones)
+  constexpr int M1 = MB > 4 ? 4 : MB;
+  multsum_body<M1, false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk,
+                          R.mask[r], R.accumulate != 0);
+  if (MB > 4)
+    multsum_body<(MB > 4 ? MB - 4 : 1), false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B,
+                                               b0 + 4, m, pos, i, src, N, mk, R.mask[r], R.accumulate != 0);
 }
 
 static u64 inv_mod_2n(u64 g, u64 twoN) {
@@ -1926,43 +1937,44 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
       R.mask[r] = masks ? masks[r0 + r] : nullptr;
       R.ginv[r] = inv_mod_2n(gs[r0 + r], twoN);
     }
-    PosList pf, pi;
+    PosList pf, pi, P;
     int nf = 0, ni = 0;
     for (int pos = 0; pos < nqp; pos++) {
       const int m = pos < nq ? pos : L + 1 + (pos - nq);
       if (T.bits[m] <= F64_LAZY_BITS) pf.pos[nf++] = (short)pos;
       else pi.pos[ni++] = (short)pos;
     }
+    {
+      int f = 0, k = 0;
+      for (int t = 0; t < ni; t++) {
+        const int upto = (int)(((long)nf * (t + 1)) / (ni + 1));
+        while (f < upto) P.pos[k++] = pf.pos[f++];
+        P.pos[k++] = pi.pos[t];
+      }
+      while (f < nf) P.pos[k++] = pf.pos[f++];
+    }
     for (int b0 = 0; b0 < batch; b0 += mstep) {
       const int mb = batch - b0 < mstep ? batch - b0 : mstep;
       // per position: each rotation's key once, the members' digits (and c0 on
       // the Q limbs) once, outputs once, the masks, the outputs read back when
       // accumulating
-      auto bytes = [&](const PosList& P, int np) {
-        double w = 0;
-        for (int k = 0; k < np; k++)
-          w += nr * 2.0 * beta + mb * (beta + (c0 && P.pos[k] < nq ? 1.0 : 0.0) + nr * 2.0) + (masks ? nr : 0.0) +
-               (R.accumulate ? mb * nr * 2.0 : 0.0);
-        return 8.0 * T.N * w;
-      };
-#define MR_CASE(K, F, P, NP)                                                                                       \
+      double w = 0;
+      for (int pos = 0; pos < nqp; pos++)
+        w += nr * 2.0 * beta + mb * (beta + (c0 && pos < nq ? 1.0 : 0.0) + nr * 2.0) + (masks ? nr : 0.0) +
+             (R.accumulate ? mb * nr * 2.0 : 0.0);
+      ProfScope ps("multsum_rot", s, 8.0 * T.N * w);
+      // FP64-only launch when every limb is FP64 (the integer branch compiled out)
+#define MR_CASE(K)                                                                                                 \
   case K:                                                                                                          \
-    hipLaunchKernelGGL((k_multsum_rot<K, F>), dim3(cdiv(nblk, 8) * 8 * nr, NP), dim3(TPB), 0, s, R, P, nr, digits, \
-                       c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);                              \
+    if (ni)                                                                                                        \
+      hipLaunchKernelGGL((k_multsum_rot<K, false>), dim3(cdiv(nblk, 8) * 8 * nr, nqp), dim3(TPB), 0, s, R, P, nr,  \
+                         digits, c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);                    \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_multsum_rot<K, true>), dim3(cdiv(nblk, 8) * 8 * nr, nqp), dim3(TPB), 0, s, R, P, nr,   \
+                         digits, c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);                    \
     break;
-      if (nf) {
-        ProfScope ps("multsum_rot", s, bytes(pf, nf));
-        switch (mb) {
-          MR_CASE(1, true, pf, nf) MR_CASE(2, true, pf, nf) MR_CASE(3, true, pf, nf) MR_CASE(4, true, pf, nf)
-          MR_CASE(5, true, pf, nf) MR_CASE(6, true, pf, nf) MR_CASE(7, true, pf, nf) MR_CASE(8, true, pf, nf)
-        }
-      }
-      if (ni) {
-        ProfScope ps("multsum_rot_int", s, bytes(pi, ni));
-        switch (mb) {
-          MR_CASE(1, false, pi, ni) MR_CASE(2, false, pi, ni) MR_CASE(3, false, pi, ni) MR_CASE(4, false, pi, ni)
-          MR_CASE(5, false, pi, ni) MR_CASE(6, false, pi, ni) MR_CASE(7, false, pi, ni) MR_CASE(8, false, pi, ni)
-        }
+      switch (mb) {
+        MR_CASE(1) MR_CASE(2) MR_CASE(3) MR_CASE(4) MR_CASE(5) MR_CASE(6) MR_CASE(7) MR_CASE(8)
       }
     }
 #undef MR_CASE
