@@ -10,7 +10,9 @@ timed on the same inputs:
   batched  the products stacked so every launch serves all of them (same
            residues as plain, checked here);
   headline batched, with lazy relinearisation (the n tensors summed and
-           relinearised once; --paper-relin keeps the paper's order).
+           relinearised once) and the A side's ModDown and Rescale as one
+           rounding by P q_l (--two-roundings keeps two; --paper-relin keeps
+           the paper's order altogether).
 The headline value is the last; the others and the speedups sit beside it.
 The headline steps run without per-kernel instrumentation; the same number
 of steps is then run again with HIP events around every launch, and the
@@ -148,6 +150,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--knobs", default="",
                     help="launch knobs set before the run, e.g. mr_members=4,ms_members=4 (with --no-autotune)")
+    ap.add_argument("--two-roundings", action="store_true",
+                    help="headline keeps the A side's ModDown and Rescale as two roundings")
     ap.add_argument("--paper-relin", action="store_true",
                     help="headline path relinearises every product (default: lazy, once per product)")
     ap.add_argument("--d", type=int, default=128)
@@ -178,10 +182,11 @@ def main():
     cB = [ctx.encrypt_matrix(b, nonce=1001 + i) for i, b in enumerate(Bs)]
     ctx.sync()
 
-    BATCHED, LAZY = 1, 2
+    BATCHED, LAZY, FUSED = 1, 2, 4
     relin = "paper" if args.paper_relin else "lazy"
-    head = {"flags": BATCHED | (0 if args.paper_relin else LAZY)}
-    names = {0: "plain", BATCHED: "batched", BATCHED | LAZY: "batched+lazy-relin"}
+    head = {"flags": BATCHED | (0 if args.paper_relin else LAZY | (0 if args.two_roundings else FUSED))}
+    names = {0: "plain", BATCHED: "batched", BATCHED | LAZY: "batched+lazy-relin",
+             BATCHED | LAZY | FUSED: "batched+lazy-relin+fused-rescale"}
 
     def timed(opts, profile, warmup=True):
         """warm-up then `--steps` timed steps of B products; returns (seconds, per-step ms, outputs of warm-up)"""

@@ -105,6 +105,14 @@ typedef struct {
  * relinearised once, saving n - 1 key switches per product.  Different
  * residues from the default (no more noise); same level and scale. */
 #define HE_MM_LAZY_RELIN 2u
+/* he_matmul, he_matmul_batch, he_covariance: the A side's ModDown and the
+ * Rescale after it (A_k = Rescale(ModDown(...)), section 4.1.1) as one
+ * rounding, round(x / (P q_l)), a variant of the paper's two roundings.
+ * Rounding twice differs from it only where round(x / P) / q_l lies within
+ * about 2^-41 of a half-integer, so the residues almost always agree; the
+ * level and scale are the same.  Needs at most 3 special primes (HE_EINVAL
+ * otherwise). */
+#define HE_MM_FUSED_RESCALE 4u
 
 /* Create a context on the current HIP device.  `dev` may be NULL.  `seed`
  * keys every random draw of the context (Philox4x64-10 streams).

@@ -954,29 +954,33 @@ static u64 big_mod_u64(big a, u64 q) {
   return (u64)r;
 }
 
-/* ModDown (Appendix A, KeySwitch): x in R_{Q_l P} (NTT domain, l+1+alpha
- * limbs) -> round(x / P) in R_{Q_l}:
- *   out_i = (x_i - [x]_P) P^{-1} mod q_i,
- * with [x]_P the exact centred residue of x modulo P, reconstructed by CRT
- * from the P limbs. */
-static void moddown_poly(const oc_ctx *c, const u64 *x, int level, u64 *out) {
+/* Exact rounded division by the product D of some limbs of x (NTT domain):
+ * the source limbs sit at positions spos[] of x with moduli smod[]; for the
+ * moduli q_0..q_{nout-1} (positions 0..nout-1)
+ *   out_i = (x_i - [x]_D) D^{-1} mod q_i,
+ * with [x]_D the exact centred residue of x modulo D, reconstructed by CRT
+ * from the source limbs.  x - [x]_D is divisible by D, so this is
+ * round(x / D) (D is odd: no ties). */
+static void divide_round_poly(const oc_ctx *c, const u64 *x, const int *spos, const int *smod, int ns, int nout,
+                              u64 *out) {
   u64 N = c->N;
-  int nq = level + 1, al = c->alpha;
-  u64 *pc = alloc_u64((size_t)al * N);
+  u64 *pc = alloc_u64((size_t)ns * N);
   int pidx[MAXMOD];
-  for (int k = 0; k < al; k++) pidx[k] = c->L + 1 + k;
-  memcpy(pc, x + (size_t)nq * N, sizeof(u64) * al * N);
-  intt_limbs(c, pc, pidx, al);
-  /* CRT constants: P, P/p_k and (P/p_k)^{-1} mod p_k */
-  big P = big_u64(1), H[MAXMOD];
+  for (int k = 0; k < ns; k++) {
+    pidx[k] = smod[k];
+    memcpy(pc + (size_t)k * N, x + (size_t)spos[k] * N, sizeof(u64) * N);
+  }
+  intt_limbs(c, pc, pidx, ns);
+  /* CRT constants: D, D/d_k and (D/d_k)^{-1} mod d_k */
+  big D = big_u64(1), H[MAXMOD];
   u64 Hinv[MAXMOD];
-  for (int k = 0; k < al; k++) P = big_mul_u64(P, c->mods[c->L + 1 + k]);
-  for (int k = 0; k < al; k++) {
-    u64 pk = c->mods[c->L + 1 + k];
+  for (int k = 0; k < ns; k++) D = big_mul_u64(D, c->mods[smod[k]]);
+  for (int k = 0; k < ns; k++) {
+    u64 dk = c->mods[smod[k]];
     H[k] = big_u64(1);
-    for (int m = 0; m < al; m++)
-      if (m != k) H[k] = big_mul_u64(H[k], c->mods[c->L + 1 + m]);
-    Hinv[k] = invmod(big_mod_u64(H[k], pk), pk);
+    for (int m = 0; m < ns; m++)
+      if (m != k) H[k] = big_mul_u64(H[k], c->mods[smod[m]]);
+    Hinv[k] = invmod(big_mod_u64(H[k], dk), dk);
   }
   /* centred residue, kept as (magnitude, sign) per coefficient */
   big *mag = (big *)malloc(sizeof(big) * N);
@@ -984,17 +988,17 @@ static void moddown_poly(const oc_ctx *c, const u64 *x, int level, u64 *out) {
 #pragma omp parallel for schedule(static)
   for (u64 t = 0; t < N; t++) {
     big S = big_u64(0);
-    for (int k = 0; k < al; k++) {
-      u64 pk = c->mods[c->L + 1 + k];
-      S = big_add(S, big_mul_u64(H[k], mulmod(pc[(size_t)k * N + t], Hinv[k], pk)));
+    for (int k = 0; k < ns; k++) {
+      u64 dk = c->mods[smod[k]];
+      S = big_add(S, big_mul_u64(H[k], mulmod(pc[(size_t)k * N + t], Hinv[k], dk)));
     }
-    while (big_cmp(S, P) >= 0) S = big_sub(S, P);
+    while (big_cmp(S, D) >= 0) S = big_sub(S, D);
     big twoS = big_add(S, S);
-    if (big_cmp(twoS, P) > 0) { mag[t] = big_sub(P, S); neg[t] = 1; }
+    if (big_cmp(twoS, D) > 0) { mag[t] = big_sub(D, S); neg[t] = 1; }
     else { mag[t] = S; neg[t] = 0; }
   }
 #pragma omp parallel for schedule(dynamic)
-  for (int i = 0; i < nq; i++) {
+  for (int i = 0; i < nout; i++) {
     u64 q = c->mods[i];
     u64 *y = alloc_u64(N);
     for (u64 t = 0; t < N; t++) {
@@ -1002,16 +1006,51 @@ static void moddown_poly(const oc_ctx *c, const u64 *x, int level, u64 *out) {
       y[t] = neg[t] ? (r ? q - r : 0) : r;
     }
     oc_ntt(c, i, y);
-    u64 pinv = 1;
-    for (int k = 0; k < al; k++) pinv = mulmod(pinv, c->mods[c->L + 1 + k] % q, q);
-    pinv = invmod(pinv, q);
+    u64 dinv = 1;
+    for (int k = 0; k < ns; k++) dinv = mulmod(dinv, c->mods[smod[k]] % q, q);
+    dinv = invmod(dinv, q);
     for (u64 t = 0; t < N; t++)
-      out[(size_t)i * N + t] = mulmod(submod(x[(size_t)i * N + t], y[t], q), pinv, q);
+      out[(size_t)i * N + t] = mulmod(submod(x[(size_t)i * N + t], y[t], q), dinv, q);
     free(y);
   }
   free(pc);
   free(mag);
   free(neg);
+}
+
+/* ModDown (Appendix A, KeySwitch): x in R_{Q_l P} (NTT domain, l+1+alpha
+ * limbs) -> round(x / P) in R_{Q_l}: the division above with the P limbs as
+ * sources. */
+static void moddown_poly(const oc_ctx *c, const u64 *x, int level, u64 *out) {
+  int spos[MAXMOD], smod[MAXMOD];
+  for (int k = 0; k < c->alpha; k++) {
+    spos[k] = level + 1 + k;
+    smod[k] = c->L + 1 + k;
+  }
+  divide_round_poly(c, x, spos, smod, c->alpha, level + 1, out);
+}
+
+/* ModDown and the Rescale after it as one rounding (a variant of the paper's
+ * two): x in R_{Q_l P} -> round(x / (P q_l)) in R_{Q_{l-1}}, the division
+ * above with q_l and the P limbs as sources.  It differs from
+ * Rescale(ModDown(x)) = round(round(x / P) / q_l) by at most one in a
+ * coefficient. */
+static void moddown_rescale_poly(const oc_ctx *c, const u64 *x, int level, u64 *out) {
+  int spos[MAXMOD], smod[MAXMOD];
+  spos[0] = level;
+  smod[0] = level;
+  for (int k = 0; k < c->alpha; k++) {
+    spos[k + 1] = level + 1 + k;
+    smod[k + 1] = c->L + 1 + k;
+  }
+  divide_round_poly(c, x, spos, smod, c->alpha + 1, level, out);
+}
+
+oc_ct *oc_moddown_rescale(const oc_ctx *c, const oc_ct *a) {
+  if (!a->qp || a->level < 1) return NULL;
+  oc_ct *r = ct_new(c, a->level - 1, 0, a->scale / (double)c->mods[a->level]);
+  for (int p = 0; p < 2; p++) moddown_rescale_poly(c, poly(c, a, p, 0), a->level, poly(c, r, p, 0));
+  return r;
 }
 
 oc_ct *oc_moddown(const oc_ctx *c, const oc_ct *a) {
@@ -1500,7 +1539,8 @@ static void col_mask(int n, int k, int second, double *out) {
 /* A side: A_k = C^k Z a for k < n.  Bases B_b = Rot(B_{b-1}, n1z) from
  * B_0 = Z a and B'_0 = Rot(Z a, -n); for k = b n1z + r:
  *   A_k = Rescale(ModDown(m_k (.) HR(B_b, r) + m'_k (.) HR(B'_b, r))). */
-static oc_ct **side_a(const oc_ctx *c, const oc_ct *ca, int n, int n1z, int npz, int *err) {
+/* (fused: one rounding by P q_l in place of ModDown then Rescale) */
+static oc_ct **side_a(const oc_ctx *c, const oc_ct *ca, int n, int n1z, int npz, int fused, int *err) {
   u64 N = c->N;
   int n2sq = n * n;
   oc_ct *A0 = sigma_dcd(c, ca, n, n1z, npz, err);
@@ -1537,10 +1577,14 @@ static oc_ct **side_a(const oc_ctx *c, const oc_ct *ca, int n, int n1z, int npz,
         qp_pmult_acc(c, acc, h, m);
         oc_ct_free(h);
       }
-      oc_ct *md = oc_moddown(c, acc);
-      Ak[k] = oc_rescale(c, md);
+      if (fused) {
+        Ak[k] = oc_moddown_rescale(c, acc);
+      } else {
+        oc_ct *md = oc_moddown(c, acc);
+        Ak[k] = oc_rescale(c, md);
+        oc_ct_free(md);
+      }
       if (Ak[k]) Ak[k]->scale = Bb->scale;
-      oc_ct_free(md);
       oc_ct_free(acc);
     }
     free(d1); free(d2);
@@ -1628,12 +1672,16 @@ static void free_list(oc_ct **l, int n) {
   free(l);
 }
 
+/* flags: 1 = lazy relinearisation (the n tensors summed, relinearised once),
+ * 2 = ModDown and Rescale of the A side as one rounding; both variants of
+ * the paper's order */
 oc_ct *oc_matmul_lazy(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int npz,
-                      int npt, int lazy, int *err) {
+                      int npt, int flags, int *err) {
+  const int lazy = flags & 1;
   *err = 0;
   if (ca->qp || cb->qp || ca->level != cb->level) { *err = -2; return NULL; }
   if ((u64)n * n > c->N / 2 || n % n1z || n % n1t || npz < 1 || npt < 1) { *err = -1; return NULL; }
-  oc_ct **Ak = side_a(c, ca, n, n1z, npz, err);
+  oc_ct **Ak = side_a(c, ca, n, n1z, npz, flags & 2, err);
   if (!Ak) return NULL;
   oc_ct **Bk = side_b(c, cb, n, n1t, npt, err);
   if (!Bk) { free_list(Ak, n); return NULL; }
@@ -1670,8 +1718,9 @@ oc_ct *oc_matmul(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n
 /* are G of block (b, a); every block ends at one level.                     */
 /* ------------------------------------------------------------------------ */
 int oc_covariance_lazy(const oc_ctx *c, oc_ct *const *x, int rb, int k, int n, u64 n_samples, int n1z, int n1t,
-                       int npz, int npt, int n1g, int lazy, oc_ct **out) {
+                       int npz, int npt, int n1g, int flags, oc_ct **out) {
   int err = 0;
+  const int lazy = flags & 1;
   int level = x[0]->level;
   oc_ct **acc = (oc_ct **)calloc(k * k, sizeof(oc_ct *));
   u64 **acc3 = (u64 **)calloc(k * k, sizeof(u64 *));
@@ -1682,7 +1731,7 @@ int oc_covariance_lazy(const oc_ctx *c, oc_ct *const *x, int rb, int k, int n, u
     for (int a = 0; a < k; a++) {
       oc_ct *xt = oc_lt_transpose(c, x[r * k + a], n, n1g, 1.0 / (double)n_samples, &err);
       if (!xt) return err ? err : -1;
-      A[a] = side_a(c, xt, n, n1z, npz, &err);
+      A[a] = side_a(c, xt, n, n1z, npz, flags & 2, &err);
       oc_ct_free(xt);
       if (!A[a]) return err ? err : -1;
     }

@@ -107,6 +107,8 @@ def lib():
         L.oc_decompose.argtypes = [C.c_void_p, u64p, C.c_int]
         L.oc_moddown.restype = C.c_void_p
         L.oc_moddown.argtypes = [C.c_void_p, C.c_void_p]
+        L.oc_moddown_rescale.restype = C.c_void_p
+        L.oc_moddown_rescale.argtypes = [C.c_void_p, C.c_void_p]
         L.oc_hoisted_rotate.restype = C.c_void_p
         L.oc_hoisted_rotate.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.oc_rotate.restype = C.c_void_p
@@ -360,6 +362,10 @@ class Oracle:
     def moddown(self, a):
         return Ct(self, lib().oc_moddown(self.ptr, a.ptr))
 
+    def moddown_rescale(self, a):
+        """round(x / (P q_l)): ModDown and the Rescale after it as one rounding"""
+        return Ct(self, lib().oc_moddown_rescale(self.ptr, a.ptr))
+
     def hoisted_rotate(self, a, step):
         return Ct(self, lib().oc_hoisted_rotate(self.ptr, a.ptr, step))
 
@@ -382,20 +388,24 @@ class Oracle:
     def lt_transpose(self, a, n, n1, weight=1.0):
         return self._lt(lib().oc_lt_transpose, a.ptr, n, n1, weight)
 
-    def matmul(self, a, b, n, n1z, n1t, npz=None, npt=None, lazy=False):
-        """lazy: relinearise once after summing the n tensors (a variant;
-        the paper's order relinearises every product)"""
+    def matmul(self, a, b, n, n1z, n1t, npz=None, npt=None, lazy=False, fused_rescale=False):
+        """lazy: relinearise once after summing the n tensors; fused_rescale:
+        the A side's ModDown and Rescale as one rounding by P q_l (both
+        variants; the paper's order relinearises every product and rounds
+        twice)"""
         npz = n - 1 if npz is None else npz
         npt = n - 1 if npt is None else npt
-        return self._lt(lib().oc_matmul_lazy, a.ptr, b.ptr, n, n1z, n1t, npz, npt, 1 if lazy else 0)
+        flags = (1 if lazy else 0) | (2 if fused_rescale else 0)
+        return self._lt(lib().oc_matmul_lazy, a.ptr, b.ptr, n, n1z, n1t, npz, npt, flags)
 
-    def covariance(self, blocks, rb, k, n, n_samples, n1z, n1t, n1g, npz=None, npt=None, lazy=False):
+    def covariance(self, blocks, rb, k, n, n_samples, n1z, n1t, n1g, npz=None, npt=None, lazy=False,
+                   fused_rescale=False):
         npz = n - 1 if npz is None else npz
         npt = n - 1 if npt is None else npt
         px = (C.c_void_p * len(blocks))(*[b.ptr for b in blocks])
         out = (C.c_void_p * (k * k))()
-        rc = lib().oc_covariance_lazy(self.ptr, px, rb, k, n, n_samples, n1z, n1t, npz, npt, n1g, 1 if lazy else 0,
-                                      out)
+        flags = (1 if lazy else 0) | (2 if fused_rescale else 0)
+        rc = lib().oc_covariance_lazy(self.ptr, px, rb, k, n, n_samples, n1z, n1t, npz, npt, n1g, flags, out)
         if rc:
             raise RuntimeError(f"covariance failed ({rc})")
         return [Ct(self, out[i]) for i in range(k * k)]

@@ -68,7 +68,7 @@ void check_ct(const he_ctx* c, const he_ct* a) {
 }
 struct MmOpts {
   int n1z, n1t, npz, npt;
-  bool lazy;
+  bool lazy, fused;
 };
 MmOpts opts_of(const he_matmul_opts* o, int d) {
   MmOpts m;
@@ -79,6 +79,7 @@ MmOpts opts_of(const he_matmul_opts* o, int d) {
   if (m.npz > d - 1) m.npz = d - 1;
   if (m.npt > d - 1) m.npt = d - 1;
   m.lazy = o && (o->flags & HE_MM_LAZY_RELIN);
+  m.fused = o && (o->flags & HE_MM_FUSED_RESCALE);
   if (m.n1z < 1 || m.n1t < 1 || d % m.n1z || d % m.n1t) fail(HE_EINVAL, "baby-step counts must divide d");
   return m;
 }
@@ -329,7 +330,7 @@ he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, con
     HeCtxImpl& c = ctx->impl;
     MmOpts m = opts_of(opts, (int)d);
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
-    HeCt r = c.matmul(a->ct, b->ct, (int)d, m.n1z, m.n1t, m.npz, m.npt, m.lazy);
+    HeCt r = c.matmul(a->ct, b->ct, (int)d, m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused);
     hip_check(hipEventRecord(c.ev1, c.stream), "event");
     *out = wrap(ctx, std::move(r));
   });
@@ -364,7 +365,7 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
           }
           MmOpts m = opts_of(opts, (int)d[i]);
           HeCt sa = c.stack(xa), sb = c.stack(xb);
-          HeCt r = c.matmul(sa, sb, (int)d[i], m.n1z, m.n1t, m.npz, m.npt, m.lazy);
+          HeCt r = c.matmul(sa, sb, (int)d[i], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused);
           std::vector<HeCt> parts = c.unstack(r);
           for (size_t k = i; k < j; k++) out[k] = wrap(ctx, std::move(parts[k - i]));
           i = j;
@@ -372,7 +373,7 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
       } else {
         for (size_t i = 0; i < count; i++) {
           MmOpts m = opts_of(opts, (int)d[i]);
-          out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], m.n1z, m.n1t, m.npz, m.npt, m.lazy));
+          out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused));
         }
       }
     } catch (...) {
@@ -401,7 +402,7 @@ he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks,
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
     std::vector<HeCt> r =
         c.covariance(xs, (int)row_blocks, (int)k, (int)d, n_samples, m.n1z, m.n1t, default_n1((int)d), m.npz, m.npt,
-                     m.lazy);
+                     m.lazy, m.fused);
     hip_check(hipEventRecord(c.ev1, c.stream), "event");
     for (uint32_t i = 0; i < k * k; i++) cov[i] = wrap(ctx, std::move(r[i]));
   });

@@ -64,8 +64,10 @@ struct HeCtxImpl {
   std::vector<ModConst> mc;
   std::vector<DevBuf> tables;
   std::vector<std::vector<FbcTable>> up;  // [level][digit]
+  std::vector<FbcTable> down_rs;          // [level]: sources q_l and P (empty when alpha > 3)
   FbcTable down;                          // P -> Q
   DevBuf pmod, pinv, qlinv;
+  DevBuf pqlinv;  // [level][nmods][2]: (P q_l)^-1 mod q_k with Shoup companions
   DevBuf s_ntt, pk;
   bool have_sk = false;
   std::map<u64, DevBuf> keys;             // Galois element -> key; 0 = relinearisation
@@ -114,6 +116,8 @@ struct HeCtxImpl {
   void hoisted_masked(const HeCt& x, const u64* digits, const std::vector<u64>& gs, const std::vector<u64*>& outs,
                       const std::vector<const u64*>& masks, bool accumulate);
   HeCt moddown(const HeCt& x, int out_level = -1);
+  // ModDown and Rescale as one rounding by P q_l (a variant)
+  HeCt moddown_rescale(const HeCt& x, int out_level = -1);
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);
   HeCt rotate(const HeCt& x, long step);
@@ -130,15 +134,17 @@ struct HeCtxImpl {
   HeCt apply_chain(const HeCt& x, const std::vector<DcdFactor>& fs, const std::string& tag);
   HeCt sigma_dcd(const HeCt& x, int n, int n1, int nprime);
   HeCt tau_dcd(const HeCt& x, int n, int n1, int nprime);
-  HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t, int npz, int npt, bool lazy = false);
+  HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t, int npz, int npt, bool lazy = false,
+              bool fused_rs = false);
   void accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   HeCt relin_sum(const DevBuf& acc3, int level, double scale, int B);
-  std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level = -1);
+  std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level = -1,
+                                  bool fused_rs = false);
   std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t, int npt, int out_level = -1);
   void align_sides(std::vector<HeCt>& Ak, std::vector<HeCt>& Bk);
   void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,
-                               int n1t, int n1g, int npz, int npt, bool lazy = false);
+                               int n1t, int n1g, int npz, int npt, bool lazy = false, bool fused_rs = false);
 
   // PowerMethod (section 6.1) and the interactive refresh
   DevBuf decrypt_int(const HeCt& c);

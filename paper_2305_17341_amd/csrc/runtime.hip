@@ -386,6 +386,15 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
     for (int k = 0; k < alpha; k++) src.push_back(L + 1 + k);
     down = make_fbc(this, src);
   }
+  // ModDown + Rescale as one rounding: sources q_l and P (at most 4 limbs)
+  if (alpha <= 3) {
+    down_rs.resize(L + 1);
+    for (int l = 1; l <= L; l++) {
+      std::vector<int> src{l};
+      for (int k = 0; k < alpha; k++) src.push_back(L + 1 + k);
+      down_rs[l] = make_fbc(this, src);
+    }
+  }
   // P mod q, P^{-1} mod q (Shoup pairs) and q_l^{-1} mod q_k
   std::vector<u64> pm(2 * nmods), pi(2 * nmods), ql((size_t)nmods * nmods * 2);
   for (int m = 0; m < nmods; m++) {
@@ -409,6 +418,18 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
   hip_check(hipMemcpy(pinv.p, pi.data(), pi.size() * 8, hipMemcpyHostToDevice), "pinv");
   qlinv = DevBuf(&pool, ql.size());
   hip_check(hipMemcpy(qlinv.p, ql.data(), ql.size() * 8, hipMemcpyHostToDevice), "qlinv");
+  {
+    std::vector<u64> pq((size_t)(L + 1) * nmods * 2, 0);
+    for (int l = 1; l <= L; l++)
+      for (int k = 0; k < l; k++) {
+        const u64 q = mods[k];
+        const u64 v = hinv(hmul(pm[2 * k], mods[l] % q, q), q);
+        pq[((size_t)l * nmods + k) * 2] = v;
+        pq[((size_t)l * nmods + k) * 2 + 1] = shoup_pre(v, q);
+      }
+    pqlinv = DevBuf(&pool, pq.size());
+    hip_check(hipMemcpy(pqlinv.p, pq.data(), pq.size() * 8, hipMemcpyHostToDevice), "pqlinv");
+  }
   hip_check(hipDeviceSynchronize(), "init");
 }
 
@@ -749,6 +770,48 @@ HeCt HeCtxImpl::moddown(const HeCt& x, int out_level) {
   } else {
     launch_fbc_to_q(T, y.p, pc.p, nq, np, down, stream);
     launch_ntt_fwd_sub(T, y.p, nq, np, qmap(nq), x.d.p, nqp, pinv.p, c.d.p, stream);
+  }
+  n_moddown += x.B;
+  return c;
+}
+
+// ModDown and the Rescale after it as one rounding: x in R_{Q_l P} ->
+// round(x / (P q_l)) in R_{Q_{l-1}} (or a lower out_level: only the kept
+// limbs are computed): the exact centred lift of x mod P q_l from the limbs
+// q_l, p_1..p_alpha, then (x - lift) (P q_l)^-1 on the limbs below q_l.
+HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level) {
+  if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
+  const int l = x.level;
+  if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
+  if (down_rs.empty()) fail(HE_EINVAL, "one rounding for ModDown and Rescale needs at most 3 special primes");
+  if (out_level < 0) out_level = l - 1;
+  if (out_level > l - 1) fail(HE_ELEVEL, "rescale cannot raise the level");
+  const int nqx = nq_of(l), nqp = nqp_of(l), nout = out_level + 1, ns = alpha + 1;
+  const int np = (int)x.polys();
+  const FbcTable& tab = down_rs[l];
+  // sources [np][q_l, p_1..p_alpha] in the coefficient domain
+  DevBuf pc(&pool, (size_t)np * ns * N);
+  hip_check(hipMemcpy2DAsync(pc.p, (size_t)ns * N * 8, x.d.p + (size_t)l * N, (size_t)x.nlimbs * N * 8,
+                             (size_t)N * 8, np, hipMemcpyDeviceToDevice, stream),
+            "gather");
+  hip_check(hipMemcpy2DAsync(pc.p + N, (size_t)ns * N * 8, x.d.p + (size_t)nqx * N, (size_t)x.nlimbs * N * 8,
+                             (size_t)alpha * N * 8, np, hipMemcpyDeviceToDevice, stream),
+            "gather");
+  LimbMap sm;
+  sm.n = ns;
+  sm.idx[0] = (short)l;
+  for (int k = 0; k < alpha; k++) sm.idx[1 + k] = (short)(L + 1 + k);
+  launch_ntt(T, pc.p, np * ns, sm, true, stream);
+  DevBuf y(&pool, (size_t)np * nout * N);
+  HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
+  const u64* cp = pqlinv.p + (size_t)l * nmods * 2;
+  if (fused_conv) {
+    DevBuf V(&pool, (size_t)np * (ns + 1) * N);
+    if (!launch_moddown_fused(T, pc.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, V.p, stream))
+      fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
+  } else {
+    launch_fbc_to_q(T, y.p, pc.p, nout, np, tab, stream);
+    launch_ntt_fwd_sub(T, y.p, nout, np, qmap(nout), x.d.p, nqp, cp, c.d.p, stream);
   }
   n_moddown += x.B;
   return c;
@@ -1164,7 +1227,7 @@ static void col_mask(int n, int k, bool second, std::vector<double>& out) {
 // k = b n1z + r, with bases B_b = Rot(B_{b-1}, n1z), B'_0 = Rot(Z a, -n), B'_b = Rot(B'_{b-1}, n1z)
 // out_level (if >= 0) caps the level of the A_k: limbs above it are never
 // computed (the same residues as computing them and dropping them).
-std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level) {
+std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level, bool fused_rs) {
   HeCt A0 = sigma_dcd(ca, n, n1z, npz);
   const int lvl = A0.level;
   if (lvl < 1) fail(HE_ELEVEL, "no level left for the column shifts");
@@ -1234,8 +1297,13 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
         lift2 = HeCt();
       }
       HeCt sum = std::move(acc_k);
-      HeCt md = moddown(sum);
-      Ak[k] = rescale(md, out_level >= 0 ? std::min(out_level, lvl - 1) : -1);
+      const int ol = out_level >= 0 ? std::min(out_level, lvl - 1) : -1;
+      if (fused_rs) {
+        Ak[k] = moddown_rescale(sum, ol);
+      } else {
+        HeCt md = moddown(sum);
+        Ak[k] = rescale(md, ol);
+      }
       Ak[k].scale = Bb.scale;
     }
   }
@@ -1312,7 +1380,8 @@ HeCt HeCtxImpl::relin_sum(const DevBuf& acc3, int level, double scale, int B) {
   return c;
 }
 
-HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, int npz, int npt, bool lazy) {
+HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, int npz, int npt, bool lazy,
+                        bool fused_rs) {
   if (ca.qp || cb.qp || ca.level != cb.level) fail(HE_ELEVEL, "operands must be ciphertexts at one level");
   if ((u64)n * n > N / 2 || n % n1z || n % n1t || npz < 1 || npt < 1)
     fail(HE_EINVAL, "bad matrix size / baby-step count / decomposition");
@@ -1321,7 +1390,7 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, 
   // both sides produced at their common level (A: sigma, then the masks;
   // B: tau); align_sides only guards the prediction
   const int common = std::min(ca.level - dz - 1, cb.level - dt);
-  std::vector<HeCt> Ak = matmul_side_a(ca, n, n1z, npz, common);
+  std::vector<HeCt> Ak = matmul_side_a(ca, n, n1z, npz, common, fused_rs);
   std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t, npt, common);
   align_sides(Ak, Bk);
   HeCt acc;
@@ -1342,7 +1411,8 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, 
 // for b <= a, and G(block (b, a)) for a < b; the A and B sides of each
 // row block are formed once and reused for every pair (one-to-many caching).
 std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples,
-                                        int n1z, int n1t, int n1g, int npz, int npt, bool lazy) {
+                                        int n1z, int n1t, int n1g, int npz, int npt, bool lazy,
+                                        bool fused_rs) {
   if ((int)x.size() != rb * k) fail(HE_EINVAL, "block count mismatch");
   int level = x[0]->level;
   for (auto* c : x)
@@ -1361,7 +1431,7 @@ std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int r
     std::vector<std::vector<HeCt>> A(k), B(k);
     for (int a = 0; a < k; a++) {
       HeCt xt = lintrans(*x[r * k + a], LT_TRANSPOSE, n, n1g, 1.0 / (double)n_samples);
-      A[a] = matmul_side_a(xt, n, n1z, npz, common);
+      A[a] = matmul_side_a(xt, n, n1z, npz, common, fused_rs);
     }
     for (int b = 0; b < k; b++) {
       HeCt xb = drop(*x[r * k + b], level - 1);

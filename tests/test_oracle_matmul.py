@@ -125,6 +125,26 @@ def test_lazy_relinearisation_variant_decrypts_to_fp64_product(small):
     assert e_lazy < 2 * e_eager
 
 
+def test_fused_rescale_variant_decrypts_to_fp64_product(small):
+    """Variant: the A side's ModDown and Rescale as one rounding by P q_l.
+    Rounding twice differs from it only where round(x / P) / q_l falls within
+    about 2^-41 of a half-integer, so the residues agree almost everywhere;
+    same product within the bound, with lazy relinearisation and without."""
+    n = 16
+    A, B = I.uniform_matrix(5, n), I.uniform_matrix(6, n)
+    ca, cb = small.encrypt(A.ravel(), nonce=5), small.encrypt(B.ravel(), nonce=6)
+    want = np.tile((A @ B).ravel(), small.slots // (n * n))
+    for lazy in (False, True):
+        ref = small.matmul(ca, cb, n, 4, 4, lazy=lazy)
+        fused = small.matmul(ca, cb, n, 4, 4, lazy=lazy, fused_rescale=True)
+        assert fused.level == ref.level and fused.scale == ref.scale
+        assert np.mean(fused.data() != ref.data()) < 1e-3
+        e_ref = np.max(np.abs(small.decrypt(ref) - want))
+        e_fused = np.max(np.abs(small.decrypt(fused) - want))
+        assert e_fused < BOUND, e_fused
+        assert e_fused < 2 * e_ref
+
+
 def test_lazy_covariance_decrypts(oracle_mod):
     c = I.SMALL
     o = oracle_mod.Oracle(c.log_n, c.q_bits + (40, 40), c.p_bits, seed=12)

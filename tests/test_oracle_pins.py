@@ -288,6 +288,28 @@ def test_moddown_is_rounded_division_by_P(oracle_mod, p_bits):
         assert y == [t0.centred(t0.round_div(v, P), Q) for v in x]
 
 
+@pytest.mark.parametrize("p_bits", [(60,), (60, 60, 60)])
+def test_moddown_rescale_is_one_rounded_division(oracle_mod, p_bits):
+    # the variant: ModDown and the Rescale after it as round(x / (P q_l)),
+    # against a big-integer division; it differs from rounding twice by at
+    # most one per coefficient
+    o = oracle_mod.Oracle(10, (60, 40, 40, 40), p_bits, seed=4)
+    o.keygen(rot_steps=[1], relin=False)
+    z = np.random.default_rng(3).uniform(-1, 1, o.slots)
+    ct = o.encrypt(z, nonce=11)
+    h = o.hoisted_rotate(ct, 1)
+    fused = o.moddown_rescale(h)
+    twice = o.rescale(o.moddown(h))
+    assert fused.level == ct.level - 1 and fused.scale == twice.scale
+    D = math.prod(o.p) * o.q[ct.level]
+    for p in (0, 1):
+        x, _ = _coef_ints(o, h, p)
+        y, Q = _coef_ints(o, fused, p)
+        assert y == [t0.centred(t0.round_div(v, D), Q) for v in x]
+        y2, _ = _coef_ints(o, twice, p)
+        assert max(abs(a - b) for a, b in zip(y, y2)) <= 1
+
+
 def test_rotation_rotates_slots(toy):
     z = np.random.default_rng(5).uniform(-1, 1, toy.slots)
     ct = toy.encrypt(z, nonce=4)
