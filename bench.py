@@ -279,7 +279,9 @@ def main():
                 "traffic": None if traffic is None else round(traffic),
                 "avg_launch_ms": round(avg_ms, 5), "launches": launches,
                 "algorithmic_bytes_per_launch": round(bytes_per_launch)}
-    n_rescale = 2 + 1 + d  # sigma, tau, the d column shifts, the final product
+    # sigma, tau, the d column shifts (merged into their ModDowns when the A
+    # side rounds once), the final product
+    n_rescale = 2 + 1 + (0 if head["flags"] & FUSED else d)
     result = {
         "metric": METRIC,
         "value": round(value, 4),
