@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--knobs", default="",
                     help="launch knobs set before the run, e.g. mr_members=4,ms_members=4 (with --no-autotune)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="headline steps launched one kernel at a time instead of replaying a recorded HIP graph")
     ap.add_argument("--two-roundings", action="store_true",
                     help="headline keeps the A side's ModDown and Rescale as two roundings")
     ap.add_argument("--paper-relin", action="store_true",
@@ -182,11 +184,18 @@ def main():
     cB = [ctx.encrypt_matrix(b, nonce=1001 + i) for i, b in enumerate(Bs)]
     ctx.sync()
 
-    BATCHED, LAZY, FUSED = 1, 2, 4
+    BATCHED, LAZY, FUSED, GRAPH = 1, 2, 4, 8
     relin = "paper" if args.paper_relin else "lazy"
-    head = {"flags": BATCHED | (0 if args.paper_relin else LAZY | (0 if args.two_roundings else FUSED))}
-    names = {0: "plain", BATCHED: "batched", BATCHED | LAZY: "batched+lazy-relin",
-             BATCHED | LAZY | FUSED: "batched+lazy-relin+fused-rescale"}
+    head = {"flags": BATCHED | (0 if args.paper_relin else LAZY | (0 if args.two_roundings else FUSED)) |
+            (0 if args.no_graph else GRAPH)}
+
+    class Names(dict):
+        def __missing__(self, f):
+            parts = ["batched" if f & BATCHED else "plain"]
+            parts += [w for bit, w in ((LAZY, "lazy-relin"), (FUSED, "fused-rescale"), (GRAPH, "hip-graph"))
+                      if f & bit]
+            return "+".join(parts)
+    names = Names()
 
     def timed(opts, profile, warmup=True):
         """warm-up then `--steps` timed steps of B products; returns (seconds, per-step ms, outputs of warm-up)"""
@@ -217,10 +226,13 @@ def main():
     tuned = {"knobs": {k: he.knob_get(k) for k in autotune_knobs()}, "step_ms": None}
     if not args.no_autotune:
         from paper_2305_17341_amd import autotune
-        warm = ctx.matmul_batch(cA, cB, [d] * B, opts=head)   # plaintext caches
+        # launched one kernel at a time: a recording would keep the shapes it
+        # was made with (the headline records after the knobs are set)
+        tune_opts = {"flags": head["flags"] & ~GRAPH}
+        warm = ctx.matmul_batch(cA, cB, [d] * B, opts=tune_opts)   # plaintext caches
         ctx.sync()
         del warm
-        best, tt = autotune.autotune(ctx, cA, cB, d, opts=head, log=log)
+        best, tt = autotune.autotune(ctx, cA, cB, d, opts=tune_opts, log=log)
         tuned = {"knobs": best, "step_ms": tt}
 
     plain_outs = None
@@ -230,13 +242,16 @@ def main():
         # batching gives the one-at-a-time residues
         same = all(np.array_equal(p.export(), q.export()) for p, q in zip(plain_outs, bp_outs))
         del bp_outs
-    c0 = ctx.op_counts()
-    # headline: the library as deployed (no per-kernel events)
+    # headline: the library as deployed (no per-kernel events; with the
+    # recorded graph, the warm-up records it and the timed steps replay it)
     t_total, lat, outs = timed(head, False)
+    # the same steps again, launched one kernel at a time with HIP events
+    # around every launch: the kernel table, the roofline's per-launch
+    # durations and the operation counts come from these
+    eager = {"flags": head["flags"] & ~GRAPH}
+    c0 = ctx.op_counts()
+    t_prof, _, _ = timed(eager, True, warmup=False)
     c1 = ctx.op_counts()
-    # the same steps again with HIP events around every launch: the kernel
-    # table and the roofline's per-launch durations come from these
-    t_prof, _, _ = timed(head, True, warmup=False)
     fams = ["ntt_fwd_cols", "ntt_fwd_cols_modup", "ntt_fwd_cols_fbc", "ntt_fwd_cols_lift", "ntt_fwd_rows",
             "ntt_fwd_rows_sub",
             "ntt_inv_rows", "ntt_inv_cols", "multsum", "multsum_rot", "modup", "fbc_prep",
@@ -244,11 +259,11 @@ def main():
             "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor", "plift"]
     prof = {f: ctx.profile_read(f) for f in fams}
     ctx.profile_enable(False)
-    n_mm = (args.steps + args.warmup) * B
+    n_mm = args.steps * B
     per_mm = {k: (c1[k] - c0[k]) / n_mm for k in c0}
     # accuracy of a warm-up output against FP64; the headline path batched == alone
     err = float(np.max(np.abs(ctx.decrypt(outs[0], d * d) - (As[0] @ Bs[0]).ravel())))
-    alone = ctx.matmul(cA[0], cB[0], d, opts={"flags": head["flags"] & ~BATCHED})
+    alone = ctx.matmul(cA[0], cB[0], d, opts={"flags": head["flags"] & ~(BATCHED | GRAPH)})
     head_same = bool(np.array_equal(alone.export(), outs[0].export()))
     del outs, plain_outs, alone
 

@@ -113,6 +113,15 @@ typedef struct {
  * level and scale are the same.  Needs at most 3 special primes (HE_EINVAL
  * otherwise). */
 #define HE_MM_FUSED_RESCALE 4u
+/* he_matmul_batch only, with HE_MM_BATCHED: 1 to 8 products of one d (one
+ * operand level and scale) recorded once as a HIP graph and replayed by later
+ * calls with the same operand ciphertexts and options (the last 4 recordings
+ * are kept per context).  A replay reads the operands' buffers as they are at
+ * that time; results are copied out of the graph's own buffers into new
+ * ciphertexts, residue for residue those of the unrecorded call.  The first call runs the product three
+ * times (warm-up, arena sizing, recording).  Not while the kernel profile is
+ * enabled (HE_EINVAL).  he_trim and he_keygen drop the recordings. */
+#define HE_MM_GRAPH 8u
 
 /* Create a context on the current HIP device.  `dev` may be NULL.  `seed`
  * keys every random draw of the context (Philox4x64-10 streams).

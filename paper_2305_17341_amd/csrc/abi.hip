@@ -128,6 +128,7 @@ he_status he_keygen(he_ctx* ctx, const int32_t* rot_steps, size_t n_steps) {
     auto lk = hold(ctx);
     need(ctx != nullptr, "null context");
     HeCtxImpl& c = ctx->impl;
+    c.drop_graphs();  // recorded products hold the keys' addresses
     c.keygen_secret();
     c.keygen_relin();
     for (size_t i = 0; i < n_steps; i++) c.keygen_rot(rot_steps[i]);
@@ -348,6 +349,22 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
       out[i] = nullptr;
     }
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
+    if (opts && (opts->flags & HE_MM_GRAPH)) {
+      need(opts->flags & HE_MM_BATCHED, "a recorded product must be batched");
+      need(count >= 1 && count <= 8, "a recorded product takes 1 to 8 pairs");
+      need(!prof_enabled(), "no recording while the kernel profile is enabled");
+      std::vector<const HeCt*> xa, xb;
+      for (size_t k = 0; k < count; k++) {
+        need(d[k] == d[0], "a recorded product takes one matrix size");
+        xa.push_back(&a[k]->ct);
+        xb.push_back(&b[k]->ct);
+      }
+      MmOpts m = opts_of(opts, (int)d[0]);
+      std::vector<HeCt> parts = c.matmul_graph(xa, xb, (int)d[0], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused);
+      for (size_t k = 0; k < count; k++) out[k] = wrap(ctx, std::move(parts[k]));
+      hip_check(hipEventRecord(c.ev1, c.stream), "event");
+      return;
+    }
     try {
       if (opts && (opts->flags & HE_MM_BATCHED)) {
         // runs of equal d stacked into batches of up to 8: every launch of the
@@ -554,6 +571,7 @@ he_status he_trim(he_ctx* ctx) {
     auto lk = hold(ctx);
     need(ctx != nullptr, "null context");
     hip_check(hipStreamSynchronize(ctx->impl.stream), "sync");
+    ctx->impl.drop_graphs();
     ctx->impl.pool.trim();
     ctx->impl.pool.peak = ctx->impl.pool.bytes_live;
   });

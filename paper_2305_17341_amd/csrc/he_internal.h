@@ -152,6 +152,15 @@ struct DevPool {
   void* (*user_alloc)(size_t, void*) = nullptr;
   void (*user_release)(void*, void*) = nullptr;
   void* user = nullptr;
+  // while set, allocations come from (and blocks of it return to) this pool:
+  // the private arena of a HIP graph being recorded
+  DevPool* redirect = nullptr;
+  // a frozen pool serves only cached blocks (no device allocation, which a
+  // stream capture must not see)
+  bool frozen = false;
+  // serve only cached blocks of exactly the requested size (an arena sized by
+  // one run serves a repeat of the same run)
+  bool exact = false;
   void* get(size_t bytes);
   void put(void* p);
   void trim();

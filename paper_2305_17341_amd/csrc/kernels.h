@@ -158,5 +158,6 @@ bool knob_get(const char* name, int* value);
 
 // per-family device timing (HIP events around launches)
 void prof_enable(bool on);
+bool prof_enabled();
 bool prof_read(const char* family, double* ms, u64* launches, double* bytes);
 std::vector<std::string> prof_families();

@@ -114,6 +114,7 @@ void prof_collect() {
 }
 }  // namespace
 
+bool prof_enabled() { return g_prof_on; }
 void prof_enable(bool on) {
   prof_collect();
   if (on) g_prof_done.clear();

@@ -1,6 +1,8 @@
 // Host runtime declarations (internal).
 #pragma once
 #include <functional>
+#include <list>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <string>
@@ -47,6 +49,25 @@ std::vector<long> transpose_steps(int n, int n1);
 // replaces a ciphertext that ran out of levels by a fresh one (client side)
 using RefreshFn = std::function<void(HeCt&)>;
 
+// A batched product recorded as a HIP graph: replays run the whole launch
+// sequence with one call.  The graph's temporaries and outputs live in its
+// own arena, which nothing else allocates from.
+struct MmGraph {
+  std::vector<u64> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::unique_ptr<DevPool> arena;
+  std::vector<HeCt> outs;
+  MmGraph() = default;
+  MmGraph(const MmGraph&) = delete;
+  MmGraph& operator=(const MmGraph&) = delete;
+  ~MmGraph() {
+    outs.clear();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
 struct HeCtxImpl {
   int logN = 0;
   u64 N = 0;
@@ -75,6 +96,7 @@ struct HeCtxImpl {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0;
   long n_decompose = 0, n_multsum = 0, n_moddown = 0;
+  std::list<MmGraph> graphs;  // most recently used first (declared after the pool: destroyed before it)
 
   ~HeCtxImpl();
   void init(const he_params* p, const he_device* dev, u64 seed);
@@ -136,6 +158,11 @@ struct HeCtxImpl {
   HeCt tau_dcd(const HeCt& x, int n, int n1, int nprime);
   HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t, int npz, int npt, bool lazy = false,
               bool fused_rs = false);
+  // up to 8 products of one size, stacked, recorded once as a HIP graph (keyed
+  // by the operands' buffers and the options) and replayed
+  std::vector<HeCt> matmul_graph(const std::vector<const HeCt*>& a, const std::vector<const HeCt*>& b, int n,
+                                 int n1z, int n1t, int npz, int npt, bool lazy, bool fused_rs);
+  void drop_graphs();
   void accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   HeCt relin_sum(const DevBuf& acc3, int level, double scale, int B);
   std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level = -1,

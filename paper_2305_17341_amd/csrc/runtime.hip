@@ -1,6 +1,8 @@
 // Host runtime of the MI355X RNS-CKKS library: parameters and tables, device
 // memory, key generation, the CKKS operations, the double-hoisted linear
 // transforms and Jiang's matrix product.  The C ABI wrappers live in abi.hip.
+#include <cstring>
+
 #include "runtime.h"
 
 #include <algorithm>
@@ -22,10 +24,11 @@ void hip_check(hipError_t e, const char* what) {
 // device memory pool
 // ---------------------------------------------------------------------------
 void* DevPool::get(size_t bytes) {
+  if (redirect) return redirect->get(bytes);
   if (bytes == 0) bytes = 8;
   bytes = (bytes + 255) & ~(size_t)255;
   auto it = free_.lower_bound(bytes);
-  if (it != free_.end() && it->first <= bytes + bytes / 4) {
+  if (it != free_.end() && it->first <= (exact ? bytes : bytes + bytes / 4)) {
     void* p = it->second;
     size_t sz = it->first;
     free_.erase(it);
@@ -35,6 +38,7 @@ void* DevPool::get(size_t bytes) {
     peak = std::max(peak, bytes_live);
     return p;
   }
+  if (frozen) fail(HE_ENOMEM, "graph arena exhausted while recording");
   void* p = nullptr;
   for (int attempt = 0; attempt < 2; attempt++) {
     if (user_alloc) {
@@ -53,6 +57,10 @@ void* DevPool::get(size_t bytes) {
   return p;
 }
 void DevPool::put(void* p) {
+  if (redirect && redirect->live_.count(p)) {
+    redirect->put(p);
+    return;
+  }
   auto it = live_.find(p);
   if (it == live_.end()) return;
   size_t sz = it->second;
@@ -126,6 +134,7 @@ static u32 brv_host(u32 x, int bits) {
 // ---------------------------------------------------------------------------
 HeCtxImpl::~HeCtxImpl() {
   if (stream) (void)hipStreamSynchronize(stream);
+  graphs.clear();
   ptcache.clear();
   keys.clear();
   s_ntt.release();
@@ -1404,6 +1413,81 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, 
     matmul_accumulate(acc, set, Ak, Bk);
   }
   return rescale(acc);
+}
+
+// Recording: one eager run fills every cache (plaintext diagonals, tables);
+// a second run inside the graph's arena (exact-size blocks) sizes it; the
+// third, inside a stream capture, finds every block it asks for in the arena
+// (frozen: no device allocation can happen during the capture).  A replay
+// reads the operands' buffers as they are at that time and rewrites the
+// arena's outputs, which are then copied out.
+std::vector<HeCt> HeCtxImpl::matmul_graph(const std::vector<const HeCt*>& a, const std::vector<const HeCt*>& b,
+                                          int n, int n1z, int n1t, int npz, int npt, bool lazy, bool fused_rs) {
+  if (a.empty() || a.size() != b.size() || a.size() > 8) fail(HE_EINVAL, "a recorded product takes 1 to 8 pairs");
+  std::vector<u64> key{(u64)n, (u64)n1z, (u64)n1t, (u64)npz, (u64)npt, (u64)lazy, (u64)fused_rs, (u64)a.size()};
+  for (const auto* v : {&a, &b})
+    for (const HeCt* x : *v) {
+      u64 sc;
+      std::memcpy(&sc, &x->scale, 8);
+      key.insert(key.end(), {(u64)(uintptr_t)x->d.p, (u64)x->level, sc, (u64)x->nlimbs, (u64)x->B});
+    }
+  auto it = graphs.begin();
+  while (it != graphs.end() && it->key != key) ++it;
+  if (it != graphs.end()) {
+    graphs.splice(graphs.begin(), graphs, it);
+  } else {
+    if (graphs.size() >= 4) graphs.pop_back();
+    auto run = [&](std::vector<HeCt>* keep) {
+      HeCt sa = stack(a), sb = stack(b);
+      HeCt r = matmul(sa, sb, n, n1z, n1t, npz, npt, lazy, fused_rs);
+      std::vector<HeCt> parts = unstack(r);
+      if (keep) *keep = std::move(parts);
+    };
+    run(nullptr);
+    graphs.emplace_front();
+    MmGraph& g = graphs.front();
+    g.key = key;
+    g.arena.reset(new DevPool);
+    g.arena->user_alloc = pool.user_alloc;
+    g.arena->user_release = pool.user_release;
+    g.arena->user = pool.user;
+    g.arena->exact = true;
+    pool.redirect = g.arena.get();
+    try {
+      run(nullptr);
+      hip_check(hipStreamSynchronize(stream), "graph arena");
+      g.arena->frozen = true;
+      hip_check(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed), "begin capture");
+      try {
+        run(&g.outs);
+      } catch (...) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(stream, &g.graph), "end capture");
+      hip_check(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0), "graph instantiate");
+    } catch (...) {
+      pool.redirect = nullptr;
+      g.outs.clear();
+      graphs.pop_front();
+      throw;
+    }
+    pool.redirect = nullptr;
+    for (HeCt& o : g.outs) o.d.pool = g.arena.get();
+  }
+  MmGraph& g = graphs.front();
+  hip_check(hipGraphLaunch(g.exec, stream), "graph launch");
+  std::vector<HeCt> out;
+  for (const HeCt& o : g.outs) out.push_back(ct_copy(o));
+  return out;
+}
+
+void HeCtxImpl::drop_graphs() {
+  if (graphs.empty()) return;
+  (void)hipStreamSynchronize(stream);
+  graphs.clear();
 }
 
 // Covariance (Algorithm HCovMtrx, centred data): block (a, b) of X^T X / s is
