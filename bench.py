@@ -41,10 +41,10 @@ CSRC = os.path.join(ROOT, "paper_2305_17341_amd", "csrc")
 # source regions a kernel's recorded traffic depends on: (file, first line, last line), matched literally
 _MULTSUM_REGIONS = [("kernels.hip", "__device__ __forceinline__ u32 automorph_src(", "}"),
                     ("kernels.hip", "#define MS_MAXB 8", "#undef MS_CASE"),
-                    ("he_internal.h", None, None)]
+                    ("he_internal.h", "// Per-modulus constants", "// Host-side objects")]
 _NTT_REGIONS = [("kernels.hip", "__device__ __forceinline__ int grid_limb(", "return m.n;\n}"),
                 ("kernels.hip", "struct ShoupArith {", "// Galois automorphism in the evaluation domain:"),
-                ("he_internal.h", None, None)]
+                ("he_internal.h", "// Per-modulus constants", "// Host-side objects")]
 KERNEL_REGIONS = {"multsum": _MULTSUM_REGIONS, "multsum_rot": _MULTSUM_REGIONS,
                   "ntt_fwd_cols": _NTT_REGIONS, "ntt_fwd_rows": _NTT_REGIONS, "ntt_fwd_rows_sub": _NTT_REGIONS,
                   "ntt_fwd_cols_modup": _NTT_REGIONS}
