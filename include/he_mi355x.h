@@ -122,6 +122,8 @@ typedef struct {
  * times (warm-up, arena sizing, recording).  Not while the kernel profile is
  * enabled (HE_EINVAL).  he_trim and he_keygen drop the recordings. */
 #define HE_MM_GRAPH 8u
+/* he_covariance only: the dataset is not centred (see he_covariance) */
+#define HE_COV_UNCENTRED 16u
 
 /* Create a context on the current HIP device.  `dev` may be NULL.  `seed`
  * keys every random draw of the context (Philox4x64-10 streams).
@@ -195,7 +197,14 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
 
 /* Block covariance of a centred dataset (Algorithm HCovMtrx): x holds
  * row_blocks * k ciphertexts, x[r*k + j] = block (row block r, feature block
- * j) of size d x d.  cov[a*k + b] receives block (a, b) of X^T X / n_samples. */
+ * j) of size d x d.  cov[a*k + b] receives block (a, b) of X^T X / n_samples.
+ * With HE_COV_UNCENTRED in opts->flags the dataset need not be centred
+ * (section 5.2): the means mu[j] = Aggregate(sum_r x[r*k + j]; 0) / n_samples
+ * (every row of the block holds its features' means) are computed
+ * homomorphically, and block (a, b) of mu^T mu (transposition of mu[a] times
+ * mu[b]) is subtracted after being brought to the level and scale of the
+ * X^T X blocks (drop, constant 1 at the scale ratio, rescale).  Needs the
+ * rotation keys d, 2d, .. < d^2 besides those of the covariance. */
 he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks, uint32_t k, uint32_t d,
                         uint64_t n_samples, const he_matmul_opts* opts, he_ct** cov);
 

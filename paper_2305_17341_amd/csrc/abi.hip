@@ -418,8 +418,11 @@ he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks,
     HeCtxImpl& c = ctx->impl;
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
     std::vector<HeCt> r =
-        c.covariance(xs, (int)row_blocks, (int)k, (int)d, n_samples, m.n1z, m.n1t, default_n1((int)d), m.npz, m.npt,
-                     m.lazy, m.fused);
+        (opts && (opts->flags & HE_COV_UNCENTRED))
+            ? c.covariance_uncentred(xs, (int)row_blocks, (int)k, (int)d, n_samples, m.n1z, m.n1t, default_n1((int)d),
+                                     m.npz, m.npt, m.lazy, m.fused)
+            : c.covariance(xs, (int)row_blocks, (int)k, (int)d, n_samples, m.n1z, m.n1t, default_n1((int)d), m.npz,
+                           m.npt, m.lazy, m.fused);
     hip_check(hipEventRecord(c.ev1, c.stream), "event");
     for (uint32_t i = 0; i < k * k; i++) cov[i] = wrap(ctx, std::move(r[i]));
   });

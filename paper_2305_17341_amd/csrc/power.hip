@@ -233,3 +233,35 @@ void HeCtxImpl::eigen_shift(std::vector<HeCt*>& cov, int k, int n, HeCt& lambda,
       out.push_back(C.sub_matched(*cov[r * k + cc], Tm));
     }
 }
+
+// Covariance of a dataset that is not centred (section 5.2, Algorithm
+// HCovMtrx): mu[j] = Aggregate(sum_r x[r k + j]; 0) times 1/s (the row-block
+// sums, the column sums spread to every row, the true sample count), mu[a]^T
+// by the transposition G, block (a, b) of mu^T mu = mu[a]^T (.) mu[b]
+// (relinearised, rescaled), brought to the level and scale of the X^T X / s
+// blocks and subtracted.  No operand reaches level 0 on this path: a refresh
+// request is an error.
+std::vector<HeCt> HeCtxImpl::covariance_uncentred(const std::vector<const HeCt*>& x, int rb, int k, int n,
+                                                  u64 n_samples, int n1z, int n1t, int n1g, int npz, int npt,
+                                                  bool lazy, bool fused_rs) {
+  if ((int)x.size() != rb * k || rb < 1 || k < 1) fail(HE_EINVAL, "block count mismatch");
+  std::vector<HeCt> xtx = covariance(x, rb, k, n, n_samples, n1z, n1t, n1g, npz, npt, lazy, fused_rs);
+  RefreshFn no_refresh = [](HeCt&) { fail(HE_ELEVEL, "not enough levels for the mean path"); };
+  Circuit C{*this, n, no_refresh};
+  std::vector<HeCt> mu(k), mut(k);
+  for (int j = 0; j < k; j++) {
+    HeCt S = ct_copy(*x[j]);
+    for (int r = 1; r < rb; r++) S = add(S, *x[r * k + j], false);
+    HeCt A = C.aggregate(std::move(S), 0);
+    mu[j] = C.pmul_const(A, 1.0 / (double)n_samples);
+    mut[j] = lintrans(mu[j], LT_TRANSPOSE, n, n1g, 1.0);
+  }
+  std::vector<HeCt> out;
+  for (int a = 0; a < k; a++)
+    for (int b = 0; b < k; b++) {
+      const HeCt& c = xtx[a * k + b];
+      HeCt mm = C.mul(mut[a], mu[b]);
+      out.push_back(add(c, C.match(mm, c.level, c.scale), true));
+    }
+  return out;
+}

@@ -172,6 +172,9 @@ struct HeCtxImpl {
   void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,
                                int n1t, int n1g, int npz, int npt, bool lazy = false, bool fused_rs = false);
+  // the same for a dataset that is not centred: X^T X / s - mu^T mu (section 5.2)
+  std::vector<HeCt> covariance_uncentred(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples,
+                                         int n1z, int n1t, int n1g, int npz, int npt, bool lazy, bool fused_rs);
 
   // PowerMethod (section 6.1) and the interactive refresh
   DevBuf decrypt_int(const HeCt& c);
