@@ -45,3 +45,41 @@ def test_means_and_uncentred_covariance(setup):
         assert np.max(np.abs(got - full[a * n:(a + 1) * n, b * n:(b + 1) * n])) < BOUND, i
     # the centred covariance is not X^T X / s: the mean path matters here
     assert np.max(np.abs(X.T @ X / s - cov_want)) > 0.1
+
+
+def test_padding_method_2_packs_and_unpacks():
+    """Method 2 (section 5.1): n - p valid features per block,
+    p = floor((k n - t) / k); every feature lands once and comes back."""
+    n = 8
+    for t in (11, 13, 16, 17, 23):
+        X = I.dataset(t, 5, t)
+        k = -(-t // n)
+        w = I.features_per_block(t, n, 2)
+        assert w == n - (k * n - t) // k and k * w >= t and w <= n
+        B = I.blocks(X, n, method=2)
+        assert B.shape == (1, k, n, n)
+        back = np.concatenate([B[0, j, :5, :w] for j in range(k)], axis=1)[:, :t]
+        assert np.array_equal(back, X)
+        M = I.dataset(t + 100, t, t)
+        Bm = [[np.zeros((n, n)) for _ in range(k)] for _ in range(k)]
+        for f in range(t):
+            for g in range(t):
+                Bm[f // w][g // w][f % w, g % w] = M[f, g]
+        assert np.array_equal(I.unblock_square(Bm, t, n, 2), M)
+
+
+def test_uncentred_covariance_padding_method_2(setup):
+    """The covariance circuit is unchanged by the packing: with method 2 the
+    decrypted blocks, unpacked, give the FP64 covariance."""
+    from oracle import centre
+    o, n = setup
+    X = I.dataset(10, 2 * n - 3, 13)
+    s, t = X.shape
+    k, rb = -(-t // n), 2
+    blk = I.blocks(X, n, method=2)
+    cts = [o.encrypt(blk[r, j].ravel(), nonce=80 + r * k + j) for r in range(rb) for j in range(k)]
+    cov = centre.HeCentre(o, n).covariance(cts, rb, k, s, 4, 4, 4, lazy=True)
+    B = [[o.decrypt(cov[a * k + b])[: n * n].reshape(n, n) for b in range(k)] for a in range(k)]
+    got = I.unblock_square(B, t, n, method=2)
+    _, want = centre.fp64_mean_and_cov(X)
+    assert np.max(np.abs(got - want)) < BOUND
