@@ -186,6 +186,12 @@ he_status he_pmult_slots(he_ctx* ctx, const he_ct* a, const double* z, size_t n,
  * 2 = transposition (G); `weight` multiplies every diagonal (1.0 = plain). */
 he_status he_lintrans(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, double weight,
                       he_ct** out);
+/* Z (kind 0) or T (kind 1) decomposed by diagonal convergence (section 4.2,
+ * Algorithms DCDforZ / DCDforT) when 0 < nprime < d - 1, as the product's
+ * sides apply them: ceil((d - 1) / nprime) levels consumed (1 without
+ * decomposition).  Keys: he_lintrans_rot_steps(kind, d, n1, nprime). */
+he_status he_lintrans_dcd(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, uint32_t nprime,
+                          he_ct** out);
 
 /* The homomorphic d x d product (Eq. 4, Algorithm DMatrixMult): a and b at
  * the same level l >= 3 (more with decomposition); result at level l - 3. */

@@ -1540,6 +1540,17 @@ static void col_mask(int n, int k, int second, double *out) {
  * B_0 = Z a and B'_0 = Rot(Z a, -n); for k = b n1z + r:
  *   A_k = Rescale(ModDown(m_k (.) HR(B_b, r) + m'_k (.) HR(B'_b, r))). */
 /* (fused: one rounding by P q_l in place of ModDown then Rescale) */
+/* Z (kind 0) or T (kind 1) of a d x d matrix ciphertext, decomposed (section
+ * 4.2) when 0 < nprime < n - 1: the transform alone, as the product's sides
+ * start with it */
+oc_ct *oc_lt_dcd(const oc_ctx *c, const oc_ct *x, int kind, int n, int n1, int nprime, int *err) {
+  *err = 0;
+  if (kind == 0) return sigma_dcd(c, x, n, n1, nprime, err);
+  if (kind == 1) return tau_dcd(c, x, n, n1, nprime, err);
+  *err = -1;
+  return NULL;
+}
+
 static oc_ct **side_a(const oc_ctx *c, const oc_ct *ca, int n, int n1z, int npz, int fused, int *err) {
   u64 N = c->N;
   int n2sq = n * n;

@@ -117,6 +117,8 @@ def lib():
             f = getattr(L, name)
             f.restype = C.c_void_p
             f.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, intp]
+        L.oc_lt_dcd.restype = C.c_void_p
+        L.oc_lt_dcd.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, intp]
         L.oc_lt_transpose.restype = C.c_void_p
         L.oc_lt_transpose.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double, intp]
         L.oc_matmul.restype = C.c_void_p
@@ -384,6 +386,10 @@ class Oracle:
 
     def lt_tau(self, a, n, n1):
         return self._lt(lib().oc_lt_tau, a.ptr, n, n1)
+
+    def lt_dcd(self, a, kind, n, n1, nprime):
+        """Z (kind 0) or T (kind 1), decomposed when 0 < nprime < n - 1"""
+        return self._lt(lib().oc_lt_dcd, a.ptr, kind, n, n1, nprime)
 
     def lt_transpose(self, a, n, n1, weight=1.0):
         return self._lt(lib().oc_lt_transpose, a.ptr, n, n1, weight)

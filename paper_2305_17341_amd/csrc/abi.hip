@@ -321,6 +321,20 @@ he_status he_lintrans(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, ui
   });
 }
 
+he_status he_lintrans_dcd(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, uint32_t nprime,
+                          he_ct** out) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    check_ct(ctx, a);
+    need(out != nullptr && kind <= 1 && d >= 2, "bad transform");
+    const int n = (int)d, b1 = n1 ? (int)n1 : default_n1(n);
+    need(n % b1 == 0, "baby-step count must divide d");
+    const int np = (nprime == 0 || (int)nprime > n - 1) ? n - 1 : (int)nprime;
+    HeCtxImpl& c = ctx->impl;
+    *out = wrap(ctx, kind == 0 ? c.sigma_dcd(a->ct, n, b1, np) : c.tau_dcd(a->ct, n, b1, np));
+  });
+}
+
 he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, const he_matmul_opts* opts,
                     he_ct** out) {
   return guard([&] {

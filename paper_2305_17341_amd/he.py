@@ -23,7 +23,7 @@ EXPORTS = [
     "he_ctx_create", "he_ctx_destroy", "he_ctx_moduli", "he_keygen", "he_matmul_rot_steps",
     "he_transpose_rot_steps", "he_encode", "he_encrypt_slots", "he_encrypt_matrix", "he_decrypt", "he_ct_info",
     "he_ct_export", "he_ct_import", "he_ct_free", "he_add", "he_sub", "he_mult", "he_rescale", "he_rotate",
-    "he_drop_level", "he_pmult_slots", "he_lintrans", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
+    "he_drop_level", "he_pmult_slots", "he_lintrans", "he_lintrans_dcd", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
     "he_mem_info", "he_trim", "he_device_memory", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
     "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_refresh",
     "he_power_rot_steps", "he_power_step", "he_eigen_shift", "he_knob_set", "he_knob_get", "he_last_error",
@@ -91,6 +91,7 @@ def load():
         "he_drop_level": [vp, vp, C.c_uint32, C.POINTER(vp)],
         "he_pmult_slots": [vp, vp, dblp, C.c_size_t, C.c_double, C.POINTER(vp)],
         "he_lintrans": [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, C.POINTER(vp)],
+        "he_lintrans_dcd": [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(vp)],
         "he_matmul": [vp, vp, vp, C.c_uint32, C.POINTER(he_matmul_opts), C.POINTER(vp)],
         "he_matmul_batch": [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_uint32), C.c_size_t,
                             C.POINTER(he_matmul_opts), C.POINTER(vp)],
@@ -292,6 +293,11 @@ class Context:
     def lintrans(self, a, kind, d, n1=0, weight=1.0):
         k = {"sigma": 0, "tau": 1, "transpose": 2}[kind] if isinstance(kind, str) else kind
         return self._ct(load().he_lintrans, a.ptr, k, d, n1, weight)
+
+    def lintrans_dcd(self, a, kind, d, n1=0, nprime=0):
+        """Z (kind 0 / "sigma") or T (1 / "tau"), decomposed when 0 < nprime < d - 1"""
+        k = {"sigma": 0, "tau": 1}[kind] if isinstance(kind, str) else kind
+        return self._ct(load().he_lintrans_dcd, a.ptr, k, d, n1, nprime)
 
     def matmul(self, a, b, d, opts=None):
         return self._ct(load().he_matmul, a.ptr, b.ptr, d, _opts(opts))

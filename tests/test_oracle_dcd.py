@@ -150,3 +150,19 @@ def test_covariance_decrypts_to_fp64(deep):
             assert ct.level == DEEP.top_level - 5
             got = deep.decrypt(ct)[: n * n].reshape(n, n)
             assert np.max(np.abs(got - want[a * n:(a + 1) * n, b * n:(b + 1) * n])) < 2.0**-15
+
+
+@pytest.mark.parametrize("kind,nprime", [(0, 4), (0, 15), (1, 4), (1, 15)])
+def test_dcd_transform_decrypts_to_permutation(deep, kind, nprime):
+    """Z alone: entry (i, j) reads A[i, i + j]; T alone: entry (i, j) reads
+    A[i + j, j] (indices mod n), each by a single BSGS (n' = n - 1, one level)
+    or by ceil((n - 1) / n') factors (one level each)"""
+    n = 16
+    A = I.uniform_matrix(9, n)
+    want = np.empty(n * n)
+    for i in range(n):
+        for j in range(n):
+            want[i * n + j] = A[i, (i + j) % n] if kind == 0 else A[(i + j) % n, j]
+    r = deep.lt_dcd(deep.encrypt(A.ravel(), nonce=4), kind, n, 4, nprime)
+    assert r.level == DEEP.top_level - math.ceil(15 / nprime)
+    assert np.max(np.abs(deep.decrypt(r)[: n * n] - want)) < 2.0**-15
