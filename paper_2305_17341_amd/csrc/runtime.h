@@ -93,6 +93,13 @@ struct HeCtxImpl {
   bool have_sk = false;
   std::map<u64, DevBuf> keys;             // Galois element -> key; 0 = relinearisation
   std::map<std::string, DevBuf> ptcache;
+  // a transform's diagonals present (giant, baby step) and their plaintexts
+  // (entries of ptcache, kept for the context's life)
+  struct LtPlan {
+    std::vector<std::pair<int, int>> ij;
+    std::vector<const u64*> pts;
+  };
+  std::map<std::string, LtPlan> ltplans;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0;
   long n_decompose = 0, n_multsum = 0, n_moddown = 0;
@@ -148,8 +155,11 @@ struct HeCtxImpl {
   HeCt stack(const std::vector<const HeCt*>& xs);
   std::vector<HeCt> unstack(const HeCt& x);
 
-  std::vector<const u64*> plaintexts(const std::vector<std::string>& keys, const std::vector<std::vector<double>>& vecs,
-                                     int n2, int level, bool qp, double scale);
+  // encoded plaintexts by key, cached; gen(i, v) gives the slot vector of
+  // keys[i] (called only for keys not cached yet)
+  using PtGen = std::function<void(size_t, std::vector<double>&)>;
+  std::vector<const u64*> plaintexts(const std::vector<std::string>& keys, const PtGen& gen, int n2, int level,
+                                     bool qp, double scale);
   HeCt lintrans(const HeCt& x, int kind, int n, int n1, double weight);
   HeCt lintrans_perm(const HeCt& x, const std::vector<int>& perm, const LtGeom& G, double weight,
                      const std::string& tag);

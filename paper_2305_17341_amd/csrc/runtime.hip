@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <set>
+#include <unordered_map>
 
 extern "C" void he_host_dd_tables(int logN, double* fft_tw, double* zeta);
 
@@ -135,6 +136,7 @@ static u32 brv_host(u32 x, int bits) {
 HeCtxImpl::~HeCtxImpl() {
   if (stream) (void)hipStreamSynchronize(stream);
   graphs.clear();
+  ltplans.clear();
   ptcache.clear();
   keys.clear();
   s_ntt.release();
@@ -890,9 +892,8 @@ std::vector<HeCt> HeCtxImpl::unstack(const HeCt& x) {
 // ---------------------------------------------------------------------------
 // ensure every vector in `vecs` (each of length n2) has an evaluation-domain
 // plaintext over Q_level (+P if qp) under cache key keys[i]; returns pointers
-std::vector<const u64*> HeCtxImpl::plaintexts(const std::vector<std::string>& keys_,
-                                              const std::vector<std::vector<double>>& vecs, int n2, int level,
-                                              bool qp, double scale) {
+std::vector<const u64*> HeCtxImpl::plaintexts(const std::vector<std::string>& keys_, const PtGen& gen, int n2,
+                                              int level, bool qp, double scale) {
   std::vector<const u64*> out(keys_.size(), nullptr);
   std::vector<int> missing;
   char suffix[96];
@@ -908,9 +909,12 @@ std::vector<const u64*> HeCtxImpl::plaintexts(const std::vector<std::string>& ke
   const int chunk = std::max(1, (int)std::min<u64>(256, (1ull << 26) / N));
   for (size_t s0 = 0; s0 < missing.size(); s0 += chunk) {
     int b = (int)std::min(missing.size() - s0, (size_t)chunk);
-    std::vector<double> host((size_t)b * n2);
-    for (int t = 0; t < b; t++) std::copy(vecs[missing[s0 + t]].begin(), vecs[missing[s0 + t]].end(),
-                                          host.begin() + (size_t)t * n2);
+    std::vector<double> host((size_t)b * n2), v;
+    for (int t = 0; t < b; t++) {
+      gen(missing[s0 + t], v);
+      if ((int)v.size() != n2) fail(HE_EINVAL, "plaintext vector of the wrong length");
+      std::copy(v.begin(), v.end(), host.begin() + (size_t)t * n2);
+    }
     DevBuf ints = encode_batch(host.data(), n2, b, scale);
     for (int t = 0; t < b; t++) {
       int i = missing[s0 + t];
@@ -942,19 +946,25 @@ std::vector<int> make_perm(int kind, int n) {
 static long pmod_l(long a, long m) { return ((a % m) + m) % m; }
 
 // diagonal l of the (weighted) permutation, pre-rotated right by `shift`
-static bool diag_vec(const std::vector<int>& perm, long l, long shift, double w, std::vector<double>& out) {
-  long n2 = (long)perm.size();
+// the 1-entries of a permutation grouped by diagonal: diagonal l (mod n^2)
+// holds the positions s with perm[s] - s = l
+using DiagGroups = std::unordered_map<long, std::vector<int>>;
+static DiagGroups diag_groups(const std::vector<int>& perm) {
+  const long n2 = (long)perm.size();
+  DiagGroups g;
+  for (long s = 0; s < n2; s++)
+    if (perm[s] >= 0) g[pmod_l((long)perm[s] - s, n2)].push_back((int)s);
+  return g;
+}
+
+// diagonal l of the permutation matrix rotated by `shift` slots, times w;
+// false when that diagonal is empty
+static bool diag_vec(const DiagGroups& groups, long n2, long l, long shift, double w, std::vector<double>& out) {
+  auto it = groups.find(pmod_l(l, n2));
+  if (it == groups.end()) return false;
   out.assign(n2, 0.0);
-  bool nz = false;
-  long lm = pmod_l(l, n2);
-  for (long t = 0; t < n2; t++) {
-    long s = pmod_l(t - shift, n2);
-    if (perm[s] >= 0 && pmod_l((long)perm[s] - s, n2) == lm) {
-      out[t] = w;
-      nz = true;
-    }
-  }
-  return nz;
+  for (int s : it->second) out[pmod_l(s + shift, n2)] = w;
+  return true;
 }
 
 static int ceil_div_i(int a, int b) { return (a + b - 1) / b; }
@@ -979,12 +989,13 @@ HeCt HeCtxImpl::lintrans(const HeCt& x, int kind, int n, int n1, double weight) 
 
 // rotation steps a double-hoisted BSGS over `perm` with geometry G performs
 void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& out) {
-  std::vector<double> v;
+  const DiagGroups groups = diag_groups(perm);
+  const long n2 = (long)perm.size();
   for (int i = G.i_lo; i < G.i_hi; i++) {
     bool any = false;
     for (int j = 0; j < G.n1; j++) {
       long l = (long)G.a * ((long)G.n1 * i + j);
-      if (!diag_vec(perm, l, 0, 1.0, v)) continue;
+      if (!groups.count(pmod_l(l, n2))) continue;
       any = true;
       if (j) out.insert((long)G.a * j);
     }
@@ -1000,26 +1011,37 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
   const int n2sq = (int)perm.size();
   const int level = x.level;
   const int nqp = nqp_of(level);
-  // diagonals actually present
-  std::vector<std::string> keys_;
-  std::vector<std::vector<double>> vecs;
-  std::vector<std::pair<int, int>> ij;
-  std::vector<double> v;
-  for (int i = G.i_lo; i < G.i_hi; i++)
-    for (int j = 0; j < n1; j++) {
-      long l = (long)G.a * ((long)n1 * i + j);
-      if (!diag_vec(perm, l, (long)G.a * n1 * i, weight, v)) continue;
-      char key[160];
-      snprintf(key, sizeof key, "%s|a%ld|n1_%d|i%d|j%d|w%.17g", tag.c_str(), (long)G.a, n1, i, j, weight);
-      keys_.push_back(key);
-      vecs.push_back(v);
-      ij.push_back({i, j});
-    }
-  if (ij.empty()) fail(HE_EINVAL, "transform has no nonzero diagonal");
   // diagonals encoded at scale q_l: the closing rescale by q_l gives back
   // exactly the input scale
   const double ql = (double)mods[level];
-  std::vector<const u64*> pts = plaintexts(keys_, vecs, n2sq, level, true, ql);
+  // the diagonals present and their plaintexts, found once per transform,
+  // geometry, weight and level
+  char plan_key[256];
+  snprintf(plan_key, sizeof plan_key, "%s|a%ld|n1_%d|i%d..%d|w%.17g|L%d", tag.c_str(), (long)G.a, n1, G.i_lo,
+           G.i_hi, weight, level);
+  auto pit = ltplans.find(plan_key);
+  if (pit == ltplans.end()) {
+    const DiagGroups groups = diag_groups(perm);
+    std::vector<std::string> keys_;
+    std::vector<std::vector<double>> vecs;
+    LtPlan plan;
+    std::vector<double> v;
+    for (int i = G.i_lo; i < G.i_hi; i++)
+      for (int j = 0; j < n1; j++) {
+        long l = (long)G.a * ((long)n1 * i + j);
+        if (!diag_vec(groups, n2sq, l, (long)G.a * n1 * i, weight, v)) continue;
+        char key[160];
+        snprintf(key, sizeof key, "%s|a%ld|n1_%d|i%d|j%d|w%.17g", tag.c_str(), (long)G.a, n1, i, j, weight);
+        keys_.push_back(key);
+        vecs.push_back(v);
+        plan.ij.push_back({i, j});
+      }
+    if (plan.ij.empty()) fail(HE_EINVAL, "transform has no nonzero diagonal");
+    plan.pts = plaintexts(keys_, [&](size_t e, std::vector<double>& o) { o = vecs[e]; }, n2sq, level, true, ql);
+    pit = ltplans.emplace(plan_key, std::move(plan)).first;
+  }
+  const std::vector<std::pair<int, int>>& ij = pit->second.ij;
+  const std::vector<const u64*>& pts = pit->second.pts;
   std::vector<bool> used(n1, false);
   for (auto& p : ij) used[p.second] = true;
   // Decompose once, baby-step hoisted rotations kept in R_{Q_l P}
@@ -1200,8 +1222,9 @@ std::vector<long> transpose_steps(int n, int n1) {
 }
 
 HeCt HeCtxImpl::apply_chain(const HeCt& x, const std::vector<DcdFactor>& fs, const std::string& tag) {
-  HeCt cur = ct_copy(x);
-  for (size_t j = 0; j < fs.size(); j++) cur = lintrans_perm(cur, fs[j].perm, fs[j].G, 1.0, tag + "|f" + std::to_string(j));
+  if (fs.empty()) return ct_copy(x);
+  HeCt cur = lintrans_perm(x, fs[0].perm, fs[0].G, 1.0, tag + "|f0");
+  for (size_t j = 1; j < fs.size(); j++) cur = lintrans_perm(cur, fs[j].perm, fs[j].G, 1.0, tag + "|f" + std::to_string(j));
   return cur;
 }
 
@@ -1243,21 +1266,21 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
   const int nqp = nqp_of(lvl);
   LimbMap qpm = qpmap(lvl);
   std::vector<std::string> keys_;
-  std::vector<std::vector<double>> vecs;
-  std::vector<double> v;
+  std::vector<std::pair<int, int>> which;
   for (int k = 0; k < n; k++) {
     for (int second = 0; second < 2; second++) {
       if (second && k == 0) continue;
       char key[64];
       snprintf(key, sizeof key, "colmask|n%d|k%d|%d", n, k, second);
-      col_mask(n, k, second, v);
       keys_.push_back(key);
-      vecs.push_back(v);
+      which.push_back({k, second});
     }
   }
   // masks encoded at scale q_lvl: each rescale restores the base's scale
   const double ql = (double)mods[lvl];
-  std::vector<const u64*> masks = plaintexts(keys_, vecs, n * n, lvl, true, ql);
+  std::vector<const u64*> masks = plaintexts(
+      keys_, [&](size_t e, std::vector<double>& o) { col_mask(n, which[e].first, which[e].second != 0, o); }, n * n,
+      lvl, true, ql);
   auto mask_of = [&](int k, int second) { return masks[k == 0 ? 0 : 2 * k - 1 + second]; };
   std::vector<HeCt> Ak(n);
   HeCt Bb = ct_copy(A0), Bpb = rotate(A0, -(long)n);

@@ -9,7 +9,8 @@ that makes it end at the baseline level 10 (14 - 4).
 Per row: the rotation keys the transform needs (MinRotKeys) and the HBM
 bytes of those keys plus the relinearisation key (as the table's Rtk column
 counts), the hoisted-ciphertext space of the BSGS (n1 - 1 elements of
-R_{Q_l P} at the start level, the quantity the paper's Ct column models) and
+R_{Q_l P} at the level of the last factor, one above the baseline: the
+factors before it have at most three diagonals and hoist at most two) and
 the measured device peak of the call, the time of one transform (median of
 `reps` after a warm-up) and of a batch of 8 stacked ciphertexts, the levels
 consumed, and the decrypted error against the plaintext permutation."""
@@ -80,7 +81,7 @@ def run(reps: int = 3, d: int = 128, chain=I.SERVE15, seed: int = 5, log=None):
             o = ctx.lintrans_dcd(c, kind, d, n1, nprime)
         ctx.sync()
         t8 = time.perf_counter() - t0
-        qp_ct = 2 * (start + 1 + alpha) * chain.N * 8
+        qp_ct = 2 * (BASELINE + 1 + 1 + alpha) * chain.N * 8
         row = {"scheme": "dh-BSGS" if nprime == 0 else "DCDmp", "matrix": matrix, "n1": n1,
                "max_diag": maxdiag if matrix == "Z" else f"{maxdiag}*{d}",
                # the table's Rtk column counts one key more than the rotations (the
