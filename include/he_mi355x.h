@@ -147,6 +147,13 @@ he_status he_matmul_rot_steps(const he_ctx* ctx, uint32_t d, const he_matmul_opt
  * (MinRotKeys of Tables 1 and 2). */
 he_status he_lintrans_rot_steps(uint32_t kind, uint32_t d, uint32_t n1, uint32_t nprime, int32_t* steps, size_t cap,
                                 size_t* n);
+/* Planner, no context or device needed: rotation steps of Z (kind 0) or T
+ * (kind 1) by double-hoisted BSGS with the simple key substitution of section
+ * 4.2.1 (see he_lintrans_smpkeysub): of the inner loop only the prefix a j',
+ * 0 < j' < n1p (a = 1 for Z, d for T); n1p = 0 or >= n1 gives the plain
+ * dh-BSGS steps; n1p = 1 is rejected (HE_EINVAL). */
+he_status he_smpkeysub_rot_steps(uint32_t kind, uint32_t d, uint32_t n1, uint32_t n1p, int32_t* steps, size_t cap,
+                                 size_t* n);
 /* rotation steps of the transposition (G) with baby-step count n1 (0 = default) */
 he_status he_transpose_rot_steps(const he_ctx* ctx, uint32_t d, uint32_t n1, int32_t* steps, size_t cap, size_t* n);
 
@@ -192,6 +199,16 @@ he_status he_lintrans(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, ui
  * decomposition).  Keys: he_lintrans_rot_steps(kind, d, n1, nprime). */
 he_status he_lintrans_dcd(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, uint32_t nprime,
                           he_ct** out);
+/* Z (kind 0) or T (kind 1) by double-hoisted BSGS with the simple key
+ * substitution of section 4.2.1, one level consumed: the baby steps
+ * a (b n1p + j'), j' < n1p, are hoisted in blocks from bases
+ * x_b = Rot(x_{b-1}, a n1p), each formed with the prefix keys alone (ModDown
+ * of HR(x_{b-1}, a (n1p - 1)), then a rotation by a), so only the keys of
+ * he_smpkeysub_rot_steps are needed.  2 <= n1p < n1 (n1 = 0: default);
+ * n1p = 0 or >= n1 is plain dh-BSGS; n1p = 1 gives HE_EINVAL; a missing key
+ * gives HE_EKEY.  `out` receives a new ciphertext owned by the caller. */
+he_status he_lintrans_smpkeysub(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, uint32_t n1p,
+                                he_ct** out);
 
 /* The homomorphic d x d product (Eq. 4, Algorithm DMatrixMult): a and b at
  * the same level l >= 3 (more with decomposition); result at level l - 3. */

@@ -1245,17 +1245,22 @@ void oc_counts_get(int *out5) {
 
 /* U m via double-hoisted BSGS with indices a (n1 i + j), j in [0, n1),
  * i in [i_lo, i_hi); diagonals encoded at scale pt_scale; one Rescale. */
+/* With 2 <= n1p < n1 the baby steps follow the simple key substitution of
+ * section 4.2.1: only the keys a j', 0 < j' < n1p, of the inner loop exist.
+ * The steps j = b n1p + j' are taken in blocks b, HR(x_b, a j') from the
+ * block's own Decompose, where x_0 = x and x_b = Rot(x_{b-1}, a n1p) is
+ * reached with those keys: ModDown(HR(x_{b-1}, a (n1p - 1))), then Rot by a. */
 static oc_ct *lintrans(const oc_ctx *c, const oc_ct *x, const lt_perm *U, i64 a, int n1, int i_lo,
-                       int i_hi, int *err) {
+                       int i_hi, int n1p, int *err) {
   u64 N = c->N;
   int level = x->level;
   if (level < 1) { *err = -2; return NULL; }
   /* diagonals encoded at scale q_l: the closing rescale by q_l gives back
    * exactly the input scale */
   double pt_scale = (double)c->mods[level];
-  /* Decompose once; baby-step hoisted rotations HR(x, a j), j in [0, n1) */
-  u64 *dig = oc_decompose(c, poly(c, x, 1, 0), level);
-  g_counts.decompose++;
+  int blk = (n1p >= 2 && n1p < n1) ? n1p : n1;
+  oc_ct *xb = NULL; /* base of the current block when b > 0 */
+  u64 *dig = NULL;
   oc_ct **baby = (oc_ct **)calloc(n1, sizeof(oc_ct *));
   double *vec = (double *)malloc(sizeof(double) * U->n2);
   i64 *m = (i64 *)malloc(sizeof(i64) * N);
@@ -1264,12 +1269,34 @@ static oc_ct *lintrans(const oc_ctx *c, const oc_ct *x, const lt_perm *U, i64 a,
   for (int i = i_lo; i < i_hi; i++)
     for (int j = 0; j < n1; j++)
       if (diag_vec(U, a * ((i64)n1 * i + j), a * (i64)n1 * i, vec)) used[j] = 1;
-  for (int j = 0; j < n1; j++) {
-    if (!used[j]) continue;
-    baby[j] = hoisted_rot(c, x, dig, oc_galois_of_step(c, a * j), err);
-    if (!baby[j]) goto fail;
-    if (j) g_counts.multsum++;
+  for (int b = 0; b * blk < n1; b++) {
+    const oc_ct *base = b == 0 ? x : xb;
+    int more = (b + 1) * blk < n1, jl = b * blk + blk - 1;
+    dig = oc_decompose(c, poly(c, base, 1, 0), level);
+    g_counts.decompose++;
+    for (int jp = 0; jp < blk && b * blk + jp < n1; jp++) {
+      int j = b * blk + jp;
+      if (!used[j] && !(more && j == jl)) continue;
+      baby[j] = hoisted_rot(c, base, dig, oc_galois_of_step(c, a * jp), err);
+      if (!baby[j]) goto fail;
+      if (jp) g_counts.multsum++;
+    }
+    free(dig);
+    dig = NULL;
+    if (more) {
+      oc_ct *y = oc_moddown(c, baby[jl]);
+      g_counts.moddown++;
+      if (!used[jl]) { oc_ct_free(baby[jl]); baby[jl] = NULL; }
+      oc_ct *nb = oc_rotate(c, y, a);
+      g_counts.decompose++; g_counts.multsum++; g_counts.moddown++;
+      oc_ct_free(y);
+      oc_ct_free(xb);
+      xb = nb;
+      if (!xb) { *err = -4; goto fail; }
+    }
   }
+  oc_ct_free(xb);
+  xb = NULL;
   oc_ct *acc = ct_new(c, level, 1, x->scale * pt_scale);
   for (int i = i_lo; i < i_hi; i++) {
     oc_ct *inner = NULL;
@@ -1311,6 +1338,7 @@ static oc_ct *lintrans(const oc_ctx *c, const oc_ct *x, const lt_perm *U, i64 a,
   return r;
 fail:
   for (int j = 0; j < n1; j++) oc_ct_free(baby[j]);
+  oc_ct_free(xb);
   free(baby); free(vec); free(m); free(dig); free(used);
   return NULL;
 }
@@ -1356,7 +1384,7 @@ oc_ct *oc_lt_sigma(const oc_ctx *c, const oc_ct *x, int n, int n1, int *err) {
   int *p = perm_sigma(n);
   lt_perm U = {n * n, p, NULL};
   int n2 = ceil_div(n, n1);
-  oc_ct *r = lintrans(c, x, &U, 1, n1, -n2, n2, err);
+  oc_ct *r = lintrans(c, x, &U, 1, n1, -n2, n2, 0, err);
   free(p);
   return r;
 }
@@ -1365,7 +1393,7 @@ oc_ct *oc_lt_tau(const oc_ctx *c, const oc_ct *x, int n, int n1, int *err) {
   int *p = perm_tau(n);
   lt_perm U = {n * n, p, NULL};
   int n2 = ceil_div(n, n1);
-  oc_ct *r = lintrans(c, x, &U, n, n1, 0, n2, err);
+  oc_ct *r = lintrans(c, x, &U, n, n1, 0, n2, 0, err);
   free(p);
   return r;
 }
@@ -1379,7 +1407,7 @@ oc_ct *oc_lt_transpose(const oc_ctx *c, const oc_ct *x, int n, int n1, double we
   }
   lt_perm U = {n * n, p, w};
   int n2 = ceil_div(n, n1);
-  oc_ct *r = lintrans(c, x, &U, n - 1, n1, -n2, n2, err);
+  oc_ct *r = lintrans(c, x, &U, n - 1, n1, -n2, n2, 0, err);
   free(p); free(w);
   return r;
 }
@@ -1487,7 +1515,7 @@ static oc_ct *apply_chain(const oc_ctx *c, const oc_ct *x, const oc_factor *f, i
   oc_ct *cur = oc_ct_copy(c, x);
   for (int j = 0; j < nf && cur; j++) {
     lt_perm U = {f[j].n2, f[j].perm, NULL};
-    oc_ct *nx = lintrans(c, cur, &U, f[j].a, f[j].n1, f[j].i_lo, f[j].i_hi, err);
+    oc_ct *nx = lintrans(c, cur, &U, f[j].a, f[j].n1, f[j].i_lo, f[j].i_hi, 0, err);
     oc_ct_free(cur);
     cur = nx;
   }
@@ -1543,6 +1571,19 @@ static void col_mask(int n, int k, int second, double *out) {
 /* Z (kind 0) or T (kind 1) of a d x d matrix ciphertext, decomposed (section
  * 4.2) when 0 < nprime < n - 1: the transform alone, as the product's sides
  * start with it */
+/* Z (kind 0) or T (kind 1) by dh-BSGS with the simple key substitution of
+ * the baby steps (section 4.2.1), prefix n1p */
+oc_ct *oc_lt_smpkeysub(const oc_ctx *c, const oc_ct *x, int kind, int n, int n1, int n1p, int *err) {
+  *err = 0;
+  if (kind < 0 || kind > 1 || n1p == 1) { *err = -1; return NULL; }
+  int *p = kind == 0 ? perm_sigma(n) : perm_tau(n);
+  lt_perm U = {n * n, p, NULL};
+  int n2 = ceil_div(n, n1);
+  oc_ct *r = kind == 0 ? lintrans(c, x, &U, 1, n1, -n2, n2, n1p, err) : lintrans(c, x, &U, n, n1, 0, n2, n1p, err);
+  free(p);
+  return r;
+}
+
 oc_ct *oc_lt_dcd(const oc_ctx *c, const oc_ct *x, int kind, int n, int n1, int nprime, int *err) {
   *err = 0;
   if (kind == 0) return sigma_dcd(c, x, n, n1, nprime, err);

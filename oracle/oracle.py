@@ -119,6 +119,8 @@ def lib():
             f.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, intp]
         L.oc_lt_dcd.restype = C.c_void_p
         L.oc_lt_dcd.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, intp]
+        L.oc_lt_smpkeysub.restype = C.c_void_p
+        L.oc_lt_smpkeysub.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, intp]
         L.oc_lt_transpose.restype = C.c_void_p
         L.oc_lt_transpose.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double, intp]
         L.oc_matmul.restype = C.c_void_p
@@ -390,6 +392,11 @@ class Oracle:
     def lt_dcd(self, a, kind, n, n1, nprime):
         """Z (kind 0) or T (kind 1), decomposed when 0 < nprime < n - 1"""
         return self._lt(lib().oc_lt_dcd, a.ptr, kind, n, n1, nprime)
+
+    def lt_smpkeysub(self, a, kind, n, n1, n1p):
+        """Z (kind 0) or T (kind 1) by dh-BSGS whose baby steps use only the keys
+        of the prefix a j', 0 < j' < n1p (simple key substitution, section 4.2.1)"""
+        return self._lt(lib().oc_lt_smpkeysub, a.ptr, kind, n, n1, n1p)
 
     def lt_transpose(self, a, n, n1, weight=1.0):
         return self._lt(lib().oc_lt_transpose, a.ptr, n, n1, weight)

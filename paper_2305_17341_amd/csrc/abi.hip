@@ -163,6 +163,21 @@ he_status he_lintrans_rot_steps(uint32_t kind, uint32_t d, uint32_t n1, uint32_t
   });
 }
 
+he_status he_smpkeysub_rot_steps(uint32_t kind, uint32_t d, uint32_t n1, uint32_t n1p, int32_t* steps, size_t cap,
+                                 size_t* n) {
+  return guard_host([&] {
+    need(kind <= 1 && d >= 2 && n1 >= 1 && d % n1 == 0 && n1p != 1, "bad arguments");
+    std::set<long> s;
+    bsgs_steps(make_perm((int)kind, (int)d), lt_geom((int)kind, (int)d, (int)n1), s, (int)n1p);
+    if (n) *n = s.size();
+    size_t i = 0;
+    for (long v : s) {
+      if (i < cap) steps[i] = (int32_t)v;
+      i++;
+    }
+  });
+}
+
 he_status he_transpose_rot_steps(const he_ctx* ctx, uint32_t d, uint32_t n1, int32_t* steps, size_t cap, size_t* n) {
   return guard([&] {
     auto lk = hold(ctx);
@@ -332,6 +347,18 @@ he_status he_lintrans_dcd(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d
     const int np = (nprime == 0 || (int)nprime > n - 1) ? n - 1 : (int)nprime;
     HeCtxImpl& c = ctx->impl;
     *out = wrap(ctx, kind == 0 ? c.sigma_dcd(a->ct, n, b1, np) : c.tau_dcd(a->ct, n, b1, np));
+  });
+}
+
+he_status he_lintrans_smpkeysub(he_ctx* ctx, const he_ct* a, uint32_t kind, uint32_t d, uint32_t n1, uint32_t n1p,
+                                he_ct** out) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    check_ct(ctx, a);
+    need(out != nullptr && kind <= 1 && d >= 2 && n1p != 1, "bad transform");
+    const int n = (int)d, b1 = n1 ? (int)n1 : default_n1(n);
+    need(n % b1 == 0, "baby-step count must divide d");
+    *out = wrap(ctx, ctx->impl.lintrans_smpkeysub(a->ct, (int)kind, n, b1, (int)n1p));
   });
 }
 

@@ -41,7 +41,7 @@ struct DcdFactor {
   LtGeom G;
 };
 std::vector<DcdFactor> dcd_chain(int n, const std::vector<int>& perm, int which, int nprime, int n1);
-void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& out);
+void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& out, int n1p = 0);
 void lintrans_steps(int kind, int n, int n1, int nprime, std::set<long>& s);
 std::vector<long> matmul_steps(int n, int n1z, int n1t, int npz, int npt);
 std::vector<long> transpose_steps(int n, int n1);
@@ -161,8 +161,11 @@ struct HeCtxImpl {
   std::vector<const u64*> plaintexts(const std::vector<std::string>& keys, const PtGen& gen, int n2, int level,
                                      bool qp, double scale);
   HeCt lintrans(const HeCt& x, int kind, int n, int n1, double weight);
+  // n1p: simple key substitution of the baby steps (section 4.2.1) when
+  // 2 <= n1p < G.n1, else plain double hoisting
   HeCt lintrans_perm(const HeCt& x, const std::vector<int>& perm, const LtGeom& G, double weight,
-                     const std::string& tag);
+                     const std::string& tag, int n1p = 0);
+  HeCt lintrans_smpkeysub(const HeCt& x, int kind, int n, int n1, int n1p);
   HeCt apply_chain(const HeCt& x, const std::vector<DcdFactor>& fs, const std::string& tag);
   HeCt sigma_dcd(const HeCt& x, int n, int n1, int nprime);
   HeCt tau_dcd(const HeCt& x, int n, int n1, int nprime);

@@ -987,24 +987,41 @@ HeCt HeCtxImpl::lintrans(const HeCt& x, int kind, int n, int n1, double weight) 
   return lintrans_perm(x, make_perm(kind, n), lt_geom(kind, n, n1), weight, tag);
 }
 
+// Z or T by double-hoisted BSGS with the simple key substitution of the
+// baby steps (section 4.2.1): only the keys a j', j' < n1p, of the inner loop
+HeCt HeCtxImpl::lintrans_smpkeysub(const HeCt& x, int kind, int n, int n1, int n1p) {
+  if ((u64)n * n > N / 2 || n1 < 1) fail(HE_EINVAL, "matrix does not fit the slots");
+  if (n1p == 1) fail(HE_EINVAL, "a prefix of one baby step holds no key to step with");
+  char tag[64];
+  snprintf(tag, sizeof tag, "lt%d|n%d", kind, n);
+  return lintrans_perm(x, make_perm(kind, n), lt_geom(kind, n, n1), 1.0, tag, n1p);
+}
+
 // rotation steps a double-hoisted BSGS over `perm` with geometry G performs
-void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& out) {
+// (with n1p as in lintrans_perm: baby steps from the prefix a j', j' < n1p)
+void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& out, int n1p) {
   const DiagGroups groups = diag_groups(perm);
   const long n2 = (long)perm.size();
+  const int m = (n1p >= 2 && n1p < G.n1) ? n1p : G.n1;
   for (int i = G.i_lo; i < G.i_hi; i++) {
     bool any = false;
     for (int j = 0; j < G.n1; j++) {
       long l = (long)G.a * ((long)G.n1 * i + j);
       if (!groups.count(pmod_l(l, n2))) continue;
       any = true;
-      if (j) out.insert((long)G.a * j);
+      if (j % m) out.insert((long)G.a * (j % m));
     }
     if (any && i) out.insert((long)G.a * G.n1 * i);
+  }
+  if (m < G.n1) {
+    // the blocks' bases: HR by a (m - 1), then Rot by a
+    out.insert((long)G.a * (m - 1));
+    out.insert((long)G.a);
   }
 }
 
 HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const LtGeom& G, double weight,
-                              const std::string& tag) {
+                              const std::string& tag, int n1p) {
   if (x.qp) fail(HE_EINVAL, "linear transform of an R_QP element");
   if (x.level < 1) fail(HE_ELEVEL, "linear transform needs one level");
   const int n1 = G.n1;
@@ -1044,21 +1061,38 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
   const std::vector<const u64*>& pts = pit->second.pts;
   std::vector<bool> used(n1, false);
   for (auto& p : ij) used[p.second] = true;
-  // Decompose once, baby-step hoisted rotations kept in R_{Q_l P}
-  DevBuf dig = decompose(x.poly(1), level, x.B);
+  // Decompose once, baby-step hoisted rotations kept in R_{Q_l P}.  With the
+  // simple key substitution (section 4.2.1, 2 <= n1p < n1) the baby steps
+  // a (b n1p + j') come in blocks of n1p, each hoisted from its own base
+  // x_b = Rot(x_{b-1}, a n1p) with the prefix keys a j' (j' < n1p): x_b is
+  // the ModDown of the block before's last hoisted rotation
+  // HR(x_{b-1}, a (n1p - 1)), rotated once more by a.
+  const int m = (n1p >= 2 && n1p < n1) ? n1p : n1;
   std::vector<HeCt> baby(n1);
-  {
+  HeCt xb;
+  for (int b = 0; b * m < n1; b++) {
+    const HeCt& base = b == 0 ? x : xb;
+    const bool more = (b + 1) * m < n1;
+    const int jl = b * m + m - 1;
     std::vector<u64> gs;
     std::vector<int> js;
-    for (int j = 0; j < n1; j++)
-      if (used[j]) {
-        gs.push_back(galois((long)G.a * j));
-        js.push_back(j);
+    for (int jp = 0; jp < m && b * m + jp < n1; jp++)
+      if (used[b * m + jp] || (more && jp == m - 1)) {
+        gs.push_back(galois((long)G.a * jp));
+        js.push_back(b * m + jp);
       }
-    std::vector<HeCt> hs = hoisted_multi(x, dig.p, gs);
-    for (size_t t = 0; t < js.size(); t++) baby[js[t]] = std::move(hs[t]);
+    {
+      DevBuf dig = decompose(base.poly(1), level, base.B);
+      std::vector<HeCt> hs = hoisted_multi(base, dig.p, gs);
+      for (size_t t = 0; t < js.size(); t++) baby[js[t]] = std::move(hs[t]);
+    }
+    if (more) {
+      HeCt y = moddown(baby[jl]);
+      if (!used[jl]) baby[jl] = HeCt();
+      xb = rotate(y, G.a);
+    }
   }
-  dig.release();
+  xb = HeCt();
   LimbMap qpm = qpmap(level);
   HeCt acc = ct_new(level, true, x.scale * ql, x.B);
   bool acc_set = false;

@@ -23,9 +23,9 @@ EXPORTS = [
     "he_ctx_create", "he_ctx_destroy", "he_ctx_moduli", "he_keygen", "he_matmul_rot_steps",
     "he_transpose_rot_steps", "he_encode", "he_encrypt_slots", "he_encrypt_matrix", "he_decrypt", "he_ct_info",
     "he_ct_export", "he_ct_import", "he_ct_free", "he_add", "he_sub", "he_mult", "he_rescale", "he_rotate",
-    "he_drop_level", "he_pmult_slots", "he_lintrans", "he_lintrans_dcd", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
+    "he_drop_level", "he_pmult_slots", "he_lintrans", "he_lintrans_dcd", "he_lintrans_smpkeysub", "he_matmul", "he_matmul_batch", "he_covariance", "he_sync",
     "he_mem_info", "he_trim", "he_device_memory", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
-    "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_refresh",
+    "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_smpkeysub_rot_steps", "he_refresh",
     "he_power_rot_steps", "he_power_step", "he_eigen_shift", "he_knob_set", "he_knob_get", "he_last_error",
 ]
 
@@ -92,6 +92,7 @@ def load():
         "he_pmult_slots": [vp, vp, dblp, C.c_size_t, C.c_double, C.POINTER(vp)],
         "he_lintrans": [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, C.POINTER(vp)],
         "he_lintrans_dcd": [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(vp)],
+        "he_lintrans_smpkeysub": [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(vp)],
         "he_matmul": [vp, vp, vp, C.c_uint32, C.POINTER(he_matmul_opts), C.POINTER(vp)],
         "he_matmul_batch": [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_uint32), C.c_size_t,
                             C.POINTER(he_matmul_opts), C.POINTER(vp)],
@@ -110,6 +111,8 @@ def load():
         "he_op_counts": [vp, u64p, u64p, u64p],
         "he_lintrans_rot_steps": [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32), C.c_size_t,
                                   C.POINTER(C.c_size_t)],
+        "he_smpkeysub_rot_steps": [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32),
+                                   C.c_size_t, C.POINTER(C.c_size_t)],
         "he_refresh": [vp, vp, C.c_uint64],
         "he_knob_set": [C.c_char_p, C.c_int32],
         "he_knob_get": [C.c_char_p, C.POINTER(C.c_int32)],
@@ -299,6 +302,12 @@ class Context:
         k = {"sigma": 0, "tau": 1}[kind] if isinstance(kind, str) else kind
         return self._ct(load().he_lintrans_dcd, a.ptr, k, d, n1, nprime)
 
+    def lintrans_smpkeysub(self, a, kind, d, n1=0, n1p=0):
+        """Z or T by dh-BSGS with the simple key substitution of the baby steps
+        (keys of the prefix a j', j' < n1p, only)"""
+        k = {"sigma": 0, "tau": 1}[kind] if isinstance(kind, str) else kind
+        return self._ct(load().he_lintrans_smpkeysub, a.ptr, k, d, n1, n1p)
+
     def matmul(self, a, b, d, opts=None):
         return self._ct(load().he_matmul, a.ptr, b.ptr, d, _opts(opts))
 
@@ -406,6 +415,16 @@ def lintrans_rot_steps(kind, d, n1, nprime=0):
     n = C.c_size_t()
     buf = (C.c_int32 * 8192)()
     _check(load().he_lintrans_rot_steps(k, d, n1, nprime, buf, 8192, C.byref(n)))
+    return [int(buf[i]) for i in range(n.value)]
+
+
+def smpkeysub_rot_steps(kind, d, n1, n1p):
+    """Planner (host only): rotation steps of Z or T with the simple key
+    substitution of the baby steps (prefix n1p)."""
+    k = {"Z": 0, "T": 1}[kind]
+    n = C.c_size_t()
+    buf = (C.c_int32 * 8192)()
+    _check(load().he_smpkeysub_rot_steps(k, d, n1, n1p, buf, 8192, C.byref(n)))
     return [int(buf[i]) for i in range(n.value)]
 
 

@@ -166,3 +166,27 @@ def test_dcd_transform_decrypts_to_permutation(deep, kind, nprime):
     r = deep.lt_dcd(deep.encrypt(A.ravel(), nonce=4), kind, n, 4, nprime)
     assert r.level == DEEP.top_level - math.ceil(15 / nprime)
     assert np.max(np.abs(deep.decrypt(r)[: n * n] - want)) < 2.0**-15
+
+
+@pytest.mark.parametrize("kind,n1,n1p", [(0, 4, 2), (0, 8, 3), (1, 4, 2), (1, 8, 4)])
+def test_smpkeysub_transform_with_prefix_keys_only(oracle_mod, kind, n1, n1p):
+    """Simple key substitution (section 4.2.1): with keys only for the baby-step
+    prefix a j', 0 < j' < n1', and the giant steps (Table 2's MinRotKeys), Z
+    and T still decrypt to their permutations, consuming one level"""
+    n = 16
+    n2 = n // n1
+    if kind == 0:
+        steps = set(range(1, n1p)) | {n1 * i for i in range(-n2, n2) if i}
+    else:
+        steps = {n * j for j in range(1, n1p)} | {n * n1 * i for i in range(1, n2)}
+    assert len(steps) == (n1p + 2 * n2 - 2 if kind == 0 else n1p + n2 - 2)
+    o = oracle_mod.Oracle(DEEP.log_n, DEEP.q_bits, DEEP.p_bits, seed=29)
+    o.keygen(rot_steps=sorted(steps), relin=False)
+    A = I.uniform_matrix(10, n)
+    want = np.empty(n * n)
+    for i in range(n):
+        for j in range(n):
+            want[i * n + j] = A[i, (i + j) % n] if kind == 0 else A[(i + j) % n, j]
+    r = o.lt_smpkeysub(o.encrypt(A.ravel(), nonce=5), kind, n, n1, n1p)
+    assert r.level == DEEP.top_level - 1
+    assert np.max(np.abs(o.decrypt(r)[: n * n] - want)) < 2.0**-15

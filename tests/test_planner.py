@@ -47,3 +47,22 @@ def test_planner_matches_oracle_factor_keys(he, oracle_mod):
             want = transform_keys(oracle_mod, m, n, n1, nprime)
             got = set(he.lintrans_rot_steps(m, n, n1, 0 if nprime >= n - 1 else nprime))
             assert got == want, (n, n1, nprime, m)
+
+
+@pytest.mark.parametrize("n,n1,n1p", [(16, 4, 2), (64, 8, 4), (128, 8, 2), (128, 16, 4), (128, 16, 8),
+                                      (256, 16, 4)])
+def test_smpkeysub_key_counts_are_table2(he, n, n1, n1p):
+    """Table 2, SmpKeySub rows: MinRotKeys n1' + 2 n2 - 2 for Z and n1' + n2 - 2
+    for T; the baby-step keys are exactly the prefix a j', 0 < j' < n1'"""
+    n2 = n // n1
+    z = he.smpkeysub_rot_steps("Z", n, n1, n1p)
+    t = he.smpkeysub_rot_steps("T", n, n1, n1p)
+    assert len(z) == n1p + 2 * n2 - 2
+    assert len(t) == n1p + n2 - 2
+    assert {s for s in z if abs(s) < n1} == set(range(1, n1p))
+    assert {s for s in t if s % (n * n1)} == {n * j for j in range(1, n1p)}
+    # the giant steps are those of plain dh-BSGS
+    assert {s for s in z if abs(s) >= n1} == {s for s in he.lintrans_rot_steps("Z", n, n1) if abs(s) >= n1}
+    # no prefix (n1' = 0 or n1' >= n1): plain dh-BSGS
+    assert he.smpkeysub_rot_steps("Z", n, n1, 0) == he.lintrans_rot_steps("Z", n, n1)
+    assert he.smpkeysub_rot_steps("T", n, n1, n1) == he.lintrans_rot_steps("T", n, n1)
