@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving run (0: skip it)")
     ap.add_argument("--pca-components", type=int, default=8, help="components of the PCA run (0: skip it)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the PPPCA accuracy runs (R2(X), R2(V) on synthetic stand-ins)")
     ap.add_argument("--table3-reps", type=int, default=3,
                     help="repetitions per row of the Z/T decomposition table at N=2^15 (0: skip it)")
     ap.add_argument("--calib-copies", type=int, default=0,
@@ -348,6 +350,10 @@ def main():
         from paper_2305_17341_amd import pca
         log("[bench] PCA run ...")
         result["pca"] = pca.pca_bench(l_e=args.pca_components, log=log)
+    if not args.no_accuracy:
+        from paper_2305_17341_amd import pca
+        log("[bench] PPPCA accuracy runs ...")
+        result["pca_accuracy"] = pca.accuracy_bench(log=log)
     if args.table3_reps > 0:
         from paper_2305_17341_amd import table3
         log("[bench] Z/T decomposition table ...")

@@ -73,10 +73,11 @@ def power_method(ctx, cov, k, d, V0, axis, taus, x0, refresher):
     return ctx.power_step(cov, k, d, V, axis, 0, x0, True, refresher)
 
 
-def pppca(ctx, cov, k, d, l_e, l_p, seed=0, B2=2.0 ** 16, nonce0=1 << 40, on_component=None):
+def pppca(ctx, cov, k, d, l_e, l_p, seed=0, B2=2.0 ** 16, nonce0=1 << 40, on_component=None, start_nonce=1 << 50):
     """Algorithm Privacy-Preserving PCA from an encrypted covariance: l_E
     (eigenvalue, eigenvector) pairs by PowerMethod and EigenShift.  The
-    random unit start vectors are encrypted by the client (axis 1)."""
+    random unit start vectors are encrypted by the client (axis 1, nonces
+    from start_nonce; refreshes take theirs from nonce0)."""
     refresher = he.Refresher(ctx, nonce0)
     taus = lazy_schedule(l_p, B2=B2)
     x0 = taylor_point(B2)
@@ -85,7 +86,7 @@ def pppca(ctx, cov, k, d, l_e, l_p, seed=0, B2=2.0 ** 16, nonce0=1 << 40, on_com
     for m in range(l_e):
         v0 = g.standard_normal(k * d)
         v0 /= np.linalg.norm(v0)
-        V0 = [ctx.encrypt_matrix(b, nonce=(1 << 50) + m * k + i) for i, b in enumerate(replicate(v0, k, d, 1))]
+        V0 = [ctx.encrypt_matrix(b, nonce=start_nonce + m * k + i) for i, b in enumerate(replicate(v0, k, d, 1))]
         t0 = time.perf_counter()
         V, axis, lam, VT = power_method(ctx, cov, k, d, V0, 1, taus, x0, refresher)
         cov = ctx.eigen_shift(cov, k, d, lam, V, VT, axis, refresher)
@@ -94,6 +95,124 @@ def pppca(ctx, cov, k, d, l_e, l_p, seed=0, B2=2.0 ** 16, nonce0=1 << 40, on_com
         if on_component is not None:
             on_component(m, time.perf_counter() - t0)
     return out, refresher.count
+
+
+def fp64_replay(cov, l_e, l_p, seed=0, B2=2.0 ** 16):
+    """Client-side reference: the same PowerMethod rounds, Newton counts,
+    start vectors and eigen-shifts as pppca, in FP64 on the plaintext
+    covariance.  Returns the eigenvalues and the (unit-length) vectors."""
+    taus = lazy_schedule(l_p, B2=B2)
+    x0 = taylor_point(B2)
+    g = np.random.default_rng(seed)
+    shifted = np.array(cov, dtype=np.float64)
+    lams, vecs = [], []
+    for _ in range(l_e):
+        v = g.standard_normal(shifted.shape[0])
+        v /= np.linalg.norm(v)
+        for tau in taus:
+            y = shifted @ v
+            x = float(y @ y)
+            s = 1.5 * x0 ** -0.5 - 0.5 * x0 ** -1.5 * x
+            for _ in range(tau):
+                s = s * (1.5 + (-0.5 * x) * (s * s))
+            v = y * s
+        lam = float((shifted @ v) @ v)
+        shifted = shifted - lam * np.outer(v, v)
+        lams.append(lam)
+        vecs.append(v)
+    return np.array(lams), np.stack(vecs, axis=1)
+
+
+# Accuracy metrics of section 7.2 (client side, on decrypted results)
+def r2_score(y_true, y_pred):
+    """Coefficient of determination of every column, 1 - (residual sum of
+    squares) / (sum of squares about the column's mean), averaged over the
+    columns with equal weights"""
+    y_true = np.asarray(y_true, dtype=np.float64)
+    y_pred = np.asarray(y_pred, dtype=np.float64)
+    if y_true.ndim == 1:
+        y_true, y_pred = y_true[:, None], y_pred[:, None]
+    ss_res = np.sum((y_true - y_pred) ** 2, axis=0)
+    ss_tot = np.sum((y_true - y_true.mean(axis=0)) ** 2, axis=0)
+    return float(np.mean(1.0 - ss_res / ss_tot))
+
+
+def r2_x(X, V):
+    """R2(X): the dataset against its reconstruction from the components
+    (columns of V, used as they are): mu + (X - mu) V V^T"""
+    X = np.asarray(X, dtype=np.float64)
+    mu = X.mean(axis=0, keepdims=True)
+    return r2_score(X, mu + (X - mu) @ V @ V.T)
+
+
+def r2_v(U, V):
+    """R2(V): computed components (columns of V) against reference
+    eigenvectors (columns of U), each computed vector first given the sign of
+    its reference (an eigenvector is defined up to sign)"""
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    sign = np.where(np.sum(U * V, axis=0) < 0, -1.0, 1.0)
+    return r2_score(U, V * sign)
+
+
+# Synthetic stand-ins for the accuracy table's rows (section 7.2): 16 x 16
+# pixel-like features in [0, 1] (t = 256) with a planted spectrum; s samples,
+# l_E components, l_P normalising rounds.
+ACCURACY_CASES = [("s200_lE4_lP4", 200, 4, 4), ("s200_lE4_lP14", 200, 4, 14), ("s165_lE6_lP14", 165, 6, 14)]
+
+
+def accuracy_bench(cases=None, seed=7, log=print, ctx=None):
+    """The whole PPPCA pipeline from a raw (uncentred) dataset: homomorphic
+    means and covariance (HE_COV_UNCENTRED), then PowerMethod and EigenShift;
+    R2(X) and R2(V) of the decrypted components against numpy's eigenvectors
+    of the FP64 covariance, beside the same metrics for the FP64 replay of the
+    same algorithm and for exact PCA (the R2(X) ceiling)."""
+    from . import inputs as I
+    cases = ACCURACY_CASES if cases is None else cases
+    n, k, t = 128, 2, 256
+    own = ctx is None
+    if own:
+        ctx = he.chain_context(I.LARGE, seed=seed)
+        steps = set(ctx.matmul_rot_steps(n)) | set(ctx.transpose_rot_steps(n)) | set(he.power_rot_steps(n))
+        ctx.keygen(sorted(steps))
+    rows = []
+    for ci, (name, s, l_e, l_p) in enumerate(cases):
+        X = I.pca_dataset(seed + ci, s, t)
+        rb = -(-s // n)
+        blk = I.blocks(X, n)
+        cts = [ctx.encrypt_matrix(blk[r, c], nonce=(ci << 20) + r * k + c) for r in range(rb) for c in range(k)]
+        ctx.sync()
+        t0 = time.perf_counter()
+        cov_ct = ctx.covariance(cts, rb, k, n, s, {"flags": 2 | 4 | 16})   # lazy relin, one rounding, uncentred
+        ctx.sync()
+        t_cov = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        res, refreshes = pppca(ctx, cov_ct, k, n, l_e, l_p, seed=seed + ci, nonce0=(1 << 40) + (ci << 32),
+                               start_nonce=(1 << 50) + (ci << 32))
+        t_pca = time.perf_counter() - t0
+        V = np.stack([read_vector(ctx, Vc, n, axis) for _, Vc, _, axis in res], axis=1)
+        lam = np.array([float(ctx.decrypt(l, 4)[0]) for l, _, _, _ in res])
+        cov = np.cov(X, rowvar=False, bias=True)
+        w, U = np.linalg.eigh(cov)
+        w, U = w[::-1][:l_e], U[:, ::-1][:, :l_e]
+        lam_r, V_r = fp64_replay(cov, l_e, l_p, seed=seed + ci)
+        taus = lazy_schedule(l_p)
+        row = {"case": name, "s": s, "t": t, "l_E": l_e, "l_P": l_p, "l_N": round(float(np.mean(taus)), 2),
+               "covariance_s": round(t_cov, 3), "pca_s": round(t_pca, 3), "refreshes": refreshes,
+               "r2_x": round(r2_x(X, V), 4), "r2_v": round(r2_v(U, V), 4),
+               "r2_x_fp64_replay": round(r2_x(X, V_r), 4), "r2_v_fp64_replay": round(r2_v(U, V_r), 4),
+               "r2_x_exact_pca": round(r2_x(X, U), 4),
+               "max_abs_err_vs_replay": float(np.max(np.abs(V - V_r))),
+               "eigenvalue_rel_err_vs_eigh": [round(float(x), 6) for x in np.abs(lam - w) / w]}
+        rows.append(row)
+        if log:
+            log(f"[accuracy] {row}")
+        del res, cov_ct, cts
+    if own:
+        ctx.close()
+    return {"workload": "PPPCA from raw synthetic [0,1] data (t = 256 features, planted spectrum) at N=2^16: "
+                        "homomorphic means and covariance, PowerMethod + EigenShift; R2 against numpy's eigenvectors",
+            "rows": rows}
 
 
 def pca_bench(l_e=8, l_p=14, seed=3, log=print):
@@ -124,24 +243,12 @@ def pca_bench(l_e=8, l_p=14, seed=3, log=print):
     # client side: decrypt, FP64 replay of the same rounds, eigh
     cov = X.T @ X / X.shape[0]
     taus = lazy_schedule(l_p)
-    x0 = taylor_point(2.0 ** 16)
-    g = np.random.default_rng(seed)
-    shifted = cov.copy()
+    lam_r, V_r = fp64_replay(cov, l_e, l_p, seed=seed)
     err_v, err_l, eig_l, eig_cos = 0.0, 0.0, [], []
     w, U = np.linalg.eigh(cov)
     w, U = w[::-1], U[:, ::-1]
     for m, (lam, V, VT, axis) in enumerate(res):
-        v = g.standard_normal(k * n)
-        v /= np.linalg.norm(v)
-        for tau in taus:
-            y = shifted @ v
-            x = float(y @ y)
-            s = 1.5 * x0 ** -0.5 - 0.5 * x0 ** -1.5 * x
-            for _ in range(tau):
-                s = s * (1.5 + (-0.5 * x) * (s * s))
-            v = y * s
-        lf = float((shifted @ v) @ v)
-        shifted = shifted - lf * np.outer(v, v)
+        v, lf = V_r[:, m], float(lam_r[m])
         got_v = read_vector(ctx, V, n, axis)
         got_l = float(ctx.decrypt(lam, 4)[0])
         err_v = max(err_v, float(np.max(np.abs(got_v - v))))
