@@ -257,13 +257,19 @@ typedef he_status (*he_refresh_fn)(he_ct* ct, void* user);
 /* Rotation steps of Aggregate for d x d blocks: +-2^j and d 2^j, 2^j < d. */
 he_status he_power_rot_steps(uint32_t d, int32_t* steps, size_t cap, size_t* n);
 
+/* he_power_step flags: the inverse square root by Goldschmidt's iteration
+ * (section 3.4: h = y / 2, g = x y; the same iterates as Newton's, two levels
+ * per step instead of three; v_out = 2 (y h) by an addition) */
+#define HE_PM_GOLDSCHMIDT 1u
+
 /* One round of HPowerMethod on the replicated vector v[k] in `axis` form:
  *   y = Cov v (block products, Aggregate along the other axis), x = <y, y>;
  *   last == 0: v_out = y * Newton_{newton_iters}(T(x), x) in the flipped
  *              form, with T the order-1 Taylor expansion of x^-1/2 at
  *              taylor_x0 (taylor_order must be 1) and the Newton step
  *              y <- y (3 - x y^2) / 2 (Lazy Normalization: the caller picks
- *              newton_iters per round);
+ *              newton_iters per round); with HE_PM_GOLDSCHMIDT in flags the
+ *              same iterates by Goldschmidt's form (other bits: HE_EINVAL);
  *   last != 0: lambda_out = <y, v> (eigenvalue, every slot) and vt_out[k] =
  *              v flipped to the other axis (AxisFlipping); v stays the result.
  * *axis_out receives the form of v_out (last: of v).  Operands at level 0
@@ -271,7 +277,7 @@ he_status he_power_rot_steps(uint32_t d, int32_t* steps, size_t cap, size_t* n);
  * entries of cov and v in place.  Outputs are new ciphertexts owned by the
  * caller. */
 he_status he_power_step(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, he_ct* const* v, uint32_t axis,
-                        uint32_t newton_iters, double taylor_x0, uint32_t taylor_order, int last,
+                        uint32_t newton_iters, double taylor_x0, uint32_t taylor_order, int last, uint32_t flags,
                         he_refresh_fn refresh, void* user, he_ct** v_out, uint32_t* axis_out, he_ct** lambda_out,
                         he_ct** vt_out);
 

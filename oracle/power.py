@@ -98,6 +98,17 @@ def lazy_schedule(l_p, S=0.5, e=1e-5, precision=1e-3, B2=2.0 ** 16, max_tau=200)
     return taus
 
 
+def goldschmidt(y, x, tau):
+    """tau steps of Goldschmidt's iteration for x^-1/2 from y (the form the
+    paper proves equal to Newton's): h = y/2, g = x y; r = 1/2 - g h,
+    h <- h + h r, g <- g + g r; returns 2 h"""
+    h, g = 0.5 * y, x * y
+    for _ in range(tau):
+        r = 0.5 - g * h
+        h, g = h + h * r, g + g * r
+    return 2.0 * h
+
+
 def fp64_round(cov, v, tau, x0, last):
     """One PowerMethod round in FP64 with the same steps as the circuit:
     y = Cov v; not last: y * Newton_tau(T(<y,y>), <y,y>); last: lambda = <y, v>."""
@@ -246,10 +257,45 @@ class HePower:
             Y = Box(self.mul(Y, W))
         return Y
 
-    def step(self, cov, k, V, axis, tau, x0, last):
+    def goldschmidt_half(self, X, x0, tau):
+        """Goldschmidt's iteration for x^-1/2 (section 3.4, equivalent to
+        Newton's): h_0 = T(x)/2, g_0 = x T(x); c = 1/2 - g h;
+        h <- h + h c, g <- g + g c; y_tau = 2 h_tau.  Here g is carried negated
+        (gn = -g) and h + h c, g + g c are formed as h (1.5 + gn h) and
+        gn (1.5 + gn h), plaintext additions and products only.  Returns
+        h_tau.  Before each step, h or gn whose scale left
+        [Delta/2, 2 Delta] is brought back to Delta (match, one level): the
+        deviation of the scales triples with every step."""
+        c1 = -0.5 * x0 ** -1.5
+        c0 = 1.5 * x0 ** -0.5
+        H = Box(self.padd_const(self.pmul_const(X, 0.5 * c1), 0.5 * c0))
+        if tau == 0:
+            return H
+        Yn = Box(self.padd_const(self.pmul_const(X, -c1), -c0))
+        Gn = Box(self.mul(X, Yn))
+        d = self.o.delta
+
+        def renorm(A):
+            a = A.ct
+            if a.level >= 1 and (a.scale > 2.0 * d or a.scale < 0.5 * d):
+                A.ct = self.match(a, a.level - 1, d)
+
+        for it in range(tau):
+            renorm(H)
+            renorm(Gn)
+            W = Box(self.padd_const(self.mul(Gn, H), 1.5))
+            H2 = Box(self.mul(H, W))
+            if it + 1 < tau:
+                Gn = Box(self.mul(Gn, W))
+            H = H2
+        return H
+
+    def step(self, cov, k, V, axis, tau, x0, last, goldschmidt=False):
         """One round of HPowerMethod.  cov: k*k Boxes (block (r, c) at r*k+c),
         V: k Boxes of the replicated vector in `axis` form.  Returns
-        (V', axis') or, for the last round, (V, axis, lambda, V^T)."""
+        (V', axis') or, for the last round, (V, axis, lambda, V^T).
+        goldschmidt: the inverse square root by goldschmidt_half, the vector
+        scaled by 2 h as (v h) + (v h)."""
         newV = []
         for i in range(k):
             S = None
@@ -265,6 +311,13 @@ class HePower:
             S = P if S is None else self.add(S, P)
         X = Box(self.aggregate(Box(S), 1 - ax2))
         if not last:
+            if goldschmidt:
+                H = self.goldschmidt_half(X, x0, tau)
+                out = []
+                for i in range(k):
+                    P = self.mul(newV[i], H)
+                    out.append(Box(self.o.add(P, P)))
+                return out, ax2
             Y = self.newton(X, Box(self.taylor(X, x0)), tau)
             return [Box(self.mul(newV[i], Y)) for i in range(k)], ax2
         VT = [Box(self.axis_flip(V[i], axis)) for i in range(k)]

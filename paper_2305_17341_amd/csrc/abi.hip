@@ -514,12 +514,13 @@ RefreshFn make_refresh(he_ctx* ctx, he_refresh_fn fn, void* user) {
 }  // namespace
 
 he_status he_power_step(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, he_ct* const* v, uint32_t axis,
-                        uint32_t newton_iters, double taylor_x0, uint32_t taylor_order, int last,
+                        uint32_t newton_iters, double taylor_x0, uint32_t taylor_order, int last, uint32_t flags,
                         he_refresh_fn refresh, void* user, he_ct** v_out, uint32_t* axis_out, he_ct** lambda_out,
                         he_ct** vt_out) {
   return guard([&] {
     auto lk = hold(ctx);
     need(cov && v && axis_out && k > 0, "null argument");
+    need((flags & ~HE_PM_GOLDSCHMIDT) == 0, "unknown power-step flag");
     need(taylor_order == 1, "only the order-1 TaylorInit is implemented");
     need(taylor_x0 > 0, "Taylor point must be positive");
     need(last ? (lambda_out && vt_out) : (v_out != nullptr), "null output");
@@ -536,7 +537,7 @@ he_status he_power_step(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, 
     HeCt lam;
     int ax = 0;
     ctx->impl.power_step(C, (int)k, (int)d, V, (int)axis, (int)newton_iters, taylor_x0, last != 0,
-                         make_refresh(ctx, refresh, user), vo, ax, lam, vto);
+                         (flags & HE_PM_GOLDSCHMIDT) != 0, make_refresh(ctx, refresh, user), vo, ax, lam, vto);
     *axis_out = (uint32_t)ax;
     if (last) {
       *lambda_out = wrap(ctx, std::move(lam));

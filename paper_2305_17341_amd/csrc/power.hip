@@ -14,7 +14,8 @@
 //   * The transformation's j-loop multiplies V[j]; axis 0 takes block (i, j),
 //     axis 1 block (j, i).
 //   * Newton: y <- y (1.5 + (-x/2) y^2), -x/2 formed once per normalisation;
-//     three products and three levels per step.  TaylorInit of order 1:
+//     three products and three levels per step.  Goldschmidt's form of the
+//     same iterates (a variant): three products and two levels per step.  TaylorInit of order 1:
 //     T(x) = 1.5 x0^-1/2 - 0.5 x0^-3/2 x.
 //   * Constants and masks multiplied in at level l are encoded at scale q_l
 //     and rescaled; constants added are encoded at the ciphertext's scale.
@@ -147,6 +148,37 @@ struct Circuit {
     }
     return Y;
   }
+  // Goldschmidt's iteration for x^-1/2, equal to Newton's step for step
+  // (section 3.4): with h = y / 2 and g = x y, y_i = 2 h_i.  g is kept
+  // negated so that c = 1.5 - g h is a plaintext addition; the updates
+  // h + h (0.5 - g h) and g + g (0.5 - g h) are taken as h c and g c, so no
+  // two ciphertexts of different scales are added.  Two levels per step
+  // (Newton's form above takes three).  Returns h_tau = y_tau / 2.
+  // The scales' deviation from Delta (primes that are not exactly Delta)
+  // triples with every step, as in Newton's form; a pair of steps between
+  // refreshes that would let it grow past a factor 2 is prevented by taking
+  // any of h, g whose scale left [Delta/2, 2 Delta] back to Delta (match:
+  // one level) before the step.
+  HeCt goldschmidt_half(HeCt& X, double x0, int tau) {
+    const double c1 = -0.5 * std::pow(x0, -1.5), c0 = 1.5 * std::pow(x0, -0.5);
+    HeCt H = padd_const(pmul_const(X, 0.5 * c1), 0.5 * c0);  // T(x) / 2
+    if (tau == 0) return H;
+    HeCt Yn = padd_const(pmul_const(X, -c1), -c0);           // -T(x)
+    HeCt Gn = mul(X, Yn);                                    // -x T(x)
+    auto renorm = [&](HeCt& A) {
+      if (A.level >= 1 && (A.scale > 2.0 * c.delta || A.scale < 0.5 * c.delta)) A = match(A, A.level - 1, c.delta);
+    };
+    for (int it = 0; it < tau; it++) {
+      renorm(H);
+      renorm(Gn);
+      HeCt P = mul(Gn, H);
+      HeCt W = padd_const(P, 1.5);
+      HeCt H2 = mul(H, W);
+      if (it + 1 < tau) Gn = mul(Gn, W);
+      H = std::move(H2);
+    }
+    return H;
+  }
   // x at a higher level brought to (level, scale)
   HeCt match(const HeCt& x, int level, double scale) {
     if (x.level <= level) fail(HE_ELEVEL, "scale matching needs a higher level");
@@ -178,8 +210,8 @@ struct Circuit {
 }  // namespace
 
 void HeCtxImpl::power_step(std::vector<HeCt*>& cov, int k, int n, std::vector<HeCt*>& V, int axis, int tau,
-                           double x0, bool last, const RefreshFn& refresh_fn, std::vector<HeCt>& v_out,
-                           int& axis_out, HeCt& lambda_out, std::vector<HeCt>& vt_out) {
+                           double x0, bool last, bool goldschmidt, const RefreshFn& refresh_fn,
+                           std::vector<HeCt>& v_out, int& axis_out, HeCt& lambda_out, std::vector<HeCt>& vt_out) {
   if ((int)cov.size() != k * k || (int)V.size() != k || k < 1) fail(HE_EINVAL, "block counts");
   if ((u64)n * n > N / 2 || n < 2 || (n & (n - 1))) fail(HE_EINVAL, "block size must be a power of two, n^2 <= N/2");
   if (axis != 0 && axis != 1) fail(HE_EINVAL, "axis must be 0 or 1");
@@ -202,10 +234,19 @@ void HeCtxImpl::power_step(std::vector<HeCt*>& cov, int k, int n, std::vector<He
   }
   HeCt X = C.aggregate(std::move(S), 1 - ax2);
   if (!last) {
-    HeCt Y0 = C.taylor(X, x0);
-    HeCt Y = C.newton(X, std::move(Y0), tau);
     v_out.clear();
-    for (int i = 0; i < k; i++) v_out.push_back(C.mul(nv[i], Y));
+    if (goldschmidt) {
+      // y = 2 h: the doubling is an addition of the product to itself
+      HeCt H = C.goldschmidt_half(X, x0, tau);
+      for (int i = 0; i < k; i++) {
+        HeCt P = C.mul(nv[i], H);
+        v_out.push_back(add(P, P, false));
+      }
+    } else {
+      HeCt Y0 = C.taylor(X, x0);
+      HeCt Y = C.newton(X, std::move(Y0), tau);
+      for (int i = 0; i < k; i++) v_out.push_back(C.mul(nv[i], Y));
+    }
     axis_out = ax2;
     return;
   }

@@ -118,8 +118,8 @@ def load():
         "he_knob_get": [C.c_char_p, C.POINTER(C.c_int32)],
         "he_power_rot_steps": [C.c_uint32, C.POINTER(C.c_int32), C.c_size_t, C.POINTER(C.c_size_t)],
         "he_power_step": [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.POINTER(vp), C.c_uint32, C.c_uint32,
-                          C.c_double, C.c_uint32, C.c_int, REFRESH_FN, vp, C.POINTER(vp), C.POINTER(C.c_uint32),
-                          C.POINTER(vp), C.POINTER(vp)],
+                          C.c_double, C.c_uint32, C.c_int, C.c_uint32, REFRESH_FN, vp, C.POINTER(vp),
+                          C.POINTER(C.c_uint32), C.POINTER(vp), C.POINTER(vp)],
         "he_eigen_shift": [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, vp, C.POINTER(vp), C.POINTER(vp), C.c_uint32,
                            REFRESH_FN, vp, C.POINTER(vp)],
     }
@@ -331,9 +331,10 @@ class Context:
         """in place: ct becomes a top-level encryption of its message"""
         _check(load().he_refresh(self.ptr, ct.ptr, nonce))
 
-    def power_step(self, cov, k, d, V, axis, tau, x0, last, refresher=None):
+    def power_step(self, cov, k, d, V, axis, tau, x0, last, refresher=None, goldschmidt=False):
         """One HPowerMethod round.  Returns (V', axis') or, for the last
-        round, (V, axis, lambda, V^T)."""
+        round, (V, axis, lambda, V^T).  goldschmidt: the inverse square root
+        by Goldschmidt's form of the Newton iterates (HE_PM_GOLDSCHMIDT)."""
         pc = (vp * (k * k))(*[c.ptr for c in cov])
         pv = (vp * k)(*[x.ptr for x in V])
         vo = (vp * k)()
@@ -341,8 +342,8 @@ class Context:
         lam = vp()
         ax = C.c_uint32()
         fn = refresher.fn if refresher is not None else REFRESH_FN()
-        _check(load().he_power_step(self.ptr, pc, k, d, pv, axis, tau, x0, 1, 1 if last else 0, fn, None, vo,
-                                    C.byref(ax), C.byref(lam), vto))
+        _check(load().he_power_step(self.ptr, pc, k, d, pv, axis, tau, x0, 1, 1 if last else 0,
+                                    1 if goldschmidt else 0, fn, None, vo, C.byref(ax), C.byref(lam), vto))
         if last:
             return V, ax.value, Ciphertext(self, lam), [Ciphertext(self, vp(vto[i])) for i in range(k)]
         return [Ciphertext(self, vp(vo[i])) for i in range(k)], ax.value

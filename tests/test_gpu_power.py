@@ -64,6 +64,50 @@ def test_power_rounds_and_shift_bit_exact(oracle_mod):
     assert ref.count == hp.refreshes
 
 
+def test_goldschmidt_rounds_bit_exact(oracle_mod):
+    """HE_PM_GOLDSCHMIDT: the rounds with Goldschmidt's form of the inverse
+    square root, residue for residue equal to the oracle's (refreshes
+    included), and fewer refreshes than Newton's form on the same rounds"""
+    from oracle import power as P
+    from paper_2305_17341_amd import he, pca
+    log_n, qb, pb = SMALL_CHAIN
+    n, k = 16, 2
+    ctx = he.Context(log_n, qb, pb, seed=4)
+    ctx.keygen(he.power_rot_steps(n))
+    o = oracle_mod.Oracle(log_n, qb, pb, seed=4)
+    o.keygen(rot_steps=he.power_rot_steps(n))
+    cov = _planted_cov(8, n * k)
+    blocks = [cov[r * n:(r + 1) * n, c * n:(c + 1) * n] for r in range(k) for c in range(k)]
+    gC = [ctx.encrypt_matrix(b, nonce=100 + i) for i, b in enumerate(blocks)]
+    oC = [P.Box(o.encrypt(b.ravel(), nonce=100 + i)) for i, b in enumerate(blocks)]
+    v = np.random.default_rng(2).standard_normal(n * k)
+    v /= np.linalg.norm(v)
+    reps = P.replicate(v, k, n, 1)
+    gV0 = [ctx.encrypt_matrix(b, nonce=200 + i) for i, b in enumerate(reps)]
+    oV = [P.Box(o.encrypt(b.ravel(), nonce=200 + i)) for i, b in enumerate(reps)]
+    ref = he.Refresher(ctx, 1 << 40)
+    hp = P.HePower(o, n, nonce0=1 << 40)
+    gV, g_axis, o_axis = gV0, 1, 1
+    vf = v.copy()
+    taus = P.lazy_schedule(4)
+    for t, tau in enumerate(taus):
+        gV, g_axis = ctx.power_step(gC, k, n, gV, g_axis, tau, X0, False, ref, goldschmidt=True)
+        oV, o_axis = hp.step(oC, k, oV, o_axis, tau, X0, False, goldschmidt=True)
+        vf, _ = P.fp64_round(cov, vf, tau, X0, False)
+        assert g_axis == o_axis and ref.count == hp.refreshes, t
+        for i in range(k):
+            assert gV[i].level == oV[i].ct.level and gV[i].scale == oV[i].ct.scale
+            assert np.array_equal(gV[i].export(), oV[i].ct.data()), (t, i)
+        got = pca.read_vector(ctx, gV, n, g_axis)
+        assert np.max(np.abs(got - vf)) < BOUND, t
+    g_refreshes = ref.count
+    ref2 = he.Refresher(ctx, 1 << 42)
+    nV, n_axis = gV0, 1
+    for tau in taus:
+        nV, n_axis = ctx.power_step(gC, k, n, nV, n_axis, tau, X0, False, ref2)
+    assert g_refreshes < ref2.count
+
+
 def test_power_without_refresh_callback_reports_it():
     from paper_2305_17341_amd import he
     log_n, qb, pb = SMALL_CHAIN

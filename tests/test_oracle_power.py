@@ -118,3 +118,48 @@ def test_rounds_eigenvalue_and_shift_match_fp64_replay(ctx):
         for c in range(k):
             blk = _dec(o, S[r * k + c])
             assert np.max(np.abs(blk - ref[r * n:(r + 1) * n, c * n:(c + 1) * n])) < 2.0 ** -15
+
+
+@pytest.mark.parametrize("x", [1e-3, 0.3, 1.0, 7.0, 300.0, 2.0 ** 12, 2.0 ** 16])
+def test_goldschmidt_iterates_equal_newtons(x):
+    # the equivalence the paper proves for the two iterations: 2 h_i = y_i
+    y0 = P.taylor1(x, X0)
+    for tau in range(0, 40, 3):
+        a, b = P.goldschmidt(y0, x, tau), P.newton(y0, x, tau)
+        assert abs(a - b) <= 1e-12 * abs(b), (x, tau)
+
+
+def test_goldschmidt_circuit_two_levels_per_step(ctx):
+    """the encrypted Goldschmidt form decrypts to half of Newton's iterate
+    and takes 2 tau + 2 levels (Newton's form: 3 tau + 1)"""
+    o, n = ctx, N_BLK
+    hp = P.HePower(o, n)
+    x = np.linspace(1.0, 2.0 ** 16, n * n)
+    X = P.Box(o.encrypt(x, nonce=9))
+    for tau in (0, 1, 3):
+        H = hp.goldschmidt_half(X, X0, tau)
+        want = 0.5 * np.array([P.newton(P.taylor1(v, X0), v, tau) for v in x])
+        got = o.decrypt(H.ct, n * n)
+        assert np.max(np.abs(got - want) / want) < 1e-4, tau
+        assert H.ct.level == o.L - (1 if tau == 0 else 2 * tau + 2)
+        Y = hp.newton(X, P.Box(hp.taylor(X, X0)), tau)
+        assert Y.ct.level == o.L - (3 * tau + 1)
+    assert hp.refreshes == 0
+
+
+def test_goldschmidt_rounds_match_fp64_replay(ctx):
+    o, n, k = ctx, N_BLK, K
+    cov = _planted_cov(7, n * k)
+    hp = P.HePower(o, n, nonce0=1 << 41)
+    C = [P.Box(o.encrypt(cov[r * n:(r + 1) * n, c * n:(c + 1) * n].ravel(), nonce=300 + r * k + c))
+         for r in range(k) for c in range(k)]
+    v = np.random.default_rng(2).standard_normal(n * k)
+    v /= np.linalg.norm(v)
+    axis = 1
+    V = [P.Box(o.encrypt(b.ravel(), nonce=400 + i)) for i, b in enumerate(P.replicate(v, k, n, axis))]
+    vf = v.copy()
+    for tau in P.lazy_schedule(4):
+        V, axis = hp.step(C, k, V, axis, tau, X0, False, goldschmidt=True)
+        vf, _ = P.fp64_round(cov, vf, tau, X0, False)
+        got = P.unreplicate([_dec(o, b) for b in V], axis)
+        assert np.max(np.abs(got - vf)) < 2.0 ** -15
