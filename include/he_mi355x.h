@@ -258,7 +258,7 @@ typedef he_status (*he_refresh_fn)(he_ct* ct, void* user);
 he_status he_power_rot_steps(uint32_t d, int32_t* steps, size_t cap, size_t* n);
 
 /* he_power_step flags: the inverse square root by Goldschmidt's iteration
- * (section 3.4: h = y / 2, g = x y; the same iterates as Newton's, two levels
+ * (section 3.5: h = y / 2, g = x y; the same iterates as Newton's, two levels
  * per step instead of three; v_out = 2 (y h) by an addition) */
 #define HE_PM_GOLDSCHMIDT 1u
 

@@ -258,7 +258,7 @@ class HePower:
         return Y
 
     def goldschmidt_half(self, X, x0, tau):
-        """Goldschmidt's iteration for x^-1/2 (section 3.4, equivalent to
+        """Goldschmidt's iteration for x^-1/2 (section 3.5, equivalent to
         Newton's): h_0 = T(x)/2, g_0 = x T(x); c = 1/2 - g h;
         h <- h + h c, g <- g + g c; y_tau = 2 h_tau.  Here g is carried negated
         (gn = -g) and h + h c, g + g c are formed as h (1.5 + gn h) and

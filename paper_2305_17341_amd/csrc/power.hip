@@ -149,7 +149,7 @@ struct Circuit {
     return Y;
   }
   // Goldschmidt's iteration for x^-1/2, equal to Newton's step for step
-  // (section 3.4): with h = y / 2 and g = x y, y_i = 2 h_i.  g is kept
+  // (section 3.5): with h = y / 2 and g = x y, y_i = 2 h_i.  g is kept
   // negated so that c = 1.5 - g h is a plaintext addition; the updates
   // h + h (0.5 - g h) and g + g (0.5 - g h) are taken as h c and g c, so no
   // two ciphertexts of different scales are added.  Two levels per step
