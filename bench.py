@@ -350,8 +350,9 @@ def main():
         from paper_2305_17341_amd import pca
         log("[bench] PCA run ...")
         result["pca"] = pca.pca_bench(l_e=args.pca_components, log=log)
-        log("[bench] PCA run, Goldschmidt's inverse square root ...")
-        result["pca_goldschmidt"] = pca.pca_bench(l_e=args.pca_components, log=log, goldschmidt=True)
+        log("[bench] PCA run, Goldschmidt's inverse square root and packed vector refreshes ...")
+        result["pca_goldschmidt_packed"] = pca.pca_bench(l_e=args.pca_components, log=log, goldschmidt=True,
+                                                         pack=True)
     if not args.no_accuracy:
         from paper_2305_17341_amd import pca
         log("[bench] PPPCA accuracy runs ...")

@@ -261,6 +261,14 @@ he_status he_power_rot_steps(uint32_t d, int32_t* steps, size_t cap, size_t* n);
  * (section 3.5: h = y / 2, g = x y; the same iterates as Newton's, two levels
  * per step instead of three; v_out = 2 (y h) by an addition) */
 #define HE_PM_GOLDSCHMIDT 1u
+/* he_power_step flags: when a block of v enters the round with fewer than 3
+ * levels left (but at least 1) and all k > 1 blocks share level and scale,
+ * v is refreshed through one ciphertext (Appendix C): block i's segment kept
+ * in column i (axis 1) or row i (axis 0) by a mask, the blocks summed, one
+ * call of `refresh`, then each block recovered by rotation, mask and
+ * spreading rotations (keys of he_power_rot_steps); the blocks of v are
+ * replaced in place.  Otherwise operands are refreshed one by one at level 0. */
+#define HE_PM_PACK_REFRESH 2u
 
 /* One round of HPowerMethod on the replicated vector v[k] in `axis` form:
  *   y = Cov v (block products, Aggregate along the other axis), x = <y, y>;

@@ -153,6 +153,7 @@ class HePower:
         self.n = n
         self.nonce = nonce0
         self.refreshes = 0
+        self.packs = 0
 
     # -- plaintexts --------------------------------------------------------
     def _const(self, c, scale):
@@ -165,6 +166,16 @@ class HePower:
             M[:, 0] = 1.0
         else:
             M[np.arange(n), np.arange(n)] = 1.0
+        return self.o.encode(M.ravel(), delta=scale)
+
+    def _line(self, col, idx, scale):
+        """0/1 mask keeping column idx (col) or row idx"""
+        n = self.n
+        M = np.zeros((n, n))
+        if col:
+            M[:, idx] = 1.0
+        else:
+            M[idx, :] = 1.0
         return self.o.encode(M.ravel(), delta=scale)
 
     # -- refresh -------------------------------------------------------------
@@ -290,12 +301,55 @@ class HePower:
             H = H2
         return H
 
-    def step(self, cov, k, V, axis, tau, x0, last, goldschmidt=False):
+    def pack(self, V, axis):
+        """Appendix C, the single-ciphertext refresh of a replicated vector:
+        block i keeps its segment in column i (axis 1) or row i (axis 0)
+        under a 0/1 mask, and the masked blocks are summed"""
+        o = self.o
+        P = None
+        for i, A in enumerate(V):
+            self._ready(A)
+            a = A.ct
+            ql = float(o.q[a.level])
+            t = o.rescale(o.pmult(a, self._line(axis == 1, i, ql), ql))
+            P = t if P is None else self.add(P, t)
+        return P
+
+    def unpack(self, P, axis, k):
+        """block i from the packed ciphertext: rotated so that column / row i
+        comes to position 0 (power-of-two steps), masked, and spread by
+        Aggregate's rotations"""
+        o, n = self.o, self.n
+        unit = 1 if axis == 1 else n
+        out = []
+        for i in range(k):
+            R = P
+            b = 0
+            while (1 << b) <= i:
+                if (i >> b) & 1:
+                    R = o.rotate(R, unit << b)
+                b += 1
+            ql = float(o.q[R.level])
+            M = o.rescale(o.pmult(R, self._line(axis == 1, 0, ql), ql))
+            if axis == 1:
+                st = -1
+                while st > -n:
+                    M = o.add(M, o.rotate(M, st))
+                    st *= 2
+            else:
+                M = self.aggregate(Box(M), 0)
+            out.append(Box(M))
+        return out
+
+    def step(self, cov, k, V, axis, tau, x0, last, goldschmidt=False, pack=False):
         """One round of HPowerMethod.  cov: k*k Boxes (block (r, c) at r*k+c),
         V: k Boxes of the replicated vector in `axis` form.  Returns
         (V', axis') or, for the last round, (V, axis, lambda, V^T).
         goldschmidt: the inverse square root by goldschmidt_half, the vector
-        scaled by 2 h as (v h) + (v h)."""
+        scaled by 2 h as (v h) + (v h).  pack: an output vector that would
+        have fewer than 3 levels is formed packed (masks on the blocks of
+        Cov v, then the product with the factor), refreshed once and
+        unpacked, when the blocks sit above the factor."""
         newV = []
         for i in range(k):
             S = None
@@ -311,15 +365,23 @@ class HePower:
             S = P if S is None else self.add(S, P)
         X = Box(self.aggregate(Box(S), 1 - ax2))
         if not last:
-            if goldschmidt:
-                H = self.goldschmidt_half(X, x0, tau)
-                out = []
-                for i in range(k):
-                    P = self.mul(newV[i], H)
-                    out.append(Box(self.o.add(P, P)))
-                return out, ax2
-            Y = self.newton(X, Box(self.taylor(X, x0)), tau)
-            return [Box(self.mul(newV[i], Y)) for i in range(k)], ax2
+            Y = self.goldschmidt_half(X, x0, tau) if goldschmidt else self.newton(X, Box(self.taylor(X, x0)), tau)
+            if pack and 1 < k <= self.n:
+                yl = self.o.L if Y.ct.level < 1 else Y.ct.level
+                ok = all(b.ct.level >= yl + 1 and b.ct.level == newV[0].ct.level and b.ct.scale == newV[0].ct.scale
+                         for b in newV)
+                if ok and yl - 1 < 3:
+                    self.packs += 1
+                    Q = Box(self.pack(newV, ax2))
+                    P = self.mul(Q, Y)
+                    if goldschmidt:
+                        P = self.o.add(P, P)
+                    return self.unpack(self.refresh(P), ax2, k), ax2
+            out = []
+            for i in range(k):
+                P = self.mul(newV[i], Y)
+                out.append(Box(self.o.add(P, P) if goldschmidt else P))
+            return out, ax2
         VT = [Box(self.axis_flip(V[i], axis)) for i in range(k)]
         S = None
         for i in range(k):

@@ -520,7 +520,7 @@ he_status he_power_step(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, 
   return guard([&] {
     auto lk = hold(ctx);
     need(cov && v && axis_out && k > 0, "null argument");
-    need((flags & ~HE_PM_GOLDSCHMIDT) == 0, "unknown power-step flag");
+    need((flags & ~(HE_PM_GOLDSCHMIDT | HE_PM_PACK_REFRESH)) == 0, "unknown power-step flag");
     need(taylor_order == 1, "only the order-1 TaylorInit is implemented");
     need(taylor_x0 > 0, "Taylor point must be positive");
     need(last ? (lambda_out && vt_out) : (v_out != nullptr), "null output");
@@ -537,7 +537,8 @@ he_status he_power_step(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d, 
     HeCt lam;
     int ax = 0;
     ctx->impl.power_step(C, (int)k, (int)d, V, (int)axis, (int)newton_iters, taylor_x0, last != 0,
-                         (flags & HE_PM_GOLDSCHMIDT) != 0, make_refresh(ctx, refresh, user), vo, ax, lam, vto);
+                         (flags & HE_PM_GOLDSCHMIDT) != 0, (flags & HE_PM_PACK_REFRESH) != 0,
+                         make_refresh(ctx, refresh, user), vo, ax, lam, vto);
     *axis_out = (uint32_t)ax;
     if (last) {
       *lambda_out = wrap(ctx, std::move(lam));

@@ -84,6 +84,12 @@ struct Circuit {
     for (int i = 0; i < n; i++) z[(size_t)i * n + (col0 ? 0 : i)] = 1.0;
     return c.encode_batch(z.data(), n * n, 1, scale);
   }
+  // 0/1 mask keeping column idx (col) or row idx of an n x n block
+  DevBuf line_pt(bool col, int idx, double scale) {
+    std::vector<double> z((size_t)n * n, 0.0);
+    for (int i = 0; i < n; i++) z[col ? (size_t)i * n + idx : (size_t)idx * n + i] = 1.0;
+    return c.encode_batch(z.data(), n * n, 1, scale);
+  }
   void ready(HeCt& x) {
     if (x.level < 1) refresh(x);
   }
@@ -179,6 +185,44 @@ struct Circuit {
     }
     return H;
   }
+  // A replicated vector refreshed through one ciphertext (Appendix C).
+  // pack: the segment of block i kept in column i (axis 1: every column of a
+  // block holds its segment) or row i (axis 0) by a 0/1 mask, the k masked
+  // blocks summed (one level).  unpack: block i recovered from the one
+  // ciphertext as the rotation bringing column / row i to position 0
+  // (power-of-two steps), a mask keeping it (one level), and the spreading
+  // rotations of Aggregate.
+  HeCt pack(std::vector<HeCt>& V, int axis) {
+    HeCt P;
+    for (size_t i = 0; i < V.size(); i++) {
+      HeCt& A = V[i];
+      ready(A);
+      const double ql = (double)c.mods[A.level];
+      DevBuf m = line_pt(axis == 1, (int)i, ql);
+      HeCt t = c.rescale(c.pmult_int(A, (const i64*)m.p, ql));
+      P = i == 0 ? std::move(t) : add(P, t);
+    }
+    return P;
+  }
+  std::vector<HeCt> unpack(const HeCt& P, int axis, int k) {
+    std::vector<HeCt> out;
+    const long unit = axis == 1 ? 1 : n;
+    for (int i = 0; i < k; i++) {
+      HeCt R = c.ct_copy(P);
+      for (int b = 0; (1 << b) <= i; b++)
+        if ((i >> b) & 1) R = c.rotate(R, unit << b);
+      const double ql = (double)c.mods[R.level];
+      DevBuf m = line_pt(axis == 1, 0, ql);
+      HeCt M = c.rescale(c.pmult_int(R, (const i64*)m.p, ql));
+      if (axis == 1) {
+        for (long st = -1; st > -n; st *= 2) M = c.add(M, c.rotate(M, st), false);
+      } else {
+        M = aggregate(std::move(M), 0);
+      }
+      out.push_back(std::move(M));
+    }
+    return out;
+  }
   // x at a higher level brought to (level, scale)
   HeCt match(const HeCt& x, int level, double scale) {
     if (x.level <= level) fail(HE_ELEVEL, "scale matching needs a higher level");
@@ -210,7 +254,7 @@ struct Circuit {
 }  // namespace
 
 void HeCtxImpl::power_step(std::vector<HeCt*>& cov, int k, int n, std::vector<HeCt*>& V, int axis, int tau,
-                           double x0, bool last, bool goldschmidt, const RefreshFn& refresh_fn,
+                           double x0, bool last, bool goldschmidt, bool pack, const RefreshFn& refresh_fn,
                            std::vector<HeCt>& v_out, int& axis_out, HeCt& lambda_out, std::vector<HeCt>& vt_out) {
   if ((int)cov.size() != k * k || (int)V.size() != k || k < 1) fail(HE_EINVAL, "block counts");
   if ((u64)n * n > N / 2 || n < 2 || (n & (n - 1))) fail(HE_EINVAL, "block size must be a power of two, n^2 <= N/2");
@@ -235,18 +279,33 @@ void HeCtxImpl::power_step(std::vector<HeCt*>& cov, int k, int n, std::vector<He
   HeCt X = C.aggregate(std::move(S), 1 - ax2);
   if (!last) {
     v_out.clear();
-    if (goldschmidt) {
-      // y = 2 h: the doubling is an addition of the product to itself
-      HeCt H = C.goldschmidt_half(X, x0, tau);
-      for (int i = 0; i < k; i++) {
-        HeCt P = C.mul(nv[i], H);
-        v_out.push_back(add(P, P, false));
+    // the factor: y (Newton) or h = y / 2 (Goldschmidt, the product doubled
+    // by an addition to itself)
+    HeCt Y = goldschmidt ? C.goldschmidt_half(X, x0, tau) : C.newton(X, C.taylor(X, x0), tau);
+    bool packed = false;
+    if (pack && k > 1 && k <= n) {
+      // a vector that would come out with fewer than the three levels the
+      // next round's covariance transformation and inner product take is
+      // formed packed instead (the mask on the blocks, whose level is higher
+      // than the factor's, then one product), refreshed once and unpacked
+      const int yl = Y.level < 1 ? L : Y.level;  // the factor's level in the product
+      bool ok = true;
+      for (int i = 0; i < k; i++)
+        ok = ok && nv[i].level >= yl + 1 && nv[i].level == nv[0].level && nv[i].scale == nv[0].scale;
+      if (ok && yl - 1 < 3) {
+        HeCt Q = C.pack(nv, ax2);
+        HeCt P = C.mul(Q, Y);
+        if (goldschmidt) P = add(P, P, false);
+        refresh_fn(P);
+        v_out = C.unpack(P, ax2, k);
+        packed = true;
       }
-    } else {
-      HeCt Y0 = C.taylor(X, x0);
-      HeCt Y = C.newton(X, std::move(Y0), tau);
-      for (int i = 0; i < k; i++) v_out.push_back(C.mul(nv[i], Y));
     }
+    if (!packed)
+      for (int i = 0; i < k; i++) {
+        HeCt P = C.mul(nv[i], Y);
+        v_out.push_back(goldschmidt ? add(P, P, false) : std::move(P));
+      }
     axis_out = ax2;
     return;
   }

@@ -194,7 +194,7 @@ struct HeCtxImpl {
   HeCt refresh(const HeCt& c, u64 nonce);
   HeCt padd_int(const HeCt& a, const i64* m_dev);
   void power_step(std::vector<HeCt*>& cov, int k, int n, std::vector<HeCt*>& V, int axis, int tau, double x0,
-                  bool last, bool goldschmidt, const RefreshFn& refresh_fn, std::vector<HeCt>& v_out,
+                  bool last, bool goldschmidt, bool pack, const RefreshFn& refresh_fn, std::vector<HeCt>& v_out,
                   int& axis_out, HeCt& lambda_out, std::vector<HeCt>& vt_out);
   void eigen_shift(std::vector<HeCt*>& cov, int k, int n, HeCt& lambda, std::vector<HeCt*>& V,
                    std::vector<HeCt*>& VT, int axis, const RefreshFn& refresh_fn, std::vector<HeCt>& out);

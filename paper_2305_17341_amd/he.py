@@ -331,10 +331,12 @@ class Context:
         """in place: ct becomes a top-level encryption of its message"""
         _check(load().he_refresh(self.ptr, ct.ptr, nonce))
 
-    def power_step(self, cov, k, d, V, axis, tau, x0, last, refresher=None, goldschmidt=False):
+    def power_step(self, cov, k, d, V, axis, tau, x0, last, refresher=None, goldschmidt=False, pack=False):
         """One HPowerMethod round.  Returns (V', axis') or, for the last
         round, (V, axis, lambda, V^T).  goldschmidt: the inverse square root
-        by Goldschmidt's form of the Newton iterates (HE_PM_GOLDSCHMIDT)."""
+        by Goldschmidt's form of the Newton iterates (HE_PM_GOLDSCHMIDT); pack:
+        a low vector refreshed through one ciphertext (HE_PM_PACK_REFRESH).
+        Entries of V may be replaced in place by refreshes."""
         pc = (vp * (k * k))(*[c.ptr for c in cov])
         pv = (vp * k)(*[x.ptr for x in V])
         vo = (vp * k)()
@@ -343,7 +345,8 @@ class Context:
         ax = C.c_uint32()
         fn = refresher.fn if refresher is not None else REFRESH_FN()
         _check(load().he_power_step(self.ptr, pc, k, d, pv, axis, tau, x0, 1, 1 if last else 0,
-                                    1 if goldschmidt else 0, fn, None, vo, C.byref(ax), C.byref(lam), vto))
+                                    (1 if goldschmidt else 0) | (2 if pack else 0), fn, None, vo, C.byref(ax),
+                                    C.byref(lam), vto))
         if last:
             return V, ax.value, Ciphertext(self, lam), [Ciphertext(self, vp(vto[i])) for i in range(k)]
         return [Ciphertext(self, vp(vo[i])) for i in range(k)], ax.value

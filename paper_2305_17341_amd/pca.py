@@ -64,18 +64,19 @@ def read_vector(ctx, V, d, axis):
     return np.concatenate(parts)
 
 
-def power_method(ctx, cov, k, d, V0, axis, taus, x0, refresher, goldschmidt=False):
+def power_method(ctx, cov, k, d, V0, axis, taus, x0, refresher, goldschmidt=False, pack=False):
     """HPowerMethod: len(taus) normalising rounds, then the eigenvalue round.
     Returns (V, axis, lambda, V^T).  goldschmidt: Goldschmidt's form of the
-    inverse square root (the same iterates, fewer levels)."""
+    inverse square root (the same iterates, fewer levels); pack: a low output
+    vector refreshed through one ciphertext (Appendix C)."""
     V = V0
     for tau in taus:
-        V, axis = ctx.power_step(cov, k, d, V, axis, tau, x0, False, refresher, goldschmidt=goldschmidt)
+        V, axis = ctx.power_step(cov, k, d, V, axis, tau, x0, False, refresher, goldschmidt=goldschmidt, pack=pack)
     return ctx.power_step(cov, k, d, V, axis, 0, x0, True, refresher)
 
 
 def pppca(ctx, cov, k, d, l_e, l_p, seed=0, B2=2.0 ** 16, nonce0=1 << 40, on_component=None, start_nonce=1 << 50,
-          goldschmidt=False):
+          goldschmidt=False, pack=False):
     """Algorithm Privacy-Preserving PCA from an encrypted covariance: l_E
     (eigenvalue, eigenvector) pairs by PowerMethod and EigenShift.  The
     random unit start vectors are encrypted by the client (axis 1, nonces
@@ -90,7 +91,7 @@ def pppca(ctx, cov, k, d, l_e, l_p, seed=0, B2=2.0 ** 16, nonce0=1 << 40, on_com
         v0 /= np.linalg.norm(v0)
         V0 = [ctx.encrypt_matrix(b, nonce=start_nonce + m * k + i) for i, b in enumerate(replicate(v0, k, d, 1))]
         t0 = time.perf_counter()
-        V, axis, lam, VT = power_method(ctx, cov, k, d, V0, 1, taus, x0, refresher, goldschmidt)
+        V, axis, lam, VT = power_method(ctx, cov, k, d, V0, 1, taus, x0, refresher, goldschmidt, pack)
         cov = ctx.eigen_shift(cov, k, d, lam, V, VT, axis, refresher)
         ctx.sync()
         out.append((lam, V, VT, axis))
@@ -217,7 +218,7 @@ def accuracy_bench(cases=None, seed=7, log=print, ctx=None):
             "rows": rows}
 
 
-def pca_bench(l_e=8, l_p=14, seed=3, log=print, goldschmidt=False):
+def pca_bench(l_e=8, l_p=14, seed=3, log=print, goldschmidt=False, pack=False):
     """The PCA configuration at N = 2^16: a 256 x 256 dataset in [0, 1] with a
     planted spectrum, centred by the client, encrypted as 2 x 2 blocks of
     128 x 128; covariance (HCovMtrx), then l_e components by l_p + 1 power
@@ -239,7 +240,7 @@ def pca_bench(l_e=8, l_p=14, seed=3, log=print, goldschmidt=False):
     t_cov = time.perf_counter() - t0
     comp_s = []
     t0 = time.perf_counter()
-    res, refreshes = pppca(ctx, cov_ct, k, n, l_e, l_p, seed=seed, goldschmidt=goldschmidt,
+    res, refreshes = pppca(ctx, cov_ct, k, n, l_e, l_p, seed=seed, goldschmidt=goldschmidt, pack=pack,
                            on_component=lambda m, s: (comp_s.append(s), log(f"[pca] component {m}: {s:.2f} s")))
     t_pca = time.perf_counter() - t0
     # client side: decrypt, FP64 replay of the same rounds, eigh
@@ -260,7 +261,8 @@ def pca_bench(l_e=8, l_p=14, seed=3, log=print, goldschmidt=False):
     return {
         "workload": f"PCA of a 256x256 [0,1] dataset with planted spectrum at N=2^16: covariance (2x2 blocks of "
                     f"128), {l_e} components x ({l_p} + 1) power rounds, Lazy Normalization schedule {taus}, "
-                    f"inverse square root by {'Goldschmidt' if goldschmidt else 'Newton'}",
+                    f"inverse square root by {'Goldschmidt' if goldschmidt else 'Newton'}"
+                    f"{', low vectors refreshed packed' if pack else ''}",
         "covariance_s": round(t_cov, 3),
         "pca_s": round(t_pca, 3),
         "s_per_component": [round(x, 3) for x in comp_s],

@@ -108,6 +108,44 @@ def test_goldschmidt_rounds_bit_exact(oracle_mod):
     assert g_refreshes < ref2.count
 
 
+@pytest.mark.parametrize("goldschmidt", [False, True])
+def test_packed_refresh_rounds_bit_exact(oracle_mod, goldschmidt):
+    """HE_PM_PACK_REFRESH: low output vectors formed packed, refreshed once
+    and unpacked, residue for residue equal to the oracle (refresh count and
+    nonces included) and within the bound of the FP64 replay"""
+    from oracle import power as P
+    from paper_2305_17341_amd import he, pca
+    log_n, qb, pb = SMALL_CHAIN
+    n, k = 16, 2
+    ctx = he.Context(log_n, qb, pb, seed=5)
+    ctx.keygen(he.power_rot_steps(n))
+    o = oracle_mod.Oracle(log_n, qb, pb, seed=5)
+    o.keygen(rot_steps=he.power_rot_steps(n))
+    cov = _planted_cov(9, n * k)
+    blocks = [cov[r * n:(r + 1) * n, c * n:(c + 1) * n] for r in range(k) for c in range(k)]
+    gC = [ctx.encrypt_matrix(b, nonce=100 + i) for i, b in enumerate(blocks)]
+    oC = [P.Box(o.encrypt(b.ravel(), nonce=100 + i)) for i, b in enumerate(blocks)]
+    v = np.random.default_rng(4).standard_normal(n * k)
+    v /= np.linalg.norm(v)
+    reps = P.replicate(v, k, n, 1)
+    gV = [ctx.encrypt_matrix(b, nonce=200 + i) for i, b in enumerate(reps)]
+    oV = [P.Box(o.encrypt(b.ravel(), nonce=200 + i)) for i, b in enumerate(reps)]
+    ref = he.Refresher(ctx, 1 << 40)
+    hp = P.HePower(o, n, nonce0=1 << 40)
+    g_axis = o_axis = 1
+    vf = v.copy()
+    for t, tau in enumerate([2, 3, 2, 3, 2, 3]):
+        gV, g_axis = ctx.power_step(gC, k, n, gV, g_axis, tau, X0, False, ref, goldschmidt=goldschmidt, pack=True)
+        oV, o_axis = hp.step(oC, k, oV, o_axis, tau, X0, False, goldschmidt=goldschmidt, pack=True)
+        vf, _ = P.fp64_round(cov, vf, tau, X0, False)
+        assert g_axis == o_axis and ref.count == hp.refreshes, t
+        for i in range(k):
+            assert gV[i].level == oV[i].ct.level and gV[i].scale == oV[i].ct.scale
+            assert np.array_equal(gV[i].export(), oV[i].ct.data()), (t, i)
+        assert np.max(np.abs(pca.read_vector(ctx, gV, n, g_axis) - vf)) < BOUND, t
+    assert hp.packs > 0
+
+
 def test_power_without_refresh_callback_reports_it():
     from paper_2305_17341_amd import he
     log_n, qb, pb = SMALL_CHAIN

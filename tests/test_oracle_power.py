@@ -163,3 +163,42 @@ def test_goldschmidt_rounds_match_fp64_replay(ctx):
         vf, _ = P.fp64_round(cov, vf, tau, X0, False)
         got = P.unreplicate([_dec(o, b) for b in V], axis)
         assert np.max(np.abs(got - vf)) < 2.0 ** -15
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_pack_then_unpack_restores_blocks(ctx, axis):
+    """Appendix C's single-ciphertext refresh of a vector: packed (one
+    level), refreshed once, unpacked (one level), the k blocks come back
+    replicated in the same form"""
+    o, n, k = ctx, N_BLK, K
+    hp = P.HePower(o, n, nonce0=1 << 43)
+    v = np.random.default_rng(6).standard_normal(n * k)
+    reps = P.replicate(v, k, n, axis)
+    V = [P.Box(o.encrypt(b.ravel(), level=2, nonce=500 + i)) for i, b in enumerate(reps)]
+    Pk = hp.pack(V, axis)
+    assert Pk.level == 1
+    U = hp.unpack(hp.refresh(Pk), axis, k)
+    assert hp.refreshes == 1
+    for i in range(k):
+        assert U[i].ct.level == o.L - 1
+        assert np.max(np.abs(_dec(o, U[i]) - reps[i])) < 2.0 ** -15
+
+
+def test_pack_refresh_rounds_match_fp64_replay(ctx):
+    o, n, k = ctx, N_BLK, K
+    cov = _planted_cov(7, n * k)
+    for pack in (False, True):
+        hp = P.HePower(o, n, nonce0=1 << 44)
+        C = [P.Box(o.encrypt(cov[r * n:(r + 1) * n, c * n:(c + 1) * n].ravel(), nonce=600 + r * k + c))
+             for r in range(k) for c in range(k)]
+        v = np.random.default_rng(3).standard_normal(n * k)
+        v /= np.linalg.norm(v)
+        axis = 1
+        V = [P.Box(o.encrypt(b.ravel(), nonce=700 + i)) for i, b in enumerate(P.replicate(v, k, n, axis))]
+        vf = v.copy()
+        for tau in [2, 3, 2, 3, 2]:
+            V, axis = hp.step(C, k, V, axis, tau, X0, False, pack=pack)
+            vf, _ = P.fp64_round(cov, vf, tau, X0, False)
+            got = P.unreplicate([_dec(o, b) for b in V], axis)
+            assert np.max(np.abs(got - vf)) < 2.0 ** -15
+        assert (hp.packs > 0) == pack
