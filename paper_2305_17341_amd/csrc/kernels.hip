@@ -653,7 +653,15 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
     // inverse bits [0, GD) of e
     constexpr int ITD = 16 >> GD;
     constexpr int HIGHD = 1 << (S2 - GD);
-    for (int e = tid; e < TILE; e += TPB) sh[lds_be(e / T1, e % T1, T1)] = ar.load(a[e]);
+    // all sixteen loads of a thread in flight before the first LDS store
+    static_assert(TILE / TPB == 16, "one register per coefficient of a thread");
+#pragma unroll
+    for (int k = 0; k < TILE / TPB; k++) v[k] = ar.load(a[tid + k * TPB]);
+#pragma unroll
+    for (int k = 0; k < TILE / TPB; k++) {
+      const int e = tid + k * TPB;
+      sh[lds_be(e / T1, e % T1, T1)] = v[k];
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITD; k++) {
@@ -822,9 +830,16 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2_modup(u64* digits, ModupSrc S
   const int c0 = blockIdx.x * C;
   if (pos < S.nq && pos / S.alpha == j) {
     const u64* src = S.ntt_in + ((size_t)b * S.nq + pos) * N;
-    for (int e = threadIdx.x; e < TILE; e += TPB) {
-      const size_t idx = (size_t)(e / C) * T1 + c0 + e % C;
-      a[idx] = src[idx];
+    u64 t[TILE / TPB];
+#pragma unroll
+    for (int k = 0; k < TILE / TPB; k++) {
+      const int e = threadIdx.x + k * TPB;
+      t[k] = src[(size_t)(e / C) * T1 + c0 + e % C];
+    }
+#pragma unroll
+    for (int k = 0; k < TILE / TPB; k++) {
+      const int e = threadIdx.x + k * TPB;
+      a[(size_t)(e / C) * T1 + c0 + e % C] = t[k];
     }
     return;
   }
