@@ -780,40 +780,51 @@ struct ModupSrc {
   const u64* hat_t_sh[16];
 };
 // F64: every source below 4 q (signed exact products, one reduction);
-// otherwise Shoup products.  The source loop is fixed at 4 without branches
-// (sources past ns repeat the last one, against zero constants), so the loads
-// of a tile's values can all be in flight together.
-template <bool F64>
-struct ModupLoad {
-  struct Raw {
-    u64 x[4];
-  };
+// otherwise Shoup products.  The source loop has a compile-time length NS
+// without branches: 3 for a full digit of three limbs, else 4 with sources
+// past ns repeating the last one against zero constants; so the loads of a
+// tile's values can all be in flight together.
+struct ModupData {
   const u64* y0;
   u64 N;
   int ns;
   u64 q, h[4], hs[4];
   double qf, qinvf, hf[4];
+};
+template <bool F64, int NS = 4>
+struct ModupLoad : ModupData {
+  struct Raw {
+    u64 x[NS];
+  };
   __device__ __forceinline__ void raw(size_t idx, Raw& r) const {
 #pragma unroll
-    for (int a = 0; a < 4; a++) r.x[a] = y0[(size_t)(a < ns ? a : ns - 1) * N + idx];
+    for (int a = 0; a < NS; a++) r.x[a] = y0[(size_t)(a < ns ? a : ns - 1) * N + idx];
   }
   __device__ __forceinline__ double sum_f64(const Raw& r) const {
     double acc = 0.0;
 #pragma unroll
-    for (int a = 0; a < 4; a++) acc += f64_mulmod_signed(u2d(r.x[a]), hf[a], qf, qinvf);
+    for (int a = 0; a < NS; a++) acc += f64_mulmod_signed(u2d(r.x[a]), hf[a], qf, qinvf);
     return acc;
   }
   __device__ __forceinline__ u64 fin_u(const Raw& r) const {
     if (F64) return d2u(f64_canon(sum_f64(r), qf, qinvf));
     u64 acc = 0;
 #pragma unroll
-    for (int a = 0; a < 4; a++) acc = add_mod(acc, shoup_mul(r.x[a], h[a], hs[a], q), q);
+    for (int a = 0; a < NS; a++) acc = add_mod(acc, shoup_mul(r.x[a], h[a], hs[a], q), q);
     return acc;
   }
   __device__ __forceinline__ double fin_d(const Raw& r) const { return f64_centre(sum_f64(r), qf, qinvf); }
 };
-__device__ __forceinline__ double fin(const F64LazyArith&, const ModupLoad<true>& ld, const ModupLoad<true>::Raw& r) {
+template <int NS>
+__device__ __forceinline__ double fin(const F64LazyArith&, const ModupLoad<true, NS>& ld,
+                                      const typename ModupLoad<true, NS>::Raw& r) {
   return ld.fin_d(r);
+}
+template <class L>
+__device__ __forceinline__ L loader_of(const ModupData& d) {
+  L l;
+  static_cast<ModupData&>(l) = d;
+  return l;
 }
 template <int LOGN, int GA, int GB>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2_modup(u64* digits, ModupSrc S, const u64* __restrict__ tw,
@@ -845,37 +856,31 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2_modup(u64* digits, ModupSrc S
   }
   const int m = pos < S.nq ? pos : S.L + 1 + (pos - S.nq);
   const ModConst mk = mc[m];
-  ModupLoad<true> lf;
-  lf.y0 = S.y + ((size_t)b * S.nq + (size_t)j * S.alpha) * N;
-  lf.N = N;
-  lf.ns = S.ns[j];
-  lf.q = mk.q;
-  lf.qf = mk.qf;
-  lf.qinvf = mk.qinvf;
+  ModupData d;
+  d.y0 = S.y + ((size_t)b * S.nq + (size_t)j * S.alpha) * N;
+  d.N = N;
+  d.ns = S.ns[j];
+  d.q = mk.q;
+  d.qf = mk.qf;
+  d.qinvf = mk.qinvf;
   for (int x = 0; x < 4; x++) {
-    const bool in = x < lf.ns;
-    lf.h[x] = in ? S.hat_t[j][(size_t)x * nmods + m] : 0;
-    lf.hs[x] = in ? S.hat_t_sh[j][(size_t)x * nmods + m] : 0;
-    lf.hf[x] = u2d(lf.h[x]);
-  }
-  ModupLoad<false> li;
-  li.y0 = lf.y0;
-  li.N = N;
-  li.ns = lf.ns;
-  li.q = mk.q;
-  for (int x = 0; x < 4; x++) {
-    li.h[x] = lf.h[x];
-    li.hs[x] = lf.hs[x];
+    const bool in = x < d.ns;
+    d.h[x] = in ? S.hat_t[j][(size_t)x * nmods + m] : 0;
+    d.hs[x] = in ? S.hat_t_sh[j][(size_t)x * nmods + m] : 0;
+    d.hf[x] = u2d(d.h[x]);
   }
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
-    if (S.srcbits[j] <= (int)mk.bits + 1)
-      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, lf);
+    double* shd = reinterpret_cast<double*>(sh);
+    if (S.srcbits[j] > (int)mk.bits + 1)
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, shd, ar, loader_of<ModupLoad<false>>(d));
+    else if (d.ns == 3)  // a full digit of three limbs: no padding source
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, shd, ar, loader_of<ModupLoad<true, 3>>(d));
     else
-      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, li);
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, shd, ar, loader_of<ModupLoad<true>>(d));
   } else {
     ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
-    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, li);
+    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, loader_of<ModupLoad<false>>(d));
   }
 }
 
@@ -1574,27 +1579,29 @@ __global__ void k_fbc_prep(u64* V, const u64* xp, FbcArgs A, int logN, const Mod
 }
 // F64 (target of 33 to 46 bits): v = v_hi 2^32 + v_lo, both halves below
 // q_t, signed exact products, one reduction; otherwise Shoup products.  No
-// branches on the source count (sources past ns repeat the last one against
-// zero constants).
-template <bool F64>
-struct FbcLoad {
-  struct Raw {
-    u64 x[4], r;
-  };
+// branches on the source count: NS = 3 for three special primes, else 4 with
+// sources past ns repeating the last one against zero constants.
+struct FbcData {
   const u64* v0;
   u64 N;
   int ns;
   u64 q, h[4], hs[4], D, Ds;
   double qf, qinvf, e0[4], e1[4], e2;
+};
+template <bool F64, int NS = 4>
+struct FbcLoad : FbcData {
+  struct Raw {
+    u64 x[NS], r;
+  };
   __device__ __forceinline__ void raw(size_t idx, Raw& w) const {
 #pragma unroll
-    for (int a = 0; a < 4; a++) w.x[a] = v0[(size_t)(a < ns ? a : ns - 1) * N + idx];
+    for (int a = 0; a < NS; a++) w.x[a] = v0[(size_t)(a < ns ? a : ns - 1) * N + idx];
     w.r = v0[(size_t)ns * N + idx];
   }
   __device__ __forceinline__ double sum_f64(const Raw& w) const {
     double acc = -f64_mulmod_signed(u2d(w.r), e2, qf, qinvf);
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
+    for (int a = 0; a < NS; a++) {
       acc += f64_mulmod_signed(u2d(w.x[a] & 0xffffffffull), e0[a], qf, qinvf);
       acc += f64_mulmod_signed(u2d(w.x[a] >> 32), e1[a], qf, qinvf);
     }
@@ -1604,13 +1611,21 @@ struct FbcLoad {
     if (F64) return d2u(f64_canon(sum_f64(w), qf, qinvf));
     u64 acc = 0;
 #pragma unroll
-    for (int a = 0; a < 4; a++) acc = add_mod(acc, shoup_mul(w.x[a], h[a], hs[a], q), q);
+    for (int a = 0; a < NS; a++) acc = add_mod(acc, shoup_mul(w.x[a], h[a], hs[a], q), q);
     return sub_mod(acc, shoup_mul(w.r, D, Ds, q), q);
   }
   __device__ __forceinline__ double fin_d(const Raw& w) const { return f64_centre(sum_f64(w), qf, qinvf); }
 };
-__device__ __forceinline__ double fin(const F64LazyArith&, const FbcLoad<true>& ld, const FbcLoad<true>::Raw& w) {
+template <int NS>
+__device__ __forceinline__ double fin(const F64LazyArith&, const FbcLoad<true, NS>& ld,
+                                      const typename FbcLoad<true, NS>::Raw& w) {
   return ld.fin_d(w);
+}
+template <class L>
+__device__ __forceinline__ L fbc_loader_of(const FbcData& d) {
+  L l;
+  static_cast<FbcData&>(l) = d;
+  return l;
 }
 template <int LOGN, int GA, int GB>
 __global__ void __launch_bounds__(TPB) k_ntt_cols2_fbc(u64* y, const u64* __restrict__ V, int nq, FbcArgs A,
@@ -1625,43 +1640,35 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2_fbc(u64* y, const u64* __rest
   u64* a = y + (size_t)limb * N;
   const int c0 = blockIdx.x * C;
   const ModConst mk = mc[t];
-  FbcLoad<true> lf;
-  lf.v0 = V + (size_t)p * (A.ns + 1) * N;
-  lf.N = N;
-  lf.ns = A.ns;
-  lf.q = mk.q;
-  lf.qf = mk.qf;
-  lf.qinvf = mk.qinvf;
-  lf.D = A.D_mod_t[2 * t];
-  lf.Ds = A.D_mod_t[2 * t + 1];
-  lf.e2 = A.hat_f[(size_t)t * 3 + 2];
+  FbcData d;
+  d.v0 = V + (size_t)p * (A.ns + 1) * N;
+  d.N = N;
+  d.ns = A.ns;
+  d.q = mk.q;
+  d.qf = mk.qf;
+  d.qinvf = mk.qinvf;
+  d.D = A.D_mod_t[2 * t];
+  d.Ds = A.D_mod_t[2 * t + 1];
+  d.e2 = A.hat_f[(size_t)t * 3 + 2];
   for (int x = 0; x < 4; x++) {
     const bool in = x < A.ns;
-    lf.h[x] = in ? A.hat_t[(size_t)x * nmods + t] : 0;
-    lf.hs[x] = in ? A.hat_t_sh[(size_t)x * nmods + t] : 0;
-    lf.e0[x] = in ? A.hat_f[((size_t)x * nmods + t) * 3] : 0.0;
-    lf.e1[x] = in ? A.hat_f[((size_t)x * nmods + t) * 3 + 1] : 0.0;
-  }
-  FbcLoad<false> li;
-  li.v0 = lf.v0;
-  li.N = N;
-  li.ns = lf.ns;
-  li.q = mk.q;
-  li.D = lf.D;
-  li.Ds = lf.Ds;
-  for (int x = 0; x < 4; x++) {
-    li.h[x] = lf.h[x];
-    li.hs[x] = lf.hs[x];
+    d.h[x] = in ? A.hat_t[(size_t)x * nmods + t] : 0;
+    d.hs[x] = in ? A.hat_t_sh[(size_t)x * nmods + t] : 0;
+    d.e0[x] = in ? A.hat_f[((size_t)x * nmods + t) * 3] : 0.0;
+    d.e1[x] = in ? A.hat_f[((size_t)x * nmods + t) * 3 + 1] : 0.0;
   }
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)t * N, mk.qf, mk.qinvf, (double)mk.ninv};
-    if (mk.bits > 32)
-      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, lf);
+    double* shd = reinterpret_cast<double*>(sh);
+    if (mk.bits <= 32)
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, shd, ar, fbc_loader_of<FbcLoad<false>>(d));
+    else if (d.ns == 3)  // three special primes: no padding source
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, shd, ar, fbc_loader_of<FbcLoad<true, 3>>(d));
     else
-      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, li);
+      ntt_cols2_body<LOGN, GA, GB, false>(a, c0, shd, ar, fbc_loader_of<FbcLoad<true>>(d));
   } else {
     ShoupArith ar{tw + (size_t)t * N, twsh + (size_t)t * N, mk.q, mk.ninv, mk.ninv_sh};
-    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, li);
+    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, fbc_loader_of<FbcLoad<false>>(d));
   }
 }
 template <int LOGN, int GA, int GB, int GC, int GD>
