@@ -161,6 +161,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving run (0: skip it)")
     ap.add_argument("--pca-components", type=int, default=8, help="components of the PCA run (0: skip it)")
+    ap.add_argument("--big-covariance", type=int, default=0, metavar="S",
+                    help="also run the serving workload's large covariance job alone on S x 256 samples (60000 in "
+                         "the workload; about a minute; 0: skip)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the PPPCA accuracy runs (R2(X), R2(V) on synthetic stand-ins)")
     ap.add_argument("--table3-reps", type=int, default=3,
@@ -353,6 +356,10 @@ def main():
         log("[bench] PCA run, Goldschmidt's inverse square root and packed vector refreshes ...")
         result["pca_goldschmidt_packed"] = pca.pca_bench(l_e=args.pca_components, log=log, goldschmidt=True,
                                                          pack=True)
+    if args.big_covariance > 0:
+        from paper_2305_17341_amd import pca
+        log(f"[bench] covariance of {args.big_covariance} x 256 samples ...")
+        result["big_covariance"] = pca.covariance_bench(s=args.big_covariance, log=log)
     if not args.no_accuracy:
         from paper_2305_17341_amd import pca
         log("[bench] PPPCA accuracy runs ...")

@@ -152,7 +152,8 @@ void launch_decode(const DeviceTables& T, double* out, const i64* m, int batch, 
 // decryption helpers
 void launch_centre_to_int(const DeviceTables& T, i64* out, const u64* coef, int mod, hipStream_t s);
 
-// launch-shape knobs: "ms_members", "mr_members", "mr_rotations" (false: unknown name or value)
+// launch-shape knobs: "ms_members", "mr_members", "mr_rotations", "ntt_interleave",
+// "ew_interleave", "cov_row_blocks" (false: unknown name or value)
 bool knob_set(const char* name, int value);
 bool knob_get(const char* name, int* value);
 

@@ -24,6 +24,7 @@ struct Knobs {
   int mr_rotations = 16;  // rotations per multi-rotation launch (1..16)
   int ntt_interleave = 0;  // block passes visit limbs of one modulus back to back (0/1)
   int ew_interleave = 1;   // plaintext-broadcast sums visit the limbs sharing a plaintext back to back (0/1)
+  int cov_row_blocks = 4;  // row blocks of a covariance stacked into one batch (1..8)
 } g_knobs;
 }
 bool knob_set(const char* name, int v) {
@@ -33,6 +34,7 @@ bool knob_set(const char* name, int v) {
   else if (n == "mr_rotations" && v >= 1 && v <= 16) g_knobs.mr_rotations = v;
   else if (n == "ntt_interleave" && (v == 0 || v == 1)) g_knobs.ntt_interleave = v;
   else if (n == "ew_interleave" && (v == 0 || v == 1)) g_knobs.ew_interleave = v;
+  else if (n == "cov_row_blocks" && v >= 1 && v <= 8) g_knobs.cov_row_blocks = v;
   else return false;
   return true;
 }
@@ -43,6 +45,7 @@ bool knob_get(const char* name, int* v) {
   else if (n == "mr_rotations") *v = g_knobs.mr_rotations;
   else if (n == "ntt_interleave") *v = g_knobs.ntt_interleave;
   else if (n == "ew_interleave") *v = g_knobs.ew_interleave;
+  else if (n == "cov_row_blocks") *v = g_knobs.cov_row_blocks;
   else return false;
   return true;
 }

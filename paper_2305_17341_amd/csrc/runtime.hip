@@ -1568,26 +1568,69 @@ std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int r
   // the sides' common level: A after the transposition, sigma and the masks,
   // B after tau
   const int common = std::min(level - 1 - dz - 1, level - 1 - dt);
-  for (int r = 0; r < rb; r++) {
+  // row blocks go through the transforms and sides stacked, g at a time (a
+  // batch of g members); each pair's products are summed over the members
+  // into one accumulator (exact sums, so the residues do not depend on g)
+  int g = 4;
+  knob_get("cov_row_blocks", &g);
+  for (int r0 = 0; r0 < rb; r0 += g) {
+    const int gb = std::min(g, rb - r0);
+    auto rows_of = [&](int col) {
+      std::vector<const HeCt*> xs;
+      for (int r = r0; r < r0 + gb; r++) xs.push_back(x[r * k + col]);
+      return gb == 1 ? ct_copy(*xs[0]) : stack(xs);
+    };
     std::vector<std::vector<HeCt>> A(k), B(k);
     for (int a = 0; a < k; a++) {
-      HeCt xt = lintrans(*x[r * k + a], LT_TRANSPOSE, n, n1g, 1.0 / (double)n_samples);
+      HeCt xt = lintrans(rows_of(a), LT_TRANSPOSE, n, n1g, 1.0 / (double)n_samples);
       A[a] = matmul_side_a(xt, n, n1z, npz, common, fused_rs);
     }
     for (int b = 0; b < k; b++) {
-      HeCt xb = drop(*x[r * k + b], level - 1);
+      HeCt xb = drop(rows_of(b), level - 1);
       B[b] = matmul_side_b(xb, n, n1t, npt, common);
     }
     for (int a = 0; a < k; a++) align_sides(A[a], B[0]);
     for (int b = 0; b < k; b++) align_sides(A[0], B[b]);
     acc_level = A[0][0].level;
     acc_scale = A[0][0].scale * B[0][0].scale;
+    const int nl = A[0][0].nlimbs;
+    const LimbMap qm = qmap(nl);
     for (int a = 0; a < k; a++)
       for (int b = 0; b <= a; b++) {
-        bool s = set[a * k + b];
-        if (lazy) accumulate_tensors(acc3[a * k + b], s, A[a], B[b]);
-        else matmul_accumulate(acc[a * k + b], s, A[a], B[b]);
-        set[a * k + b] = s;
+        const int p = a * k + b;
+        if (lazy) {
+          DevBuf g3;
+          bool gs = false;
+          accumulate_tensors(g3, gs, A[a], B[b]);
+          // [3][gb][nl][N] summed over the members into [3][1][nl][N]
+          const size_t nt = (size_t)gb * nl;
+          int m0 = 0;
+          if (!set[p]) {
+            acc3[p] = DevBuf(&pool, (size_t)3 * nl * N);
+            for (int c = 0; c < 3; c++) copy_limbs(acc3[p].p + (size_t)c * nl * N, g3.p + c * nt * N, nl);
+            m0 = 1;
+            set[p] = true;
+          }
+          for (int c = 0; c < 3; c++)
+            for (int m = m0; m < gb; m++) {
+              u64* dst = acc3[p].p + (size_t)c * nl * N;
+              launch_add(T, dst, dst, g3.p + (c * nt + (size_t)m * nl) * N, nl, qm, stream);
+            }
+        } else {
+          HeCt gacc;
+          bool gs = false;
+          matmul_accumulate(gacc, gs, A[a], B[b]);
+          std::vector<HeCt> parts = gb == 1 ? std::vector<HeCt>{} : unstack(gacc);
+          if (gb == 1) parts.push_back(std::move(gacc));
+          for (auto& part : parts) {
+            if (!set[p]) {
+              acc[p] = std::move(part);
+              set[p] = true;
+            } else {
+              add_into(acc[p], part);
+            }
+          }
+        }
       }
   }
   std::vector<HeCt> out(k * k);

@@ -218,6 +218,64 @@ def accuracy_bench(cases=None, seed=7, log=print, ctx=None):
             "rows": rows}
 
 
+def covariance_bench(s=60000, t=256, seed=13, stacked=(4, 8), log=print):
+    """The serving workload's large covariance job on its own: an s x t
+    uniform[0,1] dataset, centred by the client, encrypted as ceil(s/128) x
+    ceil(t/128) blocks of 128 x 128 at N = 2^16; X^T X / s accumulated
+    homomorphically over the row blocks (lazy relinearisation, one rounding
+    for ModDown and Rescale), with `stacked` row blocks per batch in turn
+    (the "cov_row_blocks" knob).  Reports the client's encryption time, each
+    covariance's time and device peak, and the largest error of the
+    decrypted blocks against FP64."""
+    from . import inputs as I
+    n = 128
+    k, rb = -(-t // n), -(-s // n)
+    ctx = he.chain_context(I.LARGE, seed=seed)
+    ctx.keygen(sorted(set(ctx.matmul_rot_steps(n)) | set(ctx.transpose_rot_steps(n))))
+    X = I.centre(I.dataset(seed, s, t))
+    blk = I.blocks(X, n)
+    t0 = time.perf_counter()
+    cts = [ctx.encrypt_matrix(blk[r, c], nonce=(1 << 30) + r * k + c) for r in range(rb) for c in range(k)]
+    ctx.sync()
+    t_enc = time.perf_counter() - t0
+    del blk
+    P = np.zeros((rb * n, k * n))
+    P[:s, :t] = X
+    ref = P.T @ P / s
+    old = he.knob_get("cov_row_blocks")
+    runs = []
+    try:
+        for g in stacked:
+            he.knob_set("cov_row_blocks", g)
+            ctx.trim()
+            live0, _, _ = ctx.mem_info()
+            t0 = time.perf_counter()
+            cov = ctx.covariance(cts, rb, k, n, s, {"flags": 2 | 4})
+            ctx.sync()
+            t_cov = time.perf_counter() - t0
+            _, _, peak = ctx.mem_info()
+            err = 0.0
+            for i, c in enumerate(cov):
+                a, b = divmod(i, k)
+                got = ctx.decrypt(c, n * n).reshape(n, n)
+                err = max(err, float(np.max(np.abs(got - ref[a * n:(a + 1) * n, b * n:(b + 1) * n]))))
+            run = {"row_blocks_per_batch": g, "covariance_s": round(t_cov, 2),
+                   "products_per_s": round(rb * k * (k + 1) / 2 / t_cov, 2),
+                   "device_peak_gib": round((peak - live0) / 2**30, 1), "max_abs_err": err}
+            runs.append(run)
+            if log:
+                log(f"[covariance] {run}")
+            del cov
+    finally:
+        he.knob_set("cov_row_blocks", old)
+    ctx.close()
+    return {"workload": f"covariance of a {s}x{t} uniform[0,1] dataset (centred by the client) at N=2^16: {rb} row "
+                        f"blocks x {k} feature blocks of 128 x 128 = {rb * k} ciphertexts, "
+                        f"{rb * k * (k + 1) // 2} block products",
+            "encrypt_s": round(t_enc, 2), "input_gib": round(rb * k * 2 * 31 * (1 << 16) * 8 / 2**30, 1),
+            "runs": runs}
+
+
 def pca_bench(l_e=8, l_p=14, seed=3, log=print, goldschmidt=False, pack=False):
     """The PCA configuration at N = 2^16: a 256 x 256 dataset in [0, 1] with a
     planted spectrum, centred by the client, encrypted as 2 x 2 blocks of

@@ -74,15 +74,18 @@ def product_footprint(log_n: int, top_level: int, alpha: int, d: int, batch: int
     return int(math.ceil(words * 8 * POOL_SLACK))
 
 
-def covariance_footprint(log_n: int, top_level: int, alpha: int, d: int, k: int) -> int:
-    """Upper bound for the block covariance of k feature blocks: per row
-    block the A and B sides of all k blocks are held (one-to-many reuse),
-    plus the k^2 accumulators and one product's transient."""
+def covariance_footprint(log_n: int, top_level: int, alpha: int, d: int, k: int, row_blocks: int = 1,
+                         stacked: int = 4) -> int:
+    """Upper bound for the block covariance of k feature blocks: the A and B
+    sides of all k blocks are held for the row blocks stacked into one batch
+    (min(row_blocks, stacked): the library's "cov_row_blocks"; one-to-many
+    reuse), plus the k^2 accumulators and one batch's transient."""
     l = top_level
     n1 = default_n1(d)
-    sides = 2 * k * d * 2 * l
+    g = max(1, min(row_blocks, stacked))
+    sides = 2 * k * d * 2 * l * g
     acc = k * k * 2 * l
-    trans = 2 * (2 * n1 + 4) * _qp(l, alpha) + _beta(l, alpha) * _qp(l, alpha) + 8 * (l + 1)
+    trans = g * (2 * (2 * n1 + 4) * _qp(l, alpha) + _beta(l, alpha) * _qp(l, alpha) + 8 * (l + 1))
     words = (sides + acc + trans) << log_n
     return int(math.ceil(words * 8 * POOL_SLACK))
 
@@ -135,8 +138,9 @@ class HeBackend:
         ch = self.chains[r.log_n]
         if r.kind == "matmul":
             return product_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d)
+        from . import he
         _, rb, k, _ = r.args
-        return covariance_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d, k)
+        return covariance_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d, k, rb, he.knob_get("cov_row_blocks"))
 
     def run(self, log_n: int, reqs):
         ctx = self.contexts[log_n]

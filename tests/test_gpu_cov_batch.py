@@ -1,0 +1,44 @@
+"""Row blocks of the covariance stacked into batches ("cov_row_blocks"): the
+residues do not depend on how many row blocks share a batch (the sums over
+row blocks are exact), with a ragged last batch, for lazy and per-product
+relinearisation."""
+import numpy as np
+import pytest
+
+from paper_2305_17341_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DEEP = I.Chain("n11_deep", 11, (60,) + (40,) * 6, (60, 60))
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_covariance_row_block_batches_keep_residues(flags):
+    from paper_2305_17341_amd import he
+    n, k, rb = 8, 2, 5
+    ctx = he.chain_context(DEEP, seed=61)
+    ctx.keygen(sorted(set(ctx.matmul_rot_steps(n, {"n1_z": 2, "n1_t": 2})) | set(ctx.transpose_rot_steps(n))))
+    X = I.centre(I.dataset(21, rb * n - 3, k * n - 5))
+    blocks = I.blocks(X, n)
+    cts = [ctx.encrypt_matrix(blocks[r, c], nonce=100 + r * k + c) for r in range(rb) for c in range(k)]
+    ref = None
+    old = he.knob_get("cov_row_blocks")
+    try:
+        for g in (1, 2, 4, 8):
+            he.knob_set("cov_row_blocks", g)
+            cov = ctx.covariance(cts, rb, k, n, X.shape[0], {"n1_z": 2, "n1_t": 2, "flags": flags})
+            got = [c.export() for c in cov]
+            if ref is None:
+                ref = got
+                P = np.zeros((rb * n, k * n))
+                P[: X.shape[0], : X.shape[1]] = X
+                want = P.T @ P / X.shape[0]
+                for i, c in enumerate(cov):
+                    a, b = divmod(i, k)
+                    dec = ctx.decrypt(c, n * n).reshape(n, n)
+                    assert np.max(np.abs(dec - want[a * n:(a + 1) * n, b * n:(b + 1) * n])) < 2.0 ** -15
+            else:
+                for x, y in zip(ref, got):
+                    assert np.array_equal(x, y), g
+    finally:
+        he.knob_set("cov_row_blocks", old)
