@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving run (0: skip it)")
     ap.add_argument("--pca-components", type=int, default=8, help="components of the PCA run (0: skip it)")
+    ap.add_argument("--serve-cov-samples", type=int, default=256,
+                    help="rows of the serving mix's covariance job (the workload's has 60000: about a minute more)")
     ap.add_argument("--big-covariance", type=int, default=0, metavar="S",
                     help="also run the serving workload's large covariance job alone on S x 256 samples (60000 in "
                          "the workload; about a minute; 0: skip)")
@@ -348,7 +350,8 @@ def main():
     if args.serve_jobs > 0:
         from paper_2305_17341_amd import serve
         log("[bench] serving run ...")
-        result["serving"] = serve.serve_bench(["--jobs", str(args.serve_jobs)])
+        result["serving"] = serve.serve_bench(["--jobs", str(args.serve_jobs), "--cov-samples",
+                                               str(args.serve_cov_samples)])
     if args.pca_components > 0:
         from paper_2305_17341_amd import pca
         log("[bench] PCA run ...")

@@ -337,6 +337,8 @@ def serve_bench(argv=None):
     ap.add_argument("--budget-gib", type=float, default=0.0, help="0: half of the free device memory")
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--no-covariance", action="store_true")
+    ap.add_argument("--cov-samples", type=int, default=256,
+                    help="rows of the covariance job's dataset (256 features; the workload's job has 60000)")
     args = ap.parse_args(argv)
 
     def log(m):
@@ -378,13 +380,16 @@ def serve_bench(argv=None):
                          (ctx.encrypt_matrix(A, nonce=2 * j.seed), ctx.encrypt_matrix(B, nonce=2 * j.seed + 1))))
         plain.append(A @ B)
     extra = []
+    cov_rb = -(-args.cov_samples // cov_n)
     if not args.no_covariance:
-        # 256 x 256 uniform[0,1] dataset, centred on the client, as 2 x 2 blocks of 128 x 128
-        X = I.centre(I.dataset(args.seed, 2 * cov_n, 2 * cov_n))
+        # cov_samples x 256 uniform[0,1] dataset, centred on the client, as
+        # cov_rb x 2 blocks of 128 x 128 (the last row block zero-padded)
+        X = I.centre(I.dataset(args.seed, args.cov_samples, 2 * cov_n))
         blk = I.blocks(X, cov_n)
         ctx = backend.contexts[16]
-        cts = [ctx.encrypt_matrix(blk[r, c], nonce=10**6 + 2 * r + c) for r in range(2) for c in range(2)]
-        extra.append((jobs[len(jobs) // 2].arrival, ("covariance", 16, cov_n, (cts, 2, 2, X.shape[0]))))
+        cts = [ctx.encrypt_matrix(blk[r, c], nonce=10**6 + 2 * r + c) for r in range(cov_rb) for c in range(2)]
+        extra.append((jobs[len(jobs) // 2].arrival, ("covariance", 16, cov_n, (cts, cov_rb, 2, X.shape[0]))))
+        del blk
     ctx16 = backend.contexts[16]
     for c in backend.contexts.values():
         c.sync()
@@ -413,7 +418,7 @@ def serve_bench(argv=None):
                 got = backend.contexts[ln].decrypt(res, d * d)
                 errs.append(float(np.max(np.abs(got - plain[idx].ravel()))))
         else:
-            X = I.centre(I.dataset(args.seed, 2 * cov_n, 2 * cov_n))
+            X = I.centre(I.dataset(args.seed, args.cov_samples, 2 * cov_n))
             ref = X.T @ X / X.shape[0]
             for i, c in enumerate(res):
                 a_, b_ = divmod(i, 2)
@@ -421,7 +426,7 @@ def serve_bench(argv=None):
                 errs.append(float(np.max(np.abs(got - ref[a_ * cov_n:(a_ + 1) * cov_n, b_ * cov_n:(b_ + 1) * cov_n]))))
     out = {
         "metric": "served HE jobs/s and latency percentiles (Poisson mix of d x d products over 14 (d, N) pairs"
-                  + ("" if args.no_covariance else " + one 256x256 block covariance") + ")",
+                  + ("" if args.no_covariance else f" + one {args.cov_samples}x256 block covariance") + ")",
         "jobs_per_s": st["jobs_per_s"],
         "latency_ms": {k2: 1e3 * v for k2, v in st["latency_s"].items()},
         "offered_rate": rate,
