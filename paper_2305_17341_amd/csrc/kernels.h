@@ -37,6 +37,9 @@ void launch_ntt_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const 
 // Decompose's conversion fused into the forward NTT of the digits (false:
 // not available for this ring size; nothing was launched)
 struct FbcTable;
+// generic-path digits ([0, q) residues) into the key inner products' operand
+// form: limbs of moduli below 2^46 as centred doubles (bit patterns)
+void launch_digits_f64(const DeviceTables& T, u64* d, int nlimbs, const LimbMap& map, hipStream_t s);
 bool launch_modup_ntt(const DeviceTables& T, u64* digits, const u64* y, const u64* ntt_in, int level, int L,
                       int alpha, int beta, const FbcTable* tabs, int batch, const LimbMap& rows_map, hipStream_t s);
 

@@ -582,6 +582,17 @@ struct StorePlain {
   __device__ __forceinline__ void pre() {}
   __device__ __forceinline__ void operator()(int e, int k, typename A::V v) const { a[e] = ar.store(v); }
 };
+// Decomposition digits on moduli below 2^46 are kept as the bit pattern of a
+// double holding a centred representative (|v| <= q/2 + 1), the operand form
+// of the key inner products; other limbs hold residues in [0, q).
+struct StoreCentred {
+  u64* a;
+  const F64LazyArith& ar;
+  __device__ __forceinline__ void pre() {}
+  __device__ __forceinline__ void operator()(int e, int k, double v) const {
+    a[e] = (u64)__double_as_longlong(ar.reduce(v));
+  }
+};
 // x is read into registers when the pass starts (pre), so its loads are in
 // flight during the butterflies; element e = threadIdx.x + k TPB
 struct SubScaleShoup {
@@ -714,7 +725,8 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
   }
 }
 
-template <int LOGN, int GC, int GD, bool INV>
+// DIG: the forward pass of a decomposition, F64 limbs stored centred as doubles
+template <int LOGN, int GC, int GD, bool INV, bool DIG = false>
 __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const u64* __restrict__ tw,
                                                    const u64* __restrict__ twsh, const double* __restrict__ twf,
                                                    const ModConst* __restrict__ mc, int il) {
@@ -729,7 +741,10 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
   const ModConst mk = mc[m];
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
-    ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, reinterpret_cast<double*>(sh), ar, StorePlain<F64LazyArith>{a, ar});
+    if (DIG)
+      ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, reinterpret_cast<double*>(sh), ar, StoreCentred{a, ar});
+    else
+      ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, reinterpret_cast<double*>(sh), ar, StorePlain<F64LazyArith>{a, ar});
   } else {
     ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
     ntt_rows2_body<LOGN, GC, GD, INV>(a, blk0, sh, ar, StorePlain<ShoupArith>{a, ar});
@@ -843,7 +858,9 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2_modup(u64* digits, ModupSrc S
   u64* a = digits + (size_t)limb * N;
   const int c0 = blockIdx.x * C;
   if (pos < S.nq && pos / S.alpha == j) {
+    // the digit's own limbs: the input itself (centred doubles on F64 moduli)
     const u64* src = S.ntt_in + ((size_t)b * S.nq + pos) * N;
+    const bool f64 = mc[pos].bits <= F64_LAZY_BITS;
     u64 t[TILE / TPB];
 #pragma unroll
     for (int k = 0; k < TILE / TPB; k++) {
@@ -853,7 +870,7 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2_modup(u64* digits, ModupSrc S
 #pragma unroll
     for (int k = 0; k < TILE / TPB; k++) {
       const int e = threadIdx.x + k * TPB;
-      a[(size_t)(e / C) * T1 + c0 + e % C] = t[k];
+      a[(size_t)(e / C) * T1 + c0 + e % C] = f64 ? (u64)__double_as_longlong(u2d(t[k])) : t[k];
     }
     return;
   }
@@ -901,8 +918,8 @@ static void ntt2_modup(const DeviceTables& T, u64* digits, const ModupSrc& S, in
   int active = 0;
   for (int k = 0; k < rows_map.n; k++) active += rows_map.idx[k] >= 0;
   ProfScope ps("ntt_fwd_rows", s, 16.0 * T.N * batch * active);
-  hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false>), gr, dim3(TPB), 0, s, digits, rows_map, T.psi, T.psi_sh,
-                     T.psi_f, T.mc, interleave_of(nlimbs, modulus_period(rows_map), g_knobs.ntt_interleave));
+  hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false, true>), gr, dim3(TPB), 0, s, digits, rows_map, T.psi,
+                     T.psi_sh, T.psi_f, T.mc, interleave_of(nlimbs, modulus_period(rows_map), g_knobs.ntt_interleave));
 }
 
 template <int LOGN, int GA, int GB, int GC, int GD>
@@ -1015,6 +1032,21 @@ void launch_ntt_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const 
 // Fused ModUp + forward NTT of every digit (see k_ntt_cols2_modup); false
 // when the ring size has no register-blocked NTT (the caller then converts
 // and transforms separately).  y holds the sources times their hat inverses.
+// digits from the generic path (residues in [0, q)) put into the key inner
+// products' operand form: F64 limbs as doubles
+__global__ void k_digits_f64(u64* d, LimbMap map, int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  const u32 i = blockIdx.x * TPB + threadIdx.x;
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (i >= N || m < 0 || mc[m].bits > F64_LAZY_BITS) return;
+  u64* p = d + (size_t)limb * N + i;
+  *p = (u64)__double_as_longlong(u2d(*p));
+}
+void launch_digits_f64(const DeviceTables& T, u64* d, int nlimbs, const LimbMap& map, hipStream_t s) {
+  hipLaunchKernelGGL(k_digits_f64, dim3(cdiv(T.N, TPB), nlimbs), dim3(TPB), 0, s, d, map, T.logN, T.mc);
+}
+
 bool launch_modup_ntt(const DeviceTables& T, u64* digits, const u64* y, const u64* ntt_in, int level, int L,
                       int alpha, int beta, const FbcTable* tabs, int batch, const LimbMap& rows_map, hipStream_t s) {
   if (T.logN < 12 || T.logN > 16 || alpha > 4 || beta > 16) return false;
@@ -1795,7 +1827,7 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
       const double kb = u2d(kbn), ka = u2d(kan);
       double d[MB];
 #pragma unroll
-      for (int b = 0; b < MB; b++) d[b] = u2d(dn[b]);
+      for (int b = 0; b < MB; b++) d[b] = __longlong_as_double((long long)dn[b]);  // centred double digits
       if (j + 1 < beta) {
         kbn = ldnt(&key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i]);
         kan = ldnt(&key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i]);

@@ -672,6 +672,9 @@ HeCt HeCtxImpl::rescale(const HeCt& a, int out_level) {
 // key switching (section 3.3.1; Appendix A KeySwitch)
 // ---------------------------------------------------------------------------
 // Decompose B polynomials d [B][l+1][N]: digits u64[B][beta_l][l+1+alpha][N], evaluation domain
+// Decompose: the digits [B][beta_l][nqp][N] in the evaluation domain, limbs
+// of moduli below 2^46 as centred doubles (the key inner products' operand
+// form), the others as residues in [0, q)
 DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
   int nq = nq_of(level), nqp = nqp_of(level), bl = beta_at(level);
   DevBuf coef(&pool, (size_t)B * nq * N);
@@ -703,6 +706,11 @@ DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
   }
   launch_modup(T, dig.p, coef.p, d, level, L, alpha, bl, up[level].data(), B, stream);
   launch_ntt(T, dig.p, B * m.n, m, false, stream);
+  LimbMap all;
+  all.n = bl * nqp;
+  for (int j = 0; j < bl; j++)
+    for (int pos = 0; pos < nqp; pos++) all.idx[j * nqp + pos] = (short)qp_mod(level, pos);
+  launch_digits_f64(T, dig.p, B * all.n, all, stream);
   n_decompose += B;
   return dig;
 }
