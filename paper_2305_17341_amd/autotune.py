@@ -15,6 +15,7 @@ CANDIDATES = {
     "ms_members": (4, 8),
     "ntt_interleave": (0, 1),
     "ew_interleave": (0, 1),
+    "mr_group": (1, 2, 4),
 }
 
 

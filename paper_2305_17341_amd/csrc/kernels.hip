@@ -25,6 +25,7 @@ struct Knobs {
   int ntt_interleave = 0;  // block passes visit limbs of one modulus back to back (0/1)
   int ew_interleave = 1;   // plaintext-broadcast sums visit the limbs sharing a plaintext back to back (0/1)
   int cov_row_blocks = 4;  // row blocks of a covariance stacked into one batch (1..8)
+  int mr_group = 2;        // rotations per work-group of a multi-rotation launch, sharing the digit loads (1/2/4)
 } g_knobs;
 }
 bool knob_set(const char* name, int v) {
@@ -35,6 +36,7 @@ bool knob_set(const char* name, int v) {
   else if (n == "ntt_interleave" && (v == 0 || v == 1)) g_knobs.ntt_interleave = v;
   else if (n == "ew_interleave" && (v == 0 || v == 1)) g_knobs.ew_interleave = v;
   else if (n == "cov_row_blocks" && v >= 1 && v <= 8) g_knobs.cov_row_blocks = v;
+  else if (n == "mr_group" && (v == 1 || v == 2 || v == 4)) g_knobs.mr_group = v;
   else return false;
   return true;
 }
@@ -46,6 +48,7 @@ bool knob_get(const char* name, int* v) {
   else if (n == "ntt_interleave") *v = g_knobs.ntt_interleave;
   else if (n == "ew_interleave") *v = g_knobs.ew_interleave;
   else if (n == "cov_row_blocks") *v = g_knobs.cov_row_blocks;
+  else if (n == "mr_group") *v = g_knobs.mr_group;
   else return false;
   return true;
 }
@@ -1940,34 +1943,130 @@ struct MultiRot {
 struct PosList {
   short pos[HE_MAXMOD];
 };
-template <int MB, bool F64>
+// RPW rotations r0 .. r0 + nr - 1 (nr <= RPW) of one decomposition at one
+// FP64 limb for one thread: the thread's digits (and c0) are read once and
+// serve every rotation of the group, each with its own key, output index
+// and epilogue.  The sums are those of multsum_body, term for term.
+template <int MB, int RPW>
+__device__ __forceinline__ void multsum_rot_group(const MultiRot& R, int r0, int nr, const u64* __restrict__ digits,
+                                                  const u64* __restrict__ c0, const u64* __restrict__ pmod, int nq,
+                                                  int nqp, int beta, int nmods, int B, int b0, int m, int pos,
+                                                  u32 src, int logN, u64 N, const ModConst& mk) {
+  const size_t dstride = (size_t)beta * nqp * N;
+  const double q = mk.qf, qi = mk.qinvf;
+  u32 idx[RPW];
+  const u64* key[RPW];
+#pragma unroll
+  for (int g = 0; g < RPW; g++) {
+    const int r = r0 + (g < nr ? g : 0);  // past nr: a duplicate of the first, never stored
+    idx[g] = automorph_src(src, R.ginv[r], logN);
+    key[g] = R.key[r];
+  }
+  double s0[RPW][MB], s1[RPW][MB];
+#pragma unroll
+  for (int g = 0; g < RPW; g++)
+#pragma unroll
+    for (int b = 0; b < MB; b++) s0[g][b] = s1[g][b] = 0.0;
+  // software-pipelined as multsum_body: digit j + 1 and the keys at j + 1 in
+  // flight while j is multiplied
+  u64 kbn[RPW], kan[RPW], dn[MB];
+#pragma unroll
+  for (int g = 0; g < RPW; g++) {
+    kbn[g] = ldnt(&key[g][((size_t)0 * nmods + m) * N + idx[g]]);
+    kan[g] = ldnt(&key[g][((size_t)1 * nmods + m) * N + idx[g]]);
+  }
+#pragma unroll
+  for (int b = 0; b < MB; b++) dn[b] = digits[(size_t)(b0 + b) * dstride + (size_t)pos * N + src];
+  for (int j = 0; j < beta; j++) {
+    double kb[RPW], ka[RPW], d[MB];
+#pragma unroll
+    for (int g = 0; g < RPW; g++) {
+      kb[g] = u2d(kbn[g]);
+      ka[g] = u2d(kan[g]);
+    }
+#pragma unroll
+    for (int b = 0; b < MB; b++) d[b] = __longlong_as_double((long long)dn[b]);  // centred double digits
+    if (j + 1 < beta) {
+#pragma unroll
+      for (int g = 0; g < RPW; g++) {
+        kbn[g] = ldnt(&key[g][(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + idx[g]]);
+        kan[g] = ldnt(&key[g][(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + idx[g]]);
+      }
+#pragma unroll
+      for (int b = 0; b < MB; b++) dn[b] = digits[(size_t)(b0 + b) * dstride + ((size_t)(j + 1) * nqp + pos) * N + src];
+    }
+#pragma unroll
+    for (int g = 0; g < RPW; g++)
+#pragma unroll
+      for (int b = 0; b < MB; b++) {
+        s0[g][b] += f64_mulmod_signed(d[b], kb[g], q, qi);
+        s1[g][b] += f64_mulmod_signed(d[b], ka[g], q, qi);
+      }
+  }
+  // c0 P on the Q limbs, once for the group
+  u64 cp[MB];
+#pragma unroll
+  for (int b = 0; b < MB; b++)
+    cp[b] = (c0 && pos < nq) ? mul_const_any(c0[((size_t)(b0 + b) * nq + pos) * N + src], pmod[2 * m], pmod[2 * m + 1], mk)
+                             : 0;
+#pragma unroll
+  for (int g = 0; g < RPW; g++) {
+    if (g >= nr) break;
+    const int r = r0 + g;
+    const u64* mask = R.mask[r];
+    const u32 i = idx[g];
+    const u64 mv = mask ? mask[(size_t)pos * N + i] : 0;
+#pragma unroll
+    for (int b = 0; b < MB; b++) {
+      u64 v0 = d2u(f64_canon(s0[g][b], q, qi)), v1 = d2u(f64_canon(s1[g][b], q, qi));
+      if (c0 && pos < nq) v0 = add_mod(v0, cp[b], mk.q);
+      u64* o0 = &R.out[r][((size_t)(b0 + b) * nqp + pos) * N + i];
+      u64* o1 = &R.out[r][((size_t)(B + b0 + b) * nqp + pos) * N + i];
+      if (mask) {
+        v0 = mul_mod_any(v0, mv, mk);
+        v1 = mul_mod_any(v1, mv, mk);
+        if (R.accumulate) {
+          v0 = add_mod(v0, *o0, mk.q);
+          v1 = add_mod(v1, *o1, mk.q);
+        }
+      }
+      stnt(o0, v0);
+      stnt(o1, v1);
+    }
+  }
+}
+// RPW: rotations per work-group (their FP64 limbs share the digit loads)
+template <int MB, bool F64, int RPW>
 __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, PosList P, int nrot, const u64* __restrict__ digits,
                                                      const u64* __restrict__ c0, const u64* __restrict__ pmod,
                                                      int nq, int nqp, int L, int beta, int nmods, int B, int b0,
                                                      int logN, const ModConst* __restrict__ mc) {
   const u64 N = 1ull << logN;
+  const u32 ngroups = (u32)((nrot + RPW - 1) / RPW);
   const u32 x = blockIdx.x, rest = x >> 3;
-  const u32 r = rest % (u32)nrot;
-  const u32 S = (rest / (u32)nrot) * 8 + (x & 7);
+  const int r0 = (int)(rest % ngroups) * RPW;
+  const int nr = nrot - r0 < RPW ? nrot - r0 : RPW;
+  const u32 S = (rest / ngroups) * 8 + (x & 7);
   if ((u64)S * TPB >= N) return;
   const u32 src = S * TPB + threadIdx.x;
   const int pos = P.pos[blockIdx.y];
   const int m = pos < nq ? pos : L + 1 + (pos - nq);
   const ModConst mk = mc[m];
-  const u32 i = automorph_src(src, R.ginv[r], logN);
   if (F64 || mk.bits <= F64_LAZY_BITS) {
-    multsum_body<MB, true>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk,
-                           R.mask[r], R.accumulate != 0);
+    multsum_rot_group<MB, RPW>(R, r0, nr, digits, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, logN, N, mk);
     return;
   }
-  // integer limbs: at most four members at a time (128-bit sums hold the
-  // registers of two FP64 ones)
+  // integer limbs: one rotation after another, at most four members at a
+  // time (128-bit sums hold the registers of two FP64 ones)
   constexpr int M1 = MB > 4 ? 4 : MB;
-  multsum_body<M1, false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N, mk,
-                          R.mask[r], R.accumulate != 0);
-  if (MB > 4)
-    multsum_body<(MB > 4 ? MB - 4 : 1), false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B,
-                                               b0 + 4, m, pos, i, src, N, mk, R.mask[r], R.accumulate != 0);
+  for (int r = r0; r < r0 + nr; r++) {
+    const u32 i = automorph_src(src, R.ginv[r], logN);
+    multsum_body<M1, false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N,
+                            mk, R.mask[r], R.accumulate != 0);
+    if (MB > 4)
+      multsum_body<(MB > 4 ? MB - 4 : 1), false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B,
+                                                 b0 + 4, m, pos, i, src, N, mk, R.mask[r], R.accumulate != 0);
+  }
 }
 
 static u64 inv_mod_2n(u64 g, u64 twoN) {
@@ -1985,6 +2084,7 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
   const int nblk = cdiv(T.N, TPB);
   const int rstep = std::min(MR_MAX, g_knobs.mr_rotations);
   const int mstep = std::min(MS_MAXB, g_knobs.mr_members);
+  const int rpw = g_knobs.mr_group;
   for (int r0 = 0; r0 < nrot; r0 += rstep) {
     const int nr = std::min(nrot - r0, rstep);
     MultiRot R;
@@ -2022,20 +2122,28 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
              (R.accumulate ? mb * nr * 2.0 : 0.0);
       ProfScope ps("multsum_rot", s, 8.0 * T.N * w);
       // FP64-only launch when every limb is FP64 (the integer branch compiled out)
+#define MR_LAUNCH(K, FP, G)                                                                                        \
+  hipLaunchKernelGGL((k_multsum_rot<K, FP, G>), dim3(cdiv(nblk, 8) * 8 * cdiv(nr, G), nqp), dim3(TPB), 0, s, R, P, \
+                     nr, digits, c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc)
 #define MR_CASE(K)                                                                                                 \
   case K:                                                                                                          \
-    if (ni)                                                                                                        \
-      hipLaunchKernelGGL((k_multsum_rot<K, false>), dim3(cdiv(nblk, 8) * 8 * nr, nqp), dim3(TPB), 0, s, R, P, nr,  \
-                         digits, c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);                    \
-    else                                                                                                           \
-      hipLaunchKernelGGL((k_multsum_rot<K, true>), dim3(cdiv(nblk, 8) * 8 * nr, nqp), dim3(TPB), 0, s, R, P, nr,   \
-                         digits, c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);                    \
+    if (rpw == 4) {                                                                                                \
+      if (ni) MR_LAUNCH(K, false, 4);                                                                              \
+      else MR_LAUNCH(K, true, 4);                                                                                  \
+    } else if (rpw == 2) {                                                                                         \
+      if (ni) MR_LAUNCH(K, false, 2);                                                                              \
+      else MR_LAUNCH(K, true, 2);                                                                                  \
+    } else {                                                                                                       \
+      if (ni) MR_LAUNCH(K, false, 1);                                                                              \
+      else MR_LAUNCH(K, true, 1);                                                                                  \
+    }                                                                                                              \
     break;
       switch (mb) {
         MR_CASE(1) MR_CASE(2) MR_CASE(3) MR_CASE(4) MR_CASE(5) MR_CASE(6) MR_CASE(7) MR_CASE(8)
       }
     }
 #undef MR_CASE
+#undef MR_LAUNCH
   }
 }
 
