@@ -352,24 +352,36 @@ def main():
         log("[bench] serving run ...")
         result["serving"] = serve.serve_bench(["--jobs", str(args.serve_jobs), "--cov-samples",
                                                str(args.serve_cov_samples)])
+    # each part below builds and closes its own contexts; collect what the
+    # previous part left so that its device memory is back before the next
+    import gc
+
+    def free_gib():
+        from paper_2305_17341_amd import he as H
+        return f"{H.device_memory()[0] / 2**30:.0f} GiB free"
+
+    gc.collect()
     if args.pca_components > 0:
         from paper_2305_17341_amd import pca
-        log("[bench] PCA run ...")
+        log(f"[bench] PCA run ({free_gib()}) ...")
         result["pca"] = pca.pca_bench(l_e=args.pca_components, log=log)
         log("[bench] PCA run, Goldschmidt's inverse square root and packed vector refreshes ...")
         result["pca_goldschmidt_packed"] = pca.pca_bench(l_e=args.pca_components, log=log, goldschmidt=True,
                                                          pack=True)
+    gc.collect()
     if args.big_covariance > 0:
         from paper_2305_17341_amd import pca
         log(f"[bench] covariance of {args.big_covariance} x 256 samples ...")
         result["big_covariance"] = pca.covariance_bench(s=args.big_covariance, log=log)
+    gc.collect()
     if not args.no_accuracy:
         from paper_2305_17341_amd import pca
-        log("[bench] PPPCA accuracy runs ...")
+        log(f"[bench] PPPCA accuracy runs ({free_gib()}) ...")
         result["pca_accuracy"] = pca.accuracy_bench(log=log)
+    gc.collect()
     if args.table3_reps > 0:
         from paper_2305_17341_amd import table3
-        log("[bench] Z/T decomposition table ...")
+        log(f"[bench] Z/T decomposition table ({free_gib()}) ...")
         result["table3"] = table3.run(reps=args.table3_reps, log=log)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")

@@ -303,7 +303,7 @@ he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d,
  * rotations per multi-rotation launch), "ntt_interleave" (0/1: the NTT's
  * block pass visits the limbs of one modulus back to back, so their twiddles
  * come from L2) and "ew_interleave" (0/1: the same for the limbs that share a
- * broadcast plaintext in the multiply-sums), "mr_group" (1/2/4, default 2:
+ * broadcast plaintext in the multiply-sums), "mr_group" (1/2/4, default 4:
  * rotations per work-group of a multi-rotation launch, which then read the
  * digits once for all of them), "cov_row_blocks" (1..8, default
  * 4: row blocks of he_covariance stacked into one batch through the

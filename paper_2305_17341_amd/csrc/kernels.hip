@@ -25,7 +25,7 @@ struct Knobs {
   int ntt_interleave = 0;  // block passes visit limbs of one modulus back to back (0/1)
   int ew_interleave = 1;   // plaintext-broadcast sums visit the limbs sharing a plaintext back to back (0/1)
   int cov_row_blocks = 4;  // row blocks of a covariance stacked into one batch (1..8)
-  int mr_group = 2;        // rotations per work-group of a multi-rotation launch, sharing the digit loads (1/2/4)
+  int mr_group = 4;        // rotations per work-group of a multi-rotation launch, sharing the digit loads (1/2/4)
 } g_knobs;
 }
 bool knob_set(const char* name, int v) {

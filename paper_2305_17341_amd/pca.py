@@ -316,6 +316,8 @@ def pca_bench(l_e=8, l_p=14, seed=3, log=print, goldschmidt=False, pack=False):
         err_l = max(err_l, abs(got_l - lf) / max(1.0, abs(lf)))
         eig_l.append(abs(got_l - w[m]) / w[m])
         eig_cos.append(abs(float(got_v @ U[:, m])) / float(np.linalg.norm(got_v)))
+    del res, cov_ct, cts
+    ctx.close()
     return {
         "workload": f"PCA of a 256x256 [0,1] dataset with planted spectrum at N=2^16: covariance (2x2 blocks of "
                     f"128), {l_e} components x ({l_p} + 1) power rounds, Lazy Normalization schedule {taus}, "

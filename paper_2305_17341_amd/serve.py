@@ -424,6 +424,9 @@ def serve_bench(argv=None):
                 a_, b_ = divmod(i, 2)
                 got = ctx16.decrypt(c, cov_n * cov_n).reshape(cov_n, cov_n)
                 errs.append(float(np.max(np.abs(got - ref[a_ * cov_n:(a_ + 1) * cov_n, b_ * cov_n:(b_ + 1) * cov_n]))))
+    del results, futs, payloads, extra
+    for c in backend.contexts.values():
+        c.close()
     out = {
         "metric": "served HE jobs/s and latency percentiles (Poisson mix of d x d products over 14 (d, N) pairs"
                   + ("" if args.no_covariance else f" + one {args.cov_samples}x256 block covariance") + ")",

@@ -91,7 +91,7 @@ def test_knobs_never_change_residues(small_ctx):
     saved = {n: he.knob_get(n) for n in names}
     try:
         for name, value in [("ms_members", 3), ("mr_members", 2), ("mr_rotations", 5),
-                            ("ntt_interleave", 0), ("ew_interleave", 0), ("mr_group", 4), ("mr_group", 1)]:
+                            ("ntt_interleave", 0), ("ew_interleave", 0), ("mr_group", 2), ("mr_group", 1)]:
             he.knob_set(name, value)
             got = small_ctx.matmul_batch(cA, cB, ds, opts=opts)
             for i, g in enumerate(got):
