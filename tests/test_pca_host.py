@@ -52,7 +52,7 @@ def test_r2_x_limits_and_r2_v_sign():
 
 
 def test_fp64_replay_follows_the_oracle_rounds():
-    """the driver's FP64 replay takes the oracle's round definition step by
+    """pca.fp64_replay takes the oracle's round definition step by
     step (same start vectors, Newton counts, eigen-shift), and on a planted,
     well separated spectrum approaches numpy's eigenpairs"""
     from paper_2305_17341_amd import inputs as I
