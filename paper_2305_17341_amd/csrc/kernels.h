@@ -69,6 +69,10 @@ void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs,
                       const LimbMap& m, hipStream_t s);
 void launch_neg(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const LimbMap& m, hipStream_t s);
 // batch pairs of ciphertexts [2][batch][nl] -> [3][batch][nl] (accumulate: added onto out3)
+// sum of npairs tensors (a[p], b[p] over Q_l, [2][B][nl] each) into the
+// three-component [3][B][nl] out3, or added onto it
+void launch_tensor_sum(const DeviceTables& T, u64* out3, const u64* const* a, const u64* const* b, int npairs, int nl,
+                       int batch, bool accumulate, hipStream_t s);
 void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, bool accumulate,
                    hipStream_t s);
 void launch_int_to_limbs(const DeviceTables& T, u64* out, const i64* in, int nlimbs, const LimbMap& m, hipStream_t s);

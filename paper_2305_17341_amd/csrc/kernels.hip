@@ -1372,6 +1372,78 @@ __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, i
   out[o1] = t1;
   out[o2] = t2;
 }
+// Up to TENSOR_PAIRS tensors summed in one pass, onto the running sum or not:
+// each pair is read once and the three-component sum once, where one launch
+// per pair reads and writes the sum for every pair.  The sum of the exact
+// signed products (at most 2 TENSOR_PAIRS + 1 terms below q each) stays below
+// 2^52, so the residues are those of one pair at a time.
+#define TENSOR_PAIRS 8
+struct TensorPairs {
+  const u64* a[TENSOR_PAIRS];
+  const u64* b[TENSOR_PAIRS];
+};
+template <bool ACC>
+__global__ void k_tensor_multi(u64* out, TensorPairs P, int npairs, int nl, int nt, int logN,
+                               const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  int k = blockIdx.y;
+  if (i >= N) return;
+  const ModConst mk = mc[k % nl];
+  const size_t o0 = (size_t)k * N + i, o1 = (size_t)(nt + k) * N + i, o2 = (size_t)(2 * nt + k) * N + i;
+  if (mk.bits <= F64_LAZY_BITS) {
+    const double q = mk.qf, qi = mk.qinvf;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (ACC) {
+      s0 = u2d(out[o0]);
+      s1 = u2d(out[o1]);
+      s2 = u2d(out[o2]);
+    }
+    for (int p = 0; p < npairs; p++) {
+      const double x0 = u2d(P.a[p][o0]), x1 = u2d(P.a[p][o1]), y0 = u2d(P.b[p][o0]), y1 = u2d(P.b[p][o1]);
+      s0 += f64_mulmod_signed(x0, y0, q, qi);
+      s1 += f64_mulmod_signed(x0, y1, q, qi) + f64_mulmod_signed(x1, y0, q, qi);
+      s2 += f64_mulmod_signed(x1, y1, q, qi);
+    }
+    out[o0] = d2u(f64_canon(s0, q, qi));
+    out[o1] = d2u(f64_canon(s1, q, qi));
+    out[o2] = d2u(f64_canon(s2, q, qi));
+    return;
+  }
+  u64 t0 = 0, t1 = 0, t2 = 0;
+  if (ACC) {
+    t0 = out[o0];
+    t1 = out[o1];
+    t2 = out[o2];
+  }
+  for (int p = 0; p < npairs; p++) {
+    const u64 a0 = P.a[p][o0], a1 = P.a[p][o1], b0 = P.b[p][o0], b1 = P.b[p][o1];
+    t0 = add_mod(t0, mul_mod_any(a0, b0, mk), mk.q);
+    t1 = add_mod(t1, add_mod(mul_mod_any(a0, b1, mk), mul_mod_any(a1, b0, mk), mk.q), mk.q);
+    t2 = add_mod(t2, mul_mod_any(a1, b1, mk), mk.q);
+  }
+  out[o0] = t0;
+  out[o1] = t1;
+  out[o2] = t2;
+}
+void launch_tensor_sum(const DeviceTables& T, u64* out3, const u64* const* a, const u64* const* b, int npairs, int nl,
+                       int batch, bool accumulate, hipStream_t s) {
+  const int nt = nl * batch;
+  for (int p0 = 0; p0 < npairs; p0 += TENSOR_PAIRS) {
+    const int np = std::min(TENSOR_PAIRS, npairs - p0);
+    TensorPairs P;
+    for (int p = 0; p < TENSOR_PAIRS; p++) {
+      P.a[p] = p < np ? a[p0 + p] : nullptr;
+      P.b[p] = p < np ? b[p0 + p] : nullptr;
+    }
+    const bool acc = accumulate || p0 > 0;
+    ProfScope ps("tensor", s, 8.0 * T.N * (4.0 * np + (acc ? 6 : 3)) * nt);
+    dim3 grid(cdiv(T.N, TPB), nt);
+    if (acc) hipLaunchKernelGGL(k_tensor_multi<true>, grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
+    else hipLaunchKernelGGL(k_tensor_multi<false>, grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
+  }
+}
+
 void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, bool accumulate,
                    hipStream_t s) {
   const int nt = nl * batch;

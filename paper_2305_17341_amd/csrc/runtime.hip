@@ -1439,11 +1439,15 @@ void HeCtxImpl::accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vecto
   const HeCt& a0 = Ak[0];
   const int nl = a0.nlimbs;
   if (!acc_set) acc3 = DevBuf(&pool, (size_t)3 * a0.B * nl * N);
+  std::vector<const u64*> pa, pb;
   for (size_t k = 0; k < Ak.size(); k++) {
     need_same(Ak[k], Bk[k]);
-    launch_tensor(T, acc3.p, Ak[k].d.p, Bk[k].d.p, nl, a0.B, acc_set, stream);
-    acc_set = true;
+    need_same(Ak[k], a0);
+    pa.push_back(Ak[k].d.p);
+    pb.push_back(Bk[k].d.p);
   }
+  launch_tensor_sum(T, acc3.p, pa.data(), pb.data(), (int)pa.size(), nl, a0.B, acc_set, stream);
+  acc_set = true;
 }
 // ... and relinearised once
 HeCt HeCtxImpl::relin_sum(const DevBuf& acc3, int level, double scale, int B) {
