@@ -79,16 +79,17 @@ def kernel_digest(kernel):
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, n1):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE counters,
     scaled by a plain copy's reading) recorded with a digest of the kernel's
-    source regions; None when absent or the kernel has changed since."""
+    source regions and the baby-step count the launches had; None when absent
+    or either differs."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     k = rec.get("kernels", {}).get(kernel)
-    if k is None or k.get("source_sha256") != kernel_digest(kernel):
+    if k is None or k.get("source_sha256") != kernel_digest(kernel) or k.get("n1") != n1:
         return None
     return k["bytes_per_launch"]
 
@@ -161,6 +162,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving run (0: skip it)")
     ap.add_argument("--pca-components", type=int, default=8, help="components of the PCA run (0: skip it)")
+    ap.add_argument("--n1", type=int, default=64,
+                    help="baby steps of Z and T and the block size of the column/row shifts (0: the library's "
+                         "default, 16 for d = 128); 64 measured fastest for d = 128 (130 keys, 48.6 GiB resident)")
     ap.add_argument("--serve-cov-samples", type=int, default=256,
                     help="rows of the serving mix's covariance job (the workload's has 60000: about a minute more)")
     ap.add_argument("--big-covariance", type=int, default=0, metavar="S",
@@ -183,7 +187,9 @@ def main():
     d, B = args.d, args.batch
     log(f"[bench] context N=2^{chain.log_n}, {len(chain.q_bits)} Q primes, {len(chain.p_bits)} P primes")
     ctx = he.chain_context(chain, seed=1)
-    steps = ctx.matmul_rot_steps(d)
+    # the product's geometry: baby steps of Z and T, blocks of the shifts
+    geo = {"n1_z": args.n1, "n1_t": args.n1} if args.n1 > 0 else {}
+    steps = ctx.matmul_rot_steps(d, dict(geo) if geo else None)
     t0 = time.perf_counter()
     ctx.keygen(steps)
     log(f"[bench] keygen: {len(steps)} rotation keys + relin in {time.perf_counter() - t0:.1f} s")
@@ -196,7 +202,7 @@ def main():
     BATCHED, LAZY, FUSED, GRAPH = 1, 2, 4, 8
     relin = "paper" if args.paper_relin else "lazy"
     head = {"flags": BATCHED | (0 if args.paper_relin else LAZY | (0 if args.two_roundings else FUSED)) |
-            (0 if args.no_graph else GRAPH)}
+            (0 if args.no_graph else GRAPH), **geo}
 
     class Names(dict):
         def __missing__(self, f):
@@ -237,7 +243,7 @@ def main():
         from paper_2305_17341_amd import autotune
         # launched one kernel at a time: a recording would keep the shapes it
         # was made with (the headline records after the knobs are set)
-        tune_opts = {"flags": head["flags"] & ~GRAPH}
+        tune_opts = {"flags": head["flags"] & ~GRAPH, **geo}
         warm = ctx.matmul_batch(cA, cB, [d] * B, opts=tune_opts)   # plaintext caches
         ctx.sync()
         del warm
@@ -246,8 +252,8 @@ def main():
 
     plain_outs = None
     if not args.no_plain:
-        t_plain, lat_plain, plain_outs = timed(None, False)
-        t_bp, lat_bp, bp_outs = timed({"flags": BATCHED}, False)
+        t_plain, lat_plain, plain_outs = timed({"flags": 0, **geo}, False)
+        t_bp, lat_bp, bp_outs = timed({"flags": BATCHED, **geo}, False)
         # batching gives the one-at-a-time residues
         same = all(np.array_equal(p.export(), q.export()) for p, q in zip(plain_outs, bp_outs))
         del bp_outs
@@ -257,7 +263,7 @@ def main():
     # the same steps again, launched one kernel at a time with HIP events
     # around every launch: the kernel table, the roofline's per-launch
     # durations and the operation counts come from these
-    eager = {"flags": head["flags"] & ~GRAPH}
+    eager = {"flags": head["flags"] & ~GRAPH, **geo}
     c0 = ctx.op_counts()
     t_prof, _, _ = timed(eager, True, warmup=False)
     c1 = ctx.op_counts()
@@ -272,7 +278,7 @@ def main():
     per_mm = {k: (c1[k] - c0[k]) / n_mm for k in c0}
     # accuracy of a warm-up output against FP64; the headline path batched == alone
     err = float(np.max(np.abs(ctx.decrypt(outs[0], d * d) - (As[0] @ Bs[0]).ravel())))
-    alone = ctx.matmul(cA[0], cB[0], d, opts={"flags": head["flags"] & ~(BATCHED | GRAPH)})
+    alone = ctx.matmul(cA[0], cB[0], d, opts={"flags": head["flags"] & ~(BATCHED | GRAPH), **geo})
     head_same = bool(np.array_equal(alone.export(), outs[0].export()))
     del outs, plain_outs, alone
 
@@ -297,7 +303,7 @@ def main():
     avg_ms = ms / max(launches, 1)
     bytes_per_launch = nbytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, args.n1)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),
@@ -322,7 +328,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"he_matmul d={d} at N=2^16 (q0 60b + 30x40b, P 3x60b, levels 30->27), "
                                f"uniform[-1,1] FP64 inputs", "d": d, "log_n": chain.log_n, "batch": B,
-                   "path": names[head["flags"]], "relinearisation": relin},
+                   "path": names[head["flags"]], "relinearisation": relin,
+                   "n1": args.n1 if args.n1 > 0 else None, "rotation_keys": len(steps)},
         "batched_residues_equal_alone": head_same,
         "autotune": tuned,
         "plain": None if args.no_plain else {

@@ -88,3 +88,27 @@ def test_lazy_matmul_128_full_size():
         assert err < BOUND
     alone = ctx.matmul(cA[1], cB[1], n, {"flags": LAZY})
     assert np.array_equal(alone.export(), outs[1].export())
+
+
+@pytest.mark.parametrize("n1", [8, 16])
+def test_wide_baby_steps_bit_exact(oracle_mod, n1):
+    """the headline's geometry at small size: baby steps n1 = n/2 and n (one
+    block of column and row shifts), lazy relinearisation and one rounding,
+    batched; residues equal to the oracle's"""
+    from paper_2305_17341_amd import he
+    n = 16
+    geo = {"n1_z": n1, "n1_t": n1}
+    ctx = he.chain_context(DEEP, seed=23)
+    steps = sorted(ctx.matmul_rot_steps(n, geo))
+    ctx.keygen(steps)
+    o = oracle_mod.Oracle(DEEP.log_n, DEEP.q_bits, DEEP.p_bits, seed=23)
+    o.keygen(rot_steps=steps)
+    A, B = I.uniform_matrix(31, n), I.uniform_matrix(32, n)
+    ca, cb = ctx.encrypt_matrix(A, nonce=5), ctx.encrypt_matrix(B, nonce=6)
+    outs = ctx.matmul_batch([ca, cb], [cb, ca], [n] * 2, dict(geo, flags=BATCHED | LAZY | 4))
+    want = o.matmul(o.encrypt(A.ravel(), nonce=5), o.encrypt(B.ravel(), nonce=6), n, n1, n1, lazy=True,
+                    fused_rescale=True)
+    assert outs[0].level == want.level and outs[0].scale == want.scale
+    assert np.array_equal(outs[0].export(), want.data())
+    assert np.max(np.abs(ctx.decrypt(outs[0], n * n) - (A @ B).ravel())) < BOUND
+    assert np.max(np.abs(ctx.decrypt(outs[1], n * n) - (B @ A).ravel())) < BOUND
