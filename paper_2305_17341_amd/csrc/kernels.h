@@ -55,7 +55,7 @@ void launch_mul_bcast(const DeviceTables& T, u64* out, const u64* a, const u64* 
 void launch_mul_acc(const DeviceTables& T, u64* acc, const u64* a, const u64* b, int nlimbs, int b_limbs,
                     const LimbMap& m, hipStream_t s);
 // out (+)= sum_t a[t] * p[t] (p[t] broadcast with period b_limbs), nterms pairs
-#define SUM_MAX_TERMS 16
+#define SUM_MAX_TERMS 64  // at most 64 signed products below q < 2^46: sums below 2^52
 void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms,
                     int nlimbs, int b_limbs, const LimbMap& m, bool accumulate, hipStream_t s);
 // outs[g] = sum_t a[t] * p[g * nterms + t] for g < nouts (null p: term absent);

@@ -1166,7 +1166,7 @@ __global__ void k_mul_sum(u64* out, SumTerms t, int nterms, int accumulate, int 
   const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
   u64 an = t.a[0][o], pn = t.p[0][op];
   if (mk.bits <= F64_LAZY_BITS) {
-    // up to 16 signed exact products and the old value, reduced once
+    // up to 63 signed exact products and the old value, reduced once
     const double q = mk.qf, qi = mk.qinvf;
     double acc = accumulate ? u2d(out[o]) : 0.0;
     for (int j = 0; j < nterms; j++) {
@@ -1193,8 +1193,10 @@ __global__ void k_mul_sum(u64* out, SumTerms t, int nterms, int accumulate, int 
 }
 void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms, int nl,
                     int bl, const LimbMap& m, bool accumulate, hipStream_t s) {
-  for (int t0 = 0; t0 < nterms; t0 += SUM_MAX_TERMS) {
-    const int nt = std::min(nterms - t0, SUM_MAX_TERMS);
+  // 63 terms a pass: with the old value, 64 summands below q < 2^46 each
+  constexpr int TERMS = SUM_MAX_TERMS - 1;
+  for (int t0 = 0; t0 < nterms; t0 += TERMS) {
+    const int nt = std::min(nterms - t0, TERMS);
     const bool acc = accumulate || t0 > 0;
     SumTerms t;
     for (int j = 0; j < nt; j++) {
@@ -1232,7 +1234,7 @@ __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map
 #pragma unroll
   for (int g = 0; g < G; g++) pn[g] = t.p[g][0] ? t.p[g][0][op] : 0;
   if (mk.bits <= F64_LAZY_BITS) {
-    // signed exact products summed per output (at most 16), reduced once
+    // signed exact products summed per output (at most 64), reduced once
     const double q = mk.qf, qi = mk.qinvf;
     double acc[G];
 #pragma unroll
