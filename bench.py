@@ -164,7 +164,7 @@ def main():
     ap.add_argument("--pca-components", type=int, default=8, help="components of the PCA run (0: skip it)")
     ap.add_argument("--n1", type=int, default=64,
                     help="baby steps of Z and T and the block size of the column/row shifts (0: the library's "
-                         "default, 16 for d = 128); 64 measured fastest for d = 128 (130 keys, 48.6 GiB resident)")
+                         "default, 16 for d = 128); 64 measured fastest for d = 128 (130 keys, 47.8 GiB resident)")
     ap.add_argument("--serve-cov-samples", type=int, default=256,
                     help="rows of the serving mix's covariance job (the workload's has 60000: about a minute more)")
     ap.add_argument("--big-covariance", type=int, default=0, metavar="S",
