@@ -79,17 +79,19 @@ def kernel_digest(kernel):
     return h.hexdigest()
 
 
-def measured_traffic(kernel, n1):
+def measured_traffic(kernel, n1, knobs):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE counters,
     scaled by a plain copy's reading) recorded with a digest of the kernel's
-    source regions and the baby-step count the launches had; None when absent
-    or either differs."""
+    source regions, the baby-step count and the launch knobs the launches
+    had; None when absent or any of them differs."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     k = rec.get("kernels", {}).get(kernel)
     if k is None or k.get("source_sha256") != kernel_digest(kernel) or k.get("n1") != n1:
+        return None
+    if any(knobs.get(name) != v for name, v in k.get("knobs", {}).items()):
         return None
     return k["bytes_per_launch"]
 
@@ -303,7 +305,7 @@ def main():
     avg_ms = ms / max(launches, 1)
     bytes_per_launch = nbytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom, args.n1)
+    traffic = measured_traffic(dom, args.n1, {k: he.knob_get(k) for k in autotune_knobs()})
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),

@@ -299,7 +299,7 @@ he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d,
 
 /* Launch-shape knobs (process-wide; they regroup work into launches and never
  * change a residue): "ms_members" (1..8, batch members per key inner product
- * launch), "mr_members" (1..8) and "mr_rotations" (1..16) (members and
+ * launch), "mr_members" (1..8) and "mr_rotations" (1..64) (members and
  * rotations per multi-rotation launch), "ntt_interleave" (0/1: the NTT's
  * block pass visits the limbs of one modulus back to back, so their twiddles
  * come from L2) and "ew_interleave" (0/1: the same for the limbs that share a

@@ -11,7 +11,7 @@ from . import he
 
 CANDIDATES = {
     "mr_members": (2, 4, 8),
-    "mr_rotations": (4, 8, 16),
+    "mr_rotations": (4, 8, 16, 32, 64),
     "ms_members": (4, 8),
     "ntt_interleave": (0, 1),
     "ew_interleave": (0, 1),

@@ -117,7 +117,7 @@ void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u6
 // outs[r] (each [2][batch][nqp][N]); digits read from HBM once per launch.
 // With masks (plaintexts [nqp][N] in R_{Q_l P}, one per rotation) the outputs
 // are mask (.) rotation, added onto outs[r] when `accumulate`.
-#define MR_MAX 16
+#define MR_MAX 64
 void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
                         const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
                         int batch, hipStream_t s, const u64* const* masks = nullptr, bool accumulate = false);

@@ -21,7 +21,7 @@ namespace {
 struct Knobs {
   int ms_members = 8;   // batch members per key-inner-product launch (1..8)
   int mr_members = 8;   // batch members per multi-rotation launch (1..8)
-  int mr_rotations = 16;  // rotations per multi-rotation launch (1..16)
+  int mr_rotations = 64;  // rotations per multi-rotation launch (1..64)
   int ntt_interleave = 0;  // block passes visit limbs of one modulus back to back (0/1)
   int ew_interleave = 1;   // plaintext-broadcast sums visit the limbs sharing a plaintext back to back (0/1)
   int cov_row_blocks = 4;  // row blocks of a covariance stacked into one batch (1..8)
@@ -32,7 +32,7 @@ bool knob_set(const char* name, int v) {
   std::string n(name);
   if (n == "ms_members" && v >= 1 && v <= 8) g_knobs.ms_members = v;
   else if (n == "mr_members" && v >= 1 && v <= 8) g_knobs.mr_members = v;
-  else if (n == "mr_rotations" && v >= 1 && v <= 16) g_knobs.mr_rotations = v;
+  else if (n == "mr_rotations" && v >= 1 && v <= MR_MAX) g_knobs.mr_rotations = v;
   else if (n == "ntt_interleave" && (v == 0 || v == 1)) g_knobs.ntt_interleave = v;
   else if (n == "ew_interleave" && (v == 0 || v == 1)) g_knobs.ew_interleave = v;
   else if (n == "cov_row_blocks" && v >= 1 && v <= 8) g_knobs.cov_row_blocks = v;

@@ -66,7 +66,7 @@ def test_knobs_host_side():
                 assert he.knob_get(name) == v
         finally:
             he.knob_set(name, old)
-    for name, bad in [("ms_members", 0), ("ms_members", 9), ("mr_rotations", 17), ("ntt_interleave", 2),
+    for name, bad in [("ms_members", 0), ("ms_members", 9), ("mr_rotations", 65), ("ntt_interleave", 2), ("mr_group", 3),
                       ("ew_interleave", -1), ("no_such_knob", 1)]:
         with pytest.raises(he.HeError) as e:
             he.knob_set(name, bad)
