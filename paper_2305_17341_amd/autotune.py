@@ -19,10 +19,12 @@ CANDIDATES = {
 }
 
 
-def autotune(ctx, cA, cB, d, opts=None, candidates=CANDIDATES, log=None):
+def autotune(ctx, cA, cB, d, opts=None, candidates=CANDIDATES, log=None, margin=0.01):
     """Coordinate descent over the knobs, one batched step per candidate
-    value (the plaintext caches must be warm).  Leaves the best values set
-    and returns (best, timings in ms)."""
+    value (the plaintext caches must be warm).  A knob leaves its current
+    value only for one at least `margin` faster, so that timing noise does
+    not flip it.  Leaves the chosen values set and returns (best, timings in
+    ms)."""
     best = {k: he.knob_get(k) for k in candidates}
     timings = {}
     for name, values in candidates.items():
@@ -35,7 +37,9 @@ def autotune(ctx, cA, cB, d, opts=None, candidates=CANDIDATES, log=None):
             ctx.sync()
             res[v] = 1e3 * (time.perf_counter() - t0)
             del outs
-        best[name] = min(res, key=res.get)
+        fastest = min(res, key=res.get)
+        if best[name] not in res or res[fastest] < (1.0 - margin) * res[best[name]]:
+            best[name] = fastest
         he.knob_set(name, best[name])
         timings[name] = {str(k): round(v, 2) for k, v in res.items()}
         if log:
