@@ -218,7 +218,7 @@ def accuracy_bench(cases=None, seed=7, log=print, ctx=None):
             "rows": rows}
 
 
-def covariance_bench(s=60000, t=256, seed=13, stacked=(4, 8), log=print):
+def covariance_bench(s=60000, t=256, seed=13, stacked=(4, 8), log=print, n1=64):
     """The serving workload's large covariance job on its own: an s x t
     uniform[0,1] dataset, centred by the client, encrypted as ceil(s/128) x
     ceil(t/128) blocks of 128 x 128 at N = 2^16; X^T X / s accumulated
@@ -226,12 +226,14 @@ def covariance_bench(s=60000, t=256, seed=13, stacked=(4, 8), log=print):
     for ModDown and Rescale), with `stacked` row blocks per batch in turn
     (the "cov_row_blocks" knob).  Reports the client's encryption time, each
     covariance's time and device peak, and the largest error of the
-    decrypted blocks against FP64."""
+    decrypted blocks against FP64.  n1: baby steps of Z and T and the shift
+    blocks of the products (0: the library's default)."""
     from . import inputs as I
     n = 128
     k, rb = -(-t // n), -(-s // n)
+    geo = {"n1_z": n1, "n1_t": n1} if n1 else {}
     ctx = he.chain_context(I.LARGE, seed=seed)
-    ctx.keygen(sorted(set(ctx.matmul_rot_steps(n)) | set(ctx.transpose_rot_steps(n))))
+    ctx.keygen(sorted(set(ctx.matmul_rot_steps(n, dict(geo) or None)) | set(ctx.transpose_rot_steps(n))))
     X = I.centre(I.dataset(seed, s, t))
     blk = I.blocks(X, n)
     t0 = time.perf_counter()
@@ -250,7 +252,7 @@ def covariance_bench(s=60000, t=256, seed=13, stacked=(4, 8), log=print):
             ctx.trim()
             live0, _, _ = ctx.mem_info()
             t0 = time.perf_counter()
-            cov = ctx.covariance(cts, rb, k, n, s, {"flags": 2 | 4})
+            cov = ctx.covariance(cts, rb, k, n, s, {"flags": 2 | 4, **geo})
             ctx.sync()
             t_cov = time.perf_counter() - t0
             _, _, peak = ctx.mem_info()
@@ -259,7 +261,7 @@ def covariance_bench(s=60000, t=256, seed=13, stacked=(4, 8), log=print):
                 a, b = divmod(i, k)
                 got = ctx.decrypt(c, n * n).reshape(n, n)
                 err = max(err, float(np.max(np.abs(got - ref[a * n:(a + 1) * n, b * n:(b + 1) * n]))))
-            run = {"row_blocks_per_batch": g, "covariance_s": round(t_cov, 2),
+            run = {"row_blocks_per_batch": g, "n1": n1 or None, "covariance_s": round(t_cov, 2),
                    "products_per_s": round(rb * k * (k + 1) / 2 / t_cov, 2),
                    "device_peak_gib": round((peak - live0) / 2**30, 1), "max_abs_err": err}
             runs.append(run)
