@@ -180,7 +180,7 @@ def main():
                     help="device copies of one top-level ciphertext at the end (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library runs on one device",
               file=sys.stderr)
         sys.exit(2)
 
