@@ -152,6 +152,10 @@ struct DevPool {
   void* (*user_alloc)(size_t, void*) = nullptr;
   void (*user_release)(void*, void*) = nullptr;
   void* user = nullptr;
+  // the stream every block of this pool was last used on (the owning
+  // context's): trim waits for it alone, so trimming one context does not
+  // stall the others
+  hipStream_t stream = nullptr;
   // while set, allocations come from (and blocks of it return to) this pool:
   // the private arena of a HIP graph being recorded
   DevPool* redirect = nullptr;
@@ -164,6 +168,7 @@ struct DevPool {
   void* get(size_t bytes);
   void put(void* p);
   void trim();
+  void wait();
   ~DevPool();
 };
 

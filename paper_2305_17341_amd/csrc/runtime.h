@@ -61,7 +61,11 @@ struct MmGraph {
   MmGraph() = default;
   MmGraph(const MmGraph&) = delete;
   MmGraph& operator=(const MmGraph&) = delete;
+  // The owner synchronises the stream a replay ran on before destroying a
+  // recording (HIP leaves destroying an executable graph that is still
+  // running undefined); the device-wide wait here covers any other path.
   ~MmGraph() {
+    if (exec) (void)hipDeviceSynchronize();
     outs.clear();
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -145,6 +149,7 @@ struct HeCtxImpl {
   void hoisted_masked(const HeCt& x, const u64* digits, const std::vector<u64>& gs, const std::vector<u64*>& outs,
                       const std::vector<const u64*>& masks, bool accumulate);
   HeCt moddown(const HeCt& x, int out_level = -1);
+  void moddown_to(const HeCt& x, int out_level, u64* out);
   // ModDown and Rescale as one rounding by P q_l (a variant)
   HeCt moddown_rescale(const HeCt& x, int out_level = -1);
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);

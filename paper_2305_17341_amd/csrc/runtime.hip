@@ -70,8 +70,13 @@ void DevPool::put(void* p) {
   free_.insert({sz, p});
   bytes_cached += sz;
 }
+void DevPool::wait() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  else (void)hipDeviceSynchronize();
+}
 void DevPool::trim() {
-  (void)hipDeviceSynchronize();
+  if (free_.empty()) return;
+  wait();
   for (auto& kv : free_) {
     if (user_release) user_release(kv.second, user);
     else (void)hipFree(kv.second);
@@ -80,6 +85,8 @@ void DevPool::trim() {
   bytes_cached = 0;
 }
 DevPool::~DevPool() {
+  if (free_.empty() && live_.empty()) return;
+  wait();
   trim();
   for (auto& kv : live_) {
     if (user_release) user_release(kv.first, user);
@@ -146,6 +153,9 @@ HeCtxImpl::~HeCtxImpl() {
     for (auto& t : row) (void)t;
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  // the pool is destroyed after this body: its last trim must not wait on a
+  // stream that is gone (or, for a caller's stream, may be gone)
+  pool.stream = nullptr;
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -308,6 +318,7 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
     hip_check(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "stream");
     own_stream = true;
   }
+  pool.stream = stream;
   hip_check(hipEventCreate(&ev0), "event");
   hip_check(hipEventCreate(&ev1), "event");
 
@@ -772,6 +783,12 @@ HeCt HeCtxImpl::moddown(const HeCt& x, int out_level) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   if (out_level < 0) out_level = x.level;
   if (out_level > x.level) fail(HE_ELEVEL, "moddown cannot raise the level");
+  HeCt c = ct_new(out_level, false, x.scale, x.B);
+  moddown_to(x, out_level, c.d.p);
+  return c;
+}
+// the same into out [2][B][out_level + 1][N]
+void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out) {
   int nq = nq_of(out_level), nqp = nqp_of(x.level);
   const int np = (int)x.polys();
   DevBuf pc(&pool, (size_t)np * alpha * N);
@@ -781,17 +798,15 @@ HeCt HeCtxImpl::moddown(const HeCt& x, int out_level) {
   for (int k = 0; k < alpha; k++) pm.idx[k] = (short)(L + 1 + k);
   launch_ntt(T, pc.p, np * alpha, pm, true, stream);
   DevBuf y(&pool, (size_t)np * nq * N);
-  HeCt c = ct_new(out_level, false, x.scale, x.B);
   if (fused_conv) {
     DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
-    if (!launch_moddown_fused(T, pc.p, nq, np, down, x.d.p, nqp, pinv.p, c.d.p, y.p, V.p, stream))
+    if (!launch_moddown_fused(T, pc.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
   } else {
     launch_fbc_to_q(T, y.p, pc.p, nq, np, down, stream);
-    launch_ntt_fwd_sub(T, y.p, nq, np, qmap(nq), x.d.p, nqp, pinv.p, c.d.p, stream);
+    launch_ntt_fwd_sub(T, y.p, nq, np, qmap(nq), x.d.p, nqp, pinv.p, out, stream);
   }
   n_moddown += x.B;
-  return c;
 }
 
 // ModDown and the Rescale after it as one rounding: x in R_{Q_l P} ->
@@ -1505,7 +1520,12 @@ std::vector<HeCt> HeCtxImpl::matmul_graph(const std::vector<const HeCt*>& a, con
   if (it != graphs.end()) {
     graphs.splice(graphs.begin(), graphs, it);
   } else {
-    if (graphs.size() >= 4) graphs.pop_back();
+    if (graphs.size() >= 4) {
+      // the evicted recording may still be replaying, and the copies out of
+      // its arena may still be in flight
+      hip_check(hipStreamSynchronize(stream), "graph eviction");
+      graphs.pop_back();
+    }
     auto run = [&](std::vector<HeCt>* keep) {
       HeCt sa = stack(a), sb = stack(b);
       HeCt r = matmul(sa, sb, n, n1z, n1t, npz, npt, lazy, fused_rs);
@@ -1521,6 +1541,7 @@ std::vector<HeCt> HeCtxImpl::matmul_graph(const std::vector<const HeCt*>& a, con
     g.arena->user_release = pool.user_release;
     g.arena->user = pool.user;
     g.arena->exact = true;
+    g.arena->stream = stream;
     pool.redirect = g.arena.get();
     try {
       run(nullptr);
