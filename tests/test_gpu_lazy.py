@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from tests.fullcrt import FullDecryptor
 
 pytestmark = pytest.mark.gpu
 
@@ -70,7 +71,7 @@ def test_lazy_covariance_bit_exact(pair):
         assert np.max(np.abs(got - ref[a * n:(a + 1) * n, b * n:(b + 1) * n])) < BOUND
 
 
-def test_lazy_matmul_128_full_size():
+def test_lazy_matmul_128_full_size(oracle_mod):
     from paper_2305_17341_amd import he
     ch = I.LARGE
     n = 128
@@ -81,9 +82,10 @@ def test_lazy_matmul_128_full_size():
     cA = [ctx.encrypt_matrix(a, nonce=1 + i) for i, a in enumerate(As)]
     cB = [ctx.encrypt_matrix(b, nonce=101 + i) for i, b in enumerate(Bs)]
     outs = ctx.matmul_batch(cA, cB, [n] * 3, {"flags": LAZY | BATCHED})
+    fd = FullDecryptor(oracle_mod, ch, 31)
     for i in range(3):
         assert outs[i].level == ch.top_level - 3
-        err = np.max(np.abs(ctx.decrypt(outs[i], n * n) - (As[i] @ Bs[i]).ravel()))
+        err = np.max(np.abs(fd.decrypt(outs[i], n * n) - (As[i] @ Bs[i]).ravel()))
         print(f"lazy 128x128 product {i}: max abs error {err:.3e}", flush=True)
         assert err < BOUND
     alone = ctx.matmul(cA[1], cB[1], n, {"flags": LAZY})
