@@ -185,6 +185,32 @@ he_status he_mult(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
 he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out);
 he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out);
 he_status he_drop_level(he_ctx* ctx, const he_ct* a, uint32_t level, he_ct** out);
+
+/* Rotation that allocates no device memory, for callers that cannot call
+ * hipMalloc: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Same residues as he_rotate(ctx, a, step).
+ *   out  an existing ciphertext (from any call of this library) at a's level
+ *        and batch size; its residues are overwritten and its scale set to
+ *        a's.  out == a is allowed.
+ *   Workspace: a file-scope device array of HE_NOALLOC_WS_BYTES per GPU,
+ *        allocated when the library's code is loaded and held until the
+ *        process ends.  Every temporary of the rotation (Decompose digits,
+ *        the R_{Q_l P} hoisted rotation, ModDown's lift) lives there; no
+ *        kernel reads a workspace word before writing it, so nothing needs
+ *        clearing.  All contexts on one GPU share that GPU's array, which
+ *        keeps the last call's contents: calls that overlap on one GPU
+ *        (different contexts on different host threads, or streams running
+ *        concurrently) race and must be serialised by the caller.
+ *   Errors: HE_EINVAL if the rotation at a's level needs more workspace than
+ *        HE_NOALLOC_WS_BYTES (he_rotate_workspace_bytes gives the need; about
+ *        48 MiB at N = 2^15 with 15 Q and 3 P primes, 288 MiB at N = 2^16
+ *        with 31 and 3, which is rejected), or if out does not match a;
+ *        HE_EKEY if the step's key is missing (nothing is launched then). */
+#define HE_NOALLOC_WS_BYTES (64ull << 20)
+he_status he_rotate_noalloc(he_ctx* ctx, const he_ct* a, int32_t step, he_ct* out);
+/* Workspace bytes he_rotate_noalloc needs for a single ciphertext at `level`
+ * (host-side arithmetic only). */
+he_status he_rotate_workspace_bytes(const he_ctx* ctx, uint32_t level, size_t* bytes);
 /* PMult by the encoding of z (n slots, replicated) at scale pt_scale */
 he_status he_pmult_slots(he_ctx* ctx, const he_ct* a, const double* z, size_t n, double pt_scale, he_ct** out);
 

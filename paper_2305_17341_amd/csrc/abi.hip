@@ -1,9 +1,17 @@
 // C ABI of the library (include/he_mi355x.h): argument checks, error
 // translation and ownership; all computation is in runtime.hip / kernels.hip.
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <set>
 
 #include "runtime.h"
+
+// Workspace of the allocation-free entry points: one copy per device, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): it uses the
+// address hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) u64 scratch[HE_NOALLOC_WS_BYTES / 8];
 
 namespace {
 template <class F>
@@ -66,6 +74,22 @@ void check_ct(const he_ctx* c, const he_ct* a) {
   need(a != nullptr, "null ciphertext");
   need(a->ctx == c, "ciphertext belongs to another context");
 }
+// device -> that device's address of `scratch`, looked up once per device
+std::mutex g_ws_mu;
+std::map<int, void*> g_ws_ptr;
+void* workspace_of_current_device(int* dev_out) {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "current device");
+  *dev_out = dev;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto it = g_ws_ptr.find(dev);
+  if (it != g_ws_ptr.end()) return it->second;
+  void* p = nullptr;
+  hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "workspace address");
+  if (!p) fail(HE_EDEVICE, "workspace address is null");
+  g_ws_ptr[dev] = p;
+  return p;
+}
 struct MmOpts {
   int n1z, n1t, npz, npt;
   bool lazy, fused;
@@ -100,6 +124,7 @@ he_status he_ctx_create(const he_params* params, const he_device* dev, uint64_t 
     }
     he_ctx* c = new he_ctx;
     try {
+      c->impl.noalloc_ws = workspace_of_current_device(&c->impl.device);
       c->impl.init(params, dev, seed);
     } catch (...) {
       delete c;
@@ -306,6 +331,31 @@ he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out) {
     auto lk = hold(ctx);
     check_ct(ctx, a);
     *out = wrap(ctx, ctx->impl.rotate(a->ct, step));
+  });
+}
+he_status he_rotate_noalloc(he_ctx* ctx, const he_ct* a, int32_t step, he_ct* out) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    check_ct(ctx, a);
+    check_ct(ctx, out);
+    need(!a->ct.qp && !out->ct.qp, "rotation of an R_QP element");
+    need(out->ct.level == a->ct.level && out->ct.B == a->ct.B,
+         "the output must be a ciphertext at the input's level");
+    HeCtxImpl& c = ctx->impl;
+    const size_t need_bytes = c.rotate_workspace_bytes(a->ct.level, a->ct.B);
+    if (need_bytes > HE_NOALLOC_WS_BYTES)
+      fail(HE_EINVAL, "rotation at this level needs " + std::to_string(need_bytes) +
+                          " bytes of workspace; the allocation-free entry point has " +
+                          std::to_string((size_t)HE_NOALLOC_WS_BYTES));
+    c.rotate_into(a->ct, step, out->ct.d.p, c.noalloc_ws, HE_NOALLOC_WS_BYTES);
+    out->ct.scale = a->ct.scale;
+  });
+}
+he_status he_rotate_workspace_bytes(const he_ctx* ctx, uint32_t level, size_t* bytes) {
+  return guard_host([&] {
+    need(ctx != nullptr && bytes != nullptr, "null argument");
+    need((int)level <= ctx->impl.L, "level out of range");
+    *bytes = ctx->impl.rotate_workspace_bytes((int)level, 1);
   });
 }
 he_status he_drop_level(he_ctx* ctx, const he_ct* a, uint32_t level, he_ct** out) {

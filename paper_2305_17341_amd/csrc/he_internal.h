@@ -165,6 +165,10 @@ struct DevPool {
   // serve only cached blocks of exactly the requested size (an arena sized by
   // one run serves a repeat of the same run)
   bool exact = false;
+  // a fixed device region handed out front to back, never given back (the
+  // workspace of the allocation-free entry points; reset by the caller)
+  char* bump_base = nullptr;
+  size_t bump_cap = 0, bump_off = 0;
   void* get(size_t bytes);
   void put(void* p);
   void trim();

@@ -84,6 +84,10 @@ struct HeCtxImpl {
   u64 seed = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // device the context was created on, and that device's copy of the
+  // allocation-free entry points' workspace
+  int device = 0;
+  void* noalloc_ws = nullptr;
   DevPool pool;
   DeviceTables T;
   std::vector<ModConst> mc;
@@ -155,6 +159,8 @@ struct HeCtxImpl {
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);
   HeCt rotate(const HeCt& x, long step);
+  size_t rotate_workspace_bytes(int level, int B) const;
+  void rotate_into(const HeCt& x, long step, u64* out, void* ws, size_t ws_bytes);
   HeCt pmult_int(const HeCt& a, const i64* m_dev, double pt_scale);
   void gather_limbs(u64* dst, const HeCt& x, int first, int count);
   HeCt stack(const std::vector<const HeCt*>& xs);

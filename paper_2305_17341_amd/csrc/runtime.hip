@@ -28,6 +28,13 @@ void* DevPool::get(size_t bytes) {
   if (redirect) return redirect->get(bytes);
   if (bytes == 0) bytes = 8;
   bytes = (bytes + 255) & ~(size_t)255;
+  if (bump_base) {
+    if (bytes > bump_cap - bump_off) fail(HE_ENOMEM, "allocation-free workspace exhausted");
+    void* p = bump_base + bump_off;
+    bump_off += bytes;
+    peak = std::max(peak, bump_off);
+    return p;
+  }
   auto it = free_.lower_bound(bytes);
   if (it != free_.end() && it->first <= (exact ? bytes : bytes + bytes / 4)) {
     void* p = it->second;
@@ -878,6 +885,47 @@ HeCt HeCtxImpl::rotate(const HeCt& x, long step) {
   DevBuf dig = decompose(x.poly(1), x.level, x.B);
   HeCt h = hoisted(x, dig.p, g);
   return moddown(h);
+}
+
+// device words a rotation of B members at `level` takes besides its input and
+// output (Decompose's coefficients and digits, the R_{Q_l P} hoisted
+// rotation, ModDown's special-prime limbs, lift and quotient), each block
+// rounded up to the pool's 256-byte granule
+size_t HeCtxImpl::rotate_workspace_bytes(int level, int B) const {
+  const size_t nq = nq_of(level), nqp = nqp_of(level), bl = beta_at(level), np = 2 * (size_t)B;
+  const size_t blocks[] = {B * nq, B * bl * nqp, np * nqp, np * alpha, np * nq, np * (alpha + 1)};
+  size_t total = 0;
+  for (size_t w : blocks) total += (w * N * 8 + 255) & ~(size_t)255;
+  return total;
+}
+
+// Rotation into a caller's buffer with every temporary taken from `ws`
+// (bytes of device memory): no pool block is requested.  The residues are
+// those of rotate().
+void HeCtxImpl::rotate_into(const HeCt& x, long step, u64* out, void* ws, size_t ws_bytes) {
+  if (x.qp) fail(HE_EINVAL, "rotation of an R_QP element");
+  const u64 g = galois(step);
+  if (g == 1) {
+    if (out != x.d.p)
+      hip_check(hipMemcpyAsync(out, x.d.p, x.d.words * 8, hipMemcpyDeviceToDevice, stream), "copy");
+    return;
+  }
+  if (rotate_workspace_bytes(x.level, x.B) > ws_bytes) fail(HE_EINVAL, "rotation needs a larger workspace");
+  key(g);  // a missing key fails before anything is launched
+  DevPool ws_pool;
+  ws_pool.bump_base = (char*)ws;
+  ws_pool.bump_cap = ws_bytes;
+  DevPool* saved = pool.redirect;
+  pool.redirect = &ws_pool;
+  try {
+    DevBuf dig = decompose(x.poly(1), x.level, x.B);
+    HeCt h = hoisted(x, dig.p, g);
+    moddown_to(h, x.level, out);
+  } catch (...) {
+    pool.redirect = saved;
+    throw;
+  }
+  pool.redirect = saved;
 }
 
 HeCt HeCtxImpl::pmult_int(const HeCt& a, const i64* m_dev, double pt_scale) {

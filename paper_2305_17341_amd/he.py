@@ -15,6 +15,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhe_mi355x.so")
 
 HE_OK = 0
+# bytes of the per-GPU workspace of the allocation-free entry points (HE_NOALLOC_WS_BYTES)
+NOALLOC_WS_BYTES = 64 << 20
 STATUS = {0: "HE_OK", -1: "HE_EINVAL", -2: "HE_ELEVEL", -3: "HE_ESCALE", -4: "HE_EKEY", -5: "HE_ENOMEM",
           -6: "HE_EDEVICE", -7: "HE_EBUSY", -8: "HE_ENEEDREFRESH"}
 
@@ -27,6 +29,7 @@ EXPORTS = [
     "he_mem_info", "he_trim", "he_device_memory", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
     "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_smpkeysub_rot_steps", "he_refresh",
     "he_power_rot_steps", "he_power_step", "he_eigen_shift", "he_knob_set", "he_knob_get", "he_last_error",
+    "he_rotate_noalloc", "he_rotate_workspace_bytes",
 ]
 
 # he_refresh_fn: status (he_ct*, void* user)
@@ -89,6 +92,8 @@ def load():
         "he_rescale": [vp, vp, C.POINTER(vp)],
         "he_rotate": [vp, vp, C.c_int32, C.POINTER(vp)],
         "he_drop_level": [vp, vp, C.c_uint32, C.POINTER(vp)],
+        "he_rotate_noalloc": [vp, vp, C.c_int32, vp],
+        "he_rotate_workspace_bytes": [vp, C.c_uint32, C.POINTER(C.c_size_t)],
         "he_pmult_slots": [vp, vp, dblp, C.c_size_t, C.c_double, C.POINTER(vp)],
         "he_lintrans": [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, C.POINTER(vp)],
         "he_lintrans_dcd": [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(vp)],
@@ -285,6 +290,17 @@ class Context:
 
     def rotate(self, a, step):
         return self._ct(load().he_rotate, a.ptr, int(step))
+
+    def rotate_noalloc(self, a, step, out):
+        """Rotation into the existing ciphertext `out` (a's level) with no
+        device allocation: temporaries in the library's per-GPU workspace."""
+        _check(load().he_rotate_noalloc(self.ptr, a.ptr, int(step), out.ptr))
+        return out
+
+    def rotate_workspace_bytes(self, level):
+        n = C.c_size_t()
+        _check(load().he_rotate_workspace_bytes(self.ptr, level, C.byref(n)))
+        return n.value
 
     def drop(self, a, level):
         return self._ct(load().he_drop_level, a.ptr, level)
