@@ -23,6 +23,7 @@
  *   - [x]_q is the centred residue in (-q/2, q/2]; "x mod q" is in [0, q).
  */
 #include <math.h>
+#include <omp.h>
 #include <quadmath.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -1173,6 +1174,18 @@ oc_ct *oc_hoisted_rotate(const oc_ctx *c, const oc_ct *x, i64 step) {
   return r;
 }
 
+/* The same with the digits Decompose(c1) given by the caller (so that the
+ * key inner product can be timed on its own). */
+oc_ct *oc_hoisted_rotate_digits(const oc_ctx *c, const oc_ct *x, const u64 *digits, i64 step) {
+  if (x->qp) return NULL;
+  int err = 0;
+  return hoisted_rot(c, x, digits, oc_galois_of_step(c, step), &err);
+}
+
+/* OpenMP threads of the oracle's loops over limbs (timing runs only) */
+void oc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oc_get_threads(void) { return omp_get_max_threads(); }
+
 /* Rot(c, k) = ModDown(HR(c, 5^k)). */
 oc_ct *oc_rotate(const oc_ctx *c, const oc_ct *x, i64 step) {
   oc_ct *h = oc_hoisted_rotate(c, x, step);
@@ -1724,16 +1737,56 @@ static void free_list(oc_ct **l, int n) {
   free(l);
 }
 
+/* Permutation of the folded A side: C^k applied after Z, output (i, j) takes
+ * A_{i, (i + j + k) mod n} (phi^k(sigma(A)) of Eq. 5 read as one map). */
+static int *perm_phi_sigma(int n, int k) {
+  int *p = (int *)malloc(sizeof(int) * n * n);
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) p[i * n + j] = i * n + (i + j + k) % n;
+  return p;
+}
+void oc_perm_phi_sigma(int n, int k, int *out) {
+  int *p = perm_phi_sigma(n, k);
+  memcpy(out, p, sizeof(int) * n * n);
+  free(p);
+}
+
+/* A side with the masks of C^k folded into Z (section 4.1.1 computes
+ * C^k(Z a) with two masks and a level of its own): phi^k o sigma is a
+ * permutation whose diagonals are C^k's masks times Z's diagonals, with
+ * Z's diagonal indices (in (-n, n)), so A_k = U_k a is one double-hoisted
+ * BSGS transform on a with Z's geometry and keys, one level in all. */
+static oc_ct **side_a_folded(const oc_ctx *c, const oc_ct *ca, int n, int n1z, int *err) {
+  oc_ct **Ak = (oc_ct **)calloc(n, sizeof(oc_ct *));
+  int n2 = ceil_div(n, n1z);
+  for (int k = 0; k < n; k++) {
+    int *p = perm_phi_sigma(n, k);
+    lt_perm U = {n * n, p, NULL};
+    Ak[k] = lintrans(c, ca, &U, 1, n1z, -n2, n2, 0, err);
+    free(p);
+    if (!Ak[k]) {
+      if (!*err) *err = -4;
+      for (int j = 0; j < n; j++) oc_ct_free(Ak[j]);
+      free(Ak);
+      return NULL;
+    }
+  }
+  return Ak;
+}
+
 /* flags: 1 = lazy relinearisation (the n tensors summed, relinearised once),
  * 2 = ModDown and Rescale of the A side as one rounding; both variants of
- * the paper's order */
+ * the paper's order.  4 = the A side with the masks folded into Z
+ * (side_a_folded): two levels in all instead of three (no decomposition of
+ * Z, not with flag 2). */
 oc_ct *oc_matmul_lazy(const oc_ctx *c, const oc_ct *ca, const oc_ct *cb, int n, int n1z, int n1t, int npz,
                       int npt, int flags, int *err) {
-  const int lazy = flags & 1;
+  const int lazy = flags & 1, folded = flags & 4;
   *err = 0;
   if (ca->qp || cb->qp || ca->level != cb->level) { *err = -2; return NULL; }
   if ((u64)n * n > c->N / 2 || n % n1z || n % n1t || npz < 1 || npt < 1) { *err = -1; return NULL; }
-  oc_ct **Ak = side_a(c, ca, n, n1z, npz, flags & 2, err);
+  if (folded && ((flags & 2) || npz < n - 1)) { *err = -1; return NULL; }
+  oc_ct **Ak = folded ? side_a_folded(c, ca, n, n1z, err) : side_a(c, ca, n, n1z, npz, flags & 2, err);
   if (!Ak) return NULL;
   oc_ct **Bk = side_b(c, cb, n, n1t, npt, err);
   if (!Bk) { free_list(Ak, n); return NULL; }

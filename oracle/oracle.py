@@ -111,6 +111,10 @@ def lib():
         L.oc_moddown_rescale.argtypes = [C.c_void_p, C.c_void_p]
         L.oc_hoisted_rotate.restype = C.c_void_p
         L.oc_hoisted_rotate.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+        L.oc_hoisted_rotate_digits.restype = C.c_void_p
+        L.oc_hoisted_rotate_digits.argtypes = [C.c_void_p, C.c_void_p, u64p, C.c_int64]
+        L.oc_set_threads.argtypes = [C.c_int]
+        L.oc_get_threads.argtypes = []
         L.oc_rotate.restype = C.c_void_p
         L.oc_rotate.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         for name in ("oc_lt_sigma", "oc_lt_tau"):
@@ -138,10 +142,20 @@ def lib():
         L.oc_covariance.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_uint64,
                                     C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
         L.oc_perm.argtypes = [C.c_int, C.c_int, intp]
+        L.oc_perm_phi_sigma.argtypes = [C.c_int, C.c_int, intp]
         L.oc_counts_reset.argtypes = []
         L.oc_counts_get.argtypes = [intp]
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (for timing)"""
+    lib().oc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().oc_get_threads())
 
 
 def _u64(a):
@@ -373,6 +387,11 @@ class Oracle:
     def hoisted_rotate(self, a, step):
         return Ct(self, lib().oc_hoisted_rotate(self.ptr, a.ptr, step))
 
+    def hoisted_rotate_digits(self, a, digits, step):
+        """hoisted rotation with the digits Decompose(c1) given (as from decompose())"""
+        d, p = _u64(np.asarray(digits, dtype=np.uint64).ravel())
+        return Ct(self, lib().oc_hoisted_rotate_digits(self.ptr, a.ptr, p, step))
+
     def rotate(self, a, step):
         return Ct(self, lib().oc_rotate(self.ptr, a.ptr, step))
 
@@ -401,14 +420,15 @@ class Oracle:
     def lt_transpose(self, a, n, n1, weight=1.0):
         return self._lt(lib().oc_lt_transpose, a.ptr, n, n1, weight)
 
-    def matmul(self, a, b, n, n1z, n1t, npz=None, npt=None, lazy=False, fused_rescale=False):
+    def matmul(self, a, b, n, n1z, n1t, npz=None, npt=None, lazy=False, fused_rescale=False, folded=False):
         """lazy: relinearise once after summing the n tensors; fused_rescale:
         the A side's ModDown and Rescale as one rounding by P q_l (both
         variants; the paper's order relinearises every product and rounds
-        twice)"""
+        twice); folded: the masks of C^k folded into Z, so the product takes
+        two levels instead of three"""
         npz = n - 1 if npz is None else npz
         npt = n - 1 if npt is None else npt
-        flags = (1 if lazy else 0) | (2 if fused_rescale else 0)
+        flags = (1 if lazy else 0) | (2 if fused_rescale else 0) | (4 if folded else 0)
         return self._lt(lib().oc_matmul_lazy, a.ptr, b.ptr, n, n1z, n1t, npz, npt, flags)
 
     def covariance(self, blocks, rb, k, n, n_samples, n1z, n1t, n1g, npz=None, npt=None, lazy=False,
@@ -439,6 +459,13 @@ def dcd_factors(n, which, nprime, n1):
         raise ValueError("decomposition is not a product of partial permutations")
     return [(perms[j * n * n:(j + 1) * n * n].copy(), tuple(int(v) for v in geom[4 * j:4 * j + 4]))
             for j in range(nf)]
+
+
+def perm_phi_sigma(n: int, k: int) -> np.ndarray:
+    """the folded A side's permutation: output (i, j) takes A[i, (i + j + k) mod n]"""
+    out = np.zeros(n * n, dtype=np.int32)
+    lib().oc_perm_phi_sigma(n, k, out.ctypes.data_as(intp))
+    return out
 
 
 def perm(which: str, n: int) -> np.ndarray:

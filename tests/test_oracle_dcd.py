@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from oracle import packing as opacking
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -138,7 +139,7 @@ def test_covariance_decrypts_to_fp64(deep):
     n, k, rb = 8, 2, 2
     X = I.centre(I.dataset(3, rb * n - 3, k * n - 5))   # ragged: padded rows and features
     s = X.shape[0]
-    blocks = I.blocks(X, n)
+    blocks = opacking.pack(X, n)
     cts = [deep.encrypt(blocks[r, j].ravel(), nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
     cov = deep.covariance(cts, rb, k, n, s, 2, 2, 2)
     P = np.zeros((rb * n, k * n))

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from oracle import packing as opacking
 
 BOUND = 2.0**-15
 
@@ -153,7 +154,7 @@ def test_lazy_covariance_decrypts(oracle_mod):
     steps = {s for s in range(-n * n + 1, n * n) if s}
     o.keygen(rot_steps=sorted(steps), relin=True)
     X = I.centre(I.dataset(5, rb * n - 3, k * n - 5))
-    blk = I.blocks(X, n)
+    blk = opacking.pack(X, n)
     cts = [o.encrypt(blk[r, j].ravel(), nonce=10 + r * k + j) for r in range(rb) for j in range(k)]
     cov = o.covariance(cts, rb, k, n, X.shape[0], 4, 4, 4, lazy=True)
     ref = np.zeros((k * n, k * n))
