@@ -124,6 +124,34 @@ typedef struct {
 #define HE_MM_GRAPH 8u
 /* he_covariance only: the dataset is not centred (see he_covariance) */
 #define HE_COV_UNCENTRED 16u
+/* he_matmul, he_matmul_batch, he_matmul_rot_steps: the masks of C^k
+ * (section 4.1.1) folded into Z.  phi^k(sigma(A)) is one permutation of A's
+ * entries whose diagonals are C^k's masks times Z's diagonals, with Z's
+ * diagonal indices, so A_k is a single double-hoisted BSGS transform of a
+ * (Z's geometry and keys, no column-shift keys) and the product takes two
+ * levels instead of three: for chains with only two rescales, such as q0 +
+ * two 40-bit primes.  Costs n transforms in place of Z and the shifts.  Not
+ * with HE_MM_FUSED_RESCALE or a decomposition of Z (HE_EINVAL); not for
+ * he_covariance. */
+#define HE_MM_FOLDED 32u
+/* he_matmul_batch only: products of any sizes and levels run together.
+ * Products of equal d, level and scales are stacked (up to 8, wherever they
+ * stand in the list); the stacks run concurrently on the context's stream,
+ * taking turns, and their key inner products (the hoisted rotations of every
+ * transform and shift, the relinearisations) are merged: each merged launch
+ * (one per member count) serves one key-switch step of every product at
+ * once, items of different levels and rotation sets side by side.  Results
+ * are residue-for-residue those of each product computed alone.  Not with
+ * HE_MM_GRAPH. */
+#define HE_MM_MERGED 64u
+
+/* Host only (no device needed): the moduli a context with these parameters
+ * uses, q_0..q_L then p_0..p_{alpha-1} (Setparams of Appendix A: the largest
+ * primes 1 mod 2N below 2^bits, Q first in chain order, then P), and each
+ * modulus's NTT root psi = x^((q-1)/2N) for the smallest x >= 2 whose power
+ * has order 2N (the smallest quadratic non-residue).  Both arrays hold at
+ * least n_q + n_p words (`cap`). */
+he_status he_params_moduli(const he_params* p, uint64_t* moduli, uint64_t* psi, size_t cap);
 
 /* Create a context on the current HIP device.  `dev` may be NULL.  `seed`
  * keys every random draw of the context (Philox4x64-10 streams).
@@ -185,6 +213,15 @@ he_status he_mult(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
 he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out);
 he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out);
 he_status he_drop_level(he_ctx* ctx, const he_ct* a, uint32_t level, he_ct** out);
+/* Hoisted rotations (section 3.3.1) of `count` ciphertexts (1..64, one level
+ * and scale) by `nsteps` steps each: one Decompose of the whole batch, the key
+ * inner products of all steps in one multi-rotation launch (per 64 steps),
+ * one ModDown per step for the whole batch.  out[i * nsteps + r] (caller's
+ * array of count * nsteps handles) = Rot(a[i], steps[r]), residue for residue
+ * what he_rotate gives.  HE_EKEY before any launch if a step's key is
+ * missing; on any error no handle is returned. */
+he_status he_rotate_many(he_ctx* ctx, const he_ct* const* a, size_t count, const int32_t* steps, size_t nsteps,
+                         he_ct** out);
 
 /* Rotation that allocates no device memory, for callers that cannot call
  * hipMalloc: code under HIP graph capture, tight serving loops, harnesses
@@ -208,6 +245,17 @@ he_status he_drop_level(he_ctx* ctx, const he_ct* a, uint32_t level, he_ct** out
  *        HE_EKEY if the step's key is missing (nothing is launched then). */
 #define HE_NOALLOC_WS_BYTES (64ull << 20)
 he_status he_rotate_noalloc(he_ctx* ctx, const he_ct* a, int32_t step, he_ct* out);
+/* Measured VALU ceiling of the modular products the kernels use, on the
+ * current device: blocks x 256 threads each run `iters` steps of eight
+ * independent product chains in registers (no memory traffic), timed with HIP
+ * events.  kind 0 = lazy signed FP64 product a w - k q (the arithmetic of
+ * moduli below 2^46), 1 = Shoup product by a constant (60-bit moduli), 2 =
+ * Barrett product of two residues (60-bit moduli), 3 = lazy FP64 butterfly
+ * (one product, one add, one subtract, the re-centring of both outputs).
+ * *products_per_s = blocks * 256 * iters * 8 / elapsed; *ms (may be NULL) the
+ * elapsed time.  Allocates and frees its own small output buffer. */
+he_status he_modmul_peak(uint32_t kind, uint64_t iters, uint32_t blocks, double* products_per_s, double* ms);
+
 /* Workspace bytes he_rotate_noalloc needs for a single ciphertext at `level`
  * (host-side arithmetic only). */
 he_status he_rotate_workspace_bytes(const he_ctx* ctx, uint32_t level, size_t* bytes);
@@ -383,6 +431,21 @@ he_status he_last_op_ms(const he_ctx* ctx, double* ms);
  * library. */
 he_status he_profile_enable(he_ctx* ctx, int on);
 he_status he_profile_read(he_ctx* ctx, const char* family, double* total_ms, uint64_t* launches, double* bytes);
+/* Algorithmic modular products of a kernel family since enabling, by the
+ * arithmetic of their moduli: lazy FP64 (moduli below 2^46) and 64-bit
+ * integer (the others).  Counted per launch from its shape: (N/2) x stages
+ * butterflies per limb of an NTT pass, the basis conversions' terms (one
+ * product per source and target value, plus the quotient's), 2 beta key
+ * products per output value of a key inner product (plus P c_0 and masks),
+ * four per tensor value, one per elementwise or multiply-sum product.  With
+ * he_modmul_peak's measured rates this gives the VALU side of a roofline.
+ * `unit_bytes` (may be NULL): the family's bytes in the key switch's unit
+ * of work, each switching key read once per launch (2 beta_l (l+1+alpha)
+ * limbs) and each member's ciphertext read and written once per rotation
+ * (4 (l+1) limbs); for other families the algorithmic bytes of
+ * he_profile_read. */
+he_status he_profile_read_ops(he_ctx* ctx, const char* family, double* modmuls_f64, double* modmuls_int,
+                              double* unit_bytes);
 /* counts of Decompose / MultSum / ModDown operations issued by the context */
 he_status he_op_counts(const he_ctx* ctx, uint64_t* decompose, uint64_t* multsum, uint64_t* moddown);
 

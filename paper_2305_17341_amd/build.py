@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhe_mi355x.so")
-HIP_SRCS = ["kernels.hip", "runtime.hip", "power.hip", "abi.hip"]
+HIP_SRCS = ["kernels.hip", "runtime.hip", "power.hip", "abi.hip", "microbench.hip"]
 CXX_SRCS = ["tables_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",

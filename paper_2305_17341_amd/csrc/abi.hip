@@ -1,6 +1,7 @@
 // C ABI of the library (include/he_mi355x.h): argument checks, error
 // translation and ownership; all computation is in runtime.hip / kernels.hip.
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <set>
@@ -92,7 +93,7 @@ void* workspace_of_current_device(int* dev_out) {
 }
 struct MmOpts {
   int n1z, n1t, npz, npt;
-  bool lazy, fused;
+  bool lazy, fused, folded;
 };
 MmOpts opts_of(const he_matmul_opts* o, int d) {
   MmOpts m;
@@ -104,6 +105,7 @@ MmOpts opts_of(const he_matmul_opts* o, int d) {
   if (m.npt > d - 1) m.npt = d - 1;
   m.lazy = o && (o->flags & HE_MM_LAZY_RELIN);
   m.fused = o && (o->flags & HE_MM_FUSED_RESCALE);
+  m.folded = o && (o->flags & HE_MM_FOLDED);
   if (m.n1z < 1 || m.n1t < 1 || d % m.n1z || d % m.n1t) fail(HE_EINVAL, "baby-step counts must divide d");
   return m;
 }
@@ -167,9 +169,23 @@ he_status he_matmul_rot_steps(const he_ctx* ctx, uint32_t d, const he_matmul_opt
     auto lk = hold(ctx);
     need(ctx != nullptr && d >= 2, "bad arguments");
     MmOpts m = opts_of(opts, (int)d);
-    std::vector<long> s = matmul_steps((int)d, m.n1z, m.n1t, m.npz, m.npt);
+    std::vector<long> s = matmul_steps((int)d, m.n1z, m.n1t, m.npz, m.npt, m.folded);
     if (n) *n = s.size();
     for (size_t i = 0; i < s.size() && i < cap; i++) steps[i] = (int32_t)s[i];
+  });
+}
+
+he_status he_params_moduli(const he_params* p, uint64_t* moduli, uint64_t* psi, size_t cap) {
+  return guard_host([&] {
+    need(p && moduli && psi, "null argument");
+    need(p->log_n >= 10 && p->log_n <= 16 && p->n_q >= 1 && p->n_q <= 48 && p->n_p >= 1 && p->n_p <= 4,
+         "unsupported parameters");
+    need(cap >= p->n_q + p->n_p, "buffers too small");
+    std::vector<int> bits;
+    for (u32 k = 0; k < p->n_q; k++) bits.push_back((int)p->q_bits[k]);
+    for (u32 k = 0; k < p->n_p; k++) bits.push_back((int)p->p_bits[k]);
+    for (int b : bits) need(b >= 30 && b <= 61, "prime sizes must be 30..61 bits");
+    params_moduli((int)p->log_n, bits, moduli, psi);
   });
 }
 
@@ -333,6 +349,36 @@ he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out) {
     *out = wrap(ctx, ctx->impl.rotate(a->ct, step));
   });
 }
+he_status he_rotate_many(he_ctx* ctx, const he_ct* const* a, size_t count, const int32_t* steps, size_t nsteps,
+                         he_ct** out) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    need(a && steps && out && count >= 1 && count <= 64 && nsteps >= 1 && nsteps <= 1024, "bad arguments");
+    std::vector<const HeCt*> xs;
+    for (size_t i = 0; i < count; i++) {
+      check_ct(ctx, a[i]);
+      xs.push_back(&a[i]->ct);
+    }
+    HeCtxImpl& c = ctx->impl;
+    HeCt x = count == 1 ? c.ct_copy(*xs[0]) : c.stack(xs);
+    std::vector<HeCt> rot = c.rotate_many(x, std::vector<long>(steps, steps + nsteps));
+    std::vector<he_ct*> made;
+    try {
+      for (size_t r = 0; r < nsteps; r++) {
+        std::vector<HeCt> parts = count == 1 ? std::vector<HeCt>{} : c.unstack(rot[r]);
+        if (count == 1) parts.push_back(std::move(rot[r]));
+        rot[r] = HeCt();
+        for (size_t i = 0; i < count; i++) {
+          made.push_back(wrap(ctx, std::move(parts[i])));
+          out[i * nsteps + r] = made.back();
+        }
+      }
+    } catch (...) {
+      for (he_ct* m : made) delete m;
+      throw;
+    }
+  });
+}
 he_status he_rotate_noalloc(he_ctx* ctx, const he_ct* a, int32_t step, he_ct* out) {
   return guard([&] {
     auto lk = hold(ctx);
@@ -422,7 +468,7 @@ he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, con
     HeCtxImpl& c = ctx->impl;
     MmOpts m = opts_of(opts, (int)d);
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
-    HeCt r = c.matmul(a->ct, b->ct, (int)d, m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused);
+    HeCt r = c.matmul(a->ct, b->ct, (int)d, m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused, m.folded);
     hip_check(hipEventRecord(c.ev1, c.stream), "event");
     *out = wrap(ctx, std::move(r));
   });
@@ -442,6 +488,7 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
     if (opts && (opts->flags & HE_MM_GRAPH)) {
       need(opts->flags & HE_MM_BATCHED, "a recorded product must be batched");
+      need(!(opts->flags & HE_MM_MERGED), "merged products are not recorded");
       need(count >= 1 && count <= 8, "a recorded product takes 1 to 8 pairs");
       need(!prof_enabled(), "no recording while the kernel profile is enabled");
       std::vector<const HeCt*> xa, xb;
@@ -451,13 +498,52 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
         xb.push_back(&b[k]->ct);
       }
       MmOpts m = opts_of(opts, (int)d[0]);
-      std::vector<HeCt> parts = c.matmul_graph(xa, xb, (int)d[0], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused);
+      std::vector<HeCt> parts = c.matmul_graph(xa, xb, (int)d[0], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused, m.folded);
       for (size_t k = 0; k < count; k++) out[k] = wrap(ctx, std::move(parts[k]));
       hip_check(hipEventRecord(c.ev1, c.stream), "event");
       return;
     }
     try {
-      if (opts && (opts->flags & HE_MM_BATCHED)) {
+      if (opts && (opts->flags & HE_MM_MERGED)) {
+        // products of equal d, level and scales stacked (up to 8, wherever
+        // they stand in the list); the stacks run together with their key
+        // inner products merged into shared launches
+        std::vector<std::vector<size_t>> stacks;
+        for (size_t i = 0; i < count; i++) {
+          bool placed = false;
+          for (auto& st : stacks) {
+            const size_t j = st[0];
+            if (st.size() < 8 && d[j] == d[i] && a[j]->ct.level == a[i]->ct.level &&
+                b[j]->ct.level == b[i]->ct.level && a[j]->ct.scale == a[i]->ct.scale &&
+                b[j]->ct.scale == b[i]->ct.scale) {
+              st.push_back(i);
+              placed = true;
+              break;
+            }
+          }
+          if (!placed) stacks.push_back({i});
+        }
+        std::vector<std::function<HeCt()>> jobs;
+        for (const auto& st : stacks) {
+          jobs.push_back([&, st]() {
+            std::vector<const HeCt*> xa, xb;
+            for (size_t k : st) {
+              xa.push_back(&a[k]->ct);
+              xb.push_back(&b[k]->ct);
+            }
+            MmOpts m = opts_of(opts, (int)d[st[0]]);
+            HeCt sa = st.size() == 1 ? c.ct_copy(*xa[0]) : c.stack(xa);
+            HeCt sb = st.size() == 1 ? c.ct_copy(*xb[0]) : c.stack(xb);
+            return c.matmul(sa, sb, (int)d[st[0]], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused, m.folded);
+          });
+        }
+        std::vector<HeCt> res = c.run_merged(jobs);
+        for (size_t s_ = 0; s_ < stacks.size(); s_++) {
+          std::vector<HeCt> parts = stacks[s_].size() == 1 ? std::vector<HeCt>{} : c.unstack(res[s_]);
+          if (stacks[s_].size() == 1) parts.push_back(std::move(res[s_]));
+          for (size_t k = 0; k < stacks[s_].size(); k++) out[stacks[s_][k]] = wrap(ctx, std::move(parts[k]));
+        }
+      } else if (opts && (opts->flags & HE_MM_BATCHED)) {
         // runs of equal d stacked into batches of up to 8: every launch of the
         // plan then serves the whole batch (keys read once per batch)
         size_t i = 0;
@@ -473,7 +559,7 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
           }
           MmOpts m = opts_of(opts, (int)d[i]);
           HeCt sa = c.stack(xa), sb = c.stack(xb);
-          HeCt r = c.matmul(sa, sb, (int)d[i], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused);
+          HeCt r = c.matmul(sa, sb, (int)d[i], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused, m.folded);
           std::vector<HeCt> parts = c.unstack(r);
           for (size_t k = i; k < j; k++) out[k] = wrap(ctx, std::move(parts[k - i]));
           i = j;
@@ -481,7 +567,7 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
       } else {
         for (size_t i = 0; i < count; i++) {
           MmOpts m = opts_of(opts, (int)d[i]);
-          out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused));
+          out[i] = wrap(ctx, c.matmul(a[i]->ct, b[i]->ct, (int)d[i], m.n1z, m.n1t, m.npz, m.npt, m.lazy, m.fused, m.folded));
         }
       }
     } catch (...) {
@@ -506,6 +592,7 @@ he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks,
       xs.push_back(&x[i]->ct);
     }
     MmOpts m = opts_of(opts, (int)d);
+    need(!m.folded, "the covariance takes the three-level product");
     HeCtxImpl& c = ctx->impl;
     hip_check(hipEventRecord(c.ev0, c.stream), "event");
     std::vector<HeCt> r =
@@ -655,6 +742,13 @@ he_status he_mem_info(const he_ctx* ctx, size_t* live, size_t* cached, size_t* p
   });
 }
 
+he_status he_modmul_peak(uint32_t kind, uint64_t iters, uint32_t blocks, double* products_per_s, double* ms) {
+  return guard([&] {
+    need(products_per_s != nullptr, "null argument");
+    modmul_peak((int)kind, iters, (int)blocks, products_per_s, ms);
+  });
+}
+
 he_status he_device_memory(size_t* free_bytes, size_t* total_bytes) {
   return guard([&] {
     need(free_bytes && total_bytes, "null argument");
@@ -754,6 +848,17 @@ he_status he_profile_read(he_ctx* ctx, const char* family, double* total_ms, uin
     prof_read(family, total_ms, &n, &b);
     *launches = n;
     if (bytes) *bytes = b;
+  });
+}
+
+he_status he_profile_read_ops(he_ctx* ctx, const char* family, double* modmuls_f64, double* modmuls_int,
+                              double* unit_bytes) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    need(ctx && family && modmuls_f64 && modmuls_int, "null argument");
+    double u = 0;
+    prof_read_ops(family, modmuls_f64, modmuls_int, &u);
+    if (unit_bytes) *unit_bytes = u;
   });
 }
 

@@ -1,5 +1,7 @@
 // Launch wrappers for the gfx950 kernels (internal).
 #pragma once
+#include <functional>
+
 #include "he_internal.h"
 
 // Limb batch -> modulus index map; -1 skips the limb.
@@ -121,6 +123,30 @@ void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u6
 void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
                         const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
                         int batch, hipStream_t s, const u64* const* masks = nullptr, bool accumulate = false);
+// Key inner products handed to a sink instead of being launched (merged
+// launches of several products): the arguments of one launch_multsum_rot or
+// launch_multsum call
+struct KsWork {
+  std::vector<u64*> outs;
+  std::vector<const u64*> keys;
+  std::vector<u64> gs;
+  std::vector<const u64*> masks;  // empty: plain outputs
+  bool accumulate = false;
+  const u64* digits = nullptr;
+  const u64* c0 = nullptr;
+  const u64* pmod = nullptr;
+  int level = 0, beta = 0, B = 1;
+};
+using KsSink = std::function<void(KsWork&&)>;
+// set the calling thread's sink (null: launch as usual); returns the previous one
+KsSink* ks_sink_exchange(KsSink* s);
+// one launch per member count over every item of `works` (any levels): the
+// same residues as their own launch_multsum_rot calls.  `table` is device
+// memory of multsum_list_table_bytes() bytes for the work table (uploaded
+// from pageable memory: not for use under stream capture).
+size_t multsum_list_table_bytes(const DeviceTables& T, const std::vector<KsWork>& works, int L, int alpha);
+void launch_multsum_list(const DeviceTables& T, const std::vector<KsWork>& works, void* table, size_t table_bytes,
+                         int L, int alpha, hipStream_t s);
 // P-lift: out[2][nqp][N] = (P c0, P c1) on Q limbs, 0 on P limbs
 void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha, int npoly,
                   hipStream_t s);
@@ -164,8 +190,17 @@ void launch_centre_to_int(const DeviceTables& T, i64* out, const u64* coef, int 
 bool knob_set(const char* name, int value);
 bool knob_get(const char* name, int* value);
 
+// algorithmic modular products, split by arithmetic (f: lazy FP64 for moduli
+// below 2^46, i: 64-bit integer)
+struct Mm {
+  double f = 0, i = 0;
+  void add(int bits, double n) { (bits <= F64_LAZY_BITS ? f : i) += n; }
+};
+Mm mm_map(const DeviceTables& T, const LimbMap& m, int nlimbs, double per_limb);
+
 // per-family device timing (HIP events around launches)
 void prof_enable(bool on);
 bool prof_enabled();
 bool prof_read(const char* family, double* ms, u64* launches, double* bytes);
+bool prof_read_ops(const char* family, double* mm_f64, double* mm_int, double* unit_bytes);
 std::vector<std::string> prof_families();

@@ -26,6 +26,9 @@ struct Knobs {
   int ew_interleave = 1;   // plaintext-broadcast sums visit the limbs sharing a plaintext back to back (0/1)
   int cov_row_blocks = 4;  // row blocks of a covariance stacked into one batch (1..8)
   int mr_group = 4;        // rotations per work-group of a multi-rotation launch, sharing the digit loads (1/2/4)
+  // stage split of the register-blocked NTT per ring size (index log N):
+  // 0 = the default, 1 = one stage moved between the column and block passes
+  int ntt_split[17] = {};
 } g_knobs;
 }
 bool knob_set(const char* name, int v) {
@@ -37,6 +40,8 @@ bool knob_set(const char* name, int v) {
   else if (n == "ew_interleave" && (v == 0 || v == 1)) g_knobs.ew_interleave = v;
   else if (n == "cov_row_blocks" && v >= 1 && v <= 8) g_knobs.cov_row_blocks = v;
   else if (n == "mr_group" && (v == 1 || v == 2 || v == 4)) g_knobs.mr_group = v;
+  else if ((n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") && (v == 0 || v == 1))
+    g_knobs.ntt_split[std::stoi(n.substr(10))] = v;
   else return false;
   return true;
 }
@@ -49,14 +54,74 @@ bool knob_get(const char* name, int* v) {
   else if (n == "ew_interleave") *v = g_knobs.ew_interleave;
   else if (n == "cov_row_blocks") *v = g_knobs.cov_row_blocks;
   else if (n == "mr_group") *v = g_knobs.mr_group;
+  else if (n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") *v = g_knobs.ntt_split[std::stoi(n.substr(10))];
   else return false;
   return true;
 }
+
+// Stage splits (GA + GB stages in the column pass, GC + GD in the block pass,
+// each group at most 4: sixteen values per thread) of the register-blocked
+// NTT.  The tile is 4096 words: the column pass needs GA + GB <= 8 (R <= 256
+// rows in LDS) and the block pass GC + GD >= 6 (at most 64 blocks).  Split 1
+// (knob ntt_split_<log N>) moves one stage from one pass to the other.
+template <int LOGN_, int GA_, int GB_, int GC_, int GD_>
+struct NttSplit {
+  static constexpr int LOGN = LOGN_, GA = GA_, GB = GB_, GC = GC_, GD = GD_;
+  static_assert(GA + GB + GC + GD == LOGN && GA + GB <= 8 && GC + GD >= 6, "stage split");
+  static_assert(GA >= 1 && GA <= 4 && GB >= 1 && GB <= 4 && GC >= 1 && GC <= 4 && GD >= 1 && GD <= 4, "groups");
+};
+template <class F>
+static bool ntt_dispatch(int logN, F&& f) {
+  const int alt = logN >= 13 && logN <= 15 ? g_knobs.ntt_split[logN] : 0;
+  switch (logN * 2 + alt) {
+    case 32: f(NttSplit<16, 4, 4, 4, 4>{}); return true;
+    case 30: f(NttSplit<15, 4, 3, 4, 4>{}); return true;
+    case 31: f(NttSplit<15, 4, 4, 4, 3>{}); return true;
+    case 28: f(NttSplit<14, 4, 3, 4, 3>{}); return true;
+    case 29: f(NttSplit<14, 4, 4, 3, 3>{}); return true;
+    case 26: f(NttSplit<13, 3, 3, 4, 3>{}); return true;
+    case 27: f(NttSplit<13, 4, 3, 3, 3>{}); return true;
+    case 24: f(NttSplit<12, 3, 3, 3, 3>{}); return true;
+    default: return false;
+  }
+}
+#define NTT_SPLIT_ARGS S::LOGN, S::GA, S::GB, S::GC, S::GD
 
 // ---------------------------------------------------------------------------
 // Optional per-family device timing: HIP events recorded on the launching
 // stream around each launch while enabled.
 // ---------------------------------------------------------------------------
+// Algorithmic modular products of a launch by arithmetic: moduli below 2^46
+// take the lazy FP64 product, the others 64-bit integer products.
+Mm mm_map(const DeviceTables& T, const LimbMap& m, int nlimbs, double per_limb) {
+  Mm r;
+  for (int k = 0; k < nlimbs; k++) {
+    const int idx = m.idx[k % m.n];
+    if (idx >= 0) r.add(T.bits[idx], per_limb);
+  }
+  return r;
+}
+// limbs of q_0 .. q_{nq-1}, `reps` times
+static Mm mm_q(const DeviceTables& T, int nq, double per_limb, double reps = 1.0) {
+  Mm r;
+  for (int k = 0; k < nq; k++) r.add(T.bits[k], per_limb * reps);
+  return r;
+}
+// an R_{Q_l P} element's positions: q_0 .. q_{nq-1}, then the special primes
+static Mm mm_qp(const DeviceTables& T, int nq, int nqp, int L, double per_q, double per_p, double reps = 1.0) {
+  Mm r;
+  for (int pos = 0; pos < nqp; pos++) {
+    const int m = pos < nq ? pos : L + 1 + (pos - nq);
+    r.add(T.bits[m], (pos < nq ? per_q : per_p) * reps);
+  }
+  return r;
+}
+static Mm operator+(Mm a, const Mm& b) {
+  a.f += b.f;
+  a.i += b.i;
+  return a;
+}
+
 namespace {
 struct ProfPair {
   hipEvent_t a, b;
@@ -64,11 +129,13 @@ struct ProfPair {
 bool g_prof_on = false;
 std::map<std::string, std::vector<ProfPair>> g_prof;
 struct ProfTotal {
-  double ms = 0, bytes = 0;
+  double ms = 0, bytes = 0, mm_f64 = 0, mm_int = 0, unit_bytes = 0;
   u64 launches = 0;
 };
 std::map<std::string, ProfTotal> g_prof_done;
 std::map<std::string, double> g_prof_bytes;
+std::map<std::string, Mm> g_prof_mm;
+std::map<std::string, double> g_prof_unit;
 std::vector<hipEvent_t> g_ev_free;
 hipEvent_t ev_get() {
   if (!g_ev_free.empty()) {
@@ -81,16 +148,23 @@ hipEvent_t ev_get() {
   return e;
 }
 // `bytes` = algorithmic HBM bytes of the launch (every input read once,
-// every output written once)
+// every output written once); `mm` = its algorithmic modular products (NTT
+// butterflies, basis-conversion and inner-product terms), by arithmetic
 struct ProfScope {
   const char* name;
   hipStream_t s;
   hipEvent_t a = nullptr;
-  ProfScope(const char* n, hipStream_t st, double bytes = 0) : name(n), s(st) {
+  // `unit` = the bytes of the launch's work counted in the rotation's unit
+  // (each key read once per launch, each member's ciphertext in and out once
+  // per rotation); the kernel-I/O bytes when not given
+  ProfScope(const char* n, hipStream_t st, double bytes = 0, Mm mm = Mm(), double unit = -1.0) : name(n), s(st) {
     if (g_prof_on) {
       a = ev_get();
       (void)hipEventRecord(a, s);
       g_prof_bytes[name] += bytes;
+      g_prof_unit[name] += unit >= 0 ? unit : bytes;
+      g_prof_mm[name].f += mm.f;
+      g_prof_mm[name].i += mm.i;
     }
   }
   ~ProfScope() {
@@ -117,6 +191,13 @@ void prof_collect() {
   }
   for (auto& kv : g_prof_bytes) g_prof_done[kv.first].bytes += kv.second;
   g_prof_bytes.clear();
+  for (auto& kv : g_prof_mm) {
+    g_prof_done[kv.first].mm_f64 += kv.second.f;
+    g_prof_done[kv.first].mm_int += kv.second.i;
+  }
+  g_prof_mm.clear();
+  for (auto& kv : g_prof_unit) g_prof_done[kv.first].unit_bytes += kv.second;
+  g_prof_unit.clear();
 }
 }  // namespace
 
@@ -139,6 +220,14 @@ bool prof_read(const char* family, double* ms, u64* launches, double* bytes) {
   *launches = it->second.launches;
   *bytes = it->second.bytes;
   return true;
+}
+bool prof_read_ops(const char* family, double* mm_f64, double* mm_int, double* unit_bytes) {
+  prof_collect();
+  auto it = g_prof_done.find(family);
+  *mm_f64 = it == g_prof_done.end() ? 0 : it->second.mm_f64;
+  *mm_int = it == g_prof_done.end() ? 0 : it->second.mm_int;
+  *unit_bytes = it == g_prof_done.end() ? 0 : it->second.unit_bytes;
+  return it != g_prof_done.end();
 }
 std::vector<std::string> prof_families() {
   prof_collect();
@@ -477,6 +566,75 @@ __device__ __forceinline__ void inv_group(typename A::V (&v)[16], int b0, int lo
   }
 }
 
+// The inverse block pass's first G stages (b0 = 0, hi < 2^(log N - G)): the
+// twiddle of stage j is W'[2^(log N - 1 - j) + (hi << (G - 1 - j)) + low],
+// W'[k] = psi^-brv(k), the index pattern of the forward pass's last stages,
+// so the lazy FP64 arithmetic computes them the same way (fwd_group_last):
+// one table load and G - 1 squarings per thread, then one product per
+// twiddle from the small table W'[2^(log N - 1 - j) + low] shared by the
+// grid.  Any other arithmetic reads the table.
+template <int G, class A>
+__device__ __forceinline__ void inv_group_first(typename A::V (&v)[16], int logN, u32 hi, const A& ar) {
+  inv_group<G>(v, 0, logN, hi, ar);
+}
+template <int G>
+__device__ __forceinline__ void inv_group_first(double (&v)[16], int logN, u32 hi, const F64LazyArith& ar) {
+  double P[G];
+  P[G - 1] = ar.w[hi << (G - 1)];
+#pragma unroll
+  for (int jj = G - 2; jj >= 0; jj--) P[jj] = f64_mulmod_signed(P[jj + 1], P[jj + 1], ar.q, ar.qinv);
+#pragma unroll
+  for (int j = 0; j < G; j++) {
+    const int half = 1 << j, jj = G - 1 - j;
+    double w[1 << (G - 1)];
+#pragma unroll
+    for (int low = 0; low < (1 << jj); low++)
+      w[low] = f64_mulmod_signed(ar.w[(1u << (logN - 1 - j)) + low], P[jj], ar.q, ar.qinv);
+#pragma unroll
+    for (int r = 0; r < (1 << G); r++) {
+      if (r & half) continue;
+      const double U = v[r], V = v[r + half];
+      v[r] = U + V;
+      v[r + half] = f64_mulmod_signed(U - V, w[r >> (j + 1)], ar.q, ar.qinv);
+    }
+  }
+}
+// The inverse column pass's last G stages followed by the scaling by N^-1:
+// the final stage has the single twiddle W'[1], so its two outputs are
+// (U + V) N^-1 and (U - V) (W'[1] N^-1): the lazy FP64 arithmetic folds the
+// scaling into that stage (two products per butterfly where the stage and
+// the scaling took three).  Any other arithmetic scales afterwards.
+template <int G, class A>
+__device__ __forceinline__ void inv_group_last_scaled(typename A::V (&v)[16], int b0, int logN, const A& ar) {
+  inv_group<G>(v, b0, logN, 0u, ar);
+#pragma unroll
+  for (int mm = 0; mm < (1 << G); mm++) v[mm] = ar.scale_ninv(v[mm]);
+}
+template <int G>
+__device__ __forceinline__ void inv_group_last_scaled(double (&v)[16], int b0, int logN, const F64LazyArith& ar) {
+#pragma unroll
+  for (int j = 0; j < G - 1; j++) {
+    const int half = 1 << j;
+#pragma unroll
+    for (int r = 0; r < (1 << G); r++) {
+      if (r & half) continue;
+      const u32 widx = (1u << (logN - 1 - b0 - j)) + (u32)(r >> (j + 1));
+      const double U = v[r], V = v[r + half];
+      v[r] = U + V;
+      v[r + half] = f64_mulmod_signed(U - V, ar.w[widx], ar.q, ar.qinv);
+    }
+  }
+  // the last stage: logN - 1 - b0 - (G - 1) = 0, twiddle index 1
+  const double wn = f64_canon(f64_mulmod_signed(ar.w[1], ar.ninv, ar.q, ar.qinv), ar.q, ar.qinv);
+  constexpr int half = 1 << (G - 1);
+#pragma unroll
+  for (int r = 0; r < half; r++) {
+    const double U = v[r], V = v[r + half];
+    v[r] = f64_mulmod_signed(U + V, ar.ninv, ar.q, ar.qinv);
+    v[r + half] = f64_mulmod_signed(U - V, wn, ar.q, ar.qinv);
+  }
+}
+
 #define TILE 4096
 // LDS index of (row r, column c) in the column pass, C columns per tile
 __device__ __forceinline__ int lds_rc(int r, int c, int C) { return r * (C + 1) + c; }
@@ -567,10 +725,9 @@ __device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh
       const int it = tid + TPB * k, c = it % C, rl = it / C;
 #pragma unroll
       for (int mm = 0; mm < (1 << GA); mm++) v[mm] = ar.reduce(sh[lds_rc(rl + (mm << GB), c, C)]);
-      inv_group<GA>(v, S2 + GB, LOGN, 0u, ar);
+      inv_group_last_scaled<GA>(v, S2 + GB, LOGN, ar);
 #pragma unroll
-      for (int mm = 0; mm < (1 << GA); mm++)
-        a[(size_t)(rl + (mm << GB)) * T1 + c0 + c] = ar.store(ar.scale_ninv(v[mm]));
+      for (int mm = 0; mm < (1 << GA); mm++) a[(size_t)(rl + (mm << GB)) * T1 + c0 + c] = ar.store(v[mm]);
     }
   }
 }
@@ -685,7 +842,7 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
       const int it = tid + TPB * k, eh = it % HIGHD, b = it / HIGHD;
 #pragma unroll
       for (int mm = 0; mm < (1 << GD); mm++) v[mm] = sh[lds_be(b, (eh << GD) + mm, T1)];
-      inv_group<GD>(v, 0, LOGN, (u32)(((blk0 + b) << GC) + eh), ar);
+      inv_group_first<GD>(v, LOGN, (u32)(((blk0 + b) << GC) + eh), ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GD); mm++) sh[lds_be(b, (eh << GD) + mm, T1)] = v[mm];
     }
@@ -913,14 +1070,22 @@ static void ntt2_modup(const DeviceTables& T, u64* digits, const ModupSrc& S, in
   constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
   const int nlimbs = batch * S.beta * S.nqp;
   dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
+  // butterflies of the column stages on every converted digit limb, plus the
+  // conversion (ns products per value); the rows pass transforms the same limbs
+  Mm mm_cols;
+  for (int k = 0; k < S.beta * S.nqp; k++) {
+    const int idx = rows_map.idx[k];
+    if (idx >= 0) mm_cols.add(T.bits[idx], batch * (0.5 * T.N * (GA + GB) + (double)T.N * S.ns[k / S.nqp]));
+  }
   {
-    ProfScope ps("ntt_fwd_cols_modup", s, 8.0 * T.N * batch * (2.0 * S.nq + (double)S.beta * S.nqp));
+    ProfScope ps("ntt_fwd_cols_modup", s, 8.0 * T.N * batch * (2.0 * S.nq + (double)S.beta * S.nqp), mm_cols);
     hipLaunchKernelGGL((k_ntt_cols2_modup<LOGN, GA, GB>), gc, dim3(TPB), 0, s, digits, S, T.psi, T.psi_sh, T.psi_f,
                        T.nmods, T.mc);
   }
   int active = 0;
   for (int k = 0; k < rows_map.n; k++) active += rows_map.idx[k] >= 0;
-  ProfScope ps("ntt_fwd_rows", s, 16.0 * T.N * batch * active);
+  ProfScope ps("ntt_fwd_rows", s, 16.0 * T.N * batch * active,
+               mm_map(T, rows_map, S.beta * S.nqp, batch * 0.5 * T.N * (GC + GD)));
   hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false, true>), gr, dim3(TPB), 0, s, digits, rows_map, T.psi,
                      T.psi_sh, T.psi_f, T.mc, interleave_of(nlimbs, modulus_period(rows_map), g_knobs.ntt_interleave));
 }
@@ -932,11 +1097,11 @@ static void ntt2_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const
   const int nlimbs = nq * npoly;
   dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
   if (do_cols) {
-    ProfScope ps("ntt_fwd_cols", s, 16.0 * nlimbs * T.N);
+    ProfScope ps("ntt_fwd_cols", s, 16.0 * nlimbs * T.N, mm_map(T, map, nlimbs, 0.5 * T.N * (GA + GB)));
     hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, y, map, T.psi, T.psi_sh, T.psi_f,
                        T.mc);
   }
-  ProfScope ps("ntt_fwd_rows_sub", s, 24.0 * nlimbs * T.N);
+  ProfScope ps("ntt_fwd_rows_sub", s, 24.0 * nlimbs * T.N, mm_map(T, map, nlimbs, 0.5 * T.N * (GC + GD) + T.N));
   hipLaunchKernelGGL((k_ntt_rows2_sub<LOGN, GC, GD>), gr, dim3(TPB), 0, s, y, map, T.psi, T.psi_sh, T.psi_f, T.mc,
                      nq, x, x_stride, cpairs, out, interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave));
 }
@@ -948,22 +1113,23 @@ static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& ma
   static_assert(GA + GB + GC + GD == LOGN, "stage split");
   dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
   const int il = interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave);
+  const Mm mm_c = mm_map(T, map, nlimbs, 0.5 * T.N * (GA + GB)), mm_r = mm_map(T, map, nlimbs, 0.5 * T.N * (GC + GD));
   if (!inverse) {
     {
-      ProfScope ps("ntt_fwd_cols", s, pass_bytes);
+      ProfScope ps("ntt_fwd_cols", s, pass_bytes, mm_c);
       hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, false>), gc, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh,
                          T.psi_f, T.mc);
     }
-    ProfScope ps("ntt_fwd_rows", s, pass_bytes);
+    ProfScope ps("ntt_fwd_rows", s, pass_bytes, mm_r);
     hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, false>), gr, dim3(TPB), 0, s, data, map, T.psi, T.psi_sh,
                        T.psi_f, T.mc, il);
   } else {
     {
-      ProfScope ps("ntt_inv_rows", s, pass_bytes);
+      ProfScope ps("ntt_inv_rows", s, pass_bytes, mm_r);
       hipLaunchKernelGGL((k_ntt_rows2<LOGN, GC, GD, true>), gr, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh,
                          T.ipsi_f, T.mc, il);
     }
-    ProfScope ps("ntt_inv_cols", s, pass_bytes);
+    ProfScope ps("ntt_inv_cols", s, pass_bytes, mm_c);
     hipLaunchKernelGGL((k_ntt_cols2<LOGN, GA, GB, true>), gc, dim3(TPB), 0, s, data, map, T.ipsi, T.ipsi_sh,
                        T.ipsi_f, T.mc);
   }
@@ -971,14 +1137,10 @@ static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& ma
 
 static bool ntt_register_blocked(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse,
                                  double pass_bytes, hipStream_t s) {
-  switch (T.logN) {
-    case 16: ntt2<16, 4, 4, 4, 4>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
-    case 15: ntt2<15, 4, 3, 4, 4>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
-    case 14: ntt2<14, 4, 3, 4, 3>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
-    case 13: ntt2<13, 3, 3, 4, 3>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
-    case 12: ntt2<12, 3, 3, 3, 3>(T, data, nlimbs, map, inverse, pass_bytes, s); return true;
-    default: return false;
-  }
+  return ntt_dispatch(T.logN, [&](auto sp) {
+    using S = decltype(sp);
+    ntt2<NTT_SPLIT_ARGS>(T, data, nlimbs, map, inverse, pass_bytes, s);
+  });
 }
 
 // Each pass streams every active limb in and out once: 16 bytes per coefficient.
@@ -990,22 +1152,23 @@ void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map
   if (ntt_register_blocked(T, data, nlimbs, map, inverse, pass_bytes, s)) return;
   NttShape sh = ntt_shape(T.logN);
   dim3 gc(sh.T1 / sh.C, nlimbs), gr(sh.R / sh.K, nlimbs);
+  const Mm mm_c = mm_map(T, map, nlimbs, 0.5 * T.N * sh.s1), mm_r = mm_map(T, map, nlimbs, 0.5 * T.N * (sh.logN - sh.s1));
   if (!inverse) {
     {
-      ProfScope ps("ntt_fwd_cols", s, pass_bytes);
+      ProfScope ps("ntt_fwd_cols", s, pass_bytes, mm_c);
       hipLaunchKernelGGL(k_ntt_cols, gc, dim3(TPB), 0, s, data, map, sh.logN, sh.R, sh.T1, sh.C, 0, T.psi,
                          T.psi_sh, T.mc);
     }
-    ProfScope ps("ntt_fwd_rows", s, pass_bytes);
+    ProfScope ps("ntt_fwd_rows", s, pass_bytes, mm_r);
     hipLaunchKernelGGL(k_ntt_rows, gr, dim3(TPB), 0, s, data, map, sh.logN, sh.s1, sh.T1, sh.K, 0, T.psi,
                        T.psi_sh, T.mc);
   } else {
     {
-      ProfScope ps("ntt_inv_rows", s, pass_bytes);
+      ProfScope ps("ntt_inv_rows", s, pass_bytes, mm_r);
       hipLaunchKernelGGL(k_ntt_rows, gr, dim3(TPB), 0, s, data, map, sh.logN, sh.s1, sh.T1, sh.K, 1, T.ipsi,
                          T.ipsi_sh, T.mc);
     }
-    ProfScope ps("ntt_inv_cols", s, pass_bytes);
+    ProfScope ps("ntt_inv_cols", s, pass_bytes, mm_c);
     hipLaunchKernelGGL(k_ntt_cols, gc, dim3(TPB), 0, s, data, map, sh.logN, sh.R, sh.T1, sh.C, 1, T.ipsi,
                        T.ipsi_sh, T.mc);
   }
@@ -1018,17 +1181,14 @@ __global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, co
 void launch_ntt_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,
                         int x_stride, const u64* cpairs, u64* out, hipStream_t s) {
   if (nq <= 0 || npoly <= 0) return;
-  switch (T.logN) {
-    case 16: ntt2_fwd_sub<16, 4, 4, 4, 4>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
-    case 15: ntt2_fwd_sub<15, 4, 3, 4, 4>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
-    case 14: ntt2_fwd_sub<14, 4, 3, 4, 3>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
-    case 13: ntt2_fwd_sub<13, 3, 3, 4, 3>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
-    case 12: ntt2_fwd_sub<12, 3, 3, 3, 3>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s); return;
-    default: break;
-  }
+  if (ntt_dispatch(T.logN, [&](auto sp) {
+        using S = decltype(sp);
+        ntt2_fwd_sub<NTT_SPLIT_ARGS>(T, y, nq, npoly, map, x, x_stride, cpairs, out, s);
+      }))
+    return;
   launch_ntt(T, y, nq * npoly, map, false, s);
   dim3 grid(cdiv(T.N, TPB), nq, npoly);
-  ProfScope ps("moddown_final", s, 8.0 * T.N * 3.0 * npoly * nq);
+  ProfScope ps("moddown_final", s, 8.0 * T.N * 3.0 * npoly * nq, mm_q(T, nq, (double)T.N, npoly));
   hipLaunchKernelGGL(k_moddown_final, grid, dim3(TPB), 0, s, out, x, y, nq, cpairs, x_stride, T.logN, T.mc);
 }
 
@@ -1068,14 +1228,11 @@ bool launch_modup_ntt(const DeviceTables& T, u64* digits, const u64* y, const u6
     S.hat_t[j] = tabs[j].hat_t;
     S.hat_t_sh[j] = tabs[j].hat_t_sh;
   }
-  switch (T.logN) {
-    case 16: ntt2_modup<16, 4, 4, 4, 4>(T, digits, S, batch, rows_map, s); break;
-    case 15: ntt2_modup<15, 4, 3, 4, 4>(T, digits, S, batch, rows_map, s); break;
-    case 14: ntt2_modup<14, 4, 3, 4, 3>(T, digits, S, batch, rows_map, s); break;
-    case 13: ntt2_modup<13, 3, 3, 4, 3>(T, digits, S, batch, rows_map, s); break;
-    default: ntt2_modup<12, 3, 3, 3, 3>(T, digits, S, batch, rows_map, s); break;
-  }
-  return true;
+  const ModupSrc& src = S;
+  return ntt_dispatch(T.logN, [&](auto sp) {
+    using S = decltype(sp);
+    ntt2_modup<NTT_SPLIT_ARGS>(T, digits, src, batch, rows_map, s);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1132,7 +1289,8 @@ static void ew(const DeviceTables& T, int op, u64* out, const u64* a, const u64*
   if (nlimbs <= 0) return;
   // reads a (and b once per distinct limb), writes out; the accumulate also reads out
   double words = (double)nlimbs * (op == EW_MULACC ? 3 : (op == EW_NEG ? 2 : 2)) + (op == EW_NEG ? 0 : b_limbs);
-  ProfScope ps("elementwise", s, 8.0 * T.N * words);
+  ProfScope ps("elementwise", s, 8.0 * T.N * words,
+               op == EW_MUL || op == EW_MULACC ? mm_map(T, m, nlimbs, (double)T.N) : Mm());
   int il;
   dim3 grid = sum_grid((int)cdiv(T.N, TPB), nlimbs, b_limbs, g_knobs.ew_interleave, il);
   hipLaunchKernelGGL(k_elementwise, grid, dim3(TPB), 0, s, op, out, a, b, nlimbs, b_limbs, m, T.logN, T.mc, il);
@@ -1203,7 +1361,8 @@ void launch_mul_sum(const DeviceTables& T, u64* out, const u64* const* a, const 
       t.a[j] = a[t0 + j];
       t.p[j] = p[t0 + j];
     }
-    ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nt + 1 + (acc ? 1 : 0)) + (double)bl * nt));
+    ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nt + 1 + (acc ? 1 : 0)) + (double)bl * nt),
+                 mm_map(T, m, nl, (double)T.N * nt));
     int il;
     dim3 grid = sum_grid((int)cdiv(T.N, TPB), nl, bl, g_knobs.ew_interleave, il);
     hipLaunchKernelGGL(k_mul_sum, grid, dim3(TPB), 0, s, out, t, nt, acc ? 1 : 0, bl, m, T.logN, T.mc, il);
@@ -1291,7 +1450,8 @@ bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, co
       present += t.p[g][j] != nullptr;
     }
   }
-  ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nterms + nouts) + (double)bl * present));
+  ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nterms + nouts) + (double)bl * present),
+               mm_map(T, m, nl, (double)T.N * present));
   int il;
   dim3 grid = sum_grid((int)cdiv(T.N, TPB), nl, bl, g_knobs.ew_interleave, il);
   switch (nouts) {
@@ -1330,6 +1490,7 @@ void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs,
     c.w[2 * k + 1] = consts[2 * k + 1];
   }
   dim3 grid(cdiv(T.N, TPB), nlimbs);
+  ProfScope ps("elementwise", s, 16.0 * T.N * nlimbs, mm_map(T, m, nlimbs, (double)T.N));
   hipLaunchKernelGGL(k_mul_const, grid, dim3(TPB), 0, s, out, a, nlimbs, c, m, T.logN, T.mc);
 }
 
@@ -1439,7 +1600,7 @@ void launch_tensor_sum(const DeviceTables& T, u64* out3, const u64* const* a, co
       P.b[p] = p < np ? b[p0 + p] : nullptr;
     }
     const bool acc = accumulate || p0 > 0;
-    ProfScope ps("tensor", s, 8.0 * T.N * (4.0 * np + (acc ? 6 : 3)) * nt);
+    ProfScope ps("tensor", s, 8.0 * T.N * (4.0 * np + (acc ? 6 : 3)) * nt, mm_q(T, nl, 4.0 * T.N * np, batch));
     dim3 grid(cdiv(T.N, TPB), nt);
     if (acc) hipLaunchKernelGGL(k_tensor_multi<true>, grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
     else hipLaunchKernelGGL(k_tensor_multi<false>, grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
@@ -1449,7 +1610,7 @@ void launch_tensor_sum(const DeviceTables& T, u64* out3, const u64* const* a, co
 void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, bool accumulate,
                    hipStream_t s) {
   const int nt = nl * batch;
-  ProfScope ps("tensor", s, 8.0 * T.N * (accumulate ? 10 : 7) * nt);
+  ProfScope ps("tensor", s, 8.0 * T.N * (accumulate ? 10 : 7) * nt, mm_q(T, nl, 4.0 * T.N, batch));
   dim3 grid(cdiv(T.N, TPB), nt);
   if (accumulate) hipLaunchKernelGGL(k_tensor<true>, grid, dim3(TPB), 0, s, out3, a, b, nl, nt, T.logN, T.mc);
   else hipLaunchKernelGGL(k_tensor<false>, grid, dim3(TPB), 0, s, out3, a, b, nl, nt, T.logN, T.mc);
@@ -1551,7 +1712,11 @@ void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64
     A.hat_t[j] = tabs[j].hat_t;
     A.hat_t_sh[j] = tabs[j].hat_t_sh;
   }
-  ProfScope ps("modup", s, 8.0 * T.N * batch * ((level + 1) + (double)beta * (level + 1 + alpha)));
+  Mm mm;
+  for (int j = 0; j < beta; j++)
+    mm = mm + mm_qp(T, level + 1, level + 1 + alpha, L, (double)T.N * tabs[j].ns, (double)T.N * tabs[j].ns, batch);
+  mm = mm + mm_q(T, level + 1, (double)T.N, batch);
+  ProfScope ps("modup", s, 8.0 * T.N * batch * ((level + 1) + (double)beta * (level + 1 + alpha)), mm);
   dim3 grid(cdiv(T.N, TPB), beta, batch);
   hipLaunchKernelGGL(k_modup, grid, dim3(TPB), 0, s, digits, coef, ntt_in, A, T.logN, T.nmods, T.mc);
 }
@@ -1664,7 +1829,7 @@ void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, 
   A.hat_t_sh = tab.hat_t_sh;
   A.D_mod_t = tab.D_mod_t;
   A.hat_f = tab.hat_f;
-  ProfScope ps("fbc_to_q", s, 8.0 * T.N * npoly * ((double)tab.ns + nq));
+  ProfScope ps("fbc_to_q", s, 8.0 * T.N * npoly * ((double)tab.ns + nq), mm_q(T, nq, (double)T.N * (tab.ns + 1), npoly));
   dim3 grid(cdiv(T.N, TPB), nq < 4 ? nq : 4, npoly);
   hipLaunchKernelGGL(k_fbc_to_q, grid, dim3(TPB), 0, s, y, xp_coef, nq, A, T.logN, T.nmods, T.mc);
 }
@@ -1789,7 +1954,8 @@ static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const Fbc
   constexpr int R = 1 << (GA + GB), C = TILE / R;
   dim3 gc((1 << LOGN) / R / C, nq * npoly);
   {
-    ProfScope ps("ntt_fwd_cols_fbc", s, 8.0 * T.N * npoly * ((double)A.ns + 1 + nq));
+    ProfScope ps("ntt_fwd_cols_fbc", s, 8.0 * T.N * npoly * ((double)A.ns + 1 + nq),
+                 mm_q(T, nq, 0.5 * T.N * (GA + GB) + (double)T.N * (A.ns + 1), npoly));
     hipLaunchKernelGGL((k_ntt_cols2_fbc<LOGN, GA, GB>), gc, dim3(TPB), 0, s, y, V, nq, A, T.psi, T.psi_sh, T.psi_f,
                        T.nmods, T.mc);
   }
@@ -1816,20 +1982,18 @@ bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int
   A.D_mod_t = tab.D_mod_t;
   A.hat_f = tab.hat_f;
   {
-    ProfScope ps("fbc_prep", s, 8.0 * T.N * npoly * (2.0 * tab.ns + 1));
+    Mm mm;
+    for (int a = 0; a < tab.ns; a++) mm.add(T.bits[tab.src[a]], (double)T.N * npoly);
+    ProfScope ps("fbc_prep", s, 8.0 * T.N * npoly * (2.0 * tab.ns + 1), mm);
     hipLaunchKernelGGL(k_fbc_prep, dim3(cdiv(T.N, TPB), npoly), dim3(TPB), 0, s, V, xp_coef, A, T.logN, T.mc);
   }
   LimbMap map;
   map.n = nq;
   for (int k = 0; k < nq; k++) map.idx[k] = (short)k;
-  switch (T.logN) {
-    case 16: moddown_fused<16, 4, 4, 4, 4>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
-    case 15: moddown_fused<15, 4, 3, 4, 4>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
-    case 14: moddown_fused<14, 4, 3, 4, 3>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
-    case 13: moddown_fused<13, 3, 3, 4, 3>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
-    default: moddown_fused<12, 3, 3, 3, 3>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s); break;
-  }
-  return true;
+  return ntt_dispatch(T.logN, [&](auto sp) {
+    using S = decltype(sp);
+    moddown_fused<NTT_SPLIT_ARGS>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s);
+  });
 }
 
 // out[p][t] = (x[p][t] - y[p][t]) * P^{-1} mod q_t   (p < npoly, t < nq)
@@ -1845,7 +2009,7 @@ __global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, co
 }
 void launch_moddown_final(const DeviceTables& T, u64* out, const u64* x, const u64* y, int nq, const u64* pinv,
                           int npoly, int x_stride_limbs, hipStream_t s) {
-  ProfScope ps("moddown_final", s, 8.0 * T.N * 3.0 * npoly * nq);
+  ProfScope ps("moddown_final", s, 8.0 * T.N * 3.0 * npoly * nq, mm_q(T, nq, (double)T.N, npoly));
   dim3 grid(cdiv(T.N, TPB), nq, npoly);
   hipLaunchKernelGGL(k_moddown_final, grid, dim3(TPB), 0, s, out, x, y, nq, pinv, x_stride_limbs, T.logN, T.mc);
 }
@@ -2150,9 +2314,235 @@ static u64 inv_mod_2n(u64 g, u64 twoN) {
   return x & (twoN - 1);
 }
 
+// Limb order of an R_{Q_l P} element for the key inner products: the integer
+// limbs spread among the FP64 ones (see PosList)
+static PosList pos_order(const DeviceTables& T, int nq, int nqp, int L) {
+  PosList pf, pi, P;
+  int nf = 0, ni = 0;
+  for (int pos = 0; pos < nqp; pos++) {
+    const int m = pos < nq ? pos : L + 1 + (pos - nq);
+    if (T.bits[m] <= F64_LAZY_BITS) pf.pos[nf++] = (short)pos;
+    else pi.pos[ni++] = (short)pos;
+  }
+  int f = 0, k = 0;
+  for (int t = 0; t < ni; t++) {
+    const int upto = (int)(((long)nf * (t + 1)) / (ni + 1));
+    while (f < upto) P.pos[k++] = pf.pos[f++];
+    P.pos[k++] = pi.pos[t];
+  }
+  while (f < nf) P.pos[k++] = pf.pos[f++];
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// Merged key inner products: one launch over a list of work items of any
+// level, members and rotations (of different products), read from a device
+// table.  Each item runs exactly the arithmetic of k_multsum_rot.
+// ---------------------------------------------------------------------------
+struct KsItem {
+  MultiRot R;
+  PosList P;
+  const u64* digits;
+  const u64* c0;
+  const u64* pmod;
+  int nrot, nq, nqp, beta, B, b0;
+};
+constexpr int KS_RPW = 4;  // rotations per work-group in the merged launch
+thread_local KsSink* tls_ks_sink = nullptr;
+KsSink* ks_sink_exchange(KsSink* s) {
+  KsSink* old = tls_ks_sink;
+  tls_ks_sink = s;
+  return old;
+}
+
+template <int MB>
+__global__ void __launch_bounds__(TPB) k_multsum_list(const KsItem* __restrict__ items, const u32* __restrict__ start,
+                                                      int nitems, int L, int nmods, int logN,
+                                                      const ModConst* __restrict__ mc) {
+  const u32 x = blockIdx.x;
+  int lo = 0, hi = nitems;  // start[lo] <= x < start[lo + 1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  const KsItem& it = items[lo];
+  if ((int)blockIdx.y >= it.nqp) return;
+  const u64 N = 1ull << logN;
+  const u32 xl = x - start[lo];
+  const u32 ngroups = (u32)((it.nrot + KS_RPW - 1) / KS_RPW);
+  const u32 rest = xl >> 3;
+  const int r0 = (int)(rest % ngroups) * KS_RPW;
+  const int nr = it.nrot - r0 < KS_RPW ? it.nrot - r0 : KS_RPW;
+  const u32 S = (rest / ngroups) * 8 + (xl & 7);
+  if ((u64)S * TPB >= N) return;
+  const u32 src = S * TPB + threadIdx.x;
+  const int pos = it.P.pos[blockIdx.y];
+  const int m = pos < it.nq ? pos : L + 1 + (pos - it.nq);
+  const ModConst mk = mc[m];
+  if (mk.bits <= F64_LAZY_BITS) {
+    multsum_rot_group<MB, KS_RPW>(it.R, r0, nr, it.digits, it.c0, it.pmod, it.nq, it.nqp, it.beta, nmods, it.B,
+                                  it.b0, m, pos, src, logN, N, mk);
+    return;
+  }
+  constexpr int M1 = MB > 4 ? 4 : MB;
+  for (int r = r0; r < r0 + nr; r++) {
+    const u32 i = automorph_src(src, it.R.ginv[r], logN);
+    multsum_body<M1, false>(it.R.out[r], it.digits, it.R.key[r], it.c0, it.pmod, it.nq, it.nqp, it.beta, nmods, it.B,
+                            it.b0, m, pos, i, src, N, mk, it.R.mask[r], it.R.accumulate != 0);
+    if (MB > 4)
+      multsum_body<(MB > 4 ? MB - 4 : 1), false>(it.R.out[r], it.digits, it.R.key[r], it.c0, it.pmod, it.nq, it.nqp,
+                                                 it.beta, nmods, it.B, it.b0 + 4, m, pos, i, src, N, mk,
+                                                 it.R.mask[r], it.R.accumulate != 0);
+  }
+}
+
+// the work's items: rotations in chunks of MR_MAX, members in chunks of
+// MS_MAXB (an item's member count decides the launch it goes to)
+static void ks_items(const DeviceTables& T, const KsWork& w, int L, int alpha, std::vector<std::pair<int, KsItem>>& out) {
+  const int nq = w.level + 1, nqp = nq + alpha, nrot = (int)w.gs.size();
+  const u64 twoN = 2 * T.N;
+  const PosList P = pos_order(T, nq, nqp, L);
+  for (int r0 = 0; r0 < nrot; r0 += MR_MAX) {
+    const int nr = std::min(nrot - r0, MR_MAX);
+    for (int b0 = 0; b0 < w.B; b0 += MS_MAXB) {
+      KsItem it;
+      std::memset(&it, 0, sizeof it);
+      it.R.accumulate = !w.masks.empty() && w.accumulate ? 1 : 0;
+      for (int r = 0; r < nr; r++) {
+        it.R.out[r] = w.outs[r0 + r];
+        it.R.key[r] = w.keys[r0 + r];
+        it.R.mask[r] = w.masks.empty() ? nullptr : w.masks[r0 + r];
+        it.R.ginv[r] = inv_mod_2n(w.gs[r0 + r], twoN);
+      }
+      it.P = P;
+      it.digits = w.digits;
+      it.c0 = w.c0;
+      it.pmod = w.pmod;
+      it.nrot = nr;
+      it.nq = nq;
+      it.nqp = nqp;
+      it.beta = w.beta;
+      it.B = w.B;
+      it.b0 = b0;
+      out.push_back({std::min(MS_MAXB, w.B - b0), it});
+    }
+  }
+}
+
+// bytes of the table launch_multsum_list lays out: per distinct member count
+// a 256-aligned run of items, then a 256-aligned prefix array of its
+// work-group counts (one more entry than items)
+static size_t ks_table_bytes(std::vector<std::pair<int, KsItem>>& items) {
+  std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  size_t bytes = 0;
+  for (size_t i = 0; i < items.size();) {
+    size_t j = i;
+    while (j < items.size() && items[j].first == items[i].first) j++;
+    bytes = ((bytes + 255) & ~(size_t)255) + (j - i) * sizeof(KsItem);
+    bytes = ((bytes + 255) & ~(size_t)255) + (j - i + 1) * sizeof(u32);
+    i = j;
+  }
+  return bytes;
+}
+size_t multsum_list_table_bytes(const DeviceTables& T, const std::vector<KsWork>& works, int L, int alpha) {
+  std::vector<std::pair<int, KsItem>> items;
+  for (const KsWork& w : works) ks_items(T, w, L, alpha, items);
+  return ks_table_bytes(items);
+}
+
+void launch_multsum_list(const DeviceTables& T, const std::vector<KsWork>& works, void* table, size_t table_bytes,
+                         int L, int alpha, hipStream_t s) {
+  std::vector<std::pair<int, KsItem>> items;
+  for (const KsWork& w : works) ks_items(T, w, L, alpha, items);
+  if (items.empty()) return;
+  // one launch per member count: items sorted by it, each group's table
+  // (items, then the prefix of their work-group counts) laid out in turn
+  const size_t need = ks_table_bytes(items);
+  if (need > table_bytes) throw std::runtime_error("merged key-switch table larger than its buffer");
+  std::vector<char> host;
+  host.reserve(need);
+  struct Launch {
+    int mb, n, nqp_max;
+    size_t items_off, start_off;
+    u32 tiles;
+    double bytes, unit;
+    Mm mm;
+  };
+  std::vector<Launch> launches;
+  const u32 nblk = (u32)cdiv(T.N, TPB), per_rot_group = (u32)cdiv(nblk, 8) * 8;
+  for (size_t i = 0; i < items.size();) {
+    size_t j = i;
+    while (j < items.size() && items[j].first == items[i].first) j++;
+    Launch L_;
+    L_.mb = items[i].first;
+    L_.n = (int)(j - i);
+    L_.nqp_max = 0;
+    L_.bytes = L_.unit = 0;
+    L_.items_off = (host.size() + 255) & ~(size_t)255;
+    host.resize(L_.items_off + (size_t)L_.n * sizeof(KsItem));
+    std::vector<u32> start;
+    u32 t = 0;
+    for (size_t k = i; k < j; k++) {
+      const KsItem& it = items[k].second;
+      std::memcpy(host.data() + L_.items_off + (k - i) * sizeof(KsItem), &it, sizeof(KsItem));
+      start.push_back(t);
+      t += per_rot_group * (u32)((it.nrot + KS_RPW - 1) / KS_RPW);
+      L_.nqp_max = std::max(L_.nqp_max, it.nqp);
+      const bool masked = it.R.mask[0] != nullptr;
+      const double mb = L_.mb, nr = it.nrot;
+      L_.bytes += 8.0 * T.N * it.nqp *
+                  (nr * 2.0 * it.beta + mb * it.beta + (masked ? nr : 0.0) + mb * nr * 2.0 * (1 + it.R.accumulate)) +
+                  (it.c0 ? 8.0 * T.N * mb * it.nq : 0.0);
+      L_.unit += 8.0 * T.N * (nr * 2.0 * it.beta * it.nqp + nr * mb * 4.0 * it.nq);
+      L_.mm = L_.mm + mm_qp(T, it.nq, it.nqp, L, (double)T.N * (2.0 * it.beta + (it.c0 ? 1 : 0) + (masked ? 2 : 0)),
+                            (double)T.N * (2.0 * it.beta + (masked ? 2 : 0)), mb * nr);
+    }
+    start.push_back(t);
+    L_.tiles = t;
+    L_.start_off = (host.size() + 255) & ~(size_t)255;
+    host.resize(L_.start_off + start.size() * sizeof(u32));
+    std::memcpy(host.data() + L_.start_off, start.data(), start.size() * sizeof(u32));
+    launches.push_back(L_);
+    i = j;
+  }
+  if (host.size() != need) throw std::runtime_error("merged key-switch table layout mismatch");
+  // pageable source: the copy has read it when the call returns
+  if (hipMemcpyAsync(table, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    throw std::runtime_error("merged key-switch table upload failed");
+  for (const Launch& l : launches) {
+    const KsItem* it = (const KsItem*)((char*)table + l.items_off);
+    const u32* st = (const u32*)((char*)table + l.start_off);
+    ProfScope ps("multsum_rot", s, l.bytes, l.mm, l.unit);
+    const dim3 grid(l.tiles, l.nqp_max);
+#define ML_CASE(K)                                                                                            \
+  case K:                                                                                                     \
+    hipLaunchKernelGGL(k_multsum_list<K>, grid, dim3(TPB), 0, s, it, st, l.n, L, T.nmods, T.logN, T.mc); \
+    break;
+    switch (l.mb) { ML_CASE(1) ML_CASE(2) ML_CASE(3) ML_CASE(4) ML_CASE(5) ML_CASE(6) ML_CASE(7) ML_CASE(8) }
+#undef ML_CASE
+  }
+}
+
 void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
                         const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
                         int batch, hipStream_t s, const u64* const* masks, bool accumulate) {
+  if (tls_ks_sink) {
+    KsWork w;
+    w.outs.assign(outs, outs + nrot);
+    w.keys.assign(keys, keys + nrot);
+    w.gs.assign(gs, gs + nrot);
+    if (masks) w.masks.assign(masks, masks + nrot);
+    w.accumulate = accumulate;
+    w.digits = digits;
+    w.c0 = c0;
+    w.pmod = pmod;
+    w.level = level;
+    w.beta = beta;
+    w.B = batch;
+    (*tls_ks_sink)(std::move(w));
+    return;
+  }
   const int nq = level + 1, nqp = nq + alpha;
   const u64 twoN = 2 * T.N;
   const int nblk = cdiv(T.N, TPB);
@@ -2169,22 +2559,10 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
       R.mask[r] = masks ? masks[r0 + r] : nullptr;
       R.ginv[r] = inv_mod_2n(gs[r0 + r], twoN);
     }
-    PosList pf, pi, P;
-    int nf = 0, ni = 0;
-    for (int pos = 0; pos < nqp; pos++) {
-      const int m = pos < nq ? pos : L + 1 + (pos - nq);
-      if (T.bits[m] <= F64_LAZY_BITS) pf.pos[nf++] = (short)pos;
-      else pi.pos[ni++] = (short)pos;
-    }
-    {
-      int f = 0, k = 0;
-      for (int t = 0; t < ni; t++) {
-        const int upto = (int)(((long)nf * (t + 1)) / (ni + 1));
-        while (f < upto) P.pos[k++] = pf.pos[f++];
-        P.pos[k++] = pi.pos[t];
-      }
-      while (f < nf) P.pos[k++] = pf.pos[f++];
-    }
+    const PosList P = pos_order(T, nq, nqp, L);
+    int ni = 0;
+    for (int pos = nq; pos < nqp; pos++) ni += T.bits[L + 1 + (pos - nq)] > F64_LAZY_BITS;
+    for (int pos = 0; pos < nq; pos++) ni += T.bits[pos] > F64_LAZY_BITS;
     for (int b0 = 0; b0 < batch; b0 += mstep) {
       const int mb = batch - b0 < mstep ? batch - b0 : mstep;
       // per position: each rotation's key once, the members' digits (and c0 on
@@ -2194,7 +2572,11 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
       for (int pos = 0; pos < nqp; pos++)
         w += nr * 2.0 * beta + mb * (beta + (c0 && pos < nq ? 1.0 : 0.0) + nr * 2.0) + (masks ? nr : 0.0) +
              (R.accumulate ? mb * nr * 2.0 : 0.0);
-      ProfScope ps("multsum_rot", s, 8.0 * T.N * w);
+      // per member and rotation: 2 beta key products on every position, P c0 on the Q limbs, the mask on both halves
+      const Mm mm = mm_qp(T, nq, nqp, L, (double)T.N * (2.0 * beta + (c0 ? 1 : 0) + (masks ? 2 : 0)),
+                          (double)T.N * (2.0 * beta + (masks ? 2 : 0)), (double)mb * nr);
+      const double unit = 8.0 * T.N * ((double)nr * 2.0 * beta * nqp + (double)nr * mb * 4.0 * nq);
+      ProfScope ps("multsum_rot", s, 8.0 * T.N * w, mm, unit);
       // FP64-only launch when every limb is FP64 (the integer branch compiled out)
 #define MR_LAUNCH(K, FP, G)                                                                                        \
   hipLaunchKernelGGL((k_multsum_rot<K, FP, G>), dim3(cdiv(nblk, 8) * 8 * cdiv(nr, G), nqp), dim3(TPB), 0, s, R, P, \
@@ -2223,13 +2605,19 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
 
 void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,
                     const u64* pmod, int level, int L, int alpha, int beta, u64 g, int batch, hipStream_t s) {
+  if (tls_ks_sink) {
+    launch_multsum_rot(T, &out, &key, &g, 1, digits, c0, pmod, level, L, alpha, beta, batch, s);
+    return;
+  }
   int nq = level + 1, nqp = nq + alpha;
   dim3 grid(cdiv(T.N, TPB), nqp);
   const int mstep = std::min(MS_MAXB, g_knobs.ms_members);
   for (int b0 = 0; b0 < batch; b0 += mstep) {
     const int mb = batch - b0 < mstep ? batch - b0 : mstep;
     // key read once; digits and c0 of the mb members read once; outputs written once
-    ProfScope ps("multsum", s, 8.0 * T.N * (2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + 2.0 * nqp)));
+    ProfScope ps("multsum", s, 8.0 * T.N * (2.0 * beta * nqp + mb * (beta * nqp + (c0 ? nq : 0) + 2.0 * nqp)),
+                 mm_qp(T, nq, nqp, L, (double)T.N * (2.0 * beta + (c0 ? 1 : 0)), (double)T.N * 2.0 * beta, mb),
+                 8.0 * T.N * (2.0 * beta * nqp + (double)mb * 4.0 * nq));
 #define MS_CASE(K)                                                                                              \
   case K:                                                                                                       \
     hipLaunchKernelGGL(k_multsum<K>, grid, dim3(TPB), 0, s, out, digits, key, c0, pmod, nq, nqp, L, beta, T.nmods, \
@@ -2256,7 +2644,7 @@ __global__ void k_plift(u64* out, const u64* c, const u64* pmod, int nq, int nqp
 void launch_plift(const DeviceTables& T, u64* out, const u64* c, const u64* pmod, int level, int alpha, int npoly,
                   hipStream_t s) {
   int nq = level + 1, nqp = nq + alpha;
-  ProfScope ps("plift", s, 8.0 * T.N * npoly * ((double)nq + nqp));
+  ProfScope ps("plift", s, 8.0 * T.N * npoly * ((double)nq + nqp), mm_q(T, nq, (double)T.N, npoly));
   dim3 grid(cdiv(T.N, TPB), nqp, npoly);
   hipLaunchKernelGGL(k_plift, grid, dim3(TPB), 0, s, out, c, pmod, nq, nqp, T.logN, T.mc);
 }
@@ -2300,7 +2688,7 @@ __global__ void k_rescale_final(u64* out, const u64* x, const u64* t, int l, int
 }
 void launch_rescale_final(const DeviceTables& T, u64* out, const u64* x, const u64* t, int l, int npoly,
                           int x_stride_limbs, const u64* qlinv, hipStream_t s) {
-  ProfScope ps("rescale_final", s, 8.0 * T.N * npoly * 3.0 * l);
+  ProfScope ps("rescale_final", s, 8.0 * T.N * npoly * 3.0 * l, mm_q(T, l, (double)T.N, npoly));
   dim3 grid(cdiv(T.N, TPB), l, npoly);
   hipLaunchKernelGGL(k_rescale_final, grid, dim3(TPB), 0, s, out, x, t, l, x_stride_limbs, qlinv, T.logN, T.mc);
 }
@@ -2367,7 +2755,7 @@ static void rescale_fused(const DeviceTables& T, u64* t, const u64* top, int l, 
   constexpr int R = 1 << (GA + GB), C = TILE / R;
   dim3 gc((1 << LOGN) / R / C, nout * npoly);
   {
-    ProfScope ps("ntt_fwd_cols_lift", s, 8.0 * T.N * npoly * (1.0 + nout));
+    ProfScope ps("ntt_fwd_cols_lift", s, 8.0 * T.N * npoly * (1.0 + nout), mm_q(T, nout, 0.5 * T.N * (GA + GB), npoly));
     hipLaunchKernelGGL((k_ntt_cols2_lift<LOGN, GA, GB>), gc, dim3(TPB), 0, s, t, top, l, nout, T.psi, T.psi_sh,
                        T.psi_f, T.mc);
   }
@@ -2378,14 +2766,10 @@ static void rescale_fused(const DeviceTables& T, u64* t, const u64* top, int l, 
 }
 bool launch_rescale_fused(const DeviceTables& T, u64* t, const u64* top_coef, int l, int nout, int npoly,
                           const u64* x, int x_stride, const u64* cpairs, u64* out, hipStream_t s) {
-  switch (T.logN) {
-    case 16: rescale_fused<16, 4, 4, 4, 4>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
-    case 15: rescale_fused<15, 4, 3, 4, 4>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
-    case 14: rescale_fused<14, 4, 3, 4, 3>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
-    case 13: rescale_fused<13, 3, 3, 4, 3>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
-    case 12: rescale_fused<12, 3, 3, 3, 3>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s); return true;
-    default: return false;
-  }
+  return ntt_dispatch(T.logN, [&](auto sp) {
+    using S = decltype(sp);
+    rescale_fused<NTT_SPLIT_ARGS>(T, t, top_coef, l, nout, npoly, x, x_stride, cpairs, out, s);
+  });
 }
 
 // ---------------------------------------------------------------------------

@@ -43,8 +43,13 @@ struct DcdFactor {
 std::vector<DcdFactor> dcd_chain(int n, const std::vector<int>& perm, int which, int nprime, int n1);
 void bsgs_steps(const std::vector<int>& perm, const LtGeom& G, std::set<long>& out, int n1p = 0);
 void lintrans_steps(int kind, int n, int n1, int nprime, std::set<long>& s);
-std::vector<long> matmul_steps(int n, int n1z, int n1t, int npz, int npt);
+std::vector<long> matmul_steps(int n, int n1z, int n1t, int npz, int npt, bool folded = false);
 std::vector<long> transpose_steps(int n, int n1);
+
+// the moduli (Q then P) and their NTT roots psi for these prime sizes (host only)
+void params_moduli(int logN, const std::vector<int>& bits, u64* moduli, u64* psi);
+// measured rate of one kind of modular product (microbench.hip)
+void modmul_peak(int kind, u64 iters, int blocks, double* rate, double* ms);
 
 // replaces a ciphertext that ran out of levels by a fresh one (client side)
 using RefreshFn = std::function<void(HeCt&)>;
@@ -159,6 +164,7 @@ struct HeCtxImpl {
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);
   HeCt rotate(const HeCt& x, long step);
+  std::vector<HeCt> rotate_many(const HeCt& x, const std::vector<long>& steps);
   size_t rotate_workspace_bytes(int level, int B) const;
   void rotate_into(const HeCt& x, long step, u64* out, void* ws, size_t ws_bytes);
   HeCt pmult_int(const HeCt& a, const i64* m_dev, double pt_scale);
@@ -181,17 +187,24 @@ struct HeCtxImpl {
   HeCt sigma_dcd(const HeCt& x, int n, int n1, int nprime);
   HeCt tau_dcd(const HeCt& x, int n, int n1, int nprime);
   HeCt matmul(const HeCt& a, const HeCt& b, int n, int n1z, int n1t, int npz, int npt, bool lazy = false,
-              bool fused_rs = false);
+              bool fused_rs = false, bool folded = false);
   // up to 8 products of one size, stacked, recorded once as a HIP graph (keyed
   // by the operands' buffers and the options) and replayed
   std::vector<HeCt> matmul_graph(const std::vector<const HeCt*>& a, const std::vector<const HeCt*>& b, int n,
-                                 int n1z, int n1t, int npz, int npt, bool lazy, bool fused_rs);
+                                 int n1z, int n1t, int npz, int npt, bool lazy, bool fused_rs, bool folded = false);
   void drop_graphs();
+  // Products run together, one host thread each, taking turns on the
+  // context: their key inner products are collected and launched as one
+  // merged launch (launch_multsum_list) once every unfinished job has handed
+  // one over.  Each job's residues are those it has alone.
+  std::vector<HeCt> run_merged(const std::vector<std::function<HeCt()>>& jobs);
   void accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   HeCt relin_sum(const DevBuf& acc3, int level, double scale, int B);
   std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level = -1,
                                   bool fused_rs = false);
   std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t, int npt, int out_level = -1);
+  // the A side with C^k's masks folded into Z: A_k = U_k a, one level
+  std::vector<HeCt> matmul_side_a_folded(const HeCt& ca, int n, int n1z);
   void align_sides(std::vector<HeCt>& Ak, std::vector<HeCt>& Bk);
   void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,

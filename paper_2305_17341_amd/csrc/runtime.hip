@@ -7,6 +7,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <cstdio>
 #include <set>
 #include <unordered_map>
@@ -117,25 +121,45 @@ static u64 hpow(u64 b, u64 e, u64 q) {
 static u64 hinv(u64 a, u64 q) { return hpow(a % q, q - 2, q); }
 u64 shoup_pre(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
 
-static bool miller_rabin(u64 n) {
-  if (n < 4) return n == 2 || n == 3;
-  if (!(n & 1)) return false;
-  u64 d = n - 1;
-  int r = 0;
-  while (!(d & 1)) { d >>= 1; r++; }
-  static const u64 bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
-  for (u64 a : bases) {
-    if (a % n == 0) continue;
+// Primality below 2^64: strong-probable-prime tests to the seven bases of
+// Sinclair's set, which no composite below 2^64 passes.
+static bool is_prime_u64(u64 n) {
+  if (n < 2) return false;
+  for (u64 p : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull})
+    if (n % p == 0) return n == p;
+  const int s = __builtin_ctzll(n - 1);
+  const u64 d = (n - 1) >> s;
+  for (u64 base : {2ull, 325ull, 9375ull, 28178ull, 450775ull, 9780504ull, 1795265022ull}) {
+    const u64 a = base % n;
+    if (a == 0) continue;
     u64 x = hpow(a, d, n);
     if (x == 1 || x == n - 1) continue;
-    bool composite = true;
-    for (int k = 1; k < r && composite; k++) {
+    bool witness = true;
+    for (int r = 1; r < s; r++) {
       x = hmul(x, x, n);
-      if (x == n - 1) composite = false;
+      if (x == n - 1) {
+        witness = false;
+        break;
+      }
     }
-    if (composite) return false;
+    if (witness) return false;
   }
   return true;
+}
+
+// Jacobi symbol (a / n) for odd n > 0 (binary method)
+static int jacobi(u64 a, u64 n) {
+  int t = 1;
+  a %= n;
+  while (a) {
+    const int z = __builtin_ctzll(a);
+    a >>= z;
+    if ((z & 1) && ((n & 7) == 3 || (n & 7) == 5)) t = -t;
+    if ((a & 3) == 3 && (n & 3) == 3) t = -t;
+    std::swap(a, n);
+    a %= n;
+  }
+  return n == 1 ? t : 0;
 }
 
 static u32 brv_host(u32 x, int bits) {
@@ -198,35 +222,39 @@ u64* HeCtxImpl::table_upload(const void* host, size_t bytes) {
   return tables.back().p;
 }
 
-// Setparams (Appendix A): for each bit size the candidates 1 + t 2N below
-// 2^bits are scanned downward; Q takes them first, then P.
+// Setparams (Appendix A): every modulus is 1 mod 2N.  For each bit size b the
+// largest such primes below 2^b are used, Q's in chain order first, then P's.
+// 2^b is a multiple of 2N here (b >= 30 > log2 2N), so the candidates below
+// it are 2^b - 2N + 1, 2^b - 4N + 1, ...; a size's next search starts below
+// the prime it last gave.
 static void choose_primes(int logN, const std::vector<int>& bits, u64* out) {
-  u64 twoN = 2ull << logN;
-  std::map<int, u64> cursor;
+  const u64 step = 2ull << logN;
+  std::map<int, u64> below;  // bit size -> the last prime taken of that size
   for (size_t k = 0; k < bits.size(); k++) {
-    int b = bits[k];
-    if (!cursor.count(b)) cursor[b] = ((1ull << b) - 2) / twoN;
-    for (;;) {
-      u64 t = cursor[b];
-      if (t == 0) fail(HE_EINVAL, "no NTT-friendly prime left");
-      cursor[b] = t - 1;
-      u64 q = t * twoN + 1;
-      if (q < (1ull << (b - 1))) fail(HE_EINVAL, "not enough NTT-friendly primes of this size");
-      if (miller_rabin(q)) {
-        out[k] = q;
-        break;
-      }
-    }
+    const int b = bits[k];
+    const u64 lowest = 1ull << (b - 1);
+    u64 q = below.count(b) ? below[b] - step : (1ull << b) - step + 1;
+    while (q > lowest && !is_prime_u64(q)) q -= step;
+    if (q <= lowest) fail(HE_EINVAL, "not enough NTT-friendly primes of this size");
+    out[k] = q;
+    below[b] = q;
   }
 }
 
-// smallest x >= 2 whose (q-1)/2N-th power has order exactly 2N
+// psi of Appendix A's NTT: x^((q-1)/2N) has order exactly 2N iff its N-th
+// power is -1, i.e. iff x^((q-1)/2) = -1: x is a quadratic non-residue
+// (Euler's criterion).  The smallest non-residue x >= 2 is found with the
+// Jacobi symbol.
 static u64 root_2n(u64 q, int logN) {
-  u64 N = 1ull << logN;
-  for (u64 x = 2;; x++) {
-    u64 r = hpow(x, (q - 1) / (2 * N), q);
-    if (hpow(r, N, q) == q - 1) return r;
-  }
+  u64 x = 2;
+  while (jacobi(x, q) != -1) x++;
+  return hpow(x, (q - 1) >> (logN + 1), q);
+}
+
+// host-only: the moduli and NTT roots a context with these prime sizes uses
+void params_moduli(int logN, const std::vector<int>& bits, u64* moduli, u64* psi) {
+  choose_primes(logN, bits, moduli);
+  for (size_t k = 0; k < bits.size(); k++) psi[k] = root_2n(moduli[k], logN);
 }
 
 static FbcTable make_fbc(HeCtxImpl* c, const std::vector<int>& src) {
@@ -887,6 +915,38 @@ HeCt HeCtxImpl::rotate(const HeCt& x, long step) {
   return moddown(h);
 }
 
+// Rotations of a batch x (one level and scale) by several steps, hoisted
+// (section 3.3.1): one Decompose of the whole batch, the key inner products
+// of every step in one multi-rotation launch, one ModDown per step.  out[r]
+// is x rotated by steps[r], with the residues rotate() gives.
+std::vector<HeCt> HeCtxImpl::rotate_many(const HeCt& x, const std::vector<long>& steps) {
+  if (x.qp) fail(HE_EINVAL, "rotation of an R_QP element");
+  std::vector<HeCt> out(steps.size());
+  std::vector<u64> gs;
+  std::vector<size_t> where;
+  for (size_t r = 0; r < steps.size(); r++) {
+    const u64 g = galois(steps[r]);
+    if (g == 1) {
+      out[r] = ct_copy(x);
+    } else {
+      key(g);  // a missing key fails before anything is launched
+      gs.push_back(g);
+      where.push_back(r);
+    }
+  }
+  if (gs.empty()) return out;
+  DevBuf dig = decompose(x.poly(1), x.level, x.B);
+  for (size_t r0 = 0; r0 < gs.size(); r0 += MR_MAX) {
+    const size_t nr = std::min(gs.size() - r0, (size_t)MR_MAX);
+    std::vector<HeCt> h = hoisted_multi(x, dig.p, std::vector<u64>(gs.begin() + r0, gs.begin() + r0 + nr));
+    for (size_t r = 0; r < nr; r++) {
+      out[where[r0 + r]] = moddown(h[r]);
+      h[r] = HeCt();
+    }
+  }
+  return out;
+}
+
 // device words a rotation of B members at `level` takes besides its input and
 // output (Decompose's coefficients and digits, the R_{Q_l P} hoisted
 // rotation, ModDown's special-prime limbs, lift and quotient), each block
@@ -1307,14 +1367,17 @@ void lintrans_steps(int kind, int n, int n1, int nprime, std::set<long>& s) {
     for (auto& f : dcd_chain(n, perm, ch, nprime, n1)) bsgs_steps(f.perm, f.G, s);
 }
 
-std::vector<long> matmul_steps(int n, int n1z, int n1t, int npz, int npt) {
+std::vector<long> matmul_steps(int n, int n1z, int n1t, int npz, int npt, bool folded) {
   std::set<long> s;
   lintrans_steps(LT_SIGMA, n, n1z, npz, s);
   lintrans_steps(LT_TAU, n, n1t, npt, s);
-  // column shifts (r < n1z, chain n1z, second chain from -n), row shifts (n r, chain n n1t)
-  for (int j = 1; j < n1z; j++) s.insert(j);
-  s.insert(n1z);
-  s.insert(-(long)n);
+  // column shifts (r < n1z, chain n1z, second chain from -n; none when they
+  // are folded into Z), row shifts (n r, chain n n1t)
+  if (!folded) {
+    for (int j = 1; j < n1z; j++) s.insert(j);
+    s.insert(n1z);
+    s.insert(-(long)n);
+  }
   for (int j = 1; j < n1t; j++) s.insert((long)n * j);
   s.insert((long)n * n1t);
   return std::vector<long>(s.begin(), s.end());
@@ -1473,6 +1536,25 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int n
   return Bk;
 }
 
+// A side with the masks of C^k folded into Z: phi^k o sigma (output (i, j)
+// takes A_{i, (i + j + k) mod n}) is a permutation whose diagonals are C^k's
+// masks times Z's diagonals, at Z's diagonal indices, so A_k is one
+// double-hoisted BSGS transform of a with Z's geometry and keys: one level
+// where section 4.1.1's masked shifts add a second.
+std::vector<HeCt> HeCtxImpl::matmul_side_a_folded(const HeCt& ca, int n, int n1z) {
+  std::vector<HeCt> Ak(n);
+  const LtGeom G = lt_geom(LT_SIGMA, n, n1z);
+  std::vector<int> perm((size_t)n * n);
+  for (int k = 0; k < n; k++) {
+    for (int i = 0; i < n; i++)
+      for (int j = 0; j < n; j++) perm[(size_t)i * n + j] = i * n + (i + j + k) % n;
+    char tag[64];
+    snprintf(tag, sizeof tag, "foldZ|n%d|k%d", n, k);
+    Ak[k] = lintrans_perm(ca, perm, G, 1.0, tag);
+  }
+  return Ak;
+}
+
 // drop both sides to their common (lowest) level
 void HeCtxImpl::align_sides(std::vector<HeCt>& Ak, std::vector<HeCt>& Bk) {
   int lv = std::min(Ak[0].level, Bk[0].level);
@@ -1522,16 +1604,21 @@ HeCt HeCtxImpl::relin_sum(const DevBuf& acc3, int level, double scale, int B) {
 }
 
 HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, int npz, int npt, bool lazy,
-                        bool fused_rs) {
+                        bool fused_rs, bool folded) {
   if (ca.qp || cb.qp || ca.level != cb.level) fail(HE_ELEVEL, "operands must be ciphertexts at one level");
   if ((u64)n * n > N / 2 || n % n1z || n % n1t || npz < 1 || npt < 1)
     fail(HE_EINVAL, "bad matrix size / baby-step count / decomposition");
+  if (folded && (fused_rs || npz < n - 1))
+    fail(HE_EINVAL, "the folded A side takes neither a decomposition of Z nor one rounding");
   int dz = npz >= n - 1 ? 1 : ceil_div_i(n - 1, npz), dt = npt >= n - 1 ? 1 : ceil_div_i(n - 1, npt);
-  if (ca.level < std::max(dz + 1, dt) + 1) fail(HE_ELEVEL, "not enough levels for the product");
+  // A side: Z (dz levels), then the masked shifts (one level), or both in one
+  // transform when folded
+  const int da = folded ? 1 : dz + 1;
+  if (ca.level < std::max(da, dt) + 1) fail(HE_ELEVEL, "not enough levels for the product");
   // both sides produced at their common level (A: sigma, then the masks;
   // B: tau); align_sides only guards the prediction
-  const int common = std::min(ca.level - dz - 1, cb.level - dt);
-  std::vector<HeCt> Ak = matmul_side_a(ca, n, n1z, npz, common, fused_rs);
+  const int common = std::min(ca.level - da, cb.level - dt);
+  std::vector<HeCt> Ak = folded ? matmul_side_a_folded(ca, n, n1z) : matmul_side_a(ca, n, n1z, npz, common, fused_rs);
   std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t, npt, common);
   align_sides(Ak, Bk);
   HeCt acc;
@@ -1554,9 +1641,11 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, 
 // reads the operands' buffers as they are at that time and rewrites the
 // arena's outputs, which are then copied out.
 std::vector<HeCt> HeCtxImpl::matmul_graph(const std::vector<const HeCt*>& a, const std::vector<const HeCt*>& b,
-                                          int n, int n1z, int n1t, int npz, int npt, bool lazy, bool fused_rs) {
+                                          int n, int n1z, int n1t, int npz, int npt, bool lazy, bool fused_rs,
+                                          bool folded) {
   if (a.empty() || a.size() != b.size() || a.size() > 8) fail(HE_EINVAL, "a recorded product takes 1 to 8 pairs");
-  std::vector<u64> key{(u64)n, (u64)n1z, (u64)n1t, (u64)npz, (u64)npt, (u64)lazy, (u64)fused_rs, (u64)a.size()};
+  std::vector<u64> key{(u64)n,    (u64)n1z,      (u64)n1t,    (u64)npz,     (u64)npt,
+                       (u64)lazy, (u64)fused_rs, (u64)folded, (u64)a.size()};
   for (const auto* v : {&a, &b})
     for (const HeCt* x : *v) {
       u64 sc;
@@ -1576,7 +1665,7 @@ std::vector<HeCt> HeCtxImpl::matmul_graph(const std::vector<const HeCt*>& a, con
     }
     auto run = [&](std::vector<HeCt>* keep) {
       HeCt sa = stack(a), sb = stack(b);
-      HeCt r = matmul(sa, sb, n, n1z, n1t, npz, npt, lazy, fused_rs);
+      HeCt r = matmul(sa, sb, n, n1z, n1t, npz, npt, lazy, fused_rs, folded);
       std::vector<HeCt> parts = unstack(r);
       if (keep) *keep = std::move(parts);
     };
@@ -1620,6 +1709,71 @@ std::vector<HeCt> HeCtxImpl::matmul_graph(const std::vector<const HeCt*>& a, con
   std::vector<HeCt> out;
   for (const HeCt& o : g.outs) out.push_back(ct_copy(o));
   return out;
+}
+
+namespace {
+struct KsGroup {
+  std::mutex mu;  // held by the job that is running
+  std::condition_variable cv;
+  int active = 0, waiting = 0;
+  u64 generation = 0;
+  bool failed = false;
+  std::string error;
+  std::vector<KsWork> pending;
+};
+}  // namespace
+
+std::vector<HeCt> HeCtxImpl::run_merged(const std::vector<std::function<HeCt()>>& jobs) {
+  KsGroup g;
+  g.active = (int)jobs.size();
+  std::vector<HeCt> res(jobs.size());
+  std::vector<std::exception_ptr> errs(jobs.size());
+  // with g.mu held: launch what is pending and release the waiting jobs
+  auto flush = [&]() {
+    if (!g.pending.empty() && !g.failed) {
+      try {
+        DevBuf tab(&pool, (multsum_list_table_bytes(T, g.pending, L, alpha) + 7) / 8);
+        launch_multsum_list(T, g.pending, tab.p, tab.words * 8, L, alpha, stream);
+      } catch (const HeError& e) {
+        g.failed = true;
+        g.error = e.msg;
+      } catch (const std::exception& e) {
+        g.failed = true;
+        g.error = e.what();
+      }
+    }
+    g.pending.clear();
+    g.waiting = 0;
+    g.generation++;
+    g.cv.notify_all();
+  };
+  auto worker = [&](size_t t) {
+    std::unique_lock<std::mutex> lk(g.mu);
+    KsSink sink = [&](KsWork&& w) {
+      if (g.failed) fail(HE_EDEVICE, "merged key switch failed: " + g.error);
+      g.pending.push_back(std::move(w));
+      g.waiting++;
+      const u64 gen = g.generation;
+      if (g.waiting == g.active) flush();
+      else g.cv.wait(lk, [&] { return g.generation != gen; });
+      if (g.failed) fail(HE_EDEVICE, "merged key switch failed: " + g.error);
+    };
+    KsSink* prev = ks_sink_exchange(&sink);
+    try {
+      res[t] = jobs[t]();
+    } catch (...) {
+      errs[t] = std::current_exception();
+    }
+    ks_sink_exchange(prev);
+    g.active--;
+    if (g.active > 0 && g.waiting == g.active) flush();
+  };
+  std::vector<std::thread> threads;
+  for (size_t t = 0; t < jobs.size(); t++) threads.emplace_back(worker, t);
+  for (auto& th : threads) th.join();
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+  return res;
 }
 
 void HeCtxImpl::drop_graphs() {

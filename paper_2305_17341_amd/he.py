@@ -29,7 +29,7 @@ EXPORTS = [
     "he_mem_info", "he_trim", "he_device_memory", "he_ntt_limbs", "he_automorph_limbs", "he_hoisted_rotate_export", "he_last_op_ms",
     "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_smpkeysub_rot_steps", "he_refresh",
     "he_power_rot_steps", "he_power_step", "he_eigen_shift", "he_knob_set", "he_knob_get", "he_last_error",
-    "he_rotate_noalloc", "he_rotate_workspace_bytes",
+    "he_rotate_noalloc", "he_rotate_workspace_bytes", "he_modmul_peak", "he_profile_read_ops", "he_rotate_many", "he_params_moduli",
 ]
 
 # he_refresh_fn: status (he_ct*, void* user)
@@ -51,6 +51,26 @@ class he_params(C.Structure):
     _fields_ = [("log_n", C.c_uint32), ("q_bits", C.POINTER(C.c_uint32)), ("n_q", C.c_uint32),
                 ("p_bits", C.POINTER(C.c_uint32)), ("n_p", C.c_uint32), ("log2_scale", C.c_double),
                 ("sigma", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class he_device(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", C.c_void_p), ("hip_stream", C.c_void_p)]
+
+
+class DeviceHooks:
+    """A caller's device allocator and HIP stream for a context (he_device):
+    alloc(nbytes) -> device address (int, 0 on failure), release(address),
+    stream = a HIP stream handle (int) or None.  The callbacks stay alive
+    with this object, which must outlive the context."""
+
+    def __init__(self, alloc=None, release=None, stream=None):
+        self._alloc = ALLOC_FN(lambda n, user: alloc(n) or None) if alloc else ALLOC_FN()
+        self._release = RELEASE_FN(lambda ptr, user: release(ptr)) if release else RELEASE_FN()
+        self.struct = he_device(self._alloc, self._release, None, stream)
 
 
 class he_matmul_opts(C.Structure):
@@ -93,6 +113,10 @@ def load():
         "he_rotate": [vp, vp, C.c_int32, C.POINTER(vp)],
         "he_drop_level": [vp, vp, C.c_uint32, C.POINTER(vp)],
         "he_rotate_noalloc": [vp, vp, C.c_int32, vp],
+        "he_rotate_many": [vp, C.POINTER(vp), C.c_size_t, C.POINTER(C.c_int32), C.c_size_t, C.POINTER(vp)],
+        "he_modmul_peak": [C.c_uint32, C.c_uint64, C.c_uint32, dblp, dblp],
+        "he_params_moduli": [C.POINTER(he_params), u64p, u64p, C.c_size_t],
+        "he_profile_read_ops": [vp, C.c_char_p, dblp, dblp, dblp],
         "he_rotate_workspace_bytes": [vp, C.c_uint32, C.POINTER(C.c_size_t)],
         "he_pmult_slots": [vp, vp, dblp, C.c_size_t, C.c_double, C.POINTER(vp)],
         "he_lintrans": [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, C.POINTER(vp)],
@@ -194,13 +218,15 @@ class Ciphertext:
 class Context:
     """One CKKS parameter set on the current HIP device."""
 
-    def __init__(self, log_n, q_bits, p_bits, log2_scale=40.0, sigma=3.2, seed=1):
+    def __init__(self, log_n, q_bits, p_bits, log2_scale=40.0, sigma=3.2, seed=1, hooks=None):
         L = load()
         self._qb = (C.c_uint32 * len(q_bits))(*q_bits)
         self._pb = (C.c_uint32 * len(p_bits))(*p_bits)
         prm = he_params(log_n, self._qb, len(q_bits), self._pb, len(p_bits), log2_scale, sigma)
         ptr = vp()
-        _check(L.he_ctx_create(C.byref(prm), None, seed, C.byref(ptr)))
+        self._hooks = hooks
+        dev = C.cast(C.pointer(hooks.struct), vp) if hooks is not None else None
+        _check(L.he_ctx_create(C.byref(prm), dev, seed, C.byref(ptr)))
         self.ptr = ptr
         self.log_n = log_n
         self.N = 1 << log_n
@@ -290,6 +316,15 @@ class Context:
 
     def rotate(self, a, step):
         return self._ct(load().he_rotate, a.ptr, int(step))
+
+    def rotate_many(self, cts, steps):
+        """hoisted rotations of every ciphertext by every step: result[i][r] = Rot(cts[i], steps[r])"""
+        a = (vp * len(cts))(*[c.ptr.value for c in cts])
+        st = (C.c_int32 * len(steps))(*[int(x) for x in steps])
+        out = (vp * (len(cts) * len(steps)))()
+        _check(load().he_rotate_many(self.ptr, a, len(cts), st, len(steps), out))
+        return [[Ciphertext(self, vp(out[i * len(steps) + r])) for r in range(len(steps))]
+                for i in range(len(cts))]
 
     def rotate_noalloc(self, a, step, out):
         """Rotation into the existing ciphertext `out` (a's level) with no
@@ -401,6 +436,13 @@ class Context:
         _check(load().he_profile_read(self.ptr, family.encode(), C.byref(ms), C.byref(n), C.byref(b)))
         return ms.value, n.value, b.value
 
+    def profile_read_ops(self, family):
+        """(FP64 modular products, integer modular products, bytes in the key
+        switch's unit of work) of a kernel family since enabling."""
+        f, i, u = C.c_double(), C.c_double(), C.c_double()
+        _check(load().he_profile_read_ops(self.ptr, family.encode(), C.byref(f), C.byref(i), C.byref(u)))
+        return f.value, i.value, u.value
+
     def op_counts(self):
         a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
         _check(load().he_op_counts(self.ptr, C.byref(a), C.byref(b), C.byref(c)))
@@ -427,6 +469,28 @@ class Context:
         out = np.zeros(2 * (lv + 1 + self.alpha) * self.N, dtype=np.uint64)
         _check(load().he_hoisted_rotate_export(self.ptr, a.ptr, int(step), out.ctypes.data_as(u64p), out.size))
         return out.reshape(2, lv + 1 + self.alpha, self.N)
+
+
+def params_moduli(log_n, q_bits, p_bits):
+    """Host only: (moduli, psi) a context with these prime sizes uses."""
+    qb = (C.c_uint32 * len(q_bits))(*q_bits)
+    pb = (C.c_uint32 * len(p_bits))(*p_bits)
+    prm = he_params(log_n, qb, len(q_bits), pb, len(p_bits), 40.0, 3.2)
+    n = len(q_bits) + len(p_bits)
+    m, psi = (C.c_uint64 * n)(), (C.c_uint64 * n)()
+    _check(load().he_params_moduli(C.byref(prm), m, psi, n))
+    return [int(x) for x in m], [int(x) for x in psi]
+
+
+MODMUL_KINDS = {"f64_lazy": 0, "shoup": 1, "barrett": 2, "f64_butterfly": 3}
+
+
+def modmul_peak(kind, iters=4096, blocks=8192):
+    """Measured rate (products/s) of one kind of modular product on the
+    current device (he_modmul_peak); returns (rate, ms)."""
+    r, ms = C.c_double(), C.c_double()
+    _check(load().he_modmul_peak(MODMUL_KINDS[kind], iters, blocks, C.byref(r), C.byref(ms)))
+    return r.value, ms.value
 
 
 def lintrans_rot_steps(kind, d, n1, nprime=0):
