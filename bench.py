@@ -104,43 +104,136 @@ def pct(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if xs else None
 
 
-def cpu_baseline(chain, counts, n_rescale, seconds_budget=30.0):
-    """Oracle on a bounded sample: one Decompose, one hoisted rotation, one
-    ModDown and one Rescale at the top level of the chain, scaled to one
-    product by the product's operation counts."""
+# one wave64 VALU instruction per SIMD every 4 clocks at full rate: 256 CUs x
+# 4 SIMDs x 64 lanes at 2.4 GHz = 39.3 T lane-operations/s
+LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+# full-rate VALU instructions per lazy FP64 product (mul, fma, mul, rndne, fma, add)
+F64_LAZY_INSTR = 6
+
+
+def valu_ceilings(log=print):
+    """measured rates (products/s) of the four product kinds the kernels use
+    (he_modmul_peak: eight register-resident chains per thread, no memory),
+    best of three, beside the unit-count figure for the lazy FP64 product"""
+    from paper_2305_17341_amd import he
+    out = {}
+    for kind in he.MODMUL_KINDS:
+        he.modmul_peak(kind, iters=256, blocks=2048)
+        best = max(he.modmul_peak(kind, iters=2048, blocks=8192)[0] for _ in range(3))
+        out[kind] = {"measured": best}
+    out["f64_lazy"]["from_unit_counts"] = LANE_OPS_PEAK / F64_LAZY_INSTR
+    log("[bench] product ceilings (G/s): " + ", ".join(f"{k} {v['measured'] / 1e9:.0f}" for k, v in out.items()))
+    return out
+
+
+def cpu_model():
+    """the host's CPU model name and the threads this process may use"""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def _median_time(f, reps):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        f()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def cpu_baseline(chain, counts, n_rescale, d, log=print):
+    """The CPU oracle (plain C, 128-bit % products, OpenMP over limbs) timed on
+    this host, every figure a direct measurement:
+      * the small (N=2^13, 16x16) and mid (N=2^14, 64x64, (A B) C chained)
+        products in full, on all usable threads and on one;
+      * one key-switched rotation at N=2^16, level 30 (all threads, one);
+      * the operations of the headline product at N=2^16, level 29, each timed
+        on its own (median of three): Decompose, the key inner product of one
+        rotation, ModDown, Rescale, Tensor.
+    `value` (products/s of the headline product) is the sum of the last ones
+    weighted by the product's operation counts (from the GPU library's
+    counters: Decompose, key inner products, ModDown per product; d tensors,
+    `n_rescale` rescales); it is an extrapolation from measured operations,
+    labelled as such."""
     from oracle import oracle as O
+    from paper_2305_17341_amd import he, inputs as I
+    model, nproc, usable = cpu_model()
+    threads = int(os.environ.get("OMP_NUM_THREADS", usable))
+    out = {"unit": "matmuls/s", "cores": threads, "kind": "oracle", "cpu_model": model, "nproc": nproc,
+           "usable_cpus": usable, "measured": {}}
+    meas = out["measured"]
+
+    def both(tag, f, reps_all=1):
+        O.set_threads(threads)
+        t_all = _median_time(f, reps_all)
+        O.set_threads(1)
+        t_one = _median_time(f, 1)
+        O.set_threads(threads)
+        meas[tag] = {"s_all_threads": round(t_all, 4), "s_one_thread": round(t_one, 4)}
+        log(f"[bench] oracle {tag}: {t_all:.3f} s on {threads} threads, {t_one:.3f} s on one")
+
+    # small and mid products in full
+    for ch, n, chained, tag in ((I.SMALL, 16, False, "small_16x16_n13"), (I.MID, 64, True, "mid_64x64_n14_chained")):
+        o = O.Oracle(ch.log_n, ch.q_bits, ch.p_bits, seed=5)
+        n1 = 1 << ((n.bit_length() - 1 + 1) // 2)   # 2^ceil(log2(n) / 2), the library's default
+        steps = sorted(set(he.lintrans_rot_steps("Z", n, n1)) | set(he.lintrans_rot_steps("T", n, n1)) |
+                       set(range(1, n1)) | {n1, -n} | {n * j for j in range(1, n1)} | {n * n1})
+        o.keygen(rot_steps=steps)
+        A, B, Cm = I.uniform_matrix(1, n), I.uniform_matrix(2, n), I.uniform_matrix(3, n)
+        ca, cb = o.encrypt(A.ravel(), nonce=1), o.encrypt(B.ravel(), nonce=2)
+        if chained:
+            def run():
+                ab = o.matmul(ca, cb, n, n1, n1)
+                o.matmul(ab, o.encrypt(Cm.ravel(), level=ab.level, nonce=3), n, n1, n1)
+        else:
+            def run():
+                o.matmul(ca, cb, n, n1, n1)
+        both(tag, run)
+        del o
+    # rotation and the product's operations at N = 2^16
     o = O.Oracle(chain.log_n, chain.q_bits, chain.p_bits, seed=5)
-    o.keygen(rot_steps=[1], relin=False)
+    o.keygen(rot_steps=[1], relin=True)
     z = np.random.default_rng(0).uniform(-1, 1, o.slots)
     ct = o.encrypt(z, nonce=1)
-    lvl = ct.level
-    t0 = time.perf_counter()
-    o.decompose(ct.data()[1], lvl)
-    t_dp = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    h = o.hoisted_rotate(ct, 1)
-    t_hr = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    md = o.moddown(h)
-    t_md = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    o.rescale(md)
-    t_rs = time.perf_counter() - t0
-    t_ms = max(t_hr - t_dp, 0.0)
-    t_rot = t_hr + t_md
-    t_mm = counts["decompose"] * t_dp + counts["multsum"] * t_ms + counts["moddown"] * t_md + n_rescale * t_rs
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {
-        "value": 1.0 / t_mm,
-        "unit": "matmuls/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": (f"oracle at N=2^{chain.log_n}, level {lvl}: one Decompose ({t_dp:.2f} s), one hoisted "
-                   f"rotation ({t_hr:.2f} s), one ModDown ({t_md:.2f} s), one Rescale ({t_rs:.2f} s); one "
-                   f"product extrapolated from its operation counts {counts} and {n_rescale} rescales "
-                   f"(top-level costs, an upper bound)"),
-        "rotations_per_s": 1.0 / t_rot,
+    both(f"rotation_n16_level{ct.level}", lambda: o.rotate(ct, 1), reps_all=3)
+    c29 = o.drop(ct, ct.level - 1)
+    lvl = c29.level
+    O.set_threads(threads)
+    digits = o.decompose(c29.data()[1], lvl)
+    h = o.hoisted_rotate_digits(c29, digits, 1)
+    ops = {
+        "decompose": _median_time(lambda: o.decompose(c29.data()[1], lvl), 3),
+        "multsum": _median_time(lambda: o.hoisted_rotate_digits(c29, digits, 1), 3),
+        "moddown": _median_time(lambda: o.moddown(h), 3),
+        "rescale": _median_time(lambda: o.rescale(c29), 3),
+        "tensor": _median_time(lambda: o.tensor(c29, c29), 3),
     }
+    meas[f"ops_n16_level{lvl}_s"] = {k: round(v, 4) for k, v in ops.items()}
+    n_tensor = d
+    t_mm = (counts["decompose"] * ops["decompose"] + counts["multsum"] * ops["multsum"] +
+            counts["moddown"] * ops["moddown"] + n_rescale * ops["rescale"] + n_tensor * ops["tensor"])
+    out["value"] = 1.0 / t_mm
+    out["rotations_per_s"] = 1.0 / meas[f"rotation_n16_level{ct.level}"]["s_all_threads"]
+    out["sample"] = (f"oracle on this host ({model}, {threads} threads): the {d}x{d} product at N=2^{chain.log_n} "
+                     f"extrapolated from its operations each timed at level {lvl} (median of 3): "
+                     f"{counts['decompose']:.0f} Decompose x {ops['decompose']:.3f} s, {counts['multsum']:.0f} key "
+                     f"inner products x {ops['multsum']:.3f} s, {counts['moddown']:.0f} ModDown x "
+                     f"{ops['moddown']:.3f} s, {n_rescale} Rescale x {ops['rescale']:.3f} s, {n_tensor} Tensor x "
+                     f"{ops['tensor']:.3f} s = {t_mm:.1f} s; the small and mid products and one rotation at "
+                     f"N=2^16 measured in full (see measured)")
+    return out
 
 
 def main():
@@ -162,7 +255,10 @@ def main():
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--rotations", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving run (0: skip it)")
+    ap.add_argument("--serve-jobs", type=int, default=300,
+                    help="jobs per serving trace: the capacity run and each offered load (0: skip serving)")
+    ap.add_argument("--serve-loads", default="0.2,0.6,1.0,1.2",
+                    help="offered loads of the serving sweep, as fractions of the measured batched capacity")
     ap.add_argument("--pca-components", type=int, default=8, help="components of the PCA run (0: skip it)")
     ap.add_argument("--n1", type=int, default=64,
                     help="baby steps of Z and T and the block size of the column/row shifts (0: the library's "
@@ -275,6 +371,7 @@ def main():
             "fbc_to_q",
             "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor", "plift"]
     prof = {f: ctx.profile_read(f) for f in fams}
+    ops = {f: ctx.profile_read_ops(f) for f in fams}
     ctx.profile_enable(False)
     n_mm = args.steps * B
     per_mm = {k: (c1[k] - c0[k]) / n_mm for k in c0}
@@ -284,7 +381,8 @@ def main():
     head_same = bool(np.array_equal(alone.export(), outs[0].export()))
     del outs, plain_outs, alone
 
-    # key-switched rotations at the top level
+    # key-switched rotations at the top level: one at a time (plain), and
+    # hoisted over a batch (one Decompose, one multi-rotation launch)
     ct = cA[0]
     ctx.sync()
     t0 = time.perf_counter()
@@ -292,25 +390,69 @@ def main():
         r = ctx.rotate(ct, 1)
         del r
     ctx.sync()
-    rot_s = args.rotations / (time.perf_counter() - t0)
+    rot_s = args.rotations / (time.perf_counter() - t0) if args.rotations > 0 else None
+    rot_steps = list(range(1, args.n1)) if args.n1 > 1 else list(range(1, 16))
+    rb = ctx.rotate_many(cA, rot_steps)   # warm-up
+    ctx.sync()
+    del rb
+    t0 = time.perf_counter()
+    for _ in range(2):
+        rb = ctx.rotate_many(cA, rot_steps)
+        del rb
+    ctx.sync()
+    rot_batched_s = 2 * len(cA) * len(rot_steps) / (time.perf_counter() - t0)
     for _ in range(args.calib_copies):
         r = ctx.rotate(ct, 0)   # step 0: a plain device copy of 2 x 31 limbs
         del r
     ctx.sync()
 
     value = args.steps * B / t_total
+    step_s = t_total / args.steps
     fam_ms = {f: prof[f][0] / args.steps for f in fams}
     dom = max(fams, key=lambda f: prof[f][0])
     ms, launches, nbytes = prof[dom]
+    mmf, mmi, unit_bytes = ops[dom]
     avg_ms = ms / max(launches, 1)
     bytes_per_launch = nbytes / max(launches, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    unit_per_launch = unit_bytes / max(launches, 1)
+    achieved_io = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    achieved = unit_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(dom, args.n1, {k: he.knob_get(k) for k in autotune_knobs()})
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    # VALU side: measured ceilings of the products (lazy FP64 for moduli below
+    # 2^46, Shoup for the others) against each family's algorithmic products
+    peaks = valu_ceilings(log)
+    pf, pi = peaks["f64_lazy"]["measured"], peaks["shoup"]["measured"]
+
+    def valu_floor_s(f):
+        a, b, _ = ops[f]
+        return a / pf + b / pi
+    valu_frac = valu_floor_s(dom) / (ms * 1e-3) if ms > 0 else None
+    hbm_frac = achieved / HBM_PEAK_GBS
+    step_unit_bytes = sum(ops[f][2] for f in fams) / args.steps
+    step_mm = sum(ops[f][0] + ops[f][1] for f in fams) / args.steps
+    step_valu_s = sum(valu_floor_s(f) for f in fams) / args.steps
+    roofline = {"kernel": dom, "bound": "hbm" if hbm_frac >= (valu_frac or 0) else "alu",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm_frac, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "avg_launch_ms": round(avg_ms, 5), "launches": launches,
-                "algorithmic_bytes_per_launch": round(bytes_per_launch)}
+                "algorithmic_bytes_per_launch": round(unit_per_launch),
+                "bytes_rule": "key switch unit: each switching key read once per launch (2 beta (l+1+alpha) limbs), "
+                              "each member's ciphertext read and written once per rotation (4 (l+1) limbs)",
+                "kernel_io_bytes_per_launch": round(bytes_per_launch),
+                "kernel_io_achieved": round(achieved_io, 1), "kernel_io_frac": round(achieved_io / HBM_PEAK_GBS, 4),
+                "valu": {"modmuls_per_launch": round((mmf + mmi) / max(launches, 1)),
+                         "modmuls_f64_share": round(mmf / max(mmf + mmi, 1), 4),
+                         "achieved_modmuls_per_s": round((mmf + mmi) / max(launches, 1) / (avg_ms * 1e-3), 1),
+                         "frac": None if valu_frac is None else round(valu_frac, 4),
+                         "rule": "time the kernel's algorithmic modular products need at the measured ceilings "
+                                 "(lazy FP64 products / f64_lazy rate + integer products / shoup rate) over the "
+                                 "measured launch time"},
+                "valu_ceilings_modmuls_per_s": peaks,
+                "step": {"ms": round(step_s * 1e3, 3),
+                         "algorithmic_bytes": round(step_unit_bytes),
+                         "hbm_frac": round(step_unit_bytes / step_s / (HBM_PEAK_GBS * 1e9), 4),
+                         "modmuls": round(step_mm),
+                         "valu_frac": round(step_valu_s / step_s, 4)}}
     # sigma, tau, the d column shifts (merged into their ModDowns when the A
     # side rounds once), the final product
     n_rescale = 2 + 1 + (0 if head["flags"] & FUSED else d)
@@ -344,13 +486,23 @@ def main():
             "latency_ms": {"p50": pct(lat_bp, 50), "p99": pct(lat_bp, 99)},
             "speedup_vs_plain": round(t_plain / t_bp, 3), "residues_identical_to_plain": same},
         "speedup_vs_plain": None if args.no_plain else round(t_plain / t_total, 3),
-        "rotations_per_s": round(rot_s, 2),
+        "rotations_per_s": round(rot_s, 2) if rot_s else None,
+        "rotations_per_s_batched": {"value": round(rot_batched_s, 2),
+                                    "what": f"{len(cA)} ciphertexts x {len(rot_steps)} steps per call, hoisted: one "
+                                            "Decompose of the batch, one multi-rotation launch, one ModDown per "
+                                            "step (he_rotate_many)",
+                                    "speedup_vs_plain": round(rot_batched_s / rot_s, 3) if rot_s else None},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "max_abs_err": err,
         "op_counts_per_matmul": per_mm,
         "kernel_ms_per_step": {f: round(v, 3) for f, v in fam_ms.items()},
         "kernel_algorithmic_gbs": {f: round(prof[f][2] / (prof[f][0] * 1e-3) / 1e9, 1)
                                    for f in fams if prof[f][0] > 0},
+        # per family: HBM fraction of its algorithmic bytes, and the fraction of
+        # its time its algorithmic modular products need at the measured ceilings
+        "kernel_fracs": {f: {"hbm": round(ops[f][2] / (prof[f][0] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                             "valu": round(valu_floor_s(f) / (prof[f][0] * 1e-3), 4)}
+                         for f in fams if prof[f][0] > 0},
         "roofline": roofline,
     }
     # the recorded graph's arena and the pool's cached blocks go back to the
@@ -359,8 +511,8 @@ def main():
     if args.serve_jobs > 0:
         from paper_2305_17341_amd import serve
         log("[bench] serving run ...")
-        result["serving"] = serve.serve_bench(["--jobs", str(args.serve_jobs), "--cov-samples",
-                                               str(args.serve_cov_samples)])
+        result["serving"] = serve.serve_bench(["--jobs", str(args.serve_jobs), "--loads", args.serve_loads,
+                                               "--cov-samples", str(args.serve_cov_samples)])
     # each part below builds and closes its own contexts; collect what the
     # previous part left so that its device memory is back before the next
     import gc
@@ -394,7 +546,7 @@ def main():
         result["table3"] = table3.run(reps=args.table3_reps, log=log)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
-        result["cpu_baseline"] = cpu_baseline(chain, per_mm, n_rescale)
+        result["cpu_baseline"] = cpu_baseline(chain, per_mm, n_rescale, d, log=log)
     print(json.dumps(result), flush=True)
 
 

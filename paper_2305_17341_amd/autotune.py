@@ -1,6 +1,7 @@
 """Launch-shape autotuner: times the batched product under each value of the
 library's knobs (members and rotations per launch, the order in which the
-block passes and the plaintext sums visit limbs) and keeps the fastest.
+block passes and the plaintext sums visit limbs, the NTT's stage split
+between its column and block passes) and keeps the fastest.
 The knobs only regroup or reorder work, so every choice gives the same
 residues; the timing decides."""
 from __future__ import annotations
@@ -17,6 +18,19 @@ CANDIDATES = {
     "ew_interleave": (0, 1),
     "mr_group": (1, 2, 4),
 }
+
+
+# the NTT's stage split, per ring size that has an alternative (tuned on a
+# product of that ring size)
+NTT_SPLIT_LOG_N = (13, 14, 15)
+
+
+def autotune_ntt_split(ctx, cA, cB, d, opts=None, log=None, margin=0.01):
+    """the stage split of the register-blocked NTT for ctx's ring size"""
+    if ctx.log_n not in NTT_SPLIT_LOG_N:
+        return {}, {}
+    return autotune(ctx, cA, cB, d, opts=opts, candidates={f"ntt_split_{ctx.log_n}": (0, 1)}, log=log,
+                    margin=margin)
 
 
 def autotune(ctx, cA, cB, d, opts=None, candidates=CANDIDATES, log=None, margin=0.01):

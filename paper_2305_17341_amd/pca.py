@@ -9,7 +9,7 @@ import time
 
 import numpy as np
 
-from . import he
+from . import he, packing
 
 
 def taylor_point(B2: float) -> float:
@@ -182,7 +182,7 @@ def accuracy_bench(cases=None, seed=7, log=print, ctx=None):
     for ci, (name, s, l_e, l_p) in enumerate(cases):
         X = I.pca_dataset(seed + ci, s, t)
         rb = -(-s // n)
-        blk = I.blocks(X, n)
+        blk = packing.blocks(X, n)
         cts = [ctx.encrypt_matrix(blk[r, c], nonce=(ci << 20) + r * k + c) for r in range(rb) for c in range(k)]
         ctx.sync()
         t0 = time.perf_counter()
@@ -235,7 +235,7 @@ def covariance_bench(s=60000, t=256, seed=13, stacked=(4, 8), log=print, n1=64):
     ctx = he.chain_context(I.LARGE, seed=seed)
     ctx.keygen(sorted(set(ctx.matmul_rot_steps(n, dict(geo) or None)) | set(ctx.transpose_rot_steps(n))))
     X = I.centre(I.dataset(seed, s, t))
-    blk = I.blocks(X, n)
+    blk = packing.blocks(X, n)
     t0 = time.perf_counter()
     cts = [ctx.encrypt_matrix(blk[r, c], nonce=(1 << 30) + r * k + c) for r in range(rb) for c in range(k)]
     ctx.sync()
@@ -291,7 +291,7 @@ def pca_bench(l_e=8, l_p=14, seed=3, log=print, goldschmidt=False, pack=False):
     steps = set(ctx.matmul_rot_steps(n)) | set(ctx.transpose_rot_steps(n)) | set(he.power_rot_steps(n))
     ctx.keygen(sorted(steps))
     X = I.centre(I.pca_dataset(seed, rb * n, k * n))
-    blk = I.blocks(X, n)
+    blk = packing.blocks(X, n)
     cts = [ctx.encrypt_matrix(blk[r, c], nonce=10 + r * k + c) for r in range(rb) for c in range(k)]
     ctx.sync()
     t0 = time.perf_counter()

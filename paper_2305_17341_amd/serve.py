@@ -13,13 +13,15 @@ Scheduling
     order while the admitted footprints fit the budget; a request larger
     than the whole budget is rejected at submission.
   * Continuous batching: one worker per context.  Whenever a worker is free
-    it takes the oldest admitted request of its N together with every other
-    admitted product of the same d (up to `max_batch`) and runs them as one
-    stacked batch, so requests that arrived while earlier work was on the
-    device join the next launch sequence.  Workers of different N run
+    it takes the oldest admitted request of its N together with the other
+    admitted products of that N, of any size (up to `max_batch`), and runs
+    them as one merged batch: products of equal d are stacked, and the
+    stacks of different d run together with their key inner products merged
+    into shared launches (HE_MM_MERGED).  Requests that arrived while earlier
+    work was on the device join the next batch.  Workers of different N run
     concurrently, each on its context's stream, so their kernels overlap on
     the GPU.  Memory freed by a finished batch admits waiting requests.
-  * The batched path gives the same residues as running a product alone, so
+  * The merged path gives the same residues as running a product alone, so
     a result does not depend on what it was batched with.
 
 Latency is measured per request from submission to the host seeing its
@@ -37,6 +39,7 @@ from dataclasses import dataclass, field
 BATCHED = 1  # HE_MM_BATCHED
 LAZY_RELIN = 2  # HE_MM_LAZY_RELIN
 FUSED_RESCALE = 4  # HE_MM_FUSED_RESCALE
+MERGED = 64  # HE_MM_MERGED
 POOL_SLACK = 1.25  # a cached device block is reused for requests down to 1/1.25 of its size
 
 
@@ -149,7 +152,7 @@ class HeBackend:
             out = [ctx.covariance(blocks, rb, k, reqs[0].d, n_samples, opts={"flags": self.relin_flags})]
         else:
             out = ctx.matmul_batch([r.args[0] for r in reqs], [r.args[1] for r in reqs], [r.d for r in reqs],
-                                   opts={"flags": BATCHED | self.relin_flags})
+                                   opts={"flags": BATCHED | MERGED | self.relin_flags})
         ctx.sync()
         return out
 
@@ -251,7 +254,7 @@ class Server:
         if head.kind != "matmul":
             group = [head]
         else:
-            group = [r for r in ready if r.kind == "matmul" and r.d == head.d][: self.max_batch]
+            group = [r for r in ready if r.kind == "matmul"][: self.max_batch]
         ids = {id(r) for r in group}
         self._ready[log_n] = [r for r in ready if id(r) not in ids]
         return group
@@ -280,13 +283,16 @@ class Server:
                 self._batches.append(len(group))
                 self._admit()
                 idle = not self._ready[log_n]
+                # an idle context gives its cached blocks back only while
+                # other contexts have work waiting that may need the memory
+                others_busy = bool(self._pending) or any(self._ready[n] for n in self._ready if n != log_n)
                 self._cv.notify_all()
             for i, r in enumerate(group):
                 if err is None:
                     r.future.set_result(out[i])
                 else:
                     r.future.set_exception(err)
-            if idle and self.trim_when_idle:
+            if idle and others_busy and self.trim_when_idle:
                 self.backend.release(log_n, self.budget // len(self._ready))
 
 
@@ -321,25 +327,31 @@ def main(argv=None):
 
 
 def serve_bench(argv=None):
-    """Poisson mix of products over every (d, N) pair with d in {16, 32, 64,
+    """Poisson mixes of products over every (d, N) pair with d in {16, 32, 64,
     128}, N in {2^13 .. 2^16} and d^2 <= N/2, plus one block-covariance job
-    at N = 2^16; prints one JSON line with jobs/s and p50/p99 latency."""
+    at N = 2^16.  First the batched capacity: every job of a trace offered at
+    once (served jobs/s and mean batch); then the offered load swept as
+    fractions of that capacity (each load a trace of its own, the covariance
+    job in the middle of the last one); each reports served jobs/s, p50/p99
+    latency and the mean batch.  Returns one dict (printed by main())."""
     import argparse
     import sys
 
     import numpy as np
 
-    from . import inputs as I
+    from . import inputs as I, packing
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=120)
-    ap.add_argument("--load", type=float, default=0.8, help="offered rate as a fraction of the one-at-a-time rate")
+    ap.add_argument("--jobs", type=int, default=300, help="jobs per trace (capacity run and each load)")
+    ap.add_argument("--loads", default="0.2,0.6,1.0,1.2",
+                    help="offered rates as fractions of the measured batched capacity")
     ap.add_argument("--budget-gib", type=float, default=0.0, help="0: half of the free device memory")
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--no-covariance", action="store_true")
     ap.add_argument("--cov-samples", type=int, default=256,
                     help="rows of the covariance job's dataset (256 features; the workload's job has 60000)")
     args = ap.parse_args(argv)
+    loads = [float(x) for x in args.loads.split(",") if x]
 
     def log(m):
         print(m, file=sys.stderr, flush=True)
@@ -354,6 +366,20 @@ def serve_bench(argv=None):
     backend = HeBackend(chains, ds_by, seed=args.seed, covariance_d=() if args.no_covariance else ((16, cov_n),))
     log(f"[serve] contexts and keys for {len(pairs)} (d, N) pairs in {time.perf_counter() - t0:.1f} s")
 
+    # the NTT stage split of each ring size that has an alternative, tuned on a
+    # batch of four of its largest products
+    from . import autotune
+    tuned = {}
+    for ln, ctx in backend.contexts.items():
+        d = max(ds_by[ln])
+        A = I.uniform_matrix(3, d)
+        cs = [ctx.encrypt_matrix(A, nonce=50 + i) for i in range(4)]
+        ctx.matmul_batch(cs, cs, [d] * 4, opts={"flags": BATCHED | backend.relin_flags})   # warm caches
+        best, tt = autotune.autotune_ntt_split(ctx, cs, cs, d, opts={"flags": BATCHED | backend.relin_flags},
+                                               log=log)
+        tuned.update({k: {"value": v, "ms": tt[k]} for k, v in best.items()})
+        del cs
+
     # warm-up: every pair once alone (fills the plaintext caches), then its solo latency
     solo = {}
     for d, ln in pairs:
@@ -367,83 +393,103 @@ def serve_bench(argv=None):
             solo[(d, ln)] = time.perf_counter() - t
             del r
     one_at_a_time = len(pairs) / sum(solo.values())
-    rate = args.load * one_at_a_time
     log(f"[serve] solo latency per pair (ms): " + ", ".join(f"d={d}/2^{ln}: {1e3 * s:.1f}"
                                                           for (d, ln), s in sorted(solo.items())))
-
-    jobs = I.poisson_jobs(args.seed, args.jobs, rate, pairs)
-    payloads, plain = [], []
-    for j in jobs:
-        ctx = backend.contexts[j.log_n]
-        A, B = I.uniform_matrix(j.seed, j.d), I.uniform_matrix(j.seed + 1, j.d)
-        payloads.append(("matmul", j.log_n, j.d,
-                         (ctx.encrypt_matrix(A, nonce=2 * j.seed), ctx.encrypt_matrix(B, nonce=2 * j.seed + 1))))
-        plain.append(A @ B)
-    extra = []
-    cov_rb = -(-args.cov_samples // cov_n)
-    if not args.no_covariance:
-        # cov_samples x 256 uniform[0,1] dataset, centred on the client, as
-        # cov_rb x 2 blocks of 128 x 128 (the last row block zero-padded)
-        X = I.centre(I.dataset(args.seed, args.cov_samples, 2 * cov_n))
-        blk = I.blocks(X, cov_n)
-        ctx = backend.contexts[16]
-        cts = [ctx.encrypt_matrix(blk[r, c], nonce=10**6 + 2 * r + c) for r in range(cov_rb) for c in range(2)]
-        extra.append((jobs[len(jobs) // 2].arrival, ("covariance", 16, cov_n, (cts, cov_rb, 2, X.shape[0]))))
-        del blk
     ctx16 = backend.contexts[16]
-    for c in backend.contexts.values():
-        c.sync()
-
     if args.budget_gib > 0:
         budget = int(args.budget_gib * 2**30)
     else:
         from . import he
         free, _ = he.device_memory()
         budget = int(0.5 * free)
-    srv = Server(backend, hbm_budget=budget)
-    log(f"[serve] {len(jobs)} jobs at {rate:.2f} jobs/s offered (load {args.load} of {one_at_a_time:.2f}/s), "
-        f"budget {budget / 2**30:.1f} GiB")
-    futs = run_trace(srv, jobs, payloads, extra)
-    results = [f.result() for _, f in futs]
-    srv.close()
-    st = srv.stats()
-    log(f"[serve] done: {st['jobs']} jobs, {st['batches']} batches")
+    X = I.centre(I.dataset(args.seed, args.cov_samples, 2 * cov_n)) if not args.no_covariance else None
 
-    # client side: every 8th product and the covariance decrypted against FP64
-    errs = []
-    for (kind, ln, d, a), res in zip([p for p, _ in futs], results):
-        if kind == "matmul":
-            idx = next(i for i, p in enumerate(payloads) if p[3] is a)
-            if idx % 8 == 0:
-                got = backend.contexts[ln].decrypt(res, d * d)
-                errs.append(float(np.max(np.abs(got - plain[idx].ravel()))))
-        else:
-            X = I.centre(I.dataset(args.seed, args.cov_samples, 2 * cov_n))
-            ref = X.T @ X / X.shape[0]
-            for i, c in enumerate(res):
-                a_, b_ = divmod(i, 2)
-                got = ctx16.decrypt(c, cov_n * cov_n).reshape(cov_n, cov_n)
-                errs.append(float(np.max(np.abs(got - ref[a_ * cov_n:(a_ + 1) * cov_n, b_ * cov_n:(b_ + 1) * cov_n]))))
-    del results, futs, payloads, extra
+    def trace(seed, rate, with_cov):
+        """one trace of --jobs products at `rate` (inf: all at once); returns (stats, max sampled error)"""
+        jobs = I.poisson_jobs(seed, args.jobs, rate if np.isfinite(rate) else 1e9, pairs)
+        payloads, plain = [], []
+        for j in jobs:
+            ctx = backend.contexts[j.log_n]
+            A, B = I.uniform_matrix(j.seed, j.d), I.uniform_matrix(j.seed + 1, j.d)
+            payloads.append(("matmul", j.log_n, j.d,
+                             (ctx.encrypt_matrix(A, nonce=2 * j.seed), ctx.encrypt_matrix(B, nonce=2 * j.seed + 1))))
+            plain.append(A @ B)
+        extra = []
+        if with_cov:
+            # cov_samples x 256 uniform[0,1] dataset, centred on the client, as
+            # row blocks x 2 blocks of 128 x 128 (the last row block zero-padded)
+            cov_rb = -(-args.cov_samples // cov_n)
+            blk = packing.blocks(X, cov_n)
+            cts = [ctx16.encrypt_matrix(blk[r, c], nonce=10**6 + 2 * r + c) for r in range(cov_rb) for c in range(2)]
+            extra.append((jobs[len(jobs) // 2].arrival, ("covariance", 16, cov_n, (cts, cov_rb, 2, X.shape[0]))))
+            del blk
+        for c in backend.contexts.values():
+            c.sync()
+        srv = Server(backend, hbm_budget=budget)
+        futs = run_trace(srv, jobs, payloads, extra)
+        results = [f.result() for _, f in futs]
+        srv.close()
+        st = srv.stats()
+        # client side: every 8th product and the covariance decrypted against FP64
+        errs = []
+        for (kind, ln, d, a), res in zip([p for p, _ in futs], results):
+            if kind == "matmul":
+                idx = next(i for i, p in enumerate(payloads) if p[3] is a)
+                if idx % 8 == 0:
+                    got = backend.contexts[ln].decrypt(res, d * d)
+                    errs.append(float(np.max(np.abs(got - plain[idx].ravel()))))
+            else:
+                ref = X.T @ X / X.shape[0]
+                for i, c in enumerate(res):
+                    a_, b_ = divmod(i, 2)
+                    got = ctx16.decrypt(c, cov_n * cov_n).reshape(cov_n, cov_n)
+                    errs.append(float(np.max(np.abs(got - ref[a_ * cov_n:(a_ + 1) * cov_n,
+                                                                b_ * cov_n:(b_ + 1) * cov_n]))))
+        return st, (max(errs) if errs else None)
+
+    def summary(st, rate, err):
+        return {"offered_rate": None if not np.isfinite(rate) else round(rate, 3),
+                "jobs_per_s": round(st["jobs_per_s"], 3),
+                "latency_ms": {k2: round(1e3 * v, 2) for k2, v in st["latency_s"].items()},
+                "mean_batch": round(st["mean_batch"], 3), "batches": st["batches"], "jobs": st["jobs"],
+                "rejected": st["rejected"], "peak_admitted_gib": round(st["peak_admitted_bytes"] / 2**30, 2),
+                "max_abs_err_sampled": err}
+
+    log(f"[serve] batched capacity: {args.jobs} jobs offered at once (budget {budget / 2**30:.1f} GiB)")
+    st, err = trace(args.seed, float("inf"), False)
+    capacity = st["jobs_per_s"]
+    cap = summary(st, float("inf"), err)
+    log(f"[serve] capacity {capacity:.2f} jobs/s (one at a time {one_at_a_time:.2f}), mean batch {st['mean_batch']:.2f}")
+    sweep = []
+    for k, load in enumerate(loads):
+        rate = load * capacity
+        with_cov = X is not None and k == len(loads) - 1
+        st, err = trace(args.seed + 1 + k, rate, with_cov)
+        row = dict(summary(st, rate, err), load=load, covariance_job=with_cov)
+        sweep.append(row)
+        log(f"[serve] load {load}: offered {rate:.2f}/s, served {row['jobs_per_s']:.2f}/s, p50 "
+            f"{row['latency_ms']['p50']:.1f} ms, p99 {row['latency_ms']['p99']:.1f} ms, mean batch "
+            f"{row['mean_batch']:.2f}")
     for c in backend.contexts.values():
         c.close()
-    out = {
+    head = max(sweep, key=lambda r: r["load"]) if sweep else cap
+    errs = [r["max_abs_err_sampled"] for r in sweep + [cap] if r["max_abs_err_sampled"] is not None]
+    return {
         "metric": "served HE jobs/s and latency percentiles (Poisson mix of d x d products over 14 (d, N) pairs"
                   + ("" if args.no_covariance else f" + one {args.cov_samples}x256 block covariance") + ")",
-        "jobs_per_s": st["jobs_per_s"],
-        "latency_ms": {k2: 1e3 * v for k2, v in st["latency_s"].items()},
-        "offered_rate": rate,
-        "one_at_a_time_rate": one_at_a_time,
-        "mean_batch": st["mean_batch"],
-        "batches": st["batches"],
-        "jobs": st["jobs"],
-        "rejected": st["rejected"],
-        "peak_admitted_gib": st["peak_admitted_bytes"] / 2**30,
-        "budget_gib": budget / 2**30,
+        "jobs_per_s": head["jobs_per_s"],
+        "latency_ms": head["latency_ms"],
+        "mean_batch": head["mean_batch"],
+        "one_at_a_time_rate": round(one_at_a_time, 3),
+        "batched_capacity": cap,
+        "capacity_vs_one_at_a_time": round(capacity / one_at_a_time, 3),
+        "load_sweep": sweep,
+        "jobs_total": cap["jobs"] + sum(r["jobs"] for r in sweep),
+        "budget_gib": round(budget / 2**30, 2),
         "max_abs_err_sampled": max(errs) if errs else None,
         "solo_ms": {f"d{d}_n{ln}": round(1e3 * s, 2) for (d, ln), s in sorted(solo.items())},
+        "ntt_split_autotune": tuned,
     }
-    return out
 
 
 if __name__ == "__main__":

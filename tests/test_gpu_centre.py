@@ -6,6 +6,8 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from paper_2305_17341_amd import packing
+from oracle import packing as opacking
 
 pytestmark = pytest.mark.gpu
 
@@ -26,9 +28,10 @@ def test_uncentred_covariance_bit_exact(oracle_mod):
     o.keygen(rot_steps=steps)
     X = I.dataset(9, rb * n - 3, k * n - 5)        # values in [0, 1], not centred
     s, t = X.shape
-    blk = I.blocks(X, n)
+    blk = packing.blocks(X, n)
+    oblk = opacking.pack(X, n)
     g = [ctx.encrypt_matrix(blk[r, j], nonce=300 + r * k + j) for r in range(rb) for j in range(k)]
-    oc = [o.encrypt(blk[r, j].ravel(), nonce=300 + r * k + j) for r in range(rb) for j in range(k)]
+    oc = [o.encrypt(oblk[r, j].ravel(), nonce=300 + r * k + j) for r in range(rb) for j in range(k)]
     cov = ctx.covariance(g, rb, k, n, s, {"n1_z": 2, "n1_t": 2, "flags": LAZY | UNCENTRED})
     want = centre.HeCentre(o, n).covariance(oc, rb, k, s, 2, 2, 4, lazy=True)
     _, ref = centre.fp64_mean_and_cov(X)
@@ -51,7 +54,7 @@ def test_uncentred_covariance_256_full_size():
     steps = set(ctx.matmul_rot_steps(n)) | set(ctx.transpose_rot_steps(n)) | set(he.power_rot_steps(n))
     ctx.keygen(sorted(steps))
     X = I.dataset(12, rb * n, k * n)                # uniform [0, 1] features, not centred
-    blk = I.blocks(X, n)
+    blk = packing.blocks(X, n)
     cts = [ctx.encrypt_matrix(blk[r, c], nonce=10 + r * k + c) for r in range(rb) for c in range(k)]
     cov = ctx.covariance(cts, rb, k, n, X.shape[0], {"flags": LAZY | 4 | UNCENTRED})
     _, ref = centre.fp64_mean_and_cov(X)

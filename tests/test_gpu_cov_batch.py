@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from paper_2305_17341_amd import packing
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +20,7 @@ def test_covariance_row_block_batches_keep_residues(flags):
     ctx = he.chain_context(DEEP, seed=61)
     ctx.keygen(sorted(set(ctx.matmul_rot_steps(n, {"n1_z": 2, "n1_t": 2})) | set(ctx.transpose_rot_steps(n))))
     X = I.centre(I.dataset(21, rb * n - 3, k * n - 5))
-    blocks = I.blocks(X, n)
+    blocks = packing.blocks(X, n)
     cts = [ctx.encrypt_matrix(blocks[r, c], nonce=100 + r * k + c) for r in range(rb) for c in range(k)]
     ref = None
     old = he.knob_get("cov_row_blocks")

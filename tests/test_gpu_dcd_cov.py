@@ -7,6 +7,8 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from paper_2305_17341_amd import packing
+from oracle import packing as opacking
 
 pytestmark = pytest.mark.gpu
 
@@ -48,9 +50,10 @@ def test_covariance_bit_exact(pair):
     n, k, rb = 8, 2, 2
     X = I.centre(I.dataset(3, rb * n - 3, k * n - 5))
     s = X.shape[0]
-    blocks = I.blocks(X, n)
+    blocks = packing.blocks(X, n)
+    oblocks = opacking.pack(X, n)
     g = [ctx.encrypt_matrix(blocks[r, j], nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
-    oc = [o.encrypt(blocks[r, j].ravel(), nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
+    oc = [o.encrypt(oblocks[r, j].ravel(), nonce=100 + r * k + j) for r in range(rb) for j in range(k)]
     cov = ctx.covariance(g, rb, k, n, s, {"n1_z": 2, "n1_t": 2})
     want = o.covariance(oc, rb, k, n, s, 2, 2, 4)   # transposition: default 4 baby steps at n = 8
     P = np.zeros((rb * n, k * n))
@@ -73,7 +76,7 @@ def test_covariance_full_size_dcd(oracle_mod):
     opts = {"n1_z": 16, "n1_t": 16, "nprime_z": 32, "nprime_t": 32}
     ctx.keygen(sorted(set(ctx.matmul_rot_steps(n, opts)) | set(ctx.transpose_rot_steps(n))))
     X = I.centre(I.dataset(5, rb * n, k * n))
-    blocks = I.blocks(X, n)
+    blocks = packing.blocks(X, n)
     g = [ctx.encrypt_matrix(blocks[r, j], nonce=10 + r * k + j) for r in range(rb) for j in range(k)]
     cov = ctx.covariance(g, rb, k, n, X.shape[0], opts)
     ref = X.T @ X / X.shape[0]

@@ -7,6 +7,8 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from paper_2305_17341_amd import packing
+from oracle import packing as opacking
 from tests.fullcrt import FullDecryptor
 
 pytestmark = pytest.mark.gpu
@@ -56,9 +58,10 @@ def test_fused_covariance_bit_exact(pair):
     n, k, rb = 8, 2, 2
     X = I.centre(I.dataset(6, rb * n - 3, k * n - 5))
     s = X.shape[0]
-    blocks = I.blocks(X, n)
+    blocks = packing.blocks(X, n)
+    oblocks = opacking.pack(X, n)
     g = [ctx.encrypt_matrix(blocks[r, j], nonce=200 + r * k + j) for r in range(rb) for j in range(k)]
-    oc = [o.encrypt(blocks[r, j].ravel(), nonce=200 + r * k + j) for r in range(rb) for j in range(k)]
+    oc = [o.encrypt(oblocks[r, j].ravel(), nonce=200 + r * k + j) for r in range(rb) for j in range(k)]
     cov = ctx.covariance(g, rb, k, n, s, {"n1_z": 2, "n1_t": 2, "flags": LAZY | FUSED})
     want = o.covariance(oc, rb, k, n, s, 2, 2, 4, lazy=True, fused_rescale=True)
     P = np.zeros((rb * n, k * n))

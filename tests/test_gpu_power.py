@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from paper_2305_17341_amd import packing
 
 pytestmark = pytest.mark.gpu
 
@@ -171,7 +172,7 @@ def test_power_full_size_against_fp64_replay():
     steps = set(ctx.matmul_rot_steps(n)) | set(ctx.transpose_rot_steps(n)) | set(he.power_rot_steps(n))
     ctx.keygen(sorted(steps))
     X = I.centre(I.pca_dataset(3, rb * n, k * n))
-    blk = I.blocks(X, n)
+    blk = packing.blocks(X, n)
     cts = [ctx.encrypt_matrix(blk[r, c], nonce=10 + r * k + c) for r in range(rb) for c in range(k)]
     cov_ct = ctx.covariance(cts, rb, k, n, X.shape[0])
     cov = X.T @ X / X.shape[0]

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2305_17341_amd import inputs as I
+from oracle import packing as opacking
 
 BOUND = 2.0 ** -15
 CHAIN = (11, (60,) + (40,) * 7, (60, 60))
@@ -26,7 +27,7 @@ def test_means_and_uncentred_covariance(setup):
     k, rb = 2, 2
     X = I.dataset(8, rb * n - 3, k * n - 5)          # values in [0, 1], not centred
     s, t = X.shape
-    blk = I.blocks(X, n)
+    blk = opacking.pack(X, n)
     cts = [o.encrypt(blk[r, j].ravel(), nonce=40 + r * k + j) for r in range(rb) for j in range(k)]
     hc = centre.HeCentre(o, n)
     mu_want, cov_want = centre.fp64_mean_and_cov(X)
@@ -54,9 +55,9 @@ def test_padding_method_2_packs_and_unpacks():
     for t in (11, 13, 16, 17, 23):
         X = I.dataset(t, 5, t)
         k = -(-t // n)
-        w = I.features_per_block(t, n, 2)
+        w = opacking.width(t, n, 2)
         assert w == n - (k * n - t) // k and k * w >= t and w <= n
-        B = I.blocks(X, n, method=2)
+        B = opacking.pack(X, n, method=2)
         assert B.shape == (1, k, n, n)
         back = np.concatenate([B[0, j, :5, :w] for j in range(k)], axis=1)[:, :t]
         assert np.array_equal(back, X)
@@ -65,7 +66,7 @@ def test_padding_method_2_packs_and_unpacks():
         for f in range(t):
             for g in range(t):
                 Bm[f // w][g // w][f % w, g % w] = M[f, g]
-        assert np.array_equal(I.unblock_square(Bm, t, n, 2), M)
+        assert np.array_equal(opacking.unpack_square(Bm, t, n, 2), M)
 
 
 def test_uncentred_covariance_padding_method_2(setup):
@@ -76,10 +77,26 @@ def test_uncentred_covariance_padding_method_2(setup):
     X = I.dataset(10, 2 * n - 3, 13)
     s, t = X.shape
     k, rb = -(-t // n), 2
-    blk = I.blocks(X, n, method=2)
+    blk = opacking.pack(X, n, method=2)
     cts = [o.encrypt(blk[r, j].ravel(), nonce=80 + r * k + j) for r in range(rb) for j in range(k)]
     cov = centre.HeCentre(o, n).covariance(cts, rb, k, s, 4, 4, 4, lazy=True)
     B = [[o.decrypt(cov[a * k + b])[: n * n].reshape(n, n) for b in range(k)] for a in range(k)]
-    got = I.unblock_square(B, t, n, method=2)
+    got = opacking.unpack_square(B, t, n, method=2)
     _, want = centre.fp64_mean_and_cov(X)
     assert np.max(np.abs(got - want)) < BOUND
+
+
+def test_package_packing_equals_the_oracles():
+    """The library's client-side packing and the oracle's own give the same
+    blocks and the same unpacking, for both padding methods."""
+    from paper_2305_17341_amd import packing
+    for n in (4, 8):
+        for s, t in ((5, 13), (17, 16), (9, 23), (8, 8), (3, 31)):
+            X = I.dataset(s * 100 + t, s, t)
+            for method in (1, 2):
+                assert packing.features_per_block(t, n, method) == opacking.width(t, n, method)
+                assert np.array_equal(packing.blocks(X, n, method), opacking.pack(X, n, method))
+                k = -(-t // n)
+                B = I.rng(t).uniform(-1, 1, (k, k, n, n))
+                assert np.array_equal(packing.unblock_square(B, t, n, method),
+                                      opacking.unpack_square(B, t, n, method))

@@ -85,7 +85,7 @@ def test_strict_arrival_order_under_memory_pressure():
     assert sorted(started) == list(range(len(ds)))
 
 
-def test_batches_group_same_d_up_to_max_batch_and_covariance_alone():
+def test_batches_take_products_of_any_d_up_to_max_batch_and_covariance_alone():
     be = FakeBackend(log_ns=(16,), cost=0.05)
     srv = S.Server(be, hbm_budget=10**9, max_batch=3)
     hold = srv.submit("matmul", 16, 8, ())      # occupies the worker while the rest queue up
@@ -97,12 +97,15 @@ def test_batches_group_same_d_up_to_max_batch_and_covariance_alone():
     srv.close()
     for _, reqs, _, _ in be.calls:
         kinds = {k for k, _, _ in reqs}
-        assert len({d for _, d, _ in reqs}) == 1
         assert len(reqs) <= 3
         if "covariance" in kinds:
             assert len(reqs) == 1
     sizes = [len(reqs) for _, reqs, _, _ in be.calls]
-    assert max(sizes) == 3          # the four d=16 products went as 3 + 1
+    assert sizes.count(3) == 2      # the six queued products went as 3 + 3, sizes mixed
+    assert any(len({d for _, d, _ in reqs}) > 1 for _, reqs, _, _ in be.calls)
+    # arrival order inside and across batches
+    ids = [i for _, reqs, _, _ in be.calls for k, _, i in reqs if k == "matmul"]
+    assert ids == sorted(ids)
 
 
 def test_late_arrivals_join_the_next_batch():
@@ -131,11 +134,11 @@ def test_different_ring_dimensions_overlap():
 
 def test_backend_error_reaches_every_request_of_the_batch():
     be = FakeBackend(log_ns=(13,), cost=0.05, fail_d=32)
-    srv = S.Server(be, hbm_budget=10**9)
+    srv = S.Server(be, hbm_budget=10**9, max_batch=3)
     hold = srv.submit("matmul", 13, 16, ())
     be.started.wait(5)
-    bad = [srv.submit("matmul", 13, 32, ()) for _ in range(3)]
-    good = srv.submit("matmul", 13, 16, ())
+    bad = [srv.submit("matmul", 13, 32, ()) for _ in range(3)]    # one batch of three, which fails
+    good = srv.submit("matmul", 13, 16, ())                       # the next batch
     hold.result(timeout=10)
     for f in bad:
         with pytest.raises(RuntimeError):
