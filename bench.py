@@ -473,6 +473,11 @@ def main():
         "config": {"workload": f"he_matmul d={d} at N=2^16 (q0 60b + 30x40b, P 3x60b, levels 30->27), "
                                f"uniform[-1,1] FP64 inputs", "d": d, "log_n": chain.log_n, "batch": B,
                    "path": names[head["flags"]], "relinearisation": relin,
+                   "variants": None if args.paper_relin else (
+                       "lazy relinearisation (the d tensors summed, relinearised once)" +
+                       ("" if args.two_roundings else " and one rounding for the A side's ModDown and Rescale") +
+                       ": variants of the paper's order (relinearisation per product, two roundings), each with "
+                       "its own oracle plan; batched_paper_relin is the paper's order"),
                    "n1": args.n1 if args.n1 > 0 else None, "rotation_keys": len(steps)},
         "batched_residues_equal_alone": head_same,
         "autotune": tuned,
