@@ -367,7 +367,7 @@ def main():
     c1 = ctx.op_counts()
     fams = ["ntt_fwd_cols", "ntt_fwd_cols_modup", "ntt_fwd_cols_fbc", "ntt_fwd_cols_lift", "ntt_fwd_rows",
             "ntt_fwd_rows_sub",
-            "ntt_inv_rows", "ntt_inv_cols", "multsum", "multsum_rot", "modup", "fbc_prep",
+            "ntt_inv_rows", "ntt_inv_cols", "multsum", "multsum_rot", "multsum_rot_int", "modup", "fbc_prep",
             "fbc_to_q",
             "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor", "plift"]
     prof = {f: ctx.profile_read(f) for f in fams}

@@ -381,7 +381,13 @@ he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d,
  * rotations per work-group of a multi-rotation launch, which then read the
  * digits once for all of them), "cov_row_blocks" (1..8, default
  * 4: row blocks of he_covariance stacked into one batch through the
- * transposition and both sides; device memory for the sides grows with it).
+ * transposition and both sides; device memory for the sides grows with it),
+ * "ntt_split_13/14/15" (0/1: the NTT's alternative stage split for that ring
+ * size), and for the 60-bit limbs (q0, the special primes) of a
+ * multi-rotation launch: "mr_int_split" (0/1, default 1: in a kernel of their
+ * own), "mr_int_pass" (4/8: members per pass of that kernel), "mr_int_chunk"
+ * (1..64: rotations per dispatch chunk) and "mr_int_concurrent" (0/1, default
+ * 0: that kernel on a second stream of the context, beside the FP64 one).
  * Set them between calls, not while
  * another thread drives the library.  The autotuner in the Python package
  * picks them by timing. */

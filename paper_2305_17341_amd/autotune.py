@@ -17,6 +17,10 @@ CANDIDATES = {
     "ntt_interleave": (0, 1),
     "ew_interleave": (0, 1),
     "mr_group": (1, 2, 4),
+    "mr_int_split": (0, 1),
+    "mr_int_pass": (4, 8),
+    "mr_int_chunk": (4, 16, 64),
+    "mr_int_concurrent": (0, 1),
 }
 
 

@@ -120,9 +120,18 @@ void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u6
 // With masks (plaintexts [nqp][N] in R_{Q_l P}, one per rotation) the outputs
 // are mask (.) rotation, added onto outs[r] when `accumulate`.
 #define MR_MAX 64
+// A second stream forked from and joined to the launching stream with
+// events (default priority).  With it, a multi-rotation launch runs the
+// kernel of its 60-bit limbs there, beside the kernel of its FP64 limbs: the
+// one is bound by integer and FP64 issue, the other mostly by HBM.
+struct ForkStream {
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
 void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
                         const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
-                        int batch, hipStream_t s, const u64* const* masks = nullptr, bool accumulate = false);
+                        int batch, hipStream_t s, const u64* const* masks = nullptr, bool accumulate = false,
+                        const ForkStream* fs = nullptr);
 // Key inner products handed to a sink instead of being launched (merged
 // launches of several products): the arguments of one launch_multsum_rot or
 // launch_multsum call

@@ -25,6 +25,10 @@ struct Knobs {
   int ntt_interleave = 0;  // block passes visit limbs of one modulus back to back (0/1)
   int ew_interleave = 1;   // plaintext-broadcast sums visit the limbs sharing a plaintext back to back (0/1)
   int cov_row_blocks = 4;  // row blocks of a covariance stacked into one batch (1..8)
+  int mr_int_split = 1;    // 60-bit limbs of a multi-rotation launch in their own kernel (0/1)
+  int mr_int_pass = 4;     // members per pass of that kernel (4/8)
+  int mr_int_chunk = 64;   // rotations per dispatch chunk of that kernel (1..64)
+  int mr_int_concurrent = 0;  // that kernel on a forked stream, beside the FP64 one (0/1)
   int mr_group = 4;        // rotations per work-group of a multi-rotation launch, sharing the digit loads (1/2/4)
   // stage split of the register-blocked NTT per ring size (index log N):
   // 0 = the default, 1 = one stage moved between the column and block passes
@@ -40,6 +44,10 @@ bool knob_set(const char* name, int v) {
   else if (n == "ew_interleave" && (v == 0 || v == 1)) g_knobs.ew_interleave = v;
   else if (n == "cov_row_blocks" && v >= 1 && v <= 8) g_knobs.cov_row_blocks = v;
   else if (n == "mr_group" && (v == 1 || v == 2 || v == 4)) g_knobs.mr_group = v;
+  else if (n == "mr_int_split" && (v == 0 || v == 1)) g_knobs.mr_int_split = v;
+  else if (n == "mr_int_pass" && (v == 4 || v == 8)) g_knobs.mr_int_pass = v;
+  else if (n == "mr_int_chunk" && v >= 1 && v <= MR_MAX) g_knobs.mr_int_chunk = v;
+  else if (n == "mr_int_concurrent" && (v == 0 || v == 1)) g_knobs.mr_int_concurrent = v;
   else if ((n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") && (v == 0 || v == 1))
     g_knobs.ntt_split[std::stoi(n.substr(10))] = v;
   else return false;
@@ -54,6 +62,10 @@ bool knob_get(const char* name, int* v) {
   else if (n == "ew_interleave") *v = g_knobs.ew_interleave;
   else if (n == "cov_row_blocks") *v = g_knobs.cov_row_blocks;
   else if (n == "mr_group") *v = g_knobs.mr_group;
+  else if (n == "mr_int_split") *v = g_knobs.mr_int_split;
+  else if (n == "mr_int_pass") *v = g_knobs.mr_int_pass;
+  else if (n == "mr_int_chunk") *v = g_knobs.mr_int_chunk;
+  else if (n == "mr_int_concurrent") *v = g_knobs.mr_int_concurrent;
   else if (n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") *v = g_knobs.ntt_split[std::stoi(n.substr(10))];
   else return false;
   return true;
@@ -2273,6 +2285,130 @@ __device__ __forceinline__ void multsum_rot_group(const MultiRot& R, int r0, int
     }
   }
 }
+// Key inner products on the 60-bit limbs (q0 and the special primes), where
+// the lazy FP64 product does not apply.  Each product d k is taken apart into
+// 20-bit pieces, d = d0 + d1 2^20 + d2 2^40 and k likewise, and the nine
+// piece products (below 2^42 for residues below 2^61) are summed with FMAs
+// into five sums by weight 2^(20 w): S_w holds at most 3 beta of them, below
+// 2^50 for beta <= 64, so every FMA is exact.  The sum over the digits is
+// X = sum_w S_w 2^(20 w) < beta 2^122 <= 2^128, the same integer the 128-bit
+// multiply-accumulate forms, and it is reduced once, so the residues are
+// those of the integer products.  Nine full-rate FP64 FMAs take the place of
+// four quarter-rate 32-bit multiplies and the carries of a 128-bit sum.
+// Each digit is taken apart once for both key halves; members go four at a
+// time (2 x 4 x 5 sums).
+constexpr u64 PIECE20 = (1ull << 20) - 1;
+__device__ __forceinline__ void split20(u64 x, double& x0, double& x1, double& x2) {
+  x0 = u2d(x & PIECE20);
+  x1 = u2d((x >> 20) & PIECE20);
+  x2 = u2d(x >> 40);
+}
+__device__ __forceinline__ u64 fold_pieces(const double* S, const ModConst& mk) {
+  u64 lo = d2u(S[0]), hi = 0;
+#pragma unroll
+  for (int w = 1; w < 5; w++) {
+    const u64 v = d2u(S[w]);
+    const int sh = 20 * w;
+    const u64 l = sh < 64 ? v << sh : 0, h = sh < 64 ? v >> (64 - sh) : v << (sh - 64);
+    lo += l;
+    hi += h + (lo < l ? 1 : 0);
+  }
+  return u128_reduce(U128{lo, hi}, mk);
+}
+template <int MB>
+__device__ __forceinline__ void multsum_int_pass(const MultiRot& R, int r, u32 i, const u64* __restrict__ dig,
+                                                 size_t dstride, size_t jstride, const u64* __restrict__ c0,
+                                                 const u64* __restrict__ pmod, int nq, int nqp, int beta, int nmods,
+                                                 int B, int b0, int m, int pos, u32 src, u64 N, const ModConst& mk) {
+  const u64* key = R.key[r];
+  double S0[MB][5], S1[MB][5];
+#pragma unroll
+  for (int b = 0; b < MB; b++)
+#pragma unroll
+    for (int w = 0; w < 5; w++) S0[b][w] = S1[b][w] = 0.0;
+  // software-pipelined: the key words and digits of j + 1 are in flight
+  // while j is multiplied.  Plain loads: the keys are read again by the
+  // next pass over the members, from L2.
+  u64 kbn = key[(size_t)m * N + i], kan = key[((size_t)nmods + m) * N + i], dn[MB];
+#pragma unroll
+  for (int b = 0; b < MB; b++) dn[b] = dig[(size_t)b * dstride];
+  for (int j = 0; j < beta; j++) {
+    double kb0, kb1, kb2, ka0, ka1, ka2;
+    split20(kbn, kb0, kb1, kb2);
+    split20(kan, ka0, ka1, ka2);
+    u64 dw[MB];
+#pragma unroll
+    for (int b = 0; b < MB; b++) dw[b] = dn[b];
+    if (j + 1 < beta) {
+      kbn = key[(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + i];
+      kan = key[(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + i];
+#pragma unroll
+      for (int b = 0; b < MB; b++) dn[b] = dig[(size_t)b * dstride + (size_t)(j + 1) * jstride];
+    }
+#pragma unroll
+    for (int b = 0; b < MB; b++) {
+      double d0, d1, d2;
+      split20(dw[b], d0, d1, d2);
+      S0[b][0] = fma(d0, kb0, S0[b][0]);
+      S0[b][1] = fma(d0, kb1, S0[b][1]);
+      S0[b][1] = fma(d1, kb0, S0[b][1]);
+      S0[b][2] = fma(d0, kb2, S0[b][2]);
+      S0[b][2] = fma(d1, kb1, S0[b][2]);
+      S0[b][2] = fma(d2, kb0, S0[b][2]);
+      S0[b][3] = fma(d1, kb2, S0[b][3]);
+      S0[b][3] = fma(d2, kb1, S0[b][3]);
+      S0[b][4] = fma(d2, kb2, S0[b][4]);
+      S1[b][0] = fma(d0, ka0, S1[b][0]);
+      S1[b][1] = fma(d0, ka1, S1[b][1]);
+      S1[b][1] = fma(d1, ka0, S1[b][1]);
+      S1[b][2] = fma(d0, ka2, S1[b][2]);
+      S1[b][2] = fma(d1, ka1, S1[b][2]);
+      S1[b][2] = fma(d2, ka0, S1[b][2]);
+      S1[b][3] = fma(d1, ka2, S1[b][3]);
+      S1[b][3] = fma(d2, ka1, S1[b][3]);
+      S1[b][4] = fma(d2, ka2, S1[b][4]);
+    }
+  }
+  const u64* mask = R.mask[r];
+  const u64 mv = mask ? mask[(size_t)pos * N + i] : 0;
+#pragma unroll
+  for (int b = 0; b < MB; b++) {
+    u64 v0 = fold_pieces(S0[b], mk), v1 = fold_pieces(S1[b], mk);
+    if (c0 && pos < nq)
+      v0 = add_mod(v0, mul_const_any(c0[((size_t)(b0 + b) * nq + pos) * N + src], pmod[2 * m], pmod[2 * m + 1], mk),
+                   mk.q);
+    u64* o0 = &R.out[r][((size_t)(b0 + b) * nqp + pos) * N + i];
+    u64* o1 = &R.out[r][((size_t)(B + b0 + b) * nqp + pos) * N + i];
+    if (mask) {
+      v0 = mul_mod_any(v0, mv, mk);
+      v1 = mul_mod_any(v1, mv, mk);
+      if (R.accumulate) {
+        v0 = add_mod(v0, *o0, mk.q);
+        v1 = add_mod(v1, *o1, mk.q);
+      }
+    }
+    stnt(o0, v0);
+    stnt(o1, v1);
+  }
+}
+// MP: members per pass over the digits (4, or all 8 in one pass where the
+// launch gives the sums the registers)
+template <int MB, int MP = 4>
+__device__ __forceinline__ void multsum_rot_group_int(const MultiRot& R, int r0, int nr, const u64* __restrict__ digits,
+                                                      const u64* __restrict__ c0, const u64* __restrict__ pmod,
+                                                      int nq, int nqp, int beta, int nmods, int B, int b0, int m,
+                                                      int pos, u32 src, int logN, u64 N, const ModConst& mk) {
+  const size_t dstride = (size_t)beta * nqp * N, jstride = (size_t)nqp * N;
+  const u64* dig = digits + (size_t)b0 * dstride + (size_t)pos * N + src;
+  constexpr int M1 = MB > MP ? MP : MB;
+  for (int r = r0; r < r0 + nr; r++) {
+    const u32 i = automorph_src(src, R.ginv[r], logN);
+    multsum_int_pass<M1>(R, r, i, dig, dstride, jstride, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, N, mk);
+    if (MB > M1)
+      multsum_int_pass<(MB > M1 ? MB - M1 : 1)>(R, r, i, dig + M1 * dstride, dstride, jstride, c0, pmod, nq, nqp,
+                                                beta, nmods, B, b0 + M1, m, pos, src, N, mk);
+  }
+}
 // RPW: rotations per work-group (their FP64 limbs share the digit loads)
 template <int MB, bool F64, int RPW>
 __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, PosList P, int nrot, const u64* __restrict__ digits,
@@ -2294,17 +2430,35 @@ __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, PosList P, int 
     multsum_rot_group<MB, RPW>(R, r0, nr, digits, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, logN, N, mk);
     return;
   }
-  // integer limbs: one rotation after another, at most four members at a
-  // time (128-bit sums hold the registers of two FP64 ones)
-  constexpr int M1 = MB > 4 ? 4 : MB;
-  for (int r = r0; r < r0 + nr; r++) {
-    const u32 i = automorph_src(src, R.ginv[r], logN);
-    multsum_body<M1, false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, i, src, N,
-                            mk, R.mask[r], R.accumulate != 0);
-    if (MB > 4)
-      multsum_body<(MB > 4 ? MB - 4 : 1), false>(R.out[r], digits, R.key[r], c0, pmod, nq, nqp, beta, nmods, B,
-                                                 b0 + 4, m, pos, i, src, N, mk, R.mask[r], R.accumulate != 0);
-  }
+  multsum_rot_group_int<MB>(R, r0, nr, digits, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, logN, N, mk);
+}
+
+// The 60-bit limbs of a multi-rotation launch on their own (knob
+// "mr_int_split"): a kernel without the FP64 group's sums in its registers,
+// one rotation per work-group.  Dispatch order: the rotations in chunks of
+// rc (knob "mr_int_chunk"); inside a chunk, source blocks in octets, and the
+// chunk's rotations of one octet back to back.  Block S goes to XCD S mod 8
+// for every rotation, so its digits are read from HBM about once per chunk.
+template <int MB, int MP>
+__global__ void __launch_bounds__(TPB) k_multsum_rot_int(MultiRot R, PosList P, int nrot, int rc,
+                                                         const u64* __restrict__ digits,
+                                                         const u64* __restrict__ c0, const u64* __restrict__ pmod,
+                                                         int nq, int nqp, int L, int beta, int nmods, int B, int b0,
+                                                         int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  const u32 x = blockIdx.x, rest = x >> 3;
+  const u32 octets = (u32)((N + 8 * TPB - 1) / (8 * TPB));  // source-block octets
+  const u32 per_chunk = octets * (u32)rc;
+  const u32 chunk = rest / per_chunk, within = rest - chunk * per_chunk;
+  const u32 rcc = (u32)(nrot - (int)chunk * rc) < (u32)rc ? (u32)(nrot - (int)chunk * rc) : (u32)rc;
+  const int r = (int)(chunk * (u32)rc + within % rcc);
+  const u32 S = (within / rcc) * 8 + (x & 7);
+  if ((u64)S * TPB >= N) return;
+  const u32 src = S * TPB + threadIdx.x;
+  const int pos = P.pos[blockIdx.y];
+  const int m = pos < nq ? pos : L + 1 + (pos - nq);
+  const ModConst mk = mc[m];
+  multsum_rot_group_int<MB, MP>(R, r, 1, digits, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, logN, N, mk);
 }
 
 static u64 inv_mod_2n(u64 g, u64 twoN) {
@@ -2385,16 +2539,8 @@ __global__ void __launch_bounds__(TPB) k_multsum_list(const KsItem* __restrict__
                                   it.b0, m, pos, src, logN, N, mk);
     return;
   }
-  constexpr int M1 = MB > 4 ? 4 : MB;
-  for (int r = r0; r < r0 + nr; r++) {
-    const u32 i = automorph_src(src, it.R.ginv[r], logN);
-    multsum_body<M1, false>(it.R.out[r], it.digits, it.R.key[r], it.c0, it.pmod, it.nq, it.nqp, it.beta, nmods, it.B,
-                            it.b0, m, pos, i, src, N, mk, it.R.mask[r], it.R.accumulate != 0);
-    if (MB > 4)
-      multsum_body<(MB > 4 ? MB - 4 : 1), false>(it.R.out[r], it.digits, it.R.key[r], it.c0, it.pmod, it.nq, it.nqp,
-                                                 it.beta, nmods, it.B, it.b0 + 4, m, pos, i, src, N, mk,
-                                                 it.R.mask[r], it.R.accumulate != 0);
-  }
+  multsum_rot_group_int<MB>(it.R, r0, nr, it.digits, it.c0, it.pmod, it.nq, it.nqp, it.beta, nmods, it.B, it.b0, m,
+                            pos, src, logN, N, mk);
 }
 
 // the work's items: rotations in chunks of MR_MAX, members in chunks of
@@ -2524,9 +2670,39 @@ void launch_multsum_list(const DeviceTables& T, const std::vector<KsWork>& works
   }
 }
 
+// HBM bytes (each rotation's key once, the members' digits and c0 once,
+// outputs once, the masks, the outputs read back when accumulating),
+// modular products (2 beta key products per member, rotation and value, P c0
+// on the Q limbs, the mask on both halves) and key-switch unit bytes of one
+// multi-rotation launch over the positions pl[0 .. n)
+static void fork_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw std::runtime_error(std::string("forked stream: ") + what + ": " + hipGetErrorString(e));
+}
+struct MrCost {
+  double bytes = 0, unit = 0;
+  Mm mm;
+};
+static MrCost mr_cost(const DeviceTables& T, const PosList& pl, int n, int nq, int L, int nr, int mb, int beta,
+                      bool c0, bool masks, bool acc) {
+  MrCost c;
+  double w = 0, u = 0;
+  for (int x = 0; x < n; x++) {
+    const int pos = pl.pos[x];
+    const int m = pos < nq ? pos : L + 1 + (pos - nq);
+    const bool q = pos < nq;
+    w += nr * 2.0 * beta + mb * (beta + (c0 && q ? 1.0 : 0.0) + nr * 2.0) + (masks ? nr : 0.0) +
+         (acc ? mb * nr * 2.0 : 0.0);
+    c.mm.add(T.bits[m], (double)T.N * (2.0 * beta + (c0 && q ? 1 : 0) + (masks ? 2 : 0)) * mb * nr);
+    u += nr * 2.0 * beta + (q ? nr * mb * 4.0 : 0.0);
+  }
+  c.bytes = 8.0 * T.N * w;
+  c.unit = 8.0 * T.N * u;
+  return c;
+}
 void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
                         const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
-                        int batch, hipStream_t s, const u64* const* masks, bool accumulate) {
+                        int batch, hipStream_t s, const u64* const* masks, bool accumulate,
+                        const ForkStream* fs) {
   if (tls_ks_sink) {
     KsWork w;
     w.outs.assign(outs, outs + nrot);
@@ -2560,45 +2736,83 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
       R.ginv[r] = inv_mod_2n(gs[r0 + r], twoN);
     }
     const PosList P = pos_order(T, nq, nqp, L);
-    int ni = 0;
-    for (int pos = nq; pos < nqp; pos++) ni += T.bits[L + 1 + (pos - nq)] > F64_LAZY_BITS;
-    for (int pos = 0; pos < nq; pos++) ni += T.bits[pos] > F64_LAZY_BITS;
+    // the launch order split into FP64 and integer positions
+    PosList pf, pi;
+    int nf = 0, ni = 0;
+    for (int x = 0; x < nqp; x++) {
+      const int pos = P.pos[x];
+      const int m = pos < nq ? pos : L + 1 + (pos - nq);
+      if (T.bits[m] <= F64_LAZY_BITS) pf.pos[nf++] = (short)pos;
+      else pi.pos[ni++] = (short)pos;
+    }
+    const bool split = ni > 0 && g_knobs.mr_int_split != 0;
     for (int b0 = 0; b0 < batch; b0 += mstep) {
       const int mb = batch - b0 < mstep ? batch - b0 : mstep;
-      // per position: each rotation's key once, the members' digits (and c0 on
-      // the Q limbs) once, outputs once, the masks, the outputs read back when
-      // accumulating
-      double w = 0;
-      for (int pos = 0; pos < nqp; pos++)
-        w += nr * 2.0 * beta + mb * (beta + (c0 && pos < nq ? 1.0 : 0.0) + nr * 2.0) + (masks ? nr : 0.0) +
-             (R.accumulate ? mb * nr * 2.0 : 0.0);
-      // per member and rotation: 2 beta key products on every position, P c0 on the Q limbs, the mask on both halves
-      const Mm mm = mm_qp(T, nq, nqp, L, (double)T.N * (2.0 * beta + (c0 ? 1 : 0) + (masks ? 2 : 0)),
-                          (double)T.N * (2.0 * beta + (masks ? 2 : 0)), (double)mb * nr);
-      const double unit = 8.0 * T.N * ((double)nr * 2.0 * beta * nqp + (double)nr * mb * 4.0 * nq);
-      ProfScope ps("multsum_rot", s, 8.0 * T.N * w, mm, unit);
-      // FP64-only launch when every limb is FP64 (the integer branch compiled out)
-#define MR_LAUNCH(K, FP, G)                                                                                        \
-  hipLaunchKernelGGL((k_multsum_rot<K, FP, G>), dim3(cdiv(nblk, 8) * 8 * cdiv(nr, G), nqp), dim3(TPB), 0, s, R, P, \
+      const MrCost all = mr_cost(T, P, nqp, nq, L, nr, mb, beta, c0 != nullptr, masks != nullptr, R.accumulate != 0);
+      const MrCost fp = split ? mr_cost(T, pf, nf, nq, L, nr, mb, beta, c0 != nullptr, masks != nullptr,
+                                        R.accumulate != 0)
+                              : all;
+      // FP64-only kernel when every launched limb is FP64 (the integer branch compiled out)
+#define MR_LAUNCH(K, FP, G, PL, NP)                                                                                \
+  hipLaunchKernelGGL((k_multsum_rot<K, FP, G>), dim3(cdiv(nblk, 8) * 8 * cdiv(nr, G), NP), dim3(TPB), 0, s, R, PL, \
                      nr, digits, c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc)
-#define MR_CASE(K)                                                                                                 \
-  case K:                                                                                                          \
-    if (rpw == 4) {                                                                                                \
-      if (ni) MR_LAUNCH(K, false, 4);                                                                              \
-      else MR_LAUNCH(K, true, 4);                                                                                  \
-    } else if (rpw == 2) {                                                                                         \
-      if (ni) MR_LAUNCH(K, false, 2);                                                                              \
-      else MR_LAUNCH(K, true, 2);                                                                                  \
-    } else {                                                                                                       \
-      if (ni) MR_LAUNCH(K, false, 1);                                                                              \
-      else MR_LAUNCH(K, true, 1);                                                                                  \
-    }                                                                                                              \
+#define MR_GROUPS(K, FP, PL, NP)             \
+  if (rpw == 4) MR_LAUNCH(K, FP, 4, PL, NP); \
+  else if (rpw == 2) MR_LAUNCH(K, FP, 2, PL, NP); \
+  else MR_LAUNCH(K, FP, 1, PL, NP);
+#define MR_CASE(K)                                     \
+  case K:                                              \
+    if (split) {                                       \
+      MR_GROUPS(K, true, pf, nf)                       \
+    } else if (ni) {                                   \
+      MR_GROUPS(K, false, P, nqp)                      \
+    } else {                                           \
+      MR_GROUPS(K, true, P, nqp)                       \
+    }                                                  \
     break;
-      switch (mb) {
-        MR_CASE(1) MR_CASE(2) MR_CASE(3) MR_CASE(4) MR_CASE(5) MR_CASE(6) MR_CASE(7) MR_CASE(8)
+      // the integer limbs' kernel first: on the forked stream it runs beside
+      // the FP64 kernel, joined before anything else is launched on s
+      const bool concurrent = split && fs && fs->aux && g_knobs.mr_int_concurrent != 0;
+      if (split) {
+        hipStream_t si = s;
+        if (concurrent) {
+          fork_check(hipEventRecord(fs->fork, s), "event record");
+          fork_check(hipStreamWaitEvent(fs->aux, fs->fork, 0), "stream wait");
+          si = fs->aux;
+        }
+        const MrCost ic = mr_cost(T, pi, ni, nq, L, nr, mb, beta, c0 != nullptr, masks != nullptr, R.accumulate != 0);
+        ProfScope ps("multsum_rot_int", si, ic.bytes, ic.mm, ic.unit);
+        const dim3 grid(cdiv(nblk, 8) * 8 * nr, ni);
+        const int rc = std::min(nr, g_knobs.mr_int_chunk);
+#define MRI_CASE(K)                                                                                              \
+  case K:                                                                                                        \
+    if (g_knobs.mr_int_pass == 8)                                                                                \
+      hipLaunchKernelGGL((k_multsum_rot_int<K, 8>), grid, dim3(TPB), 0, si, R, pi, nr, rc, digits, c0, pmod, nq, \
+                         nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);                                        \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_multsum_rot_int<K, 4>), grid, dim3(TPB), 0, si, R, pi, nr, rc, digits, c0, pmod, nq, \
+                         nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);                                        \
+    break;
+        switch (mb) {
+          MRI_CASE(1) MRI_CASE(2) MRI_CASE(3) MRI_CASE(4) MRI_CASE(5) MRI_CASE(6) MRI_CASE(7) MRI_CASE(8)
+        }
+#undef MRI_CASE
+      }
+      {
+        // per member and rotation: 2 beta key products on every position, P c0
+        // on the Q limbs, the mask on both halves
+        ProfScope ps("multsum_rot", s, fp.bytes, fp.mm, fp.unit);
+        switch (mb) {
+          MR_CASE(1) MR_CASE(2) MR_CASE(3) MR_CASE(4) MR_CASE(5) MR_CASE(6) MR_CASE(7) MR_CASE(8)
+        }
+      }
+      if (concurrent) {
+        fork_check(hipEventRecord(fs->join, fs->aux), "event record");
+        fork_check(hipStreamWaitEvent(s, fs->join, 0), "stream wait");
       }
     }
 #undef MR_CASE
+#undef MR_GROUPS
 #undef MR_LAUNCH
   }
 }

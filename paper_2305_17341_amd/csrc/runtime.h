@@ -89,6 +89,8 @@ struct HeCtxImpl {
   u64 seed = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // second stream of the multi-rotation launches (see ForkStream)
+  ForkStream fork;
   // device the context was created on, and that device's copy of the
   // allocation-free entry points' workspace
   int device = 0;

@@ -187,6 +187,10 @@ HeCtxImpl::~HeCtxImpl() {
   // the pool is destroyed after this body: its last trim must not wait on a
   // stream that is gone (or, for a caller's stream, may be gone)
   pool.stream = nullptr;
+  if (fork.aux) (void)hipStreamSynchronize(fork.aux);
+  if (fork.fork) (void)hipEventDestroy(fork.fork);
+  if (fork.join) (void)hipEventDestroy(fork.join);
+  if (fork.aux) (void)hipStreamDestroy(fork.aux);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -354,6 +358,9 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
     own_stream = true;
   }
   pool.stream = stream;
+  hip_check(hipStreamCreateWithFlags(&fork.aux, hipStreamNonBlocking), "stream");
+  hip_check(hipEventCreateWithFlags(&fork.fork, hipEventDisableTiming), "event");
+  hip_check(hipEventCreateWithFlags(&fork.join, hipEventDisableTiming), "event");
   hip_check(hipEventCreate(&ev0), "event");
   hip_check(hipEventCreate(&ev1), "event");
 
@@ -792,7 +799,7 @@ std::vector<HeCt> HeCtxImpl::hoisted_multi(const HeCt& x, const u64* digits, con
   }
   if (!outs.empty())
     launch_multsum_rot(T, outs.data(), ks.data(), g2.data(), (int)outs.size(), digits, x.poly(0), pmod.p, x.level,
-                       L, alpha, beta_at(x.level), x.B, stream);
+                       L, alpha, beta_at(x.level), x.B, stream, nullptr, false, &fork);
   n_multsum += (long)x.B * (long)outs.size();
   return out;
 }
@@ -808,7 +815,7 @@ void HeCtxImpl::hoisted_masked(const HeCt& x, const u64* digits, const std::vect
     ks.push_back(key(g).p);
   }
   launch_multsum_rot(T, outs.data(), ks.data(), gs.data(), (int)gs.size(), digits, x.poly(0), pmod.p, x.level, L,
-                     alpha, beta_at(x.level), x.B, stream, masks.data(), accumulate);
+                     alpha, beta_at(x.level), x.B, stream, masks.data(), accumulate, &fork);
   n_multsum += (long)x.B * (long)gs.size();
 }
 
