@@ -305,6 +305,27 @@ he_status he_matmul_batch(he_ctx* ctx, const he_ct* const* a, const he_ct* const
 he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks, uint32_t k, uint32_t d,
                         uint64_t n_samples, const he_matmul_opts* opts, he_ct** cov);
 
+/* The block covariance of he_covariance in parts (Algorithm HCovMtrx), for
+ * a dataset that arrives, or is to be scheduled, a few row blocks at a time.
+ * he_covariance_begin fixes k, d, n_samples and the product options (a
+ * centred dataset: HE_COV_UNCENTRED is refused) and returns a state in *st;
+ * each he_covariance_add takes row_blocks * k more blocks in he_covariance's
+ * layout (x[r*k + j] = row block r, feature block j), every block of every
+ * call at one level; he_covariance_end writes the k*k blocks of
+ * X^T X / n_samples to cov[k*k] as new ciphertexts and empties the state (it
+ * may then take another dataset).  Any split of the row blocks over calls
+ * gives exactly he_covariance's residues: the products of the row blocks
+ * are summed exactly, mod q, before the one relinearisation and rescale.
+ * The state holds device memory of its context: free it with
+ * he_covariance_free before he_ctx_destroy.  Calls on one state, and on its
+ * context, are serialised by the context's lock. */
+typedef struct he_cov he_cov;
+he_status he_covariance_begin(he_ctx* ctx, uint32_t k, uint32_t d, uint64_t n_samples, const he_matmul_opts* opts,
+                              he_cov** st);
+he_status he_covariance_add(he_cov* st, const he_ct* const* x, uint32_t row_blocks);
+he_status he_covariance_end(he_cov* st, he_ct** cov);
+he_status he_covariance_free(he_cov* st);
+
 /* ------------------------------------------------------------------------
  * PowerMethod (section 6.1; Algorithms Aggregate, TaylorInit,
  * IterativeInvSRTbyNewton, AxisFlipping, HPowerMethod, HEigenShift).

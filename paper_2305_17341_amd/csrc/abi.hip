@@ -606,6 +606,61 @@ he_status he_covariance(he_ctx* ctx, const he_ct* const* x, uint32_t row_blocks,
   });
 }
 
+he_status he_covariance_begin(he_ctx* ctx, uint32_t k, uint32_t d, uint64_t n_samples, const he_matmul_opts* opts,
+                              he_cov** st) {
+  return guard([&] {
+    auto lk = hold(ctx);
+    need(st && k > 0 && d >= 2 && n_samples > 0, "bad arguments");
+    need(!(opts && (opts->flags & HE_COV_UNCENTRED)), "the covariance in parts takes a centred dataset");
+    MmOpts m = opts_of(opts, (int)d);
+    need(!m.folded, "the covariance takes the three-level product");
+    he_cov* c = new he_cov;
+    c->ctx = ctx;
+    c->st = ctx->impl.cov_begin((int)k, (int)d, n_samples, m.n1z, m.n1t, default_n1((int)d), m.npz, m.npt, m.lazy,
+                                m.fused);
+    *st = c;
+  });
+}
+
+he_status he_covariance_add(he_cov* st, const he_ct* const* x, uint32_t row_blocks) {
+  return guard([&] {
+    need(st != nullptr, "null covariance state");
+    he_ctx* ctx = st->ctx;
+    auto lk = hold(ctx);
+    need(x && row_blocks > 0, "bad arguments");
+    std::vector<const HeCt*> xs;
+    for (uint32_t i = 0; i < row_blocks * (uint32_t)st->st.k; i++) {
+      check_ct(ctx, x[i]);
+      xs.push_back(&x[i]->ct);
+    }
+    HeCtxImpl& c = ctx->impl;
+    hip_check(hipEventRecord(c.ev0, c.stream), "event");
+    c.cov_add(st->st, xs, (int)row_blocks);
+    hip_check(hipEventRecord(c.ev1, c.stream), "event");
+  });
+}
+
+he_status he_covariance_end(he_cov* st, he_ct** cov) {
+  return guard([&] {
+    need(st != nullptr && cov != nullptr, "bad arguments");
+    he_ctx* ctx = st->ctx;
+    auto lk = hold(ctx);
+    HeCtxImpl& c = ctx->impl;
+    hip_check(hipEventRecord(c.ev0, c.stream), "event");
+    std::vector<HeCt> r = c.cov_end(st->st);
+    hip_check(hipEventRecord(c.ev1, c.stream), "event");
+    for (size_t i = 0; i < r.size(); i++) cov[i] = wrap(ctx, std::move(r[i]));
+  });
+}
+
+he_status he_covariance_free(he_cov* st) {
+  return guard([&] {
+    if (!st) return;
+    auto lk = hold(st->ctx);
+    delete st;
+  });
+}
+
 // ---------------------------------------------------------------------------
 // PowerMethod (section 6.1) and the interactive refresh
 // ---------------------------------------------------------------------------

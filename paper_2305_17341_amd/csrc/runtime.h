@@ -77,6 +77,24 @@ struct MmGraph {
   }
 };
 
+// A block covariance accumulated over calls (Algorithm HCovMtrx): the
+// product options, the level the dataset blocks share, and the k^2 running
+// sums of XtX over the row blocks seen (three-component tensor sums with lazy
+// relinearisation, else relinearised products).
+struct CovState {
+  int k = 0, n = 0;
+  u64 n_samples = 0;
+  int n1z = 0, n1t = 0, n1g = 0, npz = 0, npt = 0;
+  bool lazy = false, fused = false;
+  int level = -1;
+  long row_blocks = 0;
+  int acc_level = 0;
+  double acc_scale = 0;
+  std::vector<HeCt> acc;
+  std::vector<DevBuf> acc3;
+  std::vector<bool> set;
+};
+
 struct HeCtxImpl {
   int logN = 0;
   u64 N = 0;
@@ -211,6 +229,12 @@ struct HeCtxImpl {
   void matmul_accumulate(HeCt& acc, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   std::vector<HeCt> covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples, int n1z,
                                int n1t, int n1g, int npz, int npt, bool lazy = false, bool fused_rs = false);
+  // the same in parts: any split of the row blocks over cov_add calls gives
+  // covariance's residues (the sums over row blocks are exact)
+  CovState cov_begin(int k, int n, u64 n_samples, int n1z, int n1t, int n1g, int npz, int npt, bool lazy,
+                     bool fused_rs);
+  void cov_add(CovState& st, const std::vector<const HeCt*>& x, int rb);
+  std::vector<HeCt> cov_end(CovState& st);
   // the same for a dataset that is not centred: X^T X / s - mu^T mu (section 5.2)
   std::vector<HeCt> covariance_uncentred(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples,
                                          int n1z, int n1t, int n1g, int npz, int npt, bool lazy, bool fused_rs);
@@ -233,4 +257,8 @@ struct he_ctx {
 struct he_ct {
   he_ctx* ctx;
   HeCt ct;
+};
+struct he_cov {
+  he_ctx* ctx;
+  CovState st;
 };

@@ -1793,26 +1793,43 @@ void HeCtxImpl::drop_graphs() {
 //   Rescale( sum_r sum_k Relin(Tensor(A_k(G(X_a[r]) / s), B_k(X_b[r]))) )
 // for b <= a, and G(block (b, a)) for a < b; the A and B sides of each
 // row block are formed once and reused for every pair (one-to-many caching).
-std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples,
-                                        int n1z, int n1t, int n1g, int npz, int npt, bool lazy,
-                                        bool fused_rs) {
-  if ((int)x.size() != rb * k) fail(HE_EINVAL, "block count mismatch");
-  int level = x[0]->level;
+CovState HeCtxImpl::cov_begin(int k, int n, u64 n_samples, int n1z, int n1t, int n1g, int npz, int npt, bool lazy,
+                              bool fused_rs) {
+  if (k < 1 || n < 2 || n_samples == 0) fail(HE_EINVAL, "bad covariance shape");
+  CovState st;
+  st.k = k;
+  st.n = n;
+  st.n_samples = n_samples;
+  st.n1z = n1z;
+  st.n1t = n1t;
+  st.n1g = n1g;
+  st.npz = npz;
+  st.npt = npt;
+  st.lazy = lazy;
+  st.fused = fused_rs;
+  st.acc.resize(k * k);
+  st.acc3.resize(k * k);
+  st.set.assign(k * k, false);
+  return st;
+}
+
+void HeCtxImpl::cov_add(CovState& st, const std::vector<const HeCt*>& x, int rb) {
+  const int k = st.k, n = st.n;
+  if (rb < 1 || (int)x.size() != rb * k) fail(HE_EINVAL, "block count mismatch");
+  const int level = x[0]->level;
   for (auto* c : x)
     if (c->level != level || c->qp) fail(HE_ELEVEL, "dataset blocks must share one level");
-  int dz = npz >= n - 1 ? 1 : ceil_div_i(n - 1, npz), dt = npt >= n - 1 ? 1 : ceil_div_i(n - 1, npt);
+  if (st.level >= 0 && level != st.level) fail(HE_ELEVEL, "dataset blocks must share one level over all calls");
+  const int dz = st.npz >= n - 1 ? 1 : ceil_div_i(n - 1, st.npz), dt = st.npt >= n - 1 ? 1 : ceil_div_i(n - 1, st.npt);
   if (level < std::max(dz + 1, dt) + 3) fail(HE_ELEVEL, "not enough levels for the covariance");
-  std::vector<HeCt> acc(k * k);
-  std::vector<DevBuf> acc3(k * k);
-  std::vector<bool> set(k * k, false);
-  int acc_level = 0;
-  double acc_scale = 0;
+  st.level = level;
   // the sides' common level: A after the transposition, sigma and the masks,
   // B after tau
   const int common = std::min(level - 1 - dz - 1, level - 1 - dt);
   // row blocks go through the transforms and sides stacked, g at a time (a
   // batch of g members); each pair's products are summed over the members
-  // into one accumulator (exact sums, so the residues do not depend on g)
+  // into one accumulator (exact sums, so the residues depend neither on g
+  // nor on how the row blocks are split over calls)
   int g = 4;
   knob_get("cov_row_blocks", &g);
   for (int r0 = 0; r0 < rb; r0 += g) {
@@ -1824,38 +1841,38 @@ std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int r
     };
     std::vector<std::vector<HeCt>> A(k), B(k);
     for (int a = 0; a < k; a++) {
-      HeCt xt = lintrans(rows_of(a), LT_TRANSPOSE, n, n1g, 1.0 / (double)n_samples);
-      A[a] = matmul_side_a(xt, n, n1z, npz, common, fused_rs);
+      HeCt xt = lintrans(rows_of(a), LT_TRANSPOSE, n, st.n1g, 1.0 / (double)st.n_samples);
+      A[a] = matmul_side_a(xt, n, st.n1z, st.npz, common, st.fused);
     }
     for (int b = 0; b < k; b++) {
       HeCt xb = drop(rows_of(b), level - 1);
-      B[b] = matmul_side_b(xb, n, n1t, npt, common);
+      B[b] = matmul_side_b(xb, n, st.n1t, st.npt, common);
     }
     for (int a = 0; a < k; a++) align_sides(A[a], B[0]);
     for (int b = 0; b < k; b++) align_sides(A[0], B[b]);
-    acc_level = A[0][0].level;
-    acc_scale = A[0][0].scale * B[0][0].scale;
+    st.acc_level = A[0][0].level;
+    st.acc_scale = A[0][0].scale * B[0][0].scale;
     const int nl = A[0][0].nlimbs;
     const LimbMap qm = qmap(nl);
     for (int a = 0; a < k; a++)
       for (int b = 0; b <= a; b++) {
         const int p = a * k + b;
-        if (lazy) {
+        if (st.lazy) {
           DevBuf g3;
           bool gs = false;
           accumulate_tensors(g3, gs, A[a], B[b]);
           // [3][gb][nl][N] summed over the members into [3][1][nl][N]
           const size_t nt = (size_t)gb * nl;
           int m0 = 0;
-          if (!set[p]) {
-            acc3[p] = DevBuf(&pool, (size_t)3 * nl * N);
-            for (int c = 0; c < 3; c++) copy_limbs(acc3[p].p + (size_t)c * nl * N, g3.p + c * nt * N, nl);
+          if (!st.set[p]) {
+            st.acc3[p] = DevBuf(&pool, (size_t)3 * nl * N);
+            for (int c = 0; c < 3; c++) copy_limbs(st.acc3[p].p + (size_t)c * nl * N, g3.p + c * nt * N, nl);
             m0 = 1;
-            set[p] = true;
+            st.set[p] = true;
           }
           for (int c = 0; c < 3; c++)
             for (int m = m0; m < gb; m++) {
-              u64* dst = acc3[p].p + (size_t)c * nl * N;
+              u64* dst = st.acc3[p].p + (size_t)c * nl * N;
               launch_add(T, dst, dst, g3.p + (c * nt + (size_t)m * nl) * N, nl, qm, stream);
             }
         } else {
@@ -1865,31 +1882,49 @@ std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int r
           std::vector<HeCt> parts = gb == 1 ? std::vector<HeCt>{} : unstack(gacc);
           if (gb == 1) parts.push_back(std::move(gacc));
           for (auto& part : parts) {
-            if (!set[p]) {
-              acc[p] = std::move(part);
-              set[p] = true;
+            if (!st.set[p]) {
+              st.acc[p] = std::move(part);
+              st.set[p] = true;
             } else {
-              add_into(acc[p], part);
+              add_into(st.acc[p], part);
             }
           }
         }
       }
   }
+  st.row_blocks += rb;
+}
+
+std::vector<HeCt> HeCtxImpl::cov_end(CovState& st) {
+  const int k = st.k, n = st.n;
+  if (st.row_blocks == 0) fail(HE_EINVAL, "covariance of no row blocks");
   std::vector<HeCt> out(k * k);
   for (int a = 0; a < k; a++)
     for (int b = 0; b <= a; b++) {
-      if (lazy) {
-        acc[a * k + b] = relin_sum(acc3[a * k + b], acc_level, acc_scale, 1);
-        acc3[a * k + b].release();
+      if (st.lazy) {
+        st.acc[a * k + b] = relin_sum(st.acc3[a * k + b], st.acc_level, st.acc_scale, 1);
+        st.acc3[a * k + b].release();
       }
-      out[a * k + b] = rescale(acc[a * k + b]);
+      out[a * k + b] = rescale(st.acc[a * k + b]);
+      st.acc[a * k + b] = HeCt();
     }
   for (int a = 0; a < k; a++)
-    for (int b = a + 1; b < k; b++) out[a * k + b] = lintrans(out[b * k + a], LT_TRANSPOSE, n, n1g, 1.0);
+    for (int b = a + 1; b < k; b++) out[a * k + b] = lintrans(out[b * k + a], LT_TRANSPOSE, n, st.n1g, 1.0);
   if (k > 1) {
     int fl = out[1].level;
     for (int a = 0; a < k; a++)
       for (int b = 0; b <= a; b++) out[a * k + b] = drop(out[a * k + b], fl);
   }
+  st.row_blocks = 0;
+  st.set.assign(k * k, false);
   return out;
+}
+
+std::vector<HeCt> HeCtxImpl::covariance(const std::vector<const HeCt*>& x, int rb, int k, int n, u64 n_samples,
+                                        int n1z, int n1t, int n1g, int npz, int npt, bool lazy,
+                                        bool fused_rs) {
+  if ((int)x.size() != rb * k) fail(HE_EINVAL, "block count mismatch");
+  CovState st = cov_begin(k, n, n_samples, n1z, n1t, n1g, npz, npt, lazy, fused_rs);
+  cov_add(st, x, rb);
+  return cov_end(st);
 }

@@ -30,6 +30,7 @@ EXPORTS = [
     "he_profile_enable", "he_profile_read", "he_op_counts", "he_lintrans_rot_steps", "he_smpkeysub_rot_steps", "he_refresh",
     "he_power_rot_steps", "he_power_step", "he_eigen_shift", "he_knob_set", "he_knob_get", "he_last_error",
     "he_rotate_noalloc", "he_rotate_workspace_bytes", "he_modmul_peak", "he_profile_read_ops", "he_rotate_many", "he_params_moduli",
+    "he_covariance_begin", "he_covariance_add", "he_covariance_end", "he_covariance_free",
 ]
 
 # he_refresh_fn: status (he_ct*, void* user)
@@ -127,6 +128,10 @@ def load():
                             C.POINTER(he_matmul_opts), C.POINTER(vp)],
         "he_covariance": [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
                           C.POINTER(he_matmul_opts), C.POINTER(vp)],
+        "he_covariance_begin": [vp, C.c_uint32, C.c_uint32, C.c_uint64, C.POINTER(he_matmul_opts), C.POINTER(vp)],
+        "he_covariance_add": [vp, C.POINTER(vp), C.c_uint32],
+        "he_covariance_end": [vp, C.POINTER(vp)],
+        "he_covariance_free": [vp],
         "he_sync": [vp],
         "he_mem_info": [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
         "he_trim": [vp],
@@ -174,6 +179,35 @@ def _opts(opts):
     for k, v in opts.items():
         setattr(o, k, int(v))
     return C.byref(o)
+
+
+class CovarianceParts:
+    """State of he_covariance_begin/add/end (see Context.covariance_begin)."""
+
+    def __init__(self, ctx, ptr, k):
+        self.ctx, self.ptr, self.k = ctx, ptr, k
+
+    def add(self, blocks, row_blocks):
+        px = (vp * (row_blocks * self.k))(*[x.ptr for x in blocks])
+        _check(load().he_covariance_add(self.ptr, px, row_blocks))
+
+    def end(self):
+        out = (vp * (self.k * self.k))()
+        _check(load().he_covariance_end(self.ptr, out))
+        return [Ciphertext(self.ctx, vp(out[i])) for i in range(self.k * self.k)]
+
+    def free(self):
+        if self.ptr and self.ptr.value:
+            _check(load().he_covariance_free(self.ptr))
+            self.ptr = vp()
+
+    def __del__(self):
+        try:
+            if _lib is not None and self.ptr and self.ptr.value and self.ctx.ptr and self.ctx.ptr.value:
+                _lib.he_covariance_free(self.ptr)
+                self.ptr = vp()
+        except Exception:
+            pass
 
 
 class Ciphertext:
@@ -377,6 +411,13 @@ class Context:
         out = (vp * (k * k))()
         _check(load().he_covariance(self.ptr, px, row_blocks, k, d, n_samples, _opts(opts), out))
         return [Ciphertext(self, vp(out[i])) for i in range(k * k)]
+
+    def covariance_begin(self, k, d, n_samples, opts=None):
+        """the covariance in parts: a state taking row blocks (add) and
+        returning the k*k blocks (end), with he_covariance's residues"""
+        st = vp()
+        _check(load().he_covariance_begin(self.ptr, k, d, n_samples, _opts(opts), C.byref(st)))
+        return CovarianceParts(self, st, k)
 
     def refresh(self, ct, nonce):
         """in place: ct becomes a top-level encryption of its message"""

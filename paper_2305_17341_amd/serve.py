@@ -21,6 +21,11 @@ Scheduling
     work was on the device join the next batch.  Workers of different N run
     concurrently, each on its context's stream, so their kernels overlap on
     the GPU.  Memory freed by a finished batch admits waiting requests.
+  * A covariance job runs in chunks of row blocks (he_covariance_begin /
+    add / end, `cov_chunk` row blocks a call), and a worker that has just
+    run a chunk takes the waiting products of its N before the next one, so
+    a long covariance does not hold them back.  Its residues do not depend
+    on the chunks (the sums over row blocks are exact).
   * The merged path gives the same residues as running a product alone, so
     a result does not depend on what it was batched with.
 
@@ -107,6 +112,8 @@ class Request:
     t_done: float = 0.0
     batch: int = 0
     future: Future = field(default_factory=Future)
+    state: object = None            # covariance in parts: the library's state
+    cursor: int = 0                 # covariance in parts: row blocks done
 
     @property
     def latency(self) -> float:
@@ -116,8 +123,9 @@ class Request:
 class HeBackend:
     """One context per ring dimension, keys for every served product size."""
 
-    def __init__(self, chains, ds_by_log_n, seed=1, covariance_d=(), lazy_relin=True):
+    def __init__(self, chains, ds_by_log_n, seed=1, covariance_d=(), lazy_relin=True, cov_chunk=16):
         from . import he
+        self.cov_chunk = cov_chunk
         # the benchmark headline's variants: lazy relinearisation and one
         # rounding for the A side's ModDown and Rescale
         self.relin_flags = LAZY_RELIN | FUSED_RESCALE if lazy_relin else 0
@@ -146,10 +154,23 @@ class HeBackend:
         return covariance_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d, k, rb, he.knob_get("cov_row_blocks"))
 
     def run(self, log_n: int, reqs):
+        """Runs a merged batch of products, or the next chunk of a covariance
+        job; returns the results, or None while a covariance is unfinished."""
         ctx = self.contexts[log_n]
         if reqs[0].kind == "covariance":
-            blocks, rb, k, n_samples = reqs[0].args
-            out = [ctx.covariance(blocks, rb, k, reqs[0].d, n_samples, opts={"flags": self.relin_flags})]
+            r = reqs[0]
+            blocks, rb, k, n_samples = r.args
+            if r.state is None:
+                r.state = ctx.covariance_begin(k, r.d, n_samples, opts={"flags": self.relin_flags})
+            g = min(self.cov_chunk, rb - r.cursor)
+            r.state.add(blocks[r.cursor * k:(r.cursor + g) * k], g)
+            r.cursor += g
+            if r.cursor < rb:
+                ctx.sync()
+                return None
+            out = [r.state.end()]
+            r.state.free()
+            r.state = None
         else:
             out = ctx.matmul_batch([r.args[0] for r in reqs], [r.args[1] for r in reqs], [r.d for r in reqs],
                                    opts={"flags": BATCHED | MERGED | self.relin_flags})
@@ -181,6 +202,8 @@ class Server:
         self._done = []
         self._rejected = 0
         self._batches = []
+        self._cov_chunks = 0
+        self._last_cov = {n: False for n in backend.log_ns()}
         self._workers = [threading.Thread(target=self._work, args=(n,), daemon=True) for n in backend.log_ns()]
         for w in self._workers:
             w.start()
@@ -232,8 +255,9 @@ class Server:
             "rejected": rejected,
             "jobs_per_s": len(done) / span if span > 0 else None,
             "latency_s": {"p50": q(50), "p99": q(99), "max": lat[-1]},
-            "mean_batch": sum(batches) / len(batches),
+            "mean_batch": sum(batches) / len(batches) if batches else None,
             "batches": len(batches),
+            "covariance_chunks": self._cov_chunks,
             "peak_admitted_bytes": peak,
             "budget_bytes": self.budget,
         }
@@ -250,11 +274,14 @@ class Server:
 
     def _take(self, log_n):
         ready = self._ready[log_n]
+        mats = [r for r in ready if r.kind == "matmul"]
         head = ready[0]
-        if head.kind != "matmul":
+        # after a covariance chunk the waiting products go first
+        if head.kind != "matmul" and not (self._last_cov[log_n] and mats):
             group = [head]
         else:
-            group = [r for r in ready if r.kind == "matmul"][: self.max_batch]
+            group = mats[: self.max_batch]
+        self._last_cov[log_n] = group[0].kind != "matmul"
         ids = {id(r) for r in group}
         self._ready[log_n] = [r for r in ready if id(r) not in ids]
         return group
@@ -273,14 +300,31 @@ class Server:
                 out = self.backend.run(log_n, group)
             except Exception as e:  # delivered to every request of the batch
                 err = e
+                for r in group:
+                    if r.state is not None:
+                        r.state.free()
+                        r.state = None
             t1 = time.perf_counter()
+            if err is None and out is None:
+                # a covariance chunk: the job goes back to the head of its
+                # queue, still holding its admitted memory
+                with self._cv:
+                    self._cov_chunks += 1
+                    if group[0].t_start == 0.0:
+                        group[0].t_start = t0
+                    self._ready[log_n].insert(0, group[0])
+                    self._cv.notify_all()
+                continue
             with self._cv:
                 for r in group:
                     self._in_use -= r.footprint
-                    r.t_start, r.t_done, r.batch = t0, t1, len(group)
+                    r.t_start, r.t_done, r.batch = r.t_start or t0, t1, len(group)
                     if err is None:
                         self._done.append(r)
-                self._batches.append(len(group))
+                if group[0].kind == "matmul":
+                    self._batches.append(len(group))
+                else:
+                    self._cov_chunks += 1
                 self._admit()
                 idle = not self._ready[log_n]
                 # an idle context gives its cached blocks back only while

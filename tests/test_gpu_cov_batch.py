@@ -43,3 +43,37 @@ def test_covariance_row_block_batches_keep_residues(flags):
                     assert np.array_equal(x, y), g
     finally:
         he.knob_set("cov_row_blocks", old)
+
+
+@pytest.mark.parametrize("flags", [0, 2 | 4])
+def test_covariance_in_parts_equals_whole(flags):
+    """he_covariance_begin/add/end over row blocks split 2 + 1 + 2 (and a
+    second dataset through the same state after end) gives he_covariance's
+    residues; an uncentred request and a level mismatch are refused."""
+    from paper_2305_17341_amd import he
+    n, k, rb = 8, 2, 5
+    ctx = he.chain_context(DEEP, seed=62)
+    geo = {"n1_z": 2, "n1_t": 2, "flags": flags}
+    ctx.keygen(sorted(set(ctx.matmul_rot_steps(n, geo)) | set(ctx.transpose_rot_steps(n))))
+    for seed in (23, 24):
+        X = I.centre(I.dataset(seed, rb * n - 3, k * n - 5))
+        blocks = packing.blocks(X, n)
+        cts = [ctx.encrypt_matrix(blocks[r, c], nonce=seed * 100 + r * k + c) for r in range(rb) for c in range(k)]
+        whole = [c.export() for c in ctx.covariance(cts, rb, k, n, X.shape[0], geo)]
+        if seed == 23:
+            st = ctx.covariance_begin(k, n, X.shape[0], geo)
+        r0 = 0
+        for part in (2, 1, 2):
+            st.add(cts[r0 * k:(r0 + part) * k], part)
+            r0 += part
+        parts = st.end()
+        for x, y in zip(whole, parts):
+            assert np.array_equal(x, y.export())
+    # a block one level down does not join the state's level
+    st.add(cts[:k], 1)
+    low = [ctx.drop(c, cts[0].level - 1) for c in cts[k:2 * k]]
+    with pytest.raises(he.HeError):
+        st.add(low, 1)
+    st.free()
+    with pytest.raises(he.HeError):
+        ctx.covariance_begin(k, n, 10, {"flags": 16})

@@ -97,3 +97,36 @@ def test_footprint_model_bounds_allocation_d128():
         print(f"N=2^16 d=128 batch={batch}: measured {used} B, model {model} B", flush=True)
         assert used <= model
         assert model < 2 * used
+
+
+def test_covariance_job_in_chunks_equals_whole():
+    """A covariance job served in chunks of two row blocks, with products
+    arriving while it runs, returns he_covariance's residues (computed in
+    one call) and decrypts within 2^-15; the products run between chunks."""
+    from paper_2305_17341_amd import packing
+    n, k, rb = 16, 2, 5
+    be = S.HeBackend([I.MID], {14: (16,)}, seed=13, covariance_d=((14, n),), cov_chunk=2)
+    ctx = be.contexts[14]
+    X = I.centre(I.dataset(5, rb * n - 7, k * n))
+    blocks = packing.blocks(X, n)
+    cts = [ctx.encrypt_matrix(blocks[r, c], nonce=500 + r * k + c) for r in range(rb) for c in range(k)]
+    A = I.uniform_matrix(8, n)
+    ca = ctx.encrypt_matrix(A, nonce=7)
+    srv = S.Server(be, hbm_budget=8 * 2**30)
+    fc = srv.submit("covariance", 14, n, (cts, rb, k, X.shape[0]))
+    fm = [srv.submit("matmul", 14, n, (ca, ca)) for _ in range(3)]
+    cov = fc.result(timeout=300)
+    mats = [f.result(timeout=300) for f in fm]
+    srv.close()
+    st = srv.stats()
+    assert st["covariance_chunks"] == 3, st
+    whole = ctx.covariance(cts, rb, k, n, X.shape[0], opts={"flags": be.relin_flags})
+    want = X.T @ X / X.shape[0]
+    for i, (c, w) in enumerate(zip(cov, whole)):
+        assert np.array_equal(c.export(), w.export()), i
+        a, b = divmod(i, k)
+        dec = ctx.decrypt(c, n * n).reshape(n, n)
+        assert np.max(np.abs(dec - want[a * n:(a + 1) * n, b * n:(b + 1) * n])) < BOUND
+    alone = ctx.matmul(ca, ca, n, opts={"flags": be.relin_flags}).export()
+    for m in mats:
+        assert np.array_equal(m.export(), alone)

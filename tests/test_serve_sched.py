@@ -165,3 +165,45 @@ def test_valid_pairs_match_the_fourteen_served_shapes():
     pairs = S.valid_pairs([I.SMALL, I.MID, I.SERVE15, I.LARGE])
     assert len(pairs) == 14
     assert all(d * d <= (1 << ln) // 2 for d, ln in pairs)
+
+
+class ChunkedBackend(FakeBackend):
+    """a covariance job takes `chunks` calls (None until the last), as the
+    library's covariance in parts does"""
+
+    def __init__(self, chunks=3, **kw):
+        super().__init__(**kw)
+        self.chunks = chunks
+
+    def run(self, log_n, reqs):
+        if reqs[0].kind == "covariance":
+            t0 = time.perf_counter()
+            self.started.set()
+            time.sleep(self.cost)
+            with self.lock:
+                self.calls.append((log_n, [(r.kind, r.d, r.id) for r in reqs], t0, time.perf_counter()))
+            reqs[0].cursor += 1
+            return None if reqs[0].cursor < self.chunks else [("cov", reqs[0].id)]
+        return super().run(log_n, reqs)
+
+
+def test_products_run_between_covariance_chunks():
+    """A covariance job runs a chunk at a time; products that arrive meanwhile
+    get a batch between its chunks instead of waiting for the whole job,
+    and the job still completes with its result."""
+    be = ChunkedBackend(chunks=4, log_ns=(16,), cost=0.03)
+    srv = S.Server(be, hbm_budget=100_000)
+    cov = srv.submit("covariance", 16, 128, ())
+    assert be.started.wait(5)
+    mats = [srv.submit("matmul", 16, 16, (i,)) for i in range(3)]
+    assert cov.result(timeout=10) == ("cov", 0)
+    for f in mats:
+        f.result(timeout=10)
+    srv.close()
+    kinds = [reqs[0][0] for _, reqs, _, _ in sorted(be.calls, key=lambda c: c[2])]
+    assert kinds.count("covariance") == 4
+    first_mat = kinds.index("matmul")
+    assert first_mat < len(kinds) - 1 and "covariance" in kinds[first_mat + 1:], kinds
+    st = srv.stats()
+    assert st["covariance_chunks"] == 4 and st["jobs"] == 4
+    assert srv.stats()["peak_admitted_bytes"] >= 128 * 10
