@@ -45,7 +45,7 @@ _MULTSUM_REGIONS = [("kernels.hip", "__device__ __forceinline__ u32 automorph_sr
 _NTT_REGIONS = [("kernels.hip", "__device__ __forceinline__ int grid_limb(", "return m.n;\n}"),
                 ("kernels.hip", "struct ShoupArith {", "// Galois automorphism in the evaluation domain:"),
                 ("he_internal.h", "// Per-modulus constants", "// Host-side objects")]
-KERNEL_REGIONS = {"multsum": _MULTSUM_REGIONS, "multsum_rot": _MULTSUM_REGIONS,
+KERNEL_REGIONS = {"multsum": _MULTSUM_REGIONS, "multsum_rot": _MULTSUM_REGIONS, "multsum_rot_int": _MULTSUM_REGIONS,
                   "ntt_fwd_cols": _NTT_REGIONS, "ntt_fwd_rows": _NTT_REGIONS, "ntt_fwd_rows_sub": _NTT_REGIONS,
                   "ntt_fwd_cols_modup": _NTT_REGIONS}
 # the fused ModDown column pass also depends on the conversion's constants and quotient
@@ -255,7 +255,7 @@ def main():
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--rotations", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=300,
+    ap.add_argument("--serve-jobs", type=int, default=400,
                     help="jobs per serving trace: the capacity run and each offered load (0: skip serving)")
     ap.add_argument("--serve-loads", default="0.2,0.6,1.0,1.2",
                     help="offered loads of the serving sweep, as fractions of the measured batched capacity")
@@ -263,8 +263,8 @@ def main():
     ap.add_argument("--n1", type=int, default=64,
                     help="baby steps of Z and T and the block size of the column/row shifts (0: the library's "
                          "default, 16 for d = 128); 64 measured fastest for d = 128 (130 keys, 47.8 GiB resident)")
-    ap.add_argument("--serve-cov-samples", type=int, default=256,
-                    help="rows of the serving mix's covariance job (the workload's has 60000: about a minute more)")
+    ap.add_argument("--serve-cov-samples", type=int, default=60000,
+                    help="rows of the serving mix's covariance job (256 features)")
     ap.add_argument("--big-covariance", type=int, default=0, metavar="S",
                     help="also run the serving workload's large covariance job alone on S x 256 samples (60000 in "
                          "the workload; about a minute; 0: skip)")

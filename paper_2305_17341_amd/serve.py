@@ -22,10 +22,11 @@ Scheduling
     concurrently, each on its context's stream, so their kernels overlap on
     the GPU.  Memory freed by a finished batch admits waiting requests.
   * A covariance job runs in chunks of row blocks (he_covariance_begin /
-    add / end, `cov_chunk` row blocks a call), and a worker that has just
-    run a chunk takes the waiting products of its N before the next one, so
-    a long covariance does not hold them back.  Its residues do not depend
-    on the chunks (the sums over row blocks are exact).
+    add / end, `cov_chunk` row blocks a call).  Between two chunks a worker
+    runs up to `cov_yield` batches of the products waiting on its N, so a
+    long covariance does not hold them back, and it still advances while
+    products keep arriving.  Its residues do not depend on the chunks (the
+    sums over row blocks are exact).
   * The merged path gives the same residues as running a product alone, so
     a result does not depend on what it was batched with.
 
@@ -123,7 +124,7 @@ class Request:
 class HeBackend:
     """One context per ring dimension, keys for every served product size."""
 
-    def __init__(self, chains, ds_by_log_n, seed=1, covariance_d=(), lazy_relin=True, cov_chunk=16):
+    def __init__(self, chains, ds_by_log_n, seed=1, covariance_d=(), lazy_relin=True, cov_chunk=8):
         from . import he
         self.cov_chunk = cov_chunk
         # the benchmark headline's variants: lazy relinearisation and one
@@ -187,8 +188,10 @@ class HeBackend:
 
 
 class Server:
-    def __init__(self, backend, hbm_budget: int, max_batch: int = 8, trim_when_idle: bool = True):
+    def __init__(self, backend, hbm_budget: int, max_batch: int = 8, trim_when_idle: bool = True,
+                 cov_yield: int = 4):
         self.backend = backend
+        self.cov_yield = cov_yield
         self.budget = int(hbm_budget)
         self.max_batch = max_batch
         self.trim_when_idle = trim_when_idle
@@ -203,7 +206,7 @@ class Server:
         self._rejected = 0
         self._batches = []
         self._cov_chunks = 0
-        self._last_cov = {n: False for n in backend.log_ns()}
+        self._since_chunk = {n: 0 for n in backend.log_ns()}   # product batches since the last chunk
         self._workers = [threading.Thread(target=self._work, args=(n,), daemon=True) for n in backend.log_ns()]
         for w in self._workers:
             w.start()
@@ -244,17 +247,28 @@ class Server:
             peak, rejected = self._peak, self._rejected
         if not done:
             return {"jobs": 0, "rejected": rejected}
-        lat = sorted(r.latency for r in done)
 
-        def q(p):
-            k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
-            return lat[k]
-        span = max(r.t_done for r in done) - min(r.t_submit for r in done)
+        def pct(rs):
+            lat = sorted(r.latency for r in rs)
+
+            def q(p):
+                return lat[min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))]
+            return {"p50": q(50), "p99": q(99), "max": lat[-1]}
+
+        def rate(rs):
+            span = max(r.t_done for r in rs) - min(r.t_submit for r in rs)
+            return len(rs) / span if span > 0 else None
+        prods = [r for r in done if r.kind == "matmul"]
         return {
             "jobs": len(done),
             "rejected": rejected,
-            "jobs_per_s": len(done) / span if span > 0 else None,
-            "latency_s": {"p50": q(50), "p99": q(99), "max": lat[-1]},
+            "jobs_per_s": rate(done),
+            "latency_s": pct(done),
+            # the products alone: a long covariance job would otherwise set
+            # the span and the tail of every trace it is part of
+            "products_per_s": rate(prods) if prods else None,
+            "product_latency_s": pct(prods) if prods else None,
+            "covariance_latency_s": [r.latency for r in done if r.kind != "matmul"],
             "mean_batch": sum(batches) / len(batches) if batches else None,
             "batches": len(batches),
             "covariance_chunks": self._cov_chunks,
@@ -276,12 +290,13 @@ class Server:
         ready = self._ready[log_n]
         mats = [r for r in ready if r.kind == "matmul"]
         head = ready[0]
-        # after a covariance chunk the waiting products go first
-        if head.kind != "matmul" and not (self._last_cov[log_n] and mats):
+        # between two covariance chunks, up to cov_yield batches of products
+        if head.kind != "matmul" and not (mats and self._since_chunk[log_n] < self.cov_yield):
             group = [head]
+            self._since_chunk[log_n] = 0
         else:
             group = mats[: self.max_batch]
-        self._last_cov[log_n] = group[0].kind != "matmul"
+            self._since_chunk[log_n] += 1
         ids = {id(r) for r in group}
         self._ready[log_n] = [r for r in ready if id(r) not in ids]
         return group
@@ -389,7 +404,8 @@ def serve_bench(argv=None):
     ap.add_argument("--jobs", type=int, default=300, help="jobs per trace (capacity run and each load)")
     ap.add_argument("--loads", default="0.2,0.6,1.0,1.2",
                     help="offered rates as fractions of the measured batched capacity")
-    ap.add_argument("--budget-gib", type=float, default=0.0, help="0: half of the free device memory")
+    ap.add_argument("--budget-gib", type=float, default=0.0,
+                    help="0: 3/4 of the device memory free once a trace's inputs are resident")
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--no-covariance", action="store_true")
     ap.add_argument("--cov-samples", type=int, default=256,
@@ -440,12 +456,18 @@ def serve_bench(argv=None):
     log(f"[serve] solo latency per pair (ms): " + ", ".join(f"d={d}/2^{ln}: {1e3 * s:.1f}"
                                                           for (d, ln), s in sorted(solo.items())))
     ctx16 = backend.contexts[16]
-    if args.budget_gib > 0:
-        budget = int(args.budget_gib * 2**30)
-    else:
+
+    def budget_now():
+        """the admission budget: --budget-gib, else 3/4 of the device memory
+        free once the trace's inputs are resident and cached blocks are back"""
+        if args.budget_gib > 0:
+            return int(args.budget_gib * 2**30)
         from . import he
+        for c in backend.contexts.values():
+            c.sync()
+            c.trim()
         free, _ = he.device_memory()
-        budget = int(0.5 * free)
+        return int(0.75 * free)
     X = I.centre(I.dataset(args.seed, args.cov_samples, 2 * cov_n)) if not args.no_covariance else None
 
     def trace(seed, rate, with_cov):
@@ -467,8 +489,7 @@ def serve_bench(argv=None):
             cts = [ctx16.encrypt_matrix(blk[r, c], nonce=10**6 + 2 * r + c) for r in range(cov_rb) for c in range(2)]
             extra.append((jobs[len(jobs) // 2].arrival, ("covariance", 16, cov_n, (cts, cov_rb, 2, X.shape[0]))))
             del blk
-        for c in backend.contexts.values():
-            c.sync()
+        budget = budget_now()
         srv = Server(backend, hbm_budget=budget)
         futs = run_trace(srv, jobs, payloads, extra)
         results = [f.result() for _, f in futs]
@@ -495,15 +516,20 @@ def serve_bench(argv=None):
         return {"offered_rate": None if not np.isfinite(rate) else round(rate, 3),
                 "jobs_per_s": round(st["jobs_per_s"], 3),
                 "latency_ms": {k2: round(1e3 * v, 2) for k2, v in st["latency_s"].items()},
+                "products_per_s": round(st["products_per_s"], 3),
+                "product_latency_ms": {k2: round(1e3 * v, 2) for k2, v in st["product_latency_s"].items()},
+                "covariance_latency_s": [round(v, 3) for v in st["covariance_latency_s"]],
                 "mean_batch": round(st["mean_batch"], 3), "batches": st["batches"], "jobs": st["jobs"],
                 "rejected": st["rejected"], "peak_admitted_gib": round(st["peak_admitted_bytes"] / 2**30, 2),
+                "budget_gib": round(st["budget_bytes"] / 2**30, 2), "covariance_chunks": st["covariance_chunks"],
                 "max_abs_err_sampled": err}
 
-    log(f"[serve] batched capacity: {args.jobs} jobs offered at once (budget {budget / 2**30:.1f} GiB)")
+    log(f"[serve] batched capacity: {args.jobs} jobs offered at once")
     st, err = trace(args.seed, float("inf"), False)
     capacity = st["jobs_per_s"]
     cap = summary(st, float("inf"), err)
-    log(f"[serve] capacity {capacity:.2f} jobs/s (one at a time {one_at_a_time:.2f}), mean batch {st['mean_batch']:.2f}")
+    log(f"[serve] capacity {capacity:.2f} jobs/s (one at a time {one_at_a_time:.2f}), mean batch "
+        f"{st['mean_batch']:.2f}, budget {cap['budget_gib']:.1f} GiB")
     sweep = []
     for k, load in enumerate(loads):
         rate = load * capacity
@@ -511,9 +537,10 @@ def serve_bench(argv=None):
         st, err = trace(args.seed + 1 + k, rate, with_cov)
         row = dict(summary(st, rate, err), load=load, covariance_job=with_cov)
         sweep.append(row)
-        log(f"[serve] load {load}: offered {rate:.2f}/s, served {row['jobs_per_s']:.2f}/s, p50 "
-            f"{row['latency_ms']['p50']:.1f} ms, p99 {row['latency_ms']['p99']:.1f} ms, mean batch "
-            f"{row['mean_batch']:.2f}")
+        log(f"[serve] load {load}: offered {rate:.2f}/s, products served {row['products_per_s']:.2f}/s, p50 "
+            f"{row['product_latency_ms']['p50']:.1f} ms, p99 {row['product_latency_ms']['p99']:.1f} ms, mean batch "
+            f"{row['mean_batch']:.2f}" + (f", covariance job {row['covariance_latency_s'][0]:.1f} s in "
+                                          f"{row['covariance_chunks']} chunks" if row['covariance_latency_s'] else ""))
     for c in backend.contexts.values():
         c.close()
     head = max(sweep, key=lambda r: r["load"]) if sweep else cap
@@ -523,13 +550,14 @@ def serve_bench(argv=None):
                   + ("" if args.no_covariance else f" + one {args.cov_samples}x256 block covariance") + ")",
         "jobs_per_s": head["jobs_per_s"],
         "latency_ms": head["latency_ms"],
+        "products_per_s": head["products_per_s"],
+        "product_latency_ms": head["product_latency_ms"],
         "mean_batch": head["mean_batch"],
         "one_at_a_time_rate": round(one_at_a_time, 3),
         "batched_capacity": cap,
         "capacity_vs_one_at_a_time": round(capacity / one_at_a_time, 3),
         "load_sweep": sweep,
         "jobs_total": cap["jobs"] + sum(r["jobs"] for r in sweep),
-        "budget_gib": round(budget / 2**30, 2),
         "max_abs_err_sampled": max(errs) if errs else None,
         "solo_ms": {f"d{d}_n{ln}": round(1e3 * s, 2) for (d, ln), s in sorted(solo.items())},
         "ntt_split_autotune": tuned,
