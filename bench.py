@@ -370,7 +370,10 @@ def main():
             "ntt_inv_rows", "ntt_inv_cols", "multsum", "multsum_rot", "multsum_rot_int", "modup", "fbc_prep",
             "fbc_to_q",
             "moddown_final", "rescale_lift", "rescale_final", "elementwise", "tensor", "plift"]
-    prof = {f: ctx.profile_read(f) for f in fams}
+    # device-to-device copies (stacking, gathers before a transform): step
+    # time, not algorithmic work, so kept out of the roofline sums
+    copy_fams = ["copy_ct", "copy_limbs", "copy_gather", "copy_decompose", "copy_stack", "copy_unstack"]
+    prof = {f: ctx.profile_read(f) for f in fams + copy_fams}
     ops = {f: ctx.profile_read_ops(f) for f in fams}
     ctx.profile_enable(False)
     n_mm = args.steps * B
@@ -408,7 +411,7 @@ def main():
 
     value = args.steps * B / t_total
     step_s = t_total / args.steps
-    fam_ms = {f: prof[f][0] / args.steps for f in fams}
+    fam_ms = {f: prof[f][0] / args.steps for f in fams + copy_fams}
     dom = max(fams, key=lambda f: prof[f][0])
     ms, launches, nbytes = prof[dom]
     mmf, mmi, unit_bytes = ops[dom]

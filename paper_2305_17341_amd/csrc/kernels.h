@@ -8,6 +8,10 @@
 struct LimbMap {
   int n;                 // period
   short idx[960];
+  // the transforms (launch_ntt) only: with slot_per > 0, limb k lives in
+  // memory slot (k / slot_per) * slot_stride + slot_off + k % slot_per (for
+  // example the special-prime limbs of an R_{Q_l P} element, in place)
+  short slot_per = 0, slot_stride = 0, slot_off = 0;
 };
 
 struct DeviceTables {
@@ -103,8 +107,12 @@ void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64
 // ModDown's conversion fused into the forward NTT of the Q limbs (the tail
 // (x - y) P^-1 in its block pass): scratch y [npoly][nq][N] and V
 // [npoly][ns + 1][N]; false when the ring size has no register-blocked NTT
+// xp_coef: the source limbs in the coefficient domain, [npoly][ns][N]; or,
+// with src_stride > 0, limb a of poly p at slot p * src_stride + src_off + a
+// (the sources transformed in place inside the R_{Q_l P} element)
 bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
-                          const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s);
+                          const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
+                          int src_stride = 0, int src_off = 0);
 // y[npoly][nq] = exact centred lift of the source limbs xp[npoly][ns] to each q_t
 void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                      hipStream_t s);
@@ -206,6 +214,11 @@ struct Mm {
   void add(int bits, double n) { (bits <= F64_LAZY_BITS ? f : i) += n; }
 };
 Mm mm_map(const DeviceTables& T, const LimbMap& m, int nlimbs, double per_limb);
+
+// device-to-device copies, timed under `family` while profiling is on
+hipError_t copy_async(const char* family, void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t copy2d_async(const char* family, void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                        size_t height, hipStream_t s);
 
 // per-family device timing (HIP events around launches)
 void prof_enable(bool on);

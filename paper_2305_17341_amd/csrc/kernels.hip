@@ -213,6 +213,16 @@ void prof_collect() {
 }
 }  // namespace
 
+hipError_t copy_async(const char* family, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  ProfScope ps(family, s, 2.0 * (double)bytes);
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+hipError_t copy2d_async(const char* family, void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                        size_t height, hipStream_t s) {
+  ProfScope ps(family, s, 2.0 * (double)width * (double)height);
+  return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, height, hipMemcpyDeviceToDevice, s);
+}
+
 bool prof_enabled() { return g_prof_on; }
 void prof_enable(bool on) {
   prof_collect();
@@ -249,6 +259,9 @@ std::vector<std::string> prof_families() {
 }
 
 __device__ __forceinline__ int limb_mod(const LimbMap& m, int k) { return m.idx[k % m.n]; }
+__device__ __forceinline__ size_t limb_slot(const LimbMap& m, int k) {
+  return m.slot_per > 0 ? (size_t)(k / m.slot_per) * m.slot_stride + m.slot_off + k % m.slot_per : (size_t)k;
+}
 // Limb of grid row y when `outer` groups of gridDim.y / outer limbs are
 // visited interleaved (limb j of every group, then limb j + 1, ...): limbs
 // that share a modulus or a broadcast operand then run back to back, and
@@ -341,7 +354,7 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols(u64* data, LimbMap map, int lo
   const int m = limb_mod(map, limb);
   if (m < 0) return;
   const u64 N = 1ull << logN;
-  u64* a = data + (size_t)limb * N;
+  u64* a = data + limb_slot(map, limb) * N;
   const int c0 = blockIdx.x * C;
   const int tot = R * C;
   for (int e = threadIdx.x; e < tot; e += TPB) {
@@ -406,7 +419,7 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows(u64* data, LimbMap map, int lo
   if (m < 0) return;
   const u64 N = 1ull << logN;
   const int blk0 = blockIdx.x * K;
-  u64* a = data + (size_t)limb * N + (size_t)blk0 * T1;
+  u64* a = data + limb_slot(map, limb) * N + (size_t)blk0 * T1;
   const int tot = K * T1;
   for (int e = threadIdx.x; e < tot; e += TPB) sh[e] = a[e];
   __syncthreads();
@@ -885,7 +898,7 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2(u64* data, LimbMap map, const
   const int m = limb_mod(map, limb);
   if (m < 0) return;
   const u64 N = 1ull << LOGN;
-  u64* a = data + (size_t)limb * N;
+  u64* a = data + limb_slot(map, limb) * N;
   const int c0 = blockIdx.x * C;
   const ModConst mk = mc[m];
   if (mk.bits <= F64_LAZY_BITS) {
@@ -909,7 +922,7 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
   if (m < 0) return;
   const u64 N = 1ull << LOGN;
   const int blk0 = blockIdx.x * K;
-  u64* a = data + (size_t)limb * N + (size_t)blk0 * T1;
+  u64* a = data + limb_slot(map, limb) * N + (size_t)blk0 * T1;
   const ModConst mk = mc[m];
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
@@ -1162,6 +1175,7 @@ void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map
   for (int k = 0; k < nlimbs; k++) active += map.idx[k % map.n] >= 0;
   const double pass_bytes = 16.0 * active * T.N;
   if (ntt_register_blocked(T, data, nlimbs, map, inverse, pass_bytes, s)) return;
+  if (map.slot_per > 0) throw std::runtime_error("limb slots need the register-blocked NTT (log N 12..16)");
   NttShape sh = ntt_shape(T.logN);
   dim3 gc(sh.T1 / sh.C, nlimbs), gr(sh.R / sh.K, nlimbs);
   const Mm mm_c = mm_map(T, map, nlimbs, 0.5 * T.N * sh.s1), mm_r = mm_map(T, map, nlimbs, 0.5 * T.N * (sh.logN - sh.s1));
@@ -1744,6 +1758,7 @@ struct FbcArgs {
   double qrecip[4];   // 1 / q_a of the sources
   const u64* D_mod_t;
   const double* hat_f;
+  int src_stride, src_off;  // source limb a of poly p at slot p * src_stride + src_off + a
 };
 
 // acc (4 words) += H (4 words) * y, carries beyond the top word dropped
@@ -1841,6 +1856,8 @@ void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, 
   A.hat_t_sh = tab.hat_t_sh;
   A.D_mod_t = tab.D_mod_t;
   A.hat_f = tab.hat_f;
+  A.src_stride = tab.ns;
+  A.src_off = 0;
   ProfScope ps("fbc_to_q", s, 8.0 * T.N * npoly * ((double)tab.ns + nq), mm_q(T, nq, (double)T.N * (tab.ns + 1), npoly));
   dim3 grid(cdiv(T.N, TPB), nq < 4 ? nq : 4, npoly);
   hipLaunchKernelGGL(k_fbc_to_q, grid, dim3(TPB), 0, s, y, xp_coef, nq, A, T.logN, T.nmods, T.mc);
@@ -1858,7 +1875,7 @@ __global__ void k_fbc_prep(u64* V, const u64* xp, FbcArgs A, int logN, const Mod
   u32 i = blockIdx.x * TPB + threadIdx.x;
   if (i >= N) return;
   const int poly = blockIdx.y;
-  const u64* x = xp + (size_t)poly * A.ns * N;
+  const u64* x = xp + ((size_t)poly * A.src_stride + A.src_off) * N;
   u64* o = V + (size_t)poly * (A.ns + 1) * N;
   u64 v[4];
   for (int a = 0; a < A.ns; a++) v[a] = shoup_mul(x[(size_t)a * N + i], A.hatinv[a], A.hatinv_sh[a], mc[A.src[a]].q);
@@ -1977,10 +1994,13 @@ static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const Fbc
 // domain [npoly][ns][N], x the R_{Q_l P} data ([npoly][x_stride][N]), out
 // [npoly][nq][N]; false when the ring size has no register-blocked NTT
 bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
-                          const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s) {
+                          const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
+                          int src_stride, int src_off) {
   if (T.logN < 12 || T.logN > 16 || tab.ns > 4) return false;
   FbcArgs A;
   A.ns = tab.ns;
+  A.src_stride = src_stride > 0 ? src_stride : tab.ns;
+  A.src_off = src_stride > 0 ? src_off : 0;
   for (int a = 0; a < tab.ns; a++) {
     A.src[a] = tab.src[a];
     A.hatinv[a] = tab.hatinv[a];

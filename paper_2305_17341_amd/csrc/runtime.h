@@ -153,7 +153,7 @@ struct HeCtxImpl {
 
   HeCt ct_new(int level, bool qp, double scale, int B = 1);
   HeCt ct_copy(const HeCt& x);
-  void copy_limbs(u64* dst, const u64* src, size_t nlimbs);
+  void copy_limbs(u64* dst, const u64* src, size_t nlimbs, const char* family = "copy_limbs");
 
   DevBuf encode_batch(const double* z_host, int nz, int batch, double delta);
   void int_to_ntt(u64* out, const i64* m, const LimbMap& map);
@@ -177,10 +177,12 @@ struct HeCtxImpl {
   std::vector<HeCt> hoisted_multi(const HeCt& x, const u64* digits, const std::vector<u64>& gs);
   void hoisted_masked(const HeCt& x, const u64* digits, const std::vector<u64>& gs, const std::vector<u64*>& outs,
                       const std::vector<const u64*>& masks, bool accumulate);
-  HeCt moddown(const HeCt& x, int out_level = -1);
-  void moddown_to(const HeCt& x, int out_level, u64* out);
+  // consume: x's special-prime limbs (and q_l for moddown_rescale) may be
+  // overwritten (x is a temporary the caller drops afterwards)
+  HeCt moddown(const HeCt& x, int out_level = -1, bool consume = false);
+  void moddown_to(const HeCt& x, int out_level, u64* out, bool consume = false);
   // ModDown and Rescale as one rounding by P q_l (a variant)
-  HeCt moddown_rescale(const HeCt& x, int out_level = -1);
+  HeCt moddown_rescale(const HeCt& x, int out_level = -1, bool consume = false);
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);
   HeCt rotate(const HeCt& x, long step);

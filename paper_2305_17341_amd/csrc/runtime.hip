@@ -513,11 +513,11 @@ HeCt HeCtxImpl::ct_new(int level, bool qp, double scale, int B) {
 }
 HeCt HeCtxImpl::ct_copy(const HeCt& x) {
   HeCt c = ct_new(x.level, x.qp, x.scale, x.B);
-  hip_check(hipMemcpyAsync(c.d.p, x.d.p, c.d.words * 8, hipMemcpyDeviceToDevice, stream), "copy");
+  hip_check(copy_async("copy_ct", c.d.p, x.d.p, c.d.words * 8, stream), "copy");
   return c;
 }
-void HeCtxImpl::copy_limbs(u64* dst, const u64* src, size_t nlimbs) {
-  hip_check(hipMemcpyAsync(dst, src, nlimbs * N * 8, hipMemcpyDeviceToDevice, stream), "copy");
+void HeCtxImpl::copy_limbs(u64* dst, const u64* src, size_t nlimbs, const char* family) {
+  hip_check(copy_async(family, dst, src, nlimbs * N * 8, stream), "copy");
 }
 
 // ---------------------------------------------------------------------------
@@ -684,8 +684,8 @@ void HeCtxImpl::add_into(HeCt& acc, const HeCt& b) {
 
 // the first `count` limbs of every poly of x into dst [polys][count][N]
 void HeCtxImpl::gather_limbs(u64* dst, const HeCt& x, int first, int count) {
-  hip_check(hipMemcpy2DAsync(dst, (size_t)count * N * 8, x.d.p + (size_t)first * N, (size_t)x.nlimbs * N * 8,
-                             (size_t)count * N * 8, x.polys(), hipMemcpyDeviceToDevice, stream),
+  hip_check(copy2d_async("copy_gather", dst, (size_t)count * N * 8, x.d.p + (size_t)first * N,
+                         (size_t)x.nlimbs * N * 8, (size_t)count * N * 8, x.polys(), stream),
             "gather");
 }
 
@@ -731,7 +731,7 @@ HeCt HeCtxImpl::rescale(const HeCt& a, int out_level) {
 DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
   int nq = nq_of(level), nqp = nqp_of(level), bl = beta_at(level);
   DevBuf coef(&pool, (size_t)B * nq * N);
-  copy_limbs(coef.p, d, (size_t)B * nq);
+  copy_limbs(coef.p, d, (size_t)B * nq, "copy_decompose");
   launch_ntt(T, coef.p, B * nq, qmap(nq), true, stream);
   DevBuf dig(&pool, (size_t)B * bl * nqp * N);
   LimbMap m;
@@ -821,25 +821,39 @@ void HeCtxImpl::hoisted_masked(const HeCt& x, const u64* digits, const std::vect
 
 // ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact
 // centred residue; out_level < l keeps (and computes) only the limbs up to it
-HeCt HeCtxImpl::moddown(const HeCt& x, int out_level) {
+HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   if (out_level < 0) out_level = x.level;
   if (out_level > x.level) fail(HE_ELEVEL, "moddown cannot raise the level");
   HeCt c = ct_new(out_level, false, x.scale, x.B);
-  moddown_to(x, out_level, c.d.p);
+  moddown_to(x, out_level, c.d.p, consume);
   return c;
 }
-// the same into out [2][B][out_level + 1][N]
-void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out) {
+// the same into out [2][B][out_level + 1][N].  consume: x's special-prime
+// limbs are brought to the coefficient domain in place (x is left with them
+// so) instead of in a gathered copy
+void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume) {
   int nq = nq_of(out_level), nqp = nqp_of(x.level);
   const int np = (int)x.polys();
-  DevBuf pc(&pool, (size_t)np * alpha * N);
-  gather_limbs(pc.p, x, nq_of(x.level), alpha);
+  DevBuf y(&pool, (size_t)np * nq * N);
   LimbMap pm;
   pm.n = alpha;
   for (int k = 0; k < alpha; k++) pm.idx[k] = (short)(L + 1 + k);
+  if (fused_conv && consume) {
+    pm.slot_per = (short)alpha;
+    pm.slot_stride = (short)x.nlimbs;
+    pm.slot_off = (short)nq_of(x.level);
+    launch_ntt(T, x.d.p, np * alpha, pm, true, stream);
+    DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
+    if (!launch_moddown_fused(T, x.d.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream, x.nlimbs,
+                              nq_of(x.level)))
+      fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
+    n_moddown += x.B;
+    return;
+  }
+  DevBuf pc(&pool, (size_t)np * alpha * N);
+  gather_limbs(pc.p, x, nq_of(x.level), alpha);
   launch_ntt(T, pc.p, np * alpha, pm, true, stream);
-  DevBuf y(&pool, (size_t)np * nq * N);
   if (fused_conv) {
     DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
     if (!launch_moddown_fused(T, pc.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream))
@@ -855,7 +869,7 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out) {
 // round(x / (P q_l)) in R_{Q_{l-1}} (or a lower out_level: only the kept
 // limbs are computed): the exact centred lift of x mod P q_l from the limbs
 // q_l, p_1..p_alpha, then (x - lift) (P q_l)^-1 on the limbs below q_l.
-HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level) {
+HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   const int l = x.level;
   if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
@@ -865,22 +879,37 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level) {
   const int nqx = nq_of(l), nqp = nqp_of(l), nout = out_level + 1, ns = alpha + 1;
   const int np = (int)x.polys();
   const FbcTable& tab = down_rs[l];
-  // sources [np][q_l, p_1..p_alpha] in the coefficient domain
-  DevBuf pc(&pool, (size_t)np * ns * N);
-  hip_check(hipMemcpy2DAsync(pc.p, (size_t)ns * N * 8, x.d.p + (size_t)l * N, (size_t)x.nlimbs * N * 8,
-                             (size_t)N * 8, np, hipMemcpyDeviceToDevice, stream),
-            "gather");
-  hip_check(hipMemcpy2DAsync(pc.p + N, (size_t)ns * N * 8, x.d.p + (size_t)nqx * N, (size_t)x.nlimbs * N * 8,
-                             (size_t)alpha * N * 8, np, hipMemcpyDeviceToDevice, stream),
-            "gather");
   LimbMap sm;
   sm.n = ns;
   sm.idx[0] = (short)l;
   for (int k = 0; k < alpha; k++) sm.idx[1 + k] = (short)(L + 1 + k);
+  const u64* cp = pqlinv.p + (size_t)l * nmods * 2;
+  if (fused_conv && consume) {
+    // q_l and the special primes are the consecutive slots l .. l + alpha of
+    // each poly: transformed in place, read from there
+    sm.slot_per = (short)ns;
+    sm.slot_stride = (short)x.nlimbs;
+    sm.slot_off = (short)l;
+    launch_ntt(T, x.d.p, np * ns, sm, true, stream);
+    DevBuf y(&pool, (size_t)np * nout * N);
+    HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
+    DevBuf V(&pool, (size_t)np * (ns + 1) * N);
+    if (!launch_moddown_fused(T, x.d.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, V.p, stream, x.nlimbs, l))
+      fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
+    n_moddown += x.B;
+    return c;
+  }
+  // sources [np][q_l, p_1..p_alpha] in the coefficient domain
+  DevBuf pc(&pool, (size_t)np * ns * N);
+  hip_check(copy2d_async("copy_gather", pc.p, (size_t)ns * N * 8, x.d.p + (size_t)l * N, (size_t)x.nlimbs * N * 8,
+                         (size_t)N * 8, np, stream),
+            "gather");
+  hip_check(copy2d_async("copy_gather", pc.p + N, (size_t)ns * N * 8, x.d.p + (size_t)nqx * N,
+                         (size_t)x.nlimbs * N * 8, (size_t)alpha * N * 8, np, stream),
+            "gather");
   launch_ntt(T, pc.p, np * ns, sm, true, stream);
   DevBuf y(&pool, (size_t)np * nout * N);
   HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
-  const u64* cp = pqlinv.p + (size_t)l * nmods * 2;
   if (fused_conv) {
     DevBuf V(&pool, (size_t)np * (ns + 1) * N);
     if (!launch_moddown_fused(T, pc.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, V.p, stream))
@@ -899,7 +928,7 @@ HeCt HeCtxImpl::keyswitch(const u64* d, int level, u64 g_key, int B) {
   const DevBuf& k = key(g_key);
   launch_multsum(T, h.d.p, dig.p, k.p, nullptr, pmod.p, level, L, alpha, beta_at(level), 1, B, stream);
   n_multsum += B;
-  return moddown(h);
+  return moddown(h, -1, true);
 }
 
 HeCt HeCtxImpl::mult(const HeCt& a, const HeCt& b) {
@@ -919,7 +948,7 @@ HeCt HeCtxImpl::rotate(const HeCt& x, long step) {
   if (g == 1) return ct_copy(x);
   DevBuf dig = decompose(x.poly(1), x.level, x.B);
   HeCt h = hoisted(x, dig.p, g);
-  return moddown(h);
+  return moddown(h, -1, true);
 }
 
 // Rotations of a batch x (one level and scale) by several steps, hoisted
@@ -947,7 +976,7 @@ std::vector<HeCt> HeCtxImpl::rotate_many(const HeCt& x, const std::vector<long>&
     const size_t nr = std::min(gs.size() - r0, (size_t)MR_MAX);
     std::vector<HeCt> h = hoisted_multi(x, dig.p, std::vector<u64>(gs.begin() + r0, gs.begin() + r0 + nr));
     for (size_t r = 0; r < nr; r++) {
-      out[where[r0 + r]] = moddown(h[r]);
+      out[where[r0 + r]] = moddown(h[r], -1, true);
       h[r] = HeCt();
     }
   }
@@ -1012,14 +1041,14 @@ HeCt HeCtxImpl::stack(const std::vector<const HeCt*>& xs) {
       fail(HE_EINVAL, "batched members must share level and scale");
   HeCt c = ct_new(x0.level, false, x0.scale, (int)xs.size());
   for (size_t b = 0; b < xs.size(); b++)
-    for (int p = 0; p < 2; p++) copy_limbs(c.member(p, (int)b), xs[b]->poly(p), x0.nlimbs);
+    for (int p = 0; p < 2; p++) copy_limbs(c.member(p, (int)b), xs[b]->poly(p), x0.nlimbs, "copy_stack");
   return c;
 }
 std::vector<HeCt> HeCtxImpl::unstack(const HeCt& x) {
   std::vector<HeCt> out;
   for (int b = 0; b < x.B; b++) {
     HeCt c = ct_new(x.level, x.qp, x.scale, 1);
-    for (int p = 0; p < 2; p++) copy_limbs(c.poly(p), x.member(p, b), x.nlimbs);
+    for (int p = 0; p < 2; p++) copy_limbs(c.poly(p), x.member(p, b), x.nlimbs, "copy_unstack");
     out.push_back(std::move(c));
   }
   return out;
@@ -1277,7 +1306,7 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
       if (i == 0) {
         term = std::move(inner[g]);
       } else {
-        HeCt t = moddown(inner[g]);
+        HeCt t = moddown(inner[g], -1, true);
         inner[g] = HeCt();
         DevBuf d2 = decompose(t.poly(1), level, t.B);
         term = hoisted(t, d2.p, galois((long)G.a * n1 * i));
@@ -1290,7 +1319,7 @@ HeCt HeCtxImpl::lintrans_perm(const HeCt& x, const std::vector<int>& perm, const
       }
     }
   }
-  HeCt md = moddown(acc);
+  HeCt md = moddown(acc, -1, true);
   HeCt r = rescale(md);
   r.scale = x.scale;
   return r;
@@ -1506,9 +1535,9 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       HeCt sum = std::move(acc_k);
       const int ol = out_level >= 0 ? std::min(out_level, lvl - 1) : -1;
       if (fused_rs) {
-        Ak[k] = moddown_rescale(sum, ol);
+        Ak[k] = moddown_rescale(sum, ol, true);
       } else {
-        HeCt md = moddown(sum);
+        HeCt md = moddown(sum, -1, true);
         Ak[k] = rescale(md, ol);
       }
       Ak[k].scale = Bb.scale;
@@ -1536,7 +1565,7 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int n
     }
     Bk[b * n1t] = ol < lvl ? drop(Cb, ol) : ct_copy(Cb);
     for (int r = 1; r < nr; r++) {
-      Bk[b * n1t + r] = moddown(hs[r - 1], ol);
+      Bk[b * n1t + r] = moddown(hs[r - 1], ol, true);
       hs[r - 1] = HeCt();
     }
   }
