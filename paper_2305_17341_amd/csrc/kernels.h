@@ -107,6 +107,13 @@ void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64
 // ModDown's conversion fused into the forward NTT of the Q limbs (the tail
 // (x - y) P^-1 in its block pass): scratch y [npoly][nq][N] and V
 // [npoly][ns + 1][N]; false when the ring size has no register-blocked NTT
+// Inverse NTT, in place, of the same limbs of many R_{Q_l P} elements (the
+// ModDown sources of a set of hoisted rotations): in element e (bases[e]),
+// limb j < per_elem lives at slot (j / per) * stride + off + j % per; map
+// gives the modulus of limb j by j % map.n (map.n = per).  One launch per 64
+// elements.
+void launch_intt_many(const DeviceTables& T, const std::vector<u64*>& bases, int per_elem, int per, int stride,
+                      int off, const LimbMap& map, hipStream_t s);
 // xp_coef: the source limbs in the coefficient domain, [npoly][ns][N]; or,
 // with src_stride > 0, limb a of poly p at slot p * src_stride + src_off + a
 // (the sources transformed in place inside the R_{Q_l P} element)

@@ -936,6 +936,60 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2(u64* data, LimbMap map, const
   }
 }
 
+// The inverse passes over limbs of many elements (launch_intt_many): the
+// kernels of k_ntt_rows2 / k_ntt_cols2 with the limb's address taken from a
+// table of element bases
+struct LimbBases {
+  u64* base[MR_MAX];
+  int per_elem, per, stride, off;
+};
+__device__ __forceinline__ u64* limb_base_addr(const LimbBases& lb, int k, u64 N) {
+  const int e = k / lb.per_elem, j = k - e * lb.per_elem;
+  return lb.base[e] + ((size_t)(j / lb.per) * lb.stride + lb.off + j % lb.per) * N;
+}
+template <int LOGN, int GA, int GB>
+__global__ void __launch_bounds__(TPB) k_intt_cols2_many(LimbBases lb, LimbMap map, const u64* __restrict__ tw,
+                                                         const u64* __restrict__ twsh, const double* __restrict__ twf,
+                                                         const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, C = TILE / R;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << LOGN;
+  u64* a = limb_base_addr(lb, limb, N);
+  const int c0 = blockIdx.x * C;
+  const ModConst mk = mc[m];
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
+    ntt_cols2_body<LOGN, GA, GB, true>(a, c0, reinterpret_cast<double*>(sh), ar, LoadPlain{a});
+  } else {
+    ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_cols2_body<LOGN, GA, GB, true>(a, c0, sh, ar, LoadPlain{a});
+  }
+}
+template <int LOGN, int GC, int GD>
+__global__ void __launch_bounds__(TPB) k_intt_rows2_many(LimbBases lb, LimbMap map, const u64* __restrict__ tw,
+                                                         const u64* __restrict__ twsh, const double* __restrict__ twf,
+                                                         const ModConst* __restrict__ mc, int il) {
+  constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = grid_limb(blockIdx.y, il);
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << LOGN;
+  const int blk0 = blockIdx.x * K;
+  u64* a = limb_base_addr(lb, limb, N) + (size_t)blk0 * T1;
+  const ModConst mk = mc[m];
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
+    ntt_rows2_body<LOGN, GC, GD, true>(a, blk0, reinterpret_cast<double*>(sh), ar, StorePlain<F64LazyArith>{a, ar});
+  } else {
+    ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_rows2_body<LOGN, GC, GD, true>(a, blk0, sh, ar, StorePlain<ShoupArith>{a, ar});
+  }
+}
+
 // Forward block pass whose stores are the SubScale tail: data holds npoly x
 // nq limbs y (column pass done), x [npoly][x_stride][N], c pairs (value,
 // Shoup companion) per limb t < nq, out [npoly][nq][N].
@@ -1160,12 +1214,49 @@ static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& ma
   }
 }
 
+template <int LOGN, int GA, int GB, int GC, int GD>
+static void intt2_many(const DeviceTables& T, const LimbBases& lb, int nelem, const LimbMap& map, hipStream_t s) {
+  constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
+  const int nlimbs = nelem * lb.per_elem;
+  dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
+  // the modulus pattern repeats every `per` limbs, and per_elem is a multiple of it
+  const int il = interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave);
+  const double pass_bytes = 16.0 * nlimbs * T.N;
+  {
+    ProfScope ps("ntt_inv_rows", s, pass_bytes, mm_map(T, map, nlimbs, 0.5 * T.N * (GC + GD)));
+    hipLaunchKernelGGL((k_intt_rows2_many<LOGN, GC, GD>), gr, dim3(TPB), 0, s, lb, map, T.ipsi, T.ipsi_sh, T.ipsi_f,
+                       T.mc, il);
+  }
+  ProfScope ps("ntt_inv_cols", s, pass_bytes, mm_map(T, map, nlimbs, 0.5 * T.N * (GA + GB)));
+  hipLaunchKernelGGL((k_intt_cols2_many<LOGN, GA, GB>), gc, dim3(TPB), 0, s, lb, map, T.ipsi, T.ipsi_sh, T.ipsi_f,
+                     T.mc);
+}
+
 static bool ntt_register_blocked(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse,
                                  double pass_bytes, hipStream_t s) {
   return ntt_dispatch(T.logN, [&](auto sp) {
     using S = decltype(sp);
     ntt2<NTT_SPLIT_ARGS>(T, data, nlimbs, map, inverse, pass_bytes, s);
   });
+}
+
+void launch_intt_many(const DeviceTables& T, const std::vector<u64*>& bases, int per_elem, int per, int stride,
+                      int off, const LimbMap& map, hipStream_t s) {
+  if (map.n != per || per_elem % per != 0) throw std::runtime_error("launch_intt_many: bad limb pattern");
+  for (size_t e0 = 0; e0 < bases.size(); e0 += MR_MAX) {
+    const int ne = (int)std::min(bases.size() - e0, (size_t)MR_MAX);
+    LimbBases lb;
+    for (int e = 0; e < MR_MAX; e++) lb.base[e] = e < ne ? bases[e0 + e] : nullptr;
+    lb.per_elem = per_elem;
+    lb.per = per;
+    lb.stride = stride;
+    lb.off = off;
+    if (!ntt_dispatch(T.logN, [&](auto sp) {
+          using S = decltype(sp);
+          intt2_many<NTT_SPLIT_ARGS>(T, lb, ne, map, s);
+        }))
+      throw std::runtime_error("launch_intt_many needs the register-blocked NTT (log N 12..16)");
+  }
 }
 
 // Each pass streams every active limb in and out once: 16 bytes per coefficient.

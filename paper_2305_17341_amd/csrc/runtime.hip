@@ -821,18 +821,19 @@ void HeCtxImpl::hoisted_masked(const HeCt& x, const u64* digits, const std::vect
 
 // ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact
 // centred residue; out_level < l keeps (and computes) only the limbs up to it
-HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume) {
+HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume, bool src_ready) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   if (out_level < 0) out_level = x.level;
   if (out_level > x.level) fail(HE_ELEVEL, "moddown cannot raise the level");
   HeCt c = ct_new(out_level, false, x.scale, x.B);
-  moddown_to(x, out_level, c.d.p, consume);
+  moddown_to(x, out_level, c.d.p, consume, src_ready);
   return c;
 }
 // the same into out [2][B][out_level + 1][N].  consume: x's special-prime
 // limbs are brought to the coefficient domain in place (x is left with them
-// so) instead of in a gathered copy
-void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume) {
+// so) instead of in a gathered copy; src_ready: that was done already
+// (moddown_sources over a set of elements)
+void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume, bool src_ready) {
   int nq = nq_of(out_level), nqp = nqp_of(x.level);
   const int np = (int)x.polys();
   DevBuf y(&pool, (size_t)np * nq * N);
@@ -843,7 +844,7 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume)
     pm.slot_per = (short)alpha;
     pm.slot_stride = (short)x.nlimbs;
     pm.slot_off = (short)nq_of(x.level);
-    launch_ntt(T, x.d.p, np * alpha, pm, true, stream);
+    if (!src_ready) launch_ntt(T, x.d.p, np * alpha, pm, true, stream);
     DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
     if (!launch_moddown_fused(T, x.d.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream, x.nlimbs,
                               nq_of(x.level)))
@@ -869,7 +870,7 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume)
 // round(x / (P q_l)) in R_{Q_{l-1}} (or a lower out_level: only the kept
 // limbs are computed): the exact centred lift of x mod P q_l from the limbs
 // q_l, p_1..p_alpha, then (x - lift) (P q_l)^-1 on the limbs below q_l.
-HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume) {
+HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool src_ready) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   const int l = x.level;
   if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
@@ -890,7 +891,7 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume) {
     sm.slot_per = (short)ns;
     sm.slot_stride = (short)x.nlimbs;
     sm.slot_off = (short)l;
-    launch_ntt(T, x.d.p, np * ns, sm, true, stream);
+    if (!src_ready) launch_ntt(T, x.d.p, np * ns, sm, true, stream);
     DevBuf y(&pool, (size_t)np * nout * N);
     HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
     DevBuf V(&pool, (size_t)np * (ns + 1) * N);
@@ -920,6 +921,32 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume) {
   }
   n_moddown += x.B;
   return c;
+}
+
+// The ModDown sources of a set of R_{Q_l P} elements of one level and batch,
+// brought to the coefficient domain in place by one launch per 64 elements:
+// the special-prime limbs, and q_l too when the ModDown is fused with the
+// Rescale.  The elements are then ModDown'ed with consume and src_ready.
+void HeCtxImpl::moddown_sources(const std::vector<HeCt*>& xs, bool with_rescale) {
+  if (xs.empty() || !fused_conv) return;
+  const HeCt& x0 = *xs[0];
+  std::vector<u64*> bases;
+  for (HeCt* x : xs) {
+    if (!x->qp || x->level != x0.level || x->B != x0.B) fail(HE_EINVAL, "moddown sources of unlike elements");
+    bases.push_back(x->d.p);
+  }
+  const int l = x0.level, np = (int)x0.polys();
+  LimbMap m;
+  if (with_rescale) {
+    m.n = alpha + 1;
+    m.idx[0] = (short)l;
+    for (int k = 0; k < alpha; k++) m.idx[1 + k] = (short)(L + 1 + k);
+    launch_intt_many(T, bases, np * (alpha + 1), alpha + 1, x0.nlimbs, l, m, stream);
+  } else {
+    m.n = alpha;
+    for (int k = 0; k < alpha; k++) m.idx[k] = (short)(L + 1 + k);
+    launch_intt_many(T, bases, np * alpha, alpha, x0.nlimbs, nq_of(l), m, stream);
+  }
 }
 
 HeCt HeCtxImpl::keyswitch(const u64* d, int level, u64 g_key, int B) {
@@ -1522,22 +1549,29 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       hoisted_masked(Bpb, d2.p, gs, outs, m2, true);
       if (b > 0) lift2 = hoisted(Bpb, d2.p, 1);  // k = 0 has no second term
     }
+    {
+      // r = 0: the P-lifts times their masks
+      const int k = b * n1z;
+      const u64* ta[2] = {lift1.d.p, k > 0 ? lift2.d.p : nullptr};
+      const u64* tp[2] = {mask_of(k, 0), mask_of(k, 1)};
+      launch_mul_sum(T, acc[0].d.p, ta, tp, k > 0 ? 2 : 1, 2 * Bb.B * nqp, nqp, qpm, false, stream);
+      lift1 = HeCt();
+      lift2 = HeCt();
+    }
+    {
+      std::vector<HeCt*> srcs;
+      for (auto& a : acc) srcs.push_back(&a);
+      moddown_sources(srcs, fused_rs);
+    }
+    const bool ready = fused_conv;
     for (int r = 0; r < nr; r++) {
       int k = b * n1z + r;
-      HeCt& acc_k = acc[r];
-      if (r == 0) {
-        const u64* ta[2] = {lift1.d.p, k > 0 ? lift2.d.p : nullptr};
-        const u64* tp[2] = {mask_of(k, 0), mask_of(k, 1)};
-        launch_mul_sum(T, acc_k.d.p, ta, tp, k > 0 ? 2 : 1, 2 * Bb.B * nqp, nqp, qpm, false, stream);
-        lift1 = HeCt();
-        lift2 = HeCt();
-      }
-      HeCt sum = std::move(acc_k);
+      HeCt sum = std::move(acc[r]);
       const int ol = out_level >= 0 ? std::min(out_level, lvl - 1) : -1;
       if (fused_rs) {
-        Ak[k] = moddown_rescale(sum, ol, true);
+        Ak[k] = moddown_rescale(sum, ol, true, ready);
       } else {
-        HeCt md = moddown(sum, -1, true);
+        HeCt md = moddown(sum, -1, true, ready);
         Ak[k] = rescale(md, ol);
       }
       Ak[k].scale = Bb.scale;
@@ -1564,8 +1598,13 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int n
       hs = hoisted_multi(Cb, d1.p, gs);
     }
     Bk[b * n1t] = ol < lvl ? drop(Cb, ol) : ct_copy(Cb);
+    {
+      std::vector<HeCt*> srcs;
+      for (auto& h : hs) srcs.push_back(&h);
+      moddown_sources(srcs, false);
+    }
     for (int r = 1; r < nr; r++) {
-      Bk[b * n1t + r] = moddown(hs[r - 1], ol, true);
+      Bk[b * n1t + r] = moddown(hs[r - 1], ol, true, fused_conv);
       hs[r - 1] = HeCt();
     }
   }
