@@ -27,6 +27,7 @@ struct ModConst {
   u64 ninv_sh; // Shoup companion floor(ninv * 2^64 / q)
   u64 r64;     // 2^64 mod q
   u64 r64_sh;
+  u64 r96;     // 2^96 mod q
   double qf;   // q and 1/q as doubles (FP64 path, q < 2^50)
   double qinvf;
 };

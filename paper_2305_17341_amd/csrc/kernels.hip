@@ -2364,35 +2364,43 @@ __device__ __forceinline__ void multsum_rot_group(const MultiRot& R, int r0, int
         s1[g][b] += f64_mulmod_signed(d[b], ka[g], q, qi);
       }
   }
-  // c0 P on the Q limbs, once for the group
-  u64 cp[MB];
+  // c0 P on the Q limbs, once for the group.  The epilogue stays in the
+  // lazy FP64 domain: a sum of beta terms below q in absolute value, plus
+  // c0 P in [0, q), is within 16 q for beta <= 15 (centred first otherwise),
+  // so the mask product applies to it directly; with the old output added the
+  // value is within 2 q, and one reduction gives the residue in [0, q).
+  double cpd[MB];
 #pragma unroll
   for (int b = 0; b < MB; b++)
-    cp[b] = (c0 && pos < nq) ? mul_const_any(c0[((size_t)(b0 + b) * nq + pos) * N + src], pmod[2 * m], pmod[2 * m + 1], mk)
-                             : 0;
+    cpd[b] = (c0 && pos < nq)
+                 ? u2d(mul_const_any(c0[((size_t)(b0 + b) * nq + pos) * N + src], pmod[2 * m], pmod[2 * m + 1], mk))
+                 : 0.0;
 #pragma unroll
   for (int g = 0; g < RPW; g++) {
     if (g >= nr) break;
     const int r = r0 + g;
     const u64* mask = R.mask[r];
     const u32 i = idx[g];
-    const u64 mv = mask ? mask[(size_t)pos * N + i] : 0;
+    const double mv = mask ? u2d(mask[(size_t)pos * N + i]) : 0.0;
 #pragma unroll
     for (int b = 0; b < MB; b++) {
-      u64 v0 = d2u(f64_canon(s0[g][b], q, qi)), v1 = d2u(f64_canon(s1[g][b], q, qi));
-      if (c0 && pos < nq) v0 = add_mod(v0, cp[b], mk.q);
+      double a0 = s0[g][b] + cpd[b], a1 = s1[g][b];
       u64* o0 = &R.out[r][((size_t)(b0 + b) * nqp + pos) * N + i];
       u64* o1 = &R.out[r][((size_t)(B + b0 + b) * nqp + pos) * N + i];
       if (mask) {
-        v0 = mul_mod_any(v0, mv, mk);
-        v1 = mul_mod_any(v1, mv, mk);
+        if (beta > 15) {
+          a0 = f64_centre(a0, q, qi);
+          a1 = f64_centre(a1, q, qi);
+        }
+        a0 = f64_mulmod_signed(a0, mv, q, qi);
+        a1 = f64_mulmod_signed(a1, mv, q, qi);
         if (R.accumulate) {
-          v0 = add_mod(v0, *o0, mk.q);
-          v1 = add_mod(v1, *o1, mk.q);
+          a0 += u2d(*o0);
+          a1 += u2d(*o1);
         }
       }
-      stnt(o0, v0);
-      stnt(o1, v1);
+      stnt(o0, d2u(f64_canon(a0, q, qi)));
+      stnt(o1, d2u(f64_canon(a1, q, qi)));
     }
   }
 }
@@ -2414,6 +2422,30 @@ __device__ __forceinline__ void split20(u64 x, double& x0, double& x1, double& x
   x1 = u2d((x >> 20) & PIECE20);
   x2 = u2d(x >> 40);
 }
+// x = hi 2^64 + lo (hi < 2^62) mod q for 2^46 < q < 2^61: the high word's
+// halves are folded with 2^96 and 2^64 mod q into Y < 2^95, Y's quotient by q
+// (below 2^49) is estimated in FP64, off by at most one since Y's relative
+// rounding is 2^-51, and the remainder, in (-q, 2q), is computed in 64-bit
+// words and corrected once.
+__device__ __forceinline__ u64 reduce128_est(u64 lo, u64 hi, const ModConst& m) {
+  u64 y0 = lo, y1 = 0;
+  auto mac = [&](u64 a, u64 r) {  // (y1, y0) += a r, a < 2^32
+    const u64 l = a * (r & 0xffffffffull), h = a * (r >> 32);
+    const u64 hl = h << 32;
+    u64 s = y0 + l;
+    y1 += (s < l ? 1 : 0) + (h >> 32);
+    y0 = s + hl;
+    y1 += y0 < hl ? 1 : 0;
+  };
+  mac(hi >> 32, m.r96);
+  mac(hi & 0xffffffffull, m.r64);
+  const double yd = __fma_rn((double)y1, 0x1p64, (double)y0);
+  const u64 k = (u64)__builtin_floor(yd * m.qinvf);
+  long long r = (long long)(y0 - k * m.q);
+  if (r < 0) r += (long long)m.q;
+  else if ((u64)r >= m.q) r -= (long long)m.q;
+  return (u64)r;
+}
 __device__ __forceinline__ u64 fold_pieces(const double* S, const ModConst& mk) {
   u64 lo = d2u(S[0]), hi = 0;
 #pragma unroll
@@ -2424,7 +2456,7 @@ __device__ __forceinline__ u64 fold_pieces(const double* S, const ModConst& mk) 
     lo += l;
     hi += h + (lo < l ? 1 : 0);
   }
-  return u128_reduce(U128{lo, hi}, mk);
+  return reduce128_est(lo, hi, mk);
 }
 template <int MB>
 __device__ __forceinline__ void multsum_int_pass(const MultiRot& R, int r, u32 i, const u64* __restrict__ dig,

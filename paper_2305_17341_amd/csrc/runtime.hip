@@ -378,6 +378,7 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
     k.ninv_sh = shoup_pre(k.ninv, q);
     k.r64 = (u64)(((u128)1 << 64) % q);
     k.r64_sh = shoup_pre(k.r64, q);
+    k.r96 = (u64)(((u128)k.r64 << 32) % q);
     k.qf = (double)q;
     k.qinvf = 1.0 / k.qf;
     u64 w = root_2n(q, logN), wi = hinv(w, q);
