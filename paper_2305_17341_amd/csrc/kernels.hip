@@ -1493,65 +1493,101 @@ struct SumMulti {
   const u64* p[SUM_MAX_OUTS][SUM_MAX_TERMS];
   u64* out[SUM_MAX_OUTS];
 };
-template <int G>
+// V = 2: two consecutive coefficients per thread, 16-byte loads and stores
+template <int G, int V>
 __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map, int logN,
                                 const ModConst* __restrict__ mc, int il) {
   const u64 N = 1ull << logN;
   int blk, k;
-  block_limb(il, b_limbs, (int)(N / TPB), blk, k);
-  u32 i = blk * TPB + threadIdx.x;
+  block_limb(il, b_limbs, (int)(N / (TPB * V)), blk, k);
+  const u32 i = (blk * TPB + threadIdx.x) * V;
   if (i >= N) return;
   int m = limb_mod(map, k);
   if (m < 0) return;
   const ModConst mk = mc[m];
   const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
+  struct W {
+    u64 v[V];
+  };
+  auto ld = [](const u64* p) {
+    W w;
+    if (V == 2) {
+      const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(p);
+      w.v[0] = x.x;
+      w.v[V - 1] = x.y;
+    } else {
+      w.v[0] = *p;
+    }
+    return w;
+  };
   // software-pipelined over the terms
-  u64 xn = t.a[0][o], pn[G];
+  W xn = ld(t.a[0] + o), pn[G];
 #pragma unroll
-  for (int g = 0; g < G; g++) pn[g] = t.p[g][0] ? t.p[g][0][op] : 0;
+  for (int g = 0; g < G; g++) pn[g] = t.p[g][0] ? ld(t.p[g][0] + op) : W{};
+  u64 res[G][V];
   if (mk.bits <= F64_LAZY_BITS) {
     // signed exact products summed per output (at most 64), reduced once
     const double q = mk.qf, qi = mk.qinvf;
-    double acc[G];
+    double acc[G][V];
 #pragma unroll
-    for (int g = 0; g < G; g++) acc[g] = 0.0;
+    for (int g = 0; g < G; g++)
+#pragma unroll
+      for (int e = 0; e < V; e++) acc[g][e] = 0.0;
     for (int j = 0; j < nterms; j++) {
-      const double x = u2d(xn);
-      u64 pv[G];
+      double x[V];
+#pragma unroll
+      for (int e = 0; e < V; e++) x[e] = u2d(xn.v[e]);
+      W pv[G];
 #pragma unroll
       for (int g = 0; g < G; g++) pv[g] = pn[g];
       if (j + 1 < nterms) {
-        xn = t.a[j + 1][o];
+        xn = ld(t.a[j + 1] + o);
 #pragma unroll
-        for (int g = 0; g < G; g++) pn[g] = t.p[g][j + 1] ? t.p[g][j + 1][op] : 0;
+        for (int g = 0; g < G; g++) pn[g] = t.p[g][j + 1] ? ld(t.p[g][j + 1] + op) : W{};
       }
 #pragma unroll
       for (int g = 0; g < G; g++)
-        if (t.p[g][j]) acc[g] += f64_mulmod_signed(x, u2d(pv[g]), q, qi);
-    }
+        if (t.p[g][j])
 #pragma unroll
-    for (int g = 0; g < G; g++) t.out[g][o] = d2u(f64_canon(acc[g], q, qi));
-    return;
-  }
-  u64 acc[G];
-#pragma unroll
-  for (int g = 0; g < G; g++) acc[g] = 0;
-  for (int j = 0; j < nterms; j++) {
-    const u64 x = xn;
-    u64 pv[G];
-#pragma unroll
-    for (int g = 0; g < G; g++) pv[g] = pn[g];
-    if (j + 1 < nterms) {
-      xn = t.a[j + 1][o];
-#pragma unroll
-      for (int g = 0; g < G; g++) pn[g] = t.p[g][j + 1] ? t.p[g][j + 1][op] : 0;
+          for (int e = 0; e < V; e++) acc[g][e] += f64_mulmod_signed(x[e], u2d(pv[g].v[e]), q, qi);
     }
 #pragma unroll
     for (int g = 0; g < G; g++)
-      if (t.p[g][j]) acc[g] = add_mod(acc[g], mul_mod_any(x, pv[g], mk), mk.q);
+#pragma unroll
+      for (int e = 0; e < V; e++) res[g][e] = d2u(f64_canon(acc[g][e], q, qi));
+  } else {
+#pragma unroll
+    for (int g = 0; g < G; g++)
+#pragma unroll
+      for (int e = 0; e < V; e++) res[g][e] = 0;
+    for (int j = 0; j < nterms; j++) {
+      const W x = xn;
+      W pv[G];
+#pragma unroll
+      for (int g = 0; g < G; g++) pv[g] = pn[g];
+      if (j + 1 < nterms) {
+        xn = ld(t.a[j + 1] + o);
+#pragma unroll
+        for (int g = 0; g < G; g++) pn[g] = t.p[g][j + 1] ? ld(t.p[g][j + 1] + op) : W{};
+      }
+#pragma unroll
+      for (int g = 0; g < G; g++)
+        if (t.p[g][j])
+#pragma unroll
+          for (int e = 0; e < V; e++) res[g][e] = add_mod(res[g][e], mul_mod_any(x.v[e], pv[g].v[e], mk), mk.q);
+    }
   }
 #pragma unroll
-  for (int g = 0; g < G; g++) t.out[g][o] = acc[g];
+  for (int g = 0; g < G; g++) {
+    if (V == 2) {
+      ulonglong2 y;
+      y.x = res[g][0];
+      y.y = res[g][V - 1];
+      *reinterpret_cast<ulonglong2*>(t.out[g] + o) = y;
+    } else {
+      t.out[g][o] = res[g][0];
+    }
+  }
 }
 bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, const u64* const* a,
                           const u64* const* p /* [nouts][nterms], null = absent */, int nterms, int nl, int bl,
@@ -1570,13 +1606,22 @@ bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, co
   ProfScope ps("elementwise", s, 8.0 * T.N * ((double)nl * (nterms + nouts) + (double)bl * present),
                mm_map(T, m, nl, (double)T.N * present));
   int il;
-  dim3 grid = sum_grid((int)cdiv(T.N, TPB), nl, bl, g_knobs.ew_interleave, il);
+  // two coefficients per thread where the ring fills whole work-groups
+  const bool v2 = T.N >= (u64)(2 * TPB);
+  dim3 grid = sum_grid((int)cdiv(T.N, TPB * (v2 ? 2 : 1)), nl, bl, g_knobs.ew_interleave, il);
+#define MSM_CASE(G)                                                                                              \
+  case G:                                                                                                        \
+    if (v2) hipLaunchKernelGGL((k_mul_sum_multi<G, 2>), grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); \
+    else hipLaunchKernelGGL((k_mul_sum_multi<G, 1>), grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il);   \
+    break;
   switch (nouts) {
-    case 1: hipLaunchKernelGGL(k_mul_sum_multi<1>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
-    case 2: hipLaunchKernelGGL(k_mul_sum_multi<2>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
-    case 3: hipLaunchKernelGGL(k_mul_sum_multi<3>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
-    default: hipLaunchKernelGGL(k_mul_sum_multi<4>, grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); break;
+    MSM_CASE(1) MSM_CASE(2) MSM_CASE(3)
+    default:
+      if (v2) hipLaunchKernelGGL((k_mul_sum_multi<4, 2>), grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il);
+      else hipLaunchKernelGGL((k_mul_sum_multi<4, 1>), grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il);
+      break;
   }
+#undef MSM_CASE
   return true;
 }
 
