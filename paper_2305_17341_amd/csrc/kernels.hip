@@ -2041,7 +2041,8 @@ struct FbcLoad : FbcData {
     w.r = v0[(size_t)ns * N + idx];
   }
   __device__ __forceinline__ double sum_f64(const Raw& w) const {
-    double acc = -f64_mulmod_signed(u2d(w.r), e2, qf, qinvf);
+    // the quotient r is at most the source count: r D is exact (below 2^49)
+    double acc = -u2d(w.r) * e2;
 #pragma unroll
     for (int a = 0; a < NS; a++) {
       acc += f64_mulmod_signed(u2d(w.x[a] & 0xffffffffull), e0[a], qf, qinvf);
