@@ -513,9 +513,9 @@ def main():
                          for f in fams if prof[f][0] > 0},
         "roofline": roofline,
     }
-    # the recorded graph's arena and the pool's cached blocks go back to the
-    # device before the serving run sizes its budget from the free memory
-    ctx.trim()
+    # the headline's keys, recorded graph and pool go back to the device
+    # before the serving run sizes its budget from the free memory
+    ctx.close()
     if args.serve_jobs > 0:
         from paper_2305_17341_amd import serve
         log("[bench] serving run ...")

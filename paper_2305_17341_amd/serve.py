@@ -115,6 +115,7 @@ class Request:
     future: Future = field(default_factory=Future)
     state: object = None            # covariance in parts: the library's state
     cursor: int = 0                 # covariance in parts: row blocks done
+    cov_g: int = 0                  # covariance: row blocks stacked per batch (its footprint's g)
 
     @property
     def latency(self) -> float:
@@ -146,13 +147,23 @@ class HeBackend:
     def log_ns(self):
         return sorted(self.contexts)
 
-    def footprint(self, r: Request) -> int:
+    def footprint(self, r: Request, budget: int = 0) -> int:
+        """device bytes the request's computation allocates.  A covariance
+        stacks as many row blocks per batch (the library's cov_row_blocks,
+        halved down to 1) as keep it within half the budget, so that
+        products still find memory beside it."""
         ch = self.chains[r.log_n]
         if r.kind == "matmul":
             return product_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d)
         from . import he
         _, rb, k, _ = r.args
-        return covariance_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d, k, rb, he.knob_get("cov_row_blocks"))
+        g = he.knob_get("cov_row_blocks")
+        while True:
+            fp = covariance_footprint(r.log_n, ch.top_level, len(ch.p_bits), r.d, k, rb, g)
+            if g == 1 or not budget or 2 * fp <= budget:
+                r.cov_g = g
+                return fp
+            g = max(1, g // 2)
 
     def run(self, log_n: int, reqs):
         """Runs a merged batch of products, or the next chunk of a covariance
@@ -164,7 +175,13 @@ class HeBackend:
             if r.state is None:
                 r.state = ctx.covariance_begin(k, r.d, n_samples, opts={"flags": self.relin_flags})
             g = min(self.cov_chunk, rb - r.cursor)
-            r.state.add(blocks[r.cursor * k:(r.cursor + g) * k], g)
+            from . import he
+            old = he.knob_get("cov_row_blocks")
+            he.knob_set("cov_row_blocks", r.cov_g or old)
+            try:
+                r.state.add(blocks[r.cursor * k:(r.cursor + g) * k], g)
+            finally:
+                he.knob_set("cov_row_blocks", old)
             r.cursor += g
             if r.cursor < rb:
                 ctx.sync()
@@ -216,7 +233,7 @@ class Server:
         if log_n not in self._ready:
             raise ValueError(f"no context for N = 2^{log_n}")
         r = Request(kind, log_n, d, args)
-        r.footprint = self.backend.footprint(r)
+        r.footprint = self.backend.footprint(r, self.budget)
         r.t_submit = time.perf_counter()
         with self._cv:
             r.id = self._next_id

@@ -23,7 +23,7 @@ class FakeBackend:
     def log_ns(self):
         return self._log_ns
 
-    def footprint(self, r):
+    def footprint(self, r, budget=0):
         return r.d * 10
 
     def run(self, log_n, reqs):
