@@ -408,7 +408,11 @@ he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d,
  * multi-rotation launch: "mr_int_split" (0/1, default 1: in a kernel of their
  * own), "mr_int_pass" (4/8: members per pass of that kernel), "mr_int_chunk"
  * (1..64: rotations per dispatch chunk) and "mr_int_concurrent" (0/1, default
- * 0: that kernel on a second stream of the context, beside the FP64 one).
+ * 0: that kernel on a second stream of the context, beside the FP64 one);
+ * "fbc_mfma" (0/1, default 1: ModDown's basis conversion into targets of 33
+ * to 46 bits as an int8 matrix product of 7-bit digits, else six exact FP64
+ * products per value) and "xcd_map" (0/1, default 1: that lift's work-groups
+ * renumbered so that those of one polynomial run on one XCD and share its L2).
  * Set them between calls, not while
  * another thread drives the library.  The autotuner in the Python package
  * picks them by timing. */

@@ -99,6 +99,13 @@ struct FbcTable {
   double qd[8];
   u64* D_mod_t = nullptr;   // device [nmods][2]
   double* hat_f = nullptr;  // device [ns][nmods][3]: hat mod t, 2^32 hat mod t, D mod t (FP64 path)
+  // The lift as a dot product of 7-bit digits (ModDown tables only): the
+  // record of a coefficient holds digit i of source value a at byte 9 a + i
+  // and the quotient at byte 9 ns, in kw words; cdig [nmods][8][kw] holds,
+  // for target t and row j < 7, digit j of the constant of each record byte:
+  // hat_(a,t) 2^(7 i) mod q_t, and -D mod q_t for the quotient.
+  u64* cdig = nullptr;
+  int kw = 0;
 };
 // digits[j][pos] (pos over Q_l then P): own limbs copy ntt_in, others are the
 // coefficient-domain conversion of digit j (to be transformed by the caller)
@@ -117,6 +124,8 @@ void launch_intt_many(const DeviceTables& T, const std::vector<u64*>& bases, int
 // xp_coef: the source limbs in the coefficient domain, [npoly][ns][N]; or,
 // with src_stride > 0, limb a of poly p at slot p * src_stride + src_off + a
 // (the sources transformed in place inside the R_{Q_l P} element)
+// words per coefficient the fused ModDown's V must hold ([npoly][words][N])
+int fbc_record_words(const FbcTable& tab);
 bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                           const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
                           int src_stride = 0, int src_off = 0);

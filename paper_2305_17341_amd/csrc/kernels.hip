@@ -30,6 +30,8 @@ struct Knobs {
   int mr_int_chunk = 64;   // rotations per dispatch chunk of that kernel (1..64)
   int mr_int_concurrent = 0;  // that kernel on a forked stream, beside the FP64 one (0/1)
   int mr_group = 4;        // rotations per work-group of a multi-rotation launch, sharing the digit loads (1/2/4)
+  int fbc_mfma = 1;        // ModDown's lift as an int8 matrix product (0/1)
+  int xcd_map = 1;         // the MFMA lift's work-groups of one polynomial kept on one XCD (0/1)
   // stage split of the register-blocked NTT per ring size (index log N):
   // 0 = the default, 1 = one stage moved between the column and block passes
   int ntt_split[17] = {};
@@ -48,6 +50,8 @@ bool knob_set(const char* name, int v) {
   else if (n == "mr_int_pass" && (v == 4 || v == 8)) g_knobs.mr_int_pass = v;
   else if (n == "mr_int_chunk" && v >= 1 && v <= MR_MAX) g_knobs.mr_int_chunk = v;
   else if (n == "mr_int_concurrent" && (v == 0 || v == 1)) g_knobs.mr_int_concurrent = v;
+  else if (n == "fbc_mfma" && (v == 0 || v == 1)) g_knobs.fbc_mfma = v;
+  else if (n == "xcd_map" && (v == 0 || v == 1)) g_knobs.xcd_map = v;
   else if ((n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") && (v == 0 || v == 1))
     g_knobs.ntt_split[std::stoi(n.substr(10))] = v;
   else return false;
@@ -66,6 +70,8 @@ bool knob_get(const char* name, int* v) {
   else if (n == "mr_int_pass") *v = g_knobs.mr_int_pass;
   else if (n == "mr_int_chunk") *v = g_knobs.mr_int_chunk;
   else if (n == "mr_int_concurrent") *v = g_knobs.mr_int_concurrent;
+  else if (n == "fbc_mfma") *v = g_knobs.fbc_mfma;
+  else if (n == "xcd_map") *v = g_knobs.xcd_map;
   else if (n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") *v = g_knobs.ntt_split[std::stoi(n.substr(10))];
   else return false;
   return true;
@@ -2114,16 +2120,258 @@ __global__ void __launch_bounds__(TPB) k_ntt_cols2_fbc(u64* y, const u64* __rest
     ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, fbc_loader_of<FbcLoad<false>>(d));
   }
 }
+// ModDown's lift as an int8 matrix product.  k_fbc_prep_digits writes, per
+// coefficient, a record of kw words: byte 9 a + i is 7-bit digit i of the
+// source value v_a (nine digits cover 63 bits), byte 9 ns the rounded
+// quotient r, the rest zero.  For a target t the lift
+//   sum_a v_a hat_(a,t) - r D  =  sum_k x_k C_(k,t)    (mod q_t)
+// with x_k the record bytes and C_(k,t) = hat_(a,t) 2^(7 i) mod q_t (-D mod
+// q_t for the quotient); cutting each constant into seven 7-bit digits,
+//   S_j = sum_k x_k digit_j(C_(k,t))  < 37 * 127 * 127 < 2^19.2
+// is a dot product of bytes, and the lift is sum_j S_j 2^(7 j) mod q_t.
+struct FbcTgts {
+  short t[64];
+  int n;
+};
+// Work-groups are dispatched to the 8 XCDs in turn (work-group b to XCD
+// b % 8), and each XCD has its own L2.  With map set, the launch's first
+// 8 * floor(n / 8) work-groups are renumbered so that XCD x runs the x-th
+// contiguous range of logical work-groups (x-major, launch order kept within
+// it): work-groups that read the same data (the tiles of one polynomial)
+// share an L2.  The rest keep their numbers.
+__device__ __forceinline__ void xcd_remap(int& bx, int& by, int map) {
+  if (!map) return;
+  const int gx = gridDim.x, nb = gx * gridDim.y, per = nb >> 3;
+  const int b = by * gx + bx;
+  if (b >= per * 8) return;
+  const int lb = (b & 7) * per + (b >> 3);
+  by = lb / gx;
+  bx = lb - by * gx;
+}
+template <int NS>
+struct FbcRec {
+  static constexpr int KB = 9 * NS + 1, KW = 2 * ((KB + 15) / 16);
+};
+template <int NS>
+__global__ void k_fbc_prep_digits(u64* V, const u64* xp, FbcArgs A, int logN, const ModConst* __restrict__ mc) {
+  constexpr int KW = FbcRec<NS>::KW;
+  const u64 N = 1ull << logN;
+  u32 i = blockIdx.x * TPB + threadIdx.x;
+  if (i >= N) return;
+  const int poly = blockIdx.y;
+  const u64* x = xp + ((size_t)poly * A.src_stride + A.src_off) * N;
+  u64* o = V + (size_t)poly * KW * N;
+  u64 v[4];
+#pragma unroll
+  for (int a = 0; a < NS; a++) v[a] = shoup_mul(x[(size_t)a * N + i], A.hatinv[a], A.hatinv_sh[a], mc[A.src[a]].q);
+  const u64 r = round_quotient(v, A);
+  u64 w[KW];
+#pragma unroll
+  for (int k = 0; k < KW; k++) w[k] = 0;
+#pragma unroll
+  for (int a = 0; a < NS; a++)
+#pragma unroll
+    for (int d = 0; d < 9; d++) {
+      const int k = 9 * a + d;
+      w[k >> 3] |= ((v[a] >> (7 * d)) & 127) << (8 * (k & 7));
+    }
+  w[(9 * NS) >> 3] |= r << (8 * ((9 * NS) & 7));
+#pragma unroll
+  for (int k = 0; k < KW; k++) o[(size_t)k * N + i] = w[k];
+}
+
+// The column pass of targets outside the FP64 path (and any target) from the
+// record: the source values are reassembled from their digits, then the
+// Shoup lift of FbcLoad<false>.
+template <int NS>
+struct FbcDigitLoad {
+  static constexpr int KW = FbcRec<NS>::KW;
+  struct Raw {
+    u64 w[KW];
+  };
+  const u64* v0;
+  u64 N;
+  u64 q, h[4], hs[4], D, Ds;
+  __device__ __forceinline__ void raw(size_t idx, Raw& r) const {
+#pragma unroll
+    for (int k = 0; k < KW; k++) r.w[k] = v0[(size_t)k * N + idx];
+  }
+  __device__ __forceinline__ static u64 byte(const Raw& r, int k) { return (r.w[k >> 3] >> (8 * (k & 7))) & 255; }
+  __device__ __forceinline__ u64 fin_u(const Raw& r) const {
+    u64 acc = 0;
+#pragma unroll
+    for (int a = 0; a < NS; a++) {
+      u64 v = 0;
+#pragma unroll
+      for (int d = 0; d < 9; d++) v |= byte(r, 9 * a + d) << (7 * d);
+      acc = add_mod(acc, shoup_mul(v, h[a], hs[a], q), q);
+    }
+    return sub_mod(acc, shoup_mul(byte(r, 9 * NS), D, Ds, q), q);
+  }
+};
+template <int LOGN, int GA, int GB, int NS>
+__global__ void __launch_bounds__(TPB) k_ntt_cols2_fbcd(u64* y, const u64* __restrict__ V, int nq, FbcTgts tg,
+                                                        FbcArgs A, const u64* __restrict__ tw,
+                                                        const u64* __restrict__ twsh, const double* __restrict__ twf,
+                                                        int nmods, const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, C = TILE / R, KW = FbcRec<NS>::KW;
+  __shared__ u64 sh[LDS_WORDS];
+  const int p = blockIdx.y / tg.n, t = tg.t[blockIdx.y - p * tg.n];
+  const u64 N = 1ull << LOGN;
+  u64* a = y + ((size_t)p * nq + t) * N;
+  const int c0 = blockIdx.x * C;
+  const ModConst mk = mc[t];
+  FbcDigitLoad<NS> ld;
+  ld.v0 = V + (size_t)p * KW * N;
+  ld.N = N;
+  ld.q = mk.q;
+  ld.D = A.D_mod_t[2 * t];
+  ld.Ds = A.D_mod_t[2 * t + 1];
+#pragma unroll
+  for (int x = 0; x < NS; x++) {
+    ld.h[x] = A.hat_t[(size_t)x * nmods + t];
+    ld.hs[x] = A.hat_t_sh[(size_t)x * nmods + t];
+  }
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)t * N, mk.qf, mk.qinvf, (double)mk.ninv};
+    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, ld);
+  } else {
+    ShoupArith ar{tw + (size_t)t * N, twsh + (size_t)t * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, ld);
+  }
+}
+
+typedef int mfma_i32x16 __attribute__((ext_vector_type(16)));
+// Two FP64 targets (33 to 46 bits) t0, t1 per work-group of 2 TPB threads.
+// v_mfma_i32_32x32x16_i8 takes, per lane l:
+//   A (32 x 16) row i = l % 32, bytes k = 8 (l / 32) + 0..7: rows 0-3 and
+//     8-11 hold digits 0-3 and 4-7 of t0's constants, rows 4-7 and 12-15
+//     those of t1 (row 7 of each is zero), rows 16-31 zero;
+//   B (16 x 32) column l % 32: the same bytes of a coefficient's record;
+//   D row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32,
+// so that register r < 7 of lane l is S_r of target t_(l / 32) for the
+// coefficient of column l % 32.  Lane i < 32 of wave w (both halves) takes
+// as its columns the values the column pass's thread 32 w + i loads (16 per
+// thread), and so ends holding that thread's values for target t_(l / 32):
+// the first stage group runs in registers, the second from the LDS tile of
+// the lane's target.
+template <int LOGN, int GA, int GB, int NS>
+__global__ void __launch_bounds__(2 * TPB) k_ntt_cols2_fbc_mfma(u64* y, const u64* __restrict__ V, int nq,
+                                                                FbcTgts tg, const u64* __restrict__ cdig,
+                                                                const double* __restrict__ twf,
+                                                                const ModConst* __restrict__ mc, int xcd_map) {
+  constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R, KW = FbcRec<NS>::KW;
+  constexpr int ITA = 16 >> GA, NA = 1 << GA, ITB = 16 >> GB;
+  __shared__ double sh[2][LDS_WORDS];
+  const int npair = (tg.n + 1) >> 1;
+  int bx = blockIdx.x, by = blockIdx.y;
+  xcd_remap(bx, by, xcd_map);
+  const int p = by / npair, pr = by - p * npair;
+  const int t0 = tg.t[2 * pr];
+  const bool has1 = 2 * pr + 1 < tg.n;
+  const int t1 = has1 ? tg.t[2 * pr + 1] : t0;
+  const u64 N = 1ull << LOGN;
+  const int c0 = bx * C;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, hl = lane >> 5, i = lane & 31;
+  const int tid = 32 * wave + i;  // the column-pass thread this lane stands for
+  const int t = hl ? t1 : t0;
+  const ModConst mk = mc[t];
+  const F64LazyArith ar{twf + (size_t)t * N, mk.qf, mk.qinvf, (double)mk.ninv};
+  double* tile = sh[hl];
+  {
+    const int ta = ((i >> 2) & 1) ? t1 : t0, j = (i & 3) + 4 * (i >> 3);
+    long aop[KW / 2];
+#pragma unroll
+    for (int m = 0; m < KW / 2; m++) aop[m] = i < 16 ? (long)cdig[((size_t)ta * 8 + j) * KW + 2 * m + hl] : 0;
+    const u64* rec = V + (size_t)p * KW * N + (size_t)hl * N;
+#pragma unroll
+    for (int k = 0; k < ITA; k++) {
+      const int it = tid + TPB * k, c = it % C, rl = it / C;
+      double v[16];
+#pragma unroll
+      for (int m0 = 0; m0 < NA; m0 += 4) {
+        long b[4][KW / 2];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const size_t idx = (size_t)(rl + ((m0 + u) << GB)) * T1 + c0 + c;
+#pragma unroll
+          for (int m = 0; m < KW / 2; m++) b[u][m] = (long)rec[(size_t)(2 * m) * N + idx];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          mfma_i32x16 acc = {};
+#pragma unroll
+          for (int m = 0; m < KW / 2; m++)
+            acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(aop[m], b[u][m], acc, 0, 0, 0);
+          // sum_j S_j 2^(7 j) = P_hi 2^21 + P_lo, S_j < 2^19.2: the 32-bit
+          // pairs S_2m + 2^7 S_(2m+1) < 2^26.3, then P_hi < q (the digits of
+          // a constant below q end below bit log2 q) and P_lo < 2^33.3, both
+          // exact; one signed product by 2^21 and one centring
+          const int s01 = acc[0] + (acc[1] << 7), s34 = acc[3] + (acc[4] << 7), s56 = acc[5] + (acc[6] << 7);
+          const double ph = (double)s56 * 0x1p14 + (double)s34;
+          const double pl = (double)acc[2] * 0x1p14 + (double)s01;
+          v[m0 + u] = f64_centre(f64_mulmod_signed(ph, 0x1p21, ar.q, ar.qinv) + pl, ar.q, ar.qinv);
+        }
+      }
+      fwd_group<GA>(v, 0, 0u, ar);
+#pragma unroll
+      for (int mm = 0; mm < NA; mm++) tile[lds_rc(rl + (mm << GB), c, C)] = v[mm];
+    }
+  }
+  __syncthreads();
+  // second group: r bits [0, GB) -> stages GA..S1-1
+  const bool store = !hl || has1;
+  u64* a = y + ((size_t)p * nq + t) * N;
+#pragma unroll
+  for (int k = 0; k < ITB; k++) {
+    const int it = tid + TPB * k, c = it % C, rh = it / C;
+    double v[16];
+#pragma unroll
+    for (int mm = 0; mm < (1 << GB); mm++) v[mm] = tile[lds_rc((rh << GB) + mm, c, C)];
+    fwd_group<GB>(v, GA, (u32)rh, ar);
+    if (store)
+#pragma unroll
+      for (int mm = 0; mm < (1 << GB); mm++) a[(size_t)((rh << GB) + mm) * T1 + c0 + c] = ar.store(v[mm]);
+  }
+}
+
 template <int LOGN, int GA, int GB, int GC, int GD>
 static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const FbcArgs& A, int nq, int npoly,
-                          const LimbMap& map, const u64* x, int x_stride, const u64* pinv, u64* out, hipStream_t s) {
+                          const LimbMap& map, const u64* x, int x_stride, const u64* pinv, u64* out, hipStream_t s,
+                          const u64* cdig) {
   constexpr int R = 1 << (GA + GB), C = TILE / R;
-  dim3 gc((1 << LOGN) / R / C, nq * npoly);
   {
     ProfScope ps("ntt_fwd_cols_fbc", s, 8.0 * T.N * npoly * ((double)A.ns + 1 + nq),
                  mm_q(T, nq, 0.5 * T.N * (GA + GB) + (double)T.N * (A.ns + 1), npoly));
-    hipLaunchKernelGGL((k_ntt_cols2_fbc<LOGN, GA, GB>), gc, dim3(TPB), 0, s, y, V, nq, A, T.psi, T.psi_sh, T.psi_f,
-                       T.nmods, T.mc);
+    if (!cdig) {
+      dim3 gc((1 << LOGN) / R / C, nq * npoly);
+      hipLaunchKernelGGL((k_ntt_cols2_fbc<LOGN, GA, GB>), gc, dim3(TPB), 0, s, y, V, nq, A, T.psi, T.psi_sh,
+                         T.psi_f, T.nmods, T.mc);
+    } else {
+      // FP64 targets in pairs through the MFMA lift, the others one by one
+      FbcTgts f, o;
+      f.n = o.n = 0;
+      for (int t = 0; t < nq; t++) {
+        if (T.bits[t] > 32 && T.bits[t] <= F64_LAZY_BITS) f.t[f.n++] = (short)t;
+        else o.t[o.n++] = (short)t;
+      }
+      auto go = [&](auto ns) {
+        constexpr int NS = decltype(ns)::value;
+        if (f.n > 0)
+          hipLaunchKernelGGL((k_ntt_cols2_fbc_mfma<LOGN, GA, GB, NS>),
+                             dim3((1 << LOGN) / R / C, ((f.n + 1) / 2) * npoly), dim3(2 * TPB), 0, s, y, V, nq, f,
+                             cdig, T.psi_f, T.mc, g_knobs.xcd_map);
+        if (o.n > 0)
+          hipLaunchKernelGGL((k_ntt_cols2_fbcd<LOGN, GA, GB, NS>), dim3((1 << LOGN) / R / C, o.n * npoly),
+                             dim3(TPB), 0, s, y, V, nq, o, A, T.psi, T.psi_sh, T.psi_f, T.nmods, T.mc);
+      };
+      switch (A.ns) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 3: go(std::integral_constant<int, 3>{}); break;
+        default: go(std::integral_constant<int, 4>{}); break;
+      }
+    }
   }
   ntt2_fwd_sub<LOGN, GA, GB, GC, GD>(T, y, nq, npoly, map, x, x_stride, pinv, out, s, false);
 }
@@ -2150,20 +2398,27 @@ bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int
   A.hat_t_sh = tab.hat_t_sh;
   A.D_mod_t = tab.D_mod_t;
   A.hat_f = tab.hat_f;
+  const u64* cdig = g_knobs.fbc_mfma && tab.cdig && tab.kw > 0 && nq <= 64 ? tab.cdig : nullptr;
   {
     Mm mm;
     for (int a = 0; a < tab.ns; a++) mm.add(T.bits[tab.src[a]], (double)T.N * npoly);
     ProfScope ps("fbc_prep", s, 8.0 * T.N * npoly * (2.0 * tab.ns + 1), mm);
-    hipLaunchKernelGGL(k_fbc_prep, dim3(cdiv(T.N, TPB), npoly), dim3(TPB), 0, s, V, xp_coef, A, T.logN, T.mc);
+    dim3 gp(cdiv(T.N, TPB), npoly);
+    if (!cdig) hipLaunchKernelGGL(k_fbc_prep, gp, dim3(TPB), 0, s, V, xp_coef, A, T.logN, T.mc);
+    else if (tab.ns == 1) hipLaunchKernelGGL(k_fbc_prep_digits<1>, gp, dim3(TPB), 0, s, V, xp_coef, A, T.logN, T.mc);
+    else if (tab.ns == 2) hipLaunchKernelGGL(k_fbc_prep_digits<2>, gp, dim3(TPB), 0, s, V, xp_coef, A, T.logN, T.mc);
+    else if (tab.ns == 3) hipLaunchKernelGGL(k_fbc_prep_digits<3>, gp, dim3(TPB), 0, s, V, xp_coef, A, T.logN, T.mc);
+    else hipLaunchKernelGGL(k_fbc_prep_digits<4>, gp, dim3(TPB), 0, s, V, xp_coef, A, T.logN, T.mc);
   }
   LimbMap map;
   map.n = nq;
   for (int k = 0; k < nq; k++) map.idx[k] = (short)k;
   return ntt_dispatch(T.logN, [&](auto sp) {
     using S = decltype(sp);
-    moddown_fused<NTT_SPLIT_ARGS>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s);
+    moddown_fused<NTT_SPLIT_ARGS>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s, cdig);
   });
 }
+int fbc_record_words(const FbcTable& tab) { return tab.kw > tab.ns + 1 ? tab.kw : tab.ns + 1; }
 
 // out[p][t] = (x[p][t] - y[p][t]) * P^{-1} mod q_t   (p < npoly, t < nq)
 __global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, const u64* pinv, int x_stride_limbs,

@@ -326,6 +326,38 @@ static FbcTable make_fbc(HeCtxImpl* c, const std::vector<int>& src) {
   return t;
 }
 
+// Digit tables of the MFMA form of ModDown's lift (sources of at most 63
+// bits: nine 7-bit digits each; targets of at most 46 bits: seven digits).
+static void fbc_digits(HeCtxImpl* c, FbcTable& t) {
+  if (t.ns < 1 || t.ns > 4) return;
+  const int kb = 9 * t.ns + 1;
+  t.kw = 2 * ((kb + 15) / 16);
+  std::vector<u64> cd((size_t)c->nmods * 8 * t.kw, 0);
+  for (int m = 0; m < c->nmods; m++) {
+    const u64 qt = c->mods[m];
+    if (qt >> 46) continue;  // only targets of the FP64 path use the table
+    u64 d = 1;
+    for (int a = 0; a < t.ns; a++) d = hmul(d, c->mods[t.src[a]] % qt, qt);
+    for (int k = 0; k < kb; k++) {
+      u64 cst;
+      if (k == 9 * t.ns) {
+        cst = d == 0 ? 0 : qt - d;
+      } else {
+        const int a = k / 9, i = k % 9;
+        u64 h = 1;
+        for (int b = 0; b < t.ns; b++)
+          if (b != a) h = hmul(h, c->mods[t.src[b]] % qt, qt);
+        cst = hmul(h, (u64)(((u128)1 << (7 * i)) % qt), qt);
+      }
+      for (int j = 0; j < 7; j++) {
+        const u64 dig = (cst >> (7 * j)) & 127;
+        cd[((size_t)m * 8 + j) * t.kw + k / 8] |= dig << (8 * (k % 8));
+      }
+    }
+  }
+  t.cdig = c->table_upload(cd.data(), cd.size() * 8);
+}
+
 void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
   if (!p || p->log_n < 10 || p->log_n > 16) fail(HE_EINVAL, "log_n must be in [10, 16]");
   if (p->n_q < 1 || p->n_q > 48 || p->n_p < 1 || p->n_p > 4) fail(HE_EINVAL, "1..48 Q primes and 1..4 P primes");
@@ -450,6 +482,7 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
     std::vector<int> src;
     for (int k = 0; k < alpha; k++) src.push_back(L + 1 + k);
     down = make_fbc(this, src);
+    fbc_digits(this, down);
   }
   // ModDown + Rescale as one rounding: sources q_l and P (at most 4 limbs)
   if (alpha <= 3) {
@@ -458,6 +491,7 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
       std::vector<int> src{l};
       for (int k = 0; k < alpha; k++) src.push_back(L + 1 + k);
       down_rs[l] = make_fbc(this, src);
+      fbc_digits(this, down_rs[l]);
     }
   }
   // P mod q, P^{-1} mod q (Shoup pairs) and q_l^{-1} mod q_k
@@ -846,7 +880,7 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume,
     pm.slot_stride = (short)x.nlimbs;
     pm.slot_off = (short)nq_of(x.level);
     if (!src_ready) launch_ntt(T, x.d.p, np * alpha, pm, true, stream);
-    DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
+    DevBuf V(&pool, (size_t)np * fbc_record_words(down) * N);
     if (!launch_moddown_fused(T, x.d.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream, x.nlimbs,
                               nq_of(x.level)))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
@@ -857,7 +891,7 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume,
   gather_limbs(pc.p, x, nq_of(x.level), alpha);
   launch_ntt(T, pc.p, np * alpha, pm, true, stream);
   if (fused_conv) {
-    DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
+    DevBuf V(&pool, (size_t)np * fbc_record_words(down) * N);
     if (!launch_moddown_fused(T, pc.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
   } else {
@@ -895,7 +929,7 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool
     if (!src_ready) launch_ntt(T, x.d.p, np * ns, sm, true, stream);
     DevBuf y(&pool, (size_t)np * nout * N);
     HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
-    DevBuf V(&pool, (size_t)np * (ns + 1) * N);
+    DevBuf V(&pool, (size_t)np * fbc_record_words(tab) * N);
     if (!launch_moddown_fused(T, x.d.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, V.p, stream, x.nlimbs, l))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
     n_moddown += x.B;
@@ -913,7 +947,7 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool
   DevBuf y(&pool, (size_t)np * nout * N);
   HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
   if (fused_conv) {
-    DevBuf V(&pool, (size_t)np * (ns + 1) * N);
+    DevBuf V(&pool, (size_t)np * fbc_record_words(tab) * N);
     if (!launch_moddown_fused(T, pc.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, V.p, stream))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
   } else {
@@ -1017,7 +1051,7 @@ std::vector<HeCt> HeCtxImpl::rotate_many(const HeCt& x, const std::vector<long>&
 // rounded up to the pool's 256-byte granule
 size_t HeCtxImpl::rotate_workspace_bytes(int level, int B) const {
   const size_t nq = nq_of(level), nqp = nqp_of(level), bl = beta_at(level), np = 2 * (size_t)B;
-  const size_t blocks[] = {B * nq, B * bl * nqp, np * nqp, np * alpha, np * nq, np * (alpha + 1)};
+  const size_t blocks[] = {B * nq, B * bl * nqp, np * nqp, np * alpha, np * nq, np * (size_t)fbc_record_words(down)};
   size_t total = 0;
   for (size_t w : blocks) total += (w * N * 8 + 255) & ~(size_t)255;
   return total;
