@@ -124,8 +124,6 @@ void launch_intt_many(const DeviceTables& T, const std::vector<u64*>& bases, int
 // xp_coef: the source limbs in the coefficient domain, [npoly][ns][N]; or,
 // with src_stride > 0, limb a of poly p at slot p * src_stride + src_off + a
 // (the sources transformed in place inside the R_{Q_l P} element)
-// words per coefficient the fused ModDown's V must hold ([npoly][words][N])
-int fbc_record_words(const FbcTable& tab);
 bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                           const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
                           int src_stride = 0, int src_off = 0);

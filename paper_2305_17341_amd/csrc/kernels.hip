@@ -698,6 +698,47 @@ __device__ __forceinline__ void fetch_batch(const A& ar, const LD& ld, const siz
   for (int e = 0; e < NB; e++) out[e] = fin(ar, ld, raw[e]);
 }
 
+// Forward column pass of one tile by TPB threads (tid < TPB; every thread of
+// the work-group reaches its one barrier); store = false computes without
+// writing (a work-group half with nothing to do).
+template <int LOGN, int GA, int GB, class A, class LD>
+__device__ __forceinline__ void ntt_cols2_fwd(u64* a, int c0, typename A::V* sh, const A& ar, const LD& ld, int tid,
+                                              bool store) {
+  typedef typename A::V V;
+  constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R;
+  V v[16];
+  // group A: r bits [GB, S1) -> stages 0..GA-1
+  constexpr int ITA = 16 >> GA;
+#pragma unroll
+  for (int k = 0; k < ITA; k++) {
+    const int it = tid + TPB * k, c = it % C, rl = it / C;
+    constexpr int NB = (1 << GA) < 8 ? (1 << GA) : 8;
+#pragma unroll
+    for (int h = 0; h < (1 << GA) / NB; h++) {
+      size_t idx[NB];
+#pragma unroll
+      for (int e = 0; e < NB; e++) idx[e] = (size_t)(rl + ((h * NB + e) << GB)) * T1 + c0 + c;
+      fetch_batch<NB>(ar, ld, idx, v + h * NB);
+    }
+    fwd_group<GA>(v, 0, 0u, ar);
+#pragma unroll
+    for (int mm = 0; mm < (1 << GA); mm++) sh[lds_rc(rl + (mm << GB), c, C)] = v[mm];
+  }
+  __syncthreads();
+  // group B: r bits [0, GB) -> stages GA..S1-1
+  constexpr int ITB = 16 >> GB;
+#pragma unroll
+  for (int k = 0; k < ITB; k++) {
+    const int it = tid + TPB * k, c = it % C, rh = it / C;
+#pragma unroll
+    for (int mm = 0; mm < (1 << GB); mm++) v[mm] = sh[lds_rc((rh << GB) + mm, c, C)];
+    fwd_group<GB>(v, GA, (u32)rh, ar);
+    if (store)
+#pragma unroll
+      for (int mm = 0; mm < (1 << GB); mm++) a[(size_t)((rh << GB) + mm) * T1 + c0 + c] = ar.store(v[mm]);
+  }
+}
+
 // Column pass body: rows R = 2^(GA+GB), C = TILE / R columns per work-group.
 template <int LOGN, int GA, int GB, bool INV, class A, class LD>
 __device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh, const A& ar, const LD& ld) {
@@ -706,35 +747,7 @@ __device__ __forceinline__ void ntt_cols2_body(u64* a, int c0, typename A::V* sh
   const int tid = threadIdx.x;
   V v[16];
   if (!INV) {
-    // group A: r bits [GB, S1) -> stages 0..GA-1
-    constexpr int ITA = 16 >> GA;
-#pragma unroll
-    for (int k = 0; k < ITA; k++) {
-      const int it = tid + TPB * k, c = it % C, rl = it / C;
-      constexpr int NB = (1 << GA) < 8 ? (1 << GA) : 8;
-#pragma unroll
-      for (int h = 0; h < (1 << GA) / NB; h++) {
-        size_t idx[NB];
-#pragma unroll
-        for (int e = 0; e < NB; e++) idx[e] = (size_t)(rl + ((h * NB + e) << GB)) * T1 + c0 + c;
-        fetch_batch<NB>(ar, ld, idx, v + h * NB);
-      }
-      fwd_group<GA>(v, 0, 0u, ar);
-#pragma unroll
-      for (int mm = 0; mm < (1 << GA); mm++) sh[lds_rc(rl + (mm << GB), c, C)] = v[mm];
-    }
-    __syncthreads();
-    // group B: r bits [0, GB) -> stages GA..S1-1
-    constexpr int ITB = 16 >> GB;
-#pragma unroll
-    for (int k = 0; k < ITB; k++) {
-      const int it = tid + TPB * k, c = it % C, rh = it / C;
-#pragma unroll
-      for (int mm = 0; mm < (1 << GB); mm++) v[mm] = sh[lds_rc((rh << GB) + mm, c, C)];
-      fwd_group<GB>(v, GA, (u32)rh, ar);
-#pragma unroll
-      for (int mm = 0; mm < (1 << GB); mm++) a[(size_t)((rh << GB) + mm) * T1 + c0 + c] = ar.store(v[mm]);
-    }
+    ntt_cols2_fwd<LOGN, GA, GB>(a, c0, sh, ar, ld, tid, true);
   } else {
     constexpr int S2 = LOGN - S1;
     // inverse bits [S2, S2+GB) = r bits [0, GB)
@@ -2134,40 +2147,38 @@ struct FbcTgts {
   int n;
 };
 // Work-groups are dispatched to the 8 XCDs in turn (work-group b to XCD
-// b % 8), and each XCD has its own L2.  With map set, the launch's first
-// 8 * floor(n / 8) work-groups are renumbered so that XCD x runs the x-th
-// contiguous range of logical work-groups (x-major, launch order kept within
-// it): work-groups that read the same data (the tiles of one polynomial)
-// share an L2.  The rest keep their numbers.
-__device__ __forceinline__ void xcd_remap(int& bx, int& by, int map) {
-  if (!map) return;
-  const int gx = gridDim.x, nb = gx * gridDim.y, per = nb >> 3;
-  const int b = by * gx + bx;
-  if (b >= per * 8) return;
-  const int lb = (b & 7) * per + (b >> 3);
-  by = lb / gx;
-  bx = lb - by * gx;
+// b % 8), and each XCD has its own L2.  xcd_perm renumbers the first
+// 8 * floor(n / 8) of n work-groups so that XCD x runs the x-th contiguous
+// range of logical work-groups (launch order kept within it): work-groups
+// that read the same data (the tiles of one polynomial) share an L2.  The
+// rest keep their numbers.
+__device__ __forceinline__ int xcd_perm(int b, int n) {
+  const int per = n >> 3;
+  return b < per * 8 ? (b & 7) * per + (b >> 3) : b;
 }
+// KB record bytes, KU stored words, KW words the products read (whole
+// 16-byte steps: the words past KU are zero and not stored)
 template <int NS>
 struct FbcRec {
-  static constexpr int KB = 9 * NS + 1, KW = 2 * ((KB + 15) / 16);
+  static constexpr int KB = 9 * NS + 1, KU = (KB + 7) / 8, KW = 2 * ((KB + 15) / 16);
+  static_assert(KU == NS + 1, "a record takes the words of the sources and the quotient");
 };
 template <int NS>
 __global__ void k_fbc_prep_digits(u64* V, const u64* xp, FbcArgs A, int logN, const ModConst* __restrict__ mc) {
-  constexpr int KW = FbcRec<NS>::KW;
+  constexpr int KU = FbcRec<NS>::KU;
   const u64 N = 1ull << logN;
   u32 i = blockIdx.x * TPB + threadIdx.x;
   if (i >= N) return;
   const int poly = blockIdx.y;
   const u64* x = xp + ((size_t)poly * A.src_stride + A.src_off) * N;
-  u64* o = V + (size_t)poly * KW * N;
+  u64* o = V + (size_t)poly * KU * N;
   u64 v[4];
 #pragma unroll
   for (int a = 0; a < NS; a++) v[a] = shoup_mul(x[(size_t)a * N + i], A.hatinv[a], A.hatinv_sh[a], mc[A.src[a]].q);
   const u64 r = round_quotient(v, A);
-  u64 w[KW];
+  u64 w[KU];
 #pragma unroll
-  for (int k = 0; k < KW; k++) w[k] = 0;
+  for (int k = 0; k < KU; k++) w[k] = 0;
 #pragma unroll
   for (int a = 0; a < NS; a++)
 #pragma unroll
@@ -2177,7 +2188,7 @@ __global__ void k_fbc_prep_digits(u64* V, const u64* xp, FbcArgs A, int logN, co
     }
   w[(9 * NS) >> 3] |= r << (8 * ((9 * NS) & 7));
 #pragma unroll
-  for (int k = 0; k < KW; k++) o[(size_t)k * N + i] = w[k];
+  for (int k = 0; k < KU; k++) o[(size_t)k * N + i] = w[k];
 }
 
 // The column pass of targets outside the FP64 path (and any target) from the
@@ -2185,16 +2196,16 @@ __global__ void k_fbc_prep_digits(u64* V, const u64* xp, FbcArgs A, int logN, co
 // Shoup lift of FbcLoad<false>.
 template <int NS>
 struct FbcDigitLoad {
-  static constexpr int KW = FbcRec<NS>::KW;
+  static constexpr int KU = FbcRec<NS>::KU;
   struct Raw {
-    u64 w[KW];
+    u64 w[KU];
   };
   const u64* v0;
   u64 N;
   u64 q, h[4], hs[4], D, Ds;
   __device__ __forceinline__ void raw(size_t idx, Raw& r) const {
 #pragma unroll
-    for (int k = 0; k < KW; k++) r.w[k] = v0[(size_t)k * N + idx];
+    for (int k = 0; k < KU; k++) r.w[k] = v0[(size_t)k * N + idx];
   }
   __device__ __forceinline__ static u64 byte(const Raw& r, int k) { return (r.w[k >> 3] >> (8 * (k & 7))) & 255; }
   __device__ __forceinline__ u64 fin_u(const Raw& r) const {
@@ -2209,38 +2220,6 @@ struct FbcDigitLoad {
     return sub_mod(acc, shoup_mul(byte(r, 9 * NS), D, Ds, q), q);
   }
 };
-template <int LOGN, int GA, int GB, int NS>
-__global__ void __launch_bounds__(TPB) k_ntt_cols2_fbcd(u64* y, const u64* __restrict__ V, int nq, FbcTgts tg,
-                                                        FbcArgs A, const u64* __restrict__ tw,
-                                                        const u64* __restrict__ twsh, const double* __restrict__ twf,
-                                                        int nmods, const ModConst* __restrict__ mc) {
-  constexpr int S1 = GA + GB, R = 1 << S1, C = TILE / R, KW = FbcRec<NS>::KW;
-  __shared__ u64 sh[LDS_WORDS];
-  const int p = blockIdx.y / tg.n, t = tg.t[blockIdx.y - p * tg.n];
-  const u64 N = 1ull << LOGN;
-  u64* a = y + ((size_t)p * nq + t) * N;
-  const int c0 = blockIdx.x * C;
-  const ModConst mk = mc[t];
-  FbcDigitLoad<NS> ld;
-  ld.v0 = V + (size_t)p * KW * N;
-  ld.N = N;
-  ld.q = mk.q;
-  ld.D = A.D_mod_t[2 * t];
-  ld.Ds = A.D_mod_t[2 * t + 1];
-#pragma unroll
-  for (int x = 0; x < NS; x++) {
-    ld.h[x] = A.hat_t[(size_t)x * nmods + t];
-    ld.hs[x] = A.hat_t_sh[(size_t)x * nmods + t];
-  }
-  if (mk.bits <= F64_LAZY_BITS) {
-    F64LazyArith ar{twf + (size_t)t * N, mk.qf, mk.qinvf, (double)mk.ninv};
-    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, reinterpret_cast<double*>(sh), ar, ld);
-  } else {
-    ShoupArith ar{tw + (size_t)t * N, twsh + (size_t)t * N, mk.q, mk.ninv, mk.ninv_sh};
-    ntt_cols2_body<LOGN, GA, GB, false>(a, c0, sh, ar, ld);
-  }
-}
-
 typedef int mfma_i32x16 __attribute__((ext_vector_type(16)));
 // Two FP64 targets (33 to 46 bits) t0, t1 per work-group of 2 TPB threads.
 // v_mfma_i32_32x32x16_i8 takes, per lane l:
@@ -2255,23 +2234,55 @@ typedef int mfma_i32x16 __attribute__((ext_vector_type(16)));
 // thread), and so ends holding that thread's values for target t_(l / 32):
 // the first stage group runs in registers, the second from the LDS tile of
 // the lane's target.
+// The launch's first work-groups (blockIdx.y below ceil(to.n npoly / 2))
+// instead run the targets of the Shoup path (above 46 bits, q0): two
+// (polynomial, target) units each, one per half, from the same records.
 template <int LOGN, int GA, int GB, int NS>
-__global__ void __launch_bounds__(2 * TPB) k_ntt_cols2_fbc_mfma(u64* y, const u64* __restrict__ V, int nq,
-                                                                FbcTgts tg, const u64* __restrict__ cdig,
-                                                                const double* __restrict__ twf,
-                                                                const ModConst* __restrict__ mc, int xcd_map) {
-  constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R, KW = FbcRec<NS>::KW;
+__global__ void __launch_bounds__(2 * TPB) __attribute__((amdgpu_waves_per_eu(4)))
+    k_ntt_cols2_fbc_mfma(u64* y, const u64* __restrict__ V, int nq, int npoly, FbcTgts tg, FbcTgts to, FbcArgs A,
+                         const u64* __restrict__ cdig, const u64* __restrict__ tw, const u64* __restrict__ twsh,
+                         const double* __restrict__ twf, int nmods, const ModConst* __restrict__ mc, int xcd_map) {
+  constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R, KW = FbcRec<NS>::KW,
+                KU = FbcRec<NS>::KU;
   constexpr int ITA = 16 >> GA, NA = 1 << GA, ITB = 16 >> GB;
   __shared__ double sh[2][LDS_WORDS];
+  // the Shoup-path work-groups first, in launch order (spread over the
+  // XCDs); the MFMA ones after them, grouped by XCD when xcd_map is set
+  const int gx = gridDim.x, nint = (to.n * npoly + 1) >> 1;
+  int b = blockIdx.y * gx + blockIdx.x;
+  if (xcd_map && b >= nint * gx) b = nint * gx + xcd_perm(b - nint * gx, gx * (gridDim.y - nint));
+  int by = b / gx;
+  const int bx = b - by * gx;
+  const u64 N = 1ull << LOGN;
+  const int c0 = bx * C;
+  if (by < nint) {
+    const int hs = threadIdx.x >= TPB, tid = threadIdx.x - hs * TPB;
+    int u = 2 * by + hs;
+    const bool act = u < to.n * npoly;
+    if (!act) u = 2 * by;  // an odd unit count: this half computes and stores nothing
+    const int p = u / to.n, t = to.t[u - p * to.n];
+    const ModConst mk = mc[t];
+    FbcDigitLoad<NS> ld;
+    ld.v0 = V + (size_t)p * KU * N;
+    ld.N = N;
+    ld.q = mk.q;
+    ld.D = A.D_mod_t[2 * t];
+    ld.Ds = A.D_mod_t[2 * t + 1];
+#pragma unroll
+    for (int x = 0; x < NS; x++) {
+      ld.h[x] = A.hat_t[(size_t)x * nmods + t];
+      ld.hs[x] = A.hat_t_sh[(size_t)x * nmods + t];
+    }
+    ShoupArith ar{tw + (size_t)t * N, twsh + (size_t)t * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_cols2_fwd<LOGN, GA, GB>(y + ((size_t)p * nq + t) * N, c0, reinterpret_cast<u64*>(sh[hs]), ar, ld, tid, act);
+    return;
+  }
+  by -= nint;
   const int npair = (tg.n + 1) >> 1;
-  int bx = blockIdx.x, by = blockIdx.y;
-  xcd_remap(bx, by, xcd_map);
   const int p = by / npair, pr = by - p * npair;
   const int t0 = tg.t[2 * pr];
   const bool has1 = 2 * pr + 1 < tg.n;
   const int t1 = has1 ? tg.t[2 * pr + 1] : t0;
-  const u64 N = 1ull << LOGN;
-  const int c0 = bx * C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, hl = lane >> 5, i = lane & 31;
   const int tid = 32 * wave + i;  // the column-pass thread this lane stands for
   const int t = hl ? t1 : t0;
@@ -2283,7 +2294,7 @@ __global__ void __launch_bounds__(2 * TPB) k_ntt_cols2_fbc_mfma(u64* y, const u6
     long aop[KW / 2];
 #pragma unroll
     for (int m = 0; m < KW / 2; m++) aop[m] = i < 16 ? (long)cdig[((size_t)ta * 8 + j) * KW + 2 * m + hl] : 0;
-    const u64* rec = V + (size_t)p * KW * N + (size_t)hl * N;
+    const u64* rec = V + (size_t)p * KU * N;
 #pragma unroll
     for (int k = 0; k < ITA; k++) {
       const int it = tid + TPB * k, c = it % C, rl = it / C;
@@ -2295,7 +2306,14 @@ __global__ void __launch_bounds__(2 * TPB) k_ntt_cols2_fbc_mfma(u64* y, const u6
         for (int u = 0; u < 4; u++) {
           const size_t idx = (size_t)(rl + ((m0 + u) << GB)) * T1 + c0 + c;
 #pragma unroll
-          for (int m = 0; m < KW / 2; m++) b[u][m] = (long)rec[(size_t)(2 * m) * N + idx];
+          for (int m = 0; m < KW / 2; m++) {
+            if (2 * m + 1 < KU) {
+              b[u][m] = (long)rec[(size_t)(2 * m + hl) * N + idx];
+            } else {  // the last step's upper word is padding: zero in lanes 32..63
+              const long w = (long)rec[(size_t)(2 * m) * N + idx];
+              b[u][m] = hl ? 0 : w;
+            }
+          }
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -2348,22 +2366,20 @@ static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const Fbc
       hipLaunchKernelGGL((k_ntt_cols2_fbc<LOGN, GA, GB>), gc, dim3(TPB), 0, s, y, V, nq, A, T.psi, T.psi_sh,
                          T.psi_f, T.nmods, T.mc);
     } else {
-      // FP64 targets in pairs through the MFMA lift, the others one by one
+      // FP64 targets in pairs through the MFMA lift, the Shoup-path targets
+      // (above 46 bits) two units a work-group, in one launch
       FbcTgts f, o;
       f.n = o.n = 0;
       for (int t = 0; t < nq; t++) {
-        if (T.bits[t] > 32 && T.bits[t] <= F64_LAZY_BITS) f.t[f.n++] = (short)t;
+        if (T.bits[t] <= F64_LAZY_BITS) f.t[f.n++] = (short)t;
         else o.t[o.n++] = (short)t;
       }
+      const int gy = (o.n * npoly + 1) / 2 + ((f.n + 1) / 2) * npoly;
       auto go = [&](auto ns) {
         constexpr int NS = decltype(ns)::value;
-        if (f.n > 0)
-          hipLaunchKernelGGL((k_ntt_cols2_fbc_mfma<LOGN, GA, GB, NS>),
-                             dim3((1 << LOGN) / R / C, ((f.n + 1) / 2) * npoly), dim3(2 * TPB), 0, s, y, V, nq, f,
-                             cdig, T.psi_f, T.mc, g_knobs.xcd_map);
-        if (o.n > 0)
-          hipLaunchKernelGGL((k_ntt_cols2_fbcd<LOGN, GA, GB, NS>), dim3((1 << LOGN) / R / C, o.n * npoly),
-                             dim3(TPB), 0, s, y, V, nq, o, A, T.psi, T.psi_sh, T.psi_f, T.nmods, T.mc);
+        hipLaunchKernelGGL((k_ntt_cols2_fbc_mfma<LOGN, GA, GB, NS>), dim3((1 << LOGN) / R / C, gy), dim3(2 * TPB), 0,
+                           s, y, V, nq, npoly, f, o, A, cdig, T.psi, T.psi_sh, T.psi_f, T.nmods, T.mc,
+                           g_knobs.xcd_map);
       };
       switch (A.ns) {
         case 1: go(std::integral_constant<int, 1>{}); break;
@@ -2398,7 +2414,11 @@ bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int
   A.hat_t_sh = tab.hat_t_sh;
   A.D_mod_t = tab.D_mod_t;
   A.hat_f = tab.hat_f;
-  const u64* cdig = g_knobs.fbc_mfma && tab.cdig && tab.kw > 0 && nq <= 64 ? tab.cdig : nullptr;
+  // the MFMA lift takes targets of 33 to 46 bits and, beside them, Shoup-path
+  // targets above 46 bits
+  bool small_target = false;
+  for (int t = 0; t < nq; t++) small_target |= T.bits[t] <= 32;
+  const u64* cdig = g_knobs.fbc_mfma && tab.cdig && tab.kw > 0 && nq <= 64 && !small_target ? tab.cdig : nullptr;
   {
     Mm mm;
     for (int a = 0; a < tab.ns; a++) mm.add(T.bits[tab.src[a]], (double)T.N * npoly);
@@ -2418,7 +2438,7 @@ bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int
     moddown_fused<NTT_SPLIT_ARGS>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s, cdig);
   });
 }
-int fbc_record_words(const FbcTable& tab) { return tab.kw > tab.ns + 1 ? tab.kw : tab.ns + 1; }
+
 
 // out[p][t] = (x[p][t] - y[p][t]) * P^{-1} mod q_t   (p < npoly, t < nq)
 __global__ void k_moddown_final(u64* out, const u64* x, const u64* y, int nq, const u64* pinv, int x_stride_limbs,

@@ -880,7 +880,7 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume,
     pm.slot_stride = (short)x.nlimbs;
     pm.slot_off = (short)nq_of(x.level);
     if (!src_ready) launch_ntt(T, x.d.p, np * alpha, pm, true, stream);
-    DevBuf V(&pool, (size_t)np * fbc_record_words(down) * N);
+    DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
     if (!launch_moddown_fused(T, x.d.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream, x.nlimbs,
                               nq_of(x.level)))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
@@ -891,7 +891,7 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume,
   gather_limbs(pc.p, x, nq_of(x.level), alpha);
   launch_ntt(T, pc.p, np * alpha, pm, true, stream);
   if (fused_conv) {
-    DevBuf V(&pool, (size_t)np * fbc_record_words(down) * N);
+    DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
     if (!launch_moddown_fused(T, pc.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
   } else {
@@ -929,7 +929,7 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool
     if (!src_ready) launch_ntt(T, x.d.p, np * ns, sm, true, stream);
     DevBuf y(&pool, (size_t)np * nout * N);
     HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
-    DevBuf V(&pool, (size_t)np * fbc_record_words(tab) * N);
+    DevBuf V(&pool, (size_t)np * (ns + 1) * N);
     if (!launch_moddown_fused(T, x.d.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, V.p, stream, x.nlimbs, l))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
     n_moddown += x.B;
@@ -947,7 +947,7 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool
   DevBuf y(&pool, (size_t)np * nout * N);
   HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
   if (fused_conv) {
-    DevBuf V(&pool, (size_t)np * fbc_record_words(tab) * N);
+    DevBuf V(&pool, (size_t)np * (ns + 1) * N);
     if (!launch_moddown_fused(T, pc.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, V.p, stream))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
   } else {
@@ -1051,7 +1051,7 @@ std::vector<HeCt> HeCtxImpl::rotate_many(const HeCt& x, const std::vector<long>&
 // rounded up to the pool's 256-byte granule
 size_t HeCtxImpl::rotate_workspace_bytes(int level, int B) const {
   const size_t nq = nq_of(level), nqp = nqp_of(level), bl = beta_at(level), np = 2 * (size_t)B;
-  const size_t blocks[] = {B * nq, B * bl * nqp, np * nqp, np * alpha, np * nq, np * (size_t)fbc_record_words(down)};
+  const size_t blocks[] = {B * nq, B * bl * nqp, np * nqp, np * alpha, np * nq, np * (alpha + 1)};
   size_t total = 0;
   for (size_t w : blocks) total += (w * N * 8 + 255) & ~(size_t)255;
   return total;
