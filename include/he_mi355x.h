@@ -412,7 +412,10 @@ he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d,
  * "fbc_mfma" (0/1, default 1: ModDown's basis conversion into targets of 33
  * to 46 bits as an int8 matrix product of 7-bit digits, else six exact FP64
  * products per value) and "xcd_map" (0/1, default 1: that lift's work-groups
- * renumbered so that those of one polynomial run on one XCD and share its L2).
+ * renumbered so that those of one polynomial run on one XCD and share its L2);
+ * "sum_streams" (1/2/4, default 4: term streams that share their plaintexts
+ * per thread of the multi-output multiply-sums, each plaintext word loaded
+ * once for all of them).
  * Set them between calls, not while
  * another thread drives the library.  The autotuner in the Python package
  * picks them by timing. */

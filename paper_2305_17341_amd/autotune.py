@@ -21,6 +21,7 @@ CANDIDATES = {
     "mr_int_pass": (4, 8),
     "mr_int_chunk": (4, 16, 64),
     "mr_int_concurrent": (0, 1),
+    "sum_streams": (1, 2, 4),
 }
 
 

@@ -32,6 +32,7 @@ struct Knobs {
   int mr_group = 4;        // rotations per work-group of a multi-rotation launch, sharing the digit loads (1/2/4)
   int fbc_mfma = 1;        // ModDown's lift as an int8 matrix product (0/1)
   int xcd_map = 1;         // the MFMA lift's work-groups of one polynomial kept on one XCD (0/1)
+  int sum_streams = 4;     // term streams sharing a plaintext per thread of the multi-output sums (1/2/4)
   // stage split of the register-blocked NTT per ring size (index log N):
   // 0 = the default, 1 = one stage moved between the column and block passes
   int ntt_split[17] = {};
@@ -52,6 +53,7 @@ bool knob_set(const char* name, int v) {
   else if (n == "mr_int_concurrent" && (v == 0 || v == 1)) g_knobs.mr_int_concurrent = v;
   else if (n == "fbc_mfma" && (v == 0 || v == 1)) g_knobs.fbc_mfma = v;
   else if (n == "xcd_map" && (v == 0 || v == 1)) g_knobs.xcd_map = v;
+  else if (n == "sum_streams" && (v == 1 || v == 2 || v == 4)) g_knobs.sum_streams = v;
   else if ((n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") && (v == 0 || v == 1))
     g_knobs.ntt_split[std::stoi(n.substr(10))] = v;
   else return false;
@@ -72,6 +74,7 @@ bool knob_get(const char* name, int* v) {
   else if (n == "mr_int_concurrent") *v = g_knobs.mr_int_concurrent;
   else if (n == "fbc_mfma") *v = g_knobs.fbc_mfma;
   else if (n == "xcd_map") *v = g_knobs.xcd_map;
+  else if (n == "sum_streams") *v = g_knobs.sum_streams;
   else if (n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") *v = g_knobs.ntt_split[std::stoi(n.substr(10))];
   else return false;
   return true;
@@ -1512,19 +1515,26 @@ struct SumMulti {
   const u64* p[SUM_MAX_OUTS][SUM_MAX_TERMS];
   u64* out[SUM_MAX_OUTS];
 };
-// V = 2: two consecutive coefficients per thread, 16-byte loads and stores
-template <int G, int V>
-__global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map, int logN,
+// V = 2: two consecutive coefficients per thread, 16-byte loads and stores.
+// S: a thread sums S term streams that share their plaintexts (limbs k0 +
+// s b_limbs, s < S, of the same modulus), loading each plaintext word once
+// for all of them.
+template <int G, int V, int S>
+__global__ void __launch_bounds__(TPB) k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map, int logN,
                                 const ModConst* __restrict__ mc, int il) {
   const u64 N = 1ull << logN;
   int blk, k;
   block_limb(il, b_limbs, (int)(N / (TPB * V)), blk, k);
   const u32 i = (blk * TPB + threadIdx.x) * V;
   if (i >= N) return;
-  int m = limb_mod(map, k);
+  const int pos = k % b_limbs, k0 = (k / b_limbs) * S * b_limbs + pos;
+  int m = limb_mod(map, k0);
   if (m < 0) return;
   const ModConst mk = mc[m];
-  const size_t o = (size_t)k * N + i, op = (size_t)(k % b_limbs) * N + i;
+  const size_t op = (size_t)pos * N + i;
+  size_t o[S];
+#pragma unroll
+  for (int s = 0; s < S; s++) o[s] = (size_t)(k0 + s * b_limbs) * N + i;
   struct W {
     u64 v[V];
   };
@@ -1540,27 +1550,34 @@ __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map
     return w;
   };
   // software-pipelined over the terms
-  W xn = ld(t.a[0] + o), pn[G];
+  W xn[S], pn[G];
+#pragma unroll
+  for (int s = 0; s < S; s++) xn[s] = ld(t.a[0] + o[s]);
 #pragma unroll
   for (int g = 0; g < G; g++) pn[g] = t.p[g][0] ? ld(t.p[g][0] + op) : W{};
-  u64 res[G][V];
+  u64 res[G][S][V];
   if (mk.bits <= F64_LAZY_BITS) {
     // signed exact products summed per output (at most 64), reduced once
     const double q = mk.qf, qi = mk.qinvf;
-    double acc[G][V];
+    double acc[G][S][V];
 #pragma unroll
     for (int g = 0; g < G; g++)
 #pragma unroll
-      for (int e = 0; e < V; e++) acc[g][e] = 0.0;
-    for (int j = 0; j < nterms; j++) {
-      double x[V];
+      for (int s = 0; s < S; s++)
 #pragma unroll
-      for (int e = 0; e < V; e++) x[e] = u2d(xn.v[e]);
+        for (int e = 0; e < V; e++) acc[g][s][e] = 0.0;
+    for (int j = 0; j < nterms; j++) {
+      double x[S][V];
+#pragma unroll
+      for (int s = 0; s < S; s++)
+#pragma unroll
+        for (int e = 0; e < V; e++) x[s][e] = u2d(xn[s].v[e]);
       W pv[G];
 #pragma unroll
       for (int g = 0; g < G; g++) pv[g] = pn[g];
       if (j + 1 < nterms) {
-        xn = ld(t.a[j + 1] + o);
+#pragma unroll
+        for (int s = 0; s < S; s++) xn[s] = ld(t.a[j + 1] + o[s]);
 #pragma unroll
         for (int g = 0; g < G; g++) pn[g] = t.p[g][j + 1] ? ld(t.p[g][j + 1] + op) : W{};
       }
@@ -1568,24 +1585,35 @@ __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map
       for (int g = 0; g < G; g++)
         if (t.p[g][j])
 #pragma unroll
-          for (int e = 0; e < V; e++) acc[g][e] += f64_mulmod_signed(x[e], u2d(pv[g].v[e]), q, qi);
+          for (int e = 0; e < V; e++) {
+            const double pd = u2d(pv[g].v[e]);
+#pragma unroll
+            for (int s = 0; s < S; s++) acc[g][s][e] += f64_mulmod_signed(x[s][e], pd, q, qi);
+          }
     }
 #pragma unroll
     for (int g = 0; g < G; g++)
 #pragma unroll
-      for (int e = 0; e < V; e++) res[g][e] = d2u(f64_canon(acc[g][e], q, qi));
+      for (int s = 0; s < S; s++)
+#pragma unroll
+        for (int e = 0; e < V; e++) res[g][s][e] = d2u(f64_canon(acc[g][s][e], q, qi));
   } else {
 #pragma unroll
     for (int g = 0; g < G; g++)
 #pragma unroll
-      for (int e = 0; e < V; e++) res[g][e] = 0;
+      for (int s = 0; s < S; s++)
+#pragma unroll
+        for (int e = 0; e < V; e++) res[g][s][e] = 0;
     for (int j = 0; j < nterms; j++) {
-      const W x = xn;
+      W x[S];
+#pragma unroll
+      for (int s = 0; s < S; s++) x[s] = xn[s];
       W pv[G];
 #pragma unroll
       for (int g = 0; g < G; g++) pv[g] = pn[g];
       if (j + 1 < nterms) {
-        xn = ld(t.a[j + 1] + o);
+#pragma unroll
+        for (int s = 0; s < S; s++) xn[s] = ld(t.a[j + 1] + o[s]);
 #pragma unroll
         for (int g = 0; g < G; g++) pn[g] = t.p[g][j + 1] ? ld(t.p[g][j + 1] + op) : W{};
       }
@@ -1593,20 +1621,25 @@ __global__ void k_mul_sum_multi(SumMulti t, int nterms, int b_limbs, LimbMap map
       for (int g = 0; g < G; g++)
         if (t.p[g][j])
 #pragma unroll
-          for (int e = 0; e < V; e++) res[g][e] = add_mod(res[g][e], mul_mod_any(x.v[e], pv[g].v[e], mk), mk.q);
+          for (int s = 0; s < S; s++)
+#pragma unroll
+            for (int e = 0; e < V; e++)
+              res[g][s][e] = add_mod(res[g][s][e], mul_mod_any(x[s].v[e], pv[g].v[e], mk), mk.q);
     }
   }
 #pragma unroll
-  for (int g = 0; g < G; g++) {
-    if (V == 2) {
-      ulonglong2 y;
-      y.x = res[g][0];
-      y.y = res[g][V - 1];
-      *reinterpret_cast<ulonglong2*>(t.out[g] + o) = y;
-    } else {
-      t.out[g][o] = res[g][0];
+  for (int g = 0; g < G; g++)
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+      if (V == 2) {
+        ulonglong2 y;
+        y.x = res[g][s][0];
+        y.y = res[g][s][V - 1];
+        *reinterpret_cast<ulonglong2*>(t.out[g] + o[s]) = y;
+      } else {
+        t.out[g][o[s]] = res[g][s][0];
+      }
     }
-  }
 }
 bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, const u64* const* a,
                           const u64* const* p /* [nouts][nterms], null = absent */, int nterms, int nl, int bl,
@@ -1627,20 +1660,30 @@ bool launch_mul_sum_multi(const DeviceTables& T, u64* const* outs, int nouts, co
   int il;
   // two coefficients per thread where the ring fills whole work-groups
   const bool v2 = T.N >= (u64)(2 * TPB);
-  dim3 grid = sum_grid((int)cdiv(T.N, TPB * (v2 ? 2 : 1)), nl, bl, g_knobs.ew_interleave, il);
-#define MSM_CASE(G)                                                                                              \
-  case G:                                                                                                        \
-    if (v2) hipLaunchKernelGGL((k_mul_sum_multi<G, 2>), grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il); \
-    else hipLaunchKernelGGL((k_mul_sum_multi<G, 1>), grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il);   \
-    break;
+  // streams per thread: limbs bl apart share a plaintext (the map repeats
+  // with a period dividing bl)
+  int S = g_knobs.sum_streams;
+  while (S > 1 && (bl <= 0 || nl % (bl * S) != 0 || bl % m.n != 0)) S >>= 1;
+  dim3 grid = sum_grid((int)cdiv(T.N, TPB * (v2 ? 2 : 1)), nl / S, bl, g_knobs.ew_interleave, il);
+  auto go = [&](auto gc, auto vc, auto sc) {
+    hipLaunchKernelGGL((k_mul_sum_multi<decltype(gc)::value, decltype(vc)::value, decltype(sc)::value>), grid,
+                       dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il);
+  };
+  auto by_s = [&](auto gc, auto vc) {
+    if (S == 4) go(gc, vc, std::integral_constant<int, 4>{});
+    else if (S == 2) go(gc, vc, std::integral_constant<int, 2>{});
+    else go(gc, vc, std::integral_constant<int, 1>{});
+  };
+  auto by_v = [&](auto gc) {
+    if (v2) by_s(gc, std::integral_constant<int, 2>{});
+    else by_s(gc, std::integral_constant<int, 1>{});
+  };
   switch (nouts) {
-    MSM_CASE(1) MSM_CASE(2) MSM_CASE(3)
-    default:
-      if (v2) hipLaunchKernelGGL((k_mul_sum_multi<4, 2>), grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il);
-      else hipLaunchKernelGGL((k_mul_sum_multi<4, 1>), grid, dim3(TPB), 0, s, t, nterms, bl, m, T.logN, T.mc, il);
-      break;
+    case 1: by_v(std::integral_constant<int, 1>{}); break;
+    case 2: by_v(std::integral_constant<int, 2>{}); break;
+    case 3: by_v(std::integral_constant<int, 3>{}); break;
+    default: by_v(std::integral_constant<int, 4>{}); break;
   }
-#undef MSM_CASE
   return true;
 }
 
