@@ -119,14 +119,21 @@ void launch_modup(const DeviceTables& T, u64* digits, const u64* coef, const u64
 // limb j < per_elem lives at slot (j / per) * stride + off + j % per; map
 // gives the modulus of limb j by j % map.n (map.n = per).  One launch per 64
 // elements.
+// With rec_tab and rec: the sources are those of the ModDown table rec_tab
+// (per = its ns) and the last pass writes their digit records to rec
+// ([element][per_elem / per][per + 1][N]) instead of the limbs.
 void launch_intt_many(const DeviceTables& T, const std::vector<u64*>& bases, int per_elem, int per, int stride,
-                      int off, const LimbMap& map, hipStream_t s);
+                      int off, const LimbMap& map, hipStream_t s, const FbcTable* rec_tab = nullptr,
+                      u64* rec = nullptr);
 // xp_coef: the source limbs in the coefficient domain, [npoly][ns][N]; or,
 // with src_stride > 0, limb a of poly p at slot p * src_stride + src_off + a
 // (the sources transformed in place inside the R_{Q_l P} element)
+// whether a fused ModDown into nq target limbs with this table takes digit
+// records (the int8 lift); only then may V arrive filled (v_ready)
+bool fbc_digit_path(const DeviceTables& T, const FbcTable& tab, int nq);
 bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                           const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
-                          int src_stride = 0, int src_off = 0);
+                          int src_stride = 0, int src_off = 0, bool v_ready = false);
 // y[npoly][nq] = exact centred lift of the source limbs xp[npoly][ns] to each q_t
 void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                      hipStream_t s);

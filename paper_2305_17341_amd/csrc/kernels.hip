@@ -1236,23 +1236,6 @@ static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& ma
   }
 }
 
-template <int LOGN, int GA, int GB, int GC, int GD>
-static void intt2_many(const DeviceTables& T, const LimbBases& lb, int nelem, const LimbMap& map, hipStream_t s) {
-  constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
-  const int nlimbs = nelem * lb.per_elem;
-  dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
-  // the modulus pattern repeats every `per` limbs, and per_elem is a multiple of it
-  const int il = interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave);
-  const double pass_bytes = 16.0 * nlimbs * T.N;
-  {
-    ProfScope ps("ntt_inv_rows", s, pass_bytes, mm_map(T, map, nlimbs, 0.5 * T.N * (GC + GD)));
-    hipLaunchKernelGGL((k_intt_rows2_many<LOGN, GC, GD>), gr, dim3(TPB), 0, s, lb, map, T.ipsi, T.ipsi_sh, T.ipsi_f,
-                       T.mc, il);
-  }
-  ProfScope ps("ntt_inv_cols", s, pass_bytes, mm_map(T, map, nlimbs, 0.5 * T.N * (GA + GB)));
-  hipLaunchKernelGGL((k_intt_cols2_many<LOGN, GA, GB>), gc, dim3(TPB), 0, s, lb, map, T.ipsi, T.ipsi_sh, T.ipsi_f,
-                     T.mc);
-}
 
 static bool ntt_register_blocked(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse,
                                  double pass_bytes, hipStream_t s) {
@@ -1262,24 +1245,6 @@ static bool ntt_register_blocked(const DeviceTables& T, u64* data, int nlimbs, c
   });
 }
 
-void launch_intt_many(const DeviceTables& T, const std::vector<u64*>& bases, int per_elem, int per, int stride,
-                      int off, const LimbMap& map, hipStream_t s) {
-  if (map.n != per || per_elem % per != 0) throw std::runtime_error("launch_intt_many: bad limb pattern");
-  for (size_t e0 = 0; e0 < bases.size(); e0 += MR_MAX) {
-    const int ne = (int)std::min(bases.size() - e0, (size_t)MR_MAX);
-    LimbBases lb;
-    for (int e = 0; e < MR_MAX; e++) lb.base[e] = e < ne ? bases[e0 + e] : nullptr;
-    lb.per_elem = per_elem;
-    lb.per = per;
-    lb.stride = stride;
-    lb.off = off;
-    if (!ntt_dispatch(T.logN, [&](auto sp) {
-          using S = decltype(sp);
-          intt2_many<NTT_SPLIT_ARGS>(T, lb, ne, map, s);
-        }))
-      throw std::runtime_error("launch_intt_many needs the register-blocked NTT (log N 12..16)");
-  }
-}
 
 // Each pass streams every active limb in and out once: 16 bytes per coefficient.
 void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s) {
@@ -2263,6 +2228,150 @@ struct FbcDigitLoad {
     return sub_mod(acc, shoup_mul(byte(r, 9 * NS), D, Ds, q), q);
   }
 };
+// The inverse column pass of the ns ModDown sources of one polynomial (one
+// TPB-thread group per source limb, every barrier outside the arithmetic's
+// branches), finished into the digit records k_fbc_prep_digits writes: the
+// coefficient values stay in LDS and only the records go to memory, rec
+// [polynomial][ns + 1][N] in the order of the launch's element table.
+template <int LOGN, int GA, int GB, class A>
+__device__ __forceinline__ void intt_cols_first(const u64* a, int c0, typename A::V* sh, const A& ar, int tid) {
+  typedef typename A::V V;
+  constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R, S2 = LOGN - S1, ITB = 16 >> GB;
+  V v[16];
+#pragma unroll
+  for (int k = 0; k < ITB; k++) {
+    const int it = tid + TPB * k, c = it % C, rh = it / C;
+#pragma unroll
+    for (int mm = 0; mm < (1 << GB); mm++) v[mm] = ar.load(a[(size_t)((rh << GB) + mm) * T1 + c0 + c]);
+    inv_group<GB>(v, S2, LOGN, (u32)rh, ar);
+#pragma unroll
+    for (int mm = 0; mm < (1 << GB); mm++) sh[lds_rc((rh << GB) + mm, c, C)] = v[mm];
+  }
+}
+template <int LOGN, int GA, int GB, class A>
+__device__ __forceinline__ void intt_cols_last_lds(typename A::V* sh, const A& ar, int tid) {
+  typedef typename A::V V;
+  constexpr int S1 = GA + GB, R = 1 << S1, C = TILE / R, S2 = LOGN - S1, ITA = 16 >> GA;
+  V v[16];
+#pragma unroll
+  for (int k = 0; k < ITA; k++) {
+    const int it = tid + TPB * k, c = it % C, rl = it / C;
+#pragma unroll
+    for (int mm = 0; mm < (1 << GA); mm++) v[mm] = ar.reduce(sh[lds_rc(rl + (mm << GB), c, C)]);
+    inv_group_last_scaled<GA>(v, S2 + GB, LOGN, ar);
+    // canonical residues, in place (positions only this thread reads)
+#pragma unroll
+    for (int mm = 0; mm < (1 << GA); mm++)
+      reinterpret_cast<u64*>(sh)[lds_rc(rl + (mm << GB), c, C)] = ar.store(v[mm]);
+  }
+}
+template <int LOGN, int GA, int GB, int NS>
+__global__ void __launch_bounds__(NS * TPB)
+    k_intt_cols2_rec(LimbBases lb, LimbMap map, FbcArgs A, u64* rec, const u64* __restrict__ tw,
+                     const u64* __restrict__ twsh, const double* __restrict__ twf, const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, T1 = (1 << LOGN) / R, C = TILE / R, KU = FbcRec<NS>::KU;
+  __shared__ u64 sh[NS][LDS_WORDS];
+  const int src = threadIdx.x / TPB, tid = threadIdx.x - src * TPB;
+  const int poly = blockIdx.y;
+  const u64 N = 1ull << LOGN;
+  const u64* a = limb_base_addr(lb, poly * NS + src, N);
+  const int c0 = blockIdx.x * C;
+  const ModConst mk = mc[map.idx[src]];
+  const int m = map.idx[src];
+  const bool f64 = mk.bits <= F64_LAZY_BITS;
+  const F64LazyArith af{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
+  const ShoupArith as{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
+  if (f64) intt_cols_first<LOGN, GA, GB>(a, c0, reinterpret_cast<double*>(sh[src]), af, tid);
+  else intt_cols_first<LOGN, GA, GB>(a, c0, sh[src], as, tid);
+  __syncthreads();
+  if (f64) intt_cols_last_lds<LOGN, GA, GB>(reinterpret_cast<double*>(sh[src]), af, tid);
+  else intt_cols_last_lds<LOGN, GA, GB>(sh[src], as, tid);
+  __syncthreads();
+  u64* o = rec + (size_t)poly * KU * N;
+  for (int e = threadIdx.x; e < TILE; e += NS * TPB) {
+    const int row = e / C, col = e % C;
+    u64 v[4];
+#pragma unroll
+    for (int x = 0; x < NS; x++)
+      v[x] = shoup_mul(sh[x][lds_rc(row, col, C)], A.hatinv[x], A.hatinv_sh[x], mc[A.src[x]].q);
+    const u64 r = round_quotient(v, A);
+    u64 w[KU];
+#pragma unroll
+    for (int k = 0; k < KU; k++) w[k] = 0;
+#pragma unroll
+    for (int x = 0; x < NS; x++)
+#pragma unroll
+      for (int d = 0; d < 9; d++) {
+        const int k = 9 * x + d;
+        w[k >> 3] |= ((v[x] >> (7 * d)) & 127) << (8 * (k & 7));
+      }
+    w[(9 * NS) >> 3] |= r << (8 * ((9 * NS) & 7));
+    const size_t i = (size_t)row * T1 + c0 + col;
+#pragma unroll
+    for (int k = 0; k < KU; k++) o[(size_t)k * N + i] = w[k];
+  }
+}
+
+template <int LOGN, int GA, int GB, int GC, int GD>
+static void intt2_many(const DeviceTables& T, const LimbBases& lb, int nelem, const LimbMap& map, hipStream_t s,
+                       const FbcArgs* fa, u64* rec) {
+  constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
+  const int nlimbs = nelem * lb.per_elem;
+  dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
+  // the modulus pattern repeats every `per` limbs, and per_elem is a multiple of it
+  const int il = interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave);
+  const double pass_bytes = 16.0 * nlimbs * T.N;
+  {
+    ProfScope ps("ntt_inv_rows", s, pass_bytes, mm_map(T, map, nlimbs, 0.5 * T.N * (GC + GD)));
+    hipLaunchKernelGGL((k_intt_rows2_many<LOGN, GC, GD>), gr, dim3(TPB), 0, s, lb, map, T.ipsi, T.ipsi_sh, T.ipsi_f,
+                       T.mc, il);
+  }
+  if (!rec) {
+    ProfScope ps("ntt_inv_cols", s, pass_bytes, mm_map(T, map, nlimbs, 0.5 * T.N * (GA + GB)));
+    hipLaunchKernelGGL((k_intt_cols2_many<LOGN, GA, GB>), gc, dim3(TPB), 0, s, lb, map, T.ipsi, T.ipsi_sh, T.ipsi_f,
+                       T.mc);
+    return;
+  }
+  // the last pass ends in the digit records: the sources are read once and
+  // only the records ((ns + 1) words a coefficient) are written
+  const int npoly = nlimbs / lb.per;
+  Mm mm = mm_map(T, map, nlimbs, 0.5 * T.N * (GA + GB));
+  for (int a = 0; a < fa->ns; a++) mm.add(T.bits[fa->src[a]], (double)T.N * npoly);
+  ProfScope ps("ntt_inv_cols", s, 8.0 * T.N * (nlimbs + (double)npoly * (fa->ns + 1)), mm);
+  dim3 g((1 << LOGN) / R / C, npoly);
+  switch (lb.per) {
+    case 1: hipLaunchKernelGGL((k_intt_cols2_rec<LOGN, GA, GB, 1>), g, dim3(1 * TPB), 0, s, lb, map, *fa, rec, T.ipsi, T.ipsi_sh, T.ipsi_f, T.mc); break;
+    case 2: hipLaunchKernelGGL((k_intt_cols2_rec<LOGN, GA, GB, 2>), g, dim3(2 * TPB), 0, s, lb, map, *fa, rec, T.ipsi, T.ipsi_sh, T.ipsi_f, T.mc); break;
+    case 3: hipLaunchKernelGGL((k_intt_cols2_rec<LOGN, GA, GB, 3>), g, dim3(3 * TPB), 0, s, lb, map, *fa, rec, T.ipsi, T.ipsi_sh, T.ipsi_f, T.mc); break;
+    default: hipLaunchKernelGGL((k_intt_cols2_rec<LOGN, GA, GB, 4>), g, dim3(4 * TPB), 0, s, lb, map, *fa, rec, T.ipsi, T.ipsi_sh, T.ipsi_f, T.mc); break;
+  }
+}
+
+static FbcArgs fbc_args(const FbcTable& tab, int src_stride, int src_off);
+void launch_intt_many(const DeviceTables& T, const std::vector<u64*>& bases, int per_elem, int per, int stride,
+                      int off, const LimbMap& map, hipStream_t s, const FbcTable* rec_tab, u64* rec) {
+  if (map.n != per || per_elem % per != 0) throw std::runtime_error("launch_intt_many: bad limb pattern");
+  if (rec && (!rec_tab || rec_tab->ns != per || per > 4))
+    throw std::runtime_error("launch_intt_many: records need the ModDown table of the sources");
+  FbcArgs fa;
+  if (rec) fa = fbc_args(*rec_tab, per, 0);
+  for (size_t e0 = 0; e0 < bases.size(); e0 += MR_MAX) {
+    const int ne = (int)std::min(bases.size() - e0, (size_t)MR_MAX);
+    LimbBases lb;
+    for (int e = 0; e < MR_MAX; e++) lb.base[e] = e < ne ? bases[e0 + e] : nullptr;
+    lb.per_elem = per_elem;
+    lb.per = per;
+    lb.stride = stride;
+    lb.off = off;
+    u64* rc = rec ? rec + (size_t)e0 * (per_elem / per) * (per + 1) * T.N : nullptr;
+    if (!ntt_dispatch(T.logN, [&](auto sp) {
+          using S = decltype(sp);
+          intt2_many<NTT_SPLIT_ARGS>(T, lb, ne, map, s, rec ? &fa : nullptr, rc);
+        }))
+      throw std::runtime_error("launch_intt_many needs the register-blocked NTT (log N 12..16)");
+  }
+}
+
 typedef int mfma_i32x16 __attribute__((ext_vector_type(16)));
 // Two FP64 targets (33 to 46 bits) t0, t1 per work-group of 2 TPB threads.
 // v_mfma_i32_32x32x16_i8 takes, per lane l:
@@ -2437,14 +2546,11 @@ static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const Fbc
 // ModDown of npoly polynomials: xp_coef their P limbs in the coefficient
 // domain [npoly][ns][N], x the R_{Q_l P} data ([npoly][x_stride][N]), out
 // [npoly][nq][N]; false when the ring size has no register-blocked NTT
-bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
-                          const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
-                          int src_stride, int src_off) {
-  if (T.logN < 12 || T.logN > 16 || tab.ns > 4) return false;
+static FbcArgs fbc_args(const FbcTable& tab, int src_stride, int src_off) {
   FbcArgs A;
   A.ns = tab.ns;
-  A.src_stride = src_stride > 0 ? src_stride : tab.ns;
-  A.src_off = src_stride > 0 ? src_off : 0;
+  A.src_stride = src_stride;
+  A.src_off = src_off;
   for (int a = 0; a < tab.ns; a++) {
     A.src[a] = tab.src[a];
     A.hatinv[a] = tab.hatinv[a];
@@ -2457,12 +2563,25 @@ bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int
   A.hat_t_sh = tab.hat_t_sh;
   A.D_mod_t = tab.D_mod_t;
   A.hat_f = tab.hat_f;
-  // the MFMA lift takes targets of 33 to 46 bits and, beside them, Shoup-path
-  // targets above 46 bits
-  bool small_target = false;
-  for (int t = 0; t < nq; t++) small_target |= T.bits[t] <= 32;
-  const u64* cdig = g_knobs.fbc_mfma && tab.cdig && tab.kw > 0 && nq <= 64 && !small_target ? tab.cdig : nullptr;
-  {
+  return A;
+}
+// the MFMA lift takes targets of 33 to 46 bits and, beside them, Shoup-path
+// targets above 46 bits
+bool fbc_digit_path(const DeviceTables& T, const FbcTable& tab, int nq) {
+  if (!g_knobs.fbc_mfma || !tab.cdig || tab.kw <= 0 || nq > 64 || tab.ns > 4 || T.logN < 12 || T.logN > 16)
+    return false;
+  for (int t = 0; t < nq; t++)
+    if (T.bits[t] <= 32) return false;
+  return true;
+}
+bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
+                          const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
+                          int src_stride, int src_off, bool v_ready) {
+  if (T.logN < 12 || T.logN > 16 || tab.ns > 4) return false;
+  const FbcArgs A = fbc_args(tab, src_stride > 0 ? src_stride : tab.ns, src_stride > 0 ? src_off : 0);
+  const u64* cdig = fbc_digit_path(T, tab, nq) ? tab.cdig : nullptr;
+  if (v_ready && !cdig) throw std::runtime_error("digit records given where the ModDown does not take them");
+  if (!v_ready) {
     Mm mm;
     for (int a = 0; a < tab.ns; a++) mm.add(T.bits[tab.src[a]], (double)T.N * npoly);
     ProfScope ps("fbc_prep", s, 8.0 * T.N * npoly * (2.0 * tab.ns + 1), mm);

@@ -179,11 +179,16 @@ struct HeCtxImpl {
                       const std::vector<const u64*>& masks, bool accumulate);
   // consume: x's special-prime limbs (and q_l for moddown_rescale) may be
   // overwritten (x is a temporary the caller drops afterwards)
-  HeCt moddown(const HeCt& x, int out_level = -1, bool consume = false, bool src_ready = false);
-  void moddown_to(const HeCt& x, int out_level, u64* out, bool consume = false, bool src_ready = false);
+  HeCt moddown(const HeCt& x, int out_level = -1, bool consume = false, bool src_ready = false,
+               const u64* rec = nullptr);
+  void moddown_to(const HeCt& x, int out_level, u64* out, bool consume = false, bool src_ready = false,
+                  const u64* rec = nullptr);
   // ModDown and Rescale as one rounding by P q_l (a variant)
-  HeCt moddown_rescale(const HeCt& x, int out_level = -1, bool consume = false, bool src_ready = false);
-  void moddown_sources(const std::vector<HeCt*>& xs, bool with_rescale);
+  HeCt moddown_rescale(const HeCt& x, int out_level = -1, bool consume = false, bool src_ready = false,
+                       const u64* rec = nullptr);
+  // returns the digit records of the elements' ModDown sources when the
+  // int8 lift takes them (element e's at rec + e * rec_stride), else empty
+  DevBuf moddown_sources(const std::vector<HeCt*>& xs, bool with_rescale, size_t* rec_stride = nullptr);
   HeCt keyswitch(const u64* d, int level, u64 g_key, int B = 1);
   HeCt mult(const HeCt& a, const HeCt& b);
   HeCt rotate(const HeCt& x, long step);

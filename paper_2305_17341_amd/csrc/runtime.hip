@@ -856,19 +856,20 @@ void HeCtxImpl::hoisted_masked(const HeCt& x, const u64* digits, const std::vect
 
 // ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact
 // centred residue; out_level < l keeps (and computes) only the limbs up to it
-HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume, bool src_ready) {
+HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume, bool src_ready, const u64* rec) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   if (out_level < 0) out_level = x.level;
   if (out_level > x.level) fail(HE_ELEVEL, "moddown cannot raise the level");
   HeCt c = ct_new(out_level, false, x.scale, x.B);
-  moddown_to(x, out_level, c.d.p, consume, src_ready);
+  moddown_to(x, out_level, c.d.p, consume, src_ready, rec);
   return c;
 }
 // the same into out [2][B][out_level + 1][N].  consume: x's special-prime
 // limbs are brought to the coefficient domain in place (x is left with them
 // so) instead of in a gathered copy; src_ready: that was done already
-// (moddown_sources over a set of elements)
-void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume, bool src_ready) {
+// (moddown_sources over a set of elements), and rec, when given, holds their
+// digit records
+void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume, bool src_ready, const u64* rec) {
   int nq = nq_of(out_level), nqp = nqp_of(x.level);
   const int np = (int)x.polys();
   DevBuf y(&pool, (size_t)np * nq * N);
@@ -880,9 +881,10 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume,
     pm.slot_stride = (short)x.nlimbs;
     pm.slot_off = (short)nq_of(x.level);
     if (!src_ready) launch_ntt(T, x.d.p, np * alpha, pm, true, stream);
-    DevBuf V(&pool, (size_t)np * (down.ns + 1) * N);
-    if (!launch_moddown_fused(T, x.d.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, V.p, stream, x.nlimbs,
-                              nq_of(x.level)))
+    DevBuf V;
+    if (!rec) V = DevBuf(&pool, (size_t)np * (down.ns + 1) * N);
+    if (!launch_moddown_fused(T, x.d.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, rec ? (u64*)rec : V.p, stream,
+                              x.nlimbs, nq_of(x.level), rec != nullptr))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
     n_moddown += x.B;
     return;
@@ -905,7 +907,7 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume,
 // round(x / (P q_l)) in R_{Q_{l-1}} (or a lower out_level: only the kept
 // limbs are computed): the exact centred lift of x mod P q_l from the limbs
 // q_l, p_1..p_alpha, then (x - lift) (P q_l)^-1 on the limbs below q_l.
-HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool src_ready) {
+HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool src_ready, const u64* rec) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   const int l = x.level;
   if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
@@ -929,8 +931,10 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool
     if (!src_ready) launch_ntt(T, x.d.p, np * ns, sm, true, stream);
     DevBuf y(&pool, (size_t)np * nout * N);
     HeCt c = ct_new(out_level, false, x.scale / (double)mods[l], x.B);
-    DevBuf V(&pool, (size_t)np * (ns + 1) * N);
-    if (!launch_moddown_fused(T, x.d.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, V.p, stream, x.nlimbs, l))
+    DevBuf V;
+    if (!rec) V = DevBuf(&pool, (size_t)np * (ns + 1) * N);
+    if (!launch_moddown_fused(T, x.d.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, rec ? (u64*)rec : V.p, stream,
+                              x.nlimbs, l, rec != nullptr))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
     n_moddown += x.B;
     return c;
@@ -962,8 +966,12 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool
 // brought to the coefficient domain in place by one launch per 64 elements:
 // the special-prime limbs, and q_l too when the ModDown is fused with the
 // Rescale.  The elements are then ModDown'ed with consume and src_ready.
-void HeCtxImpl::moddown_sources(const std::vector<HeCt*>& xs, bool with_rescale) {
-  if (xs.empty() || !fused_conv) return;
+// Where the ModDown takes digit records (the int8 lift into every target
+// limb up to the elements' level), the transform's last pass writes the
+// records instead of the limbs, and they are returned for the ModDowns
+// (element e's at rec + e * rec_stride).
+DevBuf HeCtxImpl::moddown_sources(const std::vector<HeCt*>& xs, bool with_rescale, size_t* rec_stride) {
+  if (xs.empty() || !fused_conv) return DevBuf();
   const HeCt& x0 = *xs[0];
   std::vector<u64*> bases;
   for (HeCt* x : xs) {
@@ -972,16 +980,29 @@ void HeCtxImpl::moddown_sources(const std::vector<HeCt*>& xs, bool with_rescale)
   }
   const int l = x0.level, np = (int)x0.polys();
   LimbMap m;
+  const FbcTable* tab;
+  int per, off, nq;
   if (with_rescale) {
-    m.n = alpha + 1;
+    m.n = per = alpha + 1;
     m.idx[0] = (short)l;
     for (int k = 0; k < alpha; k++) m.idx[1 + k] = (short)(L + 1 + k);
-    launch_intt_many(T, bases, np * (alpha + 1), alpha + 1, x0.nlimbs, l, m, stream);
+    tab = &down_rs[l];
+    off = l;
+    nq = l;
   } else {
-    m.n = alpha;
+    m.n = per = alpha;
     for (int k = 0; k < alpha; k++) m.idx[k] = (short)(L + 1 + k);
-    launch_intt_many(T, bases, np * alpha, alpha, x0.nlimbs, nq_of(l), m, stream);
+    tab = &down;
+    off = nq_of(l);
+    nq = nq_of(l);
   }
+  DevBuf rec;
+  if (rec_stride && fbc_digit_path(T, *tab, nq)) {
+    *rec_stride = (size_t)np * (per + 1) * N;
+    rec = DevBuf(&pool, xs.size() * *rec_stride);
+  }
+  launch_intt_many(T, bases, np * per, per, x0.nlimbs, off, m, stream, rec.p ? tab : nullptr, rec.p);
+  return rec;
 }
 
 HeCt HeCtxImpl::keyswitch(const u64* d, int level, u64 g_key, int B) {
@@ -1593,20 +1614,23 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       lift1 = HeCt();
       lift2 = HeCt();
     }
+    DevBuf rec;
+    size_t rs = 0;
     {
       std::vector<HeCt*> srcs;
       for (auto& a : acc) srcs.push_back(&a);
-      moddown_sources(srcs, fused_rs);
+      rec = moddown_sources(srcs, fused_rs, &rs);
     }
     const bool ready = fused_conv;
     for (int r = 0; r < nr; r++) {
       int k = b * n1z + r;
       HeCt sum = std::move(acc[r]);
       const int ol = out_level >= 0 ? std::min(out_level, lvl - 1) : -1;
+      const u64* rr = rec.p ? rec.p + r * rs : nullptr;
       if (fused_rs) {
-        Ak[k] = moddown_rescale(sum, ol, true, ready);
+        Ak[k] = moddown_rescale(sum, ol, true, ready, rr);
       } else {
-        HeCt md = moddown(sum, -1, true, ready);
+        HeCt md = moddown(sum, -1, true, ready, rr);
         Ak[k] = rescale(md, ol);
       }
       Ak[k].scale = Bb.scale;
@@ -1633,13 +1657,15 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int n
       hs = hoisted_multi(Cb, d1.p, gs);
     }
     Bk[b * n1t] = ol < lvl ? drop(Cb, ol) : ct_copy(Cb);
+    DevBuf rec;
+    size_t rs = 0;
     {
       std::vector<HeCt*> srcs;
       for (auto& h : hs) srcs.push_back(&h);
-      moddown_sources(srcs, false);
+      rec = moddown_sources(srcs, false, &rs);
     }
     for (int r = 1; r < nr; r++) {
-      Bk[b * n1t + r] = moddown(hs[r - 1], ol, true, fused_conv);
+      Bk[b * n1t + r] = moddown(hs[r - 1], ol, true, fused_conv, rec.p ? rec.p + (r - 1) * rs : nullptr);
       hs[r - 1] = HeCt();
     }
   }
