@@ -1729,58 +1729,124 @@ __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, i
 // per pair reads and writes the sum for every pair.  The sum of the exact
 // signed products (at most 2 TENSOR_PAIRS + 1 terms below q each) stays below
 // 2^52, so the residues are those of one pair at a time.
-#define TENSOR_PAIRS 8
+#define TENSOR_PAIRS 16
 struct TensorPairs {
   const u64* a[TENSOR_PAIRS];
   const u64* b[TENSOR_PAIRS];
 };
-template <bool ACC>
-__global__ void k_tensor_multi(u64* out, TensorPairs P, int npairs, int nl, int nt, int logN,
-                               const ModConst* __restrict__ mc) {
+// V = 2: two consecutive coefficients per thread, 16-byte loads and stores;
+// the next pair's four loads are in flight while a pair is multiplied
+template <bool ACC, int V>
+__global__ void __launch_bounds__(TPB) k_tensor_multi(u64* out, TensorPairs P, int npairs, int nl, int nt, int logN,
+                                                      const ModConst* __restrict__ mc) {
   const u64 N = 1ull << logN;
-  u32 i = blockIdx.x * TPB + threadIdx.x;
-  int k = blockIdx.y;
+  const u32 i = (blockIdx.x * TPB + threadIdx.x) * V;
+  const int k = blockIdx.y;
   if (i >= N) return;
   const ModConst mk = mc[k % nl];
   const size_t o0 = (size_t)k * N + i, o1 = (size_t)(nt + k) * N + i, o2 = (size_t)(2 * nt + k) * N + i;
+  struct W {
+    u64 v[V];
+  };
+  auto ld = [](const u64* p) {
+    W w;
+    if (V == 2) {
+      const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(p);
+      w.v[0] = x.x;
+      w.v[V - 1] = x.y;
+    } else {
+      w.v[0] = *p;
+    }
+    return w;
+  };
+  auto st = [](u64* p, const u64 (&r)[V]) {
+    if (V == 2) {
+      ulonglong2 y;
+      y.x = r[0];
+      y.y = r[V - 1];
+      *reinterpret_cast<ulonglong2*>(p) = y;
+    } else {
+      *p = r[0];
+    }
+  };
+  W a0n = ld(P.a[0] + o0), a1n = ld(P.a[0] + o1), b0n = ld(P.b[0] + o0), b1n = ld(P.b[0] + o1);
+  u64 r0[V], r1[V], r2[V];
   if (mk.bits <= F64_LAZY_BITS) {
     const double q = mk.qf, qi = mk.qinvf;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    double s0[V], s1[V], s2[V];
     if (ACC) {
-      s0 = u2d(out[o0]);
-      s1 = u2d(out[o1]);
-      s2 = u2d(out[o2]);
+      const W c0 = ld(out + o0), c1 = ld(out + o1), c2 = ld(out + o2);
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        s0[e] = u2d(c0.v[e]);
+        s1[e] = u2d(c1.v[e]);
+        s2[e] = u2d(c2.v[e]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; e++) s0[e] = s1[e] = s2[e] = 0.0;
     }
     for (int p = 0; p < npairs; p++) {
-      const double x0 = u2d(P.a[p][o0]), x1 = u2d(P.a[p][o1]), y0 = u2d(P.b[p][o0]), y1 = u2d(P.b[p][o1]);
-      s0 += f64_mulmod_signed(x0, y0, q, qi);
-      s1 += f64_mulmod_signed(x0, y1, q, qi) + f64_mulmod_signed(x1, y0, q, qi);
-      s2 += f64_mulmod_signed(x1, y1, q, qi);
+      const W a0 = a0n, a1 = a1n, b0 = b0n, b1 = b1n;
+      if (p + 1 < npairs) {
+        a0n = ld(P.a[p + 1] + o0);
+        a1n = ld(P.a[p + 1] + o1);
+        b0n = ld(P.b[p + 1] + o0);
+        b1n = ld(P.b[p + 1] + o1);
+      }
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        const double x0 = u2d(a0.v[e]), x1 = u2d(a1.v[e]), y0 = u2d(b0.v[e]), y1 = u2d(b1.v[e]);
+        s0[e] += f64_mulmod_signed(x0, y0, q, qi);
+        s1[e] += f64_mulmod_signed(x0, y1, q, qi) + f64_mulmod_signed(x1, y0, q, qi);
+        s2[e] += f64_mulmod_signed(x1, y1, q, qi);
+      }
     }
-    out[o0] = d2u(f64_canon(s0, q, qi));
-    out[o1] = d2u(f64_canon(s1, q, qi));
-    out[o2] = d2u(f64_canon(s2, q, qi));
-    return;
+#pragma unroll
+    for (int e = 0; e < V; e++) {
+      r0[e] = d2u(f64_canon(s0[e], q, qi));
+      r1[e] = d2u(f64_canon(s1[e], q, qi));
+      r2[e] = d2u(f64_canon(s2[e], q, qi));
+    }
+  } else {
+    if (ACC) {
+      const W c0 = ld(out + o0), c1 = ld(out + o1), c2 = ld(out + o2);
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        r0[e] = c0.v[e];
+        r1[e] = c1.v[e];
+        r2[e] = c2.v[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; e++) r0[e] = r1[e] = r2[e] = 0;
+    }
+    for (int p = 0; p < npairs; p++) {
+      const W a0 = a0n, a1 = a1n, b0 = b0n, b1 = b1n;
+      if (p + 1 < npairs) {
+        a0n = ld(P.a[p + 1] + o0);
+        a1n = ld(P.a[p + 1] + o1);
+        b0n = ld(P.b[p + 1] + o0);
+        b1n = ld(P.b[p + 1] + o1);
+      }
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        r0[e] = add_mod(r0[e], mul_mod_any(a0.v[e], b0.v[e], mk), mk.q);
+        r1[e] = add_mod(r1[e], add_mod(mul_mod_any(a0.v[e], b1.v[e], mk), mul_mod_any(a1.v[e], b0.v[e], mk), mk.q),
+                        mk.q);
+        r2[e] = add_mod(r2[e], mul_mod_any(a1.v[e], b1.v[e], mk), mk.q);
+      }
+    }
   }
-  u64 t0 = 0, t1 = 0, t2 = 0;
-  if (ACC) {
-    t0 = out[o0];
-    t1 = out[o1];
-    t2 = out[o2];
-  }
-  for (int p = 0; p < npairs; p++) {
-    const u64 a0 = P.a[p][o0], a1 = P.a[p][o1], b0 = P.b[p][o0], b1 = P.b[p][o1];
-    t0 = add_mod(t0, mul_mod_any(a0, b0, mk), mk.q);
-    t1 = add_mod(t1, add_mod(mul_mod_any(a0, b1, mk), mul_mod_any(a1, b0, mk), mk.q), mk.q);
-    t2 = add_mod(t2, mul_mod_any(a1, b1, mk), mk.q);
-  }
-  out[o0] = t0;
-  out[o1] = t1;
-  out[o2] = t2;
+  st(out + o0, r0);
+  st(out + o1, r1);
+  st(out + o2, r2);
 }
 void launch_tensor_sum(const DeviceTables& T, u64* out3, const u64* const* a, const u64* const* b, int npairs, int nl,
                        int batch, bool accumulate, hipStream_t s) {
   const int nt = nl * batch;
+  // two coefficients per thread where the ring fills whole work-groups
+  const bool v2 = T.N >= (u64)(2 * TPB);
   for (int p0 = 0; p0 < npairs; p0 += TENSOR_PAIRS) {
     const int np = std::min(TENSOR_PAIRS, npairs - p0);
     TensorPairs P;
@@ -1790,9 +1856,11 @@ void launch_tensor_sum(const DeviceTables& T, u64* out3, const u64* const* a, co
     }
     const bool acc = accumulate || p0 > 0;
     ProfScope ps("tensor", s, 8.0 * T.N * (4.0 * np + (acc ? 6 : 3)) * nt, mm_q(T, nl, 4.0 * T.N * np, batch));
-    dim3 grid(cdiv(T.N, TPB), nt);
-    if (acc) hipLaunchKernelGGL(k_tensor_multi<true>, grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
-    else hipLaunchKernelGGL(k_tensor_multi<false>, grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
+    dim3 grid(cdiv(T.N, TPB * (v2 ? 2 : 1)), nt);
+    if (acc && v2) hipLaunchKernelGGL((k_tensor_multi<true, 2>), grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
+    else if (acc) hipLaunchKernelGGL((k_tensor_multi<true, 1>), grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
+    else if (v2) hipLaunchKernelGGL((k_tensor_multi<false, 2>), grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
+    else hipLaunchKernelGGL((k_tensor_multi<false, 1>), grid, dim3(TPB), 0, s, out3, P, np, nl, nt, T.logN, T.mc);
   }
 }
 
