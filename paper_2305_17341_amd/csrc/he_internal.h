@@ -12,6 +12,8 @@
 typedef uint64_t u64;
 typedef int64_t i64;
 typedef uint32_t u32;
+typedef uint16_t u16;
+typedef uint8_t u8;
 
 #define HE_MAXMOD 64
 

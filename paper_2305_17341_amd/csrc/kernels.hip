@@ -831,8 +831,30 @@ struct SubScaleF64 {
 };
 
 // Block pass body: blocks of T1 = 2^(GC+GD) words, K = TILE / T1 blocks per work-group.
-template <int LOGN, int GC, int GD, bool INV, class A, class ST>
-__device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* sh, const A& ar, ST st) {
+// Loads of the forward block pass: the limb's words, or (LoadPacked) the
+// 32-bit plane and the high plane of a limb stored packed.
+struct LoadWords {
+  template <class A>
+  __device__ __forceinline__ typename A::V operator()(const u64* a, size_t idx, const A& ar) const {
+    return ar.load(a[idx]);
+  }
+};
+// Limbs of FP64 moduli (below 2^46) stored packed within their N-word slot:
+// the low 32 bits of every residue first (4N bytes), then the high bits, one
+// byte each for moduli of at most 40 bits (HB = 1), two bytes otherwise.
+template <int HB>
+struct LoadPacked {
+  const u32* lo;
+  const void* hi;
+  template <class A>
+  __device__ __forceinline__ typename A::V operator()(const u64*, size_t idx, const A& ar) const {
+    const u64 h = HB == 1 ? (u64) static_cast<const u8*>(hi)[idx] : (u64) static_cast<const u16*>(hi)[idx];
+    return ar.load((u64)lo[idx] | (h << 32));
+  }
+};
+template <int LOGN, int GC, int GD, bool INV, class A, class ST, class YL = LoadWords>
+__device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* sh, const A& ar, ST st,
+                                               const YL& yl = YL()) {
   typedef typename A::V V;
   constexpr int S2 = GC + GD, T1 = 1 << S2, S1 = LOGN - S2;
   const int tid = threadIdx.x;
@@ -846,7 +868,7 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
     for (int k = 0; k < ITC; k++) {
       const int it = tid + TPB * k, el = it % LOWC, b = it / LOWC;
 #pragma unroll
-      for (int mm = 0; mm < (1 << GC); mm++) v[mm] = ar.load(a[(size_t)b * T1 + el + (mm << GD)]);
+      for (int mm = 0; mm < (1 << GC); mm++) v[mm] = yl(a, (size_t)b * T1 + el + (mm << GD), ar);
       fwd_group<GC>(v, S1, (u32)(blk0 + b), ar);
 #pragma unroll
       for (int mm = 0; mm < (1 << GC); mm++) sh[lds_be(b, el + (mm << GD), T1)] = v[mm];
@@ -1020,7 +1042,8 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2_sub(u64* data, LimbMap map, c
                                                        const u64* __restrict__ twsh, const double* __restrict__ twf,
                                                        const ModConst* __restrict__ mc, int nq,
                                                        const u64* __restrict__ x, int x_stride,
-                                                       const u64* __restrict__ cpairs, u64* out, int il) {
+                                                       const u64* __restrict__ cpairs, u64* out, int il,
+                                                       int packed) {
   constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1;
   __shared__ u64 sh[LDS_WORDS];
   const int limb = grid_limb(blockIdx.y, il);
@@ -1036,8 +1059,19 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2_sub(u64* data, LimbMap map, c
   const ModConst mk = mc[m];
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
-    ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, reinterpret_cast<double*>(sh), ar,
-                                        SubScaleF64{oa, xa, u2d(cpairs[2 * t]), mk.qf, mk.qinvf});
+    const SubScaleF64 st{oa, xa, u2d(cpairs[2 * t]), mk.qf, mk.qinvf};
+    if (packed) {
+      // y of this limb packed by the column pass (the int8 lift's)
+      const u32* lo = reinterpret_cast<const u32*>(data + (size_t)limb * N);
+      if (mk.bits <= 40)
+        ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, reinterpret_cast<double*>(sh), ar, st,
+                                            LoadPacked<1>{lo + off, reinterpret_cast<const u8*>(lo + N) + off});
+      else
+        ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, reinterpret_cast<double*>(sh), ar, st,
+                                            LoadPacked<2>{lo + off, reinterpret_cast<const u16*>(lo + N) + off});
+    } else {
+      ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, reinterpret_cast<double*>(sh), ar, st);
+    }
   } else {
     ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
     ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, sh, ar, SubScaleShoup{oa, xa, cpairs[2 * t], cpairs[2 * t + 1], mk.q});
@@ -1193,7 +1227,8 @@ static void ntt2_modup(const DeviceTables& T, u64* digits, const ModupSrc& S, in
 
 template <int LOGN, int GA, int GB, int GC, int GD>
 static void ntt2_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,
-                         int x_stride, const u64* cpairs, u64* out, hipStream_t s, bool do_cols = true) {
+                         int x_stride, const u64* cpairs, u64* out, hipStream_t s, bool do_cols = true,
+                         bool packed = false) {
   constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
   const int nlimbs = nq * npoly;
   dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
@@ -1204,7 +1239,8 @@ static void ntt2_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const
   }
   ProfScope ps("ntt_fwd_rows_sub", s, 24.0 * nlimbs * T.N, mm_map(T, map, nlimbs, 0.5 * T.N * (GC + GD) + T.N));
   hipLaunchKernelGGL((k_ntt_rows2_sub<LOGN, GC, GD>), gr, dim3(TPB), 0, s, y, map, T.psi, T.psi_sh, T.psi_f, T.mc,
-                     nq, x, x_stride, cpairs, out, interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave));
+                     nq, x, x_stride, cpairs, out, interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave),
+                     packed ? 1 : 0);
 }
 
 template <int LOGN, int GA, int GB, int GC, int GD>
@@ -2557,9 +2593,13 @@ __global__ void __launch_bounds__(2 * TPB) __attribute__((amdgpu_waves_per_eu(4)
     }
   }
   __syncthreads();
-  // second group: r bits [0, GB) -> stages GA..S1-1
+  // second group: r bits [0, GB) -> stages GA..S1-1; y stored packed (the
+  // block pass reads it with LoadPacked)
   const bool store = !hl || has1;
-  u64* a = y + ((size_t)p * nq + t) * N;
+  u32* lo = reinterpret_cast<u32*>(y + ((size_t)p * nq + t) * N);
+  u8* hi1 = reinterpret_cast<u8*>(lo + N);
+  u16* hi2 = reinterpret_cast<u16*>(lo + N);
+  const bool hb1 = mk.bits <= 40;
 #pragma unroll
   for (int k = 0; k < ITB; k++) {
     const int it = tid + TPB * k, c = it % C, rh = it / C;
@@ -2569,7 +2609,13 @@ __global__ void __launch_bounds__(2 * TPB) __attribute__((amdgpu_waves_per_eu(4)
     fwd_group<GB>(v, GA, (u32)rh, ar);
     if (store)
 #pragma unroll
-      for (int mm = 0; mm < (1 << GB); mm++) a[(size_t)((rh << GB) + mm) * T1 + c0 + c] = ar.store(v[mm]);
+      for (int mm = 0; mm < (1 << GB); mm++) {
+        const size_t idx = (size_t)((rh << GB) + mm) * T1 + c0 + c;
+        const u64 w = ar.store(v[mm]);
+        lo[idx] = (u32)w;
+        if (hb1) hi1[idx] = (u8)(w >> 32);
+        else hi2[idx] = (u16)(w >> 32);
+      }
   }
 }
 
@@ -2609,7 +2655,7 @@ static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const Fbc
       }
     }
   }
-  ntt2_fwd_sub<LOGN, GA, GB, GC, GD>(T, y, nq, npoly, map, x, x_stride, pinv, out, s, false);
+  ntt2_fwd_sub<LOGN, GA, GB, GC, GD>(T, y, nq, npoly, map, x, x_stride, pinv, out, s, false, cdig != nullptr);
 }
 // ModDown of npoly polynomials: xp_coef their P limbs in the coefficient
 // domain [npoly][ns][N], x the R_{Q_l P} data ([npoly][x_stride][N]), out
