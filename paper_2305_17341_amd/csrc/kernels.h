@@ -35,6 +35,11 @@ struct DeviceTables {
 
 // transforms
 void launch_ntt(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse, hipStream_t s);
+// Inverse NTT of src into data (same layout) with limb k's result times
+// scales[2 m] (Shoup pairs by modulus m) in place of N^-1; false (nothing
+// launched) without the register-blocked NTT
+bool launch_intt_scaled(const DeviceTables& T, u64* data, const u64* src, int nlimbs, const LimbMap& map,
+                        const u64* scales, hipStream_t s);
 // forward NTT of npoly x nq limbs y, then out = (x - y) c mod q_t with x
 // [npoly][x_stride][N] and c pairs (value, Shoup companion) per t < nq
 void launch_ntt_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,

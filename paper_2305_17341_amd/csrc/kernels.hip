@@ -839,6 +839,14 @@ struct LoadWords {
     return ar.load(a[idx]);
   }
 };
+// the words of another array at the same place (an out-of-place pass)
+struct LoadFrom {
+  const u64* p;
+  template <class A>
+  __device__ __forceinline__ typename A::V operator()(const u64*, size_t idx, const A& ar) const {
+    return ar.load(p[idx]);
+  }
+};
 // Limbs of FP64 moduli (below 2^46) stored packed within their N-word slot:
 // the low 32 bits of every residue first (4N bytes), then the high bits, one
 // byte each for moduli of at most 40 bits (HB = 1), two bytes otherwise.
@@ -899,7 +907,7 @@ __device__ __forceinline__ void ntt_rows2_body(u64* a, int blk0, typename A::V* 
     // all sixteen loads of a thread in flight before the first LDS store
     static_assert(TILE / TPB == 16, "one register per coefficient of a thread");
 #pragma unroll
-    for (int k = 0; k < TILE / TPB; k++) v[k] = ar.load(a[tid + k * TPB]);
+    for (int k = 0; k < TILE / TPB; k++) v[k] = yl(a, tid + k * TPB, ar);
 #pragma unroll
     for (int k = 0; k < TILE / TPB; k++) {
       const int e = tid + k * TPB;
@@ -1272,6 +1280,78 @@ static void ntt2(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& ma
   }
 }
 
+
+// Inverse NTT from src into data whose last stage scales limb k by
+// scales[2 m] (Shoup pair; m its modulus) in place of N^-1: Decompose's
+// coefficient-domain sources times their hat inverses, from the input limbs.
+template <int LOGN, int GC, int GD>
+__global__ void __launch_bounds__(TPB) k_intt_rows2_src(u64* data, const u64* __restrict__ src, LimbMap map,
+                                                        const u64* __restrict__ tw, const u64* __restrict__ twsh,
+                                                        const double* __restrict__ twf,
+                                                        const ModConst* __restrict__ mc, int il) {
+  constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = grid_limb(blockIdx.y, il);
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << LOGN;
+  const int blk0 = blockIdx.x * K;
+  const size_t off = limb_slot(map, limb) * N + (size_t)blk0 * T1;
+  u64* a = data + off;
+  const ModConst mk = mc[m];
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
+    ntt_rows2_body<LOGN, GC, GD, true>(a, blk0, reinterpret_cast<double*>(sh), ar, StorePlain<F64LazyArith>{a, ar},
+                                       LoadFrom{src + off});
+  } else {
+    ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, mk.ninv, mk.ninv_sh};
+    ntt_rows2_body<LOGN, GC, GD, true>(a, blk0, sh, ar, StorePlain<ShoupArith>{a, ar}, LoadFrom{src + off});
+  }
+}
+template <int LOGN, int GA, int GB>
+__global__ void __launch_bounds__(TPB) k_intt_cols2_scaled(u64* data, LimbMap map, const u64* __restrict__ scales,
+                                                           const u64* __restrict__ tw, const u64* __restrict__ twsh,
+                                                           const double* __restrict__ twf,
+                                                           const ModConst* __restrict__ mc) {
+  constexpr int S1 = GA + GB, R = 1 << S1, C = TILE / R;
+  __shared__ u64 sh[LDS_WORDS];
+  const int limb = blockIdx.y;
+  const int m = limb_mod(map, limb);
+  if (m < 0) return;
+  const u64 N = 1ull << LOGN;
+  u64* a = data + limb_slot(map, limb) * N;
+  const int c0 = blockIdx.x * C;
+  const ModConst mk = mc[m];
+  const u64 c = scales[2 * m], csh = scales[2 * m + 1];
+  if (mk.bits <= F64_LAZY_BITS) {
+    F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)c};
+    ntt_cols2_body<LOGN, GA, GB, true>(a, c0, reinterpret_cast<double*>(sh), ar, LoadPlain{a});
+  } else {
+    ShoupArith ar{tw + (size_t)m * N, twsh + (size_t)m * N, mk.q, c, csh};
+    ntt_cols2_body<LOGN, GA, GB, true>(a, c0, sh, ar, LoadPlain{a});
+  }
+}
+bool launch_intt_scaled(const DeviceTables& T, u64* data, const u64* src, int nlimbs, const LimbMap& map,
+                        const u64* scales, hipStream_t s) {
+  if (nlimbs <= 0) return true;
+  if (map.slot_per > 0) return false;
+  return ntt_dispatch(T.logN, [&](auto sp) {
+    using S = decltype(sp);
+    constexpr int LOGN = S::LOGN, GA = S::GA, GB = S::GB, GC = S::GC, GD = S::GD;
+    constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
+    dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
+    const int il = interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave);
+    const double pass_bytes = 16.0 * nlimbs * T.N;
+    {
+      ProfScope ps("ntt_inv_rows", s, pass_bytes, mm_map(T, map, nlimbs, 0.5 * T.N * (GC + GD)));
+      hipLaunchKernelGGL((k_intt_rows2_src<LOGN, GC, GD>), gr, dim3(TPB), 0, s, data, src, map, T.ipsi, T.ipsi_sh,
+                         T.ipsi_f, T.mc, il);
+    }
+    ProfScope ps("ntt_inv_cols", s, pass_bytes, mm_map(T, map, nlimbs, 0.5 * T.N * (GA + GB)));
+    hipLaunchKernelGGL((k_intt_cols2_scaled<LOGN, GA, GB>), gc, dim3(TPB), 0, s, data, map, scales, T.ipsi,
+                       T.ipsi_sh, T.ipsi_f, T.mc);
+  });
+}
 
 static bool ntt_register_blocked(const DeviceTables& T, u64* data, int nlimbs, const LimbMap& map, bool inverse,
                                  double pass_bytes, hipStream_t s) {

@@ -122,6 +122,7 @@ struct HeCtxImpl {
   FbcTable down;                          // P -> Q
   DevBuf pmod, pinv, qlinv;
   DevBuf pqlinv;  // [level][nmods][2]: (P q_l)^-1 mod q_k with Shoup companions
+  DevBuf up_scale;  // [level][nmods][2]: N^-1 hatinv_t mod q_t (Decompose's digit sources)
   DevBuf s_ntt, pk;
   bool have_sk = false;
   std::map<u64, DevBuf> keys;             // Galois element -> key; 0 = relinearisation

@@ -529,6 +529,20 @@ void HeCtxImpl::init(const he_params* p, const he_device* dev, u64 seed_) {
     pqlinv = DevBuf(&pool, pq.size());
     hip_check(hipMemcpy(pqlinv.p, pq.data(), pq.size() * 8, hipMemcpyHostToDevice), "pqlinv");
   }
+  {
+    // Decompose's inverse transform ends with N^-1 times limb t's hat inverse
+    // in its digit (one constant a limb, Shoup pairs)
+    std::vector<u64> us((size_t)(L + 1) * nmods * 2, 0);
+    for (int l = 0; l <= L; l++)
+      for (int t = 0; t <= l; t++) {
+        const u64 q = mods[t];
+        const u64 v = hmul(hinv(N % q, q), up[l][t / alpha].hatinv[t % alpha], q);
+        us[((size_t)l * nmods + t) * 2] = v;
+        us[((size_t)l * nmods + t) * 2 + 1] = shoup_pre(v, q);
+      }
+    up_scale = DevBuf(&pool, us.size());
+    hip_check(hipMemcpy(up_scale.p, us.data(), us.size() * 8, hipMemcpyHostToDevice), "up_scale");
+  }
   hip_check(hipDeviceSynchronize(), "init");
 }
 
@@ -766,8 +780,10 @@ HeCt HeCtxImpl::rescale(const HeCt& a, int out_level) {
 DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
   int nq = nq_of(level), nqp = nqp_of(level), bl = beta_at(level);
   DevBuf coef(&pool, (size_t)B * nq * N);
-  copy_limbs(coef.p, d, (size_t)B * nq, "copy_decompose");
-  launch_ntt(T, coef.p, B * nq, qmap(nq), true, stream);
+  if (!fused_conv) {
+    copy_limbs(coef.p, d, (size_t)B * nq, "copy_decompose");
+    launch_ntt(T, coef.p, B * nq, qmap(nq), true, stream);
+  }
   DevBuf dig(&pool, (size_t)B * bl * nqp * N);
   LimbMap m;
   m.n = bl * nqp;
@@ -778,14 +794,19 @@ DevBuf HeCtxImpl::decompose(const u64* d, int level, int B) {
       m.idx[j * nqp + pos] = own ? (short)-1 : (short)qp_mod(level, pos);
     }
   if (fused_conv) {
-    // sources times their hat inverses, then conversion + NTT in one pass pair
+    // sources times their hat inverses (the inverse transform's last scaling,
+    // read from d directly), then conversion + NTT in one pass pair
     const std::vector<FbcTable>& tabs = up[level];
-    std::vector<u64> hinv((size_t)2 * nq);
-    for (int t = 0; t < nq; t++) {
-      hinv[2 * t] = tabs[t / alpha].hatinv[t % alpha];
-      hinv[2 * t + 1] = tabs[t / alpha].hatinv_sh[t % alpha];
+    if (!launch_intt_scaled(T, coef.p, d, B * nq, qmap(nq), up_scale.p + (size_t)level * nmods * 2, stream)) {
+      std::vector<u64> hinv((size_t)2 * nq);
+      for (int t = 0; t < nq; t++) {
+        hinv[2 * t] = tabs[t / alpha].hatinv[t % alpha];
+        hinv[2 * t + 1] = tabs[t / alpha].hatinv_sh[t % alpha];
+      }
+      copy_limbs(coef.p, d, (size_t)B * nq, "copy_decompose");
+      launch_ntt(T, coef.p, B * nq, qmap(nq), true, stream);
+      launch_mul_const(T, coef.p, coef.p, B * nq, hinv.data(), qmap(nq), stream);
     }
-    launch_mul_const(T, coef.p, coef.p, B * nq, hinv.data(), qmap(nq), stream);
     if (launch_modup_ntt(T, dig.p, coef.p, d, level, L, alpha, bl, tabs.data(), B, m, stream)) {
       n_decompose += B;
       return dig;
