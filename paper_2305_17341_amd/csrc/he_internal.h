@@ -204,6 +204,10 @@ struct HeCt {
   u64 N = 0;
   int level = 0;
   bool qp = false;
+  // limbs of FP64 moduli stored packed (a product side's ModDown output,
+  // read only by the tensor sums; every other operation takes unpacked
+  // elements)
+  bool packed = false;
   int nlimbs = 0;
   int B = 1;
   double scale = 1.0;

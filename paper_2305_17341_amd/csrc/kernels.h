@@ -81,9 +81,12 @@ void launch_mul_const(const DeviceTables& T, u64* out, const u64* a, int nlimbs,
 void launch_neg(const DeviceTables& T, u64* out, const u64* a, int nlimbs, const LimbMap& m, hipStream_t s);
 // batch pairs of ciphertexts [2][batch][nl] -> [3][batch][nl] (accumulate: added onto out3)
 // sum of npairs tensors (a[p], b[p] over Q_l, [2][B][nl] each) into the
-// three-component [3][B][nl] out3, or added onto it
+// three-component [3][B][nl] out3, or added onto it; a_packed[p] (b_packed)
+// set: a[p]'s limbs of FP64 moduli are stored packed (the fused ModDown's
+// pack_out layout)
 void launch_tensor_sum(const DeviceTables& T, u64* out3, const u64* const* a, const u64* const* b, int npairs, int nl,
-                       int batch, bool accumulate, hipStream_t s);
+                       int batch, bool accumulate, hipStream_t s, const bool* a_packed = nullptr,
+                       const bool* b_packed = nullptr);
 void launch_tensor(const DeviceTables& T, u64* out3, const u64* a, const u64* b, int nl, int batch, bool accumulate,
                    hipStream_t s);
 void launch_int_to_limbs(const DeviceTables& T, u64* out, const i64* in, int nlimbs, const LimbMap& m, hipStream_t s);
@@ -136,9 +139,12 @@ void launch_intt_many(const DeviceTables& T, const std::vector<u64*>& bases, int
 // whether a fused ModDown into nq target limbs with this table takes digit
 // records (the int8 lift); only then may V arrive filled (v_ready)
 bool fbc_digit_path(const DeviceTables& T, const FbcTable& tab, int nq);
+// pack_out: out's limbs of FP64 moduli (at most 46 bits) are stored packed in
+// their N-word slots: the low 32 bits of every residue, then one high byte
+// each (moduli of at most 40 bits) or two
 bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                           const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
-                          int src_stride = 0, int src_off = 0, bool v_ready = false);
+                          int src_stride = 0, int src_off = 0, bool v_ready = false, bool pack_out = false);
 // y[npoly][nq] = exact centred lift of the source limbs xp[npoly][ns] to each q_t
 void launch_fbc_to_q(const DeviceTables& T, u64* y, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                      hipStream_t s);

@@ -829,6 +829,26 @@ struct SubScaleF64 {
     out[e] = d2u(f64_canon(f64_mulmod_signed(u2d(xv[k]) - v, c, q, qinv), q, qinv));
   }
 };
+// the same with the output limb stored packed (the layout LoadPacked reads;
+// HB high bytes)
+template <int HB>
+struct SubScalePackedF64 {
+  u32* lo;
+  void* hi;
+  const u64* __restrict__ x;
+  double c, q, qinv;
+  u64 xv[TILE / TPB];
+  __device__ __forceinline__ void pre() {
+#pragma unroll
+    for (int k = 0; k < TILE / TPB; k++) xv[k] = x[threadIdx.x + k * TPB];
+  }
+  __device__ __forceinline__ void operator()(int e, int k, double v) const {
+    const u64 w = d2u(f64_canon(f64_mulmod_signed(u2d(xv[k]) - v, c, q, qinv), q, qinv));
+    lo[e] = (u32)w;
+    if (HB == 1) static_cast<u8*>(hi)[e] = (u8)(w >> 32);
+    else static_cast<u16*>(hi)[e] = (u16)(w >> 32);
+  }
+};
 
 // Block pass body: blocks of T1 = 2^(GC+GD) words, K = TILE / T1 blocks per work-group.
 // Loads of the forward block pass: the limb's words, or (LoadPacked) the
@@ -1051,7 +1071,7 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2_sub(u64* data, LimbMap map, c
                                                        const ModConst* __restrict__ mc, int nq,
                                                        const u64* __restrict__ x, int x_stride,
                                                        const u64* __restrict__ cpairs, u64* out, int il,
-                                                       int packed) {
+                                                       int packed, int pack_out) {
   constexpr int S2 = GC + GD, T1 = 1 << S2, K = TILE / T1;
   __shared__ u64 sh[LDS_WORDS];
   const int limb = grid_limb(blockIdx.y, il);
@@ -1068,7 +1088,30 @@ __global__ void __launch_bounds__(TPB) k_ntt_rows2_sub(u64* data, LimbMap map, c
   if (mk.bits <= F64_LAZY_BITS) {
     F64LazyArith ar{twf + (size_t)m * N, mk.qf, mk.qinvf, (double)mk.ninv};
     const SubScaleF64 st{oa, xa, u2d(cpairs[2 * t]), mk.qf, mk.qinvf};
-    if (packed) {
+    if (pack_out) {
+      // the output limb packed too (read back by the tensor sums)
+      u32* olo = reinterpret_cast<u32*>(out + ((size_t)p * nq + t) * N);
+      auto go = [&](auto sto) {
+        if (packed && mk.bits <= 40)
+          ntt_rows2_body<LOGN, GC, GD, false>(
+              a, blk0, reinterpret_cast<double*>(sh), ar, sto,
+              LoadPacked<1>{reinterpret_cast<const u32*>(data + (size_t)limb * N) + off,
+                            reinterpret_cast<const u8*>(reinterpret_cast<const u32*>(data + (size_t)limb * N) + N) + off});
+        else if (packed)
+          ntt_rows2_body<LOGN, GC, GD, false>(
+              a, blk0, reinterpret_cast<double*>(sh), ar, sto,
+              LoadPacked<2>{reinterpret_cast<const u32*>(data + (size_t)limb * N) + off,
+                            reinterpret_cast<const u16*>(reinterpret_cast<const u32*>(data + (size_t)limb * N) + N) + off});
+        else
+          ntt_rows2_body<LOGN, GC, GD, false>(a, blk0, reinterpret_cast<double*>(sh), ar, sto);
+      };
+      if (mk.bits <= 40)
+        go(SubScalePackedF64<1>{olo + off, reinterpret_cast<u8*>(olo + N) + off, xa, u2d(cpairs[2 * t]), mk.qf,
+                                mk.qinvf});
+      else
+        go(SubScalePackedF64<2>{olo + off, reinterpret_cast<u16*>(olo + N) + off, xa, u2d(cpairs[2 * t]), mk.qf,
+                                mk.qinvf});
+    } else if (packed) {
       // y of this limb packed by the column pass (the int8 lift's)
       const u32* lo = reinterpret_cast<const u32*>(data + (size_t)limb * N);
       if (mk.bits <= 40)
@@ -1236,7 +1279,7 @@ static void ntt2_modup(const DeviceTables& T, u64* digits, const ModupSrc& S, in
 template <int LOGN, int GA, int GB, int GC, int GD>
 static void ntt2_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const LimbMap& map, const u64* x,
                          int x_stride, const u64* cpairs, u64* out, hipStream_t s, bool do_cols = true,
-                         bool packed = false) {
+                         bool packed = false, bool pack_out = false) {
   constexpr int R = 1 << (GA + GB), C = TILE / R, T1 = 1 << (GC + GD), K = TILE / T1;
   const int nlimbs = nq * npoly;
   dim3 gc((1 << LOGN) / R / C, nlimbs), gr(((1 << LOGN) / T1) / K, nlimbs);
@@ -1248,7 +1291,7 @@ static void ntt2_fwd_sub(const DeviceTables& T, u64* y, int nq, int npoly, const
   ProfScope ps("ntt_fwd_rows_sub", s, 24.0 * nlimbs * T.N, mm_map(T, map, nlimbs, 0.5 * T.N * (GC + GD) + T.N));
   hipLaunchKernelGGL((k_ntt_rows2_sub<LOGN, GC, GD>), gr, dim3(TPB), 0, s, y, map, T.psi, T.psi_sh, T.psi_f, T.mc,
                      nq, x, x_stride, cpairs, out, interleave_of(nlimbs, modulus_period(map), g_knobs.ntt_interleave),
-                     packed ? 1 : 0);
+                     packed ? 1 : 0, pack_out ? 1 : 0);
 }
 
 template <int LOGN, int GA, int GB, int GC, int GD>
@@ -1849,6 +1892,7 @@ __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, i
 struct TensorPairs {
   const u64* a[TENSOR_PAIRS];
   const u64* b[TENSOR_PAIRS];
+  u32 pka, pkb;  // bit p: pair p's a (b) stored packed on FP64 limbs
 };
 // V = 2: two consecutive coefficients per thread, 16-byte loads and stores;
 // the next pair's four loads are in flight while a pair is multiplied
@@ -1885,7 +1929,37 @@ __global__ void __launch_bounds__(TPB) k_tensor_multi(u64* out, TensorPairs P, i
       *p = r[0];
     }
   };
-  W a0n = ld(P.a[0] + o0), a1n = ld(P.a[0] + o1), b0n = ld(P.b[0] + o0), b1n = ld(P.b[0] + o1);
+  // limb `slot` of an element at base, packed (the layout LoadPacked reads)
+  // when pk: FP64 limbs of the pairs marked in P.pka / P.pkb
+  const bool f64 = mk.bits <= F64_LAZY_BITS, hb1 = mk.bits <= 40;
+  auto ldx = [&](const u64* base, size_t slot, bool pk) {
+    if (!pk) return ld(base + slot * N + i);
+    const u32* lo = reinterpret_cast<const u32*>(base + slot * N);
+    W w;
+    if (V == 2) {
+      const uint2 l = *reinterpret_cast<const uint2*>(lo + i);
+      u64 h0, h1;
+      if (hb1) {
+        const u32 h = *reinterpret_cast<const u16*>(reinterpret_cast<const u8*>(lo + N) + i);
+        h0 = h & 255;
+        h1 = h >> 8;
+      } else {
+        const u32 h = *reinterpret_cast<const u32*>(reinterpret_cast<const u16*>(lo + N) + i);
+        h0 = h & 65535;
+        h1 = h >> 16;
+      }
+      w.v[0] = (u64)l.x | (h0 << 32);
+      w.v[V - 1] = (u64)l.y | (h1 << 32);
+    } else {
+      const u64 h = hb1 ? (u64) reinterpret_cast<const u8*>(lo + N)[i] : (u64) reinterpret_cast<const u16*>(lo + N)[i];
+      w.v[0] = (u64)lo[i] | (h << 32);
+    }
+    return w;
+  };
+  auto pa = [&](int p) { return f64 && ((P.pka >> p) & 1u); };
+  auto pb = [&](int p) { return f64 && ((P.pkb >> p) & 1u); };
+  W a0n = ldx(P.a[0], k, pa(0)), a1n = ldx(P.a[0], nt + k, pa(0)), b0n = ldx(P.b[0], k, pb(0)),
+    b1n = ldx(P.b[0], nt + k, pb(0));
   u64 r0[V], r1[V], r2[V];
   if (mk.bits <= F64_LAZY_BITS) {
     const double q = mk.qf, qi = mk.qinvf;
@@ -1905,10 +1979,10 @@ __global__ void __launch_bounds__(TPB) k_tensor_multi(u64* out, TensorPairs P, i
     for (int p = 0; p < npairs; p++) {
       const W a0 = a0n, a1 = a1n, b0 = b0n, b1 = b1n;
       if (p + 1 < npairs) {
-        a0n = ld(P.a[p + 1] + o0);
-        a1n = ld(P.a[p + 1] + o1);
-        b0n = ld(P.b[p + 1] + o0);
-        b1n = ld(P.b[p + 1] + o1);
+        a0n = ldx(P.a[p + 1], k, pa(p + 1));
+        a1n = ldx(P.a[p + 1], nt + k, pa(p + 1));
+        b0n = ldx(P.b[p + 1], k, pb(p + 1));
+        b1n = ldx(P.b[p + 1], nt + k, pb(p + 1));
       }
 #pragma unroll
       for (int e = 0; e < V; e++) {
@@ -1940,10 +2014,10 @@ __global__ void __launch_bounds__(TPB) k_tensor_multi(u64* out, TensorPairs P, i
     for (int p = 0; p < npairs; p++) {
       const W a0 = a0n, a1 = a1n, b0 = b0n, b1 = b1n;
       if (p + 1 < npairs) {
-        a0n = ld(P.a[p + 1] + o0);
-        a1n = ld(P.a[p + 1] + o1);
-        b0n = ld(P.b[p + 1] + o0);
-        b1n = ld(P.b[p + 1] + o1);
+        a0n = ldx(P.a[p + 1], k, pa(p + 1));
+        a1n = ldx(P.a[p + 1], nt + k, pa(p + 1));
+        b0n = ldx(P.b[p + 1], k, pb(p + 1));
+        b1n = ldx(P.b[p + 1], nt + k, pb(p + 1));
       }
 #pragma unroll
       for (int e = 0; e < V; e++) {
@@ -1959,16 +2033,19 @@ __global__ void __launch_bounds__(TPB) k_tensor_multi(u64* out, TensorPairs P, i
   st(out + o2, r2);
 }
 void launch_tensor_sum(const DeviceTables& T, u64* out3, const u64* const* a, const u64* const* b, int npairs, int nl,
-                       int batch, bool accumulate, hipStream_t s) {
+                       int batch, bool accumulate, hipStream_t s, const bool* a_packed, const bool* b_packed) {
   const int nt = nl * batch;
   // two coefficients per thread where the ring fills whole work-groups
   const bool v2 = T.N >= (u64)(2 * TPB);
   for (int p0 = 0; p0 < npairs; p0 += TENSOR_PAIRS) {
     const int np = std::min(TENSOR_PAIRS, npairs - p0);
     TensorPairs P;
+    P.pka = P.pkb = 0;
     for (int p = 0; p < TENSOR_PAIRS; p++) {
       P.a[p] = p < np ? a[p0 + p] : nullptr;
       P.b[p] = p < np ? b[p0 + p] : nullptr;
+      if (p < np && a_packed && a_packed[p0 + p]) P.pka |= 1u << p;
+      if (p < np && b_packed && b_packed[p0 + p]) P.pkb |= 1u << p;
     }
     const bool acc = accumulate || p0 > 0;
     ProfScope ps("tensor", s, 8.0 * T.N * (4.0 * np + (acc ? 6 : 3)) * nt, mm_q(T, nl, 4.0 * T.N * np, batch));
@@ -2702,7 +2779,7 @@ __global__ void __launch_bounds__(2 * TPB) __attribute__((amdgpu_waves_per_eu(4)
 template <int LOGN, int GA, int GB, int GC, int GD>
 static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const FbcArgs& A, int nq, int npoly,
                           const LimbMap& map, const u64* x, int x_stride, const u64* pinv, u64* out, hipStream_t s,
-                          const u64* cdig) {
+                          const u64* cdig, bool pack_out) {
   constexpr int R = 1 << (GA + GB), C = TILE / R;
   {
     ProfScope ps("ntt_fwd_cols_fbc", s, 8.0 * T.N * npoly * ((double)A.ns + 1 + nq),
@@ -2735,7 +2812,8 @@ static void moddown_fused(const DeviceTables& T, u64* y, const u64* V, const Fbc
       }
     }
   }
-  ntt2_fwd_sub<LOGN, GA, GB, GC, GD>(T, y, nq, npoly, map, x, x_stride, pinv, out, s, false, cdig != nullptr);
+  ntt2_fwd_sub<LOGN, GA, GB, GC, GD>(T, y, nq, npoly, map, x, x_stride, pinv, out, s, false, cdig != nullptr,
+                                     pack_out);
 }
 // ModDown of npoly polynomials: xp_coef their P limbs in the coefficient
 // domain [npoly][ns][N], x the R_{Q_l P} data ([npoly][x_stride][N]), out
@@ -2770,7 +2848,7 @@ bool fbc_digit_path(const DeviceTables& T, const FbcTable& tab, int nq) {
 }
 bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int npoly, const FbcTable& tab,
                           const u64* x, int x_stride, const u64* pinv, u64* out, u64* y, u64* V, hipStream_t s,
-                          int src_stride, int src_off, bool v_ready) {
+                          int src_stride, int src_off, bool v_ready, bool pack_out) {
   if (T.logN < 12 || T.logN > 16 || tab.ns > 4) return false;
   const FbcArgs A = fbc_args(tab, src_stride > 0 ? src_stride : tab.ns, src_stride > 0 ? src_off : 0);
   const u64* cdig = fbc_digit_path(T, tab, nq) ? tab.cdig : nullptr;
@@ -2791,7 +2869,7 @@ bool launch_moddown_fused(const DeviceTables& T, const u64* xp_coef, int nq, int
   for (int k = 0; k < nq; k++) map.idx[k] = (short)k;
   return ntt_dispatch(T.logN, [&](auto sp) {
     using S = decltype(sp);
-    moddown_fused<NTT_SPLIT_ARGS>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s, cdig);
+    moddown_fused<NTT_SPLIT_ARGS>(T, y, V, A, nq, npoly, map, x, x_stride, pinv, out, s, cdig, pack_out);
   });
 }
 

@@ -180,13 +180,15 @@ struct HeCtxImpl {
                       const std::vector<const u64*>& masks, bool accumulate);
   // consume: x's special-prime limbs (and q_l for moddown_rescale) may be
   // overwritten (x is a temporary the caller drops afterwards)
+  // pack: the output's FP64 limbs may be stored packed (HeCt::packed says
+  // whether they were: only on the fused, consuming path)
   HeCt moddown(const HeCt& x, int out_level = -1, bool consume = false, bool src_ready = false,
-               const u64* rec = nullptr);
-  void moddown_to(const HeCt& x, int out_level, u64* out, bool consume = false, bool src_ready = false,
-                  const u64* rec = nullptr);
+               const u64* rec = nullptr, bool pack = false);
+  bool moddown_to(const HeCt& x, int out_level, u64* out, bool consume = false, bool src_ready = false,
+                  const u64* rec = nullptr, bool pack = false);
   // ModDown and Rescale as one rounding by P q_l (a variant)
   HeCt moddown_rescale(const HeCt& x, int out_level = -1, bool consume = false, bool src_ready = false,
-                       const u64* rec = nullptr);
+                       const u64* rec = nullptr, bool pack = false);
   // returns the digit records of the elements' ModDown sources when the
   // int8 lift takes them (element e's at rec + e * rec_stride), else empty
   DevBuf moddown_sources(const std::vector<HeCt*>& xs, bool with_rescale, size_t* rec_stride = nullptr);
@@ -229,9 +231,11 @@ struct HeCtxImpl {
   std::vector<HeCt> run_merged(const std::vector<std::function<HeCt()>>& jobs);
   void accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vector<HeCt>& Ak, const std::vector<HeCt>& Bk);
   HeCt relin_sum(const DevBuf& acc3, int level, double scale, int B);
+  // pack: the A_k (with one rounding) and the ModDown'ed B_k may come out
+  // packed, for the tensor sums alone
   std::vector<HeCt> matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level = -1,
-                                  bool fused_rs = false);
-  std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t, int npt, int out_level = -1);
+                                  bool fused_rs = false, bool pack = false);
+  std::vector<HeCt> matmul_side_b(const HeCt& cb, int n, int n1t, int npt, int out_level = -1, bool pack = false);
   // the A side with C^k's masks folded into Z: A_k = U_k a, one level
   std::vector<HeCt> matmul_side_a_folded(const HeCt& ca, int n, int n1z);
   void align_sides(std::vector<HeCt>& Ak, std::vector<HeCt>& Bk);

@@ -563,6 +563,7 @@ HeCt HeCtxImpl::ct_new(int level, bool qp, double scale, int B) {
 HeCt HeCtxImpl::ct_copy(const HeCt& x) {
   HeCt c = ct_new(x.level, x.qp, x.scale, x.B);
   hip_check(copy_async("copy_ct", c.d.p, x.d.p, c.d.words * 8, stream), "copy");
+  c.packed = x.packed;
   return c;
 }
 void HeCtxImpl::copy_limbs(u64* dst, const u64* src, size_t nlimbs, const char* family) {
@@ -727,6 +728,7 @@ HeCt HeCtxImpl::add(const HeCt& a, const HeCt& b, bool sub) {
 }
 void HeCtxImpl::add_into(HeCt& acc, const HeCt& b) {
   need_same(acc, b);
+  if (acc.packed || b.packed) fail(HE_EINVAL, "packed limbs are for the tensor sums alone");
   LimbMap m = acc.qp ? qpmap(acc.level) : qmap(acc.level + 1);
   launch_add(T, acc.d.p, acc.d.p, b.d.p, (int)acc.polys() * acc.nlimbs, m, stream);
 }
@@ -742,6 +744,7 @@ HeCt HeCtxImpl::drop(const HeCt& a, int level) {
   if (a.qp || level > a.level || level < 0) fail(HE_ELEVEL, "bad level drop");
   HeCt c = ct_new(level, false, a.scale, a.B);
   gather_limbs(c.d.p, a, 0, level + 1);
+  c.packed = a.packed;  // whole limb slots copied
   return c;
 }
 
@@ -749,6 +752,7 @@ HeCt HeCtxImpl::drop(const HeCt& a, int level) {
 // kept limbs are computed: the same residues as Rescale followed by a drop)
 HeCt HeCtxImpl::rescale(const HeCt& a, int out_level) {
   if (a.qp) fail(HE_EINVAL, "rescale of an R_QP element");
+  if (a.packed) fail(HE_EINVAL, "packed limbs are for the tensor sums alone");
   int l = a.level;
   if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
   if (out_level < 0) out_level = l - 1;
@@ -877,12 +881,12 @@ void HeCtxImpl::hoisted_masked(const HeCt& x, const u64* digits, const std::vect
 
 // ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact
 // centred residue; out_level < l keeps (and computes) only the limbs up to it
-HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume, bool src_ready, const u64* rec) {
+HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume, bool src_ready, const u64* rec, bool pack) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   if (out_level < 0) out_level = x.level;
   if (out_level > x.level) fail(HE_ELEVEL, "moddown cannot raise the level");
   HeCt c = ct_new(out_level, false, x.scale, x.B);
-  moddown_to(x, out_level, c.d.p, consume, src_ready, rec);
+  c.packed = moddown_to(x, out_level, c.d.p, consume, src_ready, rec, pack);
   return c;
 }
 // the same into out [2][B][out_level + 1][N].  consume: x's special-prime
@@ -890,7 +894,8 @@ HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume, bool src_rea
 // so) instead of in a gathered copy; src_ready: that was done already
 // (moddown_sources over a set of elements), and rec, when given, holds their
 // digit records
-void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume, bool src_ready, const u64* rec) {
+bool HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume, bool src_ready, const u64* rec,
+                           bool pack) {
   int nq = nq_of(out_level), nqp = nqp_of(x.level);
   const int np = (int)x.polys();
   DevBuf y(&pool, (size_t)np * nq * N);
@@ -905,10 +910,10 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume,
     DevBuf V;
     if (!rec) V = DevBuf(&pool, (size_t)np * (down.ns + 1) * N);
     if (!launch_moddown_fused(T, x.d.p, nq, np, down, x.d.p, nqp, pinv.p, out, y.p, rec ? (u64*)rec : V.p, stream,
-                              x.nlimbs, nq_of(x.level), rec != nullptr))
+                              x.nlimbs, nq_of(x.level), rec != nullptr, pack))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
     n_moddown += x.B;
-    return;
+    return pack;
   }
   DevBuf pc(&pool, (size_t)np * alpha * N);
   gather_limbs(pc.p, x, nq_of(x.level), alpha);
@@ -922,13 +927,15 @@ void HeCtxImpl::moddown_to(const HeCt& x, int out_level, u64* out, bool consume,
     launch_ntt_fwd_sub(T, y.p, nq, np, qmap(nq), x.d.p, nqp, pinv.p, out, stream);
   }
   n_moddown += x.B;
+  return false;
 }
 
 // ModDown and the Rescale after it as one rounding: x in R_{Q_l P} ->
 // round(x / (P q_l)) in R_{Q_{l-1}} (or a lower out_level: only the kept
 // limbs are computed): the exact centred lift of x mod P q_l from the limbs
 // q_l, p_1..p_alpha, then (x - lift) (P q_l)^-1 on the limbs below q_l.
-HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool src_ready, const u64* rec) {
+HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool src_ready, const u64* rec,
+                                 bool pack) {
   if (!x.qp) fail(HE_EINVAL, "moddown of an R_Q element");
   const int l = x.level;
   if (l < 1) fail(HE_ELEVEL, "no level left to rescale");
@@ -955,8 +962,9 @@ HeCt HeCtxImpl::moddown_rescale(const HeCt& x, int out_level, bool consume, bool
     DevBuf V;
     if (!rec) V = DevBuf(&pool, (size_t)np * (ns + 1) * N);
     if (!launch_moddown_fused(T, x.d.p, nout, np, tab, x.d.p, nqp, cp, c.d.p, y.p, rec ? (u64*)rec : V.p, stream,
-                              x.nlimbs, l, rec != nullptr))
+                              x.nlimbs, l, rec != nullptr, pack))
       fail(HE_EINVAL, "fused ModDown unavailable for this ring size");
+    c.packed = pack;
     n_moddown += x.B;
     return c;
   }
@@ -1037,6 +1045,7 @@ HeCt HeCtxImpl::keyswitch(const u64* d, int level, u64 g_key, int B) {
 
 HeCt HeCtxImpl::mult(const HeCt& a, const HeCt& b) {
   need_same(a, b);
+  if (a.packed || b.packed) fail(HE_EINVAL, "packed limbs are for the tensor sums alone");
   if (a.qp) fail(HE_EINVAL, "mult of R_QP elements");
   int nl = a.nlimbs, nt = a.B * nl;
   DevBuf t3(&pool, (size_t)3 * nt * N);
@@ -1048,6 +1057,7 @@ HeCt HeCtxImpl::mult(const HeCt& a, const HeCt& b) {
 }
 
 HeCt HeCtxImpl::rotate(const HeCt& x, long step) {
+  if (x.packed) fail(HE_EINVAL, "packed limbs are for the tensor sums alone");
   u64 g = galois(step);
   if (g == 1) return ct_copy(x);
   DevBuf dig = decompose(x.poly(1), x.level, x.B);
@@ -1567,7 +1577,8 @@ static void col_mask(int n, int k, bool second, std::vector<double>& out) {
 // k = b n1z + r, with bases B_b = Rot(B_{b-1}, n1z), B'_0 = Rot(Z a, -n), B'_b = Rot(B'_{b-1}, n1z)
 // out_level (if >= 0) caps the level of the A_k: limbs above it are never
 // computed (the same residues as computing them and dropping them).
-std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level, bool fused_rs) {
+std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int npz, int out_level, bool fused_rs,
+                                           bool pack) {
   HeCt A0 = sigma_dcd(ca, n, n1z, npz);
   const int lvl = A0.level;
   if (lvl < 1) fail(HE_ELEVEL, "no level left for the column shifts");
@@ -1649,7 +1660,7 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
       const int ol = out_level >= 0 ? std::min(out_level, lvl - 1) : -1;
       const u64* rr = rec.p ? rec.p + r * rs : nullptr;
       if (fused_rs) {
-        Ak[k] = moddown_rescale(sum, ol, true, ready, rr);
+        Ak[k] = moddown_rescale(sum, ol, true, ready, rr, pack);
       } else {
         HeCt md = moddown(sum, -1, true, ready, rr);
         Ak[k] = rescale(md, ol);
@@ -1662,7 +1673,7 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
 
 // B side: B_k = R^k T b.  C_0 = T b, C_b = Rot(C_{b-1}, n n1t), B_k = ModDown(HR(C_b, n r))
 // out_level (if >= 0) caps the level of the B_k, as for the A side
-std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int npt, int out_level) {
+std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int npt, int out_level, bool pack) {
   HeCt Cb = tau_dcd(cb, n, n1t, npt);
   const int lvl = Cb.level;
   const int ol = out_level >= 0 ? std::min(out_level, lvl) : lvl;
@@ -1686,7 +1697,7 @@ std::vector<HeCt> HeCtxImpl::matmul_side_b(const HeCt& cb, int n, int n1t, int n
       rec = moddown_sources(srcs, false, &rs);
     }
     for (int r = 1; r < nr; r++) {
-      Bk[b * n1t + r] = moddown(hs[r - 1], ol, true, fused_conv, rec.p ? rec.p + (r - 1) * rs : nullptr);
+      Bk[b * n1t + r] = moddown(hs[r - 1], ol, true, fused_conv, rec.p ? rec.p + (r - 1) * rs : nullptr, pack);
       hs[r - 1] = HeCt();
     }
   }
@@ -1742,13 +1753,16 @@ void HeCtxImpl::accumulate_tensors(DevBuf& acc3, bool& acc_set, const std::vecto
   const int nl = a0.nlimbs;
   if (!acc_set) acc3 = DevBuf(&pool, (size_t)3 * a0.B * nl * N);
   std::vector<const u64*> pa, pb;
+  std::unique_ptr<bool[]> ka(new bool[Ak.size()]), kb(new bool[Ak.size()]);
   for (size_t k = 0; k < Ak.size(); k++) {
     need_same(Ak[k], Bk[k]);
     need_same(Ak[k], a0);
     pa.push_back(Ak[k].d.p);
     pb.push_back(Bk[k].d.p);
+    ka[k] = Ak[k].packed;
+    kb[k] = Bk[k].packed;
   }
-  launch_tensor_sum(T, acc3.p, pa.data(), pb.data(), (int)pa.size(), nl, a0.B, acc_set, stream);
+  launch_tensor_sum(T, acc3.p, pa.data(), pb.data(), (int)pa.size(), nl, a0.B, acc_set, stream, ka.get(), kb.get());
   acc_set = true;
 }
 // ... and relinearised once
@@ -1775,8 +1789,10 @@ HeCt HeCtxImpl::matmul(const HeCt& ca, const HeCt& cb, int n, int n1z, int n1t, 
   // both sides produced at their common level (A: sigma, then the masks;
   // B: tau); align_sides only guards the prediction
   const int common = std::min(ca.level - da, cb.level - dt);
-  std::vector<HeCt> Ak = folded ? matmul_side_a_folded(ca, n, n1z) : matmul_side_a(ca, n, n1z, npz, common, fused_rs);
-  std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t, npt, common);
+  // the sides come out packed where only the lazy tensor sums read them
+  std::vector<HeCt> Ak =
+      folded ? matmul_side_a_folded(ca, n, n1z) : matmul_side_a(ca, n, n1z, npz, common, fused_rs, lazy);
+  std::vector<HeCt> Bk = matmul_side_b(cb, n, n1t, npt, common, lazy);
   align_sides(Ak, Bk);
   HeCt acc;
   if (lazy) {
@@ -1992,11 +2008,11 @@ void HeCtxImpl::cov_add(CovState& st, const std::vector<const HeCt*>& x, int rb)
     std::vector<std::vector<HeCt>> A(k), B(k);
     for (int a = 0; a < k; a++) {
       HeCt xt = lintrans(rows_of(a), LT_TRANSPOSE, n, st.n1g, 1.0 / (double)st.n_samples);
-      A[a] = matmul_side_a(xt, n, st.n1z, st.npz, common, st.fused);
+      A[a] = matmul_side_a(xt, n, st.n1z, st.npz, common, st.fused, st.lazy);
     }
     for (int b = 0; b < k; b++) {
       HeCt xb = drop(rows_of(b), level - 1);
-      B[b] = matmul_side_b(xb, n, st.n1t, st.npt, common);
+      B[b] = matmul_side_b(xb, n, st.n1t, st.npt, common, st.lazy);
     }
     for (int a = 0; a < k; a++) align_sides(A[a], B[0]);
     for (int b = 0; b < k; b++) align_sides(A[0], B[b]);
