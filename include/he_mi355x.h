@@ -415,7 +415,9 @@ he_status he_eigen_shift(he_ctx* ctx, he_ct* const* cov, uint32_t k, uint32_t d,
  * renumbered so that those of one polynomial run on one XCD and share its L2);
  * "sum_streams" (1/2/4, default 4: term streams that share their plaintexts
  * per thread of the multi-output multiply-sums, each plaintext word loaded
- * once for all of them).
+ * once for all of them) and "mr_pair" (0/1, default 1: the two masked
+ * multi-rotation launches of a shift block of the product's A side as one
+ * launch over both decompositions, each key word loaded once).
  * Set them between calls, not while
  * another thread drives the library.  The autotuner in the Python package
  * picks them by timing. */

@@ -172,6 +172,13 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
                         const u64* digits, const u64* c0, const u64* pmod, int level, int L, int alpha, int beta,
                         int batch, hipStream_t s, const u64* const* masks = nullptr, bool accumulate = false,
                         const ForkStream* fs = nullptr);
+// two bases under the same keys: outs[r] = masks[r] * rotation r of base 1
+// (digits, c0) + masks2[r] * rotation r of base 2 (digits2, c02), each key
+// word loaded once; false (nothing launched) where that does not apply
+bool launch_multsum_rot_pair(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
+                             const u64* digits, const u64* c0, const u64* const* masks, const u64* digits2,
+                             const u64* c02, const u64* const* masks2, const u64* pmod, int level, int L, int alpha,
+                             int beta, int batch, hipStream_t s);
 // Key inner products handed to a sink instead of being launched (merged
 // launches of several products): the arguments of one launch_multsum_rot or
 // launch_multsum call

@@ -33,6 +33,7 @@ struct Knobs {
   int fbc_mfma = 1;        // ModDown's lift as an int8 matrix product (0/1)
   int xcd_map = 1;         // the MFMA lift's work-groups of one polynomial kept on one XCD (0/1)
   int sum_streams = 4;     // term streams sharing a plaintext per thread of the multi-output sums (1/2/4)
+  int mr_pair = 1;         // the A side's two masked multi-rotation launches as one (0/1)
   // stage split of the register-blocked NTT per ring size (index log N):
   // 0 = the default, 1 = one stage moved between the column and block passes
   int ntt_split[17] = {};
@@ -54,6 +55,7 @@ bool knob_set(const char* name, int v) {
   else if (n == "fbc_mfma" && (v == 0 || v == 1)) g_knobs.fbc_mfma = v;
   else if (n == "xcd_map" && (v == 0 || v == 1)) g_knobs.xcd_map = v;
   else if (n == "sum_streams" && (v == 1 || v == 2 || v == 4)) g_knobs.sum_streams = v;
+  else if (n == "mr_pair" && (v == 0 || v == 1)) g_knobs.mr_pair = v;
   else if ((n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") && (v == 0 || v == 1))
     g_knobs.ntt_split[std::stoi(n.substr(10))] = v;
   else return false;
@@ -75,6 +77,7 @@ bool knob_get(const char* name, int* v) {
   else if (n == "fbc_mfma") *v = g_knobs.fbc_mfma;
   else if (n == "xcd_map") *v = g_knobs.xcd_map;
   else if (n == "sum_streams") *v = g_knobs.sum_streams;
+  else if (n == "mr_pair") *v = g_knobs.mr_pair;
   else if (n == "ntt_split_13" || n == "ntt_split_14" || n == "ntt_split_15") *v = g_knobs.ntt_split[std::stoi(n.substr(10))];
   else return false;
   return true;
@@ -3052,6 +3055,11 @@ struct MultiRot {
   const u64* mask[MR_MAX];  // null: plain outputs
   u64 ginv[MR_MAX];
   int accumulate;           // with masks: add onto the outputs
+  // a second base under the same keys (pair launches): its digits, c0 and
+  // masks; each output is mask (first) + mask2 (second)
+  const u64* digits2;
+  const u64* c02;
+  const u64* mask2[MR_MAX];
 };
 // Limbs of R_{Q_l P} in launch order: the integer limbs (moduli of 47 bits
 // or more, four members at a time to bound their registers) are spread
@@ -3156,6 +3164,99 @@ __device__ __forceinline__ void multsum_rot_group(const MultiRot& R, int r0, int
       }
       stnt(o0, d2u(f64_canon(a0, q, qi)));
       stnt(o1, d2u(f64_canon(a1, q, qi)));
+    }
+  }
+}
+// The same for two bases under the same keys (pair launches): the digits of
+// base 1 (digits, c0, masks) and base 2 (R.digits2, R.c02, R.mask2) as 2 MB
+// digit lanes, so that each key word is loaded once for both; the output is
+//   mask (sum_1 + c0_1 P) + mask2 (sum_2 + c0_2 P),
+// each masked term below q in absolute value, reduced once: the residues of
+// the first base's launch followed by the second's accumulating launch.
+template <int MB, int RPW>
+__device__ __forceinline__ void multsum_rot_group_pair(const MultiRot& R, int r0, int nr,
+                                                       const u64* __restrict__ digits, const u64* __restrict__ c0,
+                                                       const u64* __restrict__ pmod, int nq, int nqp, int beta,
+                                                       int nmods, int B, int b0, int m, int pos, u32 src, int logN,
+                                                       u64 N, const ModConst& mk) {
+  constexpr int NB = 2 * MB;
+  const size_t dstride = (size_t)beta * nqp * N;
+  const double q = mk.qf, qi = mk.qinvf;
+  u32 idx[RPW];
+  const u64* key[RPW];
+#pragma unroll
+  for (int g = 0; g < RPW; g++) {
+    const int r = r0 + (g < nr ? g : 0);
+    idx[g] = automorph_src(src, R.ginv[r], logN);
+    key[g] = R.key[r];
+  }
+  const u64* dg[2] = {digits, R.digits2};
+  double s0[RPW][NB], s1[RPW][NB];
+#pragma unroll
+  for (int g = 0; g < RPW; g++)
+#pragma unroll
+    for (int b = 0; b < NB; b++) s0[g][b] = s1[g][b] = 0.0;
+  u64 kbn[RPW], kan[RPW], dn[NB];
+#pragma unroll
+  for (int g = 0; g < RPW; g++) {
+    kbn[g] = ldnt(&key[g][((size_t)0 * nmods + m) * N + idx[g]]);
+    kan[g] = ldnt(&key[g][((size_t)1 * nmods + m) * N + idx[g]]);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; b++) dn[b] = dg[b / MB][(size_t)(b0 + b % MB) * dstride + (size_t)pos * N + src];
+  for (int j = 0; j < beta; j++) {
+    double kb[RPW], ka[RPW], d[NB];
+#pragma unroll
+    for (int g = 0; g < RPW; g++) {
+      kb[g] = u2d(kbn[g]);
+      ka[g] = u2d(kan[g]);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) d[b] = __longlong_as_double((long long)dn[b]);  // centred double digits
+    if (j + 1 < beta) {
+#pragma unroll
+      for (int g = 0; g < RPW; g++) {
+        kbn[g] = ldnt(&key[g][(((size_t)(j + 1) * 2 + 0) * nmods + m) * N + idx[g]]);
+        kan[g] = ldnt(&key[g][(((size_t)(j + 1) * 2 + 1) * nmods + m) * N + idx[g]]);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; b++)
+        dn[b] = dg[b / MB][(size_t)(b0 + b % MB) * dstride + ((size_t)(j + 1) * nqp + pos) * N + src];
+    }
+#pragma unroll
+    for (int g = 0; g < RPW; g++)
+#pragma unroll
+      for (int b = 0; b < NB; b++) {
+        s0[g][b] += f64_mulmod_signed(d[b], kb[g], q, qi);
+        s1[g][b] += f64_mulmod_signed(d[b], ka[g], q, qi);
+      }
+  }
+  const u64* cs[2] = {c0, R.c02};
+  double cpd[NB];
+#pragma unroll
+  for (int b = 0; b < NB; b++)
+    cpd[b] = pos < nq ? u2d(mul_const_any(cs[b / MB][((size_t)(b0 + b % MB) * nq + pos) * N + src], pmod[2 * m],
+                                          pmod[2 * m + 1], mk))
+                      : 0.0;
+#pragma unroll
+  for (int g = 0; g < RPW; g++) {
+    if (g >= nr) break;
+    const int r = r0 + g;
+    const u32 i = idx[g];
+    const double mv1 = u2d(R.mask[r][(size_t)pos * N + i]), mv2 = u2d(R.mask2[r][(size_t)pos * N + i]);
+#pragma unroll
+    for (int b = 0; b < MB; b++) {
+      double a0 = s0[g][b] + cpd[b], a1 = s1[g][b], e0 = s0[g][MB + b] + cpd[MB + b], e1 = s1[g][MB + b];
+      if (beta > 15) {
+        a0 = f64_centre(a0, q, qi);
+        a1 = f64_centre(a1, q, qi);
+        e0 = f64_centre(e0, q, qi);
+        e1 = f64_centre(e1, q, qi);
+      }
+      a0 = f64_mulmod_signed(a0, mv1, q, qi) + f64_mulmod_signed(e0, mv2, q, qi);
+      a1 = f64_mulmod_signed(a1, mv1, q, qi) + f64_mulmod_signed(e1, mv2, q, qi);
+      stnt(&R.out[r][((size_t)(b0 + b) * nqp + pos) * N + i], d2u(f64_canon(a0, q, qi)));
+      stnt(&R.out[r][((size_t)(B + b0 + b) * nqp + pos) * N + i], d2u(f64_canon(a1, q, qi)));
     }
   }
 }
@@ -3308,7 +3409,7 @@ __device__ __forceinline__ void multsum_rot_group_int(const MultiRot& R, int r0,
   }
 }
 // RPW: rotations per work-group (their FP64 limbs share the digit loads)
-template <int MB, bool F64, int RPW>
+template <int MB, bool F64, int RPW, bool PAIR = false>
 __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, PosList P, int nrot, const u64* __restrict__ digits,
                                                      const u64* __restrict__ c0, const u64* __restrict__ pmod,
                                                      int nq, int nqp, int L, int beta, int nmods, int B, int b0,
@@ -3325,7 +3426,11 @@ __global__ void __launch_bounds__(TPB) k_multsum_rot(MultiRot R, PosList P, int 
   const int m = pos < nq ? pos : L + 1 + (pos - nq);
   const ModConst mk = mc[m];
   if (F64 || mk.bits <= F64_LAZY_BITS) {
-    multsum_rot_group<MB, RPW>(R, r0, nr, digits, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, logN, N, mk);
+    if (PAIR)
+      multsum_rot_group_pair<MB, RPW>(R, r0, nr, digits, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, logN, N,
+                                      mk);
+    else
+      multsum_rot_group<MB, RPW>(R, r0, nr, digits, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, logN, N, mk);
     return;
   }
   multsum_rot_group_int<MB>(R, r0, nr, digits, c0, pmod, nq, nqp, beta, nmods, B, b0, m, pos, src, logN, N, mk);
@@ -3713,6 +3818,90 @@ void launch_multsum_rot(const DeviceTables& T, u64* const* outs, const u64* cons
 #undef MR_GROUPS
 #undef MR_LAUNCH
   }
+}
+// Two bases under the same keys in one FP64 launch (the A side's two masked
+// hoisted sums): outs[r] = masks[r] (rotation of base 1) + masks2[r]
+// (rotation of base 2).  The 60-bit limbs run the two launches of their own
+// kernel (the second accumulating).  False (nothing launched) where the pair
+// launch does not apply: knob mr_pair off, a merged-launch sink, or 60-bit
+// limbs that do not run in a kernel of their own.
+bool launch_multsum_rot_pair(const DeviceTables& T, u64* const* outs, const u64* const* keys, const u64* gs, int nrot,
+                             const u64* digits, const u64* c0, const u64* const* masks, const u64* digits2,
+                             const u64* c02, const u64* const* masks2, const u64* pmod, int level, int L, int alpha,
+                             int beta, int batch, hipStream_t s) {
+  if (!g_knobs.mr_pair || tls_ks_sink || !masks || !masks2) return false;
+  const int nq = level + 1, nqp = nq + alpha;
+  const PosList P = pos_order(T, nq, nqp, L);
+  PosList pf, pi;
+  int nf = 0, ni = 0;
+  for (int x = 0; x < nqp; x++) {
+    const int pos = P.pos[x];
+    const int m = pos < nq ? pos : L + 1 + (pos - nq);
+    if (T.bits[m] <= F64_LAZY_BITS) pf.pos[nf++] = (short)pos;
+    else pi.pos[ni++] = (short)pos;
+  }
+  if (ni > 0 && !g_knobs.mr_int_split) return false;
+  const u64 twoN = 2 * T.N;
+  const int nblk = cdiv(T.N, TPB);
+  const int rstep = std::min(MR_MAX, g_knobs.mr_rotations);
+  const int mstep = std::min(MS_MAXB, g_knobs.mr_members);
+  constexpr int RPW = 2;  // 2 x 8 digit lanes: the sums of two rotations fill the registers
+  for (int r0 = 0; r0 < nrot; r0 += rstep) {
+    const int nr = std::min(nrot - r0, rstep);
+    MultiRot R;
+    R.accumulate = 0;
+    R.digits2 = digits2;
+    R.c02 = c02;
+    for (int r = 0; r < nr; r++) {
+      R.out[r] = outs[r0 + r];
+      R.key[r] = keys[r0 + r];
+      R.mask[r] = masks[r0 + r];
+      R.mask2[r] = masks2[r0 + r];
+      R.ginv[r] = inv_mod_2n(gs[r0 + r], twoN);
+    }
+    for (int b0 = 0; b0 < batch; b0 += mstep) {
+      const int mb = batch - b0 < mstep ? batch - b0 : mstep;
+      if (ni > 0) {
+        // the 60-bit limbs: base 1, then base 2 added on
+        MultiRot R2 = R;
+        for (int r = 0; r < nr; r++) R2.mask[r] = masks2[r0 + r];
+        R2.accumulate = 1;
+        const dim3 grid(cdiv(nblk, 8) * 8 * nr, ni);
+        const int rc = std::min(nr, g_knobs.mr_int_chunk);
+        for (int half = 0; half < 2; half++) {
+          const MultiRot& RI = half ? R2 : R;
+          const MrCost ic = mr_cost(T, pi, ni, nq, L, nr, mb, beta, true, true, half == 1);
+          ProfScope ps("multsum_rot_int", s, ic.bytes, ic.mm, ic.unit);
+          const u64* dg = half ? digits2 : digits;
+          const u64* cz = half ? c02 : c0;
+#define MRP_INT(K)                                                                                                    \
+  case K:                                                                                                             \
+    if (g_knobs.mr_int_pass == 8)                                                                                     \
+      hipLaunchKernelGGL((k_multsum_rot_int<K, 8>), grid, dim3(TPB), 0, s, RI, pi, nr, rc, dg, cz, pmod, nq, nqp, L, \
+                         beta, T.nmods, batch, b0, T.logN, T.mc);                                                     \
+    else                                                                                                              \
+      hipLaunchKernelGGL((k_multsum_rot_int<K, 4>), grid, dim3(TPB), 0, s, RI, pi, nr, rc, dg, cz, pmod, nq, nqp, L, \
+                         beta, T.nmods, batch, b0, T.logN, T.mc);                                                     \
+    break;
+          switch (mb) { MRP_INT(1) MRP_INT(2) MRP_INT(3) MRP_INT(4) MRP_INT(5) MRP_INT(6) MRP_INT(7) MRP_INT(8) }
+#undef MRP_INT
+        }
+      }
+      // the FP64 limbs: 2 mb digit lanes, each key word loaded once; the
+      // outputs of mb members written once
+      MrCost fp = mr_cost(T, pf, nf, nq, L, nr, 2 * mb, beta, true, true, false);
+      fp.bytes -= 8.0 * T.N * nf * mb * nr * 2.0;
+      ProfScope ps("multsum_rot", s, fp.bytes, fp.mm, fp.unit);
+#define MRP_FP(K)                                                                                                    \
+  case K:                                                                                                            \
+    hipLaunchKernelGGL((k_multsum_rot<K, true, RPW, true>), dim3(cdiv(nblk, 8) * 8 * cdiv(nr, RPW), nf), dim3(TPB), \
+                       0, s, R, pf, nr, digits, c0, pmod, nq, nqp, L, beta, T.nmods, batch, b0, T.logN, T.mc);      \
+    break;
+      switch (mb) { MRP_FP(1) MRP_FP(2) MRP_FP(3) MRP_FP(4) MRP_FP(5) MRP_FP(6) MRP_FP(7) MRP_FP(8) }
+#undef MRP_FP
+    }
+  }
+  return true;
 }
 
 void launch_multsum(const DeviceTables& T, u64* out, const u64* digits, const u64* key, const u64* c0,

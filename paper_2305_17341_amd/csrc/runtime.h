@@ -178,6 +178,9 @@ struct HeCtxImpl {
   std::vector<HeCt> hoisted_multi(const HeCt& x, const u64* digits, const std::vector<u64>& gs);
   void hoisted_masked(const HeCt& x, const u64* digits, const std::vector<u64>& gs, const std::vector<u64*>& outs,
                       const std::vector<const u64*>& masks, bool accumulate);
+  bool hoisted_masked_pair(const HeCt& x, const u64* dx, const std::vector<const u64*>& m1, const HeCt& y,
+                           const u64* dy, const std::vector<const u64*>& m2, const std::vector<u64>& gs,
+                           const std::vector<u64*>& outs);
   // consume: x's special-prime limbs (and q_l for moddown_rescale) may be
   // overwritten (x is a temporary the caller drops afterwards)
   // pack: the output's FP64 limbs may be stored packed (HeCt::packed says

@@ -879,6 +879,26 @@ void HeCtxImpl::hoisted_masked(const HeCt& x, const u64* digits, const std::vect
   n_multsum += (long)x.B * (long)gs.size();
 }
 
+// outs[r] = m1[r] (rotation gs[r] of x) + m2[r] (rotation gs[r] of y): one
+// multi-rotation launch over both decompositions; false where that does not
+// apply (nothing launched)
+bool HeCtxImpl::hoisted_masked_pair(const HeCt& x, const u64* dx, const std::vector<const u64*>& m1, const HeCt& y,
+                                    const u64* dy, const std::vector<const u64*>& m2, const std::vector<u64>& gs,
+                                    const std::vector<u64*>& outs) {
+  if (gs.empty()) return true;
+  if (x.level != y.level || x.B != y.B) fail(HE_EINVAL, "paired bases of unlike elements");
+  std::vector<const u64*> ks;
+  for (u64 g : gs) {
+    if (g == 1) fail(HE_EINVAL, "masked hoisted rotation by the identity");
+    ks.push_back(key(g).p);
+  }
+  if (!launch_multsum_rot_pair(T, outs.data(), ks.data(), gs.data(), (int)gs.size(), dx, x.poly(0), m1.data(), dy,
+                               y.poly(0), m2.data(), pmod.p, x.level, L, alpha, beta_at(x.level), x.B, stream))
+    return false;
+  n_multsum += 2L * x.B * (long)gs.size();
+  return true;
+}
+
 // ModDown: R_{Q_l P}^2 -> R_{Q_l}^2, (x - [x]_P) P^{-1} with [x]_P the exact
 // centred residue; out_level < l keeps (and computes) only the limbs up to it
 HeCt HeCtxImpl::moddown(const HeCt& x, int out_level, bool consume, bool src_ready, const u64* rec, bool pack) {
@@ -1628,13 +1648,15 @@ std::vector<HeCt> HeCtxImpl::matmul_side_a(const HeCt& ca, int n, int n1z, int n
     }
     HeCt lift1, lift2;
     {
+      // both bases' masked rotations in one launch where it applies (each
+      // key word loaded once), else the second added onto the first
       DevBuf d1 = decompose(Bb.poly(1), lvl, Bb.B);
-      hoisted_masked(Bb, d1.p, gs, outs, m1, false);
-      lift1 = hoisted(Bb, d1.p, 1);
-    }
-    {
       DevBuf d2 = decompose(Bpb.poly(1), lvl, Bpb.B);
-      hoisted_masked(Bpb, d2.p, gs, outs, m2, true);
+      if (!hoisted_masked_pair(Bb, d1.p, m1, Bpb, d2.p, m2, gs, outs)) {
+        hoisted_masked(Bb, d1.p, gs, outs, m1, false);
+        hoisted_masked(Bpb, d2.p, gs, outs, m2, true);
+      }
+      lift1 = hoisted(Bb, d1.p, 1);
       if (b > 0) lift2 = hoisted(Bpb, d2.p, 1);  // k = 0 has no second term
     }
     {

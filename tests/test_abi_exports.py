@@ -69,7 +69,8 @@ def test_knobs_host_side():
     for name, bad in [("ms_members", 0), ("ms_members", 9), ("mr_rotations", 65), ("ntt_interleave", 2), ("mr_group", 3),
                       ("ew_interleave", -1), ("mr_int_split", 2), ("mr_int_pass", 5), ("mr_int_chunk", 0),
                       ("mr_int_chunk", 65), ("mr_int_concurrent", 2), ("fbc_mfma", 2),
-                      ("xcd_map", 2), ("sum_streams", 3), ("no_such_knob", 1)]:
+                      ("xcd_map", 2), ("sum_streams", 3), ("mr_pair", 2),
+                      ("no_such_knob", 1)]:
         with pytest.raises(he.HeError) as e:
             he.knob_set(name, bad)
         assert e.value.status == -1

@@ -84,15 +84,16 @@ def test_knobs_never_change_residues(small_ctx):
     the multi-rotation launch inline or in their own kernel, four or eight
     members a pass; ModDown's lift by int8 matrix products or by FP64
     products, its work-groups in launch order or grouped by XCD; one, two or
-    four term streams per thread of the multi-output sums) gives the residues
-    of the default shape."""
+    four term streams per thread of the multi-output sums; the A side's two
+    masked multi-rotation launches as one or two) gives the residues of the
+    default shape."""
     from paper_2305_17341_amd import he
     ds = [16] * 5
     _, _, cA, cB = _encrypt_pairs(small_ctx, ds, 80)
     opts = {"flags": 1 | 2}
     ref = [c.export() for c in small_ctx.matmul_batch(cA, cB, ds, opts=opts)]
     names = ("ms_members", "mr_members", "mr_rotations", "ntt_interleave", "ew_interleave", "mr_group", "mr_int_split",
-             "mr_int_pass", "mr_int_chunk", "mr_int_concurrent", "fbc_mfma", "xcd_map", "sum_streams")
+             "mr_int_pass", "mr_int_chunk", "mr_int_concurrent", "fbc_mfma", "xcd_map", "sum_streams", "mr_pair")
     saved = {n: he.knob_get(n) for n in names}
     try:
         for name, value in [("ms_members", 3), ("mr_members", 2), ("mr_rotations", 5),
@@ -100,7 +101,8 @@ def test_knobs_never_change_residues(small_ctx):
                             ("mr_int_split", 0), ("mr_int_split", 1), ("mr_int_pass", 8), ("mr_int_chunk", 3),
                             ("mr_int_chunk", 1), ("mr_int_concurrent", 0), ("mr_int_concurrent", 1),
                             ("fbc_mfma", 0), ("fbc_mfma", 1), ("xcd_map", 0), ("xcd_map", 1),
-                            ("sum_streams", 1), ("sum_streams", 2), ("sum_streams", 4)]:
+                            ("sum_streams", 1), ("sum_streams", 2), ("sum_streams", 4),
+                            ("mr_pair", 0), ("mr_pair", 1)]:
             he.knob_set(name, value)
             got = small_ctx.matmul_batch(cA, cB, ds, opts=opts)
             for i, g in enumerate(got):
