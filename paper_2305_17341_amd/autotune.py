@@ -22,6 +22,7 @@ CANDIDATES = {
     "mr_int_chunk": (4, 16, 64),
     "mr_int_concurrent": (0, 1),
     "sum_streams": (1, 2, 4),
+    "mr_pair": (0, 1),
 }
 
 
