@@ -1889,9 +1889,9 @@ __global__ void k_tensor(u64* out, const u64* a, const u64* b, int nl, int nt, i
 // Up to TENSOR_PAIRS tensors summed in one pass, onto the running sum or not:
 // each pair is read once and the three-component sum once, where one launch
 // per pair reads and writes the sum for every pair.  The sum of the exact
-// signed products (at most 2 TENSOR_PAIRS + 1 terms below q each) stays below
-// 2^52, so the residues are those of one pair at a time.
-#define TENSOR_PAIRS 16
+// signed products (at most 2 TENSOR_PAIRS + 1 = 63 terms below q < 2^46
+// each) stays below 2^52, so the residues are those of one pair at a time.
+#define TENSOR_PAIRS 31
 struct TensorPairs {
   const u64* a[TENSOR_PAIRS];
   const u64* b[TENSOR_PAIRS];
