@@ -231,6 +231,10 @@ void launch_scale_int(i64* m, u64 mant, int shift, u64 N, hipStream_t s);
 // switching key b part: b = e - a s (+ pmod s' on the digit's primes)
 void launch_swk_b(const DeviceTables& T, u64* b, const u64* a, const u64* e, const u64* s_ntt, const u64* sp_ntt,
                   const u64* pmod, int nlimbs_total, int digit, int alpha, int L, hipStream_t s);
+// the FP64 limbs (at most F64_LAZY_BITS bits) of a switching key of nblocks
+// blocks of nmods limbs rewritten in place as doubles, the form the key inner
+// products read
+void launch_key_f64(const DeviceTables& T, u64* key, int nblocks, int nmods, hipStream_t s);
 
 // canonical embedding (double-double FFT)
 void launch_encode(const DeviceTables& T, i64* out, const double* z, int nz, int batch, double delta, void* scratch,

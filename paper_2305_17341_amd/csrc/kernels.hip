@@ -2946,7 +2946,8 @@ __device__ __forceinline__ void multsum_body(u64* out, const u64* __restrict__ d
 #pragma unroll
     for (int b = 0; b < MB; b++) dn[b] = digits[(size_t)(b0 + b) * dstride + (size_t)pos * N + src];
     for (int j = 0; j < beta; j++) {
-      const double kb = u2d(kbn), ka = u2d(kan);
+      // FP64 limbs of a switching key hold doubles (launch_key_f64)
+      const double kb = __longlong_as_double((long long)kbn), ka = __longlong_as_double((long long)kan);
       double d[MB];
 #pragma unroll
       for (int b = 0; b < MB; b++) d[b] = __longlong_as_double((long long)dn[b]);  // centred double digits
@@ -3105,8 +3106,8 @@ __device__ __forceinline__ void multsum_rot_group(const MultiRot& R, int r0, int
     double kb[RPW], ka[RPW], d[MB];
 #pragma unroll
     for (int g = 0; g < RPW; g++) {
-      kb[g] = u2d(kbn[g]);
-      ka[g] = u2d(kan[g]);
+      kb[g] = __longlong_as_double((long long)kbn[g]);  // key limbs stored as doubles
+      ka[g] = __longlong_as_double((long long)kan[g]);
     }
 #pragma unroll
     for (int b = 0; b < MB; b++) d[b] = __longlong_as_double((long long)dn[b]);  // centred double digits
@@ -3208,8 +3209,8 @@ __device__ __forceinline__ void multsum_rot_group_pair(const MultiRot& R, int r0
     double kb[RPW], ka[RPW], d[NB];
 #pragma unroll
     for (int g = 0; g < RPW; g++) {
-      kb[g] = u2d(kbn[g]);
-      ka[g] = u2d(kan[g]);
+      kb[g] = __longlong_as_double((long long)kbn[g]);  // key limbs stored as doubles
+      ka[g] = __longlong_as_double((long long)kan[g]);
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) d[b] = __longlong_as_double((long long)dn[b]);  // centred double digits
@@ -4186,6 +4187,23 @@ void launch_swk_b(const DeviceTables& T, u64* b, const u64* a, const u64* e, con
                   const u64* pmod, int nlimbs_total, int digit, int alpha, int L, hipStream_t s) {
   dim3 grid(cdiv(T.N, TPB), nlimbs_total);
   hipLaunchKernelGGL(k_swk_b, grid, dim3(TPB), 0, s, b, a, e, s_ntt, sp_ntt, pmod, digit, alpha, L, T.logN, T.mc);
+}
+
+// A switching key's limbs of at most F64_LAZY_BITS bits rewritten in place as
+// the IEEE doubles of their residues (exact below 2^53): the key inner
+// products read them as FP64 operands with no conversion.  The 60-bit limbs
+// stay integers.
+__global__ void k_key_f64(u64* key, int nmods, int logN, const ModConst* __restrict__ mc) {
+  const u64 N = 1ull << logN;
+  const u32 i = blockIdx.x * TPB + threadIdx.x;
+  const int m = (int)blockIdx.y % nmods;
+  if (i >= N || mc[m].bits > F64_LAZY_BITS) return;
+  u64* p = key + (size_t)blockIdx.y * N + i;
+  *p = (u64)__double_as_longlong((double)*p);
+}
+void launch_key_f64(const DeviceTables& T, u64* key, int nblocks, int nmods, hipStream_t s) {
+  dim3 grid(cdiv(T.N, TPB), nblocks * nmods);
+  hipLaunchKernelGGL(k_key_f64, grid, dim3(TPB), 0, s, key, nmods, T.logN, T.mc);
 }
 
 // centred integer of one coefficient-domain limb

@@ -631,6 +631,7 @@ void HeCtxImpl::swk_gen(const u64* sp, u64 kid, DevBuf& out) {
     int_to_ntt(en.p, (const i64*)e.p, all);
     launch_swk_b(T, bj, aj, en.p, s_ntt.p, sp, pmod.p, nmods, j, alpha, L, stream);
   }
+  launch_key_f64(T, out.p, beta * 2, nmods, stream);
 }
 
 void HeCtxImpl::keygen_relin() {
