@@ -125,7 +125,7 @@ struct HeCtxImpl {
   DevBuf up_scale;  // [level][nmods][2]: N^-1 hatinv_t mod q_t (Decompose's digit sources)
   DevBuf s_ntt, pk;
   bool have_sk = false;
-  std::map<u64, DevBuf> keys;             // Galois element -> key; 0 = relinearisation
+  std::map<u64, DevBuf> keys;             // Galois element -> key; 0 = relinearisation (FP64 limbs as doubles)
   std::map<std::string, DevBuf> ptcache;
   // a transform's diagonals present (giant, baby step) and their plaintexts
   // (entries of ptcache, kept for the context's life)
