@@ -2,8 +2,11 @@
 h = a w, l = fma(a, w, -h), k = rint(h * (1/q)), r = fma(-k, q, h) + l must
 equal a w - k q exactly, with |r| < q, for |a| <= 16 q and 0 <= w < q; the
 centred reduction fma(-rint(s / q), q, s) must stay within q/2 + 1; and the
-2^52 mantissa conversions must be exact below 2^52.  Checked with the same
-IEEE operations on the host (C with fma, 128-bit integers as reference)."""
+2^52 mantissa conversions must be exact below 2^52 and equal the plain
+conversion (double) x, the form in which the switching keys' limbs below 2^46
+are stored (so a key read as a double multiplies exactly as a converted word
+in [0, q) did).  Checked with the same IEEE operations on the host (C with
+fma, 128-bit integers as reference)."""
 import os
 import shutil
 import subprocess
